@@ -1,0 +1,212 @@
+/*
+ * negf.h -- C ABI of the MI355X (gfx950) NEGF hot-path library (libnegf.so).
+ *
+ * The library solves, at every energy point E (and transverse momentum, passed
+ * as a separate device H(k)), the retarded and lesser/greater equations of
+ * non-equilibrium Green's functions on block-tridiagonal operators:
+ *
+ *   Eq. (1)  G^R = (A - B^R)^{-1},   A - B^R = E S - H - Sigma^R_B - Sigma^R_sc
+ *   Eq. (2)  (G^R)^{-1} G^<> (G^A)^{-1} = B^<>,  i.e.  G^<> = G^R Sigma^<> G^A
+ *
+ * where Sigma_B is the open-boundary term of the two leads (the paper adds it
+ * to B without showing it, Section II after Eq. (3)) and Sigma_sc an optional
+ * block-diagonal scattering self-energy.  Only the blocks inside the sparsity
+ * pattern of A are returned (Section II, the paragraph after Fig. 3): the
+ * diagonal and first off-diagonal blocks.  The selected inversion is the
+ * recursive Green's function (RGF) algorithm the paper names as the
+ * sequential solver; energies are independent (same paragraph) and are the
+ * batch axis of every call.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ *  - Complex data are interleaved (re, im) pairs of double (complex128),
+ *    C-contiguous row-major b x b blocks: the memory layout of torch / NumPy
+ *    complex128 arrays.  Block i of an [nb][b][b] array starts at i*b*b.
+ *  - Unless stated otherwise, every array pointer is a DEVICE pointer owned by
+ *    the caller, 16-byte aligned.  The library allocates no device memory in
+ *    any call: scratch comes from the caller's workspace (negf_workspace_bytes).
+ *  - A "point" is one (problem, energy) pair.  Points are numbered problem by
+ *    problem in order, energies in order inside a problem.  Per-point outputs
+ *    are stored point-major, each point's part sized by its own (nb, b):
+ *    e.g. GR_diag holds, for each point, nb blocks of b x b.
+ *  - The device sits at real energy; z = E + i*eta enters only the leads.
+ *  - Leads repeat the first and last device cell: left lead cell (H_00, S_00)
+ *    with coupling (H_01, S_01), right lead cell (H_{N-1,N-1}, S_{N-1,N-1})
+ *    with coupling (H_{N-2,N-1}, S_{N-2,N-1}).  Their surface Green's functions
+ *    come from Sancho-Rubio decimation in double precision.
+ *  - Errors: argument errors (null required pointer, nb < 2, b < 1, b > 1024,
+ *    workspace too small, misaligned pointer) return NEGF_EINVAL
+ *    synchronously and enqueue nothing.  All work is enqueued on `stream`
+ *    (a hipStream_t; NULL = the null stream).  Numerical outcomes are written
+ *    per point into the device array info[] (LAPACK style): NEGF_OK,
+ *    NEGF_ENOCONV (decimation not converged or residual above the accept
+ *    threshold), NEGF_ESINGULAR (zero pivot), NEGF_ENONFINITE (NaN/Inf).
+ *    A HIP launch failure returns NEGF_EHIP.
+ *  - Synchronisation: the decimation loop checks convergence on the host
+ *    after each sweep once the minimum count is reached, which synchronises
+ *    `stream`; otherwise calls are asynchronous.
+ *  - Thread safety: calls on distinct workspaces and streams may run
+ *    concurrently.  The profiling counters are process-global.
+ */
+#ifndef NEGF_H
+#define NEGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NEGF_OK = 0,
+  NEGF_EINVAL = 1,
+  NEGF_ENOCONV = 2,
+  NEGF_ESINGULAR = 3,
+  NEGF_ENONFINITE = 4,
+  NEGF_EHIP = 5,
+  NEGF_ENOMEM = 6
+} negf_status;
+
+/* Arithmetic of the dense block products of the RGF sweeps.  Inversions,
+ * block sums, residuals and the lead decimation are double in every mode.
+ *  PLAIN_FP64    : every product in double (the reference method)
+ *  FP32_REFINE   : retarded forward sweep double; backward retarded and the
+ *                  lesser/greater forward products single (complex64 operands,
+ *                  single accumulation) followed by one double-precision
+ *                  residual correction per block; lesser/greater backward double
+ *  FP32_NOREFINE : every sweep product single, no correction (diagnostic)   */
+typedef enum { NEGF_PLAIN_FP64 = 0, NEGF_FP32_REFINE = 1, NEGF_FP32_NOREFINE = 2 } negf_precision;
+
+/* One block-tridiagonal device (Section II: BT shape imposed on A and B).
+ * H_diag [nb][b][b] and H_upper [nb-1][b][b] (H_{i,i+1}) are required; the
+ * lower blocks are H_{i+1,i} = H_{i,i+1}^H.  S_diag/S_upper == NULL means
+ * S = I.  sig_r_sc / sig_l_sc / sig_g_sc: optional energy-independent
+ * block-diagonal scattering self-energies [nb][b][b] (retarded, lesser,
+ * greater); NULL = none (ballistic). */
+typedef struct negf_device {
+  int32_t nb, b;
+  const void* H_diag;
+  const void* H_upper;
+  const void* S_diag;
+  const void* S_upper;
+  const void* sig_r_sc;
+  const void* sig_l_sc;
+  const void* sig_g_sc;
+} negf_device;
+
+/* A device and its list of energies (device array of n_e doubles).
+ * eta: lead broadening; mu_l, mu_r, kT: contact Fermi levels and temperature
+ * for Sigma^<_B = i f Gamma, Sigma^>_B = -i (1 - f) Gamma. */
+typedef struct negf_problem {
+  negf_device dev;
+  int32_t n_e;
+  const double* energies;
+  double eta, mu_l, mu_r, kT;
+} negf_problem;
+
+/* Optional knobs (pass NULL for the defaults in brackets). */
+typedef struct negf_options {
+  double sr_tol;        /* decimation stops when ||a||_F, ||c||_F <= tol ||d||_F  [1e-14] */
+  int32_t sr_max_iter;  /* decimation iteration cap                              [100]   */
+  double sr_accept;     /* normalised Dyson residual above which info=ENOCONV   [1e-10] */
+  int32_t batch;        /* points in flight per group (0: all points of the call) [0]   */
+  int32_t inv_nb;       /* panel width of the block inversion (16 or 32)          [32]  */
+  int32_t xcd_remap;    /* 1: place the tiles of one matrix on one XCD            [1]   */
+} negf_options;
+
+/* Operation codes for negf_workspace_bytes. */
+enum { NEGF_OP_OBC = 0, NEGF_OP_RETARDED = 1, NEGF_OP_LESSER_GREATER = 2, NEGF_OP_TRANSMISSION = 3 };
+
+/* Bytes of device workspace the call `op` needs for these problems (>= 256-byte
+ * aligned pointer expected).  With opt->batch = B the size covers B points in
+ * flight and the call loops over the points in chunks of B. */
+size_t negf_workspace_bytes(int32_t op, const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                            const negf_options* opt);
+
+/* Open-boundary self-energy of one lead (side 0 = left, 1 = right) at every
+ * point: the surface Green's function g_s = (d - alpha g_s beta)^{-1} by
+ * Sancho-Rubio decimation with z = E + i eta, d = z S0 - H0,
+ * alpha = H1 - z S1, beta = H1^H - z S1^H (H1, S1: coupling from the surface
+ * cell to the next cell away from the device), and Sigma^R = alpha g_s beta.
+ * This is the boundary term of B^R in Eq. (1).
+ *  seed     : NULL, or [points][b][b] initial guesses g~ (learned initialiser):
+ *             the candidate g0 = (d - alpha g~ beta)^{-1} is accepted when its
+ *             normalised residual is <= sr_accept, else plain decimation runs.
+ *  g_surf   : out [points][b][b]; sigma_r: out [points][b][b]
+ *  iters    : out int32 [points] decimation steps (0 when the seed was accepted)
+ *  resid    : out double [points] ||(d - alpha g_s beta) g_s - I||_F /
+ *             (||d - alpha g_s beta||_F ||g_s||_F)
+ *  info     : out int32 [points]                                              */
+negf_status negf_obc_surface(const negf_problem* problems, int32_t n_prob, int32_t side, const negf_options* opt,
+                             const void* seed, void* g_surf, void* sigma_r, int32_t* iters, double* resid,
+                             int32_t* info, void* workspace, size_t ws_bytes, void* stream);
+
+/* Retarded Green's function, Eq. (1), by RGF: the diagonal blocks
+ * GR_diag [points][nb][b][b], the upper blocks G_{i,i+1} GR_upper
+ * [points][nb-1][b][b] and (optional, NULL to skip) the lower blocks
+ * G_{i+1,i} GR_lower [points][nb-1][b][b].  Both leads are solved inside. */
+negf_status negf_rgf_retarded(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                              const negf_options* opt, void* GR_diag, void* GR_upper, void* GR_lower, int32_t* info,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/* Retarded plus lesser (and optionally greater) Green's functions, Eq. (1)
+ * and Eq. (2) with B^<> = Sigma^<>_B + Sigma^<>_sc.  GR_* as above (GR_lower
+ * may be NULL); GL_diag [points][nb][b][b] and GL_upper [points][nb-1][b][b]
+ * (G^<_{i,i+1}; the lower blocks are -(G^<_{i,i+1})^H) are required;
+ * GG_diag / GG_upper (greater) may both be NULL to skip G^>. */
+negf_status negf_rgf_lesser_greater(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                                    const negf_options* opt, void* GR_diag, void* GR_upper, void* GR_lower,
+                                    void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info,
+                                    void* workspace, size_t ws_bytes, void* stream);
+
+/* Transmission T(E) = Tr[Gamma_R G_{N-1,0} Gamma_L G_{N-1,0}^H] per point
+ * (double [points]); G_{N-1,0} from the left-connected recursion of the RGF
+ * forward sweep.  This is the observable of the paper's Fig. 7. */
+negf_status negf_transmission(const negf_problem* problems, int32_t n_prob, const negf_options* opt, double* T,
+                              int32_t* info, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- kernel-level entry points (used by the tests and the tile tuner) ---- */
+
+/* C_p = alpha op(A_p) op(B_p) + beta C_p for p < batch, complex128 M x N
+ * outputs, op = 'N' or 'C' (conjugate transpose).  lda/ldb/ldc are row
+ * strides, sa/sb/sc batch strides, all in complex elements.  alpha, beta:
+ * host arrays of 2 doubles.  prec: 0 double, 1 single products.
+ * tile: 0 default.  Returns NEGF_EINVAL for bad sizes. */
+negf_status negf_zgemm_batched(char opa, char opb, int32_t M, int32_t N, int32_t K, const double* alpha,
+                               const void* A, int64_t lda, int64_t sa, const void* B, int64_t ldb, int64_t sb,
+                               const double* beta, void* C, int64_t ldc, int64_t sc, int32_t batch, int32_t prec,
+                               int32_t tile, void* stream);
+
+/* out_p = M_p^{-1} for n x n complex128 blocks (contiguous, batch stride n*n).
+ * M is overwritten.  info [batch] receives ESINGULAR / ENONFINITE.
+ * workspace: negf_inverse_workspace_bytes(n, batch) bytes.  nb: 16 or 32. */
+size_t negf_inverse_workspace_bytes(int32_t n, int32_t batch);
+negf_status negf_zinv_batched(int32_t n, int32_t batch, void* M, void* out, int32_t* info, int32_t nb,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- profiling: per kernel class launch counts, algorithmic flops and
+ * event-timed durations, recorded on the launching stream. ---- */
+enum { NEGF_KC_GEMM64 = 0, NEGF_KC_GEMM32 = 1, NEGF_KC_INV_PANEL = 2, NEGF_KC_INV_SWAP = 3, NEGF_KC_INV_PERM = 4,
+       NEGF_KC_ELEM = 5, NEGF_KC_COUNT = 6 };
+typedef struct negf_kernel_stats {
+  int64_t launches;
+  double total_ms;   /* sum of per-launch event durations */
+  double flops;      /* algorithmic real flops of those launches */
+  double bytes;      /* algorithmic HBM bytes of those launches */
+} negf_kernel_stats;
+/* Enable (1) / disable (0) timing; enabling resets the counters.  Timing
+ * pairs events around each launch; counters are read after the caller has
+ * synchronised every stream it used. */
+void negf_profile_enable(int32_t on);
+/* Fill stats[NEGF_KC_COUNT]; returns NEGF_EHIP if an event query failed. */
+negf_status negf_profile_read(negf_kernel_stats* stats);
+
+const char* negf_status_string(negf_status s);
+int32_t negf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEGF_H */

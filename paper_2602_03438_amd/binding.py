@@ -1,0 +1,410 @@
+"""ctypes binding of libnegf.so (see include/negf.h for the contract).
+
+The functions named ``negf_*`` are the C entry points with argument
+marshalling only.  The helpers below them (``DeviceOnGPU``, ``Problem``,
+``obc_surface``, ``rgf_retarded``, ``rgf_lesser_greater``, ``transmission``,
+``zgemm``, ``zinv``) allocate outputs and workspace as torch tensors on the
+current HIP device and pass raw pointers and the current stream.  Every
+number is computed by the library's HIP kernels; there is no fallback path:
+if libnegf.so is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnegf.so")
+
+NEGF_OK, NEGF_EINVAL, NEGF_ENOCONV, NEGF_ESINGULAR, NEGF_ENONFINITE, NEGF_EHIP, NEGF_ENOMEM = range(7)
+PLAIN_FP64, FP32_REFINE, FP32_NOREFINE = 0, 1, 2
+OP_OBC, OP_RETARDED, OP_LESSER_GREATER, OP_TRANSMISSION = 0, 1, 2, 3
+KC_NAMES = ["gemm_f64", "gemm_f32", "inv_panel", "inv_swap", "inv_perm", "elementwise", "inv_update_gemm"]
+KC_COUNT = 7
+
+
+class negf_device(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("b", C.c_int32),
+                ("H_diag", C.c_void_p), ("H_upper", C.c_void_p),
+                ("S_diag", C.c_void_p), ("S_upper", C.c_void_p),
+                ("sig_r_sc", C.c_void_p), ("sig_l_sc", C.c_void_p), ("sig_g_sc", C.c_void_p)]
+
+
+class negf_problem(C.Structure):
+    _fields_ = [("dev", negf_device), ("n_e", C.c_int32), ("energies", C.c_void_p),
+                ("eta", C.c_double), ("mu_l", C.c_double), ("mu_r", C.c_double), ("kT", C.c_double)]
+
+
+class negf_options(C.Structure):
+    _fields_ = [("sr_tol", C.c_double), ("sr_max_iter", C.c_int32), ("sr_accept", C.c_double),
+                ("batch", C.c_int32), ("inv_nb", C.c_int32), ("xcd_remap", C.c_int32)]
+
+
+class negf_kernel_stats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+class NegfError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libnegf.so once; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise NegfError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_03438_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp, i32, i64, sz, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
+    L.negf_workspace_bytes.argtypes = [i32, P(negf_problem), i32, i32, P(negf_options)]
+    L.negf_workspace_bytes.restype = sz
+    L.negf_obc_surface.argtypes = [P(negf_problem), i32, i32, P(negf_options), vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.negf_obc_surface.restype = C.c_int
+    L.negf_rgf_retarded.argtypes = [P(negf_problem), i32, i32, P(negf_options), vp, vp, vp, vp, vp, sz, vp]
+    L.negf_rgf_retarded.restype = C.c_int
+    L.negf_rgf_lesser_greater.argtypes = [P(negf_problem), i32, i32, P(negf_options), vp, vp, vp, vp, vp, vp, vp,
+                                          vp, vp, sz, vp]
+    L.negf_rgf_lesser_greater.restype = C.c_int
+    L.negf_transmission.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, sz, vp]
+    L.negf_transmission.restype = C.c_int
+    L.negf_zgemm_batched.argtypes = [C.c_char, C.c_char, i32, i32, i32, P(dbl), vp, i64, i64, vp, i64, i64, P(dbl),
+                                     vp, i64, i64, i32, i32, i32, vp]
+    L.negf_zgemm_batched.restype = C.c_int
+    L.negf_inverse_workspace_bytes.argtypes = [i32, i32]
+    L.negf_inverse_workspace_bytes.restype = sz
+    L.negf_zinv_batched.argtypes = [i32, i32, vp, vp, vp, i32, vp, sz, vp]
+    L.negf_zinv_batched.restype = C.c_int
+    L.negf_profile_enable.argtypes = [i32]
+    L.negf_profile_enable.restype = None
+    L.negf_profile_read.argtypes = [P(negf_kernel_stats)]
+    L.negf_profile_read.restype = C.c_int
+    L.negf_status_string.argtypes = [C.c_int]
+    L.negf_status_string.restype = C.c_char_p
+    L.negf_version.argtypes = []
+    L.negf_version.restype = i32
+    if hasattr(L, "negf_mlp_forward"):
+        _bind_mlp(L)
+    _lib = L
+    return L
+
+
+def _bind_mlp(L):
+    vp, i32, sz, flt = C.c_void_p, C.c_int32, C.c_size_t, C.c_float
+    L.negf_mlp_forward.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.negf_mlp_forward.restype = C.c_int
+    L.negf_mlp_backward.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                    vp]
+    L.negf_mlp_backward.restype = C.c_int
+    L.negf_mlp_adam_step.argtypes = [i32, vp, vp, vp, vp, i32, flt, flt, flt, flt, vp]
+    L.negf_mlp_adam_step.restype = C.c_int
+    L.negf_mlp_infer_bf16.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.negf_mlp_infer_bf16.restype = C.c_int
+    L.negf_mlp_to_bf16.argtypes = [vp, vp, C.c_int64, vp]
+    L.negf_mlp_to_bf16.restype = C.c_int
+
+
+def status_string(code: int) -> str:
+    return lib().negf_status_string(code).decode()
+
+
+def check(code: int, what: str = "negf call"):
+    if code != NEGF_OK:
+        raise NegfError(f"{what} failed: {status_string(code)} ({code})")
+
+
+# ---------------------------------------------------------------- raw entry points
+
+def negf_workspace_bytes(op, problems, n_prob, prec, opt):
+    return lib().negf_workspace_bytes(op, problems, n_prob, prec, opt)
+
+
+def negf_obc_surface(*args):
+    return lib().negf_obc_surface(*args)
+
+
+def negf_rgf_retarded(*args):
+    return lib().negf_rgf_retarded(*args)
+
+
+def negf_rgf_lesser_greater(*args):
+    return lib().negf_rgf_lesser_greater(*args)
+
+
+def negf_transmission(*args):
+    return lib().negf_transmission(*args)
+
+
+def negf_zgemm_batched(*args):
+    return lib().negf_zgemm_batched(*args)
+
+
+def negf_zinv_batched(*args):
+    return lib().negf_zinv_batched(*args)
+
+
+def negf_inverse_workspace_bytes(n, batch):
+    return lib().negf_inverse_workspace_bytes(n, batch)
+
+
+def negf_profile_enable(on):
+    lib().negf_profile_enable(int(on))
+
+
+def negf_profile_read():
+    arr = (negf_kernel_stats * KC_COUNT)()
+    check(lib().negf_profile_read(arr), "negf_profile_read")
+    return {KC_NAMES[i]: dict(launches=arr[i].launches, total_ms=arr[i].total_ms, flops=arr[i].flops,
+                              bytes=arr[i].bytes) for i in range(KC_COUNT)}
+
+
+def negf_version():
+    return lib().negf_version()
+
+
+# ---------------------------------------------------------------- torch helpers
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise NegfError("no HIP device available: libnegf.so runs on the GPU only")
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_gpu(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+class DeviceOnGPU:
+    """The blocks of one block-tridiagonal device resident in HBM."""
+
+    def __init__(self, dev):
+        self.nb = dev.nb
+        self.b = dev.b
+        self.H_diag = to_gpu(dev.H_diag)
+        self.H_upper = to_gpu(dev.H_upper)
+        self.S_diag = to_gpu(dev.S_diag)
+        self.S_upper = to_gpu(dev.S_upper)
+        self.sig_r = to_gpu(dev.sig_r)
+        self.sig_l = to_gpu(dev.sig_l)
+        self.sig_g = to_gpu(dev.sig_g)
+
+    def struct(self) -> negf_device:
+        return negf_device(self.nb, self.b, _ptr(self.H_diag), _ptr(self.H_upper), _ptr(self.S_diag),
+                           _ptr(self.S_upper), _ptr(self.sig_r), _ptr(self.sig_l), _ptr(self.sig_g))
+
+
+class Problem:
+    """A device on the GPU plus its energies and contact parameters."""
+
+    def __init__(self, dev: DeviceOnGPU, energies, eta=1e-8, mu_l=0.0, mu_r=0.0, kT=0.025):
+        torch = _torch()
+        self.dev = dev
+        self.energies = torch.as_tensor(np.asarray(energies, dtype=np.float64)).to("cuda")
+        self.eta, self.mu_l, self.mu_r, self.kT = float(eta), float(mu_l), float(mu_r), float(kT)
+
+    @property
+    def n_e(self):
+        return int(self.energies.numel())
+
+    def struct(self) -> negf_problem:
+        return negf_problem(self.dev.struct(), self.n_e, _ptr(self.energies), self.eta, self.mu_l, self.mu_r, self.kT)
+
+
+def _problem_array(problems: Sequence[Problem]):
+    arr = (negf_problem * len(problems))(*[p.struct() for p in problems])
+    return arr
+
+
+def make_options(sr_tol=0.0, sr_max_iter=0, sr_accept=0.0, batch=0, inv_nb=0, xcd_remap=-1):
+    return negf_options(sr_tol, sr_max_iter, sr_accept, batch, inv_nb, xcd_remap)
+
+
+def _alloc_blocks(problems, per_point_blocks):
+    torch = _torch()
+    tot = sum(p.n_e * per_point_blocks(p) * p.dev.b * p.dev.b for p in problems)
+    return torch.empty(tot, dtype=torch.complex128, device="cuda")
+
+
+def _split(flat, problems, per_point_blocks):
+    out, off = [], 0
+    for p in problems:
+        n = p.n_e * per_point_blocks(p) * p.dev.b * p.dev.b
+        out.append(flat[off:off + n].view(p.n_e, per_point_blocks(p), p.dev.b, p.dev.b))
+        off += n
+    return out
+
+
+class Workspace:
+    """Reusable device workspace (a torch uint8 buffer)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes):
+        torch = _torch()
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        return self.buf
+
+
+def workspace_bytes(op, problems, prec=PLAIN_FP64, opts=None):
+    arr = _problem_array(problems)
+    return negf_workspace_bytes(op, arr, len(problems), prec, C.byref(opts) if opts else None)
+
+
+def obc_surface(problems: List[Problem], side: int, opts=None, seed=None, ws: Optional[Workspace] = None):
+    torch = _torch()
+    arr = _problem_array(problems)
+    o = C.byref(opts) if opts else None
+    nbytes = negf_workspace_bytes(OP_OBC, arr, len(problems), PLAIN_FP64, o)
+    if nbytes == 0:
+        raise NegfError("invalid problems")
+    buf = (ws or Workspace()).get(nbytes)
+    one = lambda p: 1
+    g = _alloc_blocks(problems, one)
+    sig = _alloc_blocks(problems, one)
+    npts = sum(p.n_e for p in problems)
+    iters = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    resid = torch.zeros(npts, dtype=torch.float64, device="cuda")
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    code = negf_obc_surface(arr, len(problems), side, o, _ptr(seed), _ptr(g), _ptr(sig), _ptr(iters), _ptr(resid),
+                            _ptr(info), _ptr(buf), buf.numel(), _stream())
+    check(code, "negf_obc_surface")
+    return dict(g_surf=_split(g, problems, one), sigma_r=_split(sig, problems, one), iters=iters, resid=resid,
+                info=info)
+
+
+def _rgf_outputs(problems, lesser, greater, lower):
+    diag = lambda p: p.dev.nb
+    off = lambda p: p.dev.nb - 1
+    out = dict(GR_diag=_alloc_blocks(problems, diag), GR_upper=_alloc_blocks(problems, off),
+               GR_lower=_alloc_blocks(problems, off) if lower else None)
+    if lesser:
+        out["GL_diag"] = _alloc_blocks(problems, diag)
+        out["GL_upper"] = _alloc_blocks(problems, off)
+    if greater:
+        out["GG_diag"] = _alloc_blocks(problems, diag)
+        out["GG_upper"] = _alloc_blocks(problems, off)
+    return out
+
+
+def _views(flat, problems):
+    res = {}
+    for k, v in flat.items():
+        if v is None:
+            res[k] = None
+            continue
+        per = (lambda p: p.dev.nb) if k.endswith("diag") else (lambda p: p.dev.nb - 1)
+        res[k] = _split(v, problems, per)
+    return res
+
+
+def rgf_retarded(problems, prec=PLAIN_FP64, opts=None, lower=True, ws=None, outputs=None):
+    torch = _torch()
+    arr = _problem_array(problems)
+    o = C.byref(opts) if opts else None
+    nbytes = negf_workspace_bytes(OP_RETARDED, arr, len(problems), prec, o)
+    if nbytes == 0:
+        raise NegfError("invalid problems")
+    buf = (ws or Workspace()).get(nbytes)
+    out = outputs or _rgf_outputs(problems, False, False, lower)
+    npts = sum(p.n_e for p in problems)
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    code = negf_rgf_retarded(arr, len(problems), prec, o, _ptr(out["GR_diag"]), _ptr(out["GR_upper"]),
+                             _ptr(out.get("GR_lower")), _ptr(info), _ptr(buf), buf.numel(), _stream())
+    check(code, "negf_rgf_retarded")
+    res = _views(out, problems)
+    res["info"] = info
+    res["flat"] = out
+    return res
+
+
+def rgf_lesser_greater(problems, prec=PLAIN_FP64, opts=None, greater=False, lower=True, ws=None, outputs=None):
+    torch = _torch()
+    arr = _problem_array(problems)
+    o = C.byref(opts) if opts else None
+    nbytes = negf_workspace_bytes(OP_LESSER_GREATER, arr, len(problems), prec, o)
+    if nbytes == 0:
+        raise NegfError("invalid problems")
+    buf = (ws or Workspace()).get(nbytes)
+    out = outputs or _rgf_outputs(problems, True, greater, lower)
+    npts = sum(p.n_e for p in problems)
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    code = negf_rgf_lesser_greater(arr, len(problems), prec, o, _ptr(out["GR_diag"]), _ptr(out["GR_upper"]),
+                                   _ptr(out.get("GR_lower")), _ptr(out["GL_diag"]), _ptr(out["GL_upper"]),
+                                   _ptr(out.get("GG_diag")), _ptr(out.get("GG_upper")), _ptr(info), _ptr(buf),
+                                   buf.numel(), _stream())
+    check(code, "negf_rgf_lesser_greater")
+    res = _views(out, problems)
+    res["info"] = info
+    res["flat"] = out
+    return res
+
+
+def transmission(problems, opts=None, ws=None):
+    torch = _torch()
+    arr = _problem_array(problems)
+    o = C.byref(opts) if opts else None
+    nbytes = negf_workspace_bytes(OP_TRANSMISSION, arr, len(problems), PLAIN_FP64, o)
+    if nbytes == 0:
+        raise NegfError("invalid problems")
+    buf = (ws or Workspace()).get(nbytes)
+    npts = sum(p.n_e for p in problems)
+    T = torch.zeros(npts, dtype=torch.float64, device="cuda")
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    code = negf_transmission(arr, len(problems), o, _ptr(T), _ptr(info), _ptr(buf), buf.numel(), _stream())
+    check(code, "negf_transmission")
+    return dict(T=T, info=info)
+
+
+def zgemm(A, B, C_=None, opa="N", opb="N", alpha=1.0, beta=0.0, prec=0, tile=0):
+    """Batched complex product on the library kernel: C = alpha op(A) op(B) + beta C."""
+    torch = _torch()
+    batch = A.shape[0]
+    M = A.shape[1] if opa == "N" else A.shape[2]
+    K = A.shape[2] if opa == "N" else A.shape[1]
+    N = B.shape[2] if opb == "N" else B.shape[1]
+    if C_ is None:
+        C_ = torch.zeros(batch, M, N, dtype=torch.complex128, device="cuda")
+    al = (C.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (C.c_double * 2)(complex(beta).real, complex(beta).imag)
+    code = negf_zgemm_batched(opa.encode(), opb.encode(), M, N, K, al, _ptr(A), A.shape[2], A.shape[1] * A.shape[2],
+                              _ptr(B), B.shape[2], B.shape[1] * B.shape[2], be, _ptr(C_), N, M * N, batch, prec, tile,
+                              _stream())
+    check(code, "negf_zgemm_batched")
+    return C_
+
+
+def zinv(M, nb=32):
+    """Batched inverse of [batch, n, n] complex128 blocks (M is copied, not destroyed)."""
+    torch = _torch()
+    batch, n, _ = M.shape
+    work = M.clone()
+    out = torch.empty_like(M)
+    info = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    nbytes = negf_inverse_workspace_bytes(n, batch)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    code = negf_zinv_batched(n, batch, _ptr(work), _ptr(out), _ptr(info), nb, _ptr(buf), nbytes, _stream())
+    check(code, "negf_zinv_batched")
+    return out, info

@@ -1,0 +1,957 @@
+// C ABI of the NEGF library: argument checking, workspace carving, point
+// chunking and the host-side sequencing of the batched kernels that make up
+// the lead decimation and the RGF sweeps.
+//
+// Every chunk is a run of consecutive points (problem order, energy order)
+// that share one block shape (nb, b); a chunk is processed by batched
+// launches over all of its points, so each product/inversion launch carries
+// (points x tiles) workgroups.  Per-problem data (H, S, Sigma_sc, energies,
+// Fermi levels) enter only through the assembly kernels, which are launched
+// per problem segment of the chunk.
+#include "../../include/negf.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+using namespace negf;
+
+namespace {
+
+const double2 ONE = {1.0, 0.0};
+const double2 MONE = {-1.0, 0.0};
+const double2 ZERO = {0.0, 0.0};
+
+struct Opts {
+  double tol = 1e-14;
+  int max_iter = 100;
+  double accept = 1e-10;
+  int batch = 0;
+  int inv_nb = 32;
+  int xcd = 1;
+};
+
+Opts get_opts(const negf_options* o) {
+  Opts r;
+  if (!o) return r;
+  if (o->sr_tol > 0) r.tol = o->sr_tol;
+  if (o->sr_max_iter > 0) r.max_iter = o->sr_max_iter;
+  if (o->sr_accept > 0) r.accept = o->sr_accept;
+  if (o->batch > 0) r.batch = o->batch;
+  if (o->inv_nb == 16 || o->inv_nb == 32) r.inv_nb = o->inv_nb;
+  if (o->xcd_remap == 0 || o->xcd_remap == 1) r.xcd = o->xcd_remap;
+  return r;
+}
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures, which is how negf_workspace_bytes sizes the workspace.
+struct Carver {
+  char* base;
+  size_t cap, off = 0;
+  bool overflow = false;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += bytes;
+    if (base && off > cap) overflow = true;
+    return p;
+  }
+};
+
+struct Seg {
+  const negf_problem* pr;
+  int e0, n, off;  // energies [e0, e0+n) of problem pr, at chunk-local point index off
+};
+struct Chunk {
+  int nb, b, npts;
+  long first_point;           // global index of the first point
+  size_t out_diag_off;        // offsets (complex elements) into [points][nb][b][b] outputs
+  size_t out_off_off;         // offsets into [points][nb-1][b][b] outputs
+  std::vector<Seg> segs;
+};
+
+std::vector<Chunk> make_chunks(const negf_problem* pr, int n_prob, int batch) {
+  std::vector<Chunk> out;
+  long gp = 0;
+  size_t od = 0, oo = 0;
+  for (int q = 0; q < n_prob; ++q) {
+    const int nb = pr[q].dev.nb, b = pr[q].dev.b;
+    int e = 0;
+    while (e < pr[q].n_e) {
+      const bool extend = !out.empty() && out.back().nb == nb && out.back().b == b &&
+                          (batch <= 0 || out.back().npts < batch);
+      if (!extend) {
+        Chunk c;
+        c.nb = nb; c.b = b; c.npts = 0; c.first_point = gp; c.out_diag_off = od; c.out_off_off = oo;
+        out.push_back(c);
+      }
+      Chunk& c = out.back();
+      const int room = batch > 0 ? batch - c.npts : pr[q].n_e - e;
+      const int take = std::min(room, pr[q].n_e - e);
+      c.segs.push_back(Seg{&pr[q], e, take, c.npts});
+      c.npts += take;
+      e += take;
+      gp += take;
+      od += (size_t)take * nb * b * b;
+      oo += (size_t)take * (nb - 1) * b * b;
+    }
+  }
+  return out;
+}
+
+// ------------------------------------------------------------------ buffers
+
+struct Blocks {   // a batch of b x b blocks, item p at p * stride
+  double2* p = nullptr;
+  long stride = 0;
+  double2* at(int i) const { return p + (long)i * stride; }
+};
+
+struct LeadWs {   // per (point, lead) pair scratch of the decimation
+  Blocks d, alpha, beta, eps_s, eps, a, c, g, ag, cg, t1, t2;
+  double *a2, *c2, *d2, *r2, *m2, *g2;
+  int *active, *iters, *n_active, *accepted;
+  void* inv_scratch;
+};
+
+struct PointWs {   // per point persistent data of the sweeps
+  Blocks sigL, sigR, gamL, gamR, slL, slR, sgL, sgR;
+  double2* X;     // [npts][nb-1] blocks
+  double2* Mst;   // [npts][nb] blocks (refinement only)
+  Blocks T0, T1, T2, T3, T4, C0, C1;
+  void* inv_scratch;
+  double* dot;
+};
+
+Blocks take_blocks(Carver& cv, int b, int n) {
+  Blocks r;
+  r.stride = (long)b * b;
+  r.p = cv.take<double2>((size_t)n * b * b);
+  return r;
+}
+
+LeadWs carve_leads(Carver& cv, int b, int npairs) {
+  LeadWs w;
+  Blocks* all[] = {&w.d, &w.alpha, &w.beta, &w.eps_s, &w.eps, &w.a, &w.c, &w.g, &w.ag, &w.cg, &w.t1, &w.t2};
+  for (Blocks* x : all) *x = take_blocks(cv, b, npairs);
+  w.a2 = cv.take<double>(npairs); w.c2 = cv.take<double>(npairs); w.d2 = cv.take<double>(npairs);
+  w.r2 = cv.take<double>(npairs); w.m2 = cv.take<double>(npairs); w.g2 = cv.take<double>(npairs);
+  w.active = cv.take<int>(npairs); w.iters = cv.take<int>(npairs); w.n_active = cv.take<int>(1);
+  w.accepted = cv.take<int>(npairs);
+  w.inv_scratch = cv.take<char>(inverse_scratch_bytes(b, npairs));
+  return w;
+}
+
+enum { OPK_OBC = 0, OPK_R = 1, OPK_RL = 2, OPK_T = 3 };
+
+// Lays out the workspace of one chunk.  Lead scratch and sweep temporaries
+// live in the same region (the leads finish before the sweeps start).
+struct ChunkWs {
+  PointWs pw;
+  LeadWs lw;
+};
+
+ChunkWs carve_chunk(Carver& cv, int opk, int nb, int b, int npts, negf_precision prec, int nsides) {
+  ChunkWs w{};
+  PointWs& p = w.pw;
+  if (opk != OPK_OBC) {
+    Blocks* pers[] = {&p.sigL, &p.sigR, &p.gamL, &p.gamR, &p.slL, &p.slR, &p.sgL, &p.sgR};
+    for (Blocks* x : pers) *x = take_blocks(cv, b, npts);
+    p.X = (opk == OPK_T) ? nullptr : cv.take<double2>((size_t)npts * (nb - 1) * b * b);
+    p.Mst = (prec == NEGF_FP32_REFINE && opk != OPK_T) ? cv.take<double2>((size_t)npts * nb * b * b) : nullptr;
+    p.dot = cv.take<double>(npts);
+  }
+  // shared region
+  Carver sub{cv.base ? cv.base + cv.off : nullptr, cv.base ? cv.cap - std::min(cv.cap, cv.off) : 0};
+  w.lw = carve_leads(sub, b, npts * nsides);
+  size_t lead_bytes = sub.off;
+  Carver sub2{cv.base ? cv.base + cv.off : nullptr, cv.base ? cv.cap - std::min(cv.cap, cv.off) : 0};
+  if (opk != OPK_OBC) {
+    Blocks* tmp[] = {&p.T0, &p.T1, &p.T2, &p.T3, &p.T4, &p.C0, &p.C1};
+    for (Blocks* x : tmp) *x = take_blocks(sub2, b, npts);
+    p.inv_scratch = sub2.take<char>(inverse_scratch_bytes(b, npts));
+  }
+  const size_t region = std::max(lead_bytes, sub2.off);
+  cv.take<char>(region);
+  if (sub.overflow || sub2.overflow) cv.overflow = true;
+  return w;
+}
+
+// ------------------------------------------------------------------ launch helpers
+
+struct Ctx {
+  hipStream_t s;
+  Opts o;
+  hipError_t err = hipSuccess;
+  bool ok() const { return err == hipSuccess; }
+  void chk(hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; }
+
+  // C = alpha op(A) op(B) + beta Cin over a batch of b x b blocks
+  void gemm(Prec pr, Op oa, Op ob, int b, int batch, double2 alpha, const double2* A, long sA, const double2* B,
+            long sB, double2 beta, const double2* Cin, long sCin, double2* C, long sC, const int* active = nullptr) {
+    if (!ok()) return;
+    GemmDesc g{};
+    g.M = b; g.N = b; g.K = b; g.batch = batch;
+    g.opA = oa; g.opB = ob;
+    g.A = MatRef{A, b, sA};
+    g.B = MatRef{B, b, sB};
+    g.alpha = alpha; g.beta = beta;
+    g.Cin = MatRef{Cin, b, sCin};
+    g.C = MatOut{C, b, sC};
+    g.active = active;
+    g.prec = pr;
+    g.xcd_remap = o.xcd;
+    g.prof_class = -1;
+    chk(launch_gemm(g, s));
+  }
+  void inverse(int b, int batch, double2* M, long sM, double2* out, long sO, void* scratch, int* info, int info_mod,
+               const int* active = nullptr) {
+    if (!ok()) return;
+    InvDesc d{};
+    d.n = b; d.batch = batch;
+    d.M = M; d.ldm = b; d.sM = sM;
+    d.out = out; d.ldo = b; d.sO = sO;
+    d.scratch = scratch;
+    d.info = info; d.info_mod = info_mod;
+    d.active = active;
+    d.nb = o.inv_nb;
+    chk(launch_inverse(d, s));
+  }
+  void lincomb(int b, int batch, double2 c1, const double2* X, long sX, double2 c2, const double2* Y, long sY,
+               double2 g, double2* out, long sOut, const int* active = nullptr) {
+    if (!ok()) return;
+    chk(launch_lincomb(b, batch, c1, X, sX, c2, Y, sY, g, out, sOut, active, s));
+  }
+  void assemble(AssembleDesc d) {
+    if (!ok()) return;
+    chk(launch_assemble(d, s));
+  }
+};
+
+AssembleDesc asm_base(int b, int n, const double* energies, double2* out, long sOut) {
+  AssembleDesc d{};
+  d.b = b; d.batch = n; d.energies = energies;
+  d.eta = 0.0; d.s_coef = 1.0;
+  d.h_coef = -1.0;
+  d.y_coef = -1.0; d.z_coef = -1.0;
+  d.out = out; d.sOut = sOut;
+  return d;
+}
+
+inline const double2* blk(const void* base, long i, int b) {
+  return base ? (const double2*)base + i * (long)b * b : nullptr;
+}
+
+// A_ii = E S_ii - H_ii - Sigma_sc,ii - [i==0] SigL - [i==nb-1] SigR for every point of the chunk
+void assemble_diag(Ctx& cx, const Chunk& ch, int i, const PointWs& pw, Blocks out, bool with_leads = true) {
+  const int b = ch.b, nb = ch.nb;
+  for (const Seg& sg : ch.segs) {
+    const negf_device& dv = sg.pr->dev;
+    AssembleDesc d = asm_base(b, sg.n, sg.pr->energies + sg.e0, out.at(sg.off), out.stride);
+    d.S = blk(dv.S_diag, i, b); d.s_identity = 1;
+    d.H = blk(dv.H_diag, i, b);
+    d.Y = blk(dv.sig_r_sc, i, b);
+    if (with_leads && i == 0) { d.Z = pw.sigL.at(sg.off); d.sZ = pw.sigL.stride; }
+    if (with_leads && i == nb - 1) {
+      if (d.Z) {
+        // nb == 1 is rejected by argument checking, so both leads never share a block
+      }
+      d.Z = pw.sigR.at(sg.off); d.sZ = pw.sigR.stride;
+    }
+    cx.assemble(d);
+  }
+}
+
+// A_{i,i+1} = E S_{i,i+1} - H_{i,i+1}
+void assemble_upper(Ctx& cx, const Chunk& ch, int i, Blocks out) {
+  const int b = ch.b;
+  for (const Seg& sg : ch.segs) {
+    const negf_device& dv = sg.pr->dev;
+    AssembleDesc d = asm_base(b, sg.n, sg.pr->energies + sg.e0, out.at(sg.off), out.stride);
+    d.S = blk(dv.S_upper, i, b); d.s_identity = 0;
+    d.H = blk(dv.H_upper, i, b);
+    cx.assemble(d);
+  }
+}
+
+// Sigma_i (lesser or greater, kind 0/1): scattering block plus the lead terms
+// of the end blocks.  Returns false when the block is identically zero.
+bool assemble_sigma_lg(Ctx& cx, const Chunk& ch, int i, int kind, const PointWs& pw, Blocks out) {
+  const int b = ch.b, nb = ch.nb;
+  const Blocks& leadL = kind == 0 ? pw.slL : pw.sgL;
+  const Blocks& leadR = kind == 0 ? pw.slR : pw.sgR;
+  bool any = false;
+  for (const Seg& sg : ch.segs) {
+    const negf_device& dv = sg.pr->dev;
+    const void* sc = kind == 0 ? dv.sig_l_sc : dv.sig_g_sc;
+    if (sc || i == 0 || i == nb - 1) any = true;
+  }
+  if (!any) return false;
+  for (const Seg& sg : ch.segs) {
+    const negf_device& dv = sg.pr->dev;
+    AssembleDesc d = asm_base(b, sg.n, nullptr, out.at(sg.off), out.stride);
+    d.S = nullptr; d.s_identity = 0; d.s_coef = 0.0;
+    d.H = nullptr;
+    d.Y = blk(kind == 0 ? dv.sig_l_sc : dv.sig_g_sc, i, b); d.y_coef = 1.0;
+    if (i == 0) { d.Z = leadL.at(sg.off); d.sZ = leadL.stride; d.z_coef = 1.0; }
+    if (i == nb - 1) { d.Z = leadR.at(sg.off); d.sZ = leadR.stride; d.z_coef = 1.0; }
+    cx.assemble(d);
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ decimation
+
+// Solves the leads of the given sides for every point of the chunk.  Pair
+// q = side_index * npts + p.  Writes g_s into lw.g and Sigma^R into sig_out
+// (per pair, stride b*b) and the iteration counts / residuals / info.
+void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, LeadWs& w, const double2* seed,
+                    long seed_stride, Blocks sig_out_L, Blocks sig_out_R, int* info_pts, int* iters_out,
+                    double* resid_out, int* iters_host_max) {
+  const int b = ch.b, nb = ch.nb, npts = ch.npts, np = npts * nsides;
+  const long bb = (long)b * b;
+  hipStream_t s = cx.s;
+  // --- lead blocks d, alpha, beta at z = E + i eta
+  for (int si = 0; si < nsides; ++si) {
+    const int side = sides[si];
+    for (const Seg& sg : ch.segs) {
+      const negf_device& dv = sg.pr->dev;
+      const double* en = sg.pr->energies + sg.e0;
+      const int q0 = si * npts + sg.off;
+      const long cell = side == 0 ? 0 : nb - 1;
+      const long cpl = side == 0 ? 0 : nb - 2;
+      AssembleDesc d = asm_base(b, sg.n, en, w.d.at(q0), bb);
+      d.eta = sg.pr->eta;
+      d.S = blk(dv.S_diag, cell, b); d.s_identity = 1;
+      d.H = blk(dv.H_diag, cell, b);
+      cx.assemble(d);
+      // alpha = H1 - z S1, beta = H1^H - z S1^H ; left lead: H1 = H_01^H, right: H1 = H_{N-2,N-1}
+      AssembleDesc a = asm_base(b, sg.n, en, w.alpha.at(q0), bb);
+      a.eta = sg.pr->eta; a.s_coef = -1.0; a.h_coef = 1.0;
+      a.S = blk(dv.S_upper, cpl, b); a.s_identity = 0;
+      a.H = blk(dv.H_upper, cpl, b);
+      a.op = side == 0 ? 1 : 0;
+      cx.assemble(a);
+      AssembleDesc be = a;
+      be.out = w.beta.at(q0);
+      be.op = side == 0 ? 0 : 1;
+      cx.assemble(be);
+    }
+  }
+  if (!cx.ok()) return;
+  cx.chk(launch_fill_int(np, w.active, 1, s));
+  cx.chk(launch_fill_int(np, w.iters, 0, s));
+  cx.chk(launch_fill_int(np, w.accepted, 0, s));
+  cx.chk(launch_frob2(b, np, w.d.p, bb, 0.0, w.d2, s));
+
+  // --- optional seed g~: candidate g0 = (d - alpha g~ beta)^{-1} (kept in w.g), accepted
+  // when its normalised Dyson residual is <= accept; accepted pairs skip the decimation.
+  if (seed) {
+    for (int si = 0; si < nsides; ++si)
+      cx.gemm(PREC_F64, OP_N, OP_N, b, npts, ONE, w.alpha.at(si * npts), bb, seed, seed_stride, ZERO, nullptr, 0,
+              w.t1.at(si * npts), bb);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.t1.p, bb, w.beta.p, bb, ONE, w.d.p, bb, w.eps.p, bb);
+    cx.inverse(b, np, w.eps.p, bb, w.g.p, bb, w.inv_scratch, nullptr, 0);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.alpha.p, bb, w.g.p, bb, ZERO, nullptr, 0, w.t1.p, bb);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.t1.p, bb, w.beta.p, bb, ONE, w.d.p, bb, w.t2.p, bb);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.t2.p, bb, w.g.p, bb, ZERO, nullptr, 0, w.t1.p, bb);
+    cx.chk(launch_frob2(b, np, w.t1.p, bb, 1.0, w.r2, s));
+    cx.chk(launch_frob2(b, np, w.t2.p, bb, 0.0, w.m2, s));
+    cx.chk(launch_frob2(b, np, w.g.p, bb, 0.0, w.g2, s));
+    // w.accepted[q] stays 0 (= accepted) unless the residual test fails
+    cx.chk(launch_sr_finish(np, w.r2, w.m2, w.g2, nullptr, cx.o.accept, nullptr, w.accepted, 0, s));
+    cx.chk(launch_seed_flags(np, w.accepted, w.active, w.iters, s));
+  }
+  if (!cx.ok()) return;
+  // --- plain decimation: eps_s = eps = d, a = alpha, c = beta
+  cx.lincomb(b, np, ONE, w.d.p, bb, ZERO, nullptr, 0, ZERO, w.eps_s.p, bb);
+  cx.lincomb(b, np, ONE, w.d.p, bb, ZERO, nullptr, 0, ZERO, w.eps.p, bb);
+  cx.lincomb(b, np, ONE, w.alpha.p, bb, ZERO, nullptr, 0, ZERO, w.a.p, bb);
+  cx.lincomb(b, np, ONE, w.beta.p, bb, ZERO, nullptr, 0, ZERO, w.c.p, bb);
+  Blocks a = w.a, c = w.c, t1 = w.t1, t2 = w.t2;
+  int hmax = 0;
+  for (int it = 1; it <= cx.o.max_iter && cx.ok(); ++it) {
+    const int* act = w.active;
+    // g = eps^{-1}  (eps is kept: invert a copy)
+    cx.lincomb(b, np, ONE, w.eps.p, bb, ZERO, nullptr, 0, ZERO, t1.p, bb, act);
+    cx.inverse(b, np, t1.p, bb, w.ag.p, bb, w.inv_scratch, nullptr, 0, act);   // ag temporarily holds g
+    std::swap(w.ag, w.cg);   // cg := g ; ag free
+    const Blocks g = w.cg;
+    // ag = a g, t2 = c g
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, a.p, bb, g.p, bb, ZERO, nullptr, 0, w.ag.p, bb, act);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, c.p, bb, g.p, bb, ZERO, nullptr, 0, t2.p, bb, act);
+    // t1 = ag c ; eps_s -= t1 ; eps -= t1
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.ag.p, bb, c.p, bb, ZERO, nullptr, 0, t1.p, bb, act);
+    cx.chk(launch_sub2(b, np, t1.p, bb, w.eps_s.p, bb, w.eps.p, bb, act, s));
+    // eps -= (c g) a
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, t2.p, bb, a.p, bb, ONE, w.eps.p, bb, w.eps.p, bb, act);
+    // a' = (a g) a -> t1 ; c' = (c g) c -> g buffer (g no longer needed)
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.ag.p, bb, a.p, bb, ZERO, nullptr, 0, t1.p, bb, act);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, t2.p, bb, c.p, bb, ZERO, nullptr, 0, w.cg.p, bb, act);
+    std::swap(a, t1);
+    {
+      Blocks tmp = c;
+      c = w.cg;
+      w.cg = tmp;
+    }
+    cx.chk(launch_frob2(b, np, a.p, bb, 0.0, w.a2, s));
+    cx.chk(launch_frob2(b, np, c.p, bb, 0.0, w.c2, s));
+    cx.chk(launch_sr_check(np, w.a2, w.c2, w.d2, cx.o.tol, it, w.active, w.iters, w.n_active, s));
+    hmax = it;
+    int host_active = 0;
+    cx.chk(hipMemcpyAsync(&host_active, w.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+    cx.chk(hipStreamSynchronize(s));
+    if (host_active == 0) break;
+  }
+  if (iters_host_max) *iters_host_max = hmax;
+  if (!cx.ok()) return;
+  // --- g_s = eps_s^{-1} (pairs that ran the decimation); seeded-accepted pairs keep g0
+  if (seed) {
+    cx.inverse(b, np, w.eps_s.p, bb, t1.p, bb, w.inv_scratch, nullptr, 0);
+    cx.chk(launch_seed_select(b, np, w.accepted, t1.p, w.g.p, s));   // g <- eps_s^{-1} where rejected
+  } else {
+    cx.inverse(b, np, w.eps_s.p, bb, w.g.p, bb, w.inv_scratch, nullptr, 0);
+  }
+  // --- Sigma = alpha g_s beta ; residual of the surface Dyson equation
+  cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.alpha.p, bb, w.g.p, bb, ZERO, nullptr, 0, t1.p, bb);
+  for (int si = 0; si < nsides; ++si) {
+    Blocks dst = (sides[si] == 0) ? sig_out_L : sig_out_R;
+    cx.gemm(PREC_F64, OP_N, OP_N, b, npts, ONE, t1.at(si * npts), bb, w.beta.at(si * npts), bb, ZERO, nullptr, 0,
+            dst.p, dst.stride);
+    cx.lincomb(b, npts, ONE, w.d.at(si * npts), bb, MONE, dst.p, dst.stride, ZERO, t2.at(si * npts), bb);
+  }
+  cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, t2.p, bb, w.g.p, bb, ZERO, nullptr, 0, t1.p, bb);
+  cx.chk(launch_frob2(b, np, t1.p, bb, 1.0, w.r2, s));
+  cx.chk(launch_frob2(b, np, t2.p, bb, 0.0, w.m2, s));
+  cx.chk(launch_frob2(b, np, w.g.p, bb, 0.0, w.g2, s));
+  if (info_pts) cx.chk(launch_sr_finish(np, w.r2, w.m2, w.g2, w.active, cx.o.accept, resid_out, info_pts, npts, s));
+  if (iters_out) cx.chk(hipMemcpyAsync(iters_out, w.iters, sizeof(int) * np, hipMemcpyDeviceToDevice, s));
+  if (info_pts) cx.chk(launch_check_finite(b, np, w.g.p, bb, info_pts, npts, s));
+}
+
+// ------------------------------------------------------------------ RGF sweeps
+
+struct Outs {
+  double2 *GRd, *GRu, *GRl, *GLd, *GLu, *GGd, *GGu;
+  int* info;
+  double* T;
+};
+
+// Leads of both sides into pw.sigL / pw.sigR, Gamma and (optionally) Sigma^<>.
+void leads_for_sweeps(Ctx& cx, const Chunk& ch, ChunkWs& w, int* info, bool lesser) {
+  const int sides[2] = {0, 1};
+  run_decimation(cx, ch, sides, 2, w.lw, nullptr, 0, w.pw.sigL, w.pw.sigR, info, nullptr, nullptr, nullptr);
+  const int b = ch.b;
+  for (const Seg& sg : ch.segs) {
+    const double* en = sg.pr->energies + sg.e0;
+    const PointWs& p = w.pw;
+    cx.chk(launch_gamma_sigma(b, sg.n, p.sigL.at(sg.off), p.sigL.stride, en, sg.pr->mu_l, sg.pr->kT,
+                              p.gamL.at(sg.off), p.gamL.stride, lesser ? p.slL.at(sg.off) : nullptr, p.slL.stride,
+                              lesser ? p.sgL.at(sg.off) : nullptr, p.sgL.stride, cx.s));
+    cx.chk(launch_gamma_sigma(b, sg.n, p.sigR.at(sg.off), p.sigR.stride, en, sg.pr->mu_r, sg.pr->kT,
+                              p.gamR.at(sg.off), p.gamR.stride, lesser ? p.slR.at(sg.off) : nullptr, p.slR.stride,
+                              lesser ? p.sgR.at(sg.off) : nullptr, p.sgR.stride, cx.s));
+  }
+}
+
+// Forward retarded sweep: g_i -> gdiag (per point stride nb*b*b), X_i, M_i (refine).
+// With corner != nullptr also the left-connected G_{nb-1,0} recursion for T.
+void forward_retarded(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, double2* gdiag, long gstride,
+                      int* info, bool want_X, Blocks* corner) {
+  const int b = ch.b, nb = ch.nb, n = ch.npts;
+  const long bb = (long)b * b;
+  const Prec pf = (prec == NEGF_FP32_NOREFINE) ? PREC_F32 : PREC_F64;
+  const long xs = (long)(nb - 1) * bb, ms = (long)nb * bb;
+  Blocks C = pw.C0, Cn = pw.C1;
+  for (int i = 0; i < nb && cx.ok(); ++i) {
+    assemble_diag(cx, ch, i, pw, pw.T0);
+    double2* g_prev = gdiag + (long)(i - 1) * bb;
+    if (i > 0) {
+      assemble_upper(cx, ch, i - 1, pw.T1);
+      double2* Xi = want_X ? pw.X + (long)(i - 1) * bb : pw.T2.p;
+      const long sX = want_X ? xs : bb;
+      cx.gemm(pf, OP_N, OP_N, b, n, ONE, g_prev, gstride, pw.T1.p, bb, ZERO, nullptr, 0, Xi, sX);
+      cx.gemm(pf, OP_C, OP_N, b, n, MONE, pw.T1.p, bb, Xi, sX, ONE, pw.T0.p, bb, pw.T0.p, bb);
+    }
+    if (pw.Mst) cx.lincomb(b, n, ONE, pw.T0.p, bb, ZERO, nullptr, 0, ZERO, pw.Mst + (long)i * bb, ms);
+    double2* gi = gdiag + (long)i * bb;
+    cx.inverse(b, n, pw.T0.p, bb, gi, gstride, pw.inv_scratch, info, 0);
+    if (corner) {
+      if (i == 0) {
+        cx.lincomb(b, n, ONE, gi, gstride, ZERO, nullptr, 0, ZERO, C.p, bb);
+      } else {
+        // C_i = -g_i (A_{i,i-1} C_{i-1}),  A_{i,i-1} = T1^H
+        cx.gemm(PREC_F64, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, C.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
+        cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, gi, gstride, pw.T3.p, bb, ZERO, nullptr, 0, Cn.p, bb);
+        std::swap(C, Cn);
+      }
+    }
+  }
+  if (corner) *corner = C;
+}
+
+void backward_retarded(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, const Outs& o) {
+  const int b = ch.b, nb = ch.nb, n = ch.npts;
+  const long bb = (long)b * b;
+  const long ds = (long)nb * bb, us = (long)(nb - 1) * bb;
+  const bool refine = prec == NEGF_FP32_REFINE;
+  const Prec pb = (prec == NEGF_PLAIN_FP64) ? PREC_F64 : PREC_F32;
+  double2* GRd = o.GRd + ch.out_diag_off;
+  double2* GRu = o.GRu + ch.out_off_off;
+  double2* GRl = o.GRl ? o.GRl + ch.out_off_off : nullptr;
+  for (int i = nb - 2; i >= 0 && cx.ok(); --i) {
+    assemble_upper(cx, ch, i, pw.T1);                  // A_{i,i+1}
+    double2* gi = GRd + (long)i * bb;                  // holds g_i
+    double2* Gn = GRd + (long)(i + 1) * bb;            // G_{i+1,i+1}
+    double2* Xi = pw.X + (long)i * bb;
+    const long xs = us;
+    double2* Glo = GRl ? GRl + (long)i * bb : pw.T3.p;
+    const long sLo = GRl ? us : bb;
+    double2* Gup = GRu + (long)i * bb;
+    // W = A_{i+1,i} g_i ; G_{i+1,i} = -G_{i+1,i+1} W
+    cx.gemm(pb, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gi, ds, ZERO, nullptr, 0, pw.T2.p, bb);
+    cx.gemm(pb, OP_N, OP_N, b, n, MONE, Gn, ds, pw.T2.p, bb, ZERO, nullptr, 0, Glo, sLo);
+    double2* Mi = refine ? pw.Mst + (long)i * bb : nullptr;
+    if (refine) {
+      // r = -G_{i+1,i+1} A_{i+1,i} - G_{i+1,i} M_i ; G_{i+1,i} += r g_i
+      cx.gemm(PREC_F64, OP_N, OP_C, b, n, MONE, Gn, ds, pw.T1.p, bb, ZERO, nullptr, 0, pw.T4.p, bb);
+      cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, Glo, sLo, Mi, ds, ONE, pw.T4.p, bb, pw.T4.p, bb);
+      cx.gemm(PREC_F32, OP_N, OP_N, b, n, ONE, pw.T4.p, bb, gi, ds, ONE, Glo, sLo, Glo, sLo);
+    }
+    // G_{i,i+1} = -X_i G_{i+1,i+1}
+    cx.gemm(pb, OP_N, OP_N, b, n, MONE, Xi, xs, Gn, ds, ZERO, nullptr, 0, Gup, us);
+    if (refine) {
+      // r = -A_{i,i+1} G_{i+1,i+1} - M_i G_{i,i+1} ; G_{i,i+1} += g_i r
+      cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, pw.T1.p, bb, Gn, ds, ZERO, nullptr, 0, pw.T4.p, bb);
+      cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, Mi, ds, Gup, us, ONE, pw.T4.p, bb, pw.T4.p, bb);
+      cx.gemm(PREC_F32, OP_N, OP_N, b, n, ONE, gi, ds, pw.T4.p, bb, ONE, Gup, us, Gup, us);
+      // keep g_i for the diagonal correction
+      cx.lincomb(b, n, ONE, gi, ds, ZERO, nullptr, 0, ZERO, pw.T0.p, bb);
+    }
+    // G_ii = g_i - X_i G_{i+1,i}
+    cx.gemm(pb, OP_N, OP_N, b, n, MONE, Xi, xs, Glo, sLo, ONE, gi, ds, gi, ds);
+    if (refine) {
+      // r = I - M_i G_ii - A_{i,i+1} G_{i+1,i} ; G_ii += g_i r
+      cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, Mi, ds, gi, ds, ZERO, nullptr, 0, pw.T4.p, bb);
+      cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, pw.T1.p, bb, Glo, sLo, ONE, pw.T4.p, bb, pw.T4.p, bb);
+      cx.lincomb(b, n, MONE, pw.T4.p, bb, ZERO, nullptr, 0, ONE, pw.T4.p, bb);
+      cx.gemm(PREC_F32, OP_N, OP_N, b, n, ONE, pw.T0.p, bb, pw.T4.p, bb, ONE, gi, ds, gi, ds);
+    }
+  }
+}
+
+// Forward lesser/greater sweep of one kind; g^<> into gl (stride ds).  Needs g_i in GRd.
+void forward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, int kind, const double2* GRd,
+                    double2* gl) {
+  const int b = ch.b, nb = ch.nb, n = ch.npts;
+  const long bb = (long)b * b, ds = (long)nb * bb;
+  const bool refine = prec == NEGF_FP32_REFINE;
+  const Prec pg = (prec == NEGF_PLAIN_FP64) ? PREC_F64 : PREC_F32;    // g B g^H
+  const Prec pbt = (prec == NEGF_FP32_NOREFINE) ? PREC_F32 : PREC_F64; // B formation
+  for (int i = 0; i < nb && cx.ok(); ++i) {
+    const double2* gi = GRd + (long)i * bb;
+    double2* gli = gl + (long)i * bb;
+    const bool has_sig = assemble_sigma_lg(cx, ch, i, kind, pw, pw.T4);
+    if (i > 0) {
+      assemble_upper(cx, ch, i - 1, pw.T1);   // A_{i-1,i}; A_{i,i-1} = T1^H
+      cx.gemm(pbt, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gl + (long)(i - 1) * bb, ds, ZERO, nullptr, 0, pw.T2.p, bb);
+      cx.gemm(pbt, OP_N, OP_N, b, n, ONE, pw.T2.p, bb, pw.T1.p, bb, has_sig ? ONE : ZERO, has_sig ? pw.T4.p : nullptr,
+              bb, pw.T4.p, bb);
+    } else if (!has_sig) {
+      cx.lincomb(b, n, ZERO, nullptr, 0, ZERO, nullptr, 0, ZERO, pw.T4.p, bb);
+    }
+    // g^<_i = g_i B g_i^H
+    cx.gemm(pg, OP_N, OP_N, b, n, ONE, gi, ds, pw.T4.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
+    cx.gemm(pg, OP_N, OP_C, b, n, ONE, pw.T3.p, bb, gi, ds, ZERO, nullptr, 0, gli, ds);
+    if (refine) {
+      // r = B - M_i g^<_i M_i^H ; g^<_i += g_i r g_i^H
+      const double2* Mi = pw.Mst + (long)i * bb;
+      cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, Mi, ds, gli, ds, ZERO, nullptr, 0, pw.T2.p, bb);
+      cx.gemm(PREC_F64, OP_N, OP_C, b, n, MONE, pw.T2.p, bb, Mi, ds, ONE, pw.T4.p, bb, pw.T4.p, bb);
+      cx.gemm(PREC_F32, OP_N, OP_N, b, n, ONE, gi, ds, pw.T4.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
+      cx.gemm(PREC_F32, OP_N, OP_C, b, n, ONE, pw.T3.p, bb, gi, ds, ONE, gli, ds, gli, ds);
+    }
+  }
+}
+
+void backward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, const double2* GRd,
+                     const double2* GRu, double2* Ld, double2* Lu) {
+  const int b = ch.b, nb = ch.nb, n = ch.npts;
+  const long bb = (long)b * b, ds = (long)nb * bb, us = (long)(nb - 1) * bb;
+  const Prec pp = (prec == NEGF_FP32_NOREFINE) ? PREC_F32 : PREC_F64;
+  for (int i = nb - 2; i >= 0 && cx.ok(); --i) {
+    assemble_upper(cx, ch, i, pw.T1);
+    double2* gli = Ld + (long)i * bb;                 // holds g^<_i
+    const double2* Xi = pw.X + (long)i * bb;
+    // V = A_{i+1,i} g^<_i
+    cx.gemm(pp, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gli, ds, ZERO, nullptr, 0, pw.T2.p, bb);
+    // Q = -G_{i,i+1} V
+    cx.gemm(pp, OP_N, OP_N, b, n, MONE, GRu + (long)i * bb, us, pw.T2.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
+    // Z = X_i G^<_{i+1,i+1}
+    cx.gemm(pp, OP_N, OP_N, b, n, ONE, Xi, us, Ld + (long)(i + 1) * bb, ds, ZERO, nullptr, 0, pw.T4.p, bb);
+    // G^<_ii = g^<_i + Z X_i^H + Q - Q^H
+    cx.gemm(pp, OP_N, OP_C, b, n, ONE, pw.T4.p, bb, Xi, us, ONE, gli, ds, gli, ds);
+    cx.chk(launch_add_skew(b, n, pw.T3.p, bb, gli, ds, cx.s));
+    // G^<_{i,i+1} = V^H G_{i+1,i+1}^H - Z
+    cx.gemm(pp, OP_C, OP_C, b, n, ONE, pw.T2.p, bb, GRd + (long)(i + 1) * bb, ds, MONE, pw.T4.p, bb,
+            Lu + (long)i * bb, us);
+  }
+}
+
+// ------------------------------------------------------------------ argument checks
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+negf_status check_problems(const negf_problem* pr, int n_prob) {
+  if (!pr || n_prob <= 0) return NEGF_EINVAL;
+  for (int q = 0; q < n_prob; ++q) {
+    const negf_device& d = pr[q].dev;
+    if (d.nb < 2 || d.b < 1 || d.b > 1024) return NEGF_EINVAL;
+    if (!d.H_diag || !d.H_upper) return NEGF_EINVAL;
+    if (pr[q].n_e < 0) return NEGF_EINVAL;
+    if (pr[q].n_e > 0 && !pr[q].energies) return NEGF_EINVAL;
+    if (!(pr[q].eta >= 0.0) || !(pr[q].kT >= 0.0)) return NEGF_EINVAL;
+    const void* ptrs[] = {d.H_diag, d.H_upper, d.S_diag, d.S_upper, d.sig_r_sc, d.sig_l_sc, d.sig_g_sc};
+    for (const void* p : ptrs)
+      if (p && !aligned16(p)) return NEGF_EINVAL;
+    if ((d.S_diag == nullptr) != (d.S_upper == nullptr)) return NEGF_EINVAL;
+    if ((d.sig_l_sc == nullptr) != (d.sig_g_sc == nullptr)) return NEGF_EINVAL;
+  }
+  return NEGF_OK;
+}
+
+long count_points(const negf_problem* pr, int n_prob) {
+  long n = 0;
+  for (int q = 0; q < n_prob; ++q) n += pr[q].n_e;
+  return n;
+}
+
+size_t workspace_for(int opk, const negf_problem* pr, int n_prob, negf_precision prec, const Opts& o) {
+  size_t mx = 0;
+  for (const Chunk& ch : make_chunks(pr, n_prob, o.batch)) {
+    Carver cv{nullptr, 0};
+    carve_chunk(cv, opk, ch.nb, ch.b, ch.npts, prec, opk == OPK_OBC ? 1 : 2);
+    mx = std::max(mx, cv.off);
+  }
+  return mx + 256;
+}
+
+char* align256(void* p) { return (char*)(((uintptr_t)p + 255) & ~(uintptr_t)255); }
+
+negf_status to_status(hipError_t e) { return e == hipSuccess ? NEGF_OK : NEGF_EHIP; }
+
+// ------------------------------------------------------------------ profiling state
+
+struct ProfRec {
+  hipEvent_t a, b;
+  int cls;
+  double flops, bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+negf_kernel_stats g_prof_acc[KC_COUNT];
+thread_local hipEvent_t t_open = nullptr;
+
+hipEvent_t pool_get() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ profiling hooks
+
+namespace negf {
+
+void prof_begin(int cls, hipStream_t s) {
+  (void)cls;
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  t_open = pool_get();
+  if (t_open) hipEventRecord(t_open, s);
+}
+
+void prof_end(int cls, hipStream_t s, double flops, double bytes) {
+  if (!g_prof_on || !t_open) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t e = pool_get();
+  if (!e) return;
+  hipEventRecord(e, s);
+  g_prof_pending.push_back(ProfRec{t_open, e, cls, flops, bytes});
+  t_open = nullptr;
+}
+
+}  // namespace negf
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+size_t negf_workspace_bytes(int32_t op, const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                            const negf_options* opt) {
+  if (check_problems(problems, n_prob) != NEGF_OK) return 0;
+  const int opk = op == NEGF_OP_OBC ? OPK_OBC : op == NEGF_OP_RETARDED ? OPK_R
+                : op == NEGF_OP_LESSER_GREATER ? OPK_RL : OPK_T;
+  return workspace_for(opk, problems, n_prob, prec, get_opts(opt));
+}
+
+negf_status negf_obc_surface(const negf_problem* problems, int32_t n_prob, int32_t side, const negf_options* opt,
+                             const void* seed, void* g_surf, void* sigma_r, int32_t* iters, double* resid,
+                             int32_t* info, void* workspace, size_t ws_bytes, void* stream) {
+  negf_status st = check_problems(problems, n_prob);
+  if (st != NEGF_OK) return st;
+  if (side != 0 && side != 1) return NEGF_EINVAL;
+  if (!g_surf || !sigma_r || !info || !workspace) return NEGF_EINVAL;
+  if (!aligned16(g_surf) || !aligned16(sigma_r) || (seed && !aligned16(seed))) return NEGF_EINVAL;
+  const Opts o = get_opts(opt);
+  if (ws_bytes < workspace_for(OPK_OBC, problems, n_prob, NEGF_PLAIN_FP64, o)) return NEGF_EINVAL;
+  Ctx cx;
+  cx.s = (hipStream_t)stream;
+  cx.o = o;
+  const long npts_all = count_points(problems, n_prob);
+  cx.chk(launch_fill_int((int)npts_all, info, 0, cx.s));
+  for (const Chunk& ch : make_chunks(problems, n_prob, o.batch)) {
+    Carver cv{align256(workspace), ws_bytes - (size_t)(align256(workspace) - (char*)workspace)};
+    ChunkWs w = carve_chunk(cv, OPK_OBC, ch.nb, ch.b, ch.npts, NEGF_PLAIN_FP64, 1);
+    if (cv.overflow) return NEGF_EINVAL;
+    const long bb = (long)ch.b * ch.b;
+    const long pofs = (long)ch.first_point * bb;   // all points of an OBC call share b only per chunk
+    // outputs are [points][b][b]: offset by the blocks of the previous points
+    size_t blk_off = 0;
+    {
+      long gp = 0;
+      for (int q = 0; q < n_prob && gp < ch.first_point; ++q) {
+        const long take = std::min<long>(problems[q].n_e, ch.first_point - gp);
+        blk_off += (size_t)take * problems[q].dev.b * problems[q].dev.b;
+        gp += take;
+      }
+    }
+    (void)pofs;
+    Blocks sig{(double2*)sigma_r + blk_off, bb};
+    const int sides[1] = {side};
+    const double2* sd = seed ? (const double2*)seed + blk_off : nullptr;
+    run_decimation(cx, ch, sides, 1, w.lw, sd, bb, sig, sig, info + ch.first_point,
+                   iters ? iters + ch.first_point : nullptr, resid ? resid + ch.first_point : nullptr, nullptr);
+    cx.lincomb(ch.b, ch.npts, ONE, w.lw.g.p, bb, ZERO, nullptr, 0, ZERO, (double2*)g_surf + blk_off, bb);
+    if (!cx.ok()) break;
+  }
+  return to_status(cx.err);
+}
+
+static negf_status rgf_common(int opk, const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                              const negf_options* opt, const Outs& outs, void* workspace, size_t ws_bytes,
+                              void* stream) {
+  negf_status st = check_problems(problems, n_prob);
+  if (st != NEGF_OK) return st;
+  if (prec != NEGF_PLAIN_FP64 && prec != NEGF_FP32_REFINE && prec != NEGF_FP32_NOREFINE) return NEGF_EINVAL;
+  if (!outs.info || !workspace) return NEGF_EINVAL;
+  const Opts o = get_opts(opt);
+  if (ws_bytes < workspace_for(opk, problems, n_prob, prec, o)) return NEGF_EINVAL;
+  Ctx cx;
+  cx.s = (hipStream_t)stream;
+  cx.o = o;
+  const long npts_all = count_points(problems, n_prob);
+  cx.chk(launch_fill_int((int)npts_all, outs.info, 0, cx.s));
+  const bool lesser = opk == OPK_RL;
+  for (const Chunk& ch : make_chunks(problems, n_prob, o.batch)) {
+    Carver cv{align256(workspace), ws_bytes - (size_t)(align256(workspace) - (char*)workspace)};
+    ChunkWs w = carve_chunk(cv, opk, ch.nb, ch.b, ch.npts, prec, 2);
+    if (cv.overflow) return NEGF_EINVAL;
+    int* info = outs.info + ch.first_point;
+    leads_for_sweeps(cx, ch, w, info, lesser);
+    const long bb = (long)ch.b * ch.b;
+    if (opk == OPK_T) {
+      // g ping-pong is not needed for T: store g_i in a per-point rolling pair of blocks
+      Blocks corner;
+      // gdiag needs nb blocks per point only for the previous block: use X region absent;
+      // keep g_i in C0/C1-independent storage: T2 (current) / T4 (previous) alternate
+      const int b = ch.b, nb = ch.nb, n = ch.npts;
+      Blocks C = w.pw.C0, Cn = w.pw.C1, gcur = w.pw.T2, gprev = w.pw.T4;
+      for (int i = 0; i < nb && cx.ok(); ++i) {
+        assemble_diag(cx, ch, i, w.pw, w.pw.T0);
+        if (i > 0) {
+          assemble_upper(cx, ch, i - 1, w.pw.T1);
+          cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, gprev.p, bb, w.pw.T1.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb);
+          cx.gemm(PREC_F64, OP_C, OP_N, b, n, MONE, w.pw.T1.p, bb, w.pw.T3.p, bb, ONE, w.pw.T0.p, bb, w.pw.T0.p, bb);
+        }
+        cx.inverse(b, n, w.pw.T0.p, bb, gcur.p, bb, w.pw.inv_scratch, info, 0);
+        if (i == 0) {
+          cx.lincomb(b, n, ONE, gcur.p, bb, ZERO, nullptr, 0, ZERO, C.p, bb);
+        } else {
+          cx.gemm(PREC_F64, OP_C, OP_N, b, n, ONE, w.pw.T1.p, bb, C.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb);
+          cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, gcur.p, bb, w.pw.T3.p, bb, ZERO, nullptr, 0, Cn.p, bb);
+          std::swap(C, Cn);
+        }
+        std::swap(gcur, gprev);
+      }
+      corner = C;
+      // T = Re sum (Gamma_R C) .* conj(C Gamma_L)
+      cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, w.pw.gamR.p, bb, corner.p, bb, ZERO, nullptr, 0, w.pw.T0.p, bb);
+      cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, corner.p, bb, w.pw.gamL.p, bb, ZERO, nullptr, 0, w.pw.T1.p, bb);
+      cx.chk(launch_dot_re(b, n, w.pw.T0.p, bb, w.pw.T1.p, bb, outs.T + ch.first_point, cx.s));
+      if (!cx.ok()) break;
+      continue;
+    }
+    const long ds = (long)ch.nb * bb;
+    double2* GRd = outs.GRd + ch.out_diag_off;
+    forward_retarded(cx, ch, w.pw, prec, GRd, ds, info, true, nullptr);
+    if (lesser) {
+      forward_lesser(cx, ch, w.pw, prec, 0, GRd, outs.GLd + ch.out_diag_off);
+      if (outs.GGd) forward_lesser(cx, ch, w.pw, prec, 1, GRd, outs.GGd + ch.out_diag_off);
+    }
+    backward_retarded(cx, ch, w.pw, prec, outs);
+    if (lesser) {
+      const double2* GRu = outs.GRu + ch.out_off_off;
+      backward_lesser(cx, ch, w.pw, prec, GRd, GRu, outs.GLd + ch.out_diag_off, outs.GLu + ch.out_off_off);
+      if (outs.GGd)
+        backward_lesser(cx, ch, w.pw, prec, GRd, GRu, outs.GGd + ch.out_diag_off, outs.GGu + ch.out_off_off);
+    }
+    if (!cx.ok()) break;
+  }
+  return to_status(cx.err);
+}
+
+negf_status negf_rgf_retarded(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                              const negf_options* opt, void* GR_diag, void* GR_upper, void* GR_lower, int32_t* info,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  if (!GR_diag || !GR_upper) return NEGF_EINVAL;
+  if (!aligned16(GR_diag) || !aligned16(GR_upper) || (GR_lower && !aligned16(GR_lower))) return NEGF_EINVAL;
+  Outs o{(double2*)GR_diag, (double2*)GR_upper, (double2*)GR_lower, nullptr, nullptr, nullptr, nullptr, info, nullptr};
+  return rgf_common(OPK_R, problems, n_prob, prec, opt, o, workspace, ws_bytes, stream);
+}
+
+negf_status negf_rgf_lesser_greater(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                                    const negf_options* opt, void* GR_diag, void* GR_upper, void* GR_lower,
+                                    void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  if (!GR_diag || !GR_upper || !GL_diag || !GL_upper) return NEGF_EINVAL;
+  if ((GG_diag == nullptr) != (GG_upper == nullptr)) return NEGF_EINVAL;
+  const void* ps[] = {GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper};
+  for (const void* p : ps)
+    if (p && !aligned16(p)) return NEGF_EINVAL;
+  Outs o{(double2*)GR_diag, (double2*)GR_upper, (double2*)GR_lower, (double2*)GL_diag, (double2*)GL_upper,
+         (double2*)GG_diag, (double2*)GG_upper, info, nullptr};
+  return rgf_common(OPK_RL, problems, n_prob, prec, opt, o, workspace, ws_bytes, stream);
+}
+
+negf_status negf_transmission(const negf_problem* problems, int32_t n_prob, const negf_options* opt, double* T,
+                              int32_t* info, void* workspace, size_t ws_bytes, void* stream) {
+  if (!T) return NEGF_EINVAL;
+  Outs o{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, info, T};
+  return rgf_common(OPK_T, problems, n_prob, NEGF_PLAIN_FP64, opt, o, workspace, ws_bytes, stream);
+}
+
+negf_status negf_zgemm_batched(char opa, char opb, int32_t M, int32_t N, int32_t K, const double* alpha,
+                               const void* A, int64_t lda, int64_t sa, const void* B, int64_t ldb, int64_t sb,
+                               const double* beta, void* C, int64_t ldc, int64_t sc, int32_t batch, int32_t prec,
+                               int32_t tile, void* stream) {
+  if (M < 0 || N < 0 || K < 0 || batch < 0 || !alpha || !beta) return NEGF_EINVAL;
+  if ((opa != 'N' && opa != 'C') || (opb != 'N' && opb != 'C')) return NEGF_EINVAL;
+  if (M == 0 || N == 0 || batch == 0) return NEGF_OK;
+  if (!A || !B || !C || !aligned16(A) || !aligned16(B) || !aligned16(C)) return NEGF_EINVAL;
+  GemmDesc g{};
+  g.M = M; g.N = N; g.K = K; g.batch = batch;
+  g.opA = opa == 'N' ? OP_N : OP_C;
+  g.opB = opb == 'N' ? OP_N : OP_C;
+  g.A = MatRef{(const double2*)A, (long)lda, (long)sa};
+  g.B = MatRef{(const double2*)B, (long)ldb, (long)sb};
+  g.alpha = make_double2(alpha[0], alpha[1]);
+  g.beta = make_double2(beta[0], beta[1]);
+  g.Cin = MatRef{(const double2*)C, (long)ldc, (long)sc};
+  g.C = MatOut{(double2*)C, (long)ldc, (long)sc};
+  g.prec = prec == 1 ? PREC_F32 : PREC_F64;
+  g.tile = tile;
+  g.xcd_remap = 1;
+  g.prof_class = -1;
+  return to_status(launch_gemm(g, (hipStream_t)stream));
+}
+
+size_t negf_inverse_workspace_bytes(int32_t n, int32_t batch) {
+  if (n <= 0 || batch <= 0) return 0;
+  return inverse_scratch_bytes(n, batch) + 256;
+}
+
+negf_status negf_zinv_batched(int32_t n, int32_t batch, void* M, void* out, int32_t* info, int32_t nb,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  if (n <= 0 || n > 1024 || batch < 0) return NEGF_EINVAL;
+  if (batch == 0) return NEGF_OK;
+  if (!M || !out || M == out || !workspace || !aligned16(M) || !aligned16(out)) return NEGF_EINVAL;
+  if (ws_bytes < negf_inverse_workspace_bytes(n, batch)) return NEGF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (info) {
+    hipError_t e = launch_fill_int(batch, info, 0, s);
+    if (e != hipSuccess) return NEGF_EHIP;
+  }
+  InvDesc d{};
+  d.n = n; d.batch = batch;
+  d.M = (double2*)M; d.ldm = n; d.sM = (long)n * n;
+  d.out = (double2*)out; d.ldo = n; d.sO = (long)n * n;
+  d.scratch = align256(workspace);
+  d.info = info; d.info_mod = 0;
+  d.nb = nb;
+  return to_status(launch_inverse(d, s));
+}
+
+void negf_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  if (on) {
+    for (auto& r : g_prof_pending) {
+      g_prof_pool.push_back(r.a);
+      g_prof_pool.push_back(r.b);
+    }
+    g_prof_pending.clear();
+    std::memset(g_prof_acc, 0, sizeof(g_prof_acc));
+  }
+}
+
+negf_status negf_profile_read(negf_kernel_stats* stats) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  negf_status st = NEGF_OK;
+  for (auto& r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      st = NEGF_EHIP;
+    } else {
+      negf_kernel_stats& a = g_prof_acc[r.cls];
+      a.launches += 1;
+      a.total_ms += ms;
+      a.flops += r.flops;
+      a.bytes += r.bytes;
+    }
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_pending.clear();
+  if (stats)
+    for (int i = 0; i < NEGF_KC_COUNT; ++i) stats[i] = i < KC_COUNT ? g_prof_acc[i] : negf_kernel_stats{};
+  return st;
+}
+
+const char* negf_status_string(negf_status s) {
+  switch (s) {
+    case NEGF_OK: return "ok";
+    case NEGF_EINVAL: return "invalid argument";
+    case NEGF_ENOCONV: return "lead decimation did not converge";
+    case NEGF_ESINGULAR: return "singular block";
+    case NEGF_ENONFINITE: return "non-finite value";
+    case NEGF_EHIP: return "HIP runtime error";
+    case NEGF_ENOMEM: return "out of memory";
+  }
+  return "unknown status";
+}
+
+int32_t negf_version(void) { return 100; }
+
+}  // extern "C"

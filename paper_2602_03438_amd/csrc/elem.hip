@@ -1,0 +1,395 @@
+// Element-wise and reduction kernels: assembly of the blocks of z S - H - Sigma,
+// lead self-energy post-processing, skew updates, norms and traces.
+// All of them stream b x b complex blocks through HBM with coalesced 16-byte
+// accesses; those that need a conjugate transpose go through 32 x 32 LDS tiles.
+#include "internal.h"
+
+namespace negf {
+
+namespace {
+
+constexpr int TD = 32;   // transpose tile edge
+constexpr int TR = 8;    // rows per thread pass (block = 32 x 8)
+
+__device__ __forceinline__ double2 ld_or0(const double2* p, long i) { return p ? p[i] : make_double2(0.0, 0.0); }
+
+// out_p = zc_p op(S) + h op(H) + y Y + zc Z_p  (see AssembleDesc)
+__global__ void __launch_bounds__(TD * TR) assemble_kernel(AssembleDesc d) {
+  const int p = blockIdx.z;
+  if (d.active && d.active[p] == 0) return;
+  const int b = d.b;
+  const double e = d.energies ? d.energies[p] : 0.0;
+  const double2 zc = make_double2(d.s_coef * e, d.s_coef * d.eta);
+  const int i0 = blockIdx.y * TD, j0 = blockIdx.x * TD;
+  __shared__ double2 tS[TD][TD + 1];
+  __shared__ double2 tH[TD][TD + 1];
+  if (d.op == 1) {
+    // stage the source tile (rows j0.., cols i0..) of S and H
+    for (int rr = threadIdx.y; rr < TD; rr += TR) {
+      const int sr = j0 + rr, sc = i0 + threadIdx.x;
+      double2 sv = make_double2(0.0, 0.0), hv = make_double2(0.0, 0.0);
+      if (sr < b && sc < b) {
+        if (d.S) sv = d.S[(long)sr * b + sc];
+        else if (d.s_identity && sr == sc) sv = make_double2(1.0, 0.0);
+        if (d.H) hv = d.H[(long)sr * b + sc];
+      }
+      tS[rr][threadIdx.x] = sv;
+      tH[rr][threadIdx.x] = hv;
+    }
+    __syncthreads();
+  }
+  for (int rr = threadIdx.y; rr < TD; rr += TR) {
+    const int i = i0 + rr, j = j0 + threadIdx.x;
+    if (i >= b || j >= b) continue;
+    const long o = (long)i * b + j;
+    double2 sv, hv;
+    if (d.op == 1) {
+      sv = cconj(tS[threadIdx.x][rr]);
+      hv = cconj(tH[threadIdx.x][rr]);
+    } else {
+      sv = d.S ? d.S[o] : make_double2((d.s_identity && i == j) ? 1.0 : 0.0, 0.0);
+      hv = ld_or0(d.H, o);
+    }
+    double2 r = cmul(zc, sv);
+    r.x += d.h_coef * hv.x;
+    r.y += d.h_coef * hv.y;
+    if (d.Y) {
+      const double2 y = d.Y[o];
+      r.x += d.y_coef * y.x;
+      r.y += d.y_coef * y.y;
+    }
+    if (d.Z) {
+      const double2 z = d.Z[(long)p * d.sZ + o];
+      r.x += d.z_coef * z.x;
+      r.y += d.z_coef * z.y;
+    }
+    d.out[(long)p * d.sOut + o] = r;
+  }
+}
+
+__global__ void copy_kernel(long n, int batch, const double2* src, long sS, double2* dst, long sD) {
+  const int p = blockIdx.y;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[(long)p * sD + i] = src[(long)p * sS + i];
+}
+
+__global__ void sub2_kernel(long n, const double2* x, long sx, double2* a, long sa, double2* c, long sc,
+                            const int* active) {
+  const int p = blockIdx.y;
+  if (active && active[p] == 0) return;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double2 v = x[(long)p * sx + i];
+    double2 t = a[(long)p * sa + i];
+    a[(long)p * sa + i] = csub(t, v);
+    t = c[(long)p * sc + i];
+    c[(long)p * sc + i] = csub(t, v);
+  }
+}
+
+template <int NT>
+__device__ double block_sum(double v) {
+  __shared__ double red[NT / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  return s;
+}
+
+constexpr int RED_NT = 512;
+
+__global__ void __launch_bounds__(RED_NT) frob2_kernel(int b, const double2* X, long sX, double shift, double* out) {
+  const int p = blockIdx.x;
+  const double2* x = X + (long)p * sX;
+  const long n = (long)b * b;
+  double s = 0.0;
+  for (long i = threadIdx.x; i < n; i += RED_NT) {
+    double2 v = x[i];
+    if (shift != 0.0 && (i / b) == (i % b)) v.x -= shift;
+    s += v.x * v.x + v.y * v.y;
+  }
+  s = block_sum<RED_NT>(s);
+  if (threadIdx.x == 0) out[p] = s;
+}
+
+__global__ void __launch_bounds__(RED_NT) dot_re_kernel(int b, const double2* P, long sP, const double2* Q, long sQ,
+                                                        double* out) {
+  const int p = blockIdx.x;
+  const long n = (long)b * b;
+  double s = 0.0;
+  for (long i = threadIdx.x; i < n; i += RED_NT) {
+    const double2 u = P[(long)p * sP + i], v = Q[(long)p * sQ + i];
+    s += u.x * v.x + u.y * v.y;
+  }
+  s = block_sum<RED_NT>(s);
+  if (threadIdx.x == 0) out[p] = s;
+}
+
+// One workgroup: updates the active flags of every item and counts the survivors.
+__global__ void __launch_bounds__(1024) sr_check_kernel(int batch, const double* a2, const double* c2,
+                                                        const double* d2, double tol, int iter, int* active,
+                                                        int* iters, int* n_active) {
+  int cnt = 0;
+  for (int p = threadIdx.x; p < batch; p += blockDim.x) {
+    if (active[p]) {
+      const double lim = tol * tol * d2[p];
+      const bool bad = !(a2[p] == a2[p]) || !(c2[p] == c2[p]);
+      if ((a2[p] <= lim && c2[p] <= lim) || bad) {
+        active[p] = 0;
+        iters[p] = bad ? -iter : iter;
+      } else {
+        iters[p] = iter;
+        cnt++;
+      }
+    }
+  }
+  __shared__ int red[16];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int i = 0; i < (int)((blockDim.x + 63) >> 6); ++i) s += red[i];
+    *n_active = s;
+  }
+}
+
+__global__ void sr_finish_kernel(int batch, const double* r2, const double* m2, const double* g2, const int* active,
+                                 double accept, double* resid, int* info, int info_mod) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= batch) return;
+  const double r = sqrt(r2[p]) / (sqrt(m2[p]) * sqrt(g2[p]));
+  if (resid) resid[p] = r;
+  int st = ST_OK;
+  if (!(r == r) || !isfinite(r2[p])) st = ST_ENONFINITE;
+  else if ((active && active[p]) || r > accept) st = ST_ENOCONV;
+  if (st != ST_OK && info) atomicCAS(info + (info_mod > 0 ? p % info_mod : p), ST_OK, st);
+}
+
+// gamma = i (S - S^H); sl = i f gamma; sg = -i (1 - f) gamma
+__global__ void __launch_bounds__(TD * TR) gamma_sigma_kernel(int b, const double2* sig, long sS,
+                                                              const double* energies, double mu, double kT,
+                                                              double2* gamma, long sG, double2* sl, long sL,
+                                                              double2* sg, long sGr) {
+  const int p = blockIdx.z;
+  const int i0 = blockIdx.y * TD, j0 = blockIdx.x * TD;
+  __shared__ double2 t[TD][TD + 1];
+  const double2* S = sig + (long)p * sS;
+  for (int rr = threadIdx.y; rr < TD; rr += TR) {
+    const int sr = j0 + rr, sc = i0 + threadIdx.x;
+    t[rr][threadIdx.x] = (sr < b && sc < b) ? S[(long)sr * b + sc] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double f = 0.0;
+  if (sl || sg) {
+    const double x = energies[p] - mu;
+    if (kT > 0.0) {
+      const double y = x / kT;
+      f = y > 0 ? exp(-y) / (1.0 + exp(-y)) : 1.0 / (1.0 + exp(y));
+    } else {
+      f = x < 0 ? 1.0 : (x == 0 ? 0.5 : 0.0);
+    }
+  }
+  for (int rr = threadIdx.y; rr < TD; rr += TR) {
+    const int i = i0 + rr, j = j0 + threadIdx.x;
+    if (i >= b || j >= b) continue;
+    const long o = (long)i * b + j;
+    const double2 s = S[o];
+    const double2 sh = cconj(t[threadIdx.x][rr]);   // (S^H)_ij = conj(S_ji)
+    const double2 dlt = csub(s, sh);
+    const double2 g = make_double2(-dlt.y, dlt.x);  // i * (S - S^H)
+    if (gamma) gamma[(long)p * sG + o] = g;
+    if (sl) sl[(long)p * sL + o] = make_double2(-f * g.y, f * g.x);                  // i f g
+    if (sg) sg[(long)p * sGr + o] = make_double2((1.0 - f) * g.y, -(1.0 - f) * g.x);  // -i (1-f) g
+  }
+}
+
+// C += Q - Q^H
+__global__ void __launch_bounds__(TD * TR) add_skew_kernel(int b, const double2* Qb, long sQ, double2* Cb, long sC) {
+  const int p = blockIdx.z;
+  const int i0 = blockIdx.y * TD, j0 = blockIdx.x * TD;
+  __shared__ double2 t[TD][TD + 1];
+  const double2* Q = Qb + (long)p * sQ;
+  double2* C = Cb + (long)p * sC;
+  for (int rr = threadIdx.y; rr < TD; rr += TR) {
+    const int sr = j0 + rr, sc = i0 + threadIdx.x;
+    t[rr][threadIdx.x] = (sr < b && sc < b) ? Q[(long)sr * b + sc] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int rr = threadIdx.y; rr < TD; rr += TR) {
+    const int i = i0 + rr, j = j0 + threadIdx.x;
+    if (i >= b || j >= b) continue;
+    const long o = (long)i * b + j;
+    const double2 q = Q[o];
+    const double2 qh = cconj(t[threadIdx.x][rr]);
+    const double2 c = C[o];
+    C[o] = make_double2(c.x + q.x - qh.x, c.y + q.y - qh.y);
+  }
+}
+
+__global__ void __launch_bounds__(RED_NT) check_finite_kernel(int b, const double2* X, long sX, int* info,
+                                                              int info_mod) {
+  const int p = blockIdx.x;
+  const long n = (long)b * b;
+  int bad = 0;
+  for (long i = threadIdx.x; i < n; i += RED_NT) {
+    const double2 v = X[(long)p * sX + i];
+    if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+  }
+  if (bad) atomicCAS(info + (info_mod > 0 ? p % info_mod : p), ST_OK, ST_ENONFINITE);
+}
+
+__global__ void lincomb_kernel(int b, double2 c1, const double2* X, long sX, double2 c2, const double2* Y, long sY,
+                               double2 g, double2* out, long sOut, const int* active) {
+  const int p = blockIdx.y;
+  if (active && active[p] == 0) return;
+  const long n = (long)b * b;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double2 r = make_double2(0.0, 0.0);
+    if (X) r = cmul(c1, X[(long)p * sX + i]);
+    if (Y) r = cadd(r, cmul(c2, Y[(long)p * sY + i]));
+    if ((i / b) == (i % b)) r = cadd(r, g);
+    out[(long)p * sOut + i] = r;
+  }
+}
+
+__global__ void seed_flags_kernel(int np, const int* flags, int* active, int* iters) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  active[p] = flags[p] == ST_OK ? 0 : 1;
+  iters[p] = 0;
+}
+
+__global__ void seed_select_kernel(long n, const int* flags, const double2* g_dec, double2* g) {
+  const int p = blockIdx.y;
+  if (flags[p] == ST_OK) return;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    g[(long)p * n + i] = g_dec[(long)p * n + i];
+}
+
+__global__ void fill_int_kernel(int n, int* p, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned grid_for(long n) {
+  long g = (n + 255) / 256;
+  return (unsigned)(g < 1024 ? g : 1024);
+}
+
+}  // namespace
+
+hipError_t launch_assemble(const AssembleDesc& d, hipStream_t s) {
+  if (d.batch <= 0) return hipSuccess;
+  const int nt = (d.b + TD - 1) / TD;
+  prof_begin(KC_ELEM, s);
+  hipLaunchKernelGGL(assemble_kernel, dim3(nt, nt, d.batch), dim3(TD, TR), 0, s, d);
+  prof_end(KC_ELEM, s, 0, 16.0 * d.b * d.b * d.batch * 3);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_blocks(int b, int batch, const double2* src, long sS, double2* dst, long sD, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const long n = (long)b * b;
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n), batch), dim3(256), 0, s, n, batch, src, sS, dst, sD);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub2(int b, int batch, const double2* x, long sx, double2* a, long sa, double2* c, long sc,
+                       const int* active, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const long n = (long)b * b;
+  hipLaunchKernelGGL(sub2_kernel, dim3(grid_for(n), batch), dim3(256), 0, s, n, x, sx, a, sa, c, sc, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, double* nrm2, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(frob2_kernel, dim3(batch), dim3(RED_NT), 0, s, b, X, sX, shift, nrm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_sr_check(int batch, const double* a2, const double* c2, const double* d2, double tol, int iter,
+                           int* active, int* iters, int* n_active, hipStream_t s) {
+  hipLaunchKernelGGL(sr_check_kernel, dim3(1), dim3(1024), 0, s, batch, a2, c2, d2, tol, iter, active, iters,
+                     n_active);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_sigma(int b, int batch, const double2* sig, long sS, const double* energies, double mu,
+                              double kT, double2* gamma, long sG, double2* sl, long sL, double2* sg, long sGr,
+                              hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const int nt = (b + TD - 1) / TD;
+  hipLaunchKernelGGL(gamma_sigma_kernel, dim3(nt, nt, batch), dim3(TD, TR), 0, s, b, sig, sS, energies, mu, kT,
+                     gamma, sG, sl, sL, sg, sGr);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_skew(int b, int batch, const double2* Q, long sQ, double2* C, long sC, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const int nt = (b + TD - 1) / TD;
+  prof_begin(KC_ELEM, s);
+  hipLaunchKernelGGL(add_skew_kernel, dim3(nt, nt, batch), dim3(TD, TR), 0, s, b, Q, sQ, C, sC);
+  prof_end(KC_ELEM, s, 0, 16.0 * b * b * batch * 4);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_re(int b, int batch, const double2* P, long sP, const double2* Q, long sQ, double* out,
+                         hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dot_re_kernel, dim3(batch), dim3(RED_NT), 0, s, b, P, sP, Q, sQ, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sr_finish(int batch, const double* r2, const double* m2, const double* g2, const int* active,
+                            double accept, double* resid_out, int* info, int info_mod, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sr_finish_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, batch, r2, m2, g2, active, accept,
+                     resid_out, info, info_mod);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(int b, int batch, const double2* X, long sX, int* info, int info_mod, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(check_finite_kernel, dim3(batch), dim3(RED_NT), 0, s, b, X, sX, info, info_mod);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(int b, int batch, double2 c1, const double2* X, long sX, double2 c2, const double2* Y,
+                          long sY, double2 g, double2* out, long sOut, const int* active, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const long n = (long)b * b;
+  prof_begin(KC_ELEM, s);
+  hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for(n), batch), dim3(256), 0, s, b, c1, X, sX, c2, Y, sY, g, out, sOut,
+                     active);
+  prof_end(KC_ELEM, s, 0, 16.0 * n * batch * ((X ? 1 : 0) + (Y ? 1 : 0) + 1));
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_flags(int np, const int* flags, int* active, int* iters, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(seed_flags_kernel, dim3((np + 255) / 256), dim3(256), 0, s, np, flags, active, iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_select(int b, int np, const int* flags, const double2* g_dec, double2* g, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  const long n = (long)b * b;
+  hipLaunchKernelGGL(seed_select_kernel, dim3(grid_for(n), np), dim3(256), 0, s, n, flags, g_dec, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int n, int* p, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, p, v);
+  return hipGetLastError();
+}
+
+}  // namespace negf

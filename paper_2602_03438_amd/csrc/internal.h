@@ -1,0 +1,124 @@
+// Internal launch interfaces of the NEGF library (not part of the public ABI).
+#pragma once
+#include "common.h"
+
+namespace negf {
+
+enum Op { OP_N = 0, OP_C = 1 };          // op(X) = X or X^H
+enum Prec { PREC_F64 = 0, PREC_F32 = 1 };  // arithmetic of the product
+
+// A batch of b x b (or M x K ...) complex matrices: item p starts at p * stride.
+struct MatRef {
+  const double2* p;
+  long ld;
+  long stride;
+};
+struct MatOut {
+  double2* p;
+  long ld;
+  long stride;
+};
+
+// C_p = alpha * op(A_p) op(B_p) + beta * Cin_p  for every batch item p.
+struct GemmDesc {
+  int M, N, K, batch;
+  Op opA, opB;
+  MatRef A, B;
+  double2 alpha, beta;
+  MatRef Cin;          // read only when beta != 0; may alias C
+  MatOut C;
+  const int* active;   // nullable: item p is skipped when active[p] == 0
+  Prec prec;
+  int tile;            // 0 = default tile shape; see gemm.hip
+  int xcd_remap;       // group the tiles of one batch item on one XCD
+  int prof_class;      // -1: by precision
+};
+hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
+
+// Blocked Gauss-Jordan inversion with partial pivoting of a batch of n x n
+// matrices.  M is overwritten; the inverse is written to out (may not alias M).
+struct InvDesc {
+  int n, batch;
+  double2* M;
+  long ldm, sM;
+  double2* out;
+  long ldo, sO;
+  void* scratch;        // inverse_scratch_bytes(n, batch)
+  int* info;            // nullable; item p reports into info[p % info_mod]
+  int info_mod;         // 0: info[p]
+  const int* active;    // nullable
+  int nb;               // panel width (16 or 32; 0 = default)
+};
+size_t inverse_scratch_bytes(int n, int batch);
+hipError_t launch_inverse(const InvDesc& d, hipStream_t s);
+
+// ---- element-wise and reduction kernels (elem.hip) ----
+// All "blocks" are b x b interleaved complex, batch item p at base + p * stride.
+
+// out_p = zc_p * op(S) + h_coef * op(H) + y_coef * Y + z_coef * Z_p, with
+// zc_p = s_coef * (energies[p] + i * eta) and op = identity or conjugate
+// transpose (applied to S and H only).  S == nullptr means identity when
+// s_identity is set and zero otherwise; H, Y, Z may be null (zero).
+// Y is shared by the whole batch; Z_p is per item.
+struct AssembleDesc {
+  int b, batch;
+  const double* energies;   // device, one per item; nullptr => 0
+  double eta, s_coef;
+  const double2* S;
+  int s_identity;
+  const double2* H;
+  double h_coef;
+  int op;                   // 0: as stored, 1: conjugate transpose of S and H
+  const double2* Y;
+  double y_coef;
+  const double2* Z;
+  long sZ;
+  double z_coef;
+  double2* out;
+  long sOut;
+  const int* active;
+};
+hipError_t launch_assemble(const AssembleDesc& d, hipStream_t s);
+
+// dst_p = src_p (plain copy of a batch of b x b blocks)
+hipError_t launch_copy_blocks(int b, int batch, const double2* src, long sS, double2* dst, long sD, hipStream_t s);
+// a_p -= x_p ; c_p -= x_p
+hipError_t launch_sub2(int b, int batch, const double2* x, long sx, double2* a, long sa, double2* c, long sc,
+                       const int* active, hipStream_t s);
+// nrm2[p] = ||X_p - shift * I||_F^2  (sum of squares)
+hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, double* nrm2, hipStream_t s);
+// Decimation convergence update for each item (one per (point, lead) pair).
+hipError_t launch_sr_check(int batch, const double* a2, const double* c2, const double* d2, double tol, int iter,
+                           int* active, int* iters, int* n_active, hipStream_t s);
+// From Sigma^R_p: gamma_p = i (S - S^H), sl_p = i f_p gamma_p, sg_p = -i (1 - f_p) gamma_p,
+// f_p = 1/(1+exp((E_p - mu)/kT)).  Any output may be null.
+hipError_t launch_gamma_sigma(int b, int batch, const double2* sig, long sS, const double* energies, double mu,
+                              double kT, double2* gamma, long sG, double2* sl, long sL, double2* sg, long sGr,
+                              hipStream_t s);
+// C_p += Q_p - Q_p^H
+hipError_t launch_add_skew(int b, int batch, const double2* Q, long sQ, double2* C, long sC, hipStream_t s);
+// T_p = Re sum_ij P_p[i][j] conj(Q_p[i][j])
+hipError_t launch_dot_re(int b, int batch, const double2* P, long sP, const double2* Q, long sQ, double* out,
+                         hipStream_t s);
+// SR result: resid_p = sqrt(r2) / (sqrt(m2) sqrt(g2)); info_p updated with ENOCONV when
+// not converged or resid > accept; NaN -> ENONFINITE.
+hipError_t launch_sr_finish(int batch, const double* r2, const double* m2, const double* g2, const int* active,
+                            double accept, double* resid_out, int* info, int info_mod, hipStream_t s);
+// info_p = ENONFINITE if any entry of X_p is not finite (only if info_p is OK)
+hipError_t launch_check_finite(int b, int batch, const double2* X, long sX, int* info, int info_mod, hipStream_t s);
+// out_p = c1 X_p + c2 Y_p + g I   (X, Y nullable; out may alias X or Y)
+hipError_t launch_lincomb(int b, int batch, double2 c1, const double2* X, long sX, double2 c2, const double2* Y,
+                          long sY, double2 g, double2* out, long sOut, const int* active, hipStream_t s);
+hipError_t launch_fill_int(int n, int* p, int v, hipStream_t s);
+// Seeded decimation: active_p = (flags_p != OK), iters_p = 0
+hipError_t launch_seed_flags(int np, const int* flags, int* active, int* iters, hipStream_t s);
+// g_p <- g_dec_p for every pair whose seed was rejected (flags_p != OK)
+hipError_t launch_seed_select(int b, int np, const int* flags, const double2* g_dec, double2* g, hipStream_t s);
+
+// ---- profiling (api.hip) ----
+enum KernelClass { KC_GEMM64 = 0, KC_GEMM32 = 1, KC_INV_PANEL = 2, KC_INV_SWAP = 3, KC_INV_PERM = 4, KC_ELEM = 5,
+                   KC_INV_GEMM = 6, KC_COUNT = 7 };
+void prof_begin(int cls, hipStream_t s);
+void prof_end(int cls, hipStream_t s, double flops, double bytes);
+
+}  // namespace negf

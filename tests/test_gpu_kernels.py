@@ -1,0 +1,103 @@
+"""GPU parity of the kernel-level entry points (complex products, inversion)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2602_03438_amd import binding
+    binding.lib()
+    return binding
+
+
+def _rand(r, shape):
+    return r.standard_normal(shape) + 1j * r.standard_normal(shape)
+
+
+def _op(x, o):
+    return x if o == "N" else np.conj(np.swapaxes(x, -1, -2))
+
+
+@pytest.mark.parametrize("opa", ["N", "C"])
+@pytest.mark.parametrize("opb", ["N", "C"])
+@pytest.mark.parametrize("M,N,K", [(64, 64, 64), (37, 71, 19), (130, 100, 133), (8, 8, 8), (1, 5, 3)])
+def test_zgemm_fp64_parity(nb, opa, opb, M, N, K):
+    import torch
+    r = np.random.Generator(np.random.PCG64(M * 1000 + N * 10 + K))
+    batch = 3
+    A = _rand(r, (batch, M, K) if opa == "N" else (batch, K, M))
+    B = _rand(r, (batch, K, N) if opb == "N" else (batch, N, K))
+    C0 = _rand(r, (batch, M, N))
+    alpha, beta = 0.7 - 0.3j, -1.1 + 0.4j
+    ref = alpha * (_op(A, opa) @ _op(B, opb)) + beta * C0
+    Ct = torch.from_numpy(C0.copy()).cuda()
+    nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), Ct, opa, opb, alpha, beta)
+    got = Ct.cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 1e-14 * max(1, np.sqrt(K)), err
+
+
+def test_zgemm_fp64_b512_batched(nb):
+    import torch
+    r = np.random.Generator(np.random.PCG64(5))
+    A = _rand(r, (4, 512, 512))
+    B = _rand(r, (4, 512, 512))
+    got = nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()).cpu().numpy()
+    ref = A @ B
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-14
+
+
+def test_zgemm_fp32_products(nb):
+    import torch
+    r = np.random.Generator(np.random.PCG64(6))
+    A = _rand(r, (2, 200, 150))
+    B = _rand(r, (2, 150, 90))
+    got = nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), prec=1).cpu().numpy()
+    ref = A @ B
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    # single-precision operands and accumulation: ~1e-7 relative, not double accuracy
+    assert 1e-9 < err < 1e-5, err
+
+
+@pytest.mark.parametrize("n", [1, 5, 8, 16, 33, 100, 130, 512])
+@pytest.mark.parametrize("panel", [16, 32])
+def test_zinv_parity(nb, n, panel):
+    import torch
+    r = np.random.Generator(np.random.PCG64(n + panel))
+    M = _rand(r, (3, n, n)) + 2.0 * np.sqrt(n) * np.eye(n) * np.array([1, 1j, -1])[:, None, None]
+    # a row permutation makes pivoting necessary
+    M = M[:, r.permutation(n), :]
+    out, info = nb.zinv(torch.from_numpy(M).cuda(), panel)
+    got = out.cpu().numpy()
+    ref = np.linalg.inv(M)
+    assert np.all(info.cpu().numpy() == 0)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 1e-13, err
+    eye_err = np.linalg.norm(M @ got - np.eye(n)) / np.sqrt(n)
+    assert eye_err < 1e-12
+
+
+def test_zinv_pivoting_needed(nb):
+    """A matrix with a zero leading entry is only invertible with row exchanges."""
+    import torch
+    M = np.array([[0, 1, 2], [3, 0, 1], [1, 1, 0]], dtype=np.complex128)[None]
+    out, info = nb.zinv(torch.from_numpy(M).cuda(), 16)
+    assert np.allclose(out.cpu().numpy()[0], np.linalg.inv(M[0]), atol=1e-14)
+
+
+def test_zinv_reports_singular_and_nonfinite(nb):
+    import torch
+    r = np.random.Generator(np.random.PCG64(9))
+    M = _rand(r, (3, 20, 20))
+    M[1, :, 3] = 0.0                    # exactly singular
+    M[2, 4, 4] = np.nan                 # non-finite
+    out, info = nb.zinv(torch.from_numpy(M).cuda(), 16)
+    info = info.cpu().numpy()
+    assert info[0] == nb.NEGF_OK
+    assert info[1] == nb.NEGF_ESINGULAR
+    assert info[2] in (nb.NEGF_ENONFINITE, nb.NEGF_ESINGULAR)
+    assert np.allclose(out.cpu().numpy()[0], np.linalg.inv(M[0]), atol=1e-12)

@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments synchronously (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "negf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(negf_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2602_03438_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2602_03438_amd import build
+        build.build()
+    return binding.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("negf_obc_surface", "negf_rgf_retarded", "negf_rgf_lesser_greater", "negf_transmission",
+                 "negf_workspace_bytes", "negf_status_string", "negf_version"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version(L):
+    from paper_2602_03438_amd import binding as nb
+    assert nb.status_string(nb.NEGF_OK) == "ok"
+    assert "converge" in nb.status_string(nb.NEGF_ENOCONV)
+    assert nb.negf_version() >= 100
+
+
+def _fake_problem(nb_=4, b=8, n_e=3, h=True):
+    from paper_2602_03438_amd import binding as nbd
+    # host addresses stand in for device pointers: nothing is dereferenced on these paths
+    buf = np.zeros(16, dtype=np.complex128)
+    p = buf.ctypes.data
+    dev = nbd.negf_device(nb_, b, p if h else None, p if h else None, None, None, None, None, None)
+    return nbd.negf_problem(dev, n_e, p, 1e-8, 0.1, -0.1, 0.025), buf
+
+
+def test_workspace_bytes_host_logic(L):
+    from paper_2602_03438_amd import binding as nb
+    pr, keep = _fake_problem()
+    arr = (nb.negf_problem * 1)(pr)
+    n_r = L.negf_workspace_bytes(nb.OP_RETARDED, arr, 1, nb.PLAIN_FP64, None)
+    n_l = L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr, 1, nb.PLAIN_FP64, None)
+    n_ref = L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr, 1, nb.FP32_REFINE, None)
+    assert 0 < n_r <= n_l < n_ref
+    # the batch option bounds the points in flight
+    opt = nb.make_options(batch=1)
+    assert L.negf_workspace_bytes(nb.OP_RETARDED, arr, 1, nb.PLAIN_FP64, C.byref(opt)) < n_r
+    bad, keep2 = _fake_problem(nb_=1)
+    assert L.negf_workspace_bytes(nb.OP_RETARDED, (nb.negf_problem * 1)(bad), 1, 0, None) == 0
+    bad, keep3 = _fake_problem(h=False)
+    assert L.negf_workspace_bytes(nb.OP_RETARDED, (nb.negf_problem * 1)(bad), 1, 0, None) == 0
+    bad, keep4 = _fake_problem(b=2048)
+    assert L.negf_workspace_bytes(nb.OP_RETARDED, (nb.negf_problem * 1)(bad), 1, 0, None) == 0
+
+
+def test_invalid_arguments_return_einval_synchronously(L):
+    from paper_2602_03438_amd import binding as nb
+    pr, keep = _fake_problem()
+    arr = (nb.negf_problem * 1)(pr)
+    # null outputs / workspace / zero problems: rejected before any device work
+    assert L.negf_rgf_retarded(arr, 1, 0, None, None, None, None, None, None, 0, None) == nb.NEGF_EINVAL
+    assert L.negf_rgf_retarded(arr, 0, 0, None, None, None, None, None, None, 0, None) == nb.NEGF_EINVAL
+    assert L.negf_rgf_lesser_greater(arr, 1, 0, None, None, None, None, None, None, None, None, None, None, 0,
+                                     None) == nb.NEGF_EINVAL
+    assert L.negf_transmission(arr, 1, None, None, None, None, 0, None) == nb.NEGF_EINVAL
+    assert L.negf_obc_surface(arr, 1, 2, None, None, None, None, None, None, None, None, 0, None) == nb.NEGF_EINVAL
+    # a workspace that is too small
+    x = np.zeros(64, dtype=np.complex128)
+    p = x.ctypes.data
+    info = np.zeros(3, dtype=np.int32)
+    assert L.negf_rgf_retarded(arr, 1, 0, None, p, p, None, info.ctypes.data, p, 16, None) == nb.NEGF_EINVAL
+    # misaligned output pointer
+    assert L.negf_rgf_retarded(arr, 1, 0, None, p + 8, p, None, info.ctypes.data, p, 1 << 40, None) == nb.NEGF_EINVAL
+    # bad precision code
+    assert L.negf_rgf_retarded(arr, 1, 7, None, p, p, None, info.ctypes.data, p, 1 << 40, None) == nb.NEGF_EINVAL
+    # kernel-level entry points
+    one = (C.c_double * 2)(1.0, 0.0)
+    assert L.negf_zgemm_batched(b"X", b"N", 4, 4, 4, one, p, 4, 16, p, 4, 16, one, p, 4, 16, 1, 0, 0,
+                                None) == nb.NEGF_EINVAL
+    assert L.negf_zinv_batched(2048, 1, p, p + 16, None, 16, p, 1 << 30, None) == nb.NEGF_EINVAL
+    assert L.negf_zinv_batched(4, 1, p, p, None, 16, p, 1 << 30, None) == nb.NEGF_EINVAL
