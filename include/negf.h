@@ -185,10 +185,39 @@ size_t negf_inverse_workspace_bytes(int32_t n, int32_t batch);
 negf_status negf_zinv_batched(int32_t n, int32_t batch, void* M, void* out, int32_t* info, int32_t nb,
                               void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- learned lead initialiser (small MLP, see the seed argument of
+ * negf_obc_surface).  Three linear layers X[n][F] -> H -> H -> O with tanh
+ * after the first two; weights W1 [F][H], W2 [H][H], W3 [H][O] and biases
+ * b1 [H], b2 [H], b3 [O], all float32 row-major device arrays.  Training
+ * runs in single precision; inference in bfloat16 (uint16 bit patterns) with
+ * single-precision accumulation.  Errors: EINVAL for bad sizes or null
+ * pointers, EHIP for launch failures. ---- */
+
+/* Forward pass; keeps the activations A1, A2 [n][H] for the backward pass. */
+negf_status negf_mlp_forward(int32_t n, int32_t F, int32_t H, int32_t O, const float* X, const float* W1,
+                             const float* b1, const float* W2, const float* b2, const float* W3, const float* b3,
+                             float* A1, float* A2, float* Y, void* stream);
+/* Gradients of L = mean over n*O entries of (Y - T)^2 with respect to every
+ * parameter.  dY [n][O], dZ2 [n][H], dZ1 [n][H] are caller scratch. */
+negf_status negf_mlp_backward(int32_t n, int32_t F, int32_t H, int32_t O, const float* X, const float* W2,
+                              const float* W3, const float* A1, const float* A2, const float* Y, const float* T,
+                              float* dW1, float* db1, float* dW2, float* db2, float* dW3, float* db3, float* dY,
+                              float* dZ2, float* dZ1, void* stream);
+/* One Adam step (bias-corrected, step t >= 1) on a flat parameter array. */
+negf_status negf_mlp_adam_step(int32_t count, float* param, const float* grad, float* m, float* v, int32_t t,
+                               float lr, float beta1, float beta2, float eps, void* stream);
+/* Round float32 to bfloat16 (nearest even). */
+negf_status negf_mlp_to_bf16(const float* src, uint16_t* dst, int64_t count, void* stream);
+/* bfloat16 inference: Xb [n][F], W*b bf16 weights, float biases, Y [n][O]
+ * float32; scratch holds 2*n*H bf16 activations. */
+negf_status negf_mlp_infer_bf16(int32_t n, int32_t F, int32_t H, int32_t O, const uint16_t* Xb, const uint16_t* W1b,
+                                const float* b1, const uint16_t* W2b, const float* b2, const uint16_t* W3b,
+                                const float* b3, uint16_t* scratch, float* Y, void* stream);
+
 /* ---- profiling: per kernel class launch counts, algorithmic flops and
  * event-timed durations, recorded on the launching stream. ---- */
 enum { NEGF_KC_GEMM64 = 0, NEGF_KC_GEMM32 = 1, NEGF_KC_INV_PANEL = 2, NEGF_KC_INV_SWAP = 3, NEGF_KC_INV_PERM = 4,
-       NEGF_KC_ELEM = 5, NEGF_KC_COUNT = 6 };
+       NEGF_KC_ELEM = 5, NEGF_KC_INV_GEMM = 6, NEGF_KC_COUNT = 7 };
 typedef struct negf_kernel_stats {
   int64_t launches;
   double total_ms;   /* sum of per-launch event durations */
