@@ -402,8 +402,7 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
     cx.chk(launch_sr_check(np, w.a2, w.c2, w.d2, cx.o.tol, it, w.active, w.iters, w.n_active, s));
     hmax = it;
     int host_active = 0;
-    cx.chk(hipMemcpyAsync(&host_active, w.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-    cx.chk(hipStreamSynchronize(s));
+    cx.chk(rt_read_int(&host_active, w.n_active, s));
     if (host_active == 0) break;
   }
   if (iters_host_max) *iters_host_max = hmax;
@@ -428,7 +427,7 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
   cx.chk(launch_frob2(b, np, t2.p, bb, 0.0, w.m2, s));
   cx.chk(launch_frob2(b, np, w.g.p, bb, 0.0, w.g2, s));
   if (info_pts) cx.chk(launch_sr_finish(np, w.r2, w.m2, w.g2, w.active, cx.o.accept, resid_out, info_pts, npts, s));
-  if (iters_out) cx.chk(hipMemcpyAsync(iters_out, w.iters, sizeof(int) * np, hipMemcpyDeviceToDevice, s));
+  if (iters_out) cx.chk(rt_copy_d2d(iters_out, w.iters, sizeof(int) * np, s));
   if (info_pts) cx.chk(launch_check_finite(b, np, w.g.p, bb, info_pts, npts, s));
 }
 
@@ -643,56 +642,8 @@ char* align256(void* p) { return (char*)(((uintptr_t)p + 255) & ~(uintptr_t)255)
 
 negf_status to_status(hipError_t e) { return e == hipSuccess ? NEGF_OK : NEGF_EHIP; }
 
-// ------------------------------------------------------------------ profiling state
-
-struct ProfRec {
-  hipEvent_t a, b;
-  int cls;
-  double flops, bytes;
-};
-std::mutex g_prof_mu;
-bool g_prof_on = false;
-std::vector<ProfRec> g_prof_pending;
-std::vector<hipEvent_t> g_prof_pool;
-negf_kernel_stats g_prof_acc[KC_COUNT];
-thread_local hipEvent_t t_open = nullptr;
-
-hipEvent_t pool_get() {
-  if (!g_prof_pool.empty()) {
-    hipEvent_t e = g_prof_pool.back();
-    g_prof_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
 }  // namespace
 
-// ------------------------------------------------------------------ profiling hooks
-
-namespace negf {
-
-void prof_begin(int cls, hipStream_t s) {
-  (void)cls;
-  if (!g_prof_on) return;
-  std::lock_guard<std::mutex> lk(g_prof_mu);
-  t_open = pool_get();
-  if (t_open) hipEventRecord(t_open, s);
-}
-
-void prof_end(int cls, hipStream_t s, double flops, double bytes) {
-  if (!g_prof_on || !t_open) return;
-  std::lock_guard<std::mutex> lk(g_prof_mu);
-  hipEvent_t e = pool_get();
-  if (!e) return;
-  hipEventRecord(e, s);
-  g_prof_pending.push_back(ProfRec{t_open, e, cls, flops, bytes});
-  t_open = nullptr;
-}
-
-}  // namespace negf
 
 // ------------------------------------------------------------------ C ABI
 
@@ -901,42 +852,6 @@ negf_status negf_zinv_batched(int32_t n, int32_t batch, void* M, void* out, int3
   d.info = info; d.info_mod = 0;
   d.nb = nb;
   return to_status(launch_inverse(d, s));
-}
-
-void negf_profile_enable(int32_t on) {
-  std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_on = on != 0;
-  if (on) {
-    for (auto& r : g_prof_pending) {
-      g_prof_pool.push_back(r.a);
-      g_prof_pool.push_back(r.b);
-    }
-    g_prof_pending.clear();
-    std::memset(g_prof_acc, 0, sizeof(g_prof_acc));
-  }
-}
-
-negf_status negf_profile_read(negf_kernel_stats* stats) {
-  std::lock_guard<std::mutex> lk(g_prof_mu);
-  negf_status st = NEGF_OK;
-  for (auto& r : g_prof_pending) {
-    float ms = 0.f;
-    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
-      st = NEGF_EHIP;
-    } else {
-      negf_kernel_stats& a = g_prof_acc[r.cls];
-      a.launches += 1;
-      a.total_ms += ms;
-      a.flops += r.flops;
-      a.bytes += r.bytes;
-    }
-    g_prof_pool.push_back(r.a);
-    g_prof_pool.push_back(r.b);
-  }
-  g_prof_pending.clear();
-  if (stats)
-    for (int i = 0; i < NEGF_KC_COUNT; ++i) stats[i] = i < KC_COUNT ? g_prof_acc[i] : negf_kernel_stats{};
-  return st;
 }
 
 const char* negf_status_string(negf_status s) {

@@ -115,7 +115,10 @@ hipError_t launch_seed_flags(int np, const int* flags, int* active, int* iters, 
 // g_p <- g_dec_p for every pair whose seed was rejected (flags_p != OK)
 hipError_t launch_seed_select(int b, int np, const int* flags, const double2* g_dec, double2* g, hipStream_t s);
 
-// ---- profiling (api.hip) ----
+// ---- runtime helpers and profiling (prof.hip) ----
+// *host_dst = *dev_src after the stream has drained (synchronises s)
+hipError_t rt_read_int(int* host_dst, const int* dev_src, hipStream_t s);
+hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s);
 enum KernelClass { KC_GEMM64 = 0, KC_GEMM32 = 1, KC_INV_PANEL = 2, KC_INV_SWAP = 3, KC_INV_PERM = 4, KC_ELEM = 5,
                    KC_INV_GEMM = 6, KC_COUNT = 7 };
 void prof_begin(int cls, hipStream_t s);

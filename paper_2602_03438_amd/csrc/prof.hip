@@ -1,0 +1,115 @@
+// Event-based per-kernel-class timing (negf_profile_enable / negf_profile_read)
+// and the small host/device runtime helpers the orchestration uses.
+#include "../../include/negf.h"
+#include "internal.h"
+
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+using namespace negf;
+
+namespace {
+
+
+struct ProfRec {
+  hipEvent_t a, b;
+  int cls;
+  double flops, bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+negf_kernel_stats g_prof_acc[KC_COUNT];
+thread_local hipEvent_t t_open = nullptr;
+
+hipEvent_t pool_get() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+}  // namespace
+
+namespace negf {
+
+
+void prof_begin(int cls, hipStream_t s) {
+  (void)cls;
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  t_open = pool_get();
+  if (t_open) hipEventRecord(t_open, s);
+}
+
+void prof_end(int cls, hipStream_t s, double flops, double bytes) {
+  if (!g_prof_on || !t_open) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t e = pool_get();
+  if (!e) return;
+  hipEventRecord(e, s);
+  g_prof_pending.push_back(ProfRec{t_open, e, cls, flops, bytes});
+  t_open = nullptr;
+}
+
+}  // namespace negf
+
+namespace negf {
+
+hipError_t rt_read_int(int* host_dst, const int* dev_src, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(host_dst, dev_src, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace negf
+
+extern "C" {
+
+void negf_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  if (on) {
+    for (auto& r : g_prof_pending) {
+      g_prof_pool.push_back(r.a);
+      g_prof_pool.push_back(r.b);
+    }
+    g_prof_pending.clear();
+    std::memset(g_prof_acc, 0, sizeof(g_prof_acc));
+  }
+}
+
+negf_status negf_profile_read(negf_kernel_stats* stats) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  negf_status st = NEGF_OK;
+  for (auto& r : g_prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      st = NEGF_EHIP;
+    } else {
+      negf_kernel_stats& a = g_prof_acc[r.cls];
+      a.launches += 1;
+      a.total_ms += ms;
+      a.flops += r.flops;
+      a.bytes += r.bytes;
+    }
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_pending.clear();
+  if (stats)
+    for (int i = 0; i < NEGF_KC_COUNT; ++i) stats[i] = i < KC_COUNT ? g_prof_acc[i] : negf_kernel_stats{};
+  return st;
+}
+
+}  // extern "C"

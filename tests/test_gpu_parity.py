@@ -9,6 +9,7 @@ import pytest
 import workloads as w
 from oracle import leads as oleads
 from oracle import rgf as orgf
+from helpers import well_posed
 
 pytestmark = pytest.mark.gpu
 
@@ -113,7 +114,7 @@ def test_lesser_greater_slab(nb, b, scatter):
     dev = w.slab_device(5, b, 2)
     if scatter:
         w.scattering_self_energies(dev, 3)
-    energies = np.array([-0.7, 0.02, 0.33, 1.1])
+    energies = well_posed(dev, np.array([-0.7, 0.02, 0.33, 1.1, -1.3, 0.6]))[:4]
     prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
     out = nb.rgf_lesser_greater([prob], greater=True)
     assert np.all(out["info"].cpu().numpy() == 0)
@@ -146,7 +147,7 @@ def test_lesser_gpu_identities(nb):
 
 def test_multi_problem_mixed_shapes_and_chunking(nb):
     devs = [w.slab_device(4, 40, 11), w.slab_device(3, 56, 12), w.slab_device(4, 40, 13)]
-    ens = [np.array([-0.5, 0.1, 0.7]), np.array([0.25]), np.array([-0.1, 0.9])]
+    ens = [well_posed(d, np.linspace(-1.2, 1.2, 9))[:k] for d, k in zip(devs, (3, 1, 2))]
     probs = [nb.Problem(nb.DeviceOnGPU(d), e, eta=1e-8, mu_l=0.05, mu_r=-0.05) for d, e in zip(devs, ens)]
     full = nb.rgf_lesser_greater(probs)
     chunked = nb.rgf_lesser_greater(probs, opts=nb.make_options(batch=2))
@@ -184,7 +185,7 @@ def test_transmission_periodic_wire_integer(nb):
 
 def test_fp32_refine_meets_bar_and_norefine_does_not(nb):
     dev = w.slab_device(6, 128, 2)
-    energies = np.array([-0.6, 0.2])
+    energies = well_posed(dev, np.array([-0.6, 0.2, 0.45, -0.9]))[:2]
     prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
     ref_out = nb.rgf_lesser_greater([prob], nb.PLAIN_FP64)
     refd = nb.rgf_lesser_greater([prob], nb.FP32_REFINE)

@@ -1,0 +1,193 @@
+"""The library's host orchestration, run on the CPU with the test double of its
+kernels (tests/hostsim), against the oracle.
+
+This checks the sequencing of the batched launches (operand order, conjugate
+transposes, strides, chunking, workspace carving, masks and info codes)
+without a GPU; the HIP kernels themselves are checked by the gpu tests.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import leads as oleads
+from oracle import rgf as orgf
+from helpers import well_posed
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def sim():
+    from paper_2602_03438_amd import binding as nb
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("hostsim_build", os.path.join(HERE, "hostsim", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    path = mod.build()
+    L = C.CDLL(path)
+    P = C.POINTER
+    vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+    L.negf_workspace_bytes.argtypes = [i32, P(nb.negf_problem), i32, i32, P(nb.negf_options)]
+    L.negf_workspace_bytes.restype = sz
+    L.negf_obc_surface.argtypes = [P(nb.negf_problem), i32, i32, P(nb.negf_options), vp, vp, vp, vp, vp, vp, vp, sz,
+                                   vp]
+    L.negf_rgf_retarded.argtypes = [P(nb.negf_problem), i32, i32, P(nb.negf_options), vp, vp, vp, vp, vp, sz, vp]
+    L.negf_rgf_lesser_greater.argtypes = [P(nb.negf_problem), i32, i32, P(nb.negf_options), vp, vp, vp, vp, vp, vp,
+                                          vp, vp, vp, sz, vp]
+    L.negf_transmission.argtypes = [P(nb.negf_problem), i32, P(nb.negf_options), vp, vp, vp, sz, vp]
+    return L, nb
+
+
+class HostProblem:
+    def __init__(self, nb, dev, energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025):
+        self.keep = [np.ascontiguousarray(x) if x is not None else None
+                     for x in (dev.H_diag, dev.H_upper, dev.S_diag, dev.S_upper, dev.sig_r, dev.sig_l, dev.sig_g)]
+        self.E = np.ascontiguousarray(energies, dtype=np.float64)
+        ptr = lambda a: a.ctypes.data if a is not None else None
+        d = nb.negf_device(dev.nb, dev.b, *[ptr(a) for a in self.keep])
+        self.s = nb.negf_problem(d, self.E.size, self.E.ctypes.data, eta, mu_l, mu_r, kT)
+        self.nb, self.b, self.n = dev.nb, dev.b, self.E.size
+
+
+def _run_rgf(L, nb, probs, prec=0, greater=True, opts=None):
+    arr = (nb.negf_problem * len(probs))(*[p.s for p in probs])
+    o = C.byref(opts) if opts is not None else None
+    ws = np.zeros(L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr, len(probs), prec, o) + 256, dtype=np.uint8)
+    nd = sum(p.n * p.nb * p.b * p.b for p in probs)
+    nu = sum(p.n * (p.nb - 1) * p.b * p.b for p in probs)
+    out = {k: np.zeros(nd if k.endswith("d") else nu, dtype=np.complex128)
+           for k in ("GRd", "GRu", "GRl", "GLd", "GLu", "GGd", "GGu")}
+    info = np.zeros(sum(p.n for p in probs), dtype=np.int32)
+    g = lambda k: out[k].ctypes.data if (greater or not k.startswith("GG")) else None
+    code = L.negf_rgf_lesser_greater(arr, len(probs), prec, o, g("GRd"), g("GRu"), g("GRl"), g("GLd"), g("GLu"),
+                                     g("GGd"), g("GGu"), info.ctypes.data, ws.ctypes.data, ws.size, None)
+    assert code == 0
+    return out, info
+
+
+def _unpack(flat, probs, diag):
+    res, off = [], 0
+    for p in probs:
+        k = p.nb if diag else p.nb - 1
+        n = p.n * k * p.b * p.b
+        res.append(flat[off:off + n].reshape(p.n, k, p.b, p.b))
+        off += n
+    return res
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("scatter", [False, True])
+def test_hostsim_lesser_greater_matches_oracle(sim, scatter):
+    L, nb = sim
+    dev = w.random_device(4, 5, 3, overlap=0.05)
+    if scatter:
+        w.scattering_self_energies(dev, 4, norm=0.05)
+    E = well_posed(dev, np.linspace(-1.2, 1.2, 9))[:3]
+    assert E.size == 3
+    p = HostProblem(nb, dev, E)
+    out, info = _run_rgf(L, nb, [p])
+    assert np.all(info == 0)
+    for name, ref_name, diag in (("GRd", "GR_diag", 1), ("GRu", "GR_upper", 0), ("GRl", "GR_lower", 0),
+                                 ("GLd", "GL_diag", 1), ("GLu", "GL_upper", 0), ("GGd", "GG_diag", 1),
+                                 ("GGu", "GG_upper", 0)):
+        got = _unpack(out[name], [p], diag)[0]
+        for k, e in enumerate(E):
+            ref = getattr(orgf.solve_point(dev, e, 1e-8, 0.1, -0.1, 0.025, greater=True), ref_name)
+            assert rel(got[k], ref) < 1e-11, (name, k)
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-6), (2, 1e-2)])
+def test_hostsim_chosen_forms(sim, prec, tol):
+    L, nb = sim
+    dev = w.slab_device(4, 24, 2)
+    E = np.array([0.2])
+    p = HostProblem(nb, dev, E)
+    out, info = _run_rgf(L, nb, [p], prec=prec, greater=False)
+    ref = orgf.solve_point(dev, 0.2, 1e-8, 0.1, -0.1, 0.025)
+    e_r = rel(_unpack(out["GRd"], [p], 1)[0][0], ref.GR_diag)
+    e_l = rel(_unpack(out["GLd"], [p], 1)[0][0], ref.GL_diag)
+    assert e_r < tol and e_l < tol
+    if prec == 1:
+        assert e_r < 1e-8
+
+
+def test_hostsim_mixed_shapes_and_chunking(sim):
+    L, nb = sim
+    devs = [w.random_device(3, 4, 11), w.random_device(4, 6, 12, overlap=0.05), w.random_device(3, 4, 13)]
+    ens = [well_posed(d, np.linspace(-1.2, 1.2, 9))[:k] for d, k in zip(devs, (3, 1, 2))]
+    probs = [HostProblem(nb, d, e) for d, e in zip(devs, ens)]
+    full, _ = _run_rgf(L, nb, probs, greater=False)
+    chunked, _ = _run_rgf(L, nb, probs, greater=False, opts=nb.make_options(batch=2))
+    for name in ("GRd", "GLu"):
+        assert np.array_equal(full[name], chunked[name])
+    for q, (d, e) in enumerate(zip(devs, ens)):
+        got = _unpack(full["GLd"], probs, 1)[q]
+        for k, E in enumerate(e):
+            ref = orgf.solve_point(d, E, 1e-8, 0.1, -0.1, 0.025)
+            assert rel(got[k], ref.GL_diag) < 1e-11
+
+
+def test_hostsim_transmission_and_obc(sim):
+    L, nb = sim
+    dev = w.random_device(6, 4, 1)
+    E = np.array([-0.8, 0.1, 1.2])
+    p = HostProblem(nb, dev, E, eta=1e-6)
+    arr = (nb.negf_problem * 1)(p.s)
+    ws = np.zeros(L.negf_workspace_bytes(nb.OP_TRANSMISSION, arr, 1, 0, None) + 256, dtype=np.uint8)
+    T = np.zeros(3)
+    info = np.zeros(3, dtype=np.int32)
+    assert L.negf_transmission(arr, 1, None, T.ctypes.data, info.ctypes.data, ws.ctypes.data, ws.size, None) == 0
+    for k, e in enumerate(E):
+        ref = orgf.solve_point(dev, e, 1e-6, lesser_greater=False, want_T=True).T
+        assert abs(T[k] - ref) < 1e-11
+    for side in (0, 1):
+        ws = np.zeros(L.negf_workspace_bytes(nb.OP_OBC, arr, 1, 0, None) + 256, dtype=np.uint8)
+        g = np.zeros((3, 4, 4), complex)
+        s = np.zeros((3, 4, 4), complex)
+        it = np.zeros(3, np.int32)
+        res = np.zeros(3)
+        assert L.negf_obc_surface(arr, 1, side, None, None, g.ctypes.data, s.ctypes.data, it.ctypes.data,
+                                  res.ctypes.data, info.ctypes.data, ws.ctypes.data, ws.size, None) == 0
+        for k, e in enumerate(E):
+            r = oleads.lead_self_energy(dev, side, e, 1e-6)
+            assert rel(g[k], r.g_surf) < 1e-11 and rel(s[k], r.sigma_r) < 1e-11
+            assert it[k] == r.iters
+        assert np.all(info == 0) and np.all(res < 1e-10)
+
+
+def test_hostsim_seeded_obc(sim):
+    """An exact seed is accepted with zero iterations; a bad seed falls back."""
+    L, nb = sim
+    dev = w.random_device(3, 4, 2)
+    E = np.array([0.3, -0.6])
+    p = HostProblem(nb, dev, E)
+    arr = (nb.negf_problem * 1)(p.s)
+    exact = np.stack([oleads.lead_self_energy(dev, 0, e, 1e-8).g_surf for e in E])
+    seed = exact.copy()
+    seed[1] = np.eye(4) * 0.3                       # a poor guess for the second point
+    ws = np.zeros(L.negf_workspace_bytes(nb.OP_OBC, arr, 1, 0, None) + 256, dtype=np.uint8)
+    g = np.zeros((2, 4, 4), complex)
+    s = np.zeros((2, 4, 4), complex)
+    it = np.zeros(2, np.int32)
+    res = np.zeros(2)
+    info = np.zeros(2, np.int32)
+    assert L.negf_obc_surface(arr, 1, 0, None, seed.ctypes.data, g.ctypes.data, s.ctypes.data, it.ctypes.data,
+                              res.ctypes.data, info.ctypes.data, ws.ctypes.data, ws.size, None) == 0
+    assert it[0] == 0 and it[1] > 5
+    for k in range(2):
+        assert rel(g[k], exact[k]) < 1e-10
+    assert np.all(info == 0)
+
+
+def test_hostsim_noconv_and_singular_info(sim):
+    L, nb = sim
+    dev = w.random_device(3, 4, 2)
+    p = HostProblem(nb, dev, np.array([0.3]))
+    out, info = _run_rgf(L, nb, [p], opts=nb.make_options(sr_max_iter=1), greater=False)
+    assert info[0] == nb.NEGF_ENOCONV
