@@ -113,6 +113,7 @@ typedef struct negf_options {
   int32_t batch;        /* points in flight per group (0: all points of the call) [0]   */
   int32_t inv_nb;       /* panel width of the block inversion (16 or 32)          [32]  */
   int32_t xcd_remap;    /* 1: place the tiles of one matrix on one XCD            [1]   */
+  int32_t gemm_tile;    /* product tile: 1 = 64x64, 2 = 128x64, 3 = 128x128       [1]   */
 } negf_options;
 
 /* Operation codes for negf_workspace_bytes. */
@@ -172,7 +173,8 @@ negf_status negf_transmission(const negf_problem* problems, int32_t n_prob, cons
  * outputs, op = 'N' or 'C' (conjugate transpose).  lda/ldb/ldc are row
  * strides, sa/sb/sc batch strides, all in complex elements.  alpha, beta:
  * host arrays of 2 doubles.  prec: 0 double, 1 single products.
- * tile: 0 default.  Returns NEGF_EINVAL for bad sizes. */
+ * tile: 0 default, 1 = 64x64, 2 = 128x64, 3 = 128x128 output tiles.
+ * Returns NEGF_EINVAL for bad sizes. */
 negf_status negf_zgemm_batched(char opa, char opb, int32_t M, int32_t N, int32_t K, const double* alpha,
                                const void* A, int64_t lda, int64_t sa, const void* B, int64_t ldb, int64_t sb,
                                const double* beta, void* C, int64_t ldc, int64_t sc, int32_t batch, int32_t prec,

@@ -40,7 +40,7 @@ class negf_problem(C.Structure):
 
 class negf_options(C.Structure):
     _fields_ = [("sr_tol", C.c_double), ("sr_max_iter", C.c_int32), ("sr_accept", C.c_double),
-                ("batch", C.c_int32), ("inv_nb", C.c_int32), ("xcd_remap", C.c_int32)]
+                ("batch", C.c_int32), ("inv_nb", C.c_int32), ("xcd_remap", C.c_int32), ("gemm_tile", C.c_int32)]
 
 
 class negf_kernel_stats(C.Structure):
@@ -235,8 +235,8 @@ def _problem_array(problems: Sequence[Problem]):
     return arr
 
 
-def make_options(sr_tol=0.0, sr_max_iter=0, sr_accept=0.0, batch=0, inv_nb=0, xcd_remap=-1):
-    return negf_options(sr_tol, sr_max_iter, sr_accept, batch, inv_nb, xcd_remap)
+def make_options(sr_tol=0.0, sr_max_iter=0, sr_accept=0.0, batch=0, inv_nb=0, xcd_remap=-1, gemm_tile=0):
+    return negf_options(sr_tol, sr_max_iter, sr_accept, batch, inv_nb, xcd_remap, gemm_tile)
 
 
 def _alloc_blocks(problems, per_point_blocks):

@@ -31,6 +31,7 @@ struct Opts {
   int batch = 0;
   int inv_nb = 32;
   int xcd = 1;
+  int tile = GEMM_TILE_64;
 };
 
 Opts get_opts(const negf_options* o) {
@@ -42,6 +43,7 @@ Opts get_opts(const negf_options* o) {
   if (o->batch > 0) r.batch = o->batch;
   if (o->inv_nb == 16 || o->inv_nb == 32) r.inv_nb = o->inv_nb;
   if (o->xcd_remap == 0 || o->xcd_remap == 1) r.xcd = o->xcd_remap;
+  if (o->gemm_tile >= GEMM_TILE_64 && o->gemm_tile <= GEMM_TILE_128x128) r.tile = o->gemm_tile;
   return r;
 }
 
@@ -204,6 +206,7 @@ struct Ctx {
     g.active = active;
     g.prec = pr;
     g.xcd_remap = o.xcd;
+    g.tile = o.tile;
     g.prof_class = -1;
     chk(launch_gemm(g, s));
   }

@@ -7,17 +7,20 @@
 // rounded to complex64 when they are staged, single accumulation, result
 // widened to double on store).
 //
-// Work decomposition: one 256-thread workgroup (4 waves in 2 x 2) per 64 x 64
-// output tile; each wave owns a 32 x 32 sub-tile = 2 x 2 MFMA tiles of 16 x 16
-// with separate real and imaginary accumulators.  K advances in steps of 16
-// complex values through two LDS stages: global loads for step k+1 are issued
-// into registers before the MFMAs of step k, and land in the other LDS stage
-// afterwards, so there is one barrier per step.
+// Work decomposition: one workgroup of WM x WN waves per BM x BN output tile
+// (64x64 with 2x2 waves, 128x64 and 128x128 with 4x2 waves); each wave owns
+// a (BM/WM) x (BN/WN) sub-tile of 16 x 16 MFMA tiles with separate real and
+// imaginary accumulators.  K advances in steps of 16 complex values through
+// two LDS stages: global loads for step k+1 are issued into registers before
+// the MFMAs of step k and land in the other LDS stage afterwards, so there is
+// one barrier per step.  Consecutive workgroup ids are dealt round-robin over
+// the 8 XCDs; with xcd_remap the tiles of one batch item are renumbered so
+// that they land on the same XCD and share its L2.
 //
 // LDS keeps each tile in the layout it has in HBM (no transpose on the store
 // path; the MFMA operand reads do the reorientation):
-//   "row" layout [64][16+1]: 64 rows (m or n), 16 contiguous k values
-//   "col" layout [16][64+1]: 16 k rows, 64 contiguous m or n values
+//   "row" layout [BM][16+1]: BM rows (m or n), 16 contiguous k values
+//   "col" layout [16][BM+1]: 16 k rows, BM contiguous m or n values
 // op(A)=A   (A stored M x K) -> row ; op(A)=A^H (stored K x M) -> col
 // op(B)=B   (B stored K x N) -> col ; op(B)=B^H (stored N x K) -> row
 // The +1 complex padding keeps a 16-lane group of MFMA operand reads on
@@ -28,10 +31,7 @@ namespace negf {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
-constexpr int LD_ROW = BK + 1;
-constexpr int LD_COL = BM + 1;
-constexpr int TILE_ELEMS = (BM * LD_ROW > BK * LD_COL) ? BM * LD_ROW : BK * LD_COL;
+constexpr int BK = 16;
 
 template <typename T> struct Cx;
 template <> struct Cx<double> { typedef double2 type; };
@@ -48,6 +48,9 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Row of accumulator element v of a lane (column = lane % 16) in the 16 x 16
+// output tile: 4*(lane/16)+v for the single-precision MFMA, lane/16+4*v for
+// the double-precision one (measured on gfx950).
 template <typename T> __device__ __forceinline__ int acc_row(int lk, int v);
 template <> __device__ __forceinline__ int acc_row<double>(int lk, int v) { return lk + 4 * v; }
 template <> __device__ __forceinline__ int acc_row<float>(int lk, int v) { return 4 * lk + v; }
@@ -71,42 +74,57 @@ struct KArgs {
   int tiles_m, tiles_n, xcd_remap;
 };
 
-// Stage one 64 x 16 (row layout) or 16 x 64 (col layout) operand tile into registers.
-// rows0/cols0: tile origin in the stored matrix; R/Cn: stored matrix extent.
-template <bool ROWL>
-__device__ __forceinline__ void load_tile(double2 (&r)[4], const double2* __restrict__ base, long ld, int row0,
-                                          int col0, int R, int Cn) {
+template <int BM_, int BN_, int WM_, int WN_>
+struct Cfg {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int TM = BM / WM, TN = BN / WN;   // wave sub-tile
+  static constexpr int FM = TM / 16, FN = TN / 16;   // MFMA tiles per wave
+  static constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // staged elements per thread
+  static constexpr int LD_ROW = BK + 1;
+  static constexpr int LDA_COL = BM + 1, LDB_COL = BN + 1;
+  static constexpr int A_ELEMS = (BM * LD_ROW > BK * LDA_COL) ? BM * LD_ROW : BK * LDA_COL;
+  static constexpr int B_ELEMS = (BN * LD_ROW > BK * LDB_COL) ? BN * LD_ROW : BK * LDB_COL;
+  static_assert(LA * NT == BM * BK && LB * NT == BN * BK, "tile must split evenly over the threads");
+  static_assert(FM >= 1 && FN >= 1 && TM % 16 == 0 && TN % 16 == 0, "wave tile must be 16-aligned");
+};
+
+// Stage an R x 16 (row layout) or 16 x R (col layout) operand tile into registers.
+// row0/col0: tile origin in the stored matrix; nR/nC: stored matrix extent.
+template <int R, int NT, int L, bool ROWL>
+__device__ __forceinline__ void load_tile(double2 (&r)[L], const double2* __restrict__ base, long ld, int row0,
+                                          int col0, int nR, int nC) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    int rr, cc;
-    if (ROWL) { rr = (t >> 4) + 16 * j; cc = t & 15; }
-    else      { rr = (t >> 6) + 4 * j;  cc = t & 63; }
+  for (int j = 0; j < L; ++j) {
+    const int e = t + NT * j;
+    const int rr = ROWL ? e / BK : e / R;
+    const int cc = ROWL ? e % BK : e % R;
     const int gr = row0 + rr, gc = col0 + cc;
-    r[j] = (gr < R && gc < Cn) ? base[(long)gr * ld + gc] : make_double2(0.0, 0.0);
+    r[j] = (gr < nR && gc < nC) ? base[(long)gr * ld + gc] : make_double2(0.0, 0.0);
   }
 }
 
-template <typename T, bool ROWL>
-__device__ __forceinline__ void store_tile(typename Cx<T>::type* s, const double2 (&r)[4], bool conj) {
+template <typename T, int R, int NT, int L, bool ROWL>
+__device__ __forceinline__ void store_tile(typename Cx<T>::type* s, const double2 (&r)[L], bool conj) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    int idx;
-    if (ROWL) idx = ((t >> 4) + 16 * j) * LD_ROW + (t & 15);
-    else      idx = ((t >> 6) + 4 * j) * LD_COL + (t & 63);
+  for (int j = 0; j < L; ++j) {
+    const int e = t + NT * j;
+    const int idx = ROWL ? (e / BK) * (BK + 1) + (e % BK) : (e / R) * (R + 1) + (e % R);
     s[idx] = to_cx<T>(r[j], conj);
   }
 }
 
-template <typename T, int OPA, int OPB>
-__global__ void __launch_bounds__(NT, 2) zgemm_kernel(KArgs a) {
+template <typename T, int OPA, int OPB, typename CF>
+__global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
   typedef typename Cx<T>::type CT;
   typedef typename Acc<T>::type AT;
+  constexpr int BM = CF::BM, BN = CF::BN, NT = CF::NT, FM = CF::FM, FN = CF::FN;
   constexpr bool A_ROW = (OPA == OP_N);  // A stored M x K
   constexpr bool B_ROW = (OPB == OP_C);  // B stored N x K
-  __shared__ CT sA[2][TILE_ELEMS];
-  __shared__ CT sB[2][TILE_ELEMS];
+  __shared__ CT sA[2][CF::A_ELEMS];
+  __shared__ CT sB[2][CF::B_ELEMS];
 
   const int per_item = a.tiles_m * a.tiles_n;
   const long total = (long)per_item * a.batch;
@@ -122,28 +140,28 @@ __global__ void __launch_bounds__(NT, 2) zgemm_kernel(KArgs a) {
   const double2* __restrict__ Bp = a.B + (long)p * a.sB;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / CF::WN, wn = wave % CF::WN;
   const int li = lane & 15, lk = lane >> 4;
 
-  AT accR[2][2], accI[2][2];
+  AT accR[FM][FN], accI[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < FN; ++j) {
       accR[i][j] = AT{0, 0, 0, 0};
       accI[i][j] = AT{0, 0, 0, 0};
     }
 
-  double2 ra[4], rb[4];
+  double2 ra[CF::LA], rb[CF::LB];
   auto gload = [&](int k0) {
-    if (A_ROW) load_tile<true>(ra, Ap, a.lda, m0, k0, a.M, a.K);
-    else       load_tile<false>(ra, Ap, a.lda, k0, m0, a.K, a.M);
-    if (B_ROW) load_tile<true>(rb, Bp, a.ldb, n0, k0, a.N, a.K);
-    else       load_tile<false>(rb, Bp, a.ldb, k0, n0, a.K, a.N);
+    if (A_ROW) load_tile<BM, NT, CF::LA, true>(ra, Ap, a.lda, m0, k0, a.M, a.K);
+    else       load_tile<BM, NT, CF::LA, false>(ra, Ap, a.lda, k0, m0, a.K, a.M);
+    if (B_ROW) load_tile<BN, NT, CF::LB, true>(rb, Bp, a.ldb, n0, k0, a.N, a.K);
+    else       load_tile<BN, NT, CF::LB, false>(rb, Bp, a.ldb, k0, n0, a.K, a.N);
   };
   auto lstore = [&](int st) {
-    store_tile<T, A_ROW>(sA[st], ra, OPA == OP_C);
-    store_tile<T, B_ROW>(sB[st], rb, OPB == OP_C);
+    store_tile<T, BM, NT, CF::LA, A_ROW>(sA[st], ra, OPA == OP_C);
+    store_tile<T, BN, NT, CF::LB, B_ROW>(sB[st], rb, OPB == OP_C);
   };
 
   const int nk = (a.K + BK - 1) / BK;
@@ -158,50 +176,50 @@ __global__ void __launch_bounds__(NT, 2) zgemm_kernel(KArgs a) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kq = kk * 4 + lk;
-      CT av[2], bv[2];
+      CT av[FM], bv[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int m = wm * 32 + i * 16 + li;
-        av[i] = A_ROW ? xA[m * LD_ROW + kq] : xA[kq * LD_COL + m];
-        const int n = wn * 32 + i * 16 + li;
-        bv[i] = B_ROW ? xB[n * LD_ROW + kq] : xB[kq * LD_COL + n];
+      for (int i = 0; i < FM; ++i) {
+        const int m = wm * CF::TM + i * 16 + li;
+        av[i] = A_ROW ? xA[m * CF::LD_ROW + kq] : xA[kq * CF::LDA_COL + m];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < FN; ++j) {
+        const int n = wn * CF::TN + j * 16 + li;
+        bv[j] = B_ROW ? xB[n * CF::LD_ROW + kq] : xB[kq * CF::LDB_COL + n];
+      }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
     }
     if (kt + 1 < nk) lstore(st ^ 1);
     __syncthreads();
   }
 
-  // Epilogue.  Accumulator element v of a lane sits in column lane%16 of the
-  // 16 x 16 tile; its row is 4*(lane/16)+v for the single-precision MFMA and
-  // lane/16+4*v for the double-precision one (measured on gfx950).
   double2* __restrict__ Cp = a.C + (long)p * a.sC;
   const double2* __restrict__ Ci = a.Cin ? a.Cin + (long)p * a.sCi : nullptr;
   const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0) && Ci != nullptr;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wn * 32 + j * 16 + li;
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * CF::TN + j * 16 + li;
       if (col >= a.N) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 32 + i * 16 + acc_row<T>(lk, v);
+        const int row = m0 + wm * CF::TM + i * 16 + acc_row<T>(lk, v);
         if (row >= a.M) continue;
         const double re = (double)accR[i][j][v], im = (double)accI[i][j][v];
         double2 out = make_double2(a.alpha.x * re - a.alpha.y * im, a.alpha.x * im + a.alpha.y * re);
@@ -215,13 +233,30 @@ __global__ void __launch_bounds__(NT, 2) zgemm_kernel(KArgs a) {
     }
 }
 
-template <typename T>
-hipError_t launch_t(const GemmDesc& d, const KArgs& ka, dim3 grid, hipStream_t s) {
-  if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N>), grid, dim3(NT), 0, s, ka);
-  else if (d.opA == OP_C && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N>), grid, dim3(NT), 0, s, ka);
-  else if (d.opA == OP_N && d.opB == OP_C) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_C>), grid, dim3(NT), 0, s, ka);
-  else hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_C>), grid, dim3(NT), 0, s, ka);
+typedef Cfg<64, 64, 2, 2> Cfg64;
+typedef Cfg<128, 64, 4, 2> Cfg128x64;
+typedef Cfg<128, 128, 4, 2> Cfg128;
+
+template <typename T, typename CF>
+hipError_t launch_cfg(const GemmDesc& d, KArgs ka, hipStream_t s) {
+  ka.tiles_m = (d.M + CF::BM - 1) / CF::BM;
+  ka.tiles_n = (d.N + CF::BN - 1) / CF::BN;
+  const long total = (long)ka.tiles_m * ka.tiles_n * d.batch;
+  const dim3 grid((unsigned)total), block(CF::NT);
+  if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF>), grid, block, 0, s, ka);
+  else if (d.opA == OP_C && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF>), grid, block, 0, s, ka);
+  else if (d.opA == OP_N && d.opB == OP_C) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_C, CF>), grid, block, 0, s, ka);
+  else hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_C, CF>), grid, block, 0, s, ka);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_t(const GemmDesc& d, const KArgs& ka, int tile, hipStream_t s) {
+  switch (tile) {
+    case GEMM_TILE_128x64: return launch_cfg<T, Cfg128x64>(d, ka, s);
+    case GEMM_TILE_128x128: return launch_cfg<T, Cfg128>(d, ka, s);
+    default: return launch_cfg<T, Cfg64>(d, ka, s);
+  }
 }
 
 }  // namespace
@@ -236,15 +271,15 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
   ka.C = d.C.p; ka.ldc = d.C.ld; ka.sC = d.C.stride;
   ka.alpha = d.alpha; ka.beta = d.beta;
   ka.active = d.active;
-  ka.tiles_m = (d.M + BM - 1) / BM;
-  ka.tiles_n = (d.N + BN - 1) / BN;
   ka.xcd_remap = d.xcd_remap;
-  const long total = (long)ka.tiles_m * ka.tiles_n * d.batch;
-  dim3 grid((unsigned)total);
+  ka.tiles_m = ka.tiles_n = 0;
+  int tile = d.tile;
+  if (tile == GEMM_TILE_DEFAULT) tile = GEMM_TILE_64;
   const int cls = d.prof_class >= 0 ? d.prof_class : (d.prec == PREC_F32 ? KC_GEMM32 : KC_GEMM64);
   prof_begin(cls, s);
-  hipError_t e = d.prec == PREC_F32 ? launch_t<float>(d, ka, grid, s) : launch_t<double>(d, ka, grid, s);
-  prof_end(cls, s, 8.0 * d.M * (double)d.N * d.K * d.batch, 16.0 * d.batch * ((double)d.M * d.K + (double)d.K * d.N + 2.0 * d.M * d.N));
+  hipError_t e = d.prec == PREC_F32 ? launch_t<float>(d, ka, tile, s) : launch_t<double>(d, ka, tile, s);
+  prof_end(cls, s, 8.0 * d.M * (double)d.N * d.K * d.batch,
+           16.0 * d.batch * ((double)d.M * d.K + (double)d.K * d.N + 2.0 * d.M * d.N));
   return e;
 }
 

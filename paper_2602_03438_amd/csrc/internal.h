@@ -5,6 +5,8 @@
 namespace negf {
 
 enum Op { OP_N = 0, OP_C = 1 };          // op(X) = X or X^H
+// Output tile shapes of the complex product kernel (see gemm.hip)
+enum { GEMM_TILE_DEFAULT = 0, GEMM_TILE_64 = 1, GEMM_TILE_128x64 = 2, GEMM_TILE_128x128 = 3 };
 enum Prec { PREC_F64 = 0, PREC_F32 = 1 };  // arithmetic of the product
 
 // A batch of b x b (or M x K ...) complex matrices: item p starts at p * stride.

@@ -41,6 +41,24 @@ def test_zgemm_fp64_parity(nb, opa, opb, M, N, K):
     assert err < 1e-14 * max(1, np.sqrt(K)), err
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("opa,opb", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
+@pytest.mark.parametrize("M,N,K", [(200, 130, 77), (128, 256, 64)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zgemm_tile_shapes(nb, tile, opa, opb, M, N, K, prec):
+    import torch
+    r = np.random.Generator(np.random.PCG64(M + N + K + tile))
+    A = _rand(r, (2, M, K) if opa == "N" else (2, K, M))
+    B = _rand(r, (2, K, N) if opb == "N" else (2, N, K))
+    C0 = _rand(r, (2, M, N))
+    ref = (0.5 + 0.25j) * (_op(A, opa) @ _op(B, opb)) - C0
+    Ct = torch.from_numpy(C0.copy()).cuda()
+    nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), Ct, opa, opb, 0.5 + 0.25j, -1.0, prec=prec,
+             tile=tile)
+    err = np.linalg.norm(Ct.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err < (1e-13 if prec == 0 else 1e-5), err
+
+
 def test_zgemm_fp64_b512_batched(nb):
     import torch
     r = np.random.Generator(np.random.PCG64(5))
