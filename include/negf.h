@@ -167,6 +167,42 @@ negf_status negf_rgf_lesser_greater(const negf_problem* problems, int32_t n_prob
 negf_status negf_transmission(const negf_problem* problems, int32_t n_prob, const negf_options* opt, double* T,
                               int32_t* info, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- plans: many problems of uneven block shapes in one launch ----
+ * A plan groups the points of all problems into chunks of one block shape
+ * (at most `batch` points each, per shape from `tunings`), assigns chunks to
+ * n_streams worker streams by estimated work (longest first), and runs the
+ * lesser/greater computation of negf_rgf_lesser_greater for all of them.
+ * The decimation runs a fixed number of steps (opt->sr_max_iter, 40 when 0)
+ * with converged points masked out, so a plan never synchronises with the
+ * host and can be captured: with use_graph = 1 the first execute captures the
+ * whole fork/join schedule into one hipGraph, later executes with the same
+ * pointers replay it (energies are read from the problems' device arrays at
+ * replay time, so they may be updated in place between replays).
+ * The plan is a host object; it creates its worker streams (default priority)
+ * and events on first execute and allocates no device memory. */
+typedef struct negf_plan negf_plan;
+typedef struct negf_tuning {
+  int32_t b;          /* block size this entry applies to */
+  int32_t gemm_tile;  /* as negf_options.gemm_tile (0: default) */
+  int32_t inv_nb;     /* 16 or 32 (0: default) */
+  int32_t batch;      /* points per chunk (0: all points of the shape) */
+} negf_tuning;
+negf_status negf_plan_create(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                             const negf_options* opt, const negf_tuning* tunings, int32_t n_tunings,
+                             int32_t n_streams, negf_plan** plan);
+size_t negf_plan_workspace_bytes(const negf_plan* plan);
+/* Number of chunks; fills (if non-NULL) each chunk's first point index, point
+ * count and stream index. */
+int32_t negf_plan_chunks(const negf_plan* plan, int32_t* first_point, int32_t* n_points, int32_t* stream_index);
+/* Outputs as for negf_rgf_lesser_greater.  stamps (nullable): device uint64
+ * [chunks + 1]; stamps[0] = wall clock at the start, stamps[1 + c] = when
+ * chunk c finished (ticks of negf_plan_clock_hz()). */
+negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag, void* GR_upper, void* GR_lower,
+                              void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info,
+                              uint64_t* stamps, void* workspace, size_t ws_bytes, void* stream);
+double negf_plan_clock_hz(void);
+void negf_plan_destroy(negf_plan* plan);
+
 /* ---- kernel-level entry points (used by the tests and the tile tuner) ---- */
 
 /* C_p = alpha op(A_p) op(B_p) + beta C_p for p < batch, complex128 M x N

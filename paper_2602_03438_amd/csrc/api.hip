@@ -75,12 +75,21 @@ struct Chunk {
   std::vector<Seg> segs;
 };
 
+template <typename BatchOf>
+std::vector<Chunk> make_chunks_by(const negf_problem* pr, int n_prob, BatchOf batch_of);
+
 std::vector<Chunk> make_chunks(const negf_problem* pr, int n_prob, int batch) {
+  return make_chunks_by(pr, n_prob, [batch](int, int) { return batch; });
+}
+
+template <typename BatchOf>
+std::vector<Chunk> make_chunks_by(const negf_problem* pr, int n_prob, BatchOf batch_of) {
   std::vector<Chunk> out;
   long gp = 0;
   size_t od = 0, oo = 0;
   for (int q = 0; q < n_prob; ++q) {
     const int nb = pr[q].dev.nb, b = pr[q].dev.b;
+    const int batch = batch_of(nb, b);
     int e = 0;
     while (e < pr[q].n_e) {
       const bool extend = !out.empty() && out.back().nb == nb && out.back().b == b &&
@@ -187,6 +196,7 @@ ChunkWs carve_chunk(Carver& cv, int opk, int nb, int b, int npts, negf_precision
 struct Ctx {
   hipStream_t s;
   Opts o;
+  bool fixed_sr = false;   // run exactly o.max_iter decimation steps (no host reads; graph capture)
   hipError_t err = hipSuccess;
   bool ok() const { return err == hipSuccess; }
   void chk(hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; }
@@ -404,9 +414,11 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
     cx.chk(launch_frob2(b, np, c.p, bb, 0.0, w.c2, s));
     cx.chk(launch_sr_check(np, w.a2, w.c2, w.d2, cx.o.tol, it, w.active, w.iters, w.n_active, s));
     hmax = it;
-    int host_active = 0;
-    cx.chk(rt_read_int(&host_active, w.n_active, s));
-    if (host_active == 0) break;
+    if (!cx.fixed_sr) {
+      int host_active = 0;
+      cx.chk(rt_read_int(&host_active, w.n_active, s));
+      if (host_active == 0) break;
+    }
   }
   if (iters_host_max) *iters_host_max = hmax;
   if (!cx.ok()) return;
@@ -648,6 +660,256 @@ negf_status to_status(hipError_t e) { return e == hipSuccess ? NEGF_OK : NEGF_EH
 }  // namespace
 
 
+
+namespace {
+
+// One chunk of points through the leads and the sweeps of operation opk.
+void run_chunk(Ctx& cx, int opk, const Chunk& ch, ChunkWs& w, negf_precision prec, const Outs& outs) {
+  int* info = outs.info + ch.first_point;
+  const bool lesser = opk == OPK_RL;
+  leads_for_sweeps(cx, ch, w, info, lesser);
+  const long bb = (long)ch.b * ch.b;
+  const int b = ch.b, nb = ch.nb, n = ch.npts;
+  if (opk == OPK_T) {
+    // forward recursion only: g_i alternates between T2 and T4, the corner block between C0 and C1
+    Blocks C = w.pw.C0, Cn = w.pw.C1, gcur = w.pw.T2, gprev = w.pw.T4;
+    for (int i = 0; i < nb && cx.ok(); ++i) {
+      assemble_diag(cx, ch, i, w.pw, w.pw.T0);
+      if (i > 0) {
+        assemble_upper(cx, ch, i - 1, w.pw.T1);
+        cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, gprev.p, bb, w.pw.T1.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb);
+        cx.gemm(PREC_F64, OP_C, OP_N, b, n, MONE, w.pw.T1.p, bb, w.pw.T3.p, bb, ONE, w.pw.T0.p, bb, w.pw.T0.p, bb);
+      }
+      cx.inverse(b, n, w.pw.T0.p, bb, gcur.p, bb, w.pw.inv_scratch, info, 0);
+      if (i == 0) {
+        cx.lincomb(b, n, ONE, gcur.p, bb, ZERO, nullptr, 0, ZERO, C.p, bb);
+      } else {
+        cx.gemm(PREC_F64, OP_C, OP_N, b, n, ONE, w.pw.T1.p, bb, C.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb);
+        cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, gcur.p, bb, w.pw.T3.p, bb, ZERO, nullptr, 0, Cn.p, bb);
+        std::swap(C, Cn);
+      }
+      std::swap(gcur, gprev);
+    }
+    // T = Re sum (Gamma_R C) .* conj(C Gamma_L)
+    cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, w.pw.gamR.p, bb, C.p, bb, ZERO, nullptr, 0, w.pw.T0.p, bb);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, C.p, bb, w.pw.gamL.p, bb, ZERO, nullptr, 0, w.pw.T1.p, bb);
+    cx.chk(launch_dot_re(b, n, w.pw.T0.p, bb, w.pw.T1.p, bb, outs.T + ch.first_point, cx.s));
+    return;
+  }
+  const long ds = (long)nb * bb;
+  double2* GRd = outs.GRd + ch.out_diag_off;
+  forward_retarded(cx, ch, w.pw, prec, GRd, ds, info, true, nullptr);
+  if (lesser) {
+    forward_lesser(cx, ch, w.pw, prec, 0, GRd, outs.GLd + ch.out_diag_off);
+    if (outs.GGd) forward_lesser(cx, ch, w.pw, prec, 1, GRd, outs.GGd + ch.out_diag_off);
+  }
+  backward_retarded(cx, ch, w.pw, prec, outs);
+  if (lesser) {
+    const double2* GRu = outs.GRu + ch.out_off_off;
+    backward_lesser(cx, ch, w.pw, prec, GRd, GRu, outs.GLd + ch.out_diag_off, outs.GLu + ch.out_off_off);
+    if (outs.GGd) backward_lesser(cx, ch, w.pw, prec, GRd, GRu, outs.GGd + ch.out_diag_off, outs.GGu + ch.out_off_off);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plans (batched uneven workloads)
+
+struct negf_plan {
+  std::vector<negf_problem> probs;
+  negf_precision prec;
+  Opts base;
+  std::vector<Chunk> chunks;
+  std::vector<Opts> chunk_opts;
+  std::vector<int> stream_of;
+  std::vector<size_t> stream_ws_off;
+  size_t ws_total = 0;
+  int n_streams = 1;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  void* graph = nullptr;
+  // arguments the graph was captured with (a replay is valid only for the same ones)
+  Outs cap_outs{};
+  void* cap_ws = nullptr;
+  unsigned long long* cap_stamps = nullptr;
+  hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+double chunk_cost(const Chunk& c) {
+  const double b3 = (double)c.b * c.b * c.b;
+  return c.npts * b3 * (128.0 * (c.nb - 1) + 2.0 * (56.0 * 30 + 24));
+}
+
+bool same_outs(const Outs& a, const Outs& b) {
+  return a.GRd == b.GRd && a.GRu == b.GRu && a.GRl == b.GRl && a.GLd == b.GLd && a.GLu == b.GLu && a.GGd == b.GGd &&
+         a.GGu == b.GGu && a.info == b.info;
+}
+
+// Enqueue the whole plan: start stamp, fork to the worker streams, every chunk
+// on its stream followed by its stamp, join.  No host synchronisation.
+hipError_t enqueue_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long long* stamps, hipStream_t main) {
+  const int ns = P->n_streams;
+  hipError_t e = launch_fill_int((int)count_points(P->probs.data(), (int)P->probs.size()), outs.info, 0, main);
+  if (e != hipSuccess) return e;
+  if (stamps && (e = launch_stamp(stamps, main)) != hipSuccess) return e;
+  for (int i = 0; i < ns; ++i)
+    if ((e = rt_record_wait(P->events[i], main, P->streams[i])) != hipSuccess) return e;
+  std::vector<size_t> cursor(ns, 0);
+  for (size_t c = 0; c < P->chunks.size(); ++c) {
+    const Chunk& ch = P->chunks[c];
+    const int si = P->stream_of[c];
+    Ctx cx;
+    cx.s = P->streams[si];
+    cx.o = P->chunk_opts[c];
+    cx.fixed_sr = true;
+    Carver cv{ws + P->stream_ws_off[si], P->ws_total - P->stream_ws_off[si]};
+    ChunkWs w = carve_chunk(cv, OPK_RL, ch.nb, ch.b, ch.npts, P->prec, 2);
+    if (cv.overflow) return hipErrorInvalidValue;
+    run_chunk(cx, OPK_RL, ch, w, P->prec, outs);
+    if (!cx.ok()) return cx.err;
+    if (stamps && (e = launch_stamp(stamps + 1 + c, cx.s)) != hipSuccess) return e;
+  }
+  for (int i = 0; i < ns; ++i)
+    if ((e = rt_record_wait(P->events[ns + i], P->streams[i], main)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+negf_status negf_plan_create(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                             const negf_options* opt, const negf_tuning* tunings, int32_t n_tunings,
+                             int32_t n_streams, negf_plan** plan) {
+  if (!plan) return NEGF_EINVAL;
+  *plan = nullptr;
+  negf_status st = check_problems(problems, n_prob);
+  if (st != NEGF_OK) return st;
+  if (prec != NEGF_PLAIN_FP64 && prec != NEGF_FP32_REFINE && prec != NEGF_FP32_NOREFINE) return NEGF_EINVAL;
+  if (n_streams < 1 || n_streams > 16 || n_tunings < 0 || (n_tunings > 0 && !tunings)) return NEGF_EINVAL;
+  negf_plan* P = new negf_plan();
+  P->probs.assign(problems, problems + n_prob);
+  P->prec = prec;
+  P->base = get_opts(opt);
+  if (!opt || opt->sr_max_iter <= 0) P->base.max_iter = 40;   // fixed decimation count of a plan
+  P->n_streams = n_streams;
+  auto tuning_of = [&](int b) -> const negf_tuning* {
+    for (int i = 0; i < n_tunings; ++i)
+      if (tunings[i].b == b) return &tunings[i];
+    return nullptr;
+  };
+  P->chunks = make_chunks_by(P->probs.data(), n_prob, [&](int, int b) {
+    const negf_tuning* t = tuning_of(b);
+    return (t && t->batch > 0) ? t->batch : P->base.batch;
+  });
+  for (const Chunk& c : P->chunks) {
+    Opts o = P->base;
+    if (const negf_tuning* t = tuning_of(c.b)) {
+      if (t->gemm_tile >= GEMM_TILE_64 && t->gemm_tile <= GEMM_TILE_128x128) o.tile = t->gemm_tile;
+      if (t->inv_nb == 16 || t->inv_nb == 32) o.inv_nb = t->inv_nb;
+    }
+    P->chunk_opts.push_back(o);
+  }
+  // longest-processing-time-first assignment of chunks to streams
+  std::vector<size_t> order(P->chunks.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t b) { return chunk_cost(P->chunks[a]) > chunk_cost(P->chunks[b]); });
+  std::vector<double> load(n_streams, 0.0);
+  std::vector<size_t> ws_need(n_streams, 0);
+  P->stream_of.assign(P->chunks.size(), 0);
+  for (size_t k : order) {
+    const int si = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    P->stream_of[k] = si;
+    load[si] += chunk_cost(P->chunks[k]);
+    Carver cv{nullptr, 0};
+    const Chunk& c = P->chunks[k];
+    carve_chunk(cv, OPK_RL, c.nb, c.b, c.npts, prec, 2);
+    ws_need[si] = std::max(ws_need[si], cv.off);
+  }
+  size_t off = 0;
+  for (int i = 0; i < n_streams; ++i) {
+    P->stream_ws_off.push_back(off);
+    off += (ws_need[i] + 255) & ~(size_t)255;
+  }
+  P->ws_total = off;
+  *plan = P;
+  return NEGF_OK;
+}
+
+size_t negf_plan_workspace_bytes(const negf_plan* plan) { return plan ? plan->ws_total + 256 : 0; }
+
+int32_t negf_plan_chunks(const negf_plan* plan, int32_t* first_point, int32_t* n_points, int32_t* stream_index) {
+  if (!plan) return 0;
+  for (size_t c = 0; c < plan->chunks.size(); ++c) {
+    if (first_point) first_point[c] = (int32_t)plan->chunks[c].first_point;
+    if (n_points) n_points[c] = plan->chunks[c].npts;
+    if (stream_index) stream_index[c] = plan->stream_of[c];
+  }
+  return (int32_t)plan->chunks.size();
+}
+
+double negf_plan_clock_hz(void) { return rt_wallclock_hz(); }
+
+negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag, void* GR_upper, void* GR_lower,
+                              void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info,
+                              uint64_t* stamps, void* workspace, size_t ws_bytes, void* stream) {
+  if (!plan || !GR_diag || !GR_upper || !GL_diag || !GL_upper || !info || !workspace) return NEGF_EINVAL;
+  if ((GG_diag == nullptr) != (GG_upper == nullptr)) return NEGF_EINVAL;
+  const void* ps[] = {GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper, stamps};
+  for (const void* p : ps)
+    if (p && ((uintptr_t)p & 15)) return NEGF_EINVAL;
+  if (ws_bytes < negf_plan_workspace_bytes(plan)) return NEGF_EINVAL;
+  negf_plan* P = plan;
+  hipStream_t main = (hipStream_t)stream;
+  if (P->streams.empty()) {
+    for (int i = 0; i < P->n_streams; ++i) {
+      hipStream_t st = nullptr;
+      if (rt_stream_create(&st) != hipSuccess) return NEGF_EHIP;
+      P->streams.push_back(st);
+    }
+    for (int i = 0; i < 2 * P->n_streams; ++i) {
+      hipEvent_t ev = nullptr;
+      if (rt_event_create(&ev) != hipSuccess) return NEGF_EHIP;
+      P->events.push_back(ev);
+    }
+  }
+  Outs outs{(double2*)GR_diag, (double2*)GR_upper, (double2*)GR_lower, (double2*)GL_diag, (double2*)GL_upper,
+            (double2*)GG_diag, (double2*)GG_upper, info, nullptr};
+  char* ws = align256(workspace);
+  unsigned long long* stp = (unsigned long long*)stamps;
+  if (!use_graph) return to_status(enqueue_plan(P, outs, ws, stp, main));
+  const bool reuse = P->graph && same_outs(P->cap_outs, outs) && P->cap_ws == ws && P->cap_stamps == stp &&
+                     P->cap_stream == main;
+  if (!reuse) {
+    if (P->graph) rt_graph_destroy(P->graph);
+    P->graph = nullptr;
+    if (rt_capture_begin(main) != hipSuccess) return NEGF_EHIP;
+    hipError_t e = enqueue_plan(P, outs, ws, stp, main);
+    void* exec = nullptr;
+    hipError_t e2 = rt_capture_end(main, &exec);
+    if (e != hipSuccess || e2 != hipSuccess) return NEGF_EHIP;
+    P->graph = exec;
+    P->cap_outs = outs;
+    P->cap_ws = ws;
+    P->cap_stamps = stp;
+    P->cap_stream = main;
+  }
+  return to_status(rt_graph_launch(P->graph, main));
+}
+
+void negf_plan_destroy(negf_plan* plan) {
+  if (!plan) return;
+  if (plan->graph) rt_graph_destroy(plan->graph);
+  for (hipEvent_t e : plan->events) rt_event_destroy(e);
+  for (hipStream_t s : plan->streams) rt_stream_destroy(s);
+  delete plan;
+}
+
+}  // extern "C"
+
 // ------------------------------------------------------------------ C ABI
 
 extern "C" {
@@ -717,60 +979,11 @@ static negf_status rgf_common(int opk, const negf_problem* problems, int32_t n_p
   cx.o = o;
   const long npts_all = count_points(problems, n_prob);
   cx.chk(launch_fill_int((int)npts_all, outs.info, 0, cx.s));
-  const bool lesser = opk == OPK_RL;
   for (const Chunk& ch : make_chunks(problems, n_prob, o.batch)) {
     Carver cv{align256(workspace), ws_bytes - (size_t)(align256(workspace) - (char*)workspace)};
     ChunkWs w = carve_chunk(cv, opk, ch.nb, ch.b, ch.npts, prec, 2);
     if (cv.overflow) return NEGF_EINVAL;
-    int* info = outs.info + ch.first_point;
-    leads_for_sweeps(cx, ch, w, info, lesser);
-    const long bb = (long)ch.b * ch.b;
-    if (opk == OPK_T) {
-      // g ping-pong is not needed for T: store g_i in a per-point rolling pair of blocks
-      Blocks corner;
-      // gdiag needs nb blocks per point only for the previous block: use X region absent;
-      // keep g_i in C0/C1-independent storage: T2 (current) / T4 (previous) alternate
-      const int b = ch.b, nb = ch.nb, n = ch.npts;
-      Blocks C = w.pw.C0, Cn = w.pw.C1, gcur = w.pw.T2, gprev = w.pw.T4;
-      for (int i = 0; i < nb && cx.ok(); ++i) {
-        assemble_diag(cx, ch, i, w.pw, w.pw.T0);
-        if (i > 0) {
-          assemble_upper(cx, ch, i - 1, w.pw.T1);
-          cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, gprev.p, bb, w.pw.T1.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb);
-          cx.gemm(PREC_F64, OP_C, OP_N, b, n, MONE, w.pw.T1.p, bb, w.pw.T3.p, bb, ONE, w.pw.T0.p, bb, w.pw.T0.p, bb);
-        }
-        cx.inverse(b, n, w.pw.T0.p, bb, gcur.p, bb, w.pw.inv_scratch, info, 0);
-        if (i == 0) {
-          cx.lincomb(b, n, ONE, gcur.p, bb, ZERO, nullptr, 0, ZERO, C.p, bb);
-        } else {
-          cx.gemm(PREC_F64, OP_C, OP_N, b, n, ONE, w.pw.T1.p, bb, C.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb);
-          cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, gcur.p, bb, w.pw.T3.p, bb, ZERO, nullptr, 0, Cn.p, bb);
-          std::swap(C, Cn);
-        }
-        std::swap(gcur, gprev);
-      }
-      corner = C;
-      // T = Re sum (Gamma_R C) .* conj(C Gamma_L)
-      cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, w.pw.gamR.p, bb, corner.p, bb, ZERO, nullptr, 0, w.pw.T0.p, bb);
-      cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, corner.p, bb, w.pw.gamL.p, bb, ZERO, nullptr, 0, w.pw.T1.p, bb);
-      cx.chk(launch_dot_re(b, n, w.pw.T0.p, bb, w.pw.T1.p, bb, outs.T + ch.first_point, cx.s));
-      if (!cx.ok()) break;
-      continue;
-    }
-    const long ds = (long)ch.nb * bb;
-    double2* GRd = outs.GRd + ch.out_diag_off;
-    forward_retarded(cx, ch, w.pw, prec, GRd, ds, info, true, nullptr);
-    if (lesser) {
-      forward_lesser(cx, ch, w.pw, prec, 0, GRd, outs.GLd + ch.out_diag_off);
-      if (outs.GGd) forward_lesser(cx, ch, w.pw, prec, 1, GRd, outs.GGd + ch.out_diag_off);
-    }
-    backward_retarded(cx, ch, w.pw, prec, outs);
-    if (lesser) {
-      const double2* GRu = outs.GRu + ch.out_off_off;
-      backward_lesser(cx, ch, w.pw, prec, GRd, GRu, outs.GLd + ch.out_diag_off, outs.GLu + ch.out_off_off);
-      if (outs.GGd)
-        backward_lesser(cx, ch, w.pw, prec, GRd, GRu, outs.GGd + ch.out_diag_off, outs.GGu + ch.out_off_off);
-    }
+    run_chunk(cx, opk, ch, w, prec, outs);
     if (!cx.ok()) break;
   }
   return to_status(cx.err);

@@ -273,6 +273,10 @@ __global__ void seed_select_kernel(long n, const int* flags, const double2* g_de
     g[(long)p * n + i] = g_dec[(long)p * n + i];
 }
 
+__global__ void stamp_kernel(unsigned long long* dst) {
+  if (threadIdx.x == 0) *dst = wall_clock64();
+}
+
 __global__ void fill_int_kernel(int n, int* p, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -383,6 +387,11 @@ hipError_t launch_seed_select(int b, int np, const int* flags, const double2* g_
   if (np <= 0) return hipSuccess;
   const long n = (long)b * b;
   hipLaunchKernelGGL(seed_select_kernel, dim3(grid_for(n), np), dim3(256), 0, s, n, flags, g_dec, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_stamp(unsigned long long* dst, hipStream_t s) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, s, dst);
   return hipGetLastError();
 }
 

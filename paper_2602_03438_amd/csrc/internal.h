@@ -121,6 +121,19 @@ hipError_t launch_seed_select(int b, int np, const int* flags, const double2* g_
 // *host_dst = *dev_src after the stream has drained (synchronises s)
 hipError_t rt_read_int(int* host_dst, const int* dev_src, hipStream_t s);
 hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s);
+// worker streams (default priority), fork/join events, stream capture into one graph
+hipError_t rt_stream_create(hipStream_t* s);
+hipError_t rt_stream_destroy(hipStream_t s);
+hipError_t rt_event_create(hipEvent_t* e);
+hipError_t rt_event_destroy(hipEvent_t e);
+hipError_t rt_record_wait(hipEvent_t e, hipStream_t from, hipStream_t to);   // `to` waits for `from`
+hipError_t rt_capture_begin(hipStream_t s);
+hipError_t rt_capture_end(hipStream_t s, void** exec);
+hipError_t rt_graph_launch(void* exec, hipStream_t s);
+hipError_t rt_graph_destroy(void* exec);
+double rt_wallclock_hz();
+// *dst = device wall clock (constant-rate counter) when the stream reaches this point
+hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 enum KernelClass { KC_GEMM64 = 0, KC_GEMM32 = 1, KC_INV_PANEL = 2, KC_INV_SWAP = 3, KC_INV_PERM = 4, KC_ELEM = 5,
                    KC_INV_GEMM = 6, KC_COUNT = 7 };
 void prof_begin(int cls, hipStream_t s);

@@ -23,6 +23,7 @@ std::vector<ProfRec> g_prof_pending;
 std::vector<hipEvent_t> g_prof_pool;
 negf_kernel_stats g_prof_acc[KC_COUNT];
 thread_local hipEvent_t t_open = nullptr;
+thread_local bool g_capturing = false;   // no timing events inside a captured graph
 
 hipEvent_t pool_get() {
   if (!g_prof_pool.empty()) {
@@ -42,14 +43,14 @@ namespace negf {
 
 void prof_begin(int cls, hipStream_t s) {
   (void)cls;
-  if (!g_prof_on) return;
+  if (!g_prof_on || g_capturing) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   t_open = pool_get();
   if (t_open) hipEventRecord(t_open, s);
 }
 
 void prof_end(int cls, hipStream_t s, double flops, double bytes) {
-  if (!g_prof_on || !t_open) return;
+  if (!g_prof_on || !t_open || g_capturing) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = pool_get();
   if (!e) return;
@@ -70,6 +71,47 @@ hipError_t rt_read_int(int* host_dst, const int* dev_src, hipStream_t s) {
 
 hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
   return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t rt_stream_create(hipStream_t* s) { return hipStreamCreateWithFlags(s, hipStreamNonBlocking); }
+hipError_t rt_stream_destroy(hipStream_t s) { return hipStreamDestroy(s); }
+hipError_t rt_event_create(hipEvent_t* e) { return hipEventCreateWithFlags(e, hipEventDisableTiming); }
+hipError_t rt_event_destroy(hipEvent_t e) { return hipEventDestroy(e); }
+
+hipError_t rt_record_wait(hipEvent_t e, hipStream_t from, hipStream_t to) {
+  hipError_t r = hipEventRecord(e, from);
+  if (r != hipSuccess) return r;
+  return hipStreamWaitEvent(to, e, 0);
+}
+
+hipError_t rt_capture_begin(hipStream_t s) {
+  g_capturing = true;
+  hipError_t r = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (r != hipSuccess) g_capturing = false;
+  return r;
+}
+
+hipError_t rt_capture_end(hipStream_t s, void** exec) {
+  g_capturing = false;
+  hipGraph_t g = nullptr;
+  hipError_t r = hipStreamEndCapture(s, &g);
+  if (r != hipSuccess) return r;
+  hipGraphExec_t ex = nullptr;
+  r = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (r != hipSuccess) return r;
+  *exec = (void*)ex;
+  return hipSuccess;
+}
+
+hipError_t rt_graph_launch(void* exec, hipStream_t s) { return hipGraphLaunch((hipGraphExec_t)exec, s); }
+hipError_t rt_graph_destroy(void* exec) { return exec ? hipGraphExecDestroy((hipGraphExec_t)exec) : hipSuccess; }
+
+double rt_wallclock_hz() {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0.0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0.0;
+  return 1e3 * khz;
 }
 
 }  // namespace negf

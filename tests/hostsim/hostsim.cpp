@@ -312,6 +312,37 @@ hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t) {
   return hipSuccess;
 }
 
+// streams, events and graphs: the simulation runs every launch eagerly in
+// issue order, which is one valid schedule of the fork/join plan.
+hipError_t rt_stream_create(hipStream_t* s) {
+  static int dummy[16];
+  static int next = 0;
+  *s = (hipStream_t)&dummy[(next++) % 16];
+  return hipSuccess;
+}
+hipError_t rt_stream_destroy(hipStream_t) { return hipSuccess; }
+hipError_t rt_event_create(hipEvent_t* e) {
+  static int dummy[64];
+  static int next = 0;
+  *e = (hipEvent_t)&dummy[(next++) % 64];
+  return hipSuccess;
+}
+hipError_t rt_event_destroy(hipEvent_t) { return hipSuccess; }
+hipError_t rt_record_wait(hipEvent_t, hipStream_t, hipStream_t) { return hipSuccess; }
+hipError_t rt_capture_begin(hipStream_t) { return hipSuccess; }
+hipError_t rt_capture_end(hipStream_t, void** exec) {
+  *exec = (void*)1;
+  return hipSuccess;
+}
+hipError_t rt_graph_launch(void*, hipStream_t) { return hipSuccess; }
+hipError_t rt_graph_destroy(void*) { return hipSuccess; }
+double rt_wallclock_hz() { return 1e8; }
+hipError_t launch_stamp(unsigned long long* dst, hipStream_t) {
+  static unsigned long long t = 0;
+  *dst = ++t;
+  return hipSuccess;
+}
+
 void prof_begin(int, hipStream_t) {}
 void prof_end(int, hipStream_t, double, double) {}
 

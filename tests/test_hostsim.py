@@ -38,6 +38,12 @@ def sim():
     L.negf_rgf_lesser_greater.argtypes = [P(nb.negf_problem), i32, i32, P(nb.negf_options), vp, vp, vp, vp, vp, vp,
                                           vp, vp, vp, sz, vp]
     L.negf_transmission.argtypes = [P(nb.negf_problem), i32, P(nb.negf_options), vp, vp, vp, sz, vp]
+    L.negf_plan_create.argtypes = [P(nb.negf_problem), i32, i32, P(nb.negf_options), vp, i32, i32, P(vp)]
+    L.negf_plan_workspace_bytes.argtypes = [vp]
+    L.negf_plan_workspace_bytes.restype = sz
+    L.negf_plan_chunks.argtypes = [vp, vp, vp, vp]
+    L.negf_plan_execute.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.negf_plan_destroy.argtypes = [vp]
     return L, nb
 
 
@@ -191,3 +197,39 @@ def test_hostsim_noconv_and_singular_info(sim):
     p = HostProblem(nb, dev, np.array([0.3]))
     out, info = _run_rgf(L, nb, [p], opts=nb.make_options(sr_max_iter=1), greater=False)
     assert info[0] == nb.NEGF_ENOCONV
+
+
+def test_hostsim_plan_matches_plain_calls(sim):
+    """The plan (fixed decimation count, chunks over worker streams) gives the
+    same blocks as the plain call; a graph 'replay' with the same pointers is
+    the same enqueue in the simulation."""
+    L, nb = sim
+    devs = [w.random_device(3, 4, 21), w.random_device(4, 6, 22, overlap=0.05), w.random_device(5, 4, 23)]
+    ens = [well_posed(d, np.linspace(-1.2, 1.2, 9))[:k] for d, k in zip(devs, (3, 2, 3))]
+    probs = [HostProblem(nb, d, e) for d, e in zip(devs, ens)]
+    ref, ref_info = _run_rgf(L, nb, probs, greater=False)
+    arr = (nb.negf_problem * len(probs))(*[p.s for p in probs])
+    tun = (C.c_int32 * 8)(4, 0, 16, 2, 6, 0, 32, 1)    # (b, tile, inv_nb, batch) for b = 4 and b = 6
+    plan = C.c_void_p()
+    assert L.negf_plan_create(arr, len(probs), 0, None, C.cast(tun, C.c_void_p), 2, 3, C.byref(plan)) == 0
+    nch = L.negf_plan_chunks(plan, None, None, None)
+    fp = (C.c_int32 * nch)()
+    npn = (C.c_int32 * nch)()
+    si = (C.c_int32 * nch)()
+    L.negf_plan_chunks(plan, fp, npn, si)
+    assert sum(npn) == sum(p.n for p in probs) and max(npn) <= 2 and set(si) <= {0, 1, 2}
+    ws = np.zeros(L.negf_plan_workspace_bytes(plan), dtype=np.uint8)
+    nd = sum(p.n * p.nb * p.b * p.b for p in probs)
+    nu = sum(p.n * (p.nb - 1) * p.b * p.b for p in probs)
+    out = {k: np.zeros(nd if k.endswith("d") else nu, dtype=np.complex128) for k in ("GRd", "GRu", "GRl", "GLd", "GLu")}
+    info = np.zeros(sum(p.n for p in probs), dtype=np.int32)
+    stamps = np.zeros(nch + 1, dtype=np.uint64)
+    for use_graph in (0, 1, 1):
+        assert L.negf_plan_execute(plan, use_graph, out["GRd"].ctypes.data, out["GRu"].ctypes.data,
+                                   out["GRl"].ctypes.data, out["GLd"].ctypes.data, out["GLu"].ctypes.data, None, None,
+                                   info.ctypes.data, stamps.ctypes.data, ws.ctypes.data, ws.size, None) == 0
+        assert np.array_equal(info, ref_info)
+        for k in out:
+            assert rel(out[k], ref[k]) < 1e-13, k
+        assert np.all(stamps[1:] > stamps[0])
+    L.negf_plan_destroy(plan)
