@@ -114,6 +114,7 @@ typedef struct negf_options {
   int32_t inv_nb;       /* panel width of the block inversion (16 or 32)          [32]  */
   int32_t xcd_remap;    /* 1: place the tiles of one matrix on one XCD            [1]   */
   int32_t gemm_tile;    /* product tile: 1 = 64x64, 2 = 128x64, 3 = 128x128       [1]   */
+  int32_t gemm_tile_f32;/* tile of the single-precision products                  [1]   */
 } negf_options;
 
 /* Operation codes for negf_workspace_bytes. */
@@ -184,6 +185,7 @@ typedef struct negf_plan negf_plan;
 typedef struct negf_tuning {
   int32_t b;          /* block size this entry applies to */
   int32_t gemm_tile;  /* as negf_options.gemm_tile (0: default) */
+  int32_t gemm_tile_f32;
   int32_t inv_nb;     /* 16 or 32 (0: default) */
   int32_t batch;      /* points per chunk (0: all points of the shape) */
 } negf_tuning;

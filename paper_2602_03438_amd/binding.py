@@ -40,7 +40,13 @@ class negf_problem(C.Structure):
 
 class negf_options(C.Structure):
     _fields_ = [("sr_tol", C.c_double), ("sr_max_iter", C.c_int32), ("sr_accept", C.c_double),
-                ("batch", C.c_int32), ("inv_nb", C.c_int32), ("xcd_remap", C.c_int32), ("gemm_tile", C.c_int32)]
+                ("batch", C.c_int32), ("inv_nb", C.c_int32), ("xcd_remap", C.c_int32), ("gemm_tile", C.c_int32),
+                ("gemm_tile_f32", C.c_int32)]
+
+
+class negf_tuning(C.Structure):
+    _fields_ = [("b", C.c_int32), ("gemm_tile", C.c_int32), ("gemm_tile_f32", C.c_int32), ("inv_nb", C.c_int32),
+                ("batch", C.c_int32)]
 
 
 class negf_kernel_stats(C.Structure):
@@ -90,6 +96,18 @@ def lib():
     L.negf_status_string.restype = C.c_char_p
     L.negf_version.argtypes = []
     L.negf_version.restype = i32
+    L.negf_plan_create.argtypes = [P(negf_problem), i32, i32, P(negf_options), P(negf_tuning), i32, i32, P(vp)]
+    L.negf_plan_create.restype = C.c_int
+    L.negf_plan_workspace_bytes.argtypes = [vp]
+    L.negf_plan_workspace_bytes.restype = sz
+    L.negf_plan_chunks.argtypes = [vp, vp, vp, vp]
+    L.negf_plan_chunks.restype = i32
+    L.negf_plan_execute.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.negf_plan_execute.restype = C.c_int
+    L.negf_plan_clock_hz.argtypes = []
+    L.negf_plan_clock_hz.restype = dbl
+    L.negf_plan_destroy.argtypes = [vp]
+    L.negf_plan_destroy.restype = None
     if hasattr(L, "negf_mlp_forward"):
         _bind_mlp(L)
     _lib = L
@@ -235,8 +253,9 @@ def _problem_array(problems: Sequence[Problem]):
     return arr
 
 
-def make_options(sr_tol=0.0, sr_max_iter=0, sr_accept=0.0, batch=0, inv_nb=0, xcd_remap=-1, gemm_tile=0):
-    return negf_options(sr_tol, sr_max_iter, sr_accept, batch, inv_nb, xcd_remap, gemm_tile)
+def make_options(sr_tol=0.0, sr_max_iter=0, sr_accept=0.0, batch=0, inv_nb=0, xcd_remap=-1, gemm_tile=0,
+                 gemm_tile_f32=0):
+    return negf_options(sr_tol, sr_max_iter, sr_accept, batch, inv_nb, xcd_remap, gemm_tile, gemm_tile_f32)
 
 
 def _alloc_blocks(problems, per_point_blocks):
@@ -408,3 +427,50 @@ def zinv(M, nb=32):
     code = negf_zinv_batched(n, batch, _ptr(work), _ptr(out), _ptr(info), nb, _ptr(buf), nbytes, _stream())
     check(code, "negf_zinv_batched")
     return out, info
+
+
+class Plan:
+    """A shape-grouped, stream-scheduled batch of problems (negf_plan_*)."""
+
+    def __init__(self, problems, prec=PLAIN_FP64, opts=None, tunings=None, n_streams=4):
+        self.problems = list(problems)
+        self._arr = _problem_array(self.problems)
+        tun = tunings or []
+        self._tun = (negf_tuning * max(1, len(tun)))(*[negf_tuning(*t) for t in tun])
+        self.handle = C.c_void_p()
+        check(lib().negf_plan_create(self._arr, len(self.problems), prec, C.byref(opts) if opts else None,
+                                     self._tun if tun else None, len(tun), n_streams, C.byref(self.handle)),
+              "negf_plan_create")
+        self.ws = Workspace()
+
+    def chunks(self):
+        n = lib().negf_plan_chunks(self.handle, None, None, None)
+        fp, npn, si = (C.c_int32 * n)(), (C.c_int32 * n)(), (C.c_int32 * n)()
+        lib().negf_plan_chunks(self.handle, fp, npn, si)
+        return [(fp[i], npn[i], si[i]) for i in range(n)]
+
+    def execute(self, outputs, info, use_graph=True, stamps=None):
+        buf = self.ws.get(lib().negf_plan_workspace_bytes(self.handle))
+        o = outputs
+        check(lib().negf_plan_execute(self.handle, int(use_graph), _ptr(o["GR_diag"]), _ptr(o["GR_upper"]),
+                                      _ptr(o.get("GR_lower")), _ptr(o["GL_diag"]), _ptr(o["GL_upper"]),
+                                      _ptr(o.get("GG_diag")), _ptr(o.get("GG_upper")), _ptr(info), _ptr(stamps),
+                                      _ptr(buf), buf.numel(), _stream()), "negf_plan_execute")
+
+    def outputs(self, greater=False, lower=True):
+        return _rgf_outputs(self.problems, True, greater, lower)
+
+    @staticmethod
+    def clock_hz():
+        return lib().negf_plan_clock_hz()
+
+    def close(self):
+        if self.handle:
+            lib().negf_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -32,6 +32,7 @@ struct Opts {
   int inv_nb = 32;
   int xcd = 1;
   int tile = GEMM_TILE_64;
+  int tile32 = GEMM_TILE_64;
 };
 
 Opts get_opts(const negf_options* o) {
@@ -44,6 +45,7 @@ Opts get_opts(const negf_options* o) {
   if (o->inv_nb == 16 || o->inv_nb == 32) r.inv_nb = o->inv_nb;
   if (o->xcd_remap == 0 || o->xcd_remap == 1) r.xcd = o->xcd_remap;
   if (o->gemm_tile >= GEMM_TILE_64 && o->gemm_tile <= GEMM_TILE_128x128) r.tile = o->gemm_tile;
+  if (o->gemm_tile_f32 >= GEMM_TILE_64 && o->gemm_tile_f32 <= GEMM_TILE_128x128) r.tile32 = o->gemm_tile_f32;
   return r;
 }
 
@@ -216,7 +218,7 @@ struct Ctx {
     g.active = active;
     g.prec = pr;
     g.xcd_remap = o.xcd;
-    g.tile = o.tile;
+    g.tile = pr == PREC_F32 ? o.tile32 : o.tile;
     g.prof_class = -1;
     chk(launch_gemm(g, s));
   }
@@ -808,6 +810,7 @@ negf_status negf_plan_create(const negf_problem* problems, int32_t n_prob, negf_
     Opts o = P->base;
     if (const negf_tuning* t = tuning_of(c.b)) {
       if (t->gemm_tile >= GEMM_TILE_64 && t->gemm_tile <= GEMM_TILE_128x128) o.tile = t->gemm_tile;
+      if (t->gemm_tile_f32 >= GEMM_TILE_64 && t->gemm_tile_f32 <= GEMM_TILE_128x128) o.tile32 = t->gemm_tile_f32;
       if (t->inv_nb == 16 || t->inv_nb == 32) o.inv_nb = t->inv_nb;
     }
     P->chunk_opts.push_back(o);

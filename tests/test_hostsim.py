@@ -209,7 +209,7 @@ def test_hostsim_plan_matches_plain_calls(sim):
     probs = [HostProblem(nb, d, e) for d, e in zip(devs, ens)]
     ref, ref_info = _run_rgf(L, nb, probs, greater=False)
     arr = (nb.negf_problem * len(probs))(*[p.s for p in probs])
-    tun = (C.c_int32 * 8)(4, 0, 16, 2, 6, 0, 32, 1)    # (b, tile, inv_nb, batch) for b = 4 and b = 6
+    tun = (C.c_int32 * 10)(4, 0, 0, 16, 2, 6, 0, 0, 32, 1)   # (b, tile, tile_f32, inv_nb, batch) for b = 4, 6
     plan = C.c_void_p()
     assert L.negf_plan_create(arr, len(probs), 0, None, C.cast(tun, C.c_void_p), 2, 3, C.byref(plan)) == 0
     nch = L.negf_plan_chunks(plan, None, None, None)
