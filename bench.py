@@ -120,6 +120,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-chosen", action="store_true")
     ap.add_argument("--inv-nb", type=int, default=32)
+    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned"], default="ribbon",
+                    help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
+                         "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation")
+    ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload")
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--learned-energies", type=int, default=250, help="training energies per lead")
+    ap.add_argument("--learned-eval", type=int, default=256, help="evaluation energies per held-out lead")
+    ap.add_argument("--learned-b", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU's share of the energy grid; --gpus {args.gpus} is not supported "
@@ -133,6 +141,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     nb.lib()
+    if args.workload == "uneven":
+        return bench_uneven(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     log("generating the Nb=60 b=512 slab device ...")
     dev = w.slab_device(NB, B, SEED)
     batches = energy_batches(args.points)
@@ -213,6 +225,169 @@ def main():
         "chosen_form": chosen,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_uneven(args):
+    """Six slab devices (b, Nb) in {(128,20),(256,40),(384,60),(512,80),(640,20),(768,40)} x 4 k-points,
+    refined single-product form, one plan (shape-grouped chunks over worker streams) captured as one
+    hipGraph and replayed; points/s and per-device p50/p99 completion times from GPU timestamps."""
+    import torch
+    import workloads as w
+    from paper_2602_03438_amd import autotune
+    from paper_2602_03438_amd import binding as nb
+    ks = [np.pi * j / 4 for j in range(4)]
+    grid = np.linspace(-1.5, 1.5, 2048)
+    probs, dev_of = [], []
+    n_e = args.uneven_points
+    for d, (b, nbk) in enumerate(w.DEVICE_MIX):
+        log(f"device {d}: b={b} Nb={nbk}")
+        base = w.slab_device(nbk, b, 40 + d)
+        S_d = nb.to_gpu(base.S_diag)
+        S_u = nb.to_gpu(base.S_upper)
+        for ki, k in enumerate(ks):
+            dk = w.k_device(base, 1000 + d, k)
+            g = nb.DeviceOnGPU.__new__(nb.DeviceOnGPU)
+            g.nb, g.b = dk.nb, dk.b
+            g.H_diag, g.H_upper = nb.to_gpu(dk.H_diag), nb.to_gpu(dk.H_upper)
+            g.S_diag, g.S_upper = S_d, S_u
+            g.sig_r = g.sig_l = g.sig_g = None
+            # point p of the (E, k) grid belongs to device p mod 6: take this device's share, n_e per k
+            share = grid[(np.arange(grid.size) * 4 + ki) % 6 == d]
+            E = share[np.linspace(0, share.size - 1, n_e).astype(int)]
+            probs.append(nb.Problem(g, E, eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT))
+            dev_of.append(d)
+    tunings = []
+    for b, _ in w.DEVICE_MIX:
+        t = autotune.lookup(b)
+        tunings.append((b, t["gemm_tile"], t["gemm_tile_f32"], t["inv_nb"], 2 * n_e))
+    plan = nb.Plan(probs, nb.FP32_REFINE, opts=nb.make_options(sr_max_iter=40), tunings=tunings,
+                   n_streams=args.streams)
+    chunks = plan.chunks()
+    outs = plan.outputs()
+    npts = sum(p.n_e for p in probs)
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    stamps = torch.zeros(len(chunks) + 1, dtype=torch.int64, device="cuda")
+    log(f"{len(probs)} problems, {npts} points, {len(chunks)} chunks on {args.streams} streams; capturing ...")
+    plan.execute(outs, info, use_graph=True, stamps=stamps)
+    torch.cuda.synchronize()
+    log("captured; replaying")
+    for _ in range(args.warmup):
+        plan.execute(outs, info, use_graph=True, stamps=stamps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan.execute(outs, info, use_graph=True, stamps=stamps)
+        torch.cuda.synchronize()
+        log(f"  replay {k + 1}/{args.steps} done")
+    dt = time.perf_counter() - t0
+    hz = nb.Plan.clock_hz()
+    st = stamps.cpu().numpy().astype(np.float64)
+    t_chunk = (st[1:] - st[0]) / hz
+    # per-point completion = completion of its chunk
+    first = np.array([c[0] for c in chunks])
+    count = np.array([c[1] for c in chunks])
+    pt_done = np.zeros(npts)
+    for c in range(len(chunks)):
+        pt_done[first[c]:first[c] + count[c]] = t_chunk[c]
+    dev_pt = np.concatenate([[dev_of[q]] * p.n_e for q, p in enumerate(probs)])
+    per_dev = {}
+    for d, (b, nbk) in enumerate(w.DEVICE_MIX):
+        x = pt_done[dev_pt == d]
+        per_dev[f"b{b}_nb{nbk}"] = {"points": int(x.size), "p50_s": float(np.percentile(x, 50)),
+                                    "p99_s": float(np.percentile(x, 99)), "last_s": float(x.max())}
+    # eager (no graph) for comparison
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.execute(outs, info, use_graph=False, stamps=stamps)
+    torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t1
+    line = {"metric": "energy points/s, batched uneven workload (6 devices x 4 k, refined single-product form)",
+            "value": npts * args.steps / dt, "unit": "energy points/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+            "dtype": "f32 products + f64 refinement", "data": "synthetic",
+            "config": {"workload": "uneven: six slab devices (b, Nb) in " + str(w.DEVICE_MIX) +
+                       f" x 4 k-points, {n_e} energies per (device, k)", "points_per_step": npts,
+                       "chunks": len(chunks), "streams": args.streams, "tunings": tunings},
+            "eager_points_per_s": npts / dt_eager,
+            "info_nonzero": int(torch.count_nonzero(info).item()),
+            "per_device_completion": per_dev}
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
+def bench_learned(args):
+    """MLP-seeded lead decimation: train on decimation-converged samples of 8 leads, evaluate on held-out
+    leads; report iterations to convergence, acceptance of the seed and points/s with and without it."""
+    import torch
+    import workloads as w
+    from paper_2602_03438_amd import binding as nb
+    from paper_2602_03438_amd import learned as Lm
+    b = args.learned_b
+    rng = np.random.Generator(np.random.PCG64(599))
+    t_start = time.perf_counter()
+    X_all, T_all = [], []
+    sr_iters_train = []
+    for seed in range(500, 508):
+        lead = w.slab_lead(b, seed)
+        basis = Lm.lead_basis(lead, 0)
+        gb = Lm.GPUBasis(basis)
+        E = rng.uniform(-1.5, 1.5, args.learned_energies)
+        prob = nb.Problem(nb.DeviceOnGPU(lead), E, eta=ETA)
+        out = nb.obc_surface([prob], 0)
+        g = out["g_surf"][0][:, 0].contiguous()
+        T_all.append(gb.targets(g))
+        X_all.append(torch.from_numpy(Lm.features(basis, E)).cuda())
+        sr_iters_train.append(out["iters"].cpu().numpy())
+        log(f"lead {seed}: {E.size} samples, mean decimation steps {sr_iters_train[-1].mean():.1f}")
+    X = torch.cat(X_all)
+    T = torch.cat(T_all)
+    gen_s = time.perf_counter() - t_start
+    # targets span decades near band edges: train on a signed-log compression, invert at inference
+    Tc = torch.sign(T) * torch.log1p(torch.abs(T))
+    net = Lm.MLP(seed=0)
+    t0 = time.perf_counter()
+    losses = net.train(X, Tc, epochs=4, batch=65536, lr=1e-3, log=log)
+    train_s = time.perf_counter() - t0
+    res = {"plain": {"iters": [], "s": 0.0}, "seeded": {"iters": [], "s": 0.0, "accepted": 0}}
+    n_eval = 0
+    for seed in range(600, 604):
+        lead = w.slab_lead(b, seed)
+        basis = Lm.lead_basis(lead, 0)
+        gb = Lm.GPUBasis(basis)
+        E = np.linspace(-1.5, 1.5, args.learned_eval)
+        prob = nb.Problem(nb.DeviceOnGPU(lead), E, eta=ETA)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain = nb.obc_surface([prob], 0)
+        torch.cuda.synchronize()
+        res["plain"]["s"] += time.perf_counter() - t1
+        t1 = time.perf_counter()
+        Xh = torch.from_numpy(Lm.features(basis, E)).cuda()
+        Yc = net.infer_bf16(Xh)
+        Y = torch.sign(Yc) * torch.expm1(torch.abs(Yc))
+        seeds = gb.seeds(Y)
+        seeded = nb.obc_surface([prob], 0, seed=seeds)
+        torch.cuda.synchronize()
+        res["seeded"]["s"] += time.perf_counter() - t1
+        res["plain"]["iters"] += plain["iters"].cpu().tolist()
+        it = seeded["iters"].cpu().numpy()
+        res["seeded"]["iters"] += it.tolist()
+        res["seeded"]["accepted"] += int(np.count_nonzero(it == 0))
+        d = (seeded["g_surf"][0] - plain["g_surf"][0]).abs().max().item()
+        log(f"held-out lead {seed}: plain {np.mean(plain['iters'].cpu().numpy()):.2f} steps, seeded "
+            f"{np.mean(it):.2f} steps, accepted {np.count_nonzero(it == 0)}/{E.size}, max |dg| {d:.2e}")
+        n_eval += E.size
+    line = {"metric": "learned lead initialiser: decimation steps and energy points/s with vs without the seed",
+            "unit": "energy points/s", "value": n_eval / res["seeded"]["s"], "higher_is_better": True,
+            "plain_value": n_eval / res["plain"]["s"],
+            "mean_steps_plain": float(np.mean(res["plain"]["iters"])),
+            "mean_steps_seeded": float(np.mean(res["seeded"]["iters"])),
+            "seed_acceptance": res["seeded"]["accepted"] / n_eval,
+            "fallback_rate": 1.0 - res["seeded"]["accepted"] / n_eval,
+            "train_samples": int(X.shape[0] // b), "train_rows": int(X.shape[0]), "final_mse": losses[-1],
+            "data_generation_s": gen_s, "train_s": train_s, "b": b, "eval_points": n_eval,
+            "dtype": "f32 training, bf16 inference, f64 decimation", "data": "synthetic"}
     print(json.dumps(line), flush=True)
 
 

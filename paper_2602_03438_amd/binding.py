@@ -294,6 +294,8 @@ def workspace_bytes(op, problems, prec=PLAIN_FP64, opts=None):
 
 def obc_surface(problems: List[Problem], side: int, opts=None, seed=None, ws: Optional[Workspace] = None):
     torch = _torch()
+    if seed is not None and not seed.is_contiguous():
+        raise NegfError("seed must be a C-contiguous [points, b, b] complex128 tensor")
     arr = _problem_array(problems)
     o = C.byref(opts) if opts else None
     nbytes = negf_workspace_bytes(OP_OBC, arr, len(problems), PLAIN_FP64, o)
@@ -400,6 +402,9 @@ def transmission(problems, opts=None, ws=None):
 def zgemm(A, B, C_=None, opa="N", opb="N", alpha=1.0, beta=0.0, prec=0, tile=0):
     """Batched complex product on the library kernel: C = alpha op(A) op(B) + beta C."""
     torch = _torch()
+    for t in (A, B, C_):
+        if t is not None and not t.is_contiguous():
+            raise NegfError("zgemm operands must be C-contiguous [batch, rows, cols] complex128 tensors")
     batch = A.shape[0]
     M = A.shape[1] if opa == "N" else A.shape[2]
     K = A.shape[2] if opa == "N" else A.shape[1]
@@ -419,7 +424,7 @@ def zinv(M, nb=32):
     """Batched inverse of [batch, n, n] complex128 blocks (M is copied, not destroyed)."""
     torch = _torch()
     batch, n, _ = M.shape
-    work = M.clone()
+    work = M.contiguous().clone(memory_format=torch.contiguous_format)
     out = torch.empty_like(M)
     info = torch.zeros(batch, dtype=torch.int32, device="cuda")
     nbytes = negf_inverse_workspace_bytes(n, batch)

@@ -88,7 +88,7 @@ def test_zinv_parity(nb, n, panel):
     r = np.random.Generator(np.random.PCG64(n + panel))
     M = _rand(r, (3, n, n)) + 2.0 * np.sqrt(n) * np.eye(n) * np.array([1, 1j, -1])[:, None, None]
     # a row permutation makes pivoting necessary
-    M = M[:, r.permutation(n), :]
+    M = np.ascontiguousarray(M[:, r.permutation(n), :])
     out, info = nb.zinv(torch.from_numpy(M).cuda(), panel)
     got = out.cpu().numpy()
     ref = np.linalg.inv(M)

@@ -1,0 +1,135 @@
+"""GPU: plans (uneven shapes over worker streams, one captured hipGraph) and
+the learned seed path of the decimation."""
+import numpy as np
+import pytest
+
+import workloads as w
+from helpers import well_posed
+from oracle import leads as oleads
+from oracle import rgf as orgf
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2602_03438_amd import binding
+    binding.lib()
+    return binding
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _problems(nb):
+    devs = [w.slab_device(4, 40, 31), w.slab_device(3, 72, 32), w.slab_device(5, 40, 33), w.slab_device(3, 100, 34)]
+    ens = [well_posed(d, np.linspace(-1.1, 1.1, 7))[:k] for d, k in zip(devs, (3, 2, 3, 2))]
+    probs = [nb.Problem(nb.DeviceOnGPU(d), e, eta=1e-8, mu_l=0.1, mu_r=-0.1) for d, e in zip(devs, ens)]
+    return devs, ens, probs
+
+
+def test_plan_graph_replays_match_eager_and_plain_call(nb):
+    import torch
+    devs, ens, probs = _problems(nb)
+    ref = nb.rgf_lesser_greater(probs, nb.PLAIN_FP64, opts=nb.make_options(sr_max_iter=40))
+    plan = nb.Plan(probs, nb.PLAIN_FP64, opts=nb.make_options(sr_max_iter=40),
+                   tunings=[(40, 1, 1, 32, 2), (72, 2, 1, 16, 1), (100, 3, 1, 32, 0)], n_streams=3)
+    chunks = plan.chunks()
+    assert sum(c[1] for c in chunks) == sum(p.n_e for p in probs)
+    outs = plan.outputs()
+    npts = sum(p.n_e for p in probs)
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    stamps = torch.zeros(len(chunks) + 1, dtype=torch.int64, device="cuda")
+    plan.execute(outs, info, use_graph=False, stamps=stamps)
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in outs.items() if v is not None}
+    for k in eager:
+        assert rel(eager[k].cpu().numpy(), ref["flat"][k].cpu().numpy()) < 1e-12, k
+    assert torch.equal(info, ref["info"])
+    for rep in range(3):
+        for v in outs.values():
+            if v is not None:
+                v.zero_()
+        # unrelated eager work between replays
+        x = torch.randn(256, 256, dtype=torch.float64, device="cuda")
+        (x @ x).sum().item()
+        plan.execute(outs, info, use_graph=True, stamps=stamps)
+        torch.cuda.synchronize()
+        for k in eager:
+            assert torch.equal(outs[k], eager[k]), (rep, k)
+        st = stamps.cpu().numpy()
+        assert np.all(st[1:] >= st[0])
+    plan.close()
+
+
+def test_plan_refined_form_against_oracle(nb):
+    import torch
+    devs, ens, probs = _problems(nb)
+    plan = nb.Plan(probs, nb.FP32_REFINE, opts=nb.make_options(sr_max_iter=40), n_streams=2)
+    outs = plan.outputs()
+    npts = sum(p.n_e for p in probs)
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    plan.execute(outs, info, use_graph=True)
+    torch.cuda.synchronize()
+    views = nb._views(outs, probs)
+    for q, (d, e) in enumerate(zip(devs, ens)):
+        for k, E in enumerate(e):
+            ref = orgf.solve_point(d, E, 1e-8, 0.1, -0.1, 0.025)
+            assert rel(views["GR_diag"][q][k].cpu().numpy(), ref.GR_diag) < 1e-6
+            assert rel(views["GL_diag"][q][k].cpu().numpy(), ref.GL_diag) < 1e-6
+    plan.close()
+
+
+def test_seeded_decimation_exact_and_fallback(nb):
+    import torch
+    dev = w.slab_device(3, 48, 5)
+    E = np.array([-0.7, 0.2, 0.9])
+    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=1e-8)
+    exact = np.stack([oleads.lead_self_energy(dev, 0, e, 1e-8).g_surf for e in E])
+    seed = exact.copy()
+    seed[1] = 0.3 * np.eye(48)                     # a poor guess: must fall back
+    out = nb.obc_surface([prob], 0, seed=torch.from_numpy(seed).cuda())
+    it = out["iters"].cpu().numpy()
+    assert it[0] == 0 and it[2] == 0 and it[1] > 5
+    for k in range(3):
+        assert rel(out["g_surf"][0][k, 0].cpu().numpy(), exact[k]) < 1e-10
+    assert np.all(out["info"].cpu().numpy() == 0)
+
+
+def test_learned_initialiser_end_to_end(nb):
+    """Train the per-mode MLP on decimation-converged samples of two small leads,
+    seed a held-out lead and check the result equals plain decimation; report
+    the step counts (a learned seed is not expected to shorten the iteration)."""
+    import torch
+    from paper_2602_03438_amd import learned as Lm
+    b = 40
+    X, T = [], []
+    for seed in (500, 501):
+        lead = w.slab_lead(b, seed)
+        basis = Lm.lead_basis(lead, 0)
+        E = np.linspace(-1.4, 1.4, 60)
+        out = nb.obc_surface([nb.Problem(nb.DeviceOnGPU(lead), E, eta=1e-8)], 0)
+        X.append(torch.from_numpy(Lm.features(basis, E)).cuda())
+        T.append(Lm.GPUBasis(basis).targets(out["g_surf"][0][:, 0].contiguous()))
+    X, T = torch.cat(X), torch.cat(T)
+    Tc = torch.sign(T) * torch.log1p(torch.abs(T))
+    net = Lm.MLP(seed=0, width=64)
+    losses = net.train(X, Tc, epochs=40, batch=1024, lr=2e-3)
+    assert losses[-1] < losses[0]
+    lead = w.slab_lead(b, 600)
+    basis = Lm.lead_basis(lead, 0)
+    E = np.linspace(-1.3, 1.3, 16)
+    prob = nb.Problem(nb.DeviceOnGPU(lead), E, eta=1e-8)
+    Yc = net.infer_bf16(torch.from_numpy(Lm.features(basis, E)).cuda())
+    seeds = Lm.GPUBasis(basis).seeds(torch.sign(Yc) * torch.expm1(torch.abs(Yc)))
+    plain = nb.obc_surface([prob], 0)
+    seeded = nb.obc_surface([prob], 0, seed=seeds)
+    assert torch.equal(plain["info"], seeded["info"])
+    diff = (seeded["g_surf"][0] - plain["g_surf"][0]).abs().max().item()
+    scale = plain["g_surf"][0].abs().max().item()
+    assert diff < 1e-9 * scale
+    print(f"mean steps plain {plain['iters'].float().mean().item():.2f}, "
+          f"seeded {seeded['iters'].float().mean().item():.2f}")
