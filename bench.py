@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--points", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-chosen", action="store_true")
-    ap.add_argument("--inv-nb", type=int, default=32)
+    ap.add_argument("--inv-nb", type=int, default=16)
     ap.add_argument("--workload", choices=["ribbon", "uneven", "learned"], default="ribbon",
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation")

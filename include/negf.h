@@ -71,10 +71,11 @@ typedef enum {
 /* Arithmetic of the dense block products of the RGF sweeps.  Inversions,
  * block sums, residuals and the lead decimation are double in every mode.
  *  PLAIN_FP64    : every product in double (the reference method)
- *  FP32_REFINE   : retarded forward sweep double; backward retarded and the
- *                  lesser/greater forward products single (complex64 operands,
- *                  single accumulation) followed by one double-precision
- *                  residual correction per block; lesser/greater backward double
+ *  FP32_REFINE   : backward retarded products single (complex64 operands,
+ *                  single accumulation), each block followed by one
+ *                  double-precision residual correction of its three blocks
+ *                  from the local identities of the backward step; everything
+ *                  else double
  *  FP32_NOREFINE : every sweep product single, no correction (diagnostic)   */
 typedef enum { NEGF_PLAIN_FP64 = 0, NEGF_FP32_REFINE = 1, NEGF_FP32_NOREFINE = 2 } negf_precision;
 
@@ -109,9 +110,9 @@ typedef struct negf_problem {
 typedef struct negf_options {
   double sr_tol;        /* decimation stops when ||a||_F, ||c||_F <= tol ||d||_F  [1e-14] */
   int32_t sr_max_iter;  /* decimation iteration cap                              [100]   */
-  double sr_accept;     /* normalised Dyson residual above which info=ENOCONV   [1e-10] */
+  double sr_accept;     /* normalised Dyson residual above which info=ENOCONV   [1e-8]  */
   int32_t batch;        /* points in flight per group (0: all points of the call) [0]   */
-  int32_t inv_nb;       /* panel width of the block inversion (16 or 32)          [32]  */
+  int32_t inv_nb;       /* panel width of the block inversion (16 or 32)          [16]  */
   int32_t xcd_remap;    /* 1: place the tiles of one matrix on one XCD            [1]   */
   int32_t gemm_tile;    /* product tile: 1 = 64x64, 2 = 128x64, 3 = 128x128       [1]   */
   int32_t gemm_tile_f32;/* tile of the single-precision products                  [1]   */

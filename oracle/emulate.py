@@ -11,19 +11,20 @@ inversions, block sums and residuals stay complex128.
 Variants (``mode``):
   "fp64"      -- every product in complex128 (equals ``rgf``)
   "fp32"      -- every sweep product single, no refinement
-  "refine"    -- forward retarded sweep in double; backward retarded and
-                 both lesser sweeps single, each block followed by one
-                 double-precision residual correction through g_i:
+  "refine"    -- backward retarded products single, each block followed by
+                 one double-precision residual correction through g_i; every
+                 other product double:
                    retarded  (local identities of the backward step)
                      r_lo = -G_{i+1,i+1} A_{i+1,i} - G_{i+1,i} M_i ;  G_{i+1,i} += r_lo g_i
                      r_d  = I - M_i G_ii - A_{i,i+1} G_{i+1,i}     ;  G_ii     += g_i r_d
                      r_up = -A_{i,i+1} G_{i+1,i+1} - M_i G_{i,i+1} ;  G_{i,i+1} += g_i r_up
-                   lesser forward (B_i = Sigma^<_ii + A_{i,i-1} g^<_{i-1} A_{i,i-1}^H
-                   formed in double, g^<_i = g_i B_i g_i^H single)
-                     r = B_i - M_i g^<_i M_i^H ;  g^<_i += g_i r g_i^H
-                 the lesser backward sweep stays in double: each of its five
-                 products alone leaves ~1e-5 in G^< when single, and a local
-                 residual for it costs more double products than the step.
+                 both lesser sweeps stay in double: each of the five backward
+                 products alone leaves ~1e-5 in G^< when single, and single
+                 forward products with one residual correction
+                 (r = B_i - M_i g^<_i M_i^H, g^<_i += g_i r g_i^H) still leave
+                 ~3e-7 in g^<, which the backward sweep amplifies to ~7e-6 on a
+                 60-block device.  ``lesser(..., mode="refine1")`` keeps that
+                 variant for the record.
 """
 from __future__ import annotations
 
@@ -76,23 +77,23 @@ def retarded(Ad, Au, Al, mode="refine"):
 def lesser(R, Au, Al, sig_diag, mode="refine"):
     g, M, X, Gd, Gu = R["g"], R["M"], R["X"], R["Gd"], R["Gu"]
     nb = len(g)
-    mm = mm64 if mode == "fp64" else mm32
+    mm = mm32 if mode in ("fp32", "refine1") else mm64
     gl = [None] * nb
     B = [None] * nb
     B[0] = sig_diag[0]
     gl[0] = mm(mm(g[0], B[0]), g[0].conj().T)
-    if mode == "refine":
+    if mode == "refine1":
         r = B[0] - M[0] @ gl[0] @ M[0].conj().T
         gl[0] = gl[0] + mm32(mm32(g[0], r), g[0].conj().T)
     for i in range(1, nb):
-        # in the refined variant B_i is formed in double: the residual needs it
-        mb = mm64 if mode == "refine" else mm
+        # with a residual correction B_i is formed in double: the residual needs it
+        mb = mm64 if mode == "refine1" else mm
         B[i] = sig_diag[i] + mb(mb(Al[i - 1], gl[i - 1]), Al[i - 1].conj().T)
         gl[i] = mm(mm(g[i], B[i]), g[i].conj().T)
-        if mode == "refine":
+        if mode == "refine1":
             r = B[i] - M[i] @ gl[i] @ M[i].conj().T
             gl[i] = gl[i] + mm32(mm32(g[i], r), g[i].conj().T)
-    if mode == "refine":
+    if mode in ("refine", "refine1"):
         mm = mm64
     Ld = [None] * nb
     Lu = [None] * (nb - 1)

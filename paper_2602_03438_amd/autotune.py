@@ -7,7 +7,7 @@ For a block size b it times, on the GPU, every candidate of
 and keeps the fastest.  Results are cached as JSON keyed by
 "<arch>/b=<b>/<dtype>/<op>" (``tune_cache.json`` next to this file, or the
 path in $NEGF_TUNE_CACHE); a block size with no entry gets the deterministic
-default (64x64 tiles, panel 32).
+default (64x64 tiles, panel 16).
 
     python -m paper_2602_03438_amd.autotune 128 256 384 512 640 768
 """
@@ -23,7 +23,7 @@ from . import binding as nb
 HERE = os.path.dirname(os.path.abspath(__file__))
 ARCH = "gfx950"
 TILES = {1: "64x64", 2: "128x64", 3: "128x128"}
-DEFAULT = {"gemm_tile": 1, "gemm_tile_f32": 1, "inv_nb": 32}
+DEFAULT = {"gemm_tile": 1, "gemm_tile_f32": 1, "inv_nb": 16}
 
 
 def cache_path() -> str:

@@ -27,9 +27,9 @@ const double2 ZERO = {0.0, 0.0};
 struct Opts {
   double tol = 1e-14;
   int max_iter = 100;
-  double accept = 1e-10;
+  double accept = 1e-8;
   int batch = 0;
-  int inv_nb = 32;
+  int inv_nb = 16;
   int xcd = 1;
   int tile = GEMM_TILE_64;
   int tile32 = GEMM_TILE_64;
@@ -564,9 +564,11 @@ void forward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, 
                     double2* gl) {
   const int b = ch.b, nb = ch.nb, n = ch.npts;
   const long bb = (long)b * b, ds = (long)nb * bb;
-  const bool refine = prec == NEGF_FP32_REFINE;
-  const Prec pg = (prec == NEGF_PLAIN_FP64) ? PREC_F64 : PREC_F32;    // g B g^H
-  const Prec pbt = (prec == NEGF_FP32_NOREFINE) ? PREC_F32 : PREC_F64; // B formation
+  // the refined form keeps the lesser sweeps in double: one residual correction of
+  // single-precision products here leaves ~3e-7 in g^<, which the backward sweep
+  // amplifies beyond 1e-6 over a 60-block device
+  const Prec pg = (prec == NEGF_FP32_NOREFINE) ? PREC_F32 : PREC_F64;  // g B g^H
+  const Prec pbt = pg;                                                  // B formation
   for (int i = 0; i < nb && cx.ok(); ++i) {
     const double2* gi = GRd + (long)i * bb;
     double2* gli = gl + (long)i * bb;
@@ -582,14 +584,6 @@ void forward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, 
     // g^<_i = g_i B g_i^H
     cx.gemm(pg, OP_N, OP_N, b, n, ONE, gi, ds, pw.T4.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
     cx.gemm(pg, OP_N, OP_C, b, n, ONE, pw.T3.p, bb, gi, ds, ZERO, nullptr, 0, gli, ds);
-    if (refine) {
-      // r = B - M_i g^<_i M_i^H ; g^<_i += g_i r g_i^H
-      const double2* Mi = pw.Mst + (long)i * bb;
-      cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, Mi, ds, gli, ds, ZERO, nullptr, 0, pw.T2.p, bb);
-      cx.gemm(PREC_F64, OP_N, OP_C, b, n, MONE, pw.T2.p, bb, Mi, ds, ONE, pw.T4.p, bb, pw.T4.p, bb);
-      cx.gemm(PREC_F32, OP_N, OP_N, b, n, ONE, gi, ds, pw.T4.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
-      cx.gemm(PREC_F32, OP_N, OP_C, b, n, ONE, pw.T3.p, bb, gi, ds, ONE, gli, ds, gli, ds);
-    }
   }
 }
 
