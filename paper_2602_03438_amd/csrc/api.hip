@@ -723,12 +723,12 @@ struct negf_plan {
   int n_streams = 1;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
+  hipStream_t origin = nullptr;   // capture origin (the caller's stream may be the legacy null stream)
   void* graph = nullptr;
   // arguments the graph was captured with (a replay is valid only for the same ones)
   Outs cap_outs{};
   void* cap_ws = nullptr;
   unsigned long long* cap_stamps = nullptr;
-  hipStream_t cap_stream = nullptr;
 };
 
 namespace {
@@ -862,6 +862,7 @@ negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag,
   negf_plan* P = plan;
   hipStream_t main = (hipStream_t)stream;
   if (P->streams.empty()) {
+    if (rt_stream_create(&P->origin) != hipSuccess) return NEGF_EHIP;
     for (int i = 0; i < P->n_streams; ++i) {
       hipStream_t st = nullptr;
       if (rt_stream_create(&st) != hipSuccess) return NEGF_EHIP;
@@ -878,21 +879,23 @@ negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag,
   char* ws = align256(workspace);
   unsigned long long* stp = (unsigned long long*)stamps;
   if (!use_graph) return to_status(enqueue_plan(P, outs, ws, stp, main));
-  const bool reuse = P->graph && same_outs(P->cap_outs, outs) && P->cap_ws == ws && P->cap_stamps == stp &&
-                     P->cap_stream == main;
+  const bool reuse = P->graph && same_outs(P->cap_outs, outs) && P->cap_ws == ws && P->cap_stamps == stp;
   if (!reuse) {
     if (P->graph) rt_graph_destroy(P->graph);
     P->graph = nullptr;
-    if (rt_capture_begin(main) != hipSuccess) return NEGF_EHIP;
-    hipError_t e = enqueue_plan(P, outs, ws, stp, main);
+    // capture on the plan's own origin stream; a begun capture is always ended
+    if (rt_capture_begin(P->origin) != hipSuccess) return NEGF_EHIP;
+    hipError_t e = enqueue_plan(P, outs, ws, stp, P->origin);
     void* exec = nullptr;
-    hipError_t e2 = rt_capture_end(main, &exec);
-    if (e != hipSuccess || e2 != hipSuccess) return NEGF_EHIP;
+    hipError_t e2 = rt_capture_end(P->origin, &exec);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (exec) rt_graph_destroy(exec);
+      return NEGF_EHIP;
+    }
     P->graph = exec;
     P->cap_outs = outs;
     P->cap_ws = ws;
     P->cap_stamps = stp;
-    P->cap_stream = main;
   }
   return to_status(rt_graph_launch(P->graph, main));
 }
@@ -902,6 +905,7 @@ void negf_plan_destroy(negf_plan* plan) {
   if (plan->graph) rt_graph_destroy(plan->graph);
   for (hipEvent_t e : plan->events) rt_event_destroy(e);
   for (hipStream_t s : plan->streams) rt_stream_destroy(s);
+  if (plan->origin) rt_stream_destroy(plan->origin);
   delete plan;
 }
 

@@ -93,9 +93,13 @@ hipError_t rt_capture_begin(hipStream_t s) {
 
 hipError_t rt_capture_end(hipStream_t s, void** exec) {
   g_capturing = false;
+  *exec = nullptr;
   hipGraph_t g = nullptr;
   hipError_t r = hipStreamEndCapture(s, &g);
-  if (r != hipSuccess) return r;
+  if (r != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return r;
+  }
   hipGraphExec_t ex = nullptr;
   r = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
