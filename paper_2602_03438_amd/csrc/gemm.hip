@@ -116,7 +116,9 @@ __device__ __forceinline__ void store_tile(typename Cx<T>::type* s, const double
   }
 }
 
-template <typename T, int OPA, int OPB, typename CF>
+// TAG only separates the symbol of the inversion updates from the sweep
+// products in profiles; the code is the same.
+template <typename T, int OPA, int OPB, typename CF, int TAG = 0>
 __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
   typedef typename Cx<T>::type CT;
   typedef typename Acc<T>::type AT;
@@ -243,7 +245,9 @@ hipError_t launch_cfg(const GemmDesc& d, KArgs ka, hipStream_t s) {
   ka.tiles_n = (d.N + CF::BN - 1) / CF::BN;
   const long total = (long)ka.tiles_m * ka.tiles_n * d.batch;
   const dim3 grid((unsigned)total), block(CF::NT);
-  if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF>), grid, block, 0, s, ka);
+  if (d.prof_class == KC_INV_GEMM && d.opA == OP_N && d.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 1>), grid, block, 0, s, ka);
+  else if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF>), grid, block, 0, s, ka);
   else if (d.opA == OP_C && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF>), grid, block, 0, s, ka);
   else if (d.opA == OP_N && d.opB == OP_C) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_C, CF>), grid, block, 0, s, ka);
   else hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_C, CF>), grid, block, 0, s, ka);

@@ -30,10 +30,12 @@ constexpr int NB_MAX = 32;
 
 struct PanelArgs {
   int n, j0, nbw;
+  int c0, c1;               // columns the interchanges and U cover (the current super-panel)
   double2* A; long lda, sA;
   double2* W; long sW;      // W_p: n x NB row-major
-  double2* U; long sU;      // U_p: NB x n row-major
+  double2* U; long sU;      // U_p: NB x n row-major (columns c0..c1 written)
   int* sigma; long sS;      // sigma_p[i]: original row now at position i
+  int* piv;                 // piv_p[j]: row interchanged with row j (same stride as sigma)
   int* info; int info_mod;
   const int* active;
 };
@@ -168,8 +170,8 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
       if (c < nbw) A[(long)r * a.lda + j0 + c] = make_double2(0.0, 0.0);
   }
   __syncthreads();
-  // --- interchanges on the other columns, pivot rows into U (identity in the panel columns)
-  for (int c = r; c < n; c += blockDim.x) {
+  // --- interchanges on the other columns of [c0, c1), pivot rows into U (identity in the panel columns)
+  for (int c = a.c0 + r; c < a.c1; c += blockDim.x) {
     if (c >= j0 && c < j0 + nbw) {
       for (int k = 0; k < nbw; ++k) U[(long)k * n + c] = make_double2(k == c - j0 ? 1.0 : 0.0, 0.0);
       continue;
@@ -199,6 +201,7 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
       sigma[jr] = sigma[q];
       sigma[q] = t;
     }
+  if (r < nbw) a.piv[(long)p * a.sS + j0 + r] = L.spiv[r];
   if (status != ST_OK && a.info) atomicCAS(a.info + (a.info_mod > 0 ? p % a.info_mod : p), ST_OK, status);
 }
 
@@ -223,52 +226,140 @@ __global__ void __launch_bounds__(256) gj_gather_kernel(int n, const double2* M,
   }
 }
 
-size_t per_item_bytes(int n) {
-  const size_t per = (size_t)2 * n * NB_MAX * sizeof(double2) + (size_t)n * sizeof(int);
-  return (per + 255) & ~(size_t)255;
+// Outer step of the two-level blocking, for the super-panel J = [J0, J0+mo):
+// the mo interchanges recorded by the inner panels are applied to the columns
+// outside J, the pivot rows of those columns move into Uo (mo x n, identity in
+// the columns of J) and are cleared.  One thread per column.
+__global__ void __launch_bounds__(256) gj_outer_swap_kernel(int n, int J0, int mo, double2* A, long lda, long sA,
+                                                            double2* Uo, long sU, const int* piv, long sP,
+                                                            const int* active) {
+  const int p = blockIdx.y;
+  if (active && active[p] == 0) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double2* Ap = A + (long)p * sA;
+  double2* U = Uo + (long)p * sU;
+  const int* pv = piv + (long)p * sP;
+  if (c >= J0 && c < J0 + mo) {
+    for (int k = 0; k < mo; ++k) U[(long)k * n + c] = make_double2(k == c - J0 ? 1.0 : 0.0, 0.0);
+    return;
+  }
+  for (int k = 0; k < mo; ++k) {
+    const int jr = J0 + k, q = pv[jr];
+    if (q != jr) {
+      const double2 t0 = Ap[(long)jr * lda + c];
+      Ap[(long)jr * lda + c] = Ap[(long)q * lda + c];
+      Ap[(long)q * lda + c] = t0;
+    }
+  }
+  for (int k = 0; k < mo; ++k) {
+    const long o = (long)(J0 + k) * lda + c;
+    U[(long)k * n + c] = Ap[o];
+    Ap[o] = make_double2(0.0, 0.0);
+  }
+}
+
+// Wo (n x mo) <- columns [J0, J0+mo) of A, which are then cleared.
+__global__ void __launch_bounds__(256) gj_take_panel_kernel(int n, int J0, int mo, double2* A, long lda, long sA,
+                                                            double2* Wo, long sW, const int* active) {
+  const int p = blockIdx.y;
+  if (active && active[p] == 0) return;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * mo) return;
+  const int r = (int)(e / mo), c = (int)(e % mo);
+  double2* Ap = A + (long)p * sA;
+  Wo[(long)p * sW + e] = Ap[(long)r * lda + J0 + c];
+  Ap[(long)r * lda + J0 + c] = make_double2(0.0, 0.0);
+}
+
+constexpr int NBO = 128;   // outer block of the two-level scheme
+
+struct ScratchLayout {
+  size_t per_al;
+  size_t off_W, off_U, off_Wo, off_Uo, off_sigma, off_piv;
+};
+
+ScratchLayout layout(int n) {
+  ScratchLayout L{};
+  size_t o = 0;
+  L.off_W = o;  o += (size_t)n * NB_MAX * sizeof(double2);
+  L.off_U = o;  o += (size_t)NB_MAX * n * sizeof(double2);
+  L.off_Wo = o; o += (size_t)n * NBO * sizeof(double2);
+  L.off_Uo = o; o += (size_t)NBO * n * sizeof(double2);
+  L.off_sigma = o; o += (size_t)n * sizeof(int);
+  L.off_piv = o;   o += (size_t)n * sizeof(int);
+  L.per_al = (o + 255) & ~(size_t)255;
+  return L;
+}
+
+GemmDesc update_desc(int M, int N, int K, const double2* Wm, long ldw, long sW, const double2* Um, long ldu, long sU,
+                     double2* C, long ldc, long sC, int batch, const int* active) {
+  GemmDesc g{};
+  g.M = M; g.N = N; g.K = K; g.batch = batch;
+  g.opA = OP_N; g.opB = OP_N;
+  g.A = MatRef{Wm, ldw, sW};
+  g.B = MatRef{Um, ldu, sU};
+  g.alpha = make_double2(1.0, 0.0);
+  g.beta = make_double2(1.0, 0.0);
+  g.Cin = MatRef{C, ldc, sC};
+  g.C = MatOut{C, ldc, sC};
+  g.active = active;
+  g.prec = PREC_F64;
+  g.xcd_remap = 1;
+  g.tile = GEMM_TILE_64;
+  g.prof_class = KC_INV_GEMM;
+  return g;
 }
 
 }  // namespace
 
-size_t inverse_scratch_bytes(int n, int batch) { return per_item_bytes(n) * batch; }
+size_t inverse_scratch_bytes(int n, int batch) { return layout(n).per_al * batch; }
 
 hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
   const int n = d.n;
   if (n <= 0 || d.batch <= 0) return hipSuccess;
   if (n > MAX_ROWS) return hipErrorInvalidValue;
   const int NB = (d.nb == 32 && n <= 512) ? 32 : 16;
-  const size_t per_al = per_item_bytes(n);
-  const long sItem = (long)(per_al / sizeof(double2));   // per_al is a multiple of 256 bytes
-  const long sI = (long)(per_al / sizeof(int));
+  const ScratchLayout SL = layout(n);
+  const long sItem = (long)(SL.per_al / sizeof(double2));   // per_al is a multiple of 256 bytes
+  const long sI = (long)(SL.per_al / sizeof(int));
   char* base = (char*)d.scratch;
-  double2* W = (double2*)base;
-  double2* U = (double2*)(base + (size_t)n * NB_MAX * sizeof(double2));
-  int* sigma = (int*)(base + (size_t)2 * n * NB_MAX * sizeof(double2));
+  double2* W = (double2*)(base + SL.off_W);
+  double2* U = (double2*)(base + SL.off_U);
+  double2* Wo = (double2*)(base + SL.off_Wo);
+  double2* Uo = (double2*)(base + SL.off_Uo);
+  int* sigma = (int*)(base + SL.off_sigma);
+  int* piv = (int*)(base + SL.off_piv);
   const int nthr = ((n + 63) / 64) * 64;
+  // two levels when the matrix is wider than one super-panel
+  const int outer = n > NBO ? NBO : n;
   hipError_t e = hipSuccess;
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int nbw = (n - j0 < NB) ? n - j0 : NB;
-    PanelArgs pa{n, j0, nbw, d.M, d.ldm, d.sM, W, sItem, U, sItem, sigma, sI, d.info, d.info_mod, d.active};
-    prof_begin(KC_INV_PANEL, s);
-    if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 512>), dim3(d.batch), dim3(nthr), 0, s, pa);
-    else if (n <= 512) hipLaunchKernelGGL((gj_panel_kernel<16, 512>), dim3(d.batch), dim3(nthr), 0, s, pa);
-    else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS>), dim3(d.batch), dim3(nthr), 0, s, pa);
-    prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
+  for (int J0 = 0; J0 < n; J0 += outer) {
+    const int mo = (n - J0 < outer) ? n - J0 : outer;
+    for (int j0 = J0; j0 < J0 + mo; j0 += NB) {
+      const int nbw = (J0 + mo - j0 < NB) ? J0 + mo - j0 : NB;
+      PanelArgs pa{n, j0, nbw, J0, J0 + mo, d.M, d.ldm, d.sM, W, sItem, U, sItem, sigma, sI, piv,
+                   d.info, d.info_mod, d.active};
+      prof_begin(KC_INV_PANEL, s);
+      if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 512>), dim3(d.batch), dim3(nthr), 0, s, pa);
+      else if (n <= 512) hipLaunchKernelGGL((gj_panel_kernel<16, 512>), dim3(d.batch), dim3(nthr), 0, s, pa);
+      else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS>), dim3(d.batch), dim3(nthr), 0, s, pa);
+      prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      // update of the super-panel columns: A[:, J] += W U[:, J]
+      GemmDesc g = update_desc(n, mo, nbw, W, NB, sItem, U + J0, n, sItem, d.M + J0, d.ldm, d.sM, d.batch, d.active);
+      if ((e = launch_gemm(g, s)) != hipSuccess) return e;
+    }
+    if (mo == n) break;   // one level: the super-panel was the whole matrix
+    // outer step: interchanges and pivot rows of the other columns, then A += Wo Uo
+    prof_begin(KC_INV_SWAP, s);
+    hipLaunchKernelGGL(gj_take_panel_kernel, dim3((unsigned)(((long)n * mo + 255) / 256), d.batch), dim3(256), 0, s,
+                       n, J0, mo, d.M, d.ldm, d.sM, Wo, sItem, d.active);
+    hipLaunchKernelGGL(gj_outer_swap_kernel, dim3((n + 255) / 256, d.batch), dim3(256), 0, s, n, J0, mo, d.M, d.ldm,
+                       d.sM, Uo, sItem, piv, sI, d.active);
+    prof_end(KC_INV_SWAP, s, 0, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    GemmDesc g{};
-    g.M = n; g.N = n; g.K = nbw; g.batch = d.batch;
-    g.opA = OP_N; g.opB = OP_N;
-    g.A = MatRef{W, NB, sItem};
-    g.B = MatRef{U, n, sItem};
-    g.alpha = make_double2(1.0, 0.0);
-    g.beta = make_double2(1.0, 0.0);
-    g.Cin = MatRef{d.M, d.ldm, d.sM};
-    g.C = MatOut{d.M, d.ldm, d.sM};
-    g.active = d.active;
-    g.prec = PREC_F64;
-    g.xcd_remap = 1;
-    g.tile = GEMM_TILE_64;
-    g.prof_class = KC_INV_GEMM;
+    GemmDesc g = update_desc(n, n, mo, Wo, mo, sItem, Uo, n, sItem, d.M, d.ldm, d.sM, d.batch, d.active);
     if ((e = launch_gemm(g, s)) != hipSuccess) return e;
   }
   prof_begin(KC_INV_PERM, s);
