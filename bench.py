@@ -66,10 +66,34 @@ def traffic_record():
     return rec.get("bytes_per_launch")
 
 
-def run_steps(nb, probs, batches, prec, steps, warmup, outputs, ws, opts, profile=False):
+def make_runner(nb, probs, prec, outputs, ws, opts, streams, points, sr_max_iter=40):
+    """One step of the hot path: the plain call, or a plan that splits the
+    batch over worker streams so that one half's latency-bound inversion
+    panels overlap the other half's products."""
     import torch
-    times = []
+    if streams <= 1:
+        def run():
+            return nb.rgf_lesser_greater(probs, prec, opts=opts, ws=ws, outputs=outputs, lower=True)["info"]
+        return run, None
+    from paper_2602_03438_amd import autotune
+    t = autotune.lookup(B)
+    per = max(1, points // streams)
+    plan = nb.Plan(probs, prec, opts=nb.make_options(sr_max_iter=sr_max_iter, inv_nb=opts.inv_nb),
+                   tunings=[(B, t["gemm_tile"], t["gemm_tile_f32"], opts.inv_nb or t["inv_nb"], per)],
+                   n_streams=streams)
+    info = torch.zeros(points, dtype=torch.int32, device="cuda")
+
+    def run():
+        plan.execute(outputs, info, use_graph=False)
+        return info
+    return run, plan
+
+
+def run_steps(nb, probs, batches, prec, steps, warmup, runner, profile=False):
+    import torch
     n_done = 0
+    info = None
+    failures = []
     for k in range(warmup + steps):
         if k == warmup:
             torch.cuda.synchronize()
@@ -77,9 +101,12 @@ def run_steps(nb, probs, batches, prec, steps, warmup, outputs, ws, opts, profil
                 nb.negf_profile_enable(1)
             t0 = time.perf_counter()
         probs[0].energies.copy_(torch.from_numpy(batches[k % len(batches)]).to("cuda"))
-        res = nb.rgf_lesser_greater(probs, prec, opts=opts, ws=ws, outputs=outputs, lower=True)
+        info = runner()
         if k >= warmup:
             n_done += probs[0].n_e
+            bad = info.cpu().numpy()
+            for q in np.nonzero(bad)[0]:
+                failures.append((float(batches[k % len(batches)][q]), int(bad[q])))
         torch.cuda.synchronize()
         log(f"  prec={prec} step {k + 1}/{warmup + steps} done")
     torch.cuda.synchronize()
@@ -88,7 +115,7 @@ def run_steps(nb, probs, batches, prec, steps, warmup, outputs, ws, opts, profil
     if profile:
         stats = nb.negf_profile_read()
         nb.negf_profile_enable(0)
-    return dt, n_done, res, stats
+    return dt, n_done, {"info": info, "failures": failures}, stats
 
 
 def cpu_baseline(dev, energies):
@@ -124,7 +151,10 @@ def main():
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation")
     ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload")
-    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="worker streams the batch is split over (1: the plain call on the current stream)")
+    ap.add_argument("--sr-max-iter", type=int, default=40,
+                    help="decimation steps a plan runs (it cannot poll convergence from the host)")
     ap.add_argument("--learned-energies", type=int, default=250, help="training energies per lead")
     ap.add_argument("--learned-eval", type=int, default=256, help="evaluation energies per held-out lead")
     ap.add_argument("--learned-b", type=int, default=512)
@@ -156,10 +186,11 @@ def main():
     outputs = nb._rgf_outputs(probs, True, False, True)
     torch.cuda.synchronize()
 
-    log("plain FP64 ...")
-    dt, n_pts, res, stats = run_steps(nb, probs, batches, nb.PLAIN_FP64, args.steps, args.warmup, outputs, ws, opts,
+    log(f"plain FP64, {args.streams} stream(s) ...")
+    runner, plan = make_runner(nb, probs, nb.PLAIN_FP64, outputs, ws, opts, args.streams, args.points,
+                               args.sr_max_iter)
+    dt, n_pts, res, stats = run_steps(nb, probs, batches, nb.PLAIN_FP64, args.steps, args.warmup, runner,
                                       profile=True)
-    info = res["info"].cpu().numpy()
     value = n_pts / dt
     g = stats["gemm_f64"]
     achieved = g["flops"] / (g["total_ms"] * 1e-3) if g["total_ms"] > 0 else 0.0
@@ -183,8 +214,11 @@ def main():
         out = {}
         for prec, name in ((nb.FP32_REFINE, "fp32_refine"), (nb.FP32_NOREFINE, "fp32_norefine")):
             log(f"{name} ...")
-            dtc, nc, resc, st = run_steps(nb, probs, batches, prec, args.steps, args.warmup, outputs, ws, opts,
-                                          profile=True)
+            runner_c, plan_c = make_runner(nb, probs, prec, outputs, ws, opts, args.streams, args.points,
+                                             args.sr_max_iter)
+            dtc, nc, resc, st = run_steps(nb, probs, batches, prec, args.steps, args.warmup, runner_c, profile=True)
+            if plan_c:
+                plan_c.close()
             eR = (torch.linalg.vector_norm(outputs["GR_diag"] - plain_GR) / torch.linalg.vector_norm(plain_GR)).item()
             eL = (torch.linalg.vector_norm(outputs["GL_diag"] - plain_GL) / torch.linalg.vector_norm(plain_GL)).item()
             ideal = st["gemm_f64"]["flops"] / PEAK["f64"] + st["gemm_f32"]["flops"] / PEAK["f32"]
@@ -218,8 +252,10 @@ def main():
                                "~14% dense blocks, S = I + PSD), Sancho-Rubio leads at eta=1e-8, "
                                "muL=0.1 muR=-0.1 kT=0.025, energies from 1024 in [-1.5,1.5]",
                    "points_per_step": args.points, "nb": NB, "b": B, "precision": "plain FP64",
+                   "streams": args.streams, "inversion_panel": args.inv_nb, "sr_max_iter": args.sr_max_iter,
                    "outputs": "G^R diag/upper/lower + G^< diag/upper in HBM"},
-        "info_nonzero": int(np.count_nonzero(info)),
+        "info_nonzero": len(res["failures"]),
+        "failures": res["failures"][:8],
         "roofline": roof,
         "kernels": kstats,
         "chosen_form": chosen,

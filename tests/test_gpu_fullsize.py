@@ -1,0 +1,105 @@
+"""GPU parity at the full benchmark size: Nb = 60 blocks of b = 512, 64 energy
+points split over two worker streams exactly as ``bench.py`` runs them.
+
+The oracle takes seconds per point at this size, so a sample of points (one
+from each stream's half of the batch) is compared element by element; every
+point of the batch is checked for properties that hold at any size: the
+decimation converged, G^<_ii is anti-Hermitian, and the local density of
+states -Im Tr G^R_ii / pi is non-negative.
+"""
+import numpy as np
+import pytest
+
+import workloads as w
+from helpers import point_tolerance, well_posed
+from oracle import rgf as orgf
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+NB, B, P, STREAMS = 60, 512, 64, 2
+ETA, MU_L, MU_R, KT = 1e-8, 0.1, -0.1, 0.025
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import bench
+    from paper_2602_03438_amd import binding as nb
+    nb.lib()
+    dev = w.slab_device(NB, B, 2)
+    energies = bench.energy_batches(P)[0]
+    prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT)
+    yield nb, bench, dev, energies, prob
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _sample(dev, energies):
+    """One well-posed point from each stream's half of the batch."""
+    half = len(energies) // STREAMS
+    picks = []
+    for s in range(STREAMS):
+        for k in range(s * half + half // 3, (s + 1) * half):
+            if well_posed(dev, energies[k:k + 1]).size:
+                picks.append(k)
+                break
+    assert len(picks) == STREAMS
+    return picks
+
+
+def _run(nb, bench, prob, prec):
+    import torch
+    outputs = nb._rgf_outputs([prob], True, False, True)
+    run, plan = bench.make_runner(nb, [prob], prec, outputs, None, nb.make_options(inv_nb=16), STREAMS, P)
+    info = run()
+    torch.cuda.synchronize()
+    plan.close()
+    return outputs, info.cpu().numpy()
+
+
+def _point(nb, outputs, prob, k, name):
+    return nb._views(outputs, [prob])[name][0][k].cpu().numpy()
+
+
+def _properties(nb, outputs, prob):
+    import torch
+    v = nb._views(outputs, [prob])
+    for k in range(prob.n_e):
+        gl = v["GL_diag"][0][k]
+        skew = torch.linalg.vector_norm(gl + gl.transpose(-1, -2).conj()) / torch.linalg.vector_norm(gl)
+        assert skew.item() < 1e-10, (k, skew.item())
+        ldos = -torch.diagonal(v["GR_diag"][0][k], dim1=-2, dim2=-1).imag.sum(-1)
+        scale = torch.diagonal(v["GR_diag"][0][k], dim1=-2, dim2=-1).abs().sum(-1)
+        assert torch.all(ldos >= -1e-10 * scale).item(), k
+
+
+def test_fullsize_plain_fp64_sampled_parity(setup):
+    nb, bench, dev, energies, prob = setup
+    outputs, info = _run(nb, bench, prob, nb.PLAIN_FP64)
+    assert np.all(info == 0), info
+    names = ["GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper"]
+    for k in _sample(dev, energies):
+        print(f"point {k}: E = {energies[k]:.6f}", flush=True)
+        ref, tol = point_tolerance(lambda: orgf.solve_point(dev, energies[k], ETA, MU_L, MU_R, KT), names)
+        for name in names:
+            g = _point(nb, outputs, prob, k, name)
+            r = getattr(ref, name)
+            err = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+            print(f"  {name}: {err:.3e} (tolerance {tol[name]:.1e})", flush=True)
+            assert err <= tol[name], (k, name, err, tol[name])
+    _properties(nb, outputs, prob)
+
+
+def test_fullsize_refined_form_sampled_parity(setup):
+    nb, bench, dev, energies, prob = setup
+    outputs, info = _run(nb, bench, prob, nb.FP32_REFINE)
+    assert np.all(info == 0), info
+    k = _sample(dev, energies)[-1]
+    ref = orgf.solve_point(dev, energies[k], ETA, MU_L, MU_R, KT)
+    for name in ("GR_diag", "GL_diag", "GL_upper"):
+        g = _point(nb, outputs, prob, k, name)
+        r = getattr(ref, name)
+        err = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+        print(f"point {k} {name}: {err:.3e}", flush=True)
+        assert err <= 1e-6, (k, name, err)
