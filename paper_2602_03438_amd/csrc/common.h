@@ -10,6 +10,9 @@ namespace negf {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+// Native two-double vector: arrays of it indexed by unrolled loop counters stay
+// in registers (arrays of HIP's double2 struct with conditional stores do not).
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 __host__ __device__ inline double2 cmk(double re, double im) { double2 r; r.x = re; r.y = im; return r; }
 __host__ __device__ inline double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }

@@ -4,17 +4,22 @@
 // Block step for the panel J = [j0, j0+nb) of the current matrix A:
 //   1. panel kernel (one workgroup per matrix, one thread per row, the n x nb
 //      panel in registers): nb unblocked Gauss-Jordan steps restricted to the
-//      panel -- pivot = argmax_{r >= j} |Re a_rj| + |Im a_rj|, row interchange,
-//      scale the pivot row, eliminate the column from every other row with the
+//      panel -- pivot = the row r >= j of largest |Re a_rj| + |Im a_rj| (compared
+//      to 2^-9 relative, ties to the smaller row), row interchange, scale the
+//      pivot row, eliminate the column from every other row with the
 //      multipliers stored in place.  The result W = [A_JJ^{-1}; -A_RJ A_JJ^{-1}]
 //      (rows in pivoted order) goes to scratch and the panel columns of A are
-//      cleared.  The same workgroup then applies the nb interchanges to the
-//      other columns, copies the pivot rows into U (nb x n, identity in the
-//      panel columns), clears those rows, and appends the interchanges to the
-//      row-order array sigma.
+//      cleared.  The same workgroup composes the nb interchanges into one row
+//      map, applies it to the other columns of the current super-panel, copies
+//      the pivot rows into U (nb x n, identity in the panel columns), clears
+//      those rows, and folds the map into the row orders sigma (whole matrix)
+//      and tau (since the start of the super-panel).
 //   2. product: A += W U on the matrix cores (one batched complex product,
 //      K = nb): pivot rows become A_JJ^{-1} A_JC, the other rows
 //      A_RC - A_RJ A_JJ^{-1} A_JC, and W lands in the panel columns.
+// Two levels: the panels run inside super-panels of NBO = 128 columns; the
+// columns outside a super-panel are brought up to date once per super-panel
+// (interchanges through tau, then one product with K = 128).
 // After the last panel A holds (P A)^{-1} with (P A)[i] = A[sigma[i]]; the
 // inverse A^{-1}[r][c] = (P A)^{-1}[r][sigma^{-1}[c]] is a column gather.
 // Arithmetic: 8 n^3 real flops per matrix, all but O(n^2 nb) of them in the
@@ -27,15 +32,16 @@ namespace {
 
 constexpr int MAX_ROWS = 1024;
 constexpr int NB_MAX = 32;
+constexpr int NBO = 128;   // outer block (super-panel width) of the two-level scheme
 
 struct PanelArgs {
   int n, j0, nbw;
-  int c0, c1;               // columns the interchanges and U cover (the current super-panel)
+  int c0, c1;               // the current super-panel: columns the interchanges and U cover
   double2* A; long lda, sA;
   double2* W; long sW;      // W_p: n x NB row-major
   double2* U; long sU;      // U_p: NB x n row-major (columns c0..c1 written)
-  int* sigma; long sS;      // sigma_p[i]: original row now at position i
-  int* piv;                 // piv_p[j]: row interchanged with row j (same stride as sigma)
+  int* sigma;               // sigma_p[i]: original row now at position i
+  int* tau; long sS;        // tau_p[i]: row, at the start of the super-panel, now at position i
   int* info; int info_mod;
   const int* active;
 };
@@ -43,75 +49,88 @@ struct PanelArgs {
 // Shared state of one panel workgroup.
 template <int NB>
 struct PanelLds {
-  double red_key[MAX_ROWS / 64];
-  int red_idx[MAX_ROWS / 64];
-  double2 srow[2][NB];
+  unsigned red[MAX_ROWS / 64] __attribute__((aligned(16)));
+  double2 srow[NB];
   double2 prow[NB];
   int spiv[NB];
+  int cont[MAX_ROWS];        // cont[i]: row, at the start of the panel, whose content is now at row i
+  double2 qstage[NB][NBO];   // new contents of the interchanged rows below the panel
 };
+
+// Maximum of an unsigned value over the 64 lanes of a wavefront: prefix maxima
+// inside each row of 16 lanes by DPP row shifts, then the row broadcasts carry
+// them to lane 63.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Pivot key of row r: the upper 21 bits of the magnitude |Re| + |Im| (a
+// non-negative double orders like its bit pattern; a NaN ranks above
+// everything so that it is taken and reported) and 2047 - r in the low 11
+// bits, so that the unsigned maximum picks the largest magnitude (to 2^-9
+// relative) and, among equal keys, the smallest row.
+__device__ __forceinline__ unsigned pivot_key(double2 v, int r) {
+  const double m = fabs(v.x) + fabs(v.y);
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(m) >> 32);
+  return ((m != m) ? 0xFFFFF800u : (hi & 0xFFFFF800u)) | (unsigned)(2047 - r);
+}
 
 // Gauss-Jordan step JJ of the panel.  JJ is a compile-time index so that the
 // panel row x[] stays in registers (a runtime index would move it to scratch).
+// Two barriers: after the pivot reduction, and after the pivot row (scaled by
+// its owner) and the displaced row j are published.
 template <int JJ, int NB>
-__device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, int r, int n, int j0, bool valid,
-                                           int nwaves, int& status) {
+__device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, int r, int j0, bool valid,
+                                           int& status) {
   const int lane = r & 63, wave = r >> 6;
   const int j = j0 + JJ;
-  // --- pivot search over rows r >= j (ties -> smallest row index)
-  double key = (valid && r >= j) ? fabs(x[JJ].x) + fabs(x[JJ].y) : -1.0;
-  if (key != key) key = 1e308;  // a NaN candidate is taken and reported below
-  int idx = r;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double k2 = __shfl_xor(key, off);
-    const int i2 = __shfl_xor(idx, off);
-    if (k2 > key || (k2 == key && i2 < idx)) { key = k2; idx = i2; }
-  }
-  if (lane == 0) { L.red_key[wave] = key; L.red_idx[wave] = idx; }
+  unsigned key = (valid && r >= j) ? pivot_key(x[JJ], r) : 0u;
+  key = wave_max_u32(key);
+  if (lane == 0) L.red[wave] = key;
   __syncthreads();
-  key = L.red_key[0];
-  idx = L.red_idx[0];
-  for (int w = 1; w < nwaves; ++w) {
-    const double k2 = L.red_key[w];
-    const int i2 = L.red_idx[w];
-    if (k2 > key || (k2 == key && i2 < idx)) { key = k2; idx = i2; }
-  }
-  const int pr = idx;
-  // --- interchange rows j and pr of the panel
-  if (pr != j) {
-    if (r == j) {
+  {
+    const uint4* rv = reinterpret_cast<const uint4*>(L.red);
 #pragma unroll
-      for (int c = 0; c < NB; ++c) L.srow[0][c] = x[c];
-    }
-    if (r == pr) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) L.srow[1][c] = x[c];
-    }
-    __syncthreads();
-    if (r == j) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) x[c] = L.srow[1][c];
-    }
-    if (r == pr) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) x[c] = L.srow[0][c];
+    for (int q = 0; q < MAX_ROWS / 256; ++q) {
+      const uint4 t = rv[q];
+      key = max(max(key, t.x), max(t.y, max(t.z, t.w)));
     }
   }
-  // --- scale the pivot row and publish it
-  if (r == j) {
+  const int pr = 2047 - (int)(key & 0x7FFu);
+  if (r == pr) {
     const double2 d = x[JJ];
     if (d.x == 0.0 && d.y == 0.0) status = ST_ESINGULAR;
     const double2 dinv = cinv(d);
     if (!(isfinite(dinv.x) && isfinite(dinv.y))) status = status == ST_OK ? ST_ENONFINITE : status;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) x[c] = (c == JJ) ? dinv : cmul(x[c], dinv);
+    for (int c = 0; c < NB; ++c) L.prow[c] = (c == JJ) ? dinv : cmul(x[c], dinv);
+  }
+  if (r == j) {
+    if (pr != j) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) L.prow[c] = x[c];
+      for (int c = 0; c < NB; ++c) L.srow[c] = x[c];
+      const int t = L.cont[j];
+      L.cont[j] = L.cont[pr];
+      L.cont[pr] = t;
+    }
     L.spiv[JJ] = pr;
   }
   __syncthreads();
-  // --- eliminate column JJ from every other row (multiplier stored in place)
-  if (valid && r != j) {
+  if (r == j) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[c] = L.prow[c];
+  } else if (valid) {
+    if (r == pr) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) x[c] = L.srow[c];
+    }
+    // eliminate column JJ (multiplier stored in place: x[JJ] becomes -f / pivot)
     const double2 f = x[JJ];
     x[JJ] = make_double2(0.0, 0.0);
 #pragma unroll
@@ -127,17 +146,17 @@ __device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, in
 
 template <int JJ, int NB>
 struct PanelSteps {
-  __device__ __forceinline__ static void run(double2 (&x)[NB], PanelLds<NB>& L, int r, int n, int j0, int nbw,
-                                             bool valid, int nwaves, int& status) {
+  __device__ __forceinline__ static void run(double2 (&x)[NB], PanelLds<NB>& L, int r, int j0, int nbw, bool valid,
+                                             int& status) {
     if (JJ < nbw) {
-      panel_step<JJ, NB>(x, L, r, n, j0, valid, nwaves, status);
-      PanelSteps<JJ + 1, NB>::run(x, L, r, n, j0, nbw, valid, nwaves, status);
+      panel_step<JJ, NB>(x, L, r, j0, valid, status);
+      PanelSteps<JJ + 1, NB>::run(x, L, r, j0, nbw, valid, status);
     }
   }
 };
 template <int NB>
 struct PanelSteps<NB, NB> {
-  __device__ __forceinline__ static void run(double2 (&)[NB], PanelLds<NB>&, int, int, int, int, bool, int, int&) {}
+  __device__ __forceinline__ static void run(double2 (&)[NB], PanelLds<NB>&, int, int, int, bool, int&) {}
 };
 
 template <int NB, int MAXT>
@@ -148,11 +167,15 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
   double2* __restrict__ W = a.W + (long)p * a.sW;
   double2* __restrict__ U = a.U + (long)p * a.sU;
   int* __restrict__ sigma = a.sigma + (long)p * a.sS;
+  int* __restrict__ tau = a.tau + (long)p * a.sS;
   const int r = threadIdx.x;
+  const int nt = blockDim.x;
   const int n = a.n, j0 = a.j0, nbw = a.nbw;
+  const int jend = j0 + nbw;
   const bool valid = r < n;
-  const int nwaves = (blockDim.x + 63) >> 6;
   __shared__ PanelLds<NB> L;
+  if (r < MAX_ROWS / 64) L.red[r] = 0u;   // waves beyond the last never write their slot
+  for (int i = r; i < n; i += nt) L.cont[i] = i;
 
   double2 x[NB];
 #pragma unroll
@@ -160,7 +183,7 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
     x[c] = (valid && c < nbw) ? A[(long)r * a.lda + j0 + c] : make_double2(0.0, 0.0);
 
   int status = ST_OK;
-  PanelSteps<0, NB>::run(x, L, r, n, j0, nbw, valid, nwaves, status);
+  PanelSteps<0, NB>::run(x, L, r, j0, nbw, valid, status);
 
   if (valid) {
 #pragma unroll
@@ -170,38 +193,79 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
       if (c < nbw) A[(long)r * a.lda + j0 + c] = make_double2(0.0, 0.0);
   }
   __syncthreads();
-  // --- interchanges on the other columns of [c0, c1), pivot rows into U (identity in the panel columns)
-  for (int c = a.c0 + r; c < a.c1; c += blockDim.x) {
-    if (c >= j0 && c < j0 + nbw) {
-      for (int k = 0; k < nbw; ++k) U[(long)k * n + c] = make_double2(k == c - j0 ? 1.0 : 0.0, 0.0);
-      continue;
+
+  // The nbw interchanges, composed into cont[], act on the rows D = panel rows
+  // and the rows below the panel they touched.  Every new row of D is an old
+  // row of D, so all reads go first (pivot rows into U, moved rows into LDS),
+  // then, after a barrier, the writes.
+  const int c0 = a.c0, cnt = a.c1 - a.c0;
+  const int tot = nbw * cnt;
+  const v2d* __restrict__ Av = reinterpret_cast<const v2d*>(A);
+  constexpr int G = 8;
+  for (int base = 0; base < tot; base += G * nt) {
+    v2d v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int e = base + g * nt + r;
+      const int s = e / cnt, c = c0 + e % cnt;
+      const bool outside = c < j0 || c >= jend;
+      v[g] = (e < tot && outside) ? Av[(long)L.cont[j0 + s] * a.lda + c]
+                                  : v2d{(e < tot && c - j0 == s) ? 1.0 : 0.0, 0.0};
     }
-    for (int k = 0; k < nbw; ++k) {
-      const int jr = j0 + k, q = L.spiv[k];
-      if (q != jr) {
-        const double2 t0 = A[(long)jr * a.lda + c];
-        A[(long)jr * a.lda + c] = A[(long)q * a.lda + c];
-        A[(long)q * a.lda + c] = t0;
-      }
-    }
-    for (int k = 0; k < nbw; ++k) {
-      const long o = (long)(j0 + k) * a.lda + c;
-      U[(long)k * n + c] = A[o];
-      A[o] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int e = base + g * nt + r;
+      if (e < tot) reinterpret_cast<v2d*>(U)[(long)(e / cnt) * n + c0 + e % cnt] = v[g];
     }
   }
-  // --- row order: sigma starts as the identity and takes the interchanges in order
-  if (j0 == 0)
-    for (int i = r; i < n; i += blockDim.x) sigma[i] = i;
-  __syncthreads();
-  if (r == 0)
-    for (int k = 0; k < nbw; ++k) {
-      const int jr = j0 + k, q = L.spiv[k];
-      const int t = sigma[jr];
-      sigma[jr] = sigma[q];
-      sigma[q] = t;
+  for (int base = 0; base < tot; base += G * nt) {
+    v2d v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int e = base + g * nt + r;
+      const int s = e / cnt, c = c0 + e % cnt, q = e < tot ? L.spiv[s] : 0;
+      const bool take = e < tot && q >= jend && (c < j0 || c >= jend);
+      v[g] = take ? Av[(long)L.cont[q] * a.lda + c] : v2d{0.0, 0.0};
     }
-  if (r < nbw) a.piv[(long)p * a.sS + j0 + r] = L.spiv[r];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int e = base + g * nt + r;
+      const int s = e / cnt, c = c0 + e % cnt, q = e < tot ? L.spiv[s] : 0;
+      if (e < tot && q >= jend && (c < j0 || c >= jend)) {
+        L.qstage[s][c - c0].x = v[g].x;
+        L.qstage[s][c - c0].y = v[g].y;
+      }
+    }
+  }
+  // row orders: new entry of a row d of D = old entry of row cont[d]
+  int d = -1, sv = 0, tv = 0;
+  if (r < 2 * nbw) {
+    d = r < nbw ? j0 + r : L.spiv[r - nbw];
+    if (r >= nbw && d < jend) d = -1;
+    if (d >= 0) {
+      const int src = L.cont[d];
+      sv = j0 == 0 ? src : sigma[src];
+      tv = j0 == c0 ? src : tau[src];
+    }
+  }
+  __syncthreads();
+  for (int e = r; e < tot; e += nt) {
+    const int s = e / cnt, c = c0 + e % cnt;
+    if (c >= j0 && c < jend) continue;
+    A[(long)(j0 + s) * a.lda + c] = make_double2(0.0, 0.0);
+    const int q = L.spiv[s];
+    if (q >= jend) A[(long)q * a.lda + c] = L.qstage[s][c - c0];
+  }
+  if (j0 == 0) {
+    for (int i = r; i < n; i += nt) sigma[i] = L.cont[i];
+  } else if (d >= 0) {
+    sigma[d] = sv;
+  }
+  if (j0 == c0) {
+    for (int i = r; i < n; i += nt) tau[i] = L.cont[i];
+  } else if (d >= 0) {
+    tau[d] = tv;
+  }
   if (status != ST_OK && a.info) atomicCAS(a.info + (a.info_mod > 0 ? p % a.info_mod : p), ST_OK, status);
 }
 
@@ -226,57 +290,92 @@ __global__ void __launch_bounds__(256) gj_gather_kernel(int n, const double2* M,
   }
 }
 
-// Outer step of the two-level blocking, for the super-panel J = [J0, J0+mo):
-// the mo interchanges recorded by the inner panels are applied to the columns
-// outside J, the pivot rows of those columns move into Uo (mo x n, identity in
-// the columns of J) and are cleared.  One thread per column.
-__global__ void __launch_bounds__(256) gj_outer_swap_kernel(int n, int J0, int mo, double2* A, long lda, long sA,
-                                                            double2* Uo, long sU, const int* piv, long sP,
-                                                            const int* active) {
+// Outer step of the two-level blocking for the super-panel J = [J0, J0+mo),
+// one workgroup per (matrix, OUTER_COLS columns).  Blocks inside J move their
+// columns into Wo (n x mo) and clear them, and write the identity into Uo.
+// Blocks outside J apply the super-panel's interchanges (the content map tau)
+// to their columns: the pivot rows J0..J0+mo-1 go to Uo (mo x n) and are
+// cleared, the rows below J that took part receive their new contents.  All
+// reads of a block precede its writes (a barrier between).
+constexpr int OUTER_COLS = 16;
+constexpr int OUTER_THREADS = 256;
+
+__global__ void __launch_bounds__(OUTER_THREADS) gj_outer_kernel(int n, int J0, int mo, double2* A, long lda,
+                                                                 long sA, double2* Wo, long sW, double2* Uo,
+                                                                 long sU, const int* tau, long sT,
+                                                                 const int* active) {
   const int p = blockIdx.y;
   if (active && active[p] == 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  double2* Ap = A + (long)p * sA;
-  double2* U = Uo + (long)p * sU;
-  const int* pv = piv + (long)p * sP;
-  if (c >= J0 && c < J0 + mo) {
-    for (int k = 0; k < mo; ++k) U[(long)k * n + c] = make_double2(k == c - J0 ? 1.0 : 0.0, 0.0);
+  double2* __restrict__ Ap = A + (long)p * sA;
+  double2* __restrict__ U = Uo + (long)p * sU;
+  const int cb = blockIdx.x * OUTER_COLS;
+  const int w = min(OUTER_COLS, n - cb);
+  const int t = threadIdx.x;
+  if (cb >= J0 && cb < J0 + mo) {
+    double2* __restrict__ Wp = Wo + (long)p * sW;
+    for (int e = t; e < n * OUTER_COLS; e += OUTER_THREADS) {
+      const int rr = e / OUTER_COLS, cc = e % OUTER_COLS;
+      if (cc >= w) continue;
+      const long o = (long)rr * lda + cb + cc;
+      Wp[(long)rr * mo + (cb - J0 + cc)] = Ap[o];
+      Ap[o] = make_double2(0.0, 0.0);
+    }
+    for (int e = t; e < mo * OUTER_COLS; e += OUTER_THREADS) {
+      const int k = e / OUTER_COLS, cc = e % OUTER_COLS;
+      if (cc < w) U[(long)k * n + cb + cc] = make_double2(k == cb - J0 + cc ? 1.0 : 0.0, 0.0);
+    }
     return;
   }
-  for (int k = 0; k < mo; ++k) {
-    const int jr = J0 + k, q = pv[jr];
-    if (q != jr) {
-      const double2 t0 = Ap[(long)jr * lda + c];
-      Ap[(long)jr * lda + c] = Ap[(long)q * lda + c];
-      Ap[(long)q * lda + c] = t0;
+  __shared__ int rows[2 * NBO];
+  __shared__ int srcs[2 * NBO];
+  __shared__ int nq;
+  const int* tp = tau + (long)p * sT;
+  if (t == 0) nq = 0;
+  __syncthreads();
+  for (int i = t; i < mo; i += OUTER_THREADS) {
+    rows[i] = J0 + i;
+    srcs[i] = tp[J0 + i];
+  }
+  // rows below J whose content changed (at most mo of them)
+  for (int i = J0 + mo + t; i < n; i += OUTER_THREADS) {
+    const int s = tp[i];
+    if (s != i) {
+      const int k = atomicAdd(&nq, 1);
+      if (mo + k < 2 * NBO) {
+        rows[mo + k] = i;
+        srcs[mo + k] = s;
+      }
     }
   }
-  for (int k = 0; k < mo; ++k) {
-    const long o = (long)(J0 + k) * lda + c;
-    U[(long)k * n + c] = Ap[o];
-    Ap[o] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const int tot = min(mo + nq, 2 * NBO) * OUTER_COLS;
+  constexpr int G = 2 * NBO * OUTER_COLS / OUTER_THREADS;
+  const v2d* __restrict__ Av = reinterpret_cast<const v2d*>(Ap);
+  v2d v[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int e = g * OUTER_THREADS + t, k = e / OUTER_COLS, cc = e % OUTER_COLS;
+    v[g] = (e < tot && cc < w) ? Av[(long)srcs[k] * lda + cb + cc] : v2d{0.0, 0.0};
+  }
+  __syncthreads();
+  v2d* __restrict__ Aw = reinterpret_cast<v2d*>(Ap);
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int e = g * OUTER_THREADS + t, k = e / OUTER_COLS, cc = e % OUTER_COLS;
+    if (e < tot && cc < w) {
+      if (k < mo) {
+        reinterpret_cast<v2d*>(U)[(long)k * n + cb + cc] = v[g];
+        Aw[(long)(J0 + k) * lda + cb + cc] = v2d{0.0, 0.0};
+      } else {
+        Aw[(long)rows[k] * lda + cb + cc] = v[g];
+      }
+    }
   }
 }
-
-// Wo (n x mo) <- columns [J0, J0+mo) of A, which are then cleared.
-__global__ void __launch_bounds__(256) gj_take_panel_kernel(int n, int J0, int mo, double2* A, long lda, long sA,
-                                                            double2* Wo, long sW, const int* active) {
-  const int p = blockIdx.y;
-  if (active && active[p] == 0) return;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)n * mo) return;
-  const int r = (int)(e / mo), c = (int)(e % mo);
-  double2* Ap = A + (long)p * sA;
-  Wo[(long)p * sW + e] = Ap[(long)r * lda + J0 + c];
-  Ap[(long)r * lda + J0 + c] = make_double2(0.0, 0.0);
-}
-
-constexpr int NBO = 128;   // outer block of the two-level scheme
 
 struct ScratchLayout {
   size_t per_al;
-  size_t off_W, off_U, off_Wo, off_Uo, off_sigma, off_piv;
+  size_t off_W, off_U, off_Wo, off_Uo, off_sigma, off_tau;
 };
 
 ScratchLayout layout(int n) {
@@ -287,7 +386,7 @@ ScratchLayout layout(int n) {
   L.off_Wo = o; o += (size_t)n * NBO * sizeof(double2);
   L.off_Uo = o; o += (size_t)NBO * n * sizeof(double2);
   L.off_sigma = o; o += (size_t)n * sizeof(int);
-  L.off_piv = o;   o += (size_t)n * sizeof(int);
+  L.off_tau = o;   o += (size_t)n * sizeof(int);
   L.per_al = (o + 255) & ~(size_t)255;
   return L;
 }
@@ -329,7 +428,7 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
   double2* Wo = (double2*)(base + SL.off_Wo);
   double2* Uo = (double2*)(base + SL.off_Uo);
   int* sigma = (int*)(base + SL.off_sigma);
-  int* piv = (int*)(base + SL.off_piv);
+  int* tau = (int*)(base + SL.off_tau);
   const int nthr = ((n + 63) / 64) * 64;
   // two levels when the matrix is wider than one super-panel
   const int outer = n > NBO ? NBO : n;
@@ -338,7 +437,7 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
     const int mo = (n - J0 < outer) ? n - J0 : outer;
     for (int j0 = J0; j0 < J0 + mo; j0 += NB) {
       const int nbw = (J0 + mo - j0 < NB) ? J0 + mo - j0 : NB;
-      PanelArgs pa{n, j0, nbw, J0, J0 + mo, d.M, d.ldm, d.sM, W, sItem, U, sItem, sigma, sI, piv,
+      PanelArgs pa{n, j0, nbw, J0, J0 + mo, d.M, d.ldm, d.sM, W, sItem, U, sItem, sigma, tau, sI,
                    d.info, d.info_mod, d.active};
       prof_begin(KC_INV_PANEL, s);
       if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 512>), dim3(d.batch), dim3(nthr), 0, s, pa);
@@ -353,10 +452,8 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
     if (mo == n) break;   // one level: the super-panel was the whole matrix
     // outer step: interchanges and pivot rows of the other columns, then A += Wo Uo
     prof_begin(KC_INV_SWAP, s);
-    hipLaunchKernelGGL(gj_take_panel_kernel, dim3((unsigned)(((long)n * mo + 255) / 256), d.batch), dim3(256), 0, s,
-                       n, J0, mo, d.M, d.ldm, d.sM, Wo, sItem, d.active);
-    hipLaunchKernelGGL(gj_outer_swap_kernel, dim3((n + 255) / 256, d.batch), dim3(256), 0, s, n, J0, mo, d.M, d.ldm,
-                       d.sM, Uo, sItem, piv, sI, d.active);
+    hipLaunchKernelGGL(gj_outer_kernel, dim3((n + OUTER_COLS - 1) / OUTER_COLS, d.batch), dim3(OUTER_THREADS), 0, s,
+                       n, J0, mo, d.M, d.ldm, d.sM, Wo, sItem, Uo, sItem, tau, sI, d.active);
     prof_end(KC_INV_SWAP, s, 0, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     GemmDesc g = update_desc(n, n, mo, Wo, mo, sItem, Uo, n, sItem, d.M, d.ldm, d.sM, d.batch, d.active);

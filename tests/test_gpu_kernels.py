@@ -81,7 +81,7 @@ def test_zgemm_fp32_products(nb):
     assert 1e-9 < err < 1e-5, err
 
 
-@pytest.mark.parametrize("n", [1, 5, 8, 16, 33, 100, 130, 512])
+@pytest.mark.parametrize("n", [1, 5, 8, 16, 33, 100, 130, 300, 512, 700])
 @pytest.mark.parametrize("panel", [16, 32])
 def test_zinv_parity(nb, n, panel):
     import torch
@@ -105,6 +105,27 @@ def test_zinv_pivoting_needed(nb):
     M = np.array([[0, 1, 2], [3, 0, 1], [1, 1, 0]], dtype=np.complex128)[None]
     out, info = nb.zinv(torch.from_numpy(M).cuda(), 16)
     assert np.allclose(out.cpu().numpy()[0], np.linalg.inv(M[0]), atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [64, 200, 512])
+def test_zinv_scaled_permutation(nb, n):
+    """One non-zero per row and column, anywhere in the matrix: every pivot has
+    to be the single non-zero of its column among all remaining rows (any other
+    choice is a zero pivot), so this checks the pivot search across every
+    wavefront of the workgroup, and the interchanges across super-panels."""
+    import torch
+    r = np.random.Generator(np.random.PCG64(n))
+    perm = r.permutation(n)
+    vals = np.exp(r.uniform(-5, 5, (2, n))) * np.exp(2j * np.pi * r.uniform(size=(2, n)))
+    M = np.zeros((2, n, n), dtype=np.complex128)
+    M[0, np.arange(n), perm] = vals[0]
+    M[1, perm, np.arange(n)] = vals[1]
+    out, info = nb.zinv(torch.from_numpy(M).cuda(), 16)
+    assert np.all(info.cpu().numpy() == 0)
+    got = out.cpu().numpy()
+    for k in range(2):
+        ref = np.linalg.inv(M[k])
+        assert np.linalg.norm(got[k] - ref) / np.linalg.norm(ref) < 1e-14
 
 
 def test_zinv_reports_singular_and_nonfinite(nb):
