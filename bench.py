@@ -158,6 +158,9 @@ def main():
     ap.add_argument("--learned-energies", type=int, default=250, help="training energies per lead")
     ap.add_argument("--learned-eval", type=int, default=256, help="evaluation energies per held-out lead")
     ap.add_argument("--learned-b", type=int, default=512)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the run, copy one buffer of this many MiB (a plain copy kernel of known size, "
+                         "the reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU's share of the energy grid; --gpus {args.gpus} is not supported "
@@ -171,6 +174,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     nb.lib()
+    if args.calibrate_copy > 0:
+        # one streaming elementwise kernel: reads and writes exactly N bytes each
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calibrate_copy} MiB done")
+        del src, dst
     if args.workload == "uneven":
         return bench_uneven(args)
     if args.workload == "learned":

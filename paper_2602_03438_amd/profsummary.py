@@ -1,12 +1,28 @@
-"""Summarise a rocprofv3 kernel-trace database (``*_results.db``) as a short
-text table: per kernel symbol (and grid size) the number of dispatches, total
-and average duration.
+"""Summaries of rocprofv3 output.
+
+Kernel trace (``*_results.db``): per kernel symbol (and grid size) the number
+of dispatches, total and average duration.
 
     python -m paper_2602_03438_amd.profsummary gpurun_out/prof/run_results.db [--by-grid] [--top 20]
+
+HBM traffic from two counter runs (``--pmc FETCH_SIZE`` and ``--pmc
+WRITE_SIZE``, csv output) of a program that also ran one streaming kernel of
+known size (``bench.py --calibrate-copy MIB``): both counters are scaled by
+what they read for that kernel, then averaged per launch of the kernels
+matching a pattern.
+
+    python -m paper_2602_03438_amd.profsummary --traffic FETCH_DIR WRITE_DIR --calib-mib 1024 \\
+        [--kernel REGEX] [--json out.json]
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
 import sqlite3
 import sys
 
@@ -34,11 +50,80 @@ def summarize(db: str, by_grid: bool = False, top: int = 25):
         "\n".join(out)
 
 
+def _counter_rows(d: str):
+    """(dispatch id, kernel name, counter name, value) from a csv counter run."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no *counter_collection.csv under {d}")
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                row = {k.lower(): v for k, v in row.items()}
+                yield (int(row["dispatch_id"]), row["kernel_name"], row["counter_name"],
+                       float(row["counter_value"]))
+
+
+def per_dispatch(d: str, counter: str):
+    """{dispatch id: (kernel name, value summed over the counter's instances)}"""
+    acc = {}
+    for did, name, cname, val in _counter_rows(d):
+        if cname != counter:
+            continue
+        n0, v0 = acc.get(did, (name, 0.0))
+        acc[did] = (n0, v0 + val)
+    return acc
+
+
+def gemm_source_hash(root: str) -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(root, "paper_2602_03438_amd", "csrc", "gemm.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic(fetch_dir: str, write_dir: str, calib_mib: int, kernel: str, calib_kernel: str = "elementwise"):
+    fetch = per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = per_dispatch(write_dir, "WRITE_SIZE")
+    nbytes = calib_mib << 20
+
+    def calib(table):
+        cands = [v for (n, v) in table.values() if calib_kernel in n]
+        if not cands:
+            raise RuntimeError(f"no dispatch of a kernel matching '{calib_kernel}'")
+        return max(cands) * 1024.0      # the largest one is the calibration copy; counters are in KiB
+
+    f_cal, w_cal = calib(fetch), calib(write)
+    f_scale, w_scale = nbytes / f_cal, nbytes / w_cal
+    pat = re.compile(kernel)
+    fk = [v * 1024.0 * f_scale for (n, v) in fetch.values() if pat.search(n)]
+    wk = [v * 1024.0 * w_scale for (n, v) in write.values() if pat.search(n)]
+    if not fk or not wk:
+        raise RuntimeError(f"no dispatch matching '{kernel}'")
+    return {"kernel_pattern": kernel, "launches_fetch": len(fk), "launches_write": len(wk),
+            "fetch_bytes_per_launch": sum(fk) / len(fk), "write_bytes_per_launch": sum(wk) / len(wk),
+            "bytes_per_launch": sum(fk) / len(fk) + sum(wk) / len(wk),
+            "calibration": {"bytes": nbytes, "fetch_counter_bytes": f_cal, "write_counter_bytes": w_cal,
+                            "fetch_scale": f_scale, "write_scale": w_scale}}
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("db")
+    ap.add_argument("db", nargs="?")
     ap.add_argument("--by-grid", action="store_true")
     ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--calib-mib", type=int, default=1024)
+    ap.add_argument("--kernel", default=r"zgemm_kernel<double, [01], [01], [^>]*Cfg<\d+, \d+, \d, \d>, 0>")
+    ap.add_argument("--json")
     a = ap.parse_args()
-    print(summarize(a.db, a.by_grid, a.top))
+    if a.traffic:
+        rec = traffic(a.traffic[0], a.traffic[1], a.calib_mib, a.kernel)
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        rec["kernel_sha"] = gemm_source_hash(root)
+        print(json.dumps(rec, indent=1))
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(rec, f, indent=1)
+    else:
+        print(summarize(a.db, a.by_grid, a.top))
     sys.exit(0)
