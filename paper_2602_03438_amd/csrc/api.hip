@@ -125,7 +125,7 @@ struct Blocks {   // a batch of b x b blocks, item p at p * stride
 
 struct LeadWs {   // per (point, lead) pair scratch of the decimation
   Blocks d, alpha, beta, eps_s, eps, a, c, g, ag, cg, t1, t2;
-  double *a2, *c2, *d2, *r2, *m2, *g2;
+  double *a2, *c2, *d2, *r2, *m2, *g2, *part;
   int *active, *iters, *n_active, *accepted;
   void* inv_scratch;
 };
@@ -152,6 +152,7 @@ LeadWs carve_leads(Carver& cv, int b, int npairs) {
   for (Blocks* x : all) *x = take_blocks(cv, b, npairs);
   w.a2 = cv.take<double>(npairs); w.c2 = cv.take<double>(npairs); w.d2 = cv.take<double>(npairs);
   w.r2 = cv.take<double>(npairs); w.m2 = cv.take<double>(npairs); w.g2 = cv.take<double>(npairs);
+  w.part = cv.take<double>((size_t)npairs * FROB_SPLIT);
   w.active = cv.take<int>(npairs); w.iters = cv.take<int>(npairs); w.n_active = cv.take<int>(1);
   w.accepted = cv.take<int>(npairs);
   w.inv_scratch = cv.take<char>(inverse_scratch_bytes(b, npairs));
@@ -360,7 +361,7 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
   cx.chk(launch_fill_int(np, w.active, 1, s));
   cx.chk(launch_fill_int(np, w.iters, 0, s));
   cx.chk(launch_fill_int(np, w.accepted, 0, s));
-  cx.chk(launch_frob2(b, np, w.d.p, bb, 0.0, w.d2, s));
+  cx.chk(launch_frob2(b, np, w.d.p, bb, 0.0, nullptr, w.part, w.d2, s));
 
   // --- optional seed g~: candidate g0 = (d - alpha g~ beta)^{-1} (kept in w.g), accepted
   // when its normalised Dyson residual is <= accept; accepted pairs skip the decimation.
@@ -373,9 +374,9 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.alpha.p, bb, w.g.p, bb, ZERO, nullptr, 0, w.t1.p, bb);
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.t1.p, bb, w.beta.p, bb, ONE, w.d.p, bb, w.t2.p, bb);
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.t2.p, bb, w.g.p, bb, ZERO, nullptr, 0, w.t1.p, bb);
-    cx.chk(launch_frob2(b, np, w.t1.p, bb, 1.0, w.r2, s));
-    cx.chk(launch_frob2(b, np, w.t2.p, bb, 0.0, w.m2, s));
-    cx.chk(launch_frob2(b, np, w.g.p, bb, 0.0, w.g2, s));
+    cx.chk(launch_frob2(b, np, w.t1.p, bb, 1.0, nullptr, w.part, w.r2, s));
+    cx.chk(launch_frob2(b, np, w.t2.p, bb, 0.0, nullptr, w.part, w.m2, s));
+    cx.chk(launch_frob2(b, np, w.g.p, bb, 0.0, nullptr, w.part, w.g2, s));
     // w.accepted[q] stays 0 (= accepted) unless the residual test fails
     cx.chk(launch_sr_finish(np, w.r2, w.m2, w.g2, nullptr, cx.o.accept, nullptr, w.accepted, 0, s));
     cx.chk(launch_seed_flags(np, w.accepted, w.active, w.iters, s));
@@ -412,8 +413,8 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
       c = w.cg;
       w.cg = tmp;
     }
-    cx.chk(launch_frob2(b, np, a.p, bb, 0.0, w.a2, s));
-    cx.chk(launch_frob2(b, np, c.p, bb, 0.0, w.c2, s));
+    cx.chk(launch_frob2(b, np, a.p, bb, 0.0, w.active, w.part, w.a2, s));
+    cx.chk(launch_frob2(b, np, c.p, bb, 0.0, w.active, w.part, w.c2, s));
     cx.chk(launch_sr_check(np, w.a2, w.c2, w.d2, cx.o.tol, it, w.active, w.iters, w.n_active, s));
     hmax = it;
     if (!cx.fixed_sr) {
@@ -440,9 +441,9 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
     cx.lincomb(b, npts, ONE, w.d.at(si * npts), bb, MONE, dst.p, dst.stride, ZERO, t2.at(si * npts), bb);
   }
   cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, t2.p, bb, w.g.p, bb, ZERO, nullptr, 0, t1.p, bb);
-  cx.chk(launch_frob2(b, np, t1.p, bb, 1.0, w.r2, s));
-  cx.chk(launch_frob2(b, np, t2.p, bb, 0.0, w.m2, s));
-  cx.chk(launch_frob2(b, np, w.g.p, bb, 0.0, w.g2, s));
+  cx.chk(launch_frob2(b, np, t1.p, bb, 1.0, nullptr, w.part, w.r2, s));
+  cx.chk(launch_frob2(b, np, t2.p, bb, 0.0, nullptr, w.part, w.m2, s));
+  cx.chk(launch_frob2(b, np, w.g.p, bb, 0.0, nullptr, w.part, w.g2, s));
   if (info_pts) cx.chk(launch_sr_finish(np, w.r2, w.m2, w.g2, w.active, cx.o.accept, resid_out, info_pts, npts, s));
   if (iters_out) cx.chk(rt_copy_d2d(iters_out, w.iters, sizeof(int) * np, s));
   if (info_pts) cx.chk(launch_check_finite(b, np, w.g.p, bb, info_pts, npts, s));

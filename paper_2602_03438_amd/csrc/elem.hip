@@ -103,18 +103,35 @@ __device__ double block_sum(double v) {
 
 constexpr int RED_NT = 512;
 
-__global__ void __launch_bounds__(RED_NT) frob2_kernel(int b, const double2* X, long sX, double shift, double* out) {
-  const int p = blockIdx.x;
+// Squared Frobenius norm of X_p - shift*I in FROB_SPLIT slices per item (one
+// workgroup each), then a fixed-order sum of the slices: the result does not
+// depend on scheduling.
+__global__ void __launch_bounds__(RED_NT) frob2_part_kernel(int b, const double2* X, long sX, double shift,
+                                                            const int* active, double* part) {
+  const int p = blockIdx.y, q = blockIdx.x;
+  if (active && active[p] == 0) return;
   const double2* x = X + (long)p * sX;
   const long n = (long)b * b;
+  const long per = (n + FROB_SPLIT - 1) / FROB_SPLIT;
+  const long lo = (long)q * per, hi = lo + per < n ? lo + per : n;
   double s = 0.0;
-  for (long i = threadIdx.x; i < n; i += RED_NT) {
+  for (long i = lo + threadIdx.x; i < hi; i += RED_NT) {
     double2 v = x[i];
     if (shift != 0.0 && (i / b) == (i % b)) v.x -= shift;
     s += v.x * v.x + v.y * v.y;
   }
   s = block_sum<RED_NT>(s);
-  if (threadIdx.x == 0) out[p] = s;
+  if (threadIdx.x == 0) part[(long)p * FROB_SPLIT + q] = s;
+}
+
+__global__ void __launch_bounds__(256) frob2_sum_kernel(int batch, const double* part, const int* active,
+                                                        double* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= batch || (active && active[p] == 0)) return;
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < FROB_SPLIT; ++q) s += part[(long)p * FROB_SPLIT + q];
+  out[p] = s;
 }
 
 __global__ void __launch_bounds__(RED_NT) dot_re_kernel(int b, const double2* P, long sP, const double2* Q, long sQ,
@@ -313,9 +330,11 @@ hipError_t launch_sub2(int b, int batch, const double2* x, long sx, double2* a, 
   return hipGetLastError();
 }
 
-hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, double* nrm2, hipStream_t s) {
+hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, const int* active, double* part,
+                        double* nrm2, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(frob2_kernel, dim3(batch), dim3(RED_NT), 0, s, b, X, sX, shift, nrm2);
+  hipLaunchKernelGGL(frob2_part_kernel, dim3(FROB_SPLIT, batch), dim3(RED_NT), 0, s, b, X, sX, shift, active, part);
+  hipLaunchKernelGGL(frob2_sum_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, batch, part, active, nrm2);
   return hipGetLastError();
 }
 

@@ -88,7 +88,11 @@ hipError_t launch_copy_blocks(int b, int batch, const double2* src, long sS, dou
 hipError_t launch_sub2(int b, int batch, const double2* x, long sx, double2* a, long sa, double2* c, long sc,
                        const int* active, hipStream_t s);
 // nrm2[p] = ||X_p - shift * I||_F^2  (sum of squares)
-hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, double* nrm2, hipStream_t s);
+// nrm2[p] = ||X_p - shift I||_F^2 for items with active[p] != 0 (all when active is null);
+// part: scratch of batch * FROB_SPLIT doubles.
+constexpr int FROB_SPLIT = 16;
+hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, const int* active, double* part,
+                        double* nrm2, hipStream_t s);
 // Decimation convergence update for each item (one per (point, lead) pair).
 hipError_t launch_sr_check(int batch, const double* a2, const double* c2, const double* d2, double tol, int iter,
                            int* active, int* iters, int* n_active, hipStream_t s);

@@ -161,8 +161,10 @@ hipError_t launch_sub2(int b, int batch, const double2* x, long sx, double2* a, 
   return hipSuccess;
 }
 
-hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, double* nrm2, hipStream_t) {
+hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, const int* active, double*,
+                        double* nrm2, hipStream_t) {
   for (int p = 0; p < batch; ++p) {
+    if (active && active[p] == 0) continue;
     double s = 0;
     for (long i = 0; i < (long)b * b; ++i) {
       cd v = C(X[(long)p * sX + i]);
