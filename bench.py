@@ -78,7 +78,7 @@ def make_runner(nb, probs, prec, outputs, ws, opts, streams, points, sr_max_iter
     from paper_2602_03438_amd import autotune
     t = autotune.lookup(B)
     per = max(1, points // streams)
-    plan = nb.Plan(probs, prec, opts=nb.make_options(sr_max_iter=sr_max_iter, inv_nb=opts.inv_nb),
+    plan = nb.Plan(probs, prec, opts=nb.make_options(sr_max_iter=sr_max_iter, inv_nb=opts.inv_nb, cmul=opts.cmul),
                    tunings=[(B, t["gemm_tile"], t["gemm_tile_f32"], opts.inv_nb or t["inv_nb"], per)],
                    n_streams=streams)
     info = torch.zeros(points, dtype=torch.int32, device="cuda")
@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-chosen", action="store_true")
     ap.add_argument("--inv-nb", type=int, default=16)
+    ap.add_argument("--cmul", type=int, choices=[3, 4], default=4,
+                    help="real products per complex double product (3: Gauss's method)")
     ap.add_argument("--workload", choices=["ribbon", "uneven", "learned"], default="ribbon",
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation")
@@ -192,7 +194,7 @@ def main():
     gdev = nb.DeviceOnGPU(dev)
     prob = nb.Problem(gdev, batches[0], eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT)
     probs = [prob]
-    opts = nb.make_options(inv_nb=args.inv_nb)
+    opts = nb.make_options(inv_nb=args.inv_nb, cmul=args.cmul)
     ws = nb.Workspace()
     outputs = nb._rgf_outputs(probs, True, False, True)
     torch.cuda.synchronize()
@@ -264,6 +266,7 @@ def main():
                                "muL=0.1 muR=-0.1 kT=0.025, energies from 1024 in [-1.5,1.5]",
                    "points_per_step": args.points, "nb": NB, "b": B, "precision": "plain FP64",
                    "streams": args.streams, "inversion_panel": args.inv_nb, "sr_max_iter": args.sr_max_iter,
+                   "real_products_per_complex_product": args.cmul,
                    "outputs": "G^R diag/upper/lower + G^< diag/upper in HBM"},
         "info_nonzero": len(res["failures"]),
         "failures": res["failures"][:8],

@@ -116,6 +116,9 @@ typedef struct negf_options {
   int32_t xcd_remap;    /* 1: place the tiles of one matrix on one XCD            [1]   */
   int32_t gemm_tile;    /* product tile: 1 = 64x64, 2 = 128x64, 3 = 128x128       [1]   */
   int32_t gemm_tile_f32;/* tile of the single-precision products                  [1]   */
+  int32_t cmul;         /* real products per complex double product: 4, or 3 by
+                           Gauss's method (3/4 of the matrix-core work; error
+                           bounded normwise, not componentwise)  [4]   */
 } negf_options;
 
 /* Operation codes for negf_workspace_bytes. */
@@ -211,7 +214,8 @@ void negf_plan_destroy(negf_plan* plan);
 /* C_p = alpha op(A_p) op(B_p) + beta C_p for p < batch, complex128 M x N
  * outputs, op = 'N' or 'C' (conjugate transpose).  lda/ldb/ldc are row
  * strides, sa/sb/sc batch strides, all in complex elements.  alpha, beta:
- * host arrays of 2 doubles.  prec: 0 double, 1 single products.
+ * host arrays of 2 doubles.  prec: 0 double, 1 single products, 2 double
+ * with three real products per complex product (Gauss's method).
  * tile: 0 default, 1 = 64x64, 2 = 128x64, 3 = 128x128 output tiles.
  * Returns NEGF_EINVAL for bad sizes. */
 negf_status negf_zgemm_batched(char opa, char opb, int32_t M, int32_t N, int32_t K, const double* alpha,

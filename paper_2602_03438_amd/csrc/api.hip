@@ -33,6 +33,7 @@ struct Opts {
   int xcd = 1;
   int tile = GEMM_TILE_64;
   int tile32 = GEMM_TILE_64;
+  int gauss = 0;
 };
 
 Opts get_opts(const negf_options* o) {
@@ -46,6 +47,8 @@ Opts get_opts(const negf_options* o) {
   if (o->xcd_remap == 0 || o->xcd_remap == 1) r.xcd = o->xcd_remap;
   if (o->gemm_tile >= GEMM_TILE_64 && o->gemm_tile <= GEMM_TILE_128x128) r.tile = o->gemm_tile;
   if (o->gemm_tile_f32 >= GEMM_TILE_64 && o->gemm_tile_f32 <= GEMM_TILE_128x128) r.tile32 = o->gemm_tile_f32;
+  if (o->cmul == 3) r.gauss = 1;
+  if (o->cmul == 4) r.gauss = 0;
   return r;
 }
 
@@ -221,6 +224,7 @@ struct Ctx {
     g.xcd_remap = o.xcd;
     g.tile = pr == PREC_F32 ? o.tile32 : o.tile;
     g.prof_class = -1;
+    g.gauss = pr == PREC_F64 ? o.gauss : 0;
     chk(launch_gemm(g, s));
   }
   void inverse(int b, int batch, double2* M, long sM, double2* out, long sO, void* scratch, int* info, int info_mod,
@@ -234,6 +238,7 @@ struct Ctx {
     d.info = info; d.info_mod = info_mod;
     d.active = active;
     d.nb = o.inv_nb;
+    d.gauss = o.gauss;
     chk(launch_inverse(d, s));
   }
   void lincomb(int b, int batch, double2 c1, const double2* X, long sX, double2 c2, const double2* Y, long sY,
@@ -1039,7 +1044,9 @@ negf_status negf_zgemm_batched(char opa, char opb, int32_t M, int32_t N, int32_t
   g.beta = make_double2(beta[0], beta[1]);
   g.Cin = MatRef{(const double2*)C, (long)ldc, (long)sc};
   g.C = MatOut{(double2*)C, (long)ldc, (long)sc};
+  if (prec < 0 || prec > 2) return NEGF_EINVAL;
   g.prec = prec == 1 ? PREC_F32 : PREC_F64;
+  g.gauss = prec == 2;
   g.tile = tile;
   g.xcd_remap = 1;
   g.prof_class = -1;

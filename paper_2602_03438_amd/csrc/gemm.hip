@@ -5,7 +5,13 @@
 // is formed from four real products per k-step (re*re, -im*im, re*im, im*re)
 // on v_mfma_f64_16x16x4f64 (double) or v_mfma_f32_16x16x4f32 (single: operands
 // rounded to complex64 when they are staged, single accumulation, result
-// widened to double on store).
+// widened to double on store).  The double kernel can instead use three real
+// products (Gauss's method): P1 = Re A Re B, P2 = Im A Im B,
+// P3 = (Re A + Im A)(Re B + Im B), Re C = P1 - P2, Im C = P3 - P1 - P2; the
+// operand sums are formed from the staged tiles, so the matrix cores do 3/4
+// of the work.  Its error is bounded normwise by a small multiple of the
+// four-product one (the imaginary part is not componentwise accurate when it
+// cancels).
 //
 // Work decomposition: one workgroup of WM x WN waves per BM x BN output tile
 // (64x64 with 2x2 waves, 128x64 and 128x128 with 4x2 waves); each wave owns
@@ -118,7 +124,7 @@ __device__ __forceinline__ void store_tile(typename Cx<T>::type* s, const double
 
 // TAG only separates the symbol of the inversion updates from the sweep
 // products in profiles; the code is the same.
-template <typename T, int OPA, int OPB, typename CF, int TAG = 0>
+template <typename T, int OPA, int OPB, typename CF, int TAG = 0, bool GAUSS = false>
 __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
   typedef typename Cx<T>::type CT;
   typedef typename Acc<T>::type AT;
@@ -145,7 +151,9 @@ __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
   const int wm = wave / CF::WN, wn = wave % CF::WN;
   const int li = lane & 15, lk = lane >> 4;
 
-  AT accR[FM][FN], accI[FM][FN];
+  // four products: accR = Re C, accI = Im C; Gauss: accR = P1, accI = P2, accS = P3
+  constexpr int NS = GAUSS ? FM : 1;
+  AT accR[FM][FN], accI[FM][FN], accS[NS][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -153,6 +161,10 @@ __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
       accR[i][j] = AT{0, 0, 0, 0};
       accI[i][j] = AT{0, 0, 0, 0};
     }
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) accS[i][j] = AT{0, 0, 0, 0};
 
   double2 ra[CF::LA], rb[CF::LB];
   auto gload = [&](int k0) {
@@ -189,22 +201,42 @@ __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
         const int n = wn * CF::TN + j * 16 + li;
         bv[j] = B_ROW ? xB[n * CF::LD_ROW + kq] : xB[kq * CF::LDB_COL + n];
       }
+      if constexpr (GAUSS) {
+        T as[FM], bs[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i) as[i] = av[i].x + av[i].y;
 #pragma unroll
-        for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+        for (int j = 0; j < FN; ++j) bs[j] = bv[j].x + bv[j].y;
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
+          for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
+          for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].y, accI[i][j]);
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < NS; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
+          for (int j = 0; j < FN; ++j) accS[i][j] = mfma16(as[i], bs[j], accS[i][j]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
+      }
     }
     if (kt + 1 < nk) lstore(st ^ 1);
     __syncthreads();
@@ -223,7 +255,15 @@ __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm * CF::TM + i * 16 + acc_row<T>(lk, v);
         if (row >= a.M) continue;
-        const double re = (double)accR[i][j][v], im = (double)accI[i][j][v];
+        double re, im;
+        if constexpr (GAUSS) {
+          const double p1 = (double)accR[i][j][v], p2 = (double)accI[i][j][v];
+          re = p1 - p2;
+          im = (double)accS[i < NS ? i : 0][j][v] - p1 - p2;
+        } else {
+          re = (double)accR[i][j][v];
+          im = (double)accI[i][j][v];
+        }
         double2 out = make_double2(a.alpha.x * re - a.alpha.y * im, a.alpha.x * im + a.alpha.y * re);
         if (use_beta) {
           const double2 c = Ci[(long)row * a.ldci + col];
@@ -239,27 +279,35 @@ typedef Cfg<64, 64, 2, 2> Cfg64;
 typedef Cfg<128, 64, 4, 2> Cfg128x64;
 typedef Cfg<128, 128, 4, 2> Cfg128;
 
-template <typename T, typename CF>
+template <typename T, typename CF, bool GAUSS>
 hipError_t launch_cfg(const GemmDesc& d, KArgs ka, hipStream_t s) {
   ka.tiles_m = (d.M + CF::BM - 1) / CF::BM;
   ka.tiles_n = (d.N + CF::BN - 1) / CF::BN;
   const long total = (long)ka.tiles_m * ka.tiles_n * d.batch;
   const dim3 grid((unsigned)total), block(CF::NT);
   if (d.prof_class == KC_INV_GEMM && d.opA == OP_N && d.opB == OP_N)
-    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 1>), grid, block, 0, s, ka);
-  else if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF>), grid, block, 0, s, ka);
-  else if (d.opA == OP_C && d.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF>), grid, block, 0, s, ka);
-  else if (d.opA == OP_N && d.opB == OP_C) hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_C, CF>), grid, block, 0, s, ka);
-  else hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_C, CF>), grid, block, 0, s, ka);
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 1, GAUSS>), grid, block, 0, s, ka);
+  else if (d.opA == OP_N && d.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 0, GAUSS>), grid, block, 0, s, ka);
+  else if (d.opA == OP_C && d.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF, 0, GAUSS>), grid, block, 0, s, ka);
+  else if (d.opA == OP_N && d.opB == OP_C)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_C, CF, 0, GAUSS>), grid, block, 0, s, ka);
+  else hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_C, CF, 0, GAUSS>), grid, block, 0, s, ka);
   return hipGetLastError();
 }
 
-template <typename T>
+// The three-product form keeps a third accumulator set; with 128x128 tiles
+// that no longer fits the register file, so it runs on 128x64 tiles there.
+template <typename T, bool GAUSS>
 hipError_t launch_t(const GemmDesc& d, const KArgs& ka, int tile, hipStream_t s) {
+  if (GAUSS && tile == GEMM_TILE_128x128) tile = GEMM_TILE_128x64;
   switch (tile) {
-    case GEMM_TILE_128x64: return launch_cfg<T, Cfg128x64>(d, ka, s);
-    case GEMM_TILE_128x128: return launch_cfg<T, Cfg128>(d, ka, s);
-    default: return launch_cfg<T, Cfg64>(d, ka, s);
+    case GEMM_TILE_128x64: return launch_cfg<T, Cfg128x64, GAUSS>(d, ka, s);
+    case GEMM_TILE_128x128:
+      if constexpr (!GAUSS) return launch_cfg<T, Cfg128, GAUSS>(d, ka, s);
+      [[fallthrough]];
+    default: return launch_cfg<T, Cfg64, GAUSS>(d, ka, s);
   }
 }
 
@@ -281,7 +329,9 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
   if (tile == GEMM_TILE_DEFAULT) tile = GEMM_TILE_64;
   const int cls = d.prof_class >= 0 ? d.prof_class : (d.prec == PREC_F32 ? KC_GEMM32 : KC_GEMM64);
   prof_begin(cls, s);
-  hipError_t e = d.prec == PREC_F32 ? launch_t<float>(d, ka, tile, s) : launch_t<double>(d, ka, tile, s);
+  hipError_t e = d.prec == PREC_F32 ? launch_t<float, false>(d, ka, tile, s)
+                 : d.gauss          ? launch_t<double, true>(d, ka, tile, s)
+                                    : launch_t<double, false>(d, ka, tile, s);
   prof_end(cls, s, 8.0 * d.M * (double)d.N * d.K * d.batch,
            16.0 * d.batch * ((double)d.M * d.K + (double)d.K * d.N + 2.0 * d.M * d.N));
   return e;

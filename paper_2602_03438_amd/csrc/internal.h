@@ -34,6 +34,7 @@ struct GemmDesc {
   int tile;            // 0 = default tile shape; see gemm.hip
   int xcd_remap;       // group the tiles of one batch item on one XCD
   int prof_class;      // -1: by precision
+  int gauss;           // double products with three real products per complex one
 };
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
 
@@ -50,6 +51,7 @@ struct InvDesc {
   int info_mod;         // 0: info[p]
   const int* active;    // nullable
   int nb;               // panel width (16 or 32; 0 = default)
+  int gauss;            // trailing updates with three real products per complex one
 };
 size_t inverse_scratch_bytes(int n, int batch);
 hipError_t launch_inverse(const InvDesc& d, hipStream_t s);

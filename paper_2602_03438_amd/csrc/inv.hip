@@ -392,7 +392,7 @@ ScratchLayout layout(int n) {
 }
 
 GemmDesc update_desc(int M, int N, int K, const double2* Wm, long ldw, long sW, const double2* Um, long ldu, long sU,
-                     double2* C, long ldc, long sC, int batch, const int* active) {
+                     double2* C, long ldc, long sC, int batch, const int* active, int gauss) {
   GemmDesc g{};
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.opA = OP_N; g.opB = OP_N;
@@ -407,6 +407,7 @@ GemmDesc update_desc(int M, int N, int K, const double2* Wm, long ldw, long sW, 
   g.xcd_remap = 1;
   g.tile = GEMM_TILE_64;
   g.prof_class = KC_INV_GEMM;
+  g.gauss = gauss;
   return g;
 }
 
@@ -446,7 +447,8 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
       prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       // update of the super-panel columns: A[:, J] += W U[:, J]
-      GemmDesc g = update_desc(n, mo, nbw, W, NB, sItem, U + J0, n, sItem, d.M + J0, d.ldm, d.sM, d.batch, d.active);
+      GemmDesc g = update_desc(n, mo, nbw, W, NB, sItem, U + J0, n, sItem, d.M + J0, d.ldm, d.sM, d.batch, d.active,
+                               d.gauss);
       if ((e = launch_gemm(g, s)) != hipSuccess) return e;
     }
     if (mo == n) break;   // one level: the super-panel was the whole matrix
@@ -456,7 +458,8 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
                        n, J0, mo, d.M, d.ldm, d.sM, Wo, sItem, Uo, sItem, tau, sI, d.active);
     prof_end(KC_INV_SWAP, s, 0, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    GemmDesc g = update_desc(n, n, mo, Wo, mo, sItem, Uo, n, sItem, d.M, d.ldm, d.sM, d.batch, d.active);
+    GemmDesc g =
+        update_desc(n, n, mo, Wo, mo, sItem, Uo, n, sItem, d.M, d.ldm, d.sM, d.batch, d.active, d.gauss);
     if ((e = launch_gemm(g, s)) != hipSuccess) return e;
   }
   prof_begin(KC_INV_PERM, s);

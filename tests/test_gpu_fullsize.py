@@ -48,10 +48,24 @@ def _sample(dev, energies):
     return picks
 
 
-def _run(nb, bench, prob, prec):
+@pytest.fixture(scope="module")
+def refs(setup):
+    """Oracle results (and per-point tolerances) at the sampled points."""
+    nb, bench, dev, energies, prob = setup
+    out = {}
+    for k in _sample(dev, energies):
+        out[k] = point_tolerance(lambda: orgf.solve_point(dev, energies[k], ETA, MU_L, MU_R, KT), NAMES)
+    return out
+
+
+NAMES = ["GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper"]
+
+
+def _run(nb, bench, prob, prec, cmul=0):
     import torch
     outputs = nb._rgf_outputs([prob], True, False, True)
-    run, plan = bench.make_runner(nb, [prob], prec, outputs, None, nb.make_options(inv_nb=16), STREAMS, P)
+    opts = nb.make_options(inv_nb=16, cmul=cmul)
+    run, plan = bench.make_runner(nb, [prob], prec, outputs, None, opts, STREAMS, P)
     info = run()
     torch.cuda.synchronize()
     plan.close()
@@ -74,15 +88,14 @@ def _properties(nb, outputs, prob):
         assert torch.all(ldos >= -1e-10 * scale).item(), k
 
 
-def test_fullsize_plain_fp64_sampled_parity(setup):
+@pytest.mark.parametrize("cmul", [4, 3])
+def test_fullsize_plain_fp64_sampled_parity(setup, refs, cmul):
     nb, bench, dev, energies, prob = setup
-    outputs, info = _run(nb, bench, prob, nb.PLAIN_FP64)
+    outputs, info = _run(nb, bench, prob, nb.PLAIN_FP64, cmul)
     assert np.all(info == 0), info
-    names = ["GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper"]
-    for k in _sample(dev, energies):
+    for k, (ref, tol) in refs.items():
         print(f"point {k}: E = {energies[k]:.6f}", flush=True)
-        ref, tol = point_tolerance(lambda: orgf.solve_point(dev, energies[k], ETA, MU_L, MU_R, KT), names)
-        for name in names:
+        for name in NAMES:
             g = _point(nb, outputs, prob, k, name)
             r = getattr(ref, name)
             err = float(np.linalg.norm(g - r) / np.linalg.norm(r))
@@ -91,15 +104,14 @@ def test_fullsize_plain_fp64_sampled_parity(setup):
     _properties(nb, outputs, prob)
 
 
-def test_fullsize_refined_form_sampled_parity(setup):
+def test_fullsize_refined_form_sampled_parity(setup, refs):
     nb, bench, dev, energies, prob = setup
     outputs, info = _run(nb, bench, prob, nb.FP32_REFINE)
     assert np.all(info == 0), info
-    k = _sample(dev, energies)[-1]
-    ref = orgf.solve_point(dev, energies[k], ETA, MU_L, MU_R, KT)
-    for name in ("GR_diag", "GL_diag", "GL_upper"):
-        g = _point(nb, outputs, prob, k, name)
-        r = getattr(ref, name)
-        err = float(np.linalg.norm(g - r) / np.linalg.norm(r))
-        print(f"point {k} {name}: {err:.3e}", flush=True)
-        assert err <= 1e-6, (k, name, err)
+    for k, (ref, _) in refs.items():
+        for name in ("GR_diag", "GL_diag", "GL_upper"):
+            g = _point(nb, outputs, prob, k, name)
+            r = getattr(ref, name)
+            err = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+            print(f"point {k} {name}: {err:.3e}", flush=True)
+            assert err <= 1e-6, (k, name, err)

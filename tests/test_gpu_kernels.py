@@ -22,10 +22,12 @@ def _op(x, o):
     return x if o == "N" else np.conj(np.swapaxes(x, -1, -2))
 
 
+@pytest.mark.parametrize("prec", [0, 2])
 @pytest.mark.parametrize("opa", ["N", "C"])
 @pytest.mark.parametrize("opb", ["N", "C"])
 @pytest.mark.parametrize("M,N,K", [(64, 64, 64), (37, 71, 19), (130, 100, 133), (8, 8, 8), (1, 5, 3)])
-def test_zgemm_fp64_parity(nb, opa, opb, M, N, K):
+def test_zgemm_fp64_parity(nb, opa, opb, M, N, K, prec):
+    """prec 0: four real products per complex product; 2: three (Gauss)."""
     import torch
     r = np.random.Generator(np.random.PCG64(M * 1000 + N * 10 + K))
     batch = 3
@@ -35,7 +37,7 @@ def test_zgemm_fp64_parity(nb, opa, opb, M, N, K):
     alpha, beta = 0.7 - 0.3j, -1.1 + 0.4j
     ref = alpha * (_op(A, opa) @ _op(B, opb)) + beta * C0
     Ct = torch.from_numpy(C0.copy()).cuda()
-    nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), Ct, opa, opb, alpha, beta)
+    nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), Ct, opa, opb, alpha, beta, prec=prec)
     got = Ct.cpu().numpy()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert err < 1e-14 * max(1, np.sqrt(K)), err
@@ -44,7 +46,7 @@ def test_zgemm_fp64_parity(nb, opa, opb, M, N, K):
 @pytest.mark.parametrize("tile", [1, 2, 3])
 @pytest.mark.parametrize("opa,opb", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
 @pytest.mark.parametrize("M,N,K", [(200, 130, 77), (128, 256, 64)])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_zgemm_tile_shapes(nb, tile, opa, opb, M, N, K, prec):
     import torch
     r = np.random.Generator(np.random.PCG64(M + N + K + tile))
@@ -56,15 +58,16 @@ def test_zgemm_tile_shapes(nb, tile, opa, opb, M, N, K, prec):
     nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), Ct, opa, opb, 0.5 + 0.25j, -1.0, prec=prec,
              tile=tile)
     err = np.linalg.norm(Ct.cpu().numpy() - ref) / np.linalg.norm(ref)
-    assert err < (1e-13 if prec == 0 else 1e-5), err
+    assert err < (1e-5 if prec == 1 else 1e-13), err
 
 
-def test_zgemm_fp64_b512_batched(nb):
+@pytest.mark.parametrize("prec", [0, 2])
+def test_zgemm_fp64_b512_batched(nb, prec):
     import torch
     r = np.random.Generator(np.random.PCG64(5))
     A = _rand(r, (4, 512, 512))
     B = _rand(r, (4, 512, 512))
-    got = nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()).cpu().numpy()
+    got = nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), prec=prec).cpu().numpy()
     ref = A @ B
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-14
 

@@ -117,14 +117,16 @@ def test_retarded_slab_ragged(nb, b):
 
 # ------------------------------------------------------------------ lesser / greater
 
+@pytest.mark.parametrize("cmul", [4, 3])
 @pytest.mark.parametrize("b,scatter", [(72, True), (130, True), (64, False)])
-def test_lesser_greater_slab(nb, b, scatter):
+def test_lesser_greater_slab(nb, b, scatter, cmul):
+    """cmul: real products per complex double product (3: Gauss's method)."""
     dev = w.slab_device(5, b, 2)
     if scatter:
         w.scattering_self_energies(dev, 3)
     energies = well_posed(dev, np.array([-0.7, 0.02, 0.33, 1.1, -1.3, 0.6]))[:4]
     prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
-    out = nb.rgf_lesser_greater([prob], greater=True)
+    out = nb.rgf_lesser_greater([prob], greater=True, opts=nb.make_options(cmul=cmul))
     assert np.all(out["info"].cpu().numpy() == 0)
     for k, E in enumerate(energies):
         names = ["GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper", "GG_diag", "GG_upper"]
