@@ -75,12 +75,9 @@ def make_runner(nb, probs, prec, outputs, ws, opts, streams, points, sr_max_iter
         def run():
             return nb.rgf_lesser_greater(probs, prec, opts=opts, ws=ws, outputs=outputs, lower=True)["info"]
         return run, None
-    from paper_2602_03438_amd import autotune
-    t = autotune.lookup(B)
     per = max(1, points // streams)
     plan = nb.Plan(probs, prec, opts=nb.make_options(sr_max_iter=sr_max_iter, inv_nb=opts.inv_nb, cmul=opts.cmul),
-                   tunings=[(B, t["gemm_tile"], t["gemm_tile_f32"], opts.inv_nb or t["inv_nb"], per)],
-                   n_streams=streams)
+                   tunings=[(B, opts.gemm_tile, opts.gemm_tile_f32, opts.inv_nb, per)], n_streams=streams)
     info = torch.zeros(points, dtype=torch.int32, device="cuda")
 
     def run():
@@ -146,7 +143,7 @@ def main():
     ap.add_argument("--points", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-chosen", action="store_true")
-    ap.add_argument("--inv-nb", type=int, default=16)
+    ap.add_argument("--inv-nb", type=int, default=0, help="inversion panel width (0: tuned)")
     ap.add_argument("--cmul", type=int, choices=[3, 4], default=4,
                     help="real products per complex double product (3: Gauss's method)")
     ap.add_argument("--workload", choices=["ribbon", "uneven", "learned"], default="ribbon",
@@ -194,7 +191,10 @@ def main():
     gdev = nb.DeviceOnGPU(dev)
     prob = nb.Problem(gdev, batches[0], eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT)
     probs = [prob]
-    opts = nb.make_options(inv_nb=args.inv_nb, cmul=args.cmul)
+    from paper_2602_03438_amd import autotune
+    tuned = autotune.lookup(B, args.cmul)
+    opts = nb.make_options(inv_nb=args.inv_nb or tuned["inv_nb"], cmul=args.cmul, gemm_tile=tuned["gemm_tile"],
+                           gemm_tile_f32=tuned["gemm_tile_f32"])
     ws = nb.Workspace()
     outputs = nb._rgf_outputs(probs, True, False, True)
     torch.cuda.synchronize()
@@ -265,7 +265,8 @@ def main():
                                "~14% dense blocks, S = I + PSD), Sancho-Rubio leads at eta=1e-8, "
                                "muL=0.1 muR=-0.1 kT=0.025, energies from 1024 in [-1.5,1.5]",
                    "points_per_step": args.points, "nb": NB, "b": B, "precision": "plain FP64",
-                   "streams": args.streams, "inversion_panel": args.inv_nb, "sr_max_iter": args.sr_max_iter,
+                   "streams": args.streams, "inversion_panel": opts.inv_nb, "gemm_tile": opts.gemm_tile,
+                   "sr_max_iter": args.sr_max_iter,
                    "real_products_per_complex_product": args.cmul,
                    "outputs": "G^R diag/upper/lower + G^< diag/upper in HBM"},
         "info_nonzero": len(res["failures"]),

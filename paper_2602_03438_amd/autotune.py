@@ -2,10 +2,11 @@
 
 For a block size b it times, on the GPU, every candidate of
   * the complex product kernel: output tile 64x64 / 128x64 / 128x128, for the
-    double and the single-precision products, at the batch the sweeps use;
+    double (four and three real products per complex one) and the
+    single-precision products, at the batch the sweeps use;
   * the block inversion: panel width 16 / 32;
 and keeps the fastest.  Results are cached as JSON keyed by
-"<arch>/b=<b>/<dtype>/<op>" (``tune_cache.json`` next to this file, or the
+"<arch>/b=<b>/<dtype>/<op>" (dtype f64, f64g = three-product double, f32) (``tune_cache.json`` next to this file, or the
 path in $NEGF_TUNE_CACHE); a block size with no entry gets the deterministic
 default (64x64 tiles, panel 16).
 
@@ -42,11 +43,12 @@ def key(b: int, dtype: str, op: str) -> str:
     return f"{ARCH}/b={b}/{dtype}/{op}"
 
 
-def lookup(b: int) -> dict:
-    """Tuned choices for block size b (defaults where the cache has none)."""
+def lookup(b: int, cmul: int = 4) -> dict:
+    """Tuned choices for block size b (defaults where the cache has none).
+    cmul = 3 takes the tile timed for the three-product double kernel."""
     c = load_cache()
     out = dict(DEFAULT)
-    g64 = c.get(key(b, "f64", "zgemm"))
+    g64 = c.get(key(b, "f64g" if cmul == 3 else "f64", "zgemm")) or c.get(key(b, "f64", "zgemm"))
     g32 = c.get(key(b, "f32", "zgemm"))
     inv = c.get(key(b, "f64", "zinv"))
     if g64:
@@ -75,7 +77,7 @@ def tune_block(b: int, batch: int = 64, log=print) -> dict:
     A = torch.randn(batch, b, b, dtype=torch.complex128, device="cuda")
     B = torch.randn(batch, b, b, dtype=torch.complex128, device="cuda")
     C = torch.empty_like(A)
-    for prec, dtype in ((0, "f64"), (1, "f32")):
+    for prec, dtype in ((0, "f64"), (2, "f64g"), (1, "f32")):
         times = {}
         for tile in TILES:
             t = _time(lambda: nb.zgemm(A, B, C, prec=prec, tile=tile))
