@@ -245,8 +245,22 @@ __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
   double2* __restrict__ Cp = a.C + (long)p * a.sC;
   const double2* __restrict__ Ci = a.Cin ? a.Cin + (long)p * a.sCi : nullptr;
   const bool use_beta = (a.beta.x != 0.0 || a.beta.y != 0.0) && Ci != nullptr;
+  // Per row of MFMA tiles: all Cin reads are issued before any result is
+  // stored (C may alias Cin, so the compiler would otherwise wait on each
+  // read in turn); values stay in registers as native vectors.
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i) {
+    v2d cin[FN][4];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * CF::TN + j * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * CF::TM + i * 16 + acc_row<T>(lk, v);
+        const bool ok = use_beta && col < a.N && row < a.M;
+        cin[j][v] = ok ? *reinterpret_cast<const v2d*>(Ci + (long)row * a.ldci + col) : v2d{0.0, 0.0};
+      }
+    }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       const int col = n0 + wn * CF::TN + j * 16 + li;
@@ -264,15 +278,14 @@ __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
           re = (double)accR[i][j][v];
           im = (double)accI[i][j][v];
         }
-        double2 out = make_double2(a.alpha.x * re - a.alpha.y * im, a.alpha.x * im + a.alpha.y * re);
-        if (use_beta) {
-          const double2 c = Ci[(long)row * a.ldci + col];
-          out.x += a.beta.x * c.x - a.beta.y * c.y;
-          out.y += a.beta.x * c.y + a.beta.y * c.x;
-        }
-        Cp[(long)row * a.ldc + col] = out;
+        const v2d c = cin[j][v];
+        v2d out;
+        out.x = a.alpha.x * re - a.alpha.y * im + (a.beta.x * c.x - a.beta.y * c.y);
+        out.y = a.alpha.x * im + a.alpha.y * re + (a.beta.x * c.y + a.beta.y * c.x);
+        *reinterpret_cast<v2d*>(Cp + (long)row * a.ldc + col) = out;
       }
     }
+  }
 }
 
 typedef Cfg<64, 64, 2, 2> Cfg64;
