@@ -81,16 +81,20 @@ __device__ __forceinline__ unsigned pivot_key(double2 v, int r) {
   return ((m != m) ? 0xFFFFF800u : (hi & 0xFFFFF800u)) | (unsigned)(2047 - r);
 }
 
-// Gauss-Jordan step JJ of the panel.  JJ is a compile-time index so that the
-// panel row x[] stays in registers (a runtime index would move it to scratch).
-// Two barriers: after the pivot reduction, and after the pivot row (scaled by
-// its owner) and the displaced row j are published.
-template <int JJ, int NB>
-__device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, int r, int j0, bool valid,
+// One Gauss-Jordan step of the panel, for column j = j0 + jj.  The panel row
+// is kept rotated so that the column being eliminated is always x[0]: all
+// register indices are compile-time constants while the step loop stays a
+// real loop (unrolled steps make a kernel whose straight-line code no longer
+// fits the instruction cache, and its fetches then dominate the panel time).
+// After step jj, x[c] holds panel column (jj + 1 + c) mod NB.  The pivot row
+// in LDS uses the same rotated order.  Two barriers: after the pivot
+// reduction, and after the pivot row (scaled by its owner) and the displaced
+// row j are published.  PB: pivot-row elements held in registers at a time.
+template <int NB, int PB>
+__device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, int r, int j, int jj, bool valid,
                                            int& status) {
   const int lane = r & 63, wave = r >> 6;
-  const int j = j0 + JJ;
-  unsigned key = (valid && r >= j) ? pivot_key(x[JJ], r) : 0u;
+  unsigned key = (valid && r >= j) ? pivot_key(x[0], r) : 0u;
   key = wave_max_u32(key);
   if (lane == 0) L.red[wave] = key;
   __syncthreads();
@@ -104,12 +108,13 @@ __device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, in
   }
   const int pr = 2047 - (int)(key & 0x7FFu);
   if (r == pr) {
-    const double2 d = x[JJ];
+    const double2 d = x[0];
     if (d.x == 0.0 && d.y == 0.0) status = ST_ESINGULAR;
     const double2 dinv = cinv(d);
     if (!(isfinite(dinv.x) && isfinite(dinv.y))) status = status == ST_OK ? ST_ENONFINITE : status;
+    L.prow[0] = dinv;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) L.prow[c] = (c == JJ) ? dinv : cmul(x[c], dinv);
+    for (int c = 1; c < NB; ++c) L.prow[c] = cmul(x[c], dinv);
   }
   if (r == j) {
     if (pr != j) {
@@ -119,7 +124,7 @@ __device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, in
       L.cont[j] = L.cont[pr];
       L.cont[pr] = t;
     }
-    L.spiv[JJ] = pr;
+    L.spiv[jj] = pr;
   }
   __syncthreads();
   if (r == j) {
@@ -130,34 +135,23 @@ __device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, in
 #pragma unroll
       for (int c = 0; c < NB; ++c) x[c] = L.srow[c];
     }
-    // eliminate column JJ (multiplier stored in place: x[JJ] becomes -f / pivot)
-    const double2 f = x[JJ];
-    x[JJ] = make_double2(0.0, 0.0);
+    // eliminate column j (multiplier stored in place: x[0] becomes -f / pivot)
+    const double2 f = x[0];
+    x[0] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       const double2 pc = L.prow[c];
       x[c].x -= f.x * pc.x - f.y * pc.y;
       x[c].y -= f.x * pc.y + f.y * pc.x;
-      // keep the pivot row streaming through a few registers instead of all at once
-      if ((c & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      if ((c % PB) == PB - 1) __builtin_amdgcn_sched_barrier(0);
     }
   }
+  // rotate: the next column moves to x[0]
+  const double2 t0 = x[0];
+#pragma unroll
+  for (int c = 0; c + 1 < NB; ++c) x[c] = x[c + 1];
+  x[NB - 1] = t0;
 }
-
-template <int JJ, int NB>
-struct PanelSteps {
-  __device__ __forceinline__ static void run(double2 (&x)[NB], PanelLds<NB>& L, int r, int j0, int nbw, bool valid,
-                                             int& status) {
-    if (JJ < nbw) {
-      panel_step<JJ, NB>(x, L, r, j0, valid, status);
-      PanelSteps<JJ + 1, NB>::run(x, L, r, j0, nbw, valid, status);
-    }
-  }
-};
-template <int NB>
-struct PanelSteps<NB, NB> {
-  __device__ __forceinline__ static void run(double2 (&)[NB], PanelLds<NB>&, int, int, int, bool, int&) {}
-};
 
 template <int NB, int MAXT>
 __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
@@ -183,11 +177,14 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
     x[c] = (valid && c < nbw) ? A[(long)r * a.lda + j0 + c] : make_double2(0.0, 0.0);
 
   int status = ST_OK;
-  PanelSteps<0, NB>::run(x, L, r, j0, nbw, valid, status);
+  constexpr int PB = (NB > 16 || MAXT > 512) ? 4 : 8;
+#pragma unroll 1
+  for (int jj = 0; jj < nbw; ++jj) panel_step<NB, PB>(x, L, r, j0 + jj, jj, valid, status);
 
   if (valid) {
+    // after nbw rotations x[c] holds panel column (c + nbw) mod NB
 #pragma unroll
-    for (int c = 0; c < NB; ++c) W[(long)r * NB + c] = x[c];
+    for (int c = 0; c < NB; ++c) W[(long)r * NB + (c + nbw) % NB] = x[c];
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c < nbw) A[(long)r * a.lda + j0 + c] = make_double2(0.0, 0.0);
@@ -201,7 +198,7 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
   const int c0 = a.c0, cnt = a.c1 - a.c0;
   const int tot = nbw * cnt;
   const v2d* __restrict__ Av = reinterpret_cast<const v2d*>(A);
-  constexpr int G = 8;
+  constexpr int G = (NB > 16 || MAXT > 512) ? 4 : 8;   // loads in flight per thread (register budget)
   for (int base = 0; base < tot; base += G * nt) {
     v2d v[G];
 #pragma unroll
