@@ -46,15 +46,20 @@ struct PanelArgs {
   const int* active;
 };
 
+constexpr int STAGE_ROWS = 128;   // rows per chunk of the panel's load through LDS
+
 // Shared state of one panel workgroup.
 template <int NB>
 struct PanelLds {
   unsigned red[MAX_ROWS / 64] __attribute__((aligned(16)));
-  double2 srow[NB];
-  double2 prow[NB];
+  v2d prow[NB];              // pivot row, unscaled, in the rotated column order
+  v2d srow[NB];              // row j before the interchange
   int spiv[NB];
   int cont[MAX_ROWS];        // cont[i]: row, at the start of the panel, whose content is now at row i
-  double2 qstage[NB][NBO];   // new contents of the interchanged rows below the panel
+  // first the transposition buffer of the panel load ([STAGE_ROWS][NB + 1]),
+  // later the new contents of the interchanged rows below the panel ([NB][NBO])
+  static constexpr int BUF = (STAGE_ROWS * (NB + 1) > NB * NBO) ? STAGE_ROWS * (NB + 1) : NB * NBO;
+  v2d buf[BUF];
 };
 
 // Maximum of an unsigned value over the 64 lanes of a wavefront: prefix maxima
@@ -75,26 +80,41 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 // everything so that it is taken and reported) and 2047 - r in the low 11
 // bits, so that the unsigned maximum picks the largest magnitude (to 2^-9
 // relative) and, among equal keys, the smallest row.
-__device__ __forceinline__ unsigned pivot_key(double2 v, int r) {
+__device__ __forceinline__ unsigned pivot_key(v2d v, int r) {
   const double m = fabs(v.x) + fabs(v.y);
   const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(m) >> 32);
   return ((m != m) ? 0xFFFFF800u : (hi & 0xFFFFF800u)) | (unsigned)(2047 - r);
 }
 
-// One Gauss-Jordan step of the panel, for column j = j0 + jj.  The panel row
-// is kept rotated so that the column being eliminated is always x[0]: all
-// register indices are compile-time constants while the step loop stays a
-// real loop (unrolled steps make a kernel whose straight-line code no longer
-// fits the instruction cache, and its fetches then dominate the panel time).
-// After step jj, x[c] holds panel column (jj + 1 + c) mod NB.  The pivot row
-// in LDS uses the same rotated order.  Two barriers: after the pivot
-// reduction, and after the pivot row (scaled by its owner) and the displaced
-// row j are published.  PB: pivot-row elements held in registers at a time.
-template <int NB, int PB>
-__device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, int r, int j, int jj, bool valid,
+__device__ __forceinline__ v2d vmul(v2d a, v2d b) { return v2d{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+// 1 / d = conj(d) / |d|^2 with one division: d is first scaled by the power of
+// two of its larger component (exact), so |d|^2 neither overflows nor
+// underflows.  d = 0 gives a non-finite result.
+__device__ __forceinline__ v2d vinv(v2d d) {
+  const double m = fmax(fabs(d.x), fabs(d.y));
+  const int e = m > 0.0 && m <= 1.7976931348623157e308 ? ilogb(m) : 0;
+  const double ax = ldexp(d.x, -e), ay = ldexp(d.y, -e);
+  const double q = 1.0 / (ax * ax + ay * ay);
+  return v2d{ldexp(ax * q, -e), ldexp(-ay * q, -e)};
+}
+
+// One Gauss-Jordan step of the panel, for column j = j0 + jj.  Each thread
+// holds two rows (t and t + NT).  The rows are kept rotated so that the column
+// being eliminated is always x[s][0]: every register index is a compile-time
+// constant while the step loop stays a real loop (straight-line steps would
+// overflow the instruction cache).  After step jj, x[s][c] holds panel column
+// (jj + 1 + c) mod NB; the pivot row in LDS uses the same order.  The pivot
+// row is published unscaled and every thread forms 1 / pivot itself, so the
+// only serial work between the two barriers is the owner's LDS store.
+template <int NB, int NT>
+__device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int t, int n, int j, int jj,
                                            int& status) {
-  const int lane = r & 63, wave = r >> 6;
-  unsigned key = (valid && r >= j) ? pivot_key(x[0], r) : 0u;
+  const int lane = t & 63, wave = t >> 6;
+  const int r0 = t, r1 = t + NT;
+  unsigned key = 0u;
+  if (r0 < n && r0 >= j) key = pivot_key(x[0][0], r0);
+  if (r1 < n && r1 >= j) key = max(key, pivot_key(x[1][0], r1));
   key = wave_max_u32(key);
   if (lane == 0) L.red[wave] = key;
   __syncthreads();
@@ -102,94 +122,153 @@ __device__ __forceinline__ void panel_step(double2 (&x)[NB], PanelLds<NB>& L, in
     const uint4* rv = reinterpret_cast<const uint4*>(L.red);
 #pragma unroll
     for (int q = 0; q < MAX_ROWS / 256; ++q) {
-      const uint4 t = rv[q];
-      key = max(max(key, t.x), max(t.y, max(t.z, t.w)));
+      const uint4 u = rv[q];
+      key = max(max(key, u.x), max(u.y, max(u.z, u.w)));
     }
   }
   const int pr = 2047 - (int)(key & 0x7FFu);
-  if (r == pr) {
-    const double2 d = x[0];
-    if (d.x == 0.0 && d.y == 0.0) status = ST_ESINGULAR;
-    const double2 dinv = cinv(d);
-    if (!(isfinite(dinv.x) && isfinite(dinv.y))) status = status == ST_OK ? ST_ENONFINITE : status;
-    L.prow[0] = dinv;
+  // (rows are picked by selecting values, never by a runtime register index)
+  if (pr == r0 || pr == r1) {
+    const bool first = pr == r0;
 #pragma unroll
-    for (int c = 1; c < NB; ++c) L.prow[c] = cmul(x[c], dinv);
+    for (int c = 0; c < NB; ++c) L.prow[c] = first ? x[0][c] : x[1][c];
   }
-  if (r == j) {
+  if (j == r0 || j == r1) {
     if (pr != j) {
+      const bool first = j == r0;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) L.srow[c] = x[c];
-      const int t = L.cont[j];
+      for (int c = 0; c < NB; ++c) L.srow[c] = first ? x[0][c] : x[1][c];
+      const int u = L.cont[j];
       L.cont[j] = L.cont[pr];
-      L.cont[pr] = t;
+      L.cont[pr] = u;
     }
     L.spiv[jj] = pr;
   }
   __syncthreads();
-  if (r == j) {
-#pragma unroll
-    for (int c = 0; c < NB; ++c) x[c] = L.prow[c];
-  } else if (valid) {
-    if (r == pr) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) x[c] = L.srow[c];
-    }
-    // eliminate column j (multiplier stored in place: x[0] becomes -f / pivot)
-    const double2 f = x[0];
-    x[0] = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const double2 pc = L.prow[c];
-      x[c].x -= f.x * pc.x - f.y * pc.y;
-      x[c].y -= f.x * pc.y + f.y * pc.x;
-      if ((c % PB) == PB - 1) __builtin_amdgcn_sched_barrier(0);
-    }
+  const v2d d = L.prow[0];
+  const v2d dinv = vinv(d);
+  const bool j0r = j == r0, j1r = j == r1;
+  if (j0r || j1r) {
+    if (d.x == 0.0 && d.y == 0.0) status = ST_ESINGULAR;
+    else if (!(isfinite(dinv.x) && isfinite(dinv.y))) status = status == ST_OK ? ST_ENONFINITE : status;
   }
-  // rotate: the next column moves to x[0]
-  const double2 t0 = x[0];
+  // the row that held the pivot takes the old row j
+  if (pr == r0 && !j0r) {
 #pragma unroll
-  for (int c = 0; c + 1 < NB; ++c) x[c] = x[c + 1];
-  x[NB - 1] = t0;
+    for (int c = 0; c < NB; ++c) x[0][c] = L.srow[c];
+  }
+  if (pr == r1 && !j1r) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[1][c] = L.srow[c];
+  }
+  // every other row: x_r -= (x_rj / pivot) * pivot row, the multiplier's
+  // negative stored in column j; row j becomes pivot row / pivot (the same
+  // update with a zero row and multiplier -1 / pivot)
+  const v2d f0 = j0r ? -dinv : vmul(x[0][0], dinv);
+  const v2d f1 = j1r ? -dinv : vmul(x[1][0], dinv);
+  x[0][0] = j0r ? dinv : -f0;
+  x[1][0] = j1r ? dinv : -f1;
+#pragma unroll
+  for (int c = 1; c < NB; ++c) {
+    const v2d pc = L.prow[c];
+    x[0][c] = (j0r ? v2d{0.0, 0.0} : x[0][c]) - vmul(f0, pc);
+    x[1][c] = (j1r ? v2d{0.0, 0.0} : x[1][c]) - vmul(f1, pc);
+  }
+  // rotate: the next column moves to slot 0
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const v2d u = x[s][0];
+#pragma unroll
+    for (int c = 0; c + 1 < NB; ++c) x[s][c] = x[s][c + 1];
+    x[s][NB - 1] = u;
+  }
 }
 
-template <int NB, int MAXT>
-__global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
+// Panel kernel: one workgroup of NT threads per matrix, two rows per thread
+// (n <= 2 NT).  The panel is read coalesced (consecutive lanes along a row)
+// and handed to its row owners through LDS in chunks of STAGE_ROWS rows; W is
+// written transposed and conjugated (W^H, nb x n), again coalesced.
+template <int NB, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) gj_panel_kernel(PanelArgs a) {
   const int p = blockIdx.x;
   if (a.active && a.active[p] == 0) return;
   double2* __restrict__ A = a.A + (long)p * a.sA;
-  double2* __restrict__ W = a.W + (long)p * a.sW;
+  v2d* __restrict__ Wt = reinterpret_cast<v2d*>(a.W + (long)p * a.sW);
   double2* __restrict__ U = a.U + (long)p * a.sU;
   int* __restrict__ sigma = a.sigma + (long)p * a.sS;
   int* __restrict__ tau = a.tau + (long)p * a.sS;
-  const int r = threadIdx.x;
-  const int nt = blockDim.x;
+  const v2d* __restrict__ Av = reinterpret_cast<const v2d*>(A);
+  const int t = threadIdx.x;
   const int n = a.n, j0 = a.j0, nbw = a.nbw;
   const int jend = j0 + nbw;
-  const bool valid = r < n;
+  const long lda = a.lda;
   __shared__ PanelLds<NB> L;
-  if (r < MAX_ROWS / 64) L.red[r] = 0u;   // waves beyond the last never write their slot
-  for (int i = r; i < n; i += nt) L.cont[i] = i;
+  if (t < MAX_ROWS / 64) L.red[t] = 0u;   // waves beyond the last never write their slot
+  for (int i = t; i < n; i += NT) L.cont[i] = i;
 
-  double2 x[NB];
+  // --- panel load: chunk ch covers rows [ch*STAGE_ROWS, (ch+1)*STAGE_ROWS)
+  constexpr int CH = 2 * NT / STAGE_ROWS;
+  constexpr int PER = STAGE_ROWS * NB / NT;
+  static_assert(CH * STAGE_ROWS == 2 * NT && PER * NT == STAGE_ROWS * NB, "panel load must tile evenly");
+  v2d x[2][NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c)
-    x[c] = (valid && c < nbw) ? A[(long)r * a.lda + j0 + c] : make_double2(0.0, 0.0);
+  for (int c = 0; c < NB; ++c) x[0][c] = x[1][c] = v2d{0.0, 0.0};
+  v2d ld[PER], nx[PER];
+  auto gload = [&](int ch, v2d (&dst)[PER]) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = e * NT + t, rr = ch * STAGE_ROWS + idx / NB, cc = idx % NB;
+      dst[e] = (rr < n && cc < nbw) ? Av[(long)rr * lda + j0 + cc] : v2d{0.0, 0.0};
+    }
+  };
+  gload(0, ld);
+  constexpr int CH_UNROLL = CH <= 4 ? CH : 1;   // wider unrolling only adds live address registers
+#pragma unroll CH_UNROLL
+  for (int ch = 0; ch < CH; ++ch) {
+    if (ch + 1 < CH) gload(ch + 1, nx);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = e * NT + t;
+      L.buf[(idx / NB) * (NB + 1) + idx % NB] = ld[e];
+    }
+    __syncthreads();
+    const int first = ch * STAGE_ROWS;        // first row of the chunk
+    const int tb = first % NT;                // its owner thread
+    const bool mine = t >= tb && t < tb + STAGE_ROWS;
+    const bool s0 = mine && first < NT, s1 = mine && first >= NT;
+    const int li = mine ? t - tb : 0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const v2d v = L.buf[li * (NB + 1) + c];
+      x[0][c] = s0 ? v : x[0][c];
+      x[1][c] = s1 ? v : x[1][c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) ld[e] = nx[e];
+  }
 
   int status = ST_OK;
-  constexpr int PB = (NB > 16 || MAXT > 512) ? 4 : 8;
 #pragma unroll 1
-  for (int jj = 0; jj < nbw; ++jj) panel_step<NB, PB>(x, L, r, j0 + jj, jj, valid, status);
+  for (int jj = 0; jj < nbw; ++jj) panel_step<NB, NT>(x, L, t, n, j0 + jj, jj, status);
 
-  if (valid) {
-    // after nbw rotations x[c] holds panel column (c + nbw) mod NB
+  // --- W^H (nb x n): after nbw rotations x[s][c] holds panel column (c + nbw) mod NB
 #pragma unroll
-    for (int c = 0; c < NB; ++c) W[(long)r * NB + (c + nbw) % NB] = x[c];
+  for (int s = 0; s < 2; ++s) {
+    const int r = t + s * NT;
+    if (r < n) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-      if (c < nbw) A[(long)r * a.lda + j0 + c] = make_double2(0.0, 0.0);
+      for (int c = 0; c < NB; ++c) {
+        const v2d v = x[s][c];
+        Wt[(long)((c + nbw) % NB) * n + r] = v2d{v.x, -v.y};
+      }
+    }
   }
-  __syncthreads();
+  // clear the panel columns of A (consecutive lanes along a row)
+  for (int idx = t; idx < n * nbw; idx += NT) {
+    const int rr = idx / nbw, cc = idx % nbw;
+    A[(long)rr * lda + j0 + cc] = make_double2(0.0, 0.0);
+  }
 
   // The nbw interchanges, composed into cont[], act on the rows D = panel rows
   // and the rows below the panel they touched.  Every new row of D is an old
@@ -197,48 +276,32 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
   // then, after a barrier, the writes.
   const int c0 = a.c0, cnt = a.c1 - a.c0;
   const int tot = nbw * cnt;
-  const v2d* __restrict__ Av = reinterpret_cast<const v2d*>(A);
-  constexpr int G = (NB > 16 || MAXT > 512) ? 4 : 8;   // loads in flight per thread (register budget)
-  for (int base = 0; base < tot; base += G * nt) {
-    v2d v[G];
+  constexpr int G = (NB > 16 || NT > 256) ? 4 : 8;   // loads in flight per thread and kind
+  for (int base = 0; base < tot; base += G * NT) {
+    v2d u[G], q[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const int e = base + g * nt + r;
+      const int e = base + g * NT + t;
       const int s = e / cnt, c = c0 + e % cnt;
-      const bool outside = c < j0 || c >= jend;
-      v[g] = (e < tot && outside) ? Av[(long)L.cont[j0 + s] * a.lda + c]
-                                  : v2d{(e < tot && c - j0 == s) ? 1.0 : 0.0, 0.0};
+      const bool in = e < tot, outside = c < j0 || c >= jend;
+      const int qr = in ? L.spiv[s] : 0;
+      u[g] = (in && outside) ? Av[(long)L.cont[j0 + s] * lda + c] : v2d{(in && c - j0 == s) ? 1.0 : 0.0, 0.0};
+      q[g] = (in && outside && qr >= jend) ? Av[(long)L.cont[qr] * lda + c] : v2d{0.0, 0.0};
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const int e = base + g * nt + r;
-      if (e < tot) reinterpret_cast<v2d*>(U)[(long)(e / cnt) * n + c0 + e % cnt] = v[g];
-    }
-  }
-  for (int base = 0; base < tot; base += G * nt) {
-    v2d v[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int e = base + g * nt + r;
-      const int s = e / cnt, c = c0 + e % cnt, q = e < tot ? L.spiv[s] : 0;
-      const bool take = e < tot && q >= jend && (c < j0 || c >= jend);
-      v[g] = take ? Av[(long)L.cont[q] * a.lda + c] : v2d{0.0, 0.0};
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int e = base + g * nt + r;
-      const int s = e / cnt, c = c0 + e % cnt, q = e < tot ? L.spiv[s] : 0;
-      if (e < tot && q >= jend && (c < j0 || c >= jend)) {
-        L.qstage[s][c - c0].x = v[g].x;
-        L.qstage[s][c - c0].y = v[g].y;
-      }
+      const int e = base + g * NT + t;
+      if (e >= tot) continue;
+      const int s = e / cnt, c = c0 + e % cnt;
+      reinterpret_cast<v2d*>(U)[(long)s * n + c] = u[g];
+      if (L.spiv[s] >= jend && (c < j0 || c >= jend)) L.buf[s * NBO + (c - c0)] = q[g];
     }
   }
   // row orders: new entry of a row d of D = old entry of row cont[d]
   int d = -1, sv = 0, tv = 0;
-  if (r < 2 * nbw) {
-    d = r < nbw ? j0 + r : L.spiv[r - nbw];
-    if (r >= nbw && d < jend) d = -1;
+  if (t < 2 * nbw) {
+    d = t < nbw ? j0 + t : L.spiv[t - nbw];
+    if (t >= nbw && d < jend) d = -1;
     if (d >= 0) {
       const int src = L.cont[d];
       sv = j0 == 0 ? src : sigma[src];
@@ -246,20 +309,20 @@ __global__ void __launch_bounds__(MAXT) gj_panel_kernel(PanelArgs a) {
     }
   }
   __syncthreads();
-  for (int e = r; e < tot; e += nt) {
+  for (int e = t; e < tot; e += NT) {
     const int s = e / cnt, c = c0 + e % cnt;
     if (c >= j0 && c < jend) continue;
-    A[(long)(j0 + s) * a.lda + c] = make_double2(0.0, 0.0);
-    const int q = L.spiv[s];
-    if (q >= jend) A[(long)q * a.lda + c] = L.qstage[s][c - c0];
+    A[(long)(j0 + s) * lda + c] = make_double2(0.0, 0.0);
+    const int qr = L.spiv[s];
+    if (qr >= jend) reinterpret_cast<v2d*>(A)[(long)qr * lda + c] = L.buf[s * NBO + (c - c0)];
   }
   if (j0 == 0) {
-    for (int i = r; i < n; i += nt) sigma[i] = L.cont[i];
+    for (int i = t; i < n; i += NT) sigma[i] = L.cont[i];
   } else if (d >= 0) {
     sigma[d] = sv;
   }
   if (j0 == c0) {
-    for (int i = r; i < n; i += nt) tau[i] = L.cont[i];
+    for (int i = t; i < n; i += NT) tau[i] = L.cont[i];
   } else if (d >= 0) {
     tau[d] = tv;
   }
@@ -388,11 +451,11 @@ ScratchLayout layout(int n) {
   return L;
 }
 
-GemmDesc update_desc(int M, int N, int K, const double2* Wm, long ldw, long sW, const double2* Um, long ldu, long sU,
-                     double2* C, long ldc, long sC, int batch, const int* active, int gauss) {
+GemmDesc update_desc(Op opw, int M, int N, int K, const double2* Wm, long ldw, long sW, const double2* Um, long ldu,
+                     long sU, double2* C, long ldc, long sC, int batch, const int* active, int gauss) {
   GemmDesc g{};
   g.M = M; g.N = N; g.K = K; g.batch = batch;
-  g.opA = OP_N; g.opB = OP_N;
+  g.opA = opw; g.opB = OP_N;
   g.A = MatRef{Wm, ldw, sW};
   g.B = MatRef{Um, ldu, sU};
   g.alpha = make_double2(1.0, 0.0);
@@ -427,7 +490,6 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
   double2* Uo = (double2*)(base + SL.off_Uo);
   int* sigma = (int*)(base + SL.off_sigma);
   int* tau = (int*)(base + SL.off_tau);
-  const int nthr = ((n + 63) / 64) * 64;
   // two levels when the matrix is wider than one super-panel
   const int outer = n > NBO ? NBO : n;
   hipError_t e = hipSuccess;
@@ -438,14 +500,15 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
       PanelArgs pa{n, j0, nbw, J0, J0 + mo, d.M, d.ldm, d.sM, W, sItem, U, sItem, sigma, tau, sI,
                    d.info, d.info_mod, d.active};
       prof_begin(KC_INV_PANEL, s);
-      if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 512>), dim3(d.batch), dim3(nthr), 0, s, pa);
-      else if (n <= 512) hipLaunchKernelGGL((gj_panel_kernel<16, 512>), dim3(d.batch), dim3(nthr), 0, s, pa);
-      else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS>), dim3(d.batch), dim3(nthr), 0, s, pa);
+      // two rows per thread: 256 threads up to n = 512, 512 up to n = MAX_ROWS
+      if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 256>), dim3(d.batch), dim3(256), 0, s, pa);
+      else if (n <= 512) hipLaunchKernelGGL((gj_panel_kernel<16, 256>), dim3(d.batch), dim3(256), 0, s, pa);
+      else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS / 2>), dim3(d.batch), dim3(MAX_ROWS / 2), 0, s, pa);
       prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      // update of the super-panel columns: A[:, J] += W U[:, J]
-      GemmDesc g = update_desc(n, mo, nbw, W, NB, sItem, U + J0, n, sItem, d.M + J0, d.ldm, d.sM, d.batch, d.active,
-                               d.gauss);
+      // A[:, J] += W U[:, J] with W held as W^H (nb x n)
+      GemmDesc g = update_desc(OP_C, n, mo, nbw, W, n, sItem, U + J0, n, sItem, d.M + J0, d.ldm, d.sM, d.batch,
+                               d.active, d.gauss);
       if ((e = launch_gemm(g, s)) != hipSuccess) return e;
     }
     if (mo == n) break;   // one level: the super-panel was the whole matrix
@@ -456,7 +519,7 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
     prof_end(KC_INV_SWAP, s, 0, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     GemmDesc g =
-        update_desc(n, n, mo, Wo, mo, sItem, Uo, n, sItem, d.M, d.ldm, d.sM, d.batch, d.active, d.gauss);
+        update_desc(OP_N, n, n, mo, Wo, mo, sItem, Uo, n, sItem, d.M, d.ldm, d.sM, d.batch, d.active, d.gauss);
     if ((e = launch_gemm(g, s)) != hipSuccess) return e;
   }
   prof_begin(KC_INV_PERM, s);
