@@ -99,22 +99,30 @@ __device__ __forceinline__ v2d vinv(v2d d) {
   return v2d{ldexp(ax * q, -e), ldexp(-ay * q, -e)};
 }
 
+// x -= f * p (complex), as four fused multiply-adds
+__device__ __forceinline__ void csub_mul(v2d& x, v2d f, v2d p) {
+  x.x = fma(-f.x, p.x, fma(f.y, p.y, x.x));
+  x.y = fma(-f.x, p.y, fma(-f.y, p.x, x.y));
+}
+
 // One Gauss-Jordan step of the panel, for column j = j0 + jj.  Each thread
-// holds two rows (t and t + NT).  The rows are kept rotated so that the column
-// being eliminated is always x[s][0]: every register index is a compile-time
-// constant while the step loop stays a real loop (straight-line steps would
-// overflow the instruction cache).  After step jj, x[s][c] holds panel column
-// (jj + 1 + c) mod NB; the pivot row in LDS uses the same order.  The pivot
-// row is published unscaled and every thread forms 1 / pivot itself, so the
-// only serial work between the two barriers is the owner's LDS store.
-template <int NB, int NT>
+// holds two rows (t and t + NT) as register arrays that are only ever indexed
+// by compile-time constants: the step loop advances U columns per iteration
+// (the column being eliminated is x[s][KK]) and then rotates the rows by U, so
+// the code stays a short loop (straight-line steps over the whole panel would
+// overflow the instruction cache).  Before the loop iteration that starts at
+// step jb, x[s][c] holds panel column (jb + c) mod NB; the pivot row in LDS
+// uses the same order.  The pivot row is published unscaled and every thread
+// forms 1 / pivot itself, so the only serial work between the two barriers is
+// the owner's LDS store.
+template <int NB, int NT, int KK>
 __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int t, int n, int j, int jj,
                                            int& status) {
   const int lane = t & 63, wave = t >> 6;
   const int r0 = t, r1 = t + NT;
   unsigned key = 0u;
-  if (r0 < n && r0 >= j) key = pivot_key(x[0][0], r0);
-  if (r1 < n && r1 >= j) key = max(key, pivot_key(x[1][0], r1));
+  if (r0 < n && r0 >= j) key = pivot_key(x[0][KK], r0);
+  if (r1 < n && r1 >= j) key = max(key, pivot_key(x[1][KK], r1));
   key = wave_max_u32(key);
   if (lane == 0) L.red[wave] = key;
   __syncthreads();
@@ -127,17 +135,25 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int
     }
   }
   const int pr = 2047 - (int)(key & 0x7FFu);
-  // (rows are picked by selecting values, never by a runtime register index)
-  if (pr == r0 || pr == r1) {
-    const bool first = pr == r0;
+  const bool j0r = j == r0, j1r = j == r1;
+  if (pr == r0) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) L.prow[c] = first ? x[0][c] : x[1][c];
+    for (int c = 0; c < NB; ++c) L.prow[c] = x[0][c];
   }
-  if (j == r0 || j == r1) {
-    if (pr != j) {
-      const bool first = j == r0;
+  if (pr == r1) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) L.srow[c] = first ? x[0][c] : x[1][c];
+    for (int c = 0; c < NB; ++c) L.prow[c] = x[1][c];
+  }
+  if (j0r && pr != j) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) L.srow[c] = x[0][c];
+  }
+  if (j1r && pr != j) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) L.srow[c] = x[1][c];
+  }
+  if (j0r || j1r) {
+    if (pr != j) {
       const int u = L.cont[j];
       L.cont[j] = L.cont[pr];
       L.cont[pr] = u;
@@ -145,14 +161,15 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int
     L.spiv[jj] = pr;
   }
   __syncthreads();
-  const v2d d = L.prow[0];
+  const v2d d = L.prow[KK];
   const v2d dinv = vinv(d);
-  const bool j0r = j == r0, j1r = j == r1;
   if (j0r || j1r) {
     if (d.x == 0.0 && d.y == 0.0) status = ST_ESINGULAR;
     else if (!(isfinite(dinv.x) && isfinite(dinv.y))) status = status == ST_OK ? ST_ENONFINITE : status;
   }
-  // the row that held the pivot takes the old row j
+  // the row that held the pivot takes the old row j; row j is cleared and
+  // then takes the same update as every other row with multiplier -1 / pivot,
+  // which leaves pivot row / pivot in it
   if (pr == r0 && !j0r) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) x[0][c] = L.srow[c];
@@ -161,28 +178,42 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int
 #pragma unroll
     for (int c = 0; c < NB; ++c) x[1][c] = L.srow[c];
   }
-  // every other row: x_r -= (x_rj / pivot) * pivot row, the multiplier's
-  // negative stored in column j; row j becomes pivot row / pivot (the same
-  // update with a zero row and multiplier -1 / pivot)
-  const v2d f0 = j0r ? -dinv : vmul(x[0][0], dinv);
-  const v2d f1 = j1r ? -dinv : vmul(x[1][0], dinv);
-  x[0][0] = j0r ? dinv : -f0;
-  x[1][0] = j1r ? dinv : -f1;
+  if (j0r) {
 #pragma unroll
-  for (int c = 1; c < NB; ++c) {
-    const v2d pc = L.prow[c];
-    x[0][c] = (j0r ? v2d{0.0, 0.0} : x[0][c]) - vmul(f0, pc);
-    x[1][c] = (j1r ? v2d{0.0, 0.0} : x[1][c]) - vmul(f1, pc);
+    for (int c = 0; c < NB; ++c) x[0][c] = v2d{0.0, 0.0};
   }
-  // rotate: the next column moves to slot 0
+  if (j1r) {
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const v2d u = x[s][0];
+    for (int c = 0; c < NB; ++c) x[1][c] = v2d{0.0, 0.0};
+  }
+  const v2d f0 = j0r ? -dinv : vmul(x[0][KK], dinv);
+  const v2d f1 = j1r ? -dinv : vmul(x[1][KK], dinv);
+  // column j of the inverse: -x_rj / pivot in the other rows, 1 / pivot in row j
+  x[0][KK] = -f0;
+  x[1][KK] = -f1;
 #pragma unroll
-    for (int c = 0; c + 1 < NB; ++c) x[s][c] = x[s][c + 1];
-    x[s][NB - 1] = u;
+  for (int c = 0; c < NB; ++c) {
+    if (c == KK) continue;
+    const v2d pc = L.prow[c];
+    csub_mul(x[0][c], f0, pc);
+    csub_mul(x[1][c], f1, pc);
   }
 }
+
+template <int NB, int NT, int KK, int U>
+struct PanelGroup {
+  __device__ __forceinline__ static void run(v2d (&x)[2][NB], PanelLds<NB>& L, int t, int n, int j0, int jb, int nbw,
+                                             int& status) {
+    if (jb + KK < nbw) {
+      panel_step<NB, NT, KK>(x, L, t, n, j0 + jb + KK, jb + KK, status);
+      PanelGroup<NB, NT, KK + 1, U>::run(x, L, t, n, j0, jb, nbw, status);
+    }
+  }
+};
+template <int NB, int NT, int U>
+struct PanelGroup<NB, NT, U, U> {
+  __device__ __forceinline__ static void run(v2d (&)[2][NB], PanelLds<NB>&, int, int, int, int, int, int&) {}
+};
 
 // Panel kernel: one workgroup of NT threads per matrix, two rows per thread
 // (n <= 2 NT).  The panel is read coalesced (consecutive lanes along a row)
@@ -249,10 +280,26 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
   }
 
   int status = ST_OK;
+  constexpr int SG = 4;   // steps per loop iteration
+  static_assert(NB % SG == 0, "panel width must be a multiple of the step group");
+  int rot = 0;
 #pragma unroll 1
-  for (int jj = 0; jj < nbw; ++jj) panel_step<NB, NT>(x, L, t, n, j0 + jj, jj, status);
+  for (int jb = 0; jb < nbw; jb += SG) {
+    PanelGroup<NB, NT, 0, SG>::run(x, L, t, n, j0, jb, nbw, status);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      v2d h[SG];
+#pragma unroll
+      for (int c = 0; c < SG; ++c) h[c] = x[s][c];
+#pragma unroll
+      for (int c = 0; c + SG < NB; ++c) x[s][c] = x[s][c + SG];
+#pragma unroll
+      for (int c = 0; c < SG; ++c) x[s][NB - SG + c] = h[c];
+    }
+    rot += SG;
+  }
 
-  // --- W^H (nb x n): after nbw rotations x[s][c] holds panel column (c + nbw) mod NB
+  // --- W^H (nb x n): after the rotations x[s][c] holds panel column (c + rot) mod NB
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int r = t + s * NT;
@@ -260,7 +307,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         const v2d v = x[s][c];
-        Wt[(long)((c + nbw) % NB) * n + r] = v2d{v.x, -v.y};
+        Wt[(long)((c + rot) % NB) * n + r] = v2d{v.x, -v.y};
       }
     }
   }
