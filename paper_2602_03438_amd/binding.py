@@ -472,9 +472,11 @@ class Plan:
         return lib().negf_plan_clock_hz()
 
     def close(self):
+        """Destroy the plan and release its workspace."""
         if self.handle:
             lib().negf_plan_destroy(self.handle)
             self.handle = C.c_void_p()
+        self.ws.buf = None
 
     def __del__(self):
         try:

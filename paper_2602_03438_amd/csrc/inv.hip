@@ -161,7 +161,11 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int
     L.spiv[jj] = pr;
   }
   __syncthreads();
-  const v2d d = L.prow[KK];
+  // the whole pivot row at once: one LDS latency instead of one per column
+  v2d pc[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) pc[c] = L.prow[c];
+  const v2d d = pc[KK];
   const v2d dinv = vinv(d);
   if (j0r || j1r) {
     if (d.x == 0.0 && d.y == 0.0) status = ST_ESINGULAR;
@@ -194,9 +198,8 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c == KK) continue;
-    const v2d pc = L.prow[c];
-    csub_mul(x[0][c], f0, pc);
-    csub_mul(x[1][c], f1, pc);
+    csub_mul(x[0][c], f0, pc[c]);
+    csub_mul(x[1][c], f1, pc[c]);
   }
 }
 
