@@ -300,6 +300,8 @@ hipError_t launch_cfg(const GemmDesc& d, KArgs ka, hipStream_t s) {
   const dim3 grid((unsigned)total), block(CF::NT);
   if (d.prof_class == KC_INV_GEMM && d.opA == OP_N && d.opB == OP_N)
     hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 1, GAUSS>), grid, block, 0, s, ka);
+  else if (d.prof_class == KC_INV_GEMM && d.opA == OP_C && d.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF, 1, GAUSS>), grid, block, 0, s, ka);
   else if (d.opA == OP_N && d.opB == OP_N)
     hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 0, GAUSS>), grid, block, 0, s, ka);
   else if (d.opA == OP_C && d.opB == OP_N)
