@@ -151,8 +151,9 @@ def main():
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation")
     ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload")
-    ap.add_argument("--streams", type=int, default=2,
-                    help="worker streams the batch is split over (1: the plain call on the current stream)")
+    ap.add_argument("--streams", type=int, default=None,
+                    help="worker streams the batch is split over (1: the plain call on the current stream); "
+                         "default 1 for the ribbon workload, 4 for the uneven one")
     ap.add_argument("--sr-max-iter", type=int, default=40,
                     help="decimation steps a plan runs (it cannot poll convergence from the host)")
     ap.add_argument("--learned-energies", type=int, default=250, help="training energies per lead")
@@ -183,7 +184,9 @@ def main():
         log(f"calibration copy of {args.calibrate_copy} MiB done")
         del src, dst
     if args.workload == "uneven":
+        args.streams = args.streams or 4
         return bench_uneven(args)
+    args.streams = args.streams or 1
     if args.workload == "learned":
         return bench_learned(args)
     log("generating the Nb=60 b=512 slab device ...")
@@ -318,8 +321,8 @@ def bench_uneven(args):
             g.H_diag, g.H_upper = nb.to_gpu(dk.H_diag), nb.to_gpu(dk.H_upper)
             g.S_diag, g.S_upper = S_d, S_u
             g.sig_r = g.sig_l = g.sig_g = None
-            # point p of the (E, k) grid belongs to device p mod 6: take this device's share, n_e per k
-            share = grid[(np.arange(grid.size) * 4 + ki) % 6 == d]
+            # energy index e of the grid belongs to device e mod 6 (at every k): this device's share, n_e per k
+            share = grid[d::len(w.DEVICE_MIX)]
             E = share[np.linspace(0, share.size - 1, n_e).astype(int)]
             probs.append(nb.Problem(g, E, eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT))
             dev_of.append(d)

@@ -113,13 +113,15 @@ if __name__ == "__main__":
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--calib-mib", type=int, default=1024)
-    ap.add_argument("--kernel", default=r"zgemm_kernel<double, [01], [01], [^>]*Cfg<\d+, \d+, \d, \d>, 0>")
+    ap.add_argument("--kernel", default=r"zgemm_kernel<double, [01], [01], [^>]*Cfg<\d+, \d+, \d, \d>, 0(, (true|false))?>")
     ap.add_argument("--json")
+    ap.add_argument("--note", default="", help="what the counter runs measured (stored in the JSON)")
     a = ap.parse_args()
     if a.traffic:
         rec = traffic(a.traffic[0], a.traffic[1], a.calib_mib, a.kernel)
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         rec["kernel_sha"] = gemm_source_hash(root)
+        rec["note"] = a.note
         print(json.dumps(rec, indent=1))
         if a.json:
             with open(a.json, "w") as f:
