@@ -51,9 +51,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_record():
-    """HBM traffic of the dominant kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+def traffic_per_item():
+    """HBM bytes per b x b x b complex product of the dominant kernel, from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source at this block size."""
     p = os.path.join(ROOT, "profiles", "gemm_f64_traffic.json")
     if not os.path.exists(p):
         return None
@@ -61,9 +62,9 @@ def traffic_record():
         rec = json.load(open(p))
     except Exception:
         return None
-    if rec.get("kernel_sha") != kernel_hash():
+    if rec.get("kernel_sha") != kernel_hash() or rec.get("block") != B:
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_item")
 
 
 def make_runner(nb, probs, prec, outputs, ws, opts, streams, points, sr_max_iter=40):
@@ -212,7 +213,9 @@ def main():
     g = stats["gemm_f64"]
     achieved = g["flops"] / (g["total_ms"] * 1e-3) if g["total_ms"] > 0 else 0.0
     launches = max(1, g["launches"])
-    traffic = traffic_record()
+    per_item = traffic_per_item()
+    items_per_launch = g["flops"] / launches / (8.0 * B ** 3)
+    traffic = per_item * items_per_launch if per_item else None
     # algorithmic flops of the whole step (dense-block count of the method, K_SR measured)
     # achieved counts 8 M N K flop per complex product; with three real products
     # per complex one the matrix cores execute 3/4 of that (mfma_frac)
@@ -221,7 +224,9 @@ def main():
             "achieved": achieved / 1e12, "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK["f64"], "traffic": traffic,
             "launches": int(g["launches"]), "avg_launch_ms": g["total_ms"] / launches,
-            "flops_per_launch": g["flops"] / launches,
+            "flops_per_launch": g["flops"] / launches, "items_per_launch": items_per_launch,
+            "traffic_bytes_per_item": per_item,
+            "algorithmic_bytes_per_item": 3 * 16 * B * B,
             "mfma_frac": mfma_share * achieved / PEAK["f64"],
             "note": "average over the launches of both worker streams; launches overlap, so per-launch durations "
                     "include time shared with the other stream" if args.streams > 1 else ""}

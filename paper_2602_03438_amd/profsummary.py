@@ -12,7 +12,7 @@ what they read for that kernel, then averaged per launch of the kernels
 matching a pattern.
 
     python -m paper_2602_03438_amd.profsummary --traffic FETCH_DIR WRITE_DIR --calib-mib 1024 \\
-        [--kernel REGEX] [--json out.json]
+        [--block 512] [--kernel REGEX] [--json out.json]
 """
 from __future__ import annotations
 
@@ -51,7 +51,7 @@ def summarize(db: str, by_grid: bool = False, top: int = 25):
 
 
 def _counter_rows(d: str):
-    """(dispatch id, kernel name, counter name, value) from a csv counter run."""
+    """(dispatch id, kernel name, counter name, value, grid size, workgroup size) from a csv counter run."""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise FileNotFoundError(f"no *counter_collection.csv under {d}")
@@ -60,18 +60,29 @@ def _counter_rows(d: str):
             for row in csv.DictReader(fh):
                 row = {k.lower(): v for k, v in row.items()}
                 yield (int(row["dispatch_id"]), row["kernel_name"], row["counter_name"],
-                       float(row["counter_value"]))
+                       float(row["counter_value"]), int(row["grid_size"]), int(row["workgroup_size"]))
 
 
 def per_dispatch(d: str, counter: str):
-    """{dispatch id: (kernel name, value summed over the counter's instances)}"""
+    """{dispatch id: (kernel name, value summed over the counter's instances, workgroups)}"""
     acc = {}
-    for did, name, cname, val in _counter_rows(d):
+    for did, name, cname, val, grid, wg in _counter_rows(d):
         if cname != counter:
             continue
-        n0, v0 = acc.get(did, (name, 0.0))
-        acc[did] = (n0, v0 + val)
+        n0, v0, g0 = acc.get(did, (name, 0.0, grid // max(1, wg)))
+        acc[did] = (n0, v0 + val, g0)
     return acc
+
+
+_CFG = re.compile(r"Cfg<(\d+), (\d+), \d, \d>")
+
+
+def items_of(name: str, wgs: int, block: int) -> float:
+    """Batch items (b x b x b complex products) in a dispatch of the product kernel."""
+    m = _CFG.search(name)
+    bm, bn = int(m.group(1)), int(m.group(2))
+    tiles = -(-block // bm) * -(-block // bn)
+    return wgs / tiles
 
 
 def gemm_source_hash(root: str) -> str:
@@ -81,13 +92,16 @@ def gemm_source_hash(root: str) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic(fetch_dir: str, write_dir: str, calib_mib: int, kernel: str, calib_kernel: str = "elementwise"):
+def traffic(fetch_dir: str, write_dir: str, calib_mib: int, kernel: str, block: int,
+            calib_kernel: str = "elementwise"):
+    """HBM bytes of the product kernel: per launch and per b x b x b item (so that a
+    launch of any batch can be priced as items x bytes_per_item)."""
     fetch = per_dispatch(fetch_dir, "FETCH_SIZE")
     write = per_dispatch(write_dir, "WRITE_SIZE")
     nbytes = calib_mib << 20
 
     def calib(table):
-        cands = [v for (n, v) in table.values() if calib_kernel in n]
+        cands = [v for (n, v, _) in table.values() if calib_kernel in n]
         if not cands:
             raise RuntimeError(f"no dispatch of a kernel matching '{calib_kernel}'")
         return max(cands) * 1024.0      # the largest one is the calibration copy; counters are in KiB
@@ -95,13 +109,18 @@ def traffic(fetch_dir: str, write_dir: str, calib_mib: int, kernel: str, calib_k
     f_cal, w_cal = calib(fetch), calib(write)
     f_scale, w_scale = nbytes / f_cal, nbytes / w_cal
     pat = re.compile(kernel)
-    fk = [v * 1024.0 * f_scale for (n, v) in fetch.values() if pat.search(n)]
-    wk = [v * 1024.0 * w_scale for (n, v) in write.values() if pat.search(n)]
+    fk = [(v * 1024.0 * f_scale, items_of(n, g, block)) for (n, v, g) in fetch.values() if pat.search(n)]
+    wk = [(v * 1024.0 * w_scale, items_of(n, g, block)) for (n, v, g) in write.values() if pat.search(n)]
     if not fk or not wk:
         raise RuntimeError(f"no dispatch matching '{kernel}'")
-    return {"kernel_pattern": kernel, "launches_fetch": len(fk), "launches_write": len(wk),
-            "fetch_bytes_per_launch": sum(fk) / len(fk), "write_bytes_per_launch": sum(wk) / len(wk),
-            "bytes_per_launch": sum(fk) / len(fk) + sum(wk) / len(wk),
+    f_item = sum(b for b, _ in fk) / sum(i for _, i in fk)
+    w_item = sum(b for b, _ in wk) / sum(i for _, i in wk)
+    return {"kernel_pattern": kernel, "block": block, "launches_fetch": len(fk), "launches_write": len(wk),
+            "fetch_bytes_per_launch": sum(b for b, _ in fk) / len(fk),
+            "write_bytes_per_launch": sum(b for b, _ in wk) / len(wk),
+            "bytes_per_launch": sum(b for b, _ in fk) / len(fk) + sum(b for b, _ in wk) / len(wk),
+            "items_per_launch": sum(i for _, i in fk) / len(fk),
+            "fetch_bytes_per_item": f_item, "write_bytes_per_item": w_item, "bytes_per_item": f_item + w_item,
             "calibration": {"bytes": nbytes, "fetch_counter_bytes": f_cal, "write_counter_bytes": w_cal,
                             "fetch_scale": f_scale, "write_scale": w_scale}}
 
@@ -114,11 +133,12 @@ if __name__ == "__main__":
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--calib-mib", type=int, default=1024)
     ap.add_argument("--kernel", default=r"zgemm_kernel<double, [01], [01], [^>]*Cfg<\d+, \d+, \d, \d>, 0(, (true|false))?>")
+    ap.add_argument("--block", type=int, default=512, help="block size b of the products")
     ap.add_argument("--json")
     ap.add_argument("--note", default="", help="what the counter runs measured (stored in the JSON)")
     a = ap.parse_args()
     if a.traffic:
-        rec = traffic(a.traffic[0], a.traffic[1], a.calib_mib, a.kernel)
+        rec = traffic(a.traffic[0], a.traffic[1], a.calib_mib, a.kernel, a.block)
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         rec["kernel_sha"] = gemm_source_hash(root)
         rec["note"] = a.note
