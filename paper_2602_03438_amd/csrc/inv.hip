@@ -109,8 +109,8 @@ __device__ __forceinline__ void csub_mul(v2d& x, v2d f, v2d p) {
 // holds two rows (t and t + NT) as register arrays that are only ever indexed
 // by compile-time constants: the step loop advances U columns per iteration
 // (the column being eliminated is x[s][KK]) and then rotates the rows by U, so
-// the code stays a short loop (straight-line steps over the whole panel would
-// overflow the instruction cache).  Before the loop iteration that starts at
+// the code stays a short loop (straight-line steps over the whole panel are
+// tens of KB of code).  Before the loop iteration that starts at
 // step jb, x[s][c] holds panel column (jb + c) mod NB; the pivot row in LDS
 // uses the same order.  The pivot row is published unscaled and every thread
 // forms 1 / pivot itself, so the only serial work between the two barriers is
