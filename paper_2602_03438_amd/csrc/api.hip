@@ -45,8 +45,8 @@ Opts get_opts(const negf_options* o) {
   if (o->batch > 0) r.batch = o->batch;
   if (o->inv_nb == 16 || o->inv_nb == 32) r.inv_nb = o->inv_nb;
   if (o->xcd_remap == 0 || o->xcd_remap == 1) r.xcd = o->xcd_remap;
-  if (o->gemm_tile >= GEMM_TILE_64 && o->gemm_tile <= GEMM_TILE_128x128) r.tile = o->gemm_tile;
-  if (o->gemm_tile_f32 >= GEMM_TILE_64 && o->gemm_tile_f32 <= GEMM_TILE_128x128) r.tile32 = o->gemm_tile_f32;
+  if (o->gemm_tile >= GEMM_TILE_64 && o->gemm_tile <= GEMM_TILE_LAST) r.tile = o->gemm_tile;
+  if (o->gemm_tile_f32 >= GEMM_TILE_64 && o->gemm_tile_f32 <= GEMM_TILE_LAST) r.tile32 = o->gemm_tile_f32;
   if (o->cmul == 3) r.gauss = 1;
   if (o->cmul == 4) r.gauss = 0;
   return r;
@@ -809,8 +809,8 @@ negf_status negf_plan_create(const negf_problem* problems, int32_t n_prob, negf_
   for (const Chunk& c : P->chunks) {
     Opts o = P->base;
     if (const negf_tuning* t = tuning_of(c.b)) {
-      if (t->gemm_tile >= GEMM_TILE_64 && t->gemm_tile <= GEMM_TILE_128x128) o.tile = t->gemm_tile;
-      if (t->gemm_tile_f32 >= GEMM_TILE_64 && t->gemm_tile_f32 <= GEMM_TILE_128x128) o.tile32 = t->gemm_tile_f32;
+      if (t->gemm_tile >= GEMM_TILE_64 && t->gemm_tile <= GEMM_TILE_LAST) o.tile = t->gemm_tile;
+      if (t->gemm_tile_f32 >= GEMM_TILE_64 && t->gemm_tile_f32 <= GEMM_TILE_LAST) o.tile32 = t->gemm_tile_f32;
       if (t->inv_nb == 16 || t->inv_nb == 32) o.inv_nb = t->inv_nb;
     }
     P->chunk_opts.push_back(o);

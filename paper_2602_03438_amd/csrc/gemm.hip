@@ -14,7 +14,7 @@
 // cancels).
 //
 // Work decomposition: one workgroup of WM x WN waves per BM x BN output tile
-// (64x64 with 2x2 waves, 128x64 and 128x128 with 4x2 waves); each wave owns
+// (64x64 with 2x2 or 4x2 waves, 128x64 and 128x128 with 4x2 waves); each wave owns
 // a (BM/WM) x (BN/WN) sub-tile of 16 x 16 MFMA tiles with separate real and
 // imaginary accumulators.  K advances in steps of 16 complex values through
 // two LDS stages: global loads for step k+1 are issued into registers before
@@ -291,6 +291,7 @@ __global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
 typedef Cfg<64, 64, 2, 2> Cfg64;
 typedef Cfg<128, 64, 4, 2> Cfg128x64;
 typedef Cfg<128, 128, 4, 2> Cfg128;
+typedef Cfg<64, 64, 4, 2> Cfg64w8;   // 8 waves of 16 x 32: fewer registers per wave, more waves per SIMD
 
 template <typename T, typename CF, bool GAUSS>
 hipError_t launch_cfg(const GemmDesc& d, KArgs ka, hipStream_t s) {
@@ -319,6 +320,7 @@ hipError_t launch_t(const GemmDesc& d, const KArgs& ka, int tile, hipStream_t s)
   if (GAUSS && tile == GEMM_TILE_128x128) tile = GEMM_TILE_128x64;
   switch (tile) {
     case GEMM_TILE_128x64: return launch_cfg<T, Cfg128x64, GAUSS>(d, ka, s);
+    case GEMM_TILE_64_8W: return launch_cfg<T, Cfg64w8, GAUSS>(d, ka, s);
     case GEMM_TILE_128x128:
       if constexpr (!GAUSS) return launch_cfg<T, Cfg128, GAUSS>(d, ka, s);
       [[fallthrough]];
