@@ -1,7 +1,7 @@
 """Tile and schedule tuner for the NEGF kernels on the local GPU.
 
 For a block size b it times, on the GPU, every candidate of
-  * the complex product kernel: output tile 64x64 (4 or 8 waves) / 128x64 / 128x128, for the
+  * the complex product kernel: output tile 64x64 (4 or 8 waves) / 128x64 (8 or 16) / 128x128, for the
     double (four and three real products per complex one) and the
     single-precision products, at the batch the sweeps use;
   * the block inversion: panel width 16 / 32;
@@ -23,7 +23,7 @@ from . import binding as nb
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ARCH = "gfx950"
-TILES = {1: "64x64", 2: "128x64", 3: "128x128", 4: "64x64/8w"}
+TILES = {1: "64x64", 2: "128x64", 3: "128x128", 4: "64x64/8w", 5: "128x64/16w"}
 DEFAULT = {"gemm_tile": 1, "gemm_tile_f32": 1, "inv_nb": 16}
 
 

@@ -14,7 +14,7 @@
 // cancels).
 //
 // Work decomposition: one workgroup of WM x WN waves per BM x BN output tile
-// (64x64 with 2x2 or 4x2 waves, 128x64 and 128x128 with 4x2 waves); each wave owns
+// (64x64 with 2x2 or 4x2 waves, 128x64 with 4x2 or 8x2, 128x128 with 4x2); each wave owns
 // a (BM/WM) x (BN/WN) sub-tile of 16 x 16 MFMA tiles with separate real and
 // imaginary accumulators.  K advances in steps of 16 complex values through
 // two LDS stages: global loads for step k+1 are issued into registers before
@@ -125,7 +125,7 @@ __device__ __forceinline__ void store_tile(typename Cx<T>::type* s, const double
 // TAG only separates the symbol of the inversion updates from the sweep
 // products in profiles; the code is the same.
 template <typename T, int OPA, int OPB, typename CF, int TAG = 0, bool GAUSS = false>
-__global__ void __launch_bounds__(CF::NT, 2) zgemm_kernel(KArgs a) {
+__global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(KArgs a) {
   typedef typename Cx<T>::type CT;
   typedef typename Acc<T>::type AT;
   constexpr int BM = CF::BM, BN = CF::BN, NT = CF::NT, FM = CF::FM, FN = CF::FN;
@@ -292,6 +292,7 @@ typedef Cfg<64, 64, 2, 2> Cfg64;
 typedef Cfg<128, 64, 4, 2> Cfg128x64;
 typedef Cfg<128, 128, 4, 2> Cfg128;
 typedef Cfg<64, 64, 4, 2> Cfg64w8;   // 8 waves of 16 x 32: fewer registers per wave, more waves per SIMD
+typedef Cfg<128, 64, 8, 2> Cfg128x64w16;   // 16 waves of 16 x 32
 
 template <typename T, typename CF, bool GAUSS>
 hipError_t launch_cfg(const GemmDesc& d, KArgs ka, hipStream_t s) {
@@ -321,6 +322,7 @@ hipError_t launch_t(const GemmDesc& d, const KArgs& ka, int tile, hipStream_t s)
   switch (tile) {
     case GEMM_TILE_128x64: return launch_cfg<T, Cfg128x64, GAUSS>(d, ka, s);
     case GEMM_TILE_64_8W: return launch_cfg<T, Cfg64w8, GAUSS>(d, ka, s);
+    case GEMM_TILE_128x64_16W: return launch_cfg<T, Cfg128x64w16, GAUSS>(d, ka, s);
     case GEMM_TILE_128x128:
       if constexpr (!GAUSS) return launch_cfg<T, Cfg128, GAUSS>(d, ka, s);
       [[fallthrough]];

@@ -7,7 +7,7 @@ namespace negf {
 enum Op { OP_N = 0, OP_C = 1 };          // op(X) = X or X^H
 // Output tile shapes of the complex product kernel (see gemm.hip)
 enum { GEMM_TILE_DEFAULT = 0, GEMM_TILE_64 = 1, GEMM_TILE_128x64 = 2, GEMM_TILE_128x128 = 3, GEMM_TILE_64_8W = 4,
-       GEMM_TILE_LAST = GEMM_TILE_64_8W };
+       GEMM_TILE_128x64_16W = 5, GEMM_TILE_LAST = GEMM_TILE_128x64_16W };
 enum Prec { PREC_F64 = 0, PREC_F32 = 1 };  // arithmetic of the product
 
 // A batch of b x b (or M x K ...) complex matrices: item p starts at p * stride.

@@ -43,7 +43,7 @@ def test_zgemm_fp64_parity(nb, opa, opb, M, N, K, prec):
     assert err < 1e-14 * max(1, np.sqrt(K)), err
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("opa,opb", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
 @pytest.mark.parametrize("M,N,K", [(200, 130, 77), (128, 256, 64)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
