@@ -38,8 +38,7 @@ struct PanelArgs {
   int n, j0, nbw;
   int c0, c1;               // the current super-panel: columns the interchanges and U cover
   double2* A; long lda, sA;
-  double2* W; long sW;      // W_p: n x NB row-major
-  double2* U; long sU;      // U_p: NB x n row-major (columns c0..c1 written)
+  double2* U; long sU;      // U_p: NB x n row-major (columns of [c0, c1) outside the panel written)
   int* sigma;               // sigma_p[i]: original row now at position i
   int* tau; long sS;        // tau_p[i]: row, at the start of the super-panel, now at position i
   int* info; int info_mod;
@@ -220,14 +219,13 @@ struct PanelGroup<NB, NT, U, U> {
 
 // Panel kernel: one workgroup of NT threads per matrix, two rows per thread
 // (n <= 2 NT).  The panel is read coalesced (consecutive lanes along a row)
-// and handed to its row owners through LDS in chunks of STAGE_ROWS rows; W is
-// written transposed and conjugated (W^H, nb x n), again coalesced.
+// and handed to its row owners through LDS in chunks of STAGE_ROWS rows; the
+// result W goes back into the panel columns the same way.
 template <int NB, int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) gj_panel_kernel(PanelArgs a) {
   const int p = blockIdx.x;
   if (a.active && a.active[p] == 0) return;
   double2* __restrict__ A = a.A + (long)p * a.sA;
-  v2d* __restrict__ Wt = reinterpret_cast<v2d*>(a.W + (long)p * a.sW);
   double2* __restrict__ U = a.U + (long)p * a.sU;
   int* __restrict__ sigma = a.sigma + (long)p * a.sS;
   int* __restrict__ tau = a.tau + (long)p * a.sS;
@@ -302,22 +300,30 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
     rot += SG;
   }
 
-  // --- W^H (nb x n): after the rotations x[s][c] holds panel column (c + rot) mod NB
+  // --- the panel result W = [A_JJ^{-1}; -A_RJ A_JJ^{-1}] back into A's panel columns,
+  // through LDS in chunks so that the stores are coalesced; after the rotations
+  // x[s][c] holds panel column (c + rot) mod NB
+  // (rows of slot 0 first, then slot 1: each loop names its register row statically)
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int r = t + s * NT;
-    if (r < n) {
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll CH_UNROLL
+    for (int k = 0; k < CH / 2; ++k) {
+      const int first = (half * (CH / 2) + k) * STAGE_ROWS;
+      const int tb = k * STAGE_ROWS;   // first % NT
+      const bool mine = t >= tb && t < tb + STAGE_ROWS;
+      if (mine) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const v2d v = x[s][c];
-        Wt[(long)((c + rot) % NB) * n + r] = v2d{v.x, -v.y};
+        for (int c = 0; c < NB; ++c) L.buf[(t - tb) * (NB + 1) + (c + rot) % NB] = x[half][c];
       }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int idx = e * NT + t, rr = first + idx / NB, cc = idx % NB;
+        if (rr < n && cc < nbw)
+          reinterpret_cast<v2d*>(A)[(long)rr * lda + j0 + cc] = L.buf[(idx / NB) * (NB + 1) + cc];
+      }
+      __syncthreads();
     }
-  }
-  // clear the panel columns of A (consecutive lanes along a row)
-  for (int idx = t; idx < n * nbw; idx += NT) {
-    const int rr = idx / nbw, cc = idx % nbw;
-    A[(long)rr * lda + j0 + cc] = make_double2(0.0, 0.0);
   }
 
   // The nbw interchanges, composed into cont[], act on the rows D = panel rows
@@ -335,7 +341,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
       const int s = e / cnt, c = c0 + e % cnt;
       const bool in = e < tot, outside = c < j0 || c >= jend;
       const int qr = in ? L.spiv[s] : 0;
-      u[g] = (in && outside) ? Av[(long)L.cont[j0 + s] * lda + c] : v2d{(in && c - j0 == s) ? 1.0 : 0.0, 0.0};
+      u[g] = (in && outside) ? Av[(long)L.cont[j0 + s] * lda + c] : v2d{0.0, 0.0};
       q[g] = (in && outside && qr >= jend) ? Av[(long)L.cont[qr] * lda + c] : v2d{0.0, 0.0};
     }
 #pragma unroll
@@ -343,8 +349,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
       const int e = base + g * NT + t;
       if (e >= tot) continue;
       const int s = e / cnt, c = c0 + e % cnt;
+      if (c >= j0 && c < jend) continue;
       reinterpret_cast<v2d*>(U)[(long)s * n + c] = u[g];
-      if (L.spiv[s] >= jend && (c < j0 || c >= jend)) L.buf[s * NBO + (c - c0)] = q[g];
+      if (L.spiv[s] >= jend) L.buf[s * NBO + (c - c0)] = q[g];
     }
   }
   // row orders: new entry of a row d of D = old entry of row cont[d]
@@ -401,19 +408,17 @@ __global__ void __launch_bounds__(256) gj_gather_kernel(int n, const double2* M,
 }
 
 // Outer step of the two-level blocking for the super-panel J = [J0, J0+mo),
-// one workgroup per (matrix, OUTER_COLS columns).  Blocks inside J move their
-// columns into Wo (n x mo) and clear them, and write the identity into Uo.
-// Blocks outside J apply the super-panel's interchanges (the content map tau)
-// to their columns: the pivot rows J0..J0+mo-1 go to Uo (mo x n) and are
-// cleared, the rows below J that took part receive their new contents.  All
-// reads of a block precede its writes (a barrier between).
+// one workgroup per (matrix, OUTER_COLS columns) outside J: the super-panel's
+// interchanges (the content map tau) are applied to those columns, the pivot
+// rows J0..J0+mo-1 go to Uo (mo x n) and are cleared, and the rows below J
+// that took part receive their new contents.  All reads of a block precede its
+// writes (a barrier between).  The columns of J already hold their final W.
 constexpr int OUTER_COLS = 16;
 constexpr int OUTER_THREADS = 256;
 
 __global__ void __launch_bounds__(OUTER_THREADS) gj_outer_kernel(int n, int J0, int mo, double2* A, long lda,
-                                                                 long sA, double2* Wo, long sW, double2* Uo,
-                                                                 long sU, const int* tau, long sT,
-                                                                 const int* active) {
+                                                                 long sA, double2* Uo, long sU, const int* tau,
+                                                                 long sT, const int* active) {
   const int p = blockIdx.y;
   if (active && active[p] == 0) return;
   double2* __restrict__ Ap = A + (long)p * sA;
@@ -421,21 +426,7 @@ __global__ void __launch_bounds__(OUTER_THREADS) gj_outer_kernel(int n, int J0, 
   const int cb = blockIdx.x * OUTER_COLS;
   const int w = min(OUTER_COLS, n - cb);
   const int t = threadIdx.x;
-  if (cb >= J0 && cb < J0 + mo) {
-    double2* __restrict__ Wp = Wo + (long)p * sW;
-    for (int e = t; e < n * OUTER_COLS; e += OUTER_THREADS) {
-      const int rr = e / OUTER_COLS, cc = e % OUTER_COLS;
-      if (cc >= w) continue;
-      const long o = (long)rr * lda + cb + cc;
-      Wp[(long)rr * mo + (cb - J0 + cc)] = Ap[o];
-      Ap[o] = make_double2(0.0, 0.0);
-    }
-    for (int e = t; e < mo * OUTER_COLS; e += OUTER_THREADS) {
-      const int k = e / OUTER_COLS, cc = e % OUTER_COLS;
-      if (cc < w) U[(long)k * n + cb + cc] = make_double2(k == cb - J0 + cc ? 1.0 : 0.0, 0.0);
-    }
-    return;
-  }
+  if (cb >= J0 && cb < J0 + mo) return;
   __shared__ int rows[2 * NBO];
   __shared__ int srcs[2 * NBO];
   __shared__ int nq;
@@ -485,15 +476,13 @@ __global__ void __launch_bounds__(OUTER_THREADS) gj_outer_kernel(int n, int J0, 
 
 struct ScratchLayout {
   size_t per_al;
-  size_t off_W, off_U, off_Wo, off_Uo, off_sigma, off_tau;
+  size_t off_U, off_Uo, off_sigma, off_tau;
 };
 
 ScratchLayout layout(int n) {
   ScratchLayout L{};
   size_t o = 0;
-  L.off_W = o;  o += (size_t)n * NB_MAX * sizeof(double2);
   L.off_U = o;  o += (size_t)NB_MAX * n * sizeof(double2);
-  L.off_Wo = o; o += (size_t)n * NBO * sizeof(double2);
   L.off_Uo = o; o += (size_t)NBO * n * sizeof(double2);
   L.off_sigma = o; o += (size_t)n * sizeof(int);
   L.off_tau = o;   o += (size_t)n * sizeof(int);
@@ -501,24 +490,28 @@ ScratchLayout layout(int n) {
   return L;
 }
 
-GemmDesc update_desc(Op opw, int M, int N, int K, const double2* Wm, long ldw, long sW, const double2* Um, long ldu,
-                     long sU, double2* C, long ldc, long sC, int batch, const int* active, int gauss) {
+// Columns [c_lo, c_hi) of every matrix: A[:, c] += A[:, jb:jb+K] U[:, c], the
+// first operand being the block's result W read in place (those columns are
+// not written by this product).
+hipError_t update_cols(const InvDesc& d, int n, int jb, int K, const double2* U, long sU, int c_lo, int c_hi,
+                       hipStream_t s) {
+  if (c_hi <= c_lo) return hipSuccess;
   GemmDesc g{};
-  g.M = M; g.N = N; g.K = K; g.batch = batch;
-  g.opA = opw; g.opB = OP_N;
-  g.A = MatRef{Wm, ldw, sW};
-  g.B = MatRef{Um, ldu, sU};
+  g.M = n; g.N = c_hi - c_lo; g.K = K; g.batch = d.batch;
+  g.opA = OP_N; g.opB = OP_N;
+  g.A = MatRef{d.M + jb, d.ldm, d.sM};
+  g.B = MatRef{U + c_lo, n, sU};
   g.alpha = make_double2(1.0, 0.0);
   g.beta = make_double2(1.0, 0.0);
-  g.Cin = MatRef{C, ldc, sC};
-  g.C = MatOut{C, ldc, sC};
-  g.active = active;
+  g.Cin = MatRef{d.M + c_lo, d.ldm, d.sM};
+  g.C = MatOut{d.M + c_lo, d.ldm, d.sM};
+  g.active = d.active;
   g.prec = PREC_F64;
   g.xcd_remap = 1;
   g.tile = GEMM_TILE_64;
   g.prof_class = KC_INV_GEMM;
-  g.gauss = gauss;
-  return g;
+  g.gauss = d.gauss;
+  return launch_gemm(g, s);
 }
 
 }  // namespace
@@ -534,9 +527,7 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
   const long sItem = (long)(SL.per_al / sizeof(double2));   // per_al is a multiple of 256 bytes
   const long sI = (long)(SL.per_al / sizeof(int));
   char* base = (char*)d.scratch;
-  double2* W = (double2*)(base + SL.off_W);
   double2* U = (double2*)(base + SL.off_U);
-  double2* Wo = (double2*)(base + SL.off_Wo);
   double2* Uo = (double2*)(base + SL.off_Uo);
   int* sigma = (int*)(base + SL.off_sigma);
   int* tau = (int*)(base + SL.off_tau);
@@ -547,8 +538,8 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
     const int mo = (n - J0 < outer) ? n - J0 : outer;
     for (int j0 = J0; j0 < J0 + mo; j0 += NB) {
       const int nbw = (J0 + mo - j0 < NB) ? J0 + mo - j0 : NB;
-      PanelArgs pa{n, j0, nbw, J0, J0 + mo, d.M, d.ldm, d.sM, W, sItem, U, sItem, sigma, tau, sI,
-                   d.info, d.info_mod, d.active};
+      PanelArgs pa{n, j0, nbw, J0, J0 + mo, d.M, d.ldm, d.sM, U, sItem, sigma, tau, sI, d.info, d.info_mod,
+                   d.active};
       prof_begin(KC_INV_PANEL, s);
       // two rows per thread: 256 threads up to n = 512, 512 up to n = MAX_ROWS
       if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 256>), dim3(d.batch), dim3(256), 0, s, pa);
@@ -556,21 +547,20 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
       else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS / 2>), dim3(d.batch), dim3(MAX_ROWS / 2), 0, s, pa);
       prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      // A[:, J] += W U[:, J] with W held as W^H (nb x n)
-      GemmDesc g = update_desc(OP_C, n, mo, nbw, W, n, sItem, U + J0, n, sItem, d.M + J0, d.ldm, d.sM, d.batch,
-                               d.active, d.gauss);
-      if ((e = launch_gemm(g, s)) != hipSuccess) return e;
+      // the other columns of the super-panel: A[:, c] += W U[:, c], W read in place from the panel columns
+      if ((e = update_cols(d, n, j0, nbw, U, sItem, J0, j0, s)) != hipSuccess) return e;
+      if ((e = update_cols(d, n, j0, nbw, U, sItem, j0 + nbw, J0 + mo, s)) != hipSuccess) return e;
     }
     if (mo == n) break;   // one level: the super-panel was the whole matrix
-    // outer step: interchanges and pivot rows of the other columns, then A += Wo Uo
+    // outer step: interchanges and pivot rows of the other columns, then A[:, c] += W Uo[:, c]
+    // for the columns outside J, W read in place from the columns of J
     prof_begin(KC_INV_SWAP, s);
     hipLaunchKernelGGL(gj_outer_kernel, dim3((n + OUTER_COLS - 1) / OUTER_COLS, d.batch), dim3(OUTER_THREADS), 0, s,
-                       n, J0, mo, d.M, d.ldm, d.sM, Wo, sItem, Uo, sItem, tau, sI, d.active);
+                       n, J0, mo, d.M, d.ldm, d.sM, Uo, sItem, tau, sI, d.active);
     prof_end(KC_INV_SWAP, s, 0, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    GemmDesc g =
-        update_desc(OP_N, n, n, mo, Wo, mo, sItem, Uo, n, sItem, d.M, d.ldm, d.sM, d.batch, d.active, d.gauss);
-    if ((e = launch_gemm(g, s)) != hipSuccess) return e;
+    if ((e = update_cols(d, n, J0, mo, Uo, sItem, 0, J0, s)) != hipSuccess) return e;
+    if ((e = update_cols(d, n, J0, mo, Uo, sItem, J0 + mo, n, s)) != hipSuccess) return e;
   }
   prof_begin(KC_INV_PERM, s);
   hipLaunchKernelGGL(gj_gather_kernel, dim3((n + GATHER_ROWS - 1) / GATHER_ROWS, d.batch), dim3(256), 0, s, n, d.M,
