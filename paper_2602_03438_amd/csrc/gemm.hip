@@ -78,6 +78,7 @@ struct KArgs {
   double2 alpha, beta;
   const int* active;
   int tiles_m, tiles_n, xcd_remap;
+  int upper;   // skip tiles that lie entirely below the diagonal
 };
 
 template <int BM_, int BN_, int WM_, int WN_>
@@ -143,6 +144,7 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
   if (a.active && a.active[p] == 0) return;
   const int tm = tid / a.tiles_n, tn = tid - tm * a.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
+  if (a.upper && n0 + BN <= m0) return;
 
   const double2* __restrict__ Ap = a.A + (long)p * a.sA;
   const double2* __restrict__ Bp = a.B + (long)p * a.sB;
@@ -330,6 +332,59 @@ hipError_t launch_t(const GemmDesc& d, const KArgs& ka, int tile, hipStream_t s)
   }
 }
 
+// Strict lower triangle of each n x n item from its upper triangle,
+// C[r][c] = -conj(C[c][r]) for r > c: 32 x 32 tiles on or below the diagonal,
+// each transposed through LDS so that reads and writes are coalesced.
+constexpr int MIR = 32;
+
+__global__ void __launch_bounds__(256) skew_mirror_kernel(int n, double2* C, long ldc, long sC, const int* active) {
+  const int p = blockIdx.z;
+  if (active && active[p] == 0) return;
+  const int tr = blockIdx.y, tc = blockIdx.x;   // destination tile (rows tr, columns tc)
+  if (tr < tc) return;
+  __shared__ double2 S[MIR][MIR + 1];
+  double2* Cp = C + (long)p * sC;
+  const int r0 = tr * MIR, c0 = tc * MIR;
+  // source: rows c0.., columns r0.. (upper side)
+  for (int e = threadIdx.x; e < MIR * MIR; e += blockDim.x) {
+    const int i = e / MIR, j = e % MIR;
+    const int sr = c0 + i, sc = r0 + j;
+    if (sr < n && sc < n) S[i][j] = Cp[(long)sr * ldc + sc];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < MIR * MIR; e += blockDim.x) {
+    const int i = e / MIR, j = e % MIR;
+    const int r = r0 + i, c = c0 + j;
+    if (r < n && c < n && r > c) {
+      const double2 v = S[j][i];
+      Cp[(long)r * ldc + c] = make_double2(-v.x, v.y);
+    }
+  }
+}
+
+// Fraction of the output tiles a launch computes (all, or those touching the upper triangle).
+template <typename CF>
+double computed_fraction(int M, int N, bool upper) {
+  const int tm = (M + CF::BM - 1) / CF::BM, tn = (N + CF::BN - 1) / CF::BN;
+  if (!upper) return 1.0;
+  long cnt = 0;
+  for (int i = 0; i < tm; ++i)
+    for (int j = 0; j < tn; ++j)
+      if (j * CF::BN + CF::BN > i * CF::BM) ++cnt;
+  return (double)cnt / ((double)tm * tn);
+}
+
+double tile_fraction(int tile, bool gauss, int M, int N, bool upper) {
+  if (gauss && tile == GEMM_TILE_128x128) tile = GEMM_TILE_128x64;
+  switch (tile) {
+    case GEMM_TILE_128x64: return computed_fraction<Cfg128x64>(M, N, upper);
+    case GEMM_TILE_128x128: return computed_fraction<Cfg128>(M, N, upper);
+    case GEMM_TILE_64_8W: return computed_fraction<Cfg64w8>(M, N, upper);
+    case GEMM_TILE_128x64_16W: return computed_fraction<Cfg128x64w16>(M, N, upper);
+    default: return computed_fraction<Cfg64>(M, N, upper);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
@@ -344,15 +399,25 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
   ka.active = d.active;
   ka.xcd_remap = d.xcd_remap;
   ka.tiles_m = ka.tiles_n = 0;
+  if (d.skew && d.M != d.N) return hipErrorInvalidValue;
+  ka.upper = d.skew ? 1 : 0;
   int tile = d.tile;
   if (tile == GEMM_TILE_DEFAULT) tile = GEMM_TILE_64;
+  const bool gauss = d.prec != PREC_F32 && d.gauss;
+  const double frac = tile_fraction(tile, gauss, d.M, d.N, d.skew != 0);
   const int cls = d.prof_class >= 0 ? d.prof_class : (d.prec == PREC_F32 ? KC_GEMM32 : KC_GEMM64);
   prof_begin(cls, s);
   hipError_t e = d.prec == PREC_F32 ? launch_t<float, false>(d, ka, tile, s)
-                 : d.gauss          ? launch_t<double, true>(d, ka, tile, s)
+                 : gauss            ? launch_t<double, true>(d, ka, tile, s)
                                     : launch_t<double, false>(d, ka, tile, s);
-  prof_end(cls, s, 8.0 * d.M * (double)d.N * d.K * d.batch,
+  prof_end(cls, s, frac * 8.0 * d.M * (double)d.N * d.K * d.batch,
            16.0 * d.batch * ((double)d.M * d.K + (double)d.K * d.N + 2.0 * d.M * d.N));
+  if (e == hipSuccess && d.skew) {
+    const int nt = (d.M + MIR - 1) / MIR;
+    hipLaunchKernelGGL(skew_mirror_kernel, dim3(nt, nt, d.batch), dim3(256), 0, s, d.M, d.C.p, d.C.ld, d.C.stride,
+                       d.active);
+    e = hipGetLastError();
+  }
   return e;
 }
 

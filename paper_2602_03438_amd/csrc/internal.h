@@ -36,6 +36,9 @@ struct GemmDesc {
   int xcd_remap;       // group the tiles of one batch item on one XCD
   int prof_class;      // -1: by precision
   int gauss;           // double products with three real products per complex one
+  int skew;            // the result is anti-Hermitian (M == N): only tiles touching the upper
+                       // triangle are computed, the strict lower triangle is then set to -conj
+                       // of the upper one
 };
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
 
