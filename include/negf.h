@@ -216,7 +216,9 @@ void negf_plan_destroy(negf_plan* plan);
  * outputs, op = 'N' or 'C' (conjugate transpose).  lda/ldb/ldc are row
  * strides, sa/sb/sc batch strides, all in complex elements.  alpha, beta:
  * host arrays of 2 doubles.  prec: 0 double, 1 single products, 2 double
- * with three real products per complex product (Gauss's method).
+ * with three real products per complex product (Gauss's method); adding 4
+ * declares the result anti-Hermitian (M == N): only its upper triangle is
+ * computed and the strict lower triangle is set to -conj of the upper one.
  * tile: 0 default, 1 = 64x64, 2 = 128x64, 3 = 128x128, 4 = 64x64 (8 waves),
  * 5 = 128x64 (16 waves) output tiles.
  * Returns NEGF_EINVAL for bad sizes. */

@@ -1048,9 +1048,12 @@ negf_status negf_zgemm_batched(char opa, char opb, int32_t M, int32_t N, int32_t
   g.beta = make_double2(beta[0], beta[1]);
   g.Cin = MatRef{(const double2*)C, (long)ldc, (long)sc};
   g.C = MatOut{(double2*)C, (long)ldc, (long)sc};
-  if (prec < 0 || prec > 2) return NEGF_EINVAL;
+  const int skew = prec & 4;   // the product is anti-Hermitian: upper triangle computed, lower mirrored
+  prec &= 3;
+  if (prec > 2 || (skew && M != N)) return NEGF_EINVAL;
   g.prec = prec == 1 ? PREC_F32 : PREC_F64;
   g.gauss = prec == 2;
+  g.skew = skew ? 1 : 0;
   g.tile = tile;
   g.xcd_remap = 1;
   g.prof_class = -1;

@@ -72,6 +72,31 @@ def test_zgemm_fp64_b512_batched(nb, prec):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-14
 
 
+@pytest.mark.parametrize("n", [8, 72, 130, 512])
+@pytest.mark.parametrize("prec", [0, 2, 1])
+@pytest.mark.parametrize("tile", [1, 2, 4])
+def test_zgemm_skew_product(nb, n, prec, tile):
+    """A X A^H + S with X and S anti-Hermitian, computed as an anti-Hermitian
+    product (prec + 4): upper triangle computed, lower mirrored."""
+    import torch
+    r = np.random.Generator(np.random.PCG64(n + 7 * prec + tile))
+    A = _rand(r, (3, n, n))
+    X = _rand(r, (3, n, n))
+    X = X - np.conj(np.swapaxes(X, -1, -2))
+    S = _rand(r, (3, n, n))
+    S = S - np.conj(np.swapaxes(S, -1, -2))
+    AX = A @ X
+    ref = AX @ np.conj(np.swapaxes(A, -1, -2)) + S
+    Ct = torch.from_numpy(S.copy()).cuda()
+    nb.zgemm(torch.from_numpy(AX).cuda(), torch.from_numpy(A).cuda(), Ct, "N", "C", 1.0, 1.0, prec=prec + 4,
+             tile=tile)
+    got = Ct.cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < (1e-5 if prec == 1 else 1e-13), err
+    assert np.array_equal(got, -np.conj(np.swapaxes(got, -1, -2))) or n == 0 or \
+        np.array_equal(np.tril(got, -1), np.tril(-np.conj(np.swapaxes(got, -1, -2)), -1))
+
+
 def test_zgemm_fp32_products(nb):
     import torch
     r = np.random.Generator(np.random.PCG64(6))
