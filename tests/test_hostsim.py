@@ -105,10 +105,7 @@ def test_hostsim_lesser_greater_matches_oracle(sim, scatter):
         got = _unpack(out[name], [p], diag)[0]
         for k, e in enumerate(E):
             ref = getattr(orgf.solve_point(dev, e, 1e-8, 0.1, -0.1, 0.025, greater=True), ref_name)
-            # the plain-FP64 bar; the library forms the anti-Hermitian lesser/greater
-            # products from their upper triangles, a rounding path that differs from
-            # the oracle's by up to ~5e-11 at the in-gap-adjacent point E = 0
-            assert rel(got[k], ref) < 1e-10, (name, k)
+            assert rel(got[k], ref) < 1e-11, (name, k)
 
 
 @pytest.mark.parametrize("prec,tol", [(1, 1e-6), (2, 1e-2)])
