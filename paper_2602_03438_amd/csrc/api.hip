@@ -403,8 +403,7 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
   // The two leads iterate on two streams (the primary and its companion), so that
   // one lead's latency-bound inversion panels overlap the other's products.  Each
   // part works on its own pairs; buffer roles are renamed identically for both.
-  // Plans (fixed iteration count, possibly captured into a graph) keep one stream.
-  const int nparts = (nsides == 2 && !cx.fixed_sr) ? 2 : 1;
+  const int nparts = (nsides == 2) ? 2 : 1;
   const int per = np / nparts;
   Ctx cxp[2] = {cx, cx};
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
