@@ -156,7 +156,7 @@ LeadWs carve_leads(Carver& cv, int b, int npairs) {
   w.a2 = cv.take<double>(npairs); w.c2 = cv.take<double>(npairs); w.d2 = cv.take<double>(npairs);
   w.r2 = cv.take<double>(npairs); w.m2 = cv.take<double>(npairs); w.g2 = cv.take<double>(npairs);
   w.part = cv.take<double>((size_t)npairs * FROB_SPLIT);
-  w.active = cv.take<int>(npairs); w.iters = cv.take<int>(npairs); w.n_active = cv.take<int>(2);
+  w.active = cv.take<int>(npairs); w.iters = cv.take<int>(npairs); w.n_active = cv.take<int>(1);
   w.accepted = cv.take<int>(npairs);
   w.inv_scratch = cv.take<char>(inverse_scratch_bytes(b, npairs));
   return w;
@@ -400,72 +400,40 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
   cx.lincomb(b, np, ONE, w.beta.p, bb, ZERO, nullptr, 0, ZERO, w.c.p, bb);
   Blocks a = w.a, c = w.c, t1 = w.t1, t2 = w.t2;
   int hmax = 0;
-  // The two leads iterate on two streams (the primary and its companion), so that
-  // one lead's latency-bound inversion panels overlap the other's products.  Each
-  // part works on its own pairs; buffer roles are renamed identically for both.
-  const int nparts = (nsides == 2) ? 2 : 1;
-  const int per = np / nparts;
-  Ctx cxp[2] = {cx, cx};
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  if (nparts == 2) {
-    cx.chk(rt_companion(s, &cxp[1].s, &ev_fork, &ev_join));
-    if (!cx.ok()) return;
-    cx.chk(rt_record_wait(ev_fork, s, cxp[1].s));
-  }
-  const size_t inv_item = inverse_scratch_bytes(b, 1);
   for (int it = 1; it <= cx.o.max_iter && cx.ok(); ++it) {
-    for (int k = 0; k < nparts; ++k) {
-      Ctx& c2 = cxp[k];
-      const long q = (long)k * per;
-      const int* act = w.active + q;
-      hipStream_t sk = c2.s;
-      Blocks A_{a.at(q), a.stride}, Cc{c.at(q), c.stride}, T1{t1.at(q), t1.stride}, T2{t2.at(q), t2.stride};
-      Blocks AG{w.ag.at(q), w.ag.stride}, CG{w.cg.at(q), w.cg.stride};
-      double2* eps = w.eps.at(q);
-      double2* eps_s = w.eps_s.at(q);
-      // g = eps^{-1}  (eps is kept: invert a copy); AG temporarily holds g
-      c2.lincomb(b, per, ONE, eps, bb, ZERO, nullptr, 0, ZERO, T1.p, bb, act);
-      c2.inverse(b, per, T1.p, bb, AG.p, bb, (char*)w.inv_scratch + q * inv_item, nullptr, 0, act);
-      std::swap(AG, CG);   // CG := g ; AG free
-      const Blocks g = CG;
-      // AG = a g, T2 = c g
-      c2.gemm(PREC_F64, OP_N, OP_N, b, per, ONE, A_.p, bb, g.p, bb, ZERO, nullptr, 0, AG.p, bb, act);
-      c2.gemm(PREC_F64, OP_N, OP_N, b, per, ONE, Cc.p, bb, g.p, bb, ZERO, nullptr, 0, T2.p, bb, act);
-      // T1 = AG c ; eps_s -= T1 ; eps -= T1
-      c2.gemm(PREC_F64, OP_N, OP_N, b, per, ONE, AG.p, bb, Cc.p, bb, ZERO, nullptr, 0, T1.p, bb, act);
-      c2.chk(launch_sub2(b, per, T1.p, bb, eps_s, bb, eps, bb, act, sk));
-      // eps -= (c g) a
-      c2.gemm(PREC_F64, OP_N, OP_N, b, per, MONE, T2.p, bb, A_.p, bb, ONE, eps, bb, eps, bb, act);
-      // a' = (a g) a -> T1 ; c' = (c g) c -> the g buffer (g no longer needed)
-      c2.gemm(PREC_F64, OP_N, OP_N, b, per, ONE, AG.p, bb, A_.p, bb, ZERO, nullptr, 0, T1.p, bb, act);
-      c2.gemm(PREC_F64, OP_N, OP_N, b, per, ONE, T2.p, bb, Cc.p, bb, ZERO, nullptr, 0, CG.p, bb, act);
-      // norms of a' (in T1) and c' (in CG) and the convergence flags of this part
-      c2.chk(launch_frob2(b, per, T1.p, bb, 0.0, act, w.part + q * FROB_SPLIT, w.a2 + q, sk));
-      c2.chk(launch_frob2(b, per, CG.p, bb, 0.0, act, w.part + q * FROB_SPLIT, w.c2 + q, sk));
-      c2.chk(launch_sr_check(per, w.a2 + q, w.c2 + q, w.d2 + q, cx.o.tol, it, w.active + q, w.iters + q,
-                             w.n_active + k, sk));
-    }
-    // the same renaming on the whole arrays: g moved to cg, then a <- t1, c <- cg (the old ag)
-    std::swap(w.ag, w.cg);
+    const int* act = w.active;
+    // g = eps^{-1}  (eps is kept: invert a copy)
+    cx.lincomb(b, np, ONE, w.eps.p, bb, ZERO, nullptr, 0, ZERO, t1.p, bb, act);
+    cx.inverse(b, np, t1.p, bb, w.ag.p, bb, w.inv_scratch, nullptr, 0, act);   // ag temporarily holds g
+    std::swap(w.ag, w.cg);   // cg := g ; ag free
+    const Blocks g = w.cg;
+    // ag = a g, t2 = c g
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, a.p, bb, g.p, bb, ZERO, nullptr, 0, w.ag.p, bb, act);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, c.p, bb, g.p, bb, ZERO, nullptr, 0, t2.p, bb, act);
+    // t1 = ag c ; eps_s -= t1 ; eps -= t1
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.ag.p, bb, c.p, bb, ZERO, nullptr, 0, t1.p, bb, act);
+    cx.chk(launch_sub2(b, np, t1.p, bb, w.eps_s.p, bb, w.eps.p, bb, act, s));
+    // eps -= (c g) a
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, t2.p, bb, a.p, bb, ONE, w.eps.p, bb, w.eps.p, bb, act);
+    // a' = (a g) a -> t1 ; c' = (c g) c -> g buffer (g no longer needed)
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.ag.p, bb, a.p, bb, ZERO, nullptr, 0, t1.p, bb, act);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, t2.p, bb, c.p, bb, ZERO, nullptr, 0, w.cg.p, bb, act);
     std::swap(a, t1);
     {
       Blocks tmp = c;
       c = w.cg;
       w.cg = tmp;
     }
-    for (int k = 0; k < nparts; ++k) cx.chk(cxp[k].err);
+    cx.chk(launch_frob2(b, np, a.p, bb, 0.0, w.active, w.part, w.a2, s));
+    cx.chk(launch_frob2(b, np, c.p, bb, 0.0, w.active, w.part, w.c2, s));
+    cx.chk(launch_sr_check(np, w.a2, w.c2, w.d2, cx.o.tol, it, w.active, w.iters, w.n_active, s));
     hmax = it;
-    if (!cx.fixed_sr && cx.ok()) {
-      int left = 0;
-      for (int k = 0; k < nparts; ++k) {
-        int host_active = 0;
-        cx.chk(rt_read_int(&host_active, w.n_active + k, cxp[k].s));
-        left += host_active;
-      }
-      if (left == 0) break;
+    if (!cx.fixed_sr) {
+      int host_active = 0;
+      cx.chk(rt_read_int(&host_active, w.n_active, s));
+      if (host_active == 0) break;
     }
   }
-  if (nparts == 2) cx.chk(rt_record_wait(ev_join, cxp[1].s, s));
   if (iters_host_max) *iters_host_max = hmax;
   if (!cx.ok()) return;
   // --- g_s = eps_s^{-1} (pairs that ran the decimation); seeded-accepted pairs keep g0

@@ -137,10 +137,6 @@ hipError_t rt_stream_destroy(hipStream_t s);
 hipError_t rt_event_create(hipEvent_t* e);
 hipError_t rt_event_destroy(hipEvent_t e);
 hipError_t rt_record_wait(hipEvent_t e, hipStream_t from, hipStream_t to);   // `to` waits for `from`
-// A second stream paired with `primary` (created on first use, one per primary stream
-// and device, kept until the process ends) and two events for forking work onto it and
-// joining it back.
-hipError_t rt_companion(hipStream_t primary, hipStream_t* comp, hipEvent_t* fork, hipEvent_t* join);
 hipError_t rt_capture_begin(hipStream_t s);
 hipError_t rt_capture_end(hipStream_t s, void** exec);
 hipError_t rt_graph_launch(void* exec, hipStream_t s);

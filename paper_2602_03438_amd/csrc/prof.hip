@@ -78,32 +78,6 @@ hipError_t rt_stream_destroy(hipStream_t s) { return hipStreamDestroy(s); }
 hipError_t rt_event_create(hipEvent_t* e) { return hipEventCreateWithFlags(e, hipEventDisableTiming); }
 hipError_t rt_event_destroy(hipEvent_t e) { return hipEventDestroy(e); }
 
-hipError_t rt_companion(hipStream_t primary, hipStream_t* comp, hipEvent_t* fork, hipEvent_t* join) {
-  struct Entry {
-    int dev;
-    hipStream_t primary, comp;
-    hipEvent_t fork, join;
-  };
-  static std::mutex mu;
-  static std::vector<Entry> table;
-  int dev = 0;
-  hipError_t r = hipGetDevice(&dev);
-  if (r != hipSuccess) return r;
-  std::lock_guard<std::mutex> lk(mu);
-  for (const Entry& e : table)
-    if (e.dev == dev && e.primary == primary) {
-      *comp = e.comp; *fork = e.fork; *join = e.join;
-      return hipSuccess;
-    }
-  Entry e{dev, primary, nullptr, nullptr, nullptr};
-  if ((r = hipStreamCreateWithFlags(&e.comp, hipStreamNonBlocking)) != hipSuccess) return r;
-  if ((r = hipEventCreateWithFlags(&e.fork, hipEventDisableTiming)) != hipSuccess) return r;
-  if ((r = hipEventCreateWithFlags(&e.join, hipEventDisableTiming)) != hipSuccess) return r;
-  table.push_back(e);
-  *comp = e.comp; *fork = e.fork; *join = e.join;
-  return hipSuccess;
-}
-
 hipError_t rt_record_wait(hipEvent_t e, hipStream_t from, hipStream_t to) {
   hipError_t r = hipEventRecord(e, from);
   if (r != hipSuccess) return r;

@@ -335,12 +335,6 @@ hipError_t rt_event_create(hipEvent_t* e) {
 }
 hipError_t rt_event_destroy(hipEvent_t) { return hipSuccess; }
 hipError_t rt_record_wait(hipEvent_t, hipStream_t, hipStream_t) { return hipSuccess; }
-hipError_t rt_companion(hipStream_t primary, hipStream_t* comp, hipEvent_t* fork, hipEvent_t* join) {
-  *comp = primary;   // execution is sequential here
-  *fork = nullptr;
-  *join = nullptr;
-  return hipSuccess;
-}
 hipError_t rt_capture_begin(hipStream_t) { return hipSuccess; }
 hipError_t rt_capture_end(hipStream_t, void** exec) {
   *exec = (void*)1;
