@@ -52,7 +52,6 @@ template <int NB>
 struct PanelLds {
   unsigned red[MAX_ROWS / 64] __attribute__((aligned(16)));
   v2d prow[NB];              // pivot row, unscaled, in the rotated column order
-  v2d srow[NB];              // row j before the interchange
   int spiv[NB];
   int cont[MAX_ROWS];        // cont[i]: row, at the start of the panel, whose content is now at row i
   // first the transposition buffer of the panel load ([STAGE_ROWS][NB + 1]),
@@ -115,13 +114,12 @@ __device__ __forceinline__ void csub_mul(v2d& x, v2d f, v2d p) {
 // forms 1 / pivot itself, so the only serial work between the two barriers is
 // the owner's LDS store.
 template <int NB, int NT, int KK>
-__device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int t, int n, int j, int jj,
+__device__ __forceinline__ void panel_step(v2d (&x)[2][NB], int (&lr)[2], PanelLds<NB>& L, int t, int n, int j, int jj,
                                            int& status) {
   const int lane = t & 63, wave = t >> 6;
-  const int r0 = t, r1 = t + NT;
   unsigned key = 0u;
-  if (r0 < n && r0 >= j) key = pivot_key(x[0][KK], r0);
-  if (r1 < n && r1 >= j) key = max(key, pivot_key(x[1][KK], r1));
+  if (lr[0] < n && lr[0] >= j) key = pivot_key(x[0][KK], lr[0]);
+  if (lr[1] < n && lr[1] >= j) key = max(key, pivot_key(x[1][KK], lr[1]));
   key = wave_max_u32(key);
   if (lane == 0) L.red[wave] = key;
   __syncthreads();
@@ -134,24 +132,18 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int
     }
   }
   const int pr = 2047 - (int)(key & 0x7FFu);
-  const bool j0r = j == r0, j1r = j == r1;
-  if (pr == r0) {
+  // The interchange of rows j and pr is only a relabelling: the holder of row pr
+  // becomes row j (the pivot row), the holder of row j becomes row pr.
+  const bool p0 = lr[0] == pr, p1 = lr[1] == pr;
+  if (p0) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) L.prow[c] = x[0][c];
   }
-  if (pr == r1) {
+  if (p1) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) L.prow[c] = x[1][c];
   }
-  if (j0r && pr != j) {
-#pragma unroll
-    for (int c = 0; c < NB; ++c) L.srow[c] = x[0][c];
-  }
-  if (j1r && pr != j) {
-#pragma unroll
-    for (int c = 0; c < NB; ++c) L.srow[c] = x[1][c];
-  }
-  if (j0r || j1r) {
+  if (p0 || p1) {
     if (pr != j) {
       const int u = L.cont[j];
       L.cont[j] = L.cont[pr];
@@ -166,31 +158,26 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int
   for (int c = 0; c < NB; ++c) pc[c] = L.prow[c];
   const v2d d = pc[KK];
   const v2d dinv = vinv(d);
-  if (j0r || j1r) {
+  if (p0 || p1) {
     if (d.x == 0.0 && d.y == 0.0) status = ST_ESINGULAR;
     else if (!(isfinite(dinv.x) && isfinite(dinv.y))) status = status == ST_OK ? ST_ENONFINITE : status;
   }
-  // the row that held the pivot takes the old row j; row j is cleared and
-  // then takes the same update as every other row with multiplier -1 / pivot,
-  // which leaves pivot row / pivot in it
-  if (pr == r0 && !j0r) {
-#pragma unroll
-    for (int c = 0; c < NB; ++c) x[0][c] = L.srow[c];
-  }
-  if (pr == r1 && !j1r) {
-#pragma unroll
-    for (int c = 0; c < NB; ++c) x[1][c] = L.srow[c];
-  }
-  if (j0r) {
+  if (lr[0] == j) lr[0] = pr;
+  if (lr[1] == j) lr[1] = pr;
+  if (p0) lr[0] = j;
+  if (p1) lr[1] = j;
+  // the new pivot row is cleared and then takes the same update as every other
+  // row with multiplier -1 / pivot, which leaves pivot row / pivot in it
+  if (p0) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) x[0][c] = v2d{0.0, 0.0};
   }
-  if (j1r) {
+  if (p1) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) x[1][c] = v2d{0.0, 0.0};
   }
-  const v2d f0 = j0r ? -dinv : vmul(x[0][KK], dinv);
-  const v2d f1 = j1r ? -dinv : vmul(x[1][KK], dinv);
+  const v2d f0 = p0 ? -dinv : vmul(x[0][KK], dinv);
+  const v2d f1 = p1 ? -dinv : vmul(x[1][KK], dinv);
   // column j of the inverse: -x_rj / pivot in the other rows, 1 / pivot in row j
   x[0][KK] = -f0;
   x[1][KK] = -f1;
@@ -204,17 +191,18 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], PanelLds<NB>& L, int
 
 template <int NB, int NT, int KK, int U>
 struct PanelGroup {
-  __device__ __forceinline__ static void run(v2d (&x)[2][NB], PanelLds<NB>& L, int t, int n, int j0, int jb, int nbw,
-                                             int& status) {
+  __device__ __forceinline__ static void run(v2d (&x)[2][NB], int (&lr)[2], PanelLds<NB>& L, int t, int n, int j0,
+                                             int jb, int nbw, int& status) {
     if (jb + KK < nbw) {
-      panel_step<NB, NT, KK>(x, L, t, n, j0 + jb + KK, jb + KK, status);
-      PanelGroup<NB, NT, KK + 1, U>::run(x, L, t, n, j0, jb, nbw, status);
+      panel_step<NB, NT, KK>(x, lr, L, t, n, j0 + jb + KK, jb + KK, status);
+      PanelGroup<NB, NT, KK + 1, U>::run(x, lr, L, t, n, j0, jb, nbw, status);
     }
   }
 };
 template <int NB, int NT, int U>
 struct PanelGroup<NB, NT, U, U> {
-  __device__ __forceinline__ static void run(v2d (&)[2][NB], PanelLds<NB>&, int, int, int, int, int, int&) {}
+  __device__ __forceinline__ static void run(v2d (&)[2][NB], int (&)[2], PanelLds<NB>&, int, int, int, int, int,
+                                             int&) {}
 };
 
 // Panel kernel: one workgroup of NT threads per matrix, two rows per thread
@@ -284,9 +272,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
   constexpr int SG = 4;   // steps per loop iteration
   static_assert(NB % SG == 0, "panel width must be a multiple of the step group");
   int rot = 0;
+  int lr[2] = {t, t + NT};   // logical row held in each register row
 #pragma unroll 1
   for (int jb = 0; jb < nbw; jb += SG) {
-    PanelGroup<NB, NT, 0, SG>::run(x, L, t, n, j0, jb, nbw, status);
+    PanelGroup<NB, NT, 0, SG>::run(x, lr, L, t, n, j0, jb, nbw, status);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       v2d h[SG];
@@ -303,27 +292,26 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
   // --- the panel result W = [A_JJ^{-1}; -A_RJ A_JJ^{-1}] back into A's panel columns,
   // through LDS in chunks so that the stores are coalesced; after the rotations
   // x[s][c] holds panel column (c + rot) mod NB
-  // (rows of slot 0 first, then slot 1: each loop names its register row statically)
-#pragma unroll
-  for (int half = 0; half < 2; ++half) {
+  // (each register row goes to its logical row; both slots are offered to every chunk)
 #pragma unroll CH_UNROLL
-    for (int k = 0; k < CH / 2; ++k) {
-      const int first = (half * (CH / 2) + k) * STAGE_ROWS;
-      const int tb = k * STAGE_ROWS;   // first % NT
-      const bool mine = t >= tb && t < tb + STAGE_ROWS;
-      if (mine) {
+  for (int ch = 0; ch < CH; ++ch) {
+    const int first = ch * STAGE_ROWS;
+    if (lr[0] >= first && lr[0] < first + STAGE_ROWS) {
 #pragma unroll
-        for (int c = 0; c < NB; ++c) L.buf[(t - tb) * (NB + 1) + (c + rot) % NB] = x[half][c];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int idx = e * NT + t, rr = first + idx / NB, cc = idx % NB;
-        if (rr < n && cc < nbw)
-          reinterpret_cast<v2d*>(A)[(long)rr * lda + j0 + cc] = L.buf[(idx / NB) * (NB + 1) + cc];
-      }
-      __syncthreads();
+      for (int c = 0; c < NB; ++c) L.buf[(lr[0] - first) * (NB + 1) + (c + rot) % NB] = x[0][c];
     }
+    if (lr[1] >= first && lr[1] < first + STAGE_ROWS) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) L.buf[(lr[1] - first) * (NB + 1) + (c + rot) % NB] = x[1][c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = e * NT + t, rr = first + idx / NB, cc = idx % NB;
+      if (rr < n && cc < nbw)
+        reinterpret_cast<v2d*>(A)[(long)rr * lda + j0 + cc] = L.buf[(idx / NB) * (NB + 1) + cc];
+    }
+    __syncthreads();
   }
 
   // The nbw interchanges, composed into cont[], act on the rows D = panel rows
@@ -508,7 +496,7 @@ hipError_t update_cols(const InvDesc& d, int n, int jb, int K, const double2* U,
   g.active = d.active;
   g.prec = PREC_F64;
   g.xcd_remap = 1;
-  g.tile = GEMM_TILE_64;
+  g.tile = GEMM_TILE_64_8W;
   g.prof_class = KC_INV_GEMM;
   g.gauss = d.gauss;
   return launch_gemm(g, s);
