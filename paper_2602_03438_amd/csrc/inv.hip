@@ -53,6 +53,7 @@ struct PanelLds {
   unsigned red[MAX_ROWS / 64] __attribute__((aligned(16)));
   v2d prow[NB];              // pivot row, unscaled, in the rotated column order
   int spiv[NB];
+  int status;                // first failure of the panel (set by the pivot holder of that step)
   int cont[MAX_ROWS];        // cont[i]: row, at the start of the panel, whose content is now at row i
   // first the transposition buffer of the panel load ([STAGE_ROWS][NB + 1]),
   // later the new contents of the interchanged rows below the panel ([NB][NBO])
@@ -114,8 +115,8 @@ __device__ __forceinline__ void csub_mul(v2d& x, v2d f, v2d p) {
 // forms 1 / pivot itself, so the only serial work between the two barriers is
 // the owner's LDS store.
 template <int NB, int NT, int KK>
-__device__ __forceinline__ void panel_step(v2d (&x)[2][NB], int (&lr)[2], PanelLds<NB>& L, int t, int n, int j, int jj,
-                                           int& status) {
+__device__ __forceinline__ void panel_step(v2d (&x)[2][NB], int (&lr)[2], PanelLds<NB>& L, int t, int n, int j,
+                                           int jj) {
   const int lane = t & 63, wave = t >> 6;
   unsigned key = 0u;
   if (lr[0] < n && lr[0] >= j) key = pivot_key(x[0][KK], lr[0]);
@@ -158,9 +159,9 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], int (&lr)[2], PanelL
   for (int c = 0; c < NB; ++c) pc[c] = L.prow[c];
   const v2d d = pc[KK];
   const v2d dinv = vinv(d);
-  if (p0 || p1) {
-    if (d.x == 0.0 && d.y == 0.0) status = ST_ESINGULAR;
-    else if (!(isfinite(dinv.x) && isfinite(dinv.y))) status = status == ST_OK ? ST_ENONFINITE : status;
+  if ((p0 || p1) && L.status == ST_OK) {
+    if (d.x == 0.0 && d.y == 0.0) L.status = ST_ESINGULAR;
+    else if (!(isfinite(dinv.x) && isfinite(dinv.y))) L.status = ST_ENONFINITE;
   }
   if (lr[0] == j) lr[0] = pr;
   if (lr[1] == j) lr[1] = pr;
@@ -192,17 +193,16 @@ __device__ __forceinline__ void panel_step(v2d (&x)[2][NB], int (&lr)[2], PanelL
 template <int NB, int NT, int KK, int U>
 struct PanelGroup {
   __device__ __forceinline__ static void run(v2d (&x)[2][NB], int (&lr)[2], PanelLds<NB>& L, int t, int n, int j0,
-                                             int jb, int nbw, int& status) {
+                                             int jb, int nbw) {
     if (jb + KK < nbw) {
-      panel_step<NB, NT, KK>(x, lr, L, t, n, j0 + jb + KK, jb + KK, status);
-      PanelGroup<NB, NT, KK + 1, U>::run(x, lr, L, t, n, j0, jb, nbw, status);
+      panel_step<NB, NT, KK>(x, lr, L, t, n, j0 + jb + KK, jb + KK);
+      PanelGroup<NB, NT, KK + 1, U>::run(x, lr, L, t, n, j0, jb, nbw);
     }
   }
 };
 template <int NB, int NT, int U>
 struct PanelGroup<NB, NT, U, U> {
-  __device__ __forceinline__ static void run(v2d (&)[2][NB], int (&)[2], PanelLds<NB>&, int, int, int, int, int,
-                                             int&) {}
+  __device__ __forceinline__ static void run(v2d (&)[2][NB], int (&)[2], PanelLds<NB>&, int, int, int, int, int) {}
 };
 
 // Panel kernel: one workgroup of NT threads per matrix, two rows per thread
@@ -224,6 +224,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
   const long lda = a.lda;
   __shared__ PanelLds<NB> L;
   if (t < MAX_ROWS / 64) L.red[t] = 0u;   // waves beyond the last never write their slot
+  if (t == 0) L.status = ST_OK;
   for (int i = t; i < n; i += NT) L.cont[i] = i;
 
   // --- panel load: chunk ch covers rows [ch*STAGE_ROWS, (ch+1)*STAGE_ROWS)
@@ -268,14 +269,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
     for (int e = 0; e < PER; ++e) ld[e] = nx[e];
   }
 
-  int status = ST_OK;
   constexpr int SG = 4;   // steps per loop iteration
   static_assert(NB % SG == 0, "panel width must be a multiple of the step group");
   int rot = 0;
   int lr[2] = {t, t + NT};   // logical row held in each register row
 #pragma unroll 1
   for (int jb = 0; jb < nbw; jb += SG) {
-    PanelGroup<NB, NT, 0, SG>::run(x, lr, L, t, n, j0, jb, nbw, status);
+    PanelGroup<NB, NT, 0, SG>::run(x, lr, L, t, n, j0, jb, nbw);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       v2d h[SG];
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
   } else if (d >= 0) {
     tau[d] = tv;
   }
-  if (status != ST_OK && a.info) atomicCAS(a.info + (a.info_mod > 0 ? p % a.info_mod : p), ST_OK, status);
+  if (t == 0 && L.status != ST_OK && a.info) atomicCAS(a.info + (a.info_mod > 0 ? p % a.info_mod : p), ST_OK, L.status);
 }
 
 // out[r][c] = X[r][sigma^{-1}[c]]; one workgroup per (matrix, GATHER_ROWS rows)
