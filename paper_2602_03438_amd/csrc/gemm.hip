@@ -123,9 +123,37 @@ __device__ __forceinline__ void store_tile(typename Cx<T>::type* s, const double
   }
 }
 
+// Full tiles (the tile lies inside the matrix): no bounds tests, native vectors.
+template <int R, int NT, int L, bool ROWL>
+__device__ __forceinline__ void load_tile_full(v2d (&r)[L], const double2* __restrict__ base, long ld, int row0,
+                                               int col0) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const int e = t + NT * j;
+    const int rr = ROWL ? e / BK : e / R;
+    const int cc = ROWL ? e % BK : e % R;
+    r[j] = *reinterpret_cast<const v2d*>(base + (long)(row0 + rr) * ld + col0 + cc);
+  }
+}
+
+template <typename T, int R, int NT, int L, bool ROWL>
+__device__ __forceinline__ void store_tile_v(typename Cx<T>::type* s, const v2d (&r)[L], bool conj) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const int e = t + NT * j;
+    const int idx = ROWL ? (e / BK) * (BK + 1) + (e % BK) : (e / R) * (R + 1) + (e % R);
+    s[idx] = to_cx<T>(make_double2(r[j].x, r[j].y), conj);
+  }
+}
+
 // TAG only separates the symbol of the inversion updates from the sweep
-// products in profiles; the code is the same.
-template <typename T, int OPA, int OPB, typename CF, int TAG = 0, bool GAUSS = false>
+// products in profiles; the code is the same.  FULL: M, N and K are multiples
+// of the tile and of the K-step, so no operand or result access needs a bounds
+// test; operand tiles are then fetched two K-steps ahead (two register sets)
+// instead of one.
+template <typename T, int OPA, int OPB, typename CF, int TAG = 0, bool GAUSS = false, bool FULL = false>
 __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(KArgs a) {
   typedef typename Cx<T>::type CT;
   typedef typename Acc<T>::type AT;
@@ -168,27 +196,9 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
 #pragma unroll
     for (int j = 0; j < FN; ++j) accS[i][j] = AT{0, 0, 0, 0};
 
-  double2 ra[CF::LA], rb[CF::LB];
-  auto gload = [&](int k0) {
-    if (A_ROW) load_tile<BM, NT, CF::LA, true>(ra, Ap, a.lda, m0, k0, a.M, a.K);
-    else       load_tile<BM, NT, CF::LA, false>(ra, Ap, a.lda, k0, m0, a.K, a.M);
-    if (B_ROW) load_tile<BN, NT, CF::LB, true>(rb, Bp, a.ldb, n0, k0, a.N, a.K);
-    else       load_tile<BN, NT, CF::LB, false>(rb, Bp, a.ldb, k0, n0, a.K, a.N);
-  };
-  auto lstore = [&](int st) {
-    store_tile<T, BM, NT, CF::LA, A_ROW>(sA[st], ra, OPA == OP_C);
-    store_tile<T, BN, NT, CF::LB, B_ROW>(sB[st], rb, OPB == OP_C);
-  };
-
   const int nk = (a.K + BK - 1) / BK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int st = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-    const CT* __restrict__ xA = sA[st];
-    const CT* __restrict__ xB = sB[st];
+  // one K-step of MFMAs on the LDS stage (xA, xB)
+  auto mac = [&](const CT* __restrict__ xA, const CT* __restrict__ xB) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kq = kk * 4 + lk;
@@ -240,8 +250,59 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
           for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
       }
     }
-    if (kt + 1 < nk) lstore(st ^ 1);
+  };
+  if constexpr (FULL) {
+    v2d qa[2][CF::LA], qb[2][CF::LB];
+    auto gl = [&](v2d (&ra)[CF::LA], v2d (&rb)[CF::LB], int k0) {
+      if (A_ROW) load_tile_full<BM, NT, CF::LA, true>(ra, Ap, a.lda, m0, k0);
+      else       load_tile_full<BM, NT, CF::LA, false>(ra, Ap, a.lda, k0, m0);
+      if (B_ROW) load_tile_full<BN, NT, CF::LB, true>(rb, Bp, a.ldb, n0, k0);
+      else       load_tile_full<BN, NT, CF::LB, false>(rb, Bp, a.ldb, k0, n0);
+    };
+    auto ls = [&](const v2d (&ra)[CF::LA], const v2d (&rb)[CF::LB], int st) {
+      store_tile_v<T, BM, NT, CF::LA, A_ROW>(sA[st], ra, OPA == OP_C);
+      store_tile_v<T, BN, NT, CF::LB, B_ROW>(sB[st], rb, OPB == OP_C);
+    };
+    // step k sits in LDS stage k & 1 and arrives through register set k & 1
+    gl(qa[0], qb[0], 0);
+    if (nk > 1) gl(qa[1], qb[1], BK);
+    ls(qa[0], qb[0], 0);
     __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+      if (kt + 2 < nk) gl(qa[0], qb[0], (kt + 2) * BK);
+      mac(sA[0], sB[0]);
+      if (kt + 1 < nk) ls(qa[1], qb[1], 1);
+      __syncthreads();
+      if (kt + 1 < nk) {
+        if (kt + 3 < nk) gl(qa[1], qb[1], (kt + 3) * BK);
+        mac(sA[1], sB[1]);
+        if (kt + 2 < nk) ls(qa[0], qb[0], 0);
+        __syncthreads();
+      }
+    }
+  } else {
+    double2 ra[CF::LA], rb[CF::LB];
+    auto gload = [&](int k0) {
+      if (A_ROW) load_tile<BM, NT, CF::LA, true>(ra, Ap, a.lda, m0, k0, a.M, a.K);
+      else       load_tile<BM, NT, CF::LA, false>(ra, Ap, a.lda, k0, m0, a.K, a.M);
+      if (B_ROW) load_tile<BN, NT, CF::LB, true>(rb, Bp, a.ldb, n0, k0, a.N, a.K);
+      else       load_tile<BN, NT, CF::LB, false>(rb, Bp, a.ldb, k0, n0, a.K, a.N);
+    };
+    auto lstore = [&](int st) {
+      store_tile<T, BM, NT, CF::LA, A_ROW>(sA[st], ra, OPA == OP_C);
+      store_tile<T, BN, NT, CF::LB, B_ROW>(sB[st], rb, OPB == OP_C);
+    };
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int st = kt & 1;
+      if (kt + 1 < nk) gload((kt + 1) * BK);
+      mac(sA[st], sB[st]);
+      if (kt + 1 < nk) lstore(st ^ 1);
+      __syncthreads();
+    }
   }
 
   double2* __restrict__ Cp = a.C + (long)p * a.sC;
@@ -259,18 +320,18 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm * CF::TM + i * 16 + acc_row<T>(lk, v);
-        const bool ok = use_beta && col < a.N && row < a.M;
+        const bool ok = use_beta && (FULL || (col < a.N && row < a.M));
         cin[j][v] = ok ? *reinterpret_cast<const v2d*>(Ci + (long)row * a.ldci + col) : v2d{0.0, 0.0};
       }
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       const int col = n0 + wn * CF::TN + j * 16 + li;
-      if (col >= a.N) continue;
+      if (!FULL && col >= a.N) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm * CF::TM + i * 16 + acc_row<T>(lk, v);
-        if (row >= a.M) continue;
+        if (!FULL && row >= a.M) continue;
         double re, im;
         if constexpr (GAUSS) {
           const double p1 = (double)accR[i][j][v], p2 = (double)accI[i][j][v];
@@ -296,23 +357,38 @@ typedef Cfg<128, 128, 4, 2> Cfg128;
 typedef Cfg<64, 64, 4, 2> Cfg64w8;   // 8 waves of 16 x 32: fewer registers per wave, more waves per SIMD
 typedef Cfg<128, 64, 8, 2> Cfg128x64w16;   // 16 waves of 16 x 32
 
+template <typename T, typename CF, bool GAUSS, bool FULL>
+void launch_ops(const GemmDesc& d, const KArgs& ka, dim3 grid, hipStream_t s) {
+  const dim3 block(CF::NT);
+  if (d.prof_class == KC_INV_GEMM && d.opA == OP_N && d.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 1, GAUSS, FULL>), grid, block, 0, s, ka);
+  else if (d.prof_class == KC_INV_GEMM && d.opA == OP_C && d.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF, 1, GAUSS, FULL>), grid, block, 0, s, ka);
+  else if (d.opA == OP_N && d.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 0, GAUSS, FULL>), grid, block, 0, s, ka);
+  else if (d.opA == OP_C && d.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF, 0, GAUSS, FULL>), grid, block, 0, s, ka);
+  else if (d.opA == OP_N && d.opB == OP_C)
+    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_C, CF, 0, GAUSS, FULL>), grid, block, 0, s, ka);
+  else hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_C, CF, 0, GAUSS, FULL>), grid, block, 0, s, ka);
+}
+
 template <typename T, typename CF, bool GAUSS>
 hipError_t launch_cfg(const GemmDesc& d, KArgs ka, hipStream_t s) {
   ka.tiles_m = (d.M + CF::BM - 1) / CF::BM;
   ka.tiles_n = (d.N + CF::BN - 1) / CF::BN;
   const long total = (long)ka.tiles_m * ka.tiles_n * d.batch;
-  const dim3 grid((unsigned)total), block(CF::NT);
-  if (d.prof_class == KC_INV_GEMM && d.opA == OP_N && d.opB == OP_N)
-    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 1, GAUSS>), grid, block, 0, s, ka);
-  else if (d.prof_class == KC_INV_GEMM && d.opA == OP_C && d.opB == OP_N)
-    hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF, 1, GAUSS>), grid, block, 0, s, ka);
-  else if (d.opA == OP_N && d.opB == OP_N)
-    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 0, GAUSS>), grid, block, 0, s, ka);
-  else if (d.opA == OP_C && d.opB == OP_N)
-    hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF, 0, GAUSS>), grid, block, 0, s, ka);
-  else if (d.opA == OP_N && d.opB == OP_C)
-    hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_C, CF, 0, GAUSS>), grid, block, 0, s, ka);
-  else hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_C, CF, 0, GAUSS>), grid, block, 0, s, ka);
+  const dim3 grid((unsigned)total);
+  // the 128 x 128 tile has no registers left for a second operand set
+  constexpr bool kFullOk = !(CF::BM == 128 && CF::BN == 128);
+  const bool full = kFullOk && d.M % CF::BM == 0 && d.N % CF::BN == 0 && d.K % BK == 0 && d.K >= BK;
+  if constexpr (kFullOk) {
+    if (full) {
+      launch_ops<T, CF, GAUSS, true>(d, ka, grid, s);
+      return hipGetLastError();
+    }
+  }
+  launch_ops<T, CF, GAUSS, false>(d, ka, grid, s);
   return hipGetLastError();
 }
 

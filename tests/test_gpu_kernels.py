@@ -45,9 +45,11 @@ def test_zgemm_fp64_parity(nb, opa, opb, M, N, K, prec):
 
 @pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("opa,opb", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
-@pytest.mark.parametrize("M,N,K", [(200, 130, 77), (128, 256, 64)])
+@pytest.mark.parametrize("M,N,K", [(200, 130, 77), (128, 256, 64), (128, 128, 48), (128, 64, 16)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_zgemm_tile_shapes(nb, tile, opa, opb, M, N, K, prec):
+    """Ragged sizes and sizes that are whole tiles (the unchecked full-tile
+    path), with an odd and a single K-step among the latter."""
     import torch
     r = np.random.Generator(np.random.PCG64(M + N + K + tile))
     A = _rand(r, (2, M, K) if opa == "N" else (2, K, M))
