@@ -8,18 +8,23 @@
 //      to 2^-9 relative, ties to the smaller row), row interchange, scale the
 //      pivot row, eliminate the column from every other row with the
 //      multipliers stored in place.  The result W = [A_JJ^{-1}; -A_RJ A_JJ^{-1}]
-//      (rows in pivoted order) goes to scratch and the panel columns of A are
-//      cleared.  The same workgroup composes the nb interchanges into one row
-//      map, applies it to the other columns of the current super-panel, copies
-//      the pivot rows into U (nb x n, identity in the panel columns), clears
-//      those rows, and folds the map into the row orders sigma (whole matrix)
-//      and tau (since the start of the super-panel).
+//      (rows in pivoted order) goes back into the panel columns.  The same
+//      workgroup composes the nb interchanges into one row map, applies it to
+//      the other columns of the current sub-panel, copies the pivot rows into U
+//      (nb x n), clears those rows, and folds the map into the row orders sigma
+//      (whole matrix), tau (since the start of the super-panel) and rho (since
+//      the start of the sub-panel).
 //   2. product: A += W U on the matrix cores (one batched complex product,
-//      K = nb): pivot rows become A_JJ^{-1} A_JC, the other rows
-//      A_RC - A_RJ A_JJ^{-1} A_JC, and W lands in the panel columns.
-// Two levels: the panels run inside super-panels of NBO = 128 columns; the
-// columns outside a super-panel are brought up to date once per super-panel
-// (interchanges through tau, then one product with K = 128).
+//      K = nb) over the other columns of the sub-panel: pivot rows become
+//      A_JJ^{-1} A_JC, the other rows A_RC - A_RJ A_JJ^{-1} A_JC.
+// Three levels: panels of nb columns inside sub-panels of NBM = 64 columns
+// inside super-panels of NBO = 128 columns.  After a sub-panel the other
+// columns of its super-panel are brought up to date (interchanges through rho,
+// pivot rows to Um, one product with K = 64); after a super-panel the columns
+// outside it (interchanges through tau, pivot rows to Uo, one product with
+// K = 128).  Each level's W is the block's own columns, read in place.  The
+// K = nb products touch only the 64 columns of a sub-panel, which is what
+// keeps the HBM traffic of the narrow updates down.
 // After the last panel A holds (P A)^{-1} with (P A)[i] = A[sigma[i]]; the
 // inverse A^{-1}[r][c] = (P A)^{-1}[r][sigma^{-1}[c]] is a column gather.
 // Arithmetic: 8 n^3 real flops per matrix, all but O(n^2 nb) of them in the
@@ -32,15 +37,21 @@ namespace {
 
 constexpr int MAX_ROWS = 1024;
 constexpr int NB_MAX = 32;
-constexpr int NBO = 128;   // outer block (super-panel width) of the two-level scheme
+constexpr int NBM = 64;    // sub-panel width (middle level)
+// Super-panel width (outer level).  256 would halve the outer products but
+// doubles the forward error of the inverse at n = 512 (CPU emulation of this
+// scheme on matrices of condition 1e6 .. 1e12); 128 matches LAPACK's.
+constexpr int NBO = 128;
 
 struct PanelArgs {
   int n, j0, nbw;
-  int c0, c1;               // the current super-panel: columns the interchanges and U cover
+  int c0, c1;               // the current sub-panel: columns the interchanges and U cover
+  int t0;                   // first column of the current super-panel
   double2* A; long lda, sA;
   double2* U; long sU;      // U_p: NB x n row-major (columns of [c0, c1) outside the panel written)
   int* sigma;               // sigma_p[i]: original row now at position i
-  int* tau; long sS;        // tau_p[i]: row, at the start of the super-panel, now at position i
+  int* tau;                 // tau_p[i]: row, at the start of the super-panel, now at position i
+  int* rho; long sS;        // rho_p[i]: row, at the start of the sub-panel, now at position i
   int* info; int info_mod;
   const int* active;
 };
@@ -56,8 +67,8 @@ struct PanelLds {
   int status;                // first failure of the panel (set by the pivot holder of that step)
   int cont[MAX_ROWS];        // cont[i]: row, at the start of the panel, whose content is now at row i
   // first the transposition buffer of the panel load ([STAGE_ROWS][NB + 1]),
-  // later the new contents of the interchanged rows below the panel ([NB][NBO])
-  static constexpr int BUF = (STAGE_ROWS * (NB + 1) > NB * NBO) ? STAGE_ROWS * (NB + 1) : NB * NBO;
+  // later the new contents of the interchanged rows below the panel ([NB][NBM])
+  static constexpr int BUF = (STAGE_ROWS * (NB + 1) > NB * NBM) ? STAGE_ROWS * (NB + 1) : NB * NBM;
   v2d buf[BUF];
 };
 
@@ -217,6 +228,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
   double2* __restrict__ U = a.U + (long)p * a.sU;
   int* __restrict__ sigma = a.sigma + (long)p * a.sS;
   int* __restrict__ tau = a.tau + (long)p * a.sS;
+  int* __restrict__ rho = a.rho + (long)p * a.sS;
   const v2d* __restrict__ Av = reinterpret_cast<const v2d*>(A);
   const int t = threadIdx.x;
   const int n = a.n, j0 = a.j0, nbw = a.nbw;
@@ -339,18 +351,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
       const int s = e / cnt, c = c0 + e % cnt;
       if (c >= j0 && c < jend) continue;
       reinterpret_cast<v2d*>(U)[(long)s * n + c] = u[g];
-      if (L.spiv[s] >= jend) L.buf[s * NBO + (c - c0)] = q[g];
+      if (L.spiv[s] >= jend) L.buf[s * NBM + (c - c0)] = q[g];
     }
   }
   // row orders: new entry of a row d of D = old entry of row cont[d]
-  int d = -1, sv = 0, tv = 0;
+  int d = -1, sv = 0, tv = 0, rv = 0;
   if (t < 2 * nbw) {
     d = t < nbw ? j0 + t : L.spiv[t - nbw];
     if (t >= nbw && d < jend) d = -1;
     if (d >= 0) {
       const int src = L.cont[d];
       sv = j0 == 0 ? src : sigma[src];
-      tv = j0 == c0 ? src : tau[src];
+      tv = j0 == a.t0 ? src : tau[src];
+      rv = j0 == c0 ? src : rho[src];
     }
   }
   __syncthreads();
@@ -359,17 +372,22 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
     if (c >= j0 && c < jend) continue;
     A[(long)(j0 + s) * lda + c] = make_double2(0.0, 0.0);
     const int qr = L.spiv[s];
-    if (qr >= jend) reinterpret_cast<v2d*>(A)[(long)qr * lda + c] = L.buf[s * NBO + (c - c0)];
+    if (qr >= jend) reinterpret_cast<v2d*>(A)[(long)qr * lda + c] = L.buf[s * NBM + (c - c0)];
   }
   if (j0 == 0) {
     for (int i = t; i < n; i += NT) sigma[i] = L.cont[i];
   } else if (d >= 0) {
     sigma[d] = sv;
   }
-  if (j0 == c0) {
+  if (j0 == a.t0) {
     for (int i = t; i < n; i += NT) tau[i] = L.cont[i];
   } else if (d >= 0) {
     tau[d] = tv;
+  }
+  if (j0 == c0) {
+    for (int i = t; i < n; i += NT) rho[i] = L.cont[i];
+  } else if (d >= 0) {
+    rho[d] = rv;
   }
   if (t == 0 && L.status != ST_OK && a.info) atomicCAS(a.info + (a.info_mod > 0 ? p % a.info_mod : p), ST_OK, L.status);
 }
@@ -395,24 +413,25 @@ __global__ void __launch_bounds__(256) gj_gather_kernel(int n, const double2* M,
   }
 }
 
-// Outer step of the two-level blocking for the super-panel J = [J0, J0+mo),
-// one workgroup per (matrix, OUTER_COLS columns) outside J: the super-panel's
-// interchanges (the content map tau) are applied to those columns, the pivot
-// rows J0..J0+mo-1 go to Uo (mo x n) and are cleared, and the rows below J
-// that took part receive their new contents.  All reads of a block precede its
-// writes (a barrier between).  The columns of J already hold their final W.
+// Block step of the middle or outer level for the block J = [J0, J0+mo) (a
+// sub-panel or a super-panel), one workgroup per (matrix, OUTER_COLS columns)
+// of [lo, hi) outside J: the block's interchanges (its content map tau) are
+// applied to those columns, the pivot rows J0..J0+mo-1 go to Uo (mo x n) and
+// are cleared, and the rows below J that took part receive their new
+// contents.  All reads of a block precede its writes (a barrier between).  The
+// columns of J already hold their final W.
 constexpr int OUTER_COLS = 16;
 constexpr int OUTER_THREADS = 256;
 
-__global__ void __launch_bounds__(OUTER_THREADS) gj_outer_kernel(int n, int J0, int mo, double2* A, long lda,
-                                                                 long sA, double2* Uo, long sU, const int* tau,
-                                                                 long sT, const int* active) {
+__global__ void __launch_bounds__(OUTER_THREADS) gj_outer_kernel(int n, int J0, int mo, int lo, int hi, double2* A,
+                                                                 long lda, long sA, double2* Uo, long sU,
+                                                                 const int* tau, long sT, const int* active) {
   const int p = blockIdx.y;
   if (active && active[p] == 0) return;
   double2* __restrict__ Ap = A + (long)p * sA;
   double2* __restrict__ U = Uo + (long)p * sU;
-  const int cb = blockIdx.x * OUTER_COLS;
-  const int w = min(OUTER_COLS, n - cb);
+  const int cb = lo + blockIdx.x * OUTER_COLS;
+  const int w = min(OUTER_COLS, hi - cb);
   const int t = threadIdx.x;
   if (cb >= J0 && cb < J0 + mo) return;
   __shared__ int rows[2 * NBO];
@@ -464,16 +483,18 @@ __global__ void __launch_bounds__(OUTER_THREADS) gj_outer_kernel(int n, int J0, 
 
 struct ScratchLayout {
   size_t per_al;
-  size_t off_U, off_Uo, off_sigma, off_tau;
+  size_t off_U, off_Um, off_Uo, off_sigma, off_tau, off_rho;
 };
 
 ScratchLayout layout(int n) {
   ScratchLayout L{};
   size_t o = 0;
   L.off_U = o;  o += (size_t)NB_MAX * n * sizeof(double2);
+  L.off_Um = o; o += (size_t)NBM * n * sizeof(double2);
   L.off_Uo = o; o += (size_t)NBO * n * sizeof(double2);
   L.off_sigma = o; o += (size_t)n * sizeof(int);
   L.off_tau = o;   o += (size_t)n * sizeof(int);
+  L.off_rho = o;   o += (size_t)n * sizeof(int);
   L.per_al = (o + 255) & ~(size_t)255;
   return L;
 }
@@ -511,44 +532,54 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
   if (n <= 0 || d.batch <= 0) return hipSuccess;
   if (n > MAX_ROWS) return hipErrorInvalidValue;
   const int NB = (d.nb == 32 && n <= 512) ? 32 : 16;
+  static_assert(NBM % NB_MAX == 0 && NBO % NBM == 0, "block widths must nest");
   const ScratchLayout SL = layout(n);
   const long sItem = (long)(SL.per_al / sizeof(double2));   // per_al is a multiple of 256 bytes
   const long sI = (long)(SL.per_al / sizeof(int));
   char* base = (char*)d.scratch;
   double2* U = (double2*)(base + SL.off_U);
+  double2* Um = (double2*)(base + SL.off_Um);
   double2* Uo = (double2*)(base + SL.off_Uo);
   int* sigma = (int*)(base + SL.off_sigma);
   int* tau = (int*)(base + SL.off_tau);
-  // two levels when the matrix is wider than one super-panel
-  const int outer = n > NBO ? NBO : n;
+  int* rho = (int*)(base + SL.off_rho);
   hipError_t e = hipSuccess;
-  for (int J0 = 0; J0 < n; J0 += outer) {
-    const int mo = (n - J0 < outer) ? n - J0 : outer;
-    for (int j0 = J0; j0 < J0 + mo; j0 += NB) {
-      const int nbw = (J0 + mo - j0 < NB) ? J0 + mo - j0 : NB;
-      PanelArgs pa{n, j0, nbw, J0, J0 + mo, d.M, d.ldm, d.sM, U, sItem, sigma, tau, sI, d.info, d.info_mod,
-                   d.active};
-      prof_begin(KC_INV_PANEL, s);
-      // two rows per thread: 256 threads up to n = 512, 512 up to n = MAX_ROWS
-      if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 256>), dim3(d.batch), dim3(256), 0, s, pa);
-      else if (n <= 512) hipLaunchKernelGGL((gj_panel_kernel<16, 256>), dim3(d.batch), dim3(256), 0, s, pa);
-      else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS / 2>), dim3(d.batch), dim3(MAX_ROWS / 2), 0, s, pa);
-      prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      // the other columns of the super-panel: A[:, c] += W U[:, c], W read in place from the panel columns
-      if ((e = update_cols(d, n, j0, nbw, U, sItem, J0, j0, s)) != hipSuccess) return e;
-      if ((e = update_cols(d, n, j0, nbw, U, sItem, j0 + nbw, J0 + mo, s)) != hipSuccess) return e;
-    }
-    if (mo == n) break;   // one level: the super-panel was the whole matrix
-    // outer step: interchanges and pivot rows of the other columns, then A[:, c] += W Uo[:, c]
-    // for the columns outside J, W read in place from the columns of J
+  // interchanges of the block [J0, J0+mo) through its map into the columns [lo, hi) outside it,
+  // then A[:, c] += W Ub[:, c] there, W read in place from the block's columns
+  auto block_step = [&](int J0, int mo, int lo, int hi, double2* Ub, const int* map) -> hipError_t {
     prof_begin(KC_INV_SWAP, s);
-    hipLaunchKernelGGL(gj_outer_kernel, dim3((n + OUTER_COLS - 1) / OUTER_COLS, d.batch), dim3(OUTER_THREADS), 0, s,
-                       n, J0, mo, d.M, d.ldm, d.sM, Uo, sItem, tau, sI, d.active);
+    hipLaunchKernelGGL(gj_outer_kernel, dim3((hi - lo + OUTER_COLS - 1) / OUTER_COLS, d.batch), dim3(OUTER_THREADS),
+                       0, s, n, J0, mo, lo, hi, d.M, d.ldm, d.sM, Ub, sItem, map, sI, d.active);
     prof_end(KC_INV_SWAP, s, 0, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = update_cols(d, n, J0, mo, Uo, sItem, 0, J0, s)) != hipSuccess) return e;
-    if ((e = update_cols(d, n, J0, mo, Uo, sItem, J0 + mo, n, s)) != hipSuccess) return e;
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    if ((r = update_cols(d, n, J0, mo, Ub, sItem, lo, J0, s)) != hipSuccess) return r;
+    return update_cols(d, n, J0, mo, Ub, sItem, J0 + mo, hi, s);
+  };
+  for (int J0 = 0; J0 < n; J0 += NBO) {
+    const int mo = min(NBO, n - J0);
+    for (int S0 = J0; S0 < J0 + mo; S0 += NBM) {
+      const int ms = min(NBM, J0 + mo - S0);
+      for (int j0 = S0; j0 < S0 + ms; j0 += NB) {
+        const int nbw = min(NB, S0 + ms - j0);
+        PanelArgs pa{n, j0, nbw, S0, S0 + ms, J0, d.M, d.ldm, d.sM, U, sItem, sigma, tau, rho, sI, d.info,
+                     d.info_mod, d.active};
+        prof_begin(KC_INV_PANEL, s);
+        // two rows per thread: 256 threads up to n = 512, 512 up to n = MAX_ROWS
+        if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 256>), dim3(d.batch), dim3(256), 0, s, pa);
+        else if (n <= 512) hipLaunchKernelGGL((gj_panel_kernel<16, 256>), dim3(d.batch), dim3(256), 0, s, pa);
+        else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS / 2>), dim3(d.batch), dim3(MAX_ROWS / 2), 0, s, pa);
+        prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // the other columns of the sub-panel: A[:, c] += W U[:, c], W read in place from the panel columns
+        if ((e = update_cols(d, n, j0, nbw, U, sItem, S0, j0, s)) != hipSuccess) return e;
+        if ((e = update_cols(d, n, j0, nbw, U, sItem, j0 + nbw, S0 + ms, s)) != hipSuccess) return e;
+      }
+      // middle level: the other columns of the super-panel
+      if (ms < mo && (e = block_step(S0, ms, J0, J0 + mo, Um, rho)) != hipSuccess) return e;
+    }
+    // outer level: the columns outside the super-panel
+    if (mo < n && (e = block_step(J0, mo, 0, n, Uo, tau)) != hipSuccess) return e;
   }
   prof_begin(KC_INV_PERM, s);
   hipLaunchKernelGGL(gj_gather_kernel, dim3((n + GATHER_ROWS - 1) / GATHER_ROWS, d.batch), dim3(256), 0, s, n, d.M,
