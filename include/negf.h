@@ -120,6 +120,11 @@ typedef struct negf_options {
   int32_t cmul;         /* real products per complex double product: 4, or 3 by
                            Gauss's method (3/4 of the matrix-core work; error
                            bounded normwise, not componentwise)  [4]   */
+  int32_t dense_coupling; /* 1: multiply the coupling blocks A_{i,i+1} as dense
+                           blocks; otherwise products with a coupling operand
+                           skip its 16 x 64 slabs that are zero in both H_{i,i+1}
+                           and S_{i,i+1} (exact zeros: the results are the same)
+                           [0]   */
 } negf_options;
 
 /* Operation codes for negf_workspace_bytes. */
@@ -264,9 +269,12 @@ negf_status negf_mlp_infer_bf16(int32_t n, int32_t F, int32_t H, int32_t O, cons
                                 const float* b3, uint16_t* scratch, float* Y, void* stream);
 
 /* ---- profiling: per kernel class launch counts, algorithmic flops and
- * event-timed durations, recorded on the launching stream. ---- */
+ * event-timed durations, recorded on the launching stream.  NEGF_KC_GEMM_CPL
+ * holds the products with a coupling-block operand whose zero slabs are
+ * skipped (either precision); their flops are counted as for dense blocks, an
+ * upper bound of the work done. ---- */
 enum { NEGF_KC_GEMM64 = 0, NEGF_KC_GEMM32 = 1, NEGF_KC_INV_PANEL = 2, NEGF_KC_INV_SWAP = 3, NEGF_KC_INV_PERM = 4,
-       NEGF_KC_ELEM = 5, NEGF_KC_INV_GEMM = 6, NEGF_KC_COUNT = 7 };
+       NEGF_KC_ELEM = 5, NEGF_KC_INV_GEMM = 6, NEGF_KC_GEMM_CPL = 7, NEGF_KC_COUNT = 8 };
 typedef struct negf_kernel_stats {
   int64_t launches;
   double total_ms;   /* sum of per-launch event durations */

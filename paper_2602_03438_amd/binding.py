@@ -22,8 +22,9 @@ LIB_PATH = os.path.join(_HERE, "libnegf.so")
 NEGF_OK, NEGF_EINVAL, NEGF_ENOCONV, NEGF_ESINGULAR, NEGF_ENONFINITE, NEGF_EHIP, NEGF_ENOMEM = range(7)
 PLAIN_FP64, FP32_REFINE, FP32_NOREFINE = 0, 1, 2
 OP_OBC, OP_RETARDED, OP_LESSER_GREATER, OP_TRANSMISSION = 0, 1, 2, 3
-KC_NAMES = ["gemm_f64", "gemm_f32", "inv_panel", "inv_swap", "inv_perm", "elementwise", "inv_update_gemm"]
-KC_COUNT = 7
+KC_NAMES = ["gemm_f64", "gemm_f32", "inv_panel", "inv_swap", "inv_perm", "elementwise", "inv_update_gemm",
+            "gemm_coupling"]
+KC_COUNT = 8
 
 
 class negf_device(C.Structure):
@@ -41,7 +42,7 @@ class negf_problem(C.Structure):
 class negf_options(C.Structure):
     _fields_ = [("sr_tol", C.c_double), ("sr_max_iter", C.c_int32), ("sr_accept", C.c_double),
                 ("batch", C.c_int32), ("inv_nb", C.c_int32), ("xcd_remap", C.c_int32), ("gemm_tile", C.c_int32),
-                ("gemm_tile_f32", C.c_int32), ("cmul", C.c_int32)]
+                ("gemm_tile_f32", C.c_int32), ("cmul", C.c_int32), ("dense_coupling", C.c_int32)]
 
 
 class negf_tuning(C.Structure):
@@ -254,10 +255,13 @@ def _problem_array(problems: Sequence[Problem]):
 
 
 def make_options(sr_tol=0.0, sr_max_iter=0, sr_accept=0.0, batch=0, inv_nb=0, xcd_remap=-1, gemm_tile=0,
-                 gemm_tile_f32=0, cmul=0):
+                 gemm_tile_f32=0, cmul=0, dense_coupling=0):
     """negf_options; 0 (or -1 for xcd_remap) leaves a knob at the library default.
-    cmul: real products per complex double product, 4 or 3 (Gauss's method)."""
-    return negf_options(sr_tol, sr_max_iter, sr_accept, batch, inv_nb, xcd_remap, gemm_tile, gemm_tile_f32, cmul)
+    cmul: real products per complex double product, 4 or 3 (Gauss's method).
+    dense_coupling: 1 multiplies the coupling blocks as dense blocks (no skipping
+    of their zero slabs)."""
+    return negf_options(sr_tol, sr_max_iter, sr_accept, batch, inv_nb, xcd_remap, gemm_tile, gemm_tile_f32, cmul,
+                        dense_coupling)
 
 
 def _alloc_blocks(problems, per_point_blocks):

@@ -34,6 +34,7 @@ struct Opts {
   int tile = GEMM_TILE_64;
   int tile32 = GEMM_TILE_64;
   int gauss = 0;
+  int dense = 0;       // 1: coupling blocks are multiplied as dense blocks
 };
 
 Opts get_opts(const negf_options* o) {
@@ -49,6 +50,7 @@ Opts get_opts(const negf_options* o) {
   if (o->gemm_tile_f32 >= GEMM_TILE_64 && o->gemm_tile_f32 <= GEMM_TILE_LAST) r.tile32 = o->gemm_tile_f32;
   if (o->cmul == 3) r.gauss = 1;
   if (o->cmul == 4) r.gauss = 0;
+  if (o->dense_coupling == 1) r.dense = 1;
   return r;
 }
 
@@ -140,6 +142,7 @@ struct PointWs {   // per point persistent data of the sweeps
   Blocks T0, T1, T2, T3, T4, C0, C1;
   void* inv_scratch;
   double* dot;
+  unsigned long long* cmask;   // zero-slab maps of the coupling blocks, [nb-1][b/64] (nullable)
 };
 
 Blocks take_blocks(Carver& cv, int b, int n) {
@@ -180,6 +183,7 @@ ChunkWs carve_chunk(Carver& cv, int opk, int nb, int b, int npts, negf_precision
     p.X = (opk == OPK_T) ? nullptr : cv.take<double2>((size_t)npts * (nb - 1) * b * b);
     p.Mst = (prec == NEGF_FP32_REFINE && opk != OPK_T) ? cv.take<double2>((size_t)npts * nb * b * b) : nullptr;
     p.dot = cv.take<double>(npts);
+    p.cmask = (b % 64 == 0 && b <= 1024) ? cv.take<unsigned long long>((size_t)(nb - 1) * (b / 64)) : nullptr;
   }
   // shared region
   Carver sub{cv.base ? cv.base + cv.off : nullptr, cv.base ? cv.cap - std::min(cv.cap, cv.off) : 0};
@@ -212,9 +216,17 @@ struct Ctx {
   // Not used by the sweeps: at the conditioning of these devices the non-anti-Hermitian
   // rounding of a full product (~1e-8 relative) is what the oracle also carries, and
   // mirroring one triangle moves the result that far from it.
+  // zero-slab maps of the current chunk's coupling blocks (nullptr: treat them as dense)
+  const unsigned long long* cmask = nullptr;
+  int cmask_words = 0;
+  // map of coupling block i when it enters a product as op(B) = A_{i,i+1} (op 1)
+  // or as op(A) = A_{i,i+1}^H (op 2)
+  struct KMask { const unsigned long long* m; int op; };
+  KMask cpl(int i, int op) const { return cmask ? KMask{cmask + (long)i * cmask_words, op} : KMask{nullptr, 0}; }
+
   void gemm(Prec pr, Op oa, Op ob, int b, int batch, double2 alpha, const double2* A, long sA, const double2* B,
             long sB, double2 beta, const double2* Cin, long sCin, double2* C, long sC, const int* active = nullptr,
-            bool skew = false) {
+            bool skew = false, KMask km = KMask{nullptr, 0}) {
     if (!ok()) return;
     GemmDesc g{};
     g.M = b; g.N = b; g.K = b; g.batch = batch;
@@ -231,6 +243,8 @@ struct Ctx {
     g.prof_class = -1;
     g.gauss = pr == PREC_F64 ? o.gauss : 0;
     g.skew = skew ? 1 : 0;
+    g.kmask = km.m;
+    g.kmask_op = km.op;
     chk(launch_gemm(g, s));
   }
   void inverse(int b, int batch, double2* M, long sM, double2* out, long sO, void* scratch, int* info, int info_mod,
@@ -501,8 +515,10 @@ void forward_retarded(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec
       assemble_upper(cx, ch, i - 1, pw.T1);
       double2* Xi = want_X ? pw.X + (long)(i - 1) * bb : pw.T2.p;
       const long sX = want_X ? xs : bb;
-      cx.gemm(pf, OP_N, OP_N, b, n, ONE, g_prev, gstride, pw.T1.p, bb, ZERO, nullptr, 0, Xi, sX);
-      cx.gemm(pf, OP_C, OP_N, b, n, MONE, pw.T1.p, bb, Xi, sX, ONE, pw.T0.p, bb, pw.T0.p, bb);
+      cx.gemm(pf, OP_N, OP_N, b, n, ONE, g_prev, gstride, pw.T1.p, bb, ZERO, nullptr, 0, Xi, sX, nullptr, false,
+              cx.cpl(i - 1, 1));
+      cx.gemm(pf, OP_C, OP_N, b, n, MONE, pw.T1.p, bb, Xi, sX, ONE, pw.T0.p, bb, pw.T0.p, bb, nullptr, false,
+              cx.cpl(i - 1, 2));
     }
     if (pw.Mst) cx.lincomb(b, n, ONE, pw.T0.p, bb, ZERO, nullptr, 0, ZERO, pw.Mst + (long)i * bb, ms);
     double2* gi = gdiag + (long)i * bb;
@@ -512,7 +528,8 @@ void forward_retarded(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec
         cx.lincomb(b, n, ONE, gi, gstride, ZERO, nullptr, 0, ZERO, C.p, bb);
       } else {
         // C_i = -g_i (A_{i,i-1} C_{i-1}),  A_{i,i-1} = T1^H
-        cx.gemm(PREC_F64, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, C.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
+        cx.gemm(PREC_F64, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, C.p, bb, ZERO, nullptr, 0, pw.T3.p, bb, nullptr, false,
+                cx.cpl(i - 1, 2));
         cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, gi, gstride, pw.T3.p, bb, ZERO, nullptr, 0, Cn.p, bb);
         std::swap(C, Cn);
       }
@@ -540,7 +557,8 @@ void backward_retarded(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision pre
     const long sLo = GRl ? us : bb;
     double2* Gup = GRu + (long)i * bb;
     // W = A_{i+1,i} g_i ; G_{i+1,i} = -G_{i+1,i+1} W
-    cx.gemm(pb, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gi, ds, ZERO, nullptr, 0, pw.T2.p, bb);
+    cx.gemm(pb, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gi, ds, ZERO, nullptr, 0, pw.T2.p, bb, nullptr, false,
+            cx.cpl(i, 2));
     cx.gemm(pb, OP_N, OP_N, b, n, MONE, Gn, ds, pw.T2.p, bb, ZERO, nullptr, 0, Glo, sLo);
     double2* Mi = refine ? pw.Mst + (long)i * bb : nullptr;
     if (refine) {
@@ -587,9 +605,10 @@ void forward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, 
     const bool has_sig = assemble_sigma_lg(cx, ch, i, kind, pw, pw.T4);
     if (i > 0) {
       assemble_upper(cx, ch, i - 1, pw.T1);   // A_{i-1,i}; A_{i,i-1} = T1^H
-      cx.gemm(pbt, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gl + (long)(i - 1) * bb, ds, ZERO, nullptr, 0, pw.T2.p, bb);
+      cx.gemm(pbt, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gl + (long)(i - 1) * bb, ds, ZERO, nullptr, 0, pw.T2.p, bb,
+              nullptr, false, cx.cpl(i - 1, 2));
       cx.gemm(pbt, OP_N, OP_N, b, n, ONE, pw.T2.p, bb, pw.T1.p, bb, has_sig ? ONE : ZERO, has_sig ? pw.T4.p : nullptr,
-              bb, pw.T4.p, bb);
+              bb, pw.T4.p, bb, nullptr, false, cx.cpl(i - 1, 1));
     } else if (!has_sig) {
       cx.lincomb(b, n, ZERO, nullptr, 0, ZERO, nullptr, 0, ZERO, pw.T4.p, bb);
     }
@@ -609,7 +628,8 @@ void backward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec,
     double2* gli = Ld + (long)i * bb;                 // holds g^<_i
     const double2* Xi = pw.X + (long)i * bb;
     // V = A_{i+1,i} g^<_i
-    cx.gemm(pp, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gli, ds, ZERO, nullptr, 0, pw.T2.p, bb);
+    cx.gemm(pp, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gli, ds, ZERO, nullptr, 0, pw.T2.p, bb, nullptr, false,
+            cx.cpl(i, 2));
     // Q = -G_{i,i+1} V
     cx.gemm(pp, OP_N, OP_N, b, n, MONE, GRu + (long)i * bb, us, pw.T2.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
     // Z = X_i G^<_{i+1,i+1}
@@ -676,6 +696,19 @@ void run_chunk(Ctx& cx, int opk, const Chunk& ch, ChunkWs& w, negf_precision pre
   int* info = outs.info + ch.first_point;
   const bool lesser = opk == OPK_RL;
   leads_for_sweeps(cx, ch, w, info, lesser);
+  // zero-slab maps of the coupling blocks A_{i,i+1} = E S_{i,i+1} - H_{i,i+1} (the union
+  // over the chunk's devices): products with a coupling operand skip its zero slabs
+  cx.cmask = nullptr;
+  if (w.pw.cmask && !cx.o.dense && cx.ok()) {
+    int q = 0;
+    for (const Seg& sg : ch.segs) {
+      const negf_device& dv = sg.pr->dev;
+      cx.chk(launch_slab_map(ch.b, ch.nb - 1, (const double2*)dv.H_upper, (const double2*)dv.S_upper, w.pw.cmask,
+                             q++ > 0, cx.s));
+    }
+    cx.cmask = w.pw.cmask;
+    cx.cmask_words = ch.b / 64;
+  }
   const long bb = (long)ch.b * ch.b;
   const int b = ch.b, nb = ch.nb, n = ch.npts;
   if (opk == OPK_T) {
@@ -685,14 +718,17 @@ void run_chunk(Ctx& cx, int opk, const Chunk& ch, ChunkWs& w, negf_precision pre
       assemble_diag(cx, ch, i, w.pw, w.pw.T0);
       if (i > 0) {
         assemble_upper(cx, ch, i - 1, w.pw.T1);
-        cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, gprev.p, bb, w.pw.T1.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb);
-        cx.gemm(PREC_F64, OP_C, OP_N, b, n, MONE, w.pw.T1.p, bb, w.pw.T3.p, bb, ONE, w.pw.T0.p, bb, w.pw.T0.p, bb);
+        cx.gemm(PREC_F64, OP_N, OP_N, b, n, ONE, gprev.p, bb, w.pw.T1.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb,
+                nullptr, false, cx.cpl(i - 1, 1));
+        cx.gemm(PREC_F64, OP_C, OP_N, b, n, MONE, w.pw.T1.p, bb, w.pw.T3.p, bb, ONE, w.pw.T0.p, bb, w.pw.T0.p, bb,
+                nullptr, false, cx.cpl(i - 1, 2));
       }
       cx.inverse(b, n, w.pw.T0.p, bb, gcur.p, bb, w.pw.inv_scratch, info, 0);
       if (i == 0) {
         cx.lincomb(b, n, ONE, gcur.p, bb, ZERO, nullptr, 0, ZERO, C.p, bb);
       } else {
-        cx.gemm(PREC_F64, OP_C, OP_N, b, n, ONE, w.pw.T1.p, bb, C.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb);
+        cx.gemm(PREC_F64, OP_C, OP_N, b, n, ONE, w.pw.T1.p, bb, C.p, bb, ZERO, nullptr, 0, w.pw.T3.p, bb, nullptr,
+                false, cx.cpl(i - 1, 2));
         cx.gemm(PREC_F64, OP_N, OP_N, b, n, MONE, gcur.p, bb, w.pw.T3.p, bb, ZERO, nullptr, 0, Cn.p, bb);
         std::swap(C, Cn);
       }

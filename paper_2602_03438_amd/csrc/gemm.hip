@@ -79,6 +79,8 @@ struct KArgs {
   const int* active;
   int tiles_m, tiles_n, xcd_remap;
   int upper;   // skip tiles that lie entirely below the diagonal
+  const unsigned long long* kmask;   // zero-slab map of a sparse operand (64 x 64 tiles only)
+  int kmask_op;                      // 1: indexed by the column tile, 2: by the row tile
 };
 
 template <int BM_, int BN_, int WM_, int WN_>
@@ -148,8 +150,8 @@ __device__ __forceinline__ void store_tile_v(typename Cx<T>::type* s, const v2d 
   }
 }
 
-// TAG only separates the symbol of the inversion updates from the sweep
-// products in profiles; the code is the same.  FULL: M, N and K are multiples
+// TAG only separates symbols in profiles (0: sweep products, 1: inversion
+// updates, 2: products with a sparse coupling operand); the code is the same.  FULL: M, N and K are multiples
 // of the tile and of the K-step, so no operand or result access needs a bounds
 // test; operand tiles are then fetched two K-steps ahead (two register sets)
 // instead of one.
@@ -263,20 +265,34 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
       store_tile_v<T, BM, NT, CF::LA, A_ROW>(sA[st], ra, OPA == OP_C);
       store_tile_v<T, BN, NT, CF::LB, B_ROW>(sB[st], rb, OPB == OP_C);
     };
-    // step k sits in LDS stage k & 1 and arrives through register set k & 1
-    gl(qa[0], qb[0], 0);
-    if (nk > 1) gl(qa[1], qb[1], BK);
-    ls(qa[0], qb[0], 0);
+    // The K-steps that contribute, as a bit set (all of them unless a zero-slab
+    // map of a sparse operand says otherwise); they are taken in ascending
+    // order, the j-th of them in LDS stage j & 1 through register set j & 1.
+    unsigned long long rem = nk >= 64 ? ~0ull : (1ull << nk) - 1;
+    if constexpr (BM == 64 && BN == 64) {
+      if (a.kmask && nk <= 64) rem &= a.kmask[a.kmask_op == 1 ? tn : tm];
+    }
+    const int nact = __popcll(rem);
+    auto next_k = [&]() {
+      const int k = __builtin_ctzll(rem);
+      rem &= rem - 1;
+      return k * BK;
+    };
+    if (nact > 0) {
+      gl(qa[0], qb[0], next_k());
+      if (nact > 1) gl(qa[1], qb[1], next_k());
+      ls(qa[0], qb[0], 0);
+    }
     __syncthreads();
-    for (int kt = 0; kt < nk; kt += 2) {
-      if (kt + 2 < nk) gl(qa[0], qb[0], (kt + 2) * BK);
+    for (int j = 0; j < nact; j += 2) {
+      if (j + 2 < nact) gl(qa[0], qb[0], next_k());
       mac(sA[0], sB[0]);
-      if (kt + 1 < nk) ls(qa[1], qb[1], 1);
+      if (j + 1 < nact) ls(qa[1], qb[1], 1);
       __syncthreads();
-      if (kt + 1 < nk) {
-        if (kt + 3 < nk) gl(qa[1], qb[1], (kt + 3) * BK);
+      if (j + 1 < nact) {
+        if (j + 3 < nact) gl(qa[1], qb[1], next_k());
         mac(sA[1], sB[1]);
-        if (kt + 2 < nk) ls(qa[0], qb[0], 0);
+        if (j + 2 < nact) ls(qa[0], qb[0], 0);
         __syncthreads();
       }
     }
@@ -360,6 +376,17 @@ typedef Cfg<128, 64, 8, 2> Cfg128x64w16;   // 16 waves of 16 x 32
 template <typename T, typename CF, bool GAUSS, bool FULL>
 void launch_ops(const GemmDesc& d, const KArgs& ka, dim3 grid, hipStream_t s) {
   const dim3 block(CF::NT);
+  // products that skip the zero slabs of a coupling operand: a symbol of their own (tag 2)
+  if constexpr (FULL && CF::BM == 64 && CF::BN == 64) {
+    if (ka.kmask && ka.kmask_op == 1 && d.opA == OP_N && d.opB == OP_N) {
+      hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 2, GAUSS, FULL>), grid, block, 0, s, ka);
+      return;
+    }
+    if (ka.kmask && ka.kmask_op == 2 && d.opA == OP_C && d.opB == OP_N) {
+      hipLaunchKernelGGL((zgemm_kernel<T, OP_C, OP_N, CF, 2, GAUSS, FULL>), grid, block, 0, s, ka);
+      return;
+    }
+  }
   if (d.prof_class == KC_INV_GEMM && d.opA == OP_N && d.opB == OP_N)
     hipLaunchKernelGGL((zgemm_kernel<T, OP_N, OP_N, CF, 1, GAUSS, FULL>), grid, block, 0, s, ka);
   else if (d.prof_class == KC_INV_GEMM && d.opA == OP_C && d.opB == OP_N)
@@ -438,6 +465,34 @@ __global__ void __launch_bounds__(256) skew_mirror_kernel(int n, double2* C, lon
   }
 }
 
+// Zero-slab map: one workgroup per (block, 64-column tile); bit k of the word
+// marks a nonzero in rows [16k, 16k+16) of the tile's columns, in H or S.
+__global__ void __launch_bounds__(256) slab_map_kernel(int b, const double2* H, const double2* S,
+                                                       unsigned long long* out, int accumulate) {
+  const int c = blockIdx.x, i = blockIdx.y, t = threadIdx.x;
+  const long off = (long)i * b * b + 64 * c;
+  __shared__ unsigned long long word;
+  if (t == 0) word = 0ull;
+  __syncthreads();
+  unsigned long long w = 0ull;
+  for (int e = t; e < b * 64; e += 256) {
+    const int r = e >> 6, cc = e & 63;
+    const double2 h = H[off + (long)r * b + cc];
+    bool nz = h.x != 0.0 || h.y != 0.0;
+    if (S) {
+      const double2 v = S[off + (long)r * b + cc];
+      nz = nz || v.x != 0.0 || v.y != 0.0;
+    }
+    if (nz) w |= 1ull << (r >> 4);
+  }
+  if (w) atomicOr(&word, w);
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long* o = out + (long)i * (b / 64) + c;
+    *o = accumulate ? (*o | word) : word;
+  }
+}
+
 // Fraction of the output tiles a launch computes (all, or those touching the upper triangle).
 template <typename CF>
 double computed_fraction(int M, int N, bool upper) {
@@ -475,13 +530,18 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
   ka.active = d.active;
   ka.xcd_remap = d.xcd_remap;
   ka.tiles_m = ka.tiles_n = 0;
+  ka.kmask = (d.kmask_op == 1 || d.kmask_op == 2) ? d.kmask : nullptr;
+  ka.kmask_op = d.kmask_op;
   if (d.skew && d.M != d.N) return hipErrorInvalidValue;
   ka.upper = d.skew ? 1 : 0;
   int tile = d.tile;
   if (tile == GEMM_TILE_DEFAULT) tile = GEMM_TILE_64;
   const bool gauss = d.prec != PREC_F32 && d.gauss;
   const double frac = tile_fraction(tile, gauss, d.M, d.N, d.skew != 0);
-  const int cls = d.prof_class >= 0 ? d.prof_class : (d.prec == PREC_F32 ? KC_GEMM32 : KC_GEMM64);
+  const bool coupling = ka.kmask && (ka.kmask_op == 1 || ka.kmask_op == 2);
+  const int cls = d.prof_class >= 0 ? d.prof_class
+                  : coupling        ? KC_GEMM_CPL
+                                    : (d.prec == PREC_F32 ? KC_GEMM32 : KC_GEMM64);
   prof_begin(cls, s);
   hipError_t e = d.prec == PREC_F32 ? launch_t<float, false>(d, ka, tile, s)
                  : gauss            ? launch_t<double, true>(d, ka, tile, s)
@@ -495,6 +555,14 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_slab_map(int b, int nblk, const double2* H, const double2* S, unsigned long long* out,
+                           int accumulate, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  if (b % 64 != 0 || b > 1024 || !H || !out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(slab_map_kernel, dim3(b / 64, nblk), dim3(256), 0, s, b, H, S, out, accumulate);
+  return hipGetLastError();
 }
 
 }  // namespace negf

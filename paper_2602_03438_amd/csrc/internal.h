@@ -39,8 +39,23 @@ struct GemmDesc {
   int skew;            // the result is anti-Hermitian (M == N): only tiles touching the upper
                        // triangle are computed, the strict lower triangle is then set to -conj
                        // of the upper one
+  // Zero-slab map of a sparse operand T (a b x b block stored row-major, shared
+  // by all items): kmask[c] bit k is set when T[16k .. 16k+15][64c .. 64c+63]
+  // holds a nonzero.  kmask_op 1: op(B) = T (K-steps of column tile c of B);
+  // 2: op(A) = T^H (K-steps of row tile c of op(A)).  K-steps whose slab is
+  // zero contribute exact zeros and are skipped.  Used by 64 x 64 tiles on
+  // whole-tile sizes with K <= 1024; ignored otherwise.
+  const unsigned long long* kmask;
+  int kmask_op;
 };
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
+
+// Zero-slab maps (see GemmDesc::kmask) of nblk b x b blocks T_i = x H_i + y S_i
+// for any x, y: a slab is marked when H_i or S_i (nullable) has a nonzero in
+// it.  out: nblk * (b / 64) words; accumulate = 1 ORs into the existing words.
+// b must be a multiple of 64 and at most 1024.
+hipError_t launch_slab_map(int b, int nblk, const double2* H, const double2* S, unsigned long long* out,
+                           int accumulate, hipStream_t s);
 
 // Blocked Gauss-Jordan inversion with partial pivoting of a batch of n x n
 // matrices.  M is overwritten; the inverse is written to out (may not alias M).
@@ -145,7 +160,7 @@ double rt_wallclock_hz();
 // *dst = device wall clock (constant-rate counter) when the stream reaches this point
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 enum KernelClass { KC_GEMM64 = 0, KC_GEMM32 = 1, KC_INV_PANEL = 2, KC_INV_SWAP = 3, KC_INV_PERM = 4, KC_ELEM = 5,
-                   KC_INV_GEMM = 6, KC_COUNT = 7 };
+                   KC_INV_GEMM = 6, KC_GEMM_CPL = 7, KC_COUNT = 8 };
 void prof_begin(int cls, hipStream_t s);
 void prof_end(int cls, hipStream_t s, double flops, double bytes);
 

@@ -132,7 +132,7 @@ if __name__ == "__main__":
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--calib-mib", type=int, default=1024)
-    ap.add_argument("--kernel", default=r"zgemm_kernel<double, [01], [01], [^>]*Cfg<\d+, \d+, \d, \d>, 0(, (true|false))?>")
+    ap.add_argument("--kernel", default=r"zgemm_kernel<double, [01], [01], [^>]*Cfg<\d+, \d+, \d, \d>, 0(, (true|false))*>")
     ap.add_argument("--block", type=int, default=512, help="block size b of the products")
     ap.add_argument("--json")
     ap.add_argument("--note", default="", help="what the counter runs measured (stored in the JSON)")

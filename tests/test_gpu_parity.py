@@ -134,6 +134,26 @@ def test_lesser_greater_slab(nb, b, scatter, cmul):
         _cmp_point(out, k, ref, names, tol)
 
 
+@pytest.mark.parametrize("b,cmul,prec", [(256, 4, 0), (512, 3, 0), (256, 3, 1)])
+def test_coupling_slab_skip_matches_dense(nb, b, cmul, prec):
+    """Products with a coupling operand skip its zero 16 x 64 slabs; the skipped
+    terms are exact zeros, so every output equals the dense computation."""
+    import torch
+    dev = w.slab_device(4, b, 2)
+    w.scattering_self_energies(dev, 3)
+    energies = np.array([-0.7, 0.33])
+    prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
+    sparse = nb.rgf_lesser_greater([prob], prec=prec, greater=True, opts=nb.make_options(cmul=cmul))
+    dense = nb.rgf_lesser_greater([prob], prec=prec, greater=True,
+                                  opts=nb.make_options(cmul=cmul, dense_coupling=1))
+    assert torch.equal(sparse["info"], dense["info"])
+    for key in ("GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper", "GG_diag", "GG_upper"):
+        assert torch.equal(sparse[key][0], dense[key][0]), key
+    t_sparse = nb.transmission([prob])
+    t_dense = nb.transmission([prob], opts=nb.make_options(dense_coupling=1))
+    assert torch.equal(t_sparse["T"], t_dense["T"])
+
+
 def test_lesser_gpu_identities(nb):
     """I4 and I5 on GPU outputs: G^R - G^A = G^> - G^< and anti-Hermitian G^<."""
     dev = w.slab_device(4, 96, 7)

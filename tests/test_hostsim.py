@@ -14,7 +14,7 @@ import pytest
 import workloads as w
 from oracle import leads as oleads
 from oracle import rgf as orgf
-from helpers import well_posed
+from helpers import point_tolerance, well_posed
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -121,6 +121,23 @@ def test_hostsim_chosen_forms(sim, prec, tol):
     assert e_r < tol and e_l < tol
     if prec == 1:
         assert e_r < 1e-8
+
+
+def test_hostsim_coupling_slab_maps(sim):
+    """b = 128 slab: the products that take a coupling block skip its zero
+    16 x 64 slabs.  The test double rejects a map that marks a nonzero slab as
+    zero (wrong block or operand), and the results equal the dense ones."""
+    L, nb = sim
+    dev = w.slab_device(3, 128, 2)
+    E = np.array([0.3])
+    p = HostProblem(nb, dev, E)
+    sparse, info_s = _run_rgf(L, nb, [p], greater=False)
+    dense, info_d = _run_rgf(L, nb, [p], greater=False, opts=nb.make_options(dense_coupling=1))
+    assert np.all(info_s == info_d)
+    for k in ("GRd", "GRu", "GRl", "GLd", "GLu"):
+        assert np.array_equal(sparse[k], dense[k]), k
+    ref, tol = point_tolerance(lambda: orgf.solve_point(dev, 0.3, 1e-8, 0.1, -0.1, 0.025), ["GR_diag"])
+    assert rel(_unpack(sparse["GRd"], [p], 1)[0][0], ref.GR_diag) < tol["GR_diag"]
 
 
 def test_hostsim_mixed_shapes_and_chunking(sim):
