@@ -142,7 +142,7 @@ struct PointWs {   // per point persistent data of the sweeps
   Blocks T0, T1, T2, T3, T4, C0, C1;
   void* inv_scratch;
   double* dot;
-  unsigned long long* cmask;   // zero-slab maps of the coupling blocks, [nb-1][b/64] (nullable)
+  unsigned long long* cmask;   // zero-slab maps of the coupling blocks, [nb-1][b/16] (nullable)
 };
 
 Blocks take_blocks(Carver& cv, int b, int n) {
@@ -183,7 +183,7 @@ ChunkWs carve_chunk(Carver& cv, int opk, int nb, int b, int npts, negf_precision
     p.X = (opk == OPK_T) ? nullptr : cv.take<double2>((size_t)npts * (nb - 1) * b * b);
     p.Mst = (prec == NEGF_FP32_REFINE && opk != OPK_T) ? cv.take<double2>((size_t)npts * nb * b * b) : nullptr;
     p.dot = cv.take<double>(npts);
-    p.cmask = (b % 64 == 0 && b <= 1024) ? cv.take<unsigned long long>((size_t)(nb - 1) * (b / 64)) : nullptr;
+    p.cmask = (b % 64 == 0 && b <= 1024) ? cv.take<unsigned long long>((size_t)(nb - 1) * (b / 16)) : nullptr;
   }
   // shared region
   Carver sub{cv.base ? cv.base + cv.off : nullptr, cv.base ? cv.cap - std::min(cv.cap, cv.off) : 0};
@@ -707,7 +707,7 @@ void run_chunk(Ctx& cx, int opk, const Chunk& ch, ChunkWs& w, negf_precision pre
                              q++ > 0, cx.s));
     }
     cx.cmask = w.pw.cmask;
-    cx.cmask_words = ch.b / 64;
+    cx.cmask_words = ch.b / 16;
   }
   const long bb = (long)ch.b * ch.b;
   const int b = ch.b, nb = ch.nb, n = ch.npts;

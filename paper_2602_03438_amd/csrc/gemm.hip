@@ -199,57 +199,116 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
     for (int j = 0; j < FN; ++j) accS[i][j] = AT{0, 0, 0, 0};
 
   const int nk = (a.K + BK - 1) / BK;
-  // one K-step of MFMAs on the LDS stage (xA, xB)
-  auto mac = [&](const CT* __restrict__ xA, const CT* __restrict__ xB) {
+  // one K-step of MFMAs on the LDS stage (xA, xB); bit i*FN+j of `on` enables the
+  // products of the wave's row fragment i with its column fragment j (all of them
+  // unless a sparse operand's fragment is zero in this K-step)
+  constexpr unsigned ALL_ON = (1u << (FM * FN)) - 1u;
+  // only the products with a sparse operand (tag 2, 64 x 64 tiles) read a zero-slab map
+  constexpr bool SPARSE_OK = TAG == 2 && BM == 64 && BN == 64;
+  auto mac = [&](const CT* __restrict__ xA, const CT* __restrict__ xB, unsigned on) {
+    if (!SPARSE_OK) {
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int kq = kk * 4 + lk;
-      CT av[FM], bv[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) {
-        const int m = wm * CF::TM + i * 16 + li;
-        av[i] = A_ROW ? xA[m * CF::LD_ROW + kq] : xA[kq * CF::LDA_COL + m];
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kq = kk * 4 + lk;
+        CT av[FM], bv[FN];
+  #pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          const int m = wm * CF::TM + i * 16 + li;
+          av[i] = A_ROW ? xA[m * CF::LD_ROW + kq] : xA[kq * CF::LDA_COL + m];
+        }
+  #pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int n = wn * CF::TN + j * 16 + li;
+          bv[j] = B_ROW ? xB[n * CF::LD_ROW + kq] : xB[kq * CF::LDB_COL + n];
+        }
+        if constexpr (GAUSS) {
+          T as[FM], bs[FN];
+  #pragma unroll
+          for (int i = 0; i < FM; ++i) as[i] = av[i].x + av[i].y;
+  #pragma unroll
+          for (int j = 0; j < FN; ++j) bs[j] = bv[j].x + bv[j].y;
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].y, accI[i][j]);
+  #pragma unroll
+          for (int i = 0; i < NS; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) accS[i][j] = mfma16(as[i], bs[j], accS[i][j]);
+        } else {
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
+        }
       }
+    } else {
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int n = wn * CF::TN + j * 16 + li;
-        bv[j] = B_ROW ? xB[n * CF::LD_ROW + kq] : xB[kq * CF::LDB_COL + n];
-      }
-      if constexpr (GAUSS) {
-        T as[FM], bs[FN];
-#pragma unroll
-        for (int i = 0; i < FM; ++i) as[i] = av[i].x + av[i].y;
-#pragma unroll
-        for (int j = 0; j < FN; ++j) bs[j] = bv[j].x + bv[j].y;
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].y, accI[i][j]);
-#pragma unroll
-        for (int i = 0; i < NS; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) accS[i][j] = mfma16(as[i], bs[j], accS[i][j]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kq = kk * 4 + lk;
+        CT av[FM], bv[FN];
+  #pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          const int m = wm * CF::TM + i * 16 + li;
+          av[i] = A_ROW ? xA[m * CF::LD_ROW + kq] : xA[kq * CF::LDA_COL + m];
+        }
+  #pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int n = wn * CF::TN + j * 16 + li;
+          bv[j] = B_ROW ? xB[n * CF::LD_ROW + kq] : xB[kq * CF::LDB_COL + n];
+        }
+        if constexpr (GAUSS) {
+          T as[FM], bs[FN];
+  #pragma unroll
+          for (int i = 0; i < FM; ++i) as[i] = av[i].x + av[i].y;
+  #pragma unroll
+          for (int j = 0; j < FN; ++j) bs[j] = bv[j].x + bv[j].y;
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accI[i][j] = mfma16(av[i].y, bv[j].y, accI[i][j]);
+  #pragma unroll
+          for (int i = 0; i < NS; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accS[i][j] = mfma16(as[i], bs[j], accS[i][j]);
+        } else {
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
+  #pragma unroll
+          for (int i = 0; i < FM; ++i)
+  #pragma unroll
+            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
+        }
       }
     }
   };
@@ -269,30 +328,69 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
     // map of a sparse operand says otherwise); they are taken in ascending
     // order, the j-th of them in LDS stage j & 1 through register set j & 1.
     unsigned long long rem = nk >= 64 ? ~0ull : (1ull << nk) - 1;
-    if constexpr (BM == 64 && BN == 64) {
-      if (a.kmask && nk <= 64) rem &= a.kmask[a.kmask_op == 1 ? tn : tm];
+    // per wave: K-steps in which each of its row (op 2) or column (op 1) fragments is nonzero
+    unsigned long long fm[CF::FM > CF::FN ? CF::FM : CF::FN];
+    const bool sparse = SPARSE_OK && a.kmask && nk <= 64;
+    if (sparse) {
+      const unsigned long long* w4 = a.kmask + (a.kmask_op == 1 ? 4 * tn : 4 * tm);
+      rem &= w4[0] | w4[1] | w4[2] | w4[3];
+      const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+      const int g0 = a.kmask_op == 1 ? (wv % CF::WN) * CF::TN / 16 : (wv / CF::WN) * CF::TM / 16;
+#pragma unroll
+      for (int f = 0; f < (a.kmask_op == 1 ? FN : FM); ++f) fm[f] = w4[g0 + f];
     }
+    auto enables = [&](int k) -> unsigned {
+      if (!sparse) return ALL_ON;
+      unsigned on = 0u;
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const unsigned long long w = a.kmask_op == 1 ? fm[j] : fm[i];
+          on |= (unsigned)((w >> k) & 1ull) << (i * FN + j);
+        }
+      return on;
+    };
     const int nact = __popcll(rem);
     auto next_k = [&]() {
       const int k = __builtin_ctzll(rem);
       rem &= rem - 1;
-      return k * BK;
+      return k;
     };
+    // K-step index held by register set 0/1 and by LDS stage 0/1
+    int kset0 = 0, kset1 = 0, kst0 = 0, kst1 = 0;
     if (nact > 0) {
-      gl(qa[0], qb[0], next_k());
-      if (nact > 1) gl(qa[1], qb[1], next_k());
+      kset0 = next_k();
+      gl(qa[0], qb[0], kset0 * BK);
+      if (nact > 1) {
+        kset1 = next_k();
+        gl(qa[1], qb[1], kset1 * BK);
+      }
       ls(qa[0], qb[0], 0);
+      kst0 = kset0;
     }
     __syncthreads();
     for (int j = 0; j < nact; j += 2) {
-      if (j + 2 < nact) gl(qa[0], qb[0], next_k());
-      mac(sA[0], sB[0]);
-      if (j + 1 < nact) ls(qa[1], qb[1], 1);
+      if (j + 2 < nact) {
+        kset0 = next_k();
+        gl(qa[0], qb[0], kset0 * BK);
+      }
+      mac(sA[0], sB[0], enables(kst0));
+      if (j + 1 < nact) {
+        ls(qa[1], qb[1], 1);
+        kst1 = kset1;
+      }
       __syncthreads();
       if (j + 1 < nact) {
-        if (j + 3 < nact) gl(qa[1], qb[1], next_k());
-        mac(sA[1], sB[1]);
-        if (j + 2 < nact) ls(qa[0], qb[0], 0);
+        if (j + 3 < nact) {
+          kset1 = next_k();
+          gl(qa[1], qb[1], kset1 * BK);
+        }
+        mac(sA[1], sB[1], enables(kst1));
+        if (j + 2 < nact) {
+          ls(qa[0], qb[0], 0);
+          kst0 = kset0;
+        }
         __syncthreads();
       }
     }
@@ -315,7 +413,7 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
     for (int kt = 0; kt < nk; ++kt) {
       const int st = kt & 1;
       if (kt + 1 < nk) gload((kt + 1) * BK);
-      mac(sA[st], sB[st]);
+      mac(sA[st], sB[st], ALL_ON);
       if (kt + 1 < nk) lstore(st ^ 1);
       __syncthreads();
     }
@@ -465,16 +563,17 @@ __global__ void __launch_bounds__(256) skew_mirror_kernel(int n, double2* C, lon
   }
 }
 
-// Zero-slab map: one workgroup per (block, 64-column tile); bit k of the word
-// marks a nonzero in rows [16k, 16k+16) of the tile's columns, in H or S.
+// Zero-slab map: one workgroup per (block, 64-column tile), one word per
+// 16-column group of the tile; bit k marks a nonzero in rows [16k, 16k+16) of
+// the group's columns, in H or S.
 __global__ void __launch_bounds__(256) slab_map_kernel(int b, const double2* H, const double2* S,
                                                        unsigned long long* out, int accumulate) {
   const int c = blockIdx.x, i = blockIdx.y, t = threadIdx.x;
   const long off = (long)i * b * b + 64 * c;
-  __shared__ unsigned long long word;
-  if (t == 0) word = 0ull;
+  __shared__ unsigned long long word[4];
+  if (t < 4) word[t] = 0ull;
   __syncthreads();
-  unsigned long long w = 0ull;
+  unsigned long long w[4] = {0ull, 0ull, 0ull, 0ull};
   for (int e = t; e < b * 64; e += 256) {
     const int r = e >> 6, cc = e & 63;
     const double2 h = H[off + (long)r * b + cc];
@@ -483,13 +582,16 @@ __global__ void __launch_bounds__(256) slab_map_kernel(int b, const double2* H, 
       const double2 v = S[off + (long)r * b + cc];
       nz = nz || v.x != 0.0 || v.y != 0.0;
     }
-    if (nz) w |= 1ull << (r >> 4);
+    // a thread's columns stay in one group: e advances by 256 = 4 rows
+    if (nz) w[cc >> 4] |= 1ull << (r >> 4);
   }
-  if (w) atomicOr(&word, w);
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+    if (w[g]) atomicOr(&word[g], w[g]);
   __syncthreads();
-  if (t == 0) {
-    unsigned long long* o = out + (long)i * (b / 64) + c;
-    *o = accumulate ? (*o | word) : word;
+  if (t < 4) {
+    unsigned long long* o = out + (long)i * (b / 16) + 4 * c + t;
+    *o = accumulate ? (*o | word[t]) : word[t];
   }
 }
 

@@ -40,10 +40,11 @@ struct GemmDesc {
                        // triangle are computed, the strict lower triangle is then set to -conj
                        // of the upper one
   // Zero-slab map of a sparse operand T (a b x b block stored row-major, shared
-  // by all items): kmask[c] bit k is set when T[16k .. 16k+15][64c .. 64c+63]
-  // holds a nonzero.  kmask_op 1: op(B) = T (K-steps of column tile c of B);
-  // 2: op(A) = T^H (K-steps of row tile c of op(A)).  K-steps whose slab is
-  // zero contribute exact zeros and are skipped.  Used by 64 x 64 tiles on
+  // by all items): kmask[g] bit k is set when T[16k .. 16k+15][16g .. 16g+15]
+  // holds a nonzero.  kmask_op 1: op(B) = T (column group g of B); 2:
+  // op(A) = T^H (row group g of op(A)).  A tile skips the K-steps in which all
+  // its four groups are zero, a wave the products of its fragments that are
+  // zero in a K-step: exact zeros either way.  Used by 64 x 64 tiles on
   // whole-tile sizes with K <= 1024; ignored otherwise.
   const unsigned long long* kmask;
   int kmask_op;
@@ -52,7 +53,7 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
 
 // Zero-slab maps (see GemmDesc::kmask) of nblk b x b blocks T_i = x H_i + y S_i
 // for any x, y: a slab is marked when H_i or S_i (nullable) has a nonzero in
-// it.  out: nblk * (b / 64) words; accumulate = 1 ORs into the existing words.
+// it.  out: nblk * (b / 16) words; accumulate = 1 ORs into the existing words.
 // b must be a multiple of 64 and at most 1024.
 hipError_t launch_slab_map(int b, int nblk, const double2* H, const double2* S, unsigned long long* out,
                            int accumulate, hipStream_t s);

@@ -34,15 +34,15 @@ static bool kmask_valid(const GemmDesc& d) {
   if (d.M % 64 || d.N % 64 || d.K % 16 || d.K > 1024) return true;   // the kernel ignores the map
   if ((d.kmask_op == 1 && d.opB != OP_N) || (d.kmask_op == 2 && d.opA != OP_C)) return false;
   const MatRef& T = d.kmask_op == 1 ? d.B : d.A;   // stored K x (N or M)
-  const int tiles = (d.kmask_op == 1 ? d.N : d.M) / 64;
+  const int groups = (d.kmask_op == 1 ? d.N : d.M) / 16;
   for (int p = 0; p < d.batch; ++p) {
     if (!act(d.active, p)) continue;
     const double2* Tp = T.p + (long)p * T.stride;
-    for (int c = 0; c < tiles; ++c)
+    for (int c = 0; c < groups; ++c)
       for (int k = 0; k < d.K / 16; ++k) {
         if (d.kmask[c] >> k & 1ull) continue;
         for (int r = 16 * k; r < 16 * k + 16; ++r)
-          for (int j = 64 * c; j < 64 * c + 64; ++j) {
+          for (int j = 16 * c; j < 16 * c + 16; ++j) {
             const double2 v = Tp[(long)r * T.ld + j];
             if (v.x != 0.0 || v.y != 0.0) return false;
           }
@@ -56,15 +56,15 @@ hipError_t launch_slab_map(int b, int nblk, const double2* H, const double2* S, 
   if (nblk <= 0) return hipSuccess;
   if (b % 64 != 0 || b > 1024 || !H || !out) return hipErrorInvalidValue;
   for (int i = 0; i < nblk; ++i)
-    for (int c = 0; c < b / 64; ++c) {
+    for (int c = 0; c < b / 16; ++c) {
       unsigned long long w = 0;
       for (int r = 0; r < b; ++r)
-        for (int j = 64 * c; j < 64 * c + 64; ++j) {
+        for (int j = 16 * c; j < 16 * c + 16; ++j) {
           const long e = (long)i * b * b + (long)r * b + j;
           const bool nz = H[e].x != 0.0 || H[e].y != 0.0 || (S && (S[e].x != 0.0 || S[e].y != 0.0));
           if (nz) w |= 1ull << (r / 16);
         }
-      unsigned long long& o = out[(long)i * (b / 64) + c];
+      unsigned long long& o = out[(long)i * (b / 16) + c];
       o = accumulate ? (o | w) : w;
     }
   return hipSuccess;
