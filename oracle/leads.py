@@ -99,6 +99,60 @@ def sancho_rubio(d, alpha, beta, tol=TAU_DEFAULT, max_iter=100):
     return np.linalg.inv(eps_s), it, converged
 
 
+def seeded_closure(eps, eps_s, a, c, d_seed):
+    """Surface Green's function of the decimated chain closed with a seed.
+
+    After k decimation steps the lead is the surface cell (eps_s) coupled by
+    a, c to a cell whose onsite block, seen from the surface, is its own
+    renormalisation from the decimated cells between them (eps - eps_s) plus
+    the original onsite block and the exact self-energy of the undecimated
+    lead beyond it: d - alpha g_s beta.  With g_s replaced by a seed g~
+    (d_seed = d - alpha g~ beta):
+        X = (eps - eps_s + d_seed)^{-1},  g = (eps_s - a X c)^{-1}.
+    For g~ = g_s this is exact at every step; as a, c vanish it tends to
+    eps_s^{-1}, the plain decimation result.
+    """
+    X = np.linalg.inv(eps - eps_s + d_seed)
+    return np.linalg.inv(eps_s - a @ X @ c)
+
+
+def seeded_sancho_rubio(d, alpha, beta, g_seed, accept=1e-8, tol=TAU_DEFAULT, max_iter=100):
+    """Decimation seeded with a guess g~ of the surface Green's function.
+
+    1. candidate g0 = (d - alpha g~ beta)^{-1}; accepted (0 steps) when its
+       normalised Dyson residual is <= accept;
+    2. otherwise plain decimation steps; after step k the seeded closure
+       (seeded_closure) is accepted at the first k where its residual is
+       <= accept;
+    3. otherwise the plain result when the decimation converges.
+    Returns (g_s, steps, how) with how in {"candidate", "closure", "plain"}.
+    """
+    d_seed = d - alpha @ g_seed @ beta
+    g0 = np.linalg.inv(d_seed)
+    if dyson_residual(d, alpha, beta, g0) <= accept:
+        return g0, 0, "candidate"
+    eps_s = d.copy()
+    eps = d.copy()
+    a = alpha.copy()
+    c = beta.copy()
+    dn = np.linalg.norm(d)
+    it = 0
+    for it in range(1, max_iter + 1):
+        g = np.linalg.inv(eps)
+        agc = a @ g @ c
+        cga = c @ g @ a
+        eps_s = eps_s - agc
+        eps = eps - agc - cga
+        a = a @ g @ a
+        c = c @ g @ c
+        gk = seeded_closure(eps, eps_s, a, c, d_seed)
+        if dyson_residual(d, alpha, beta, gk) <= accept:
+            return gk, it, "closure"
+        if np.linalg.norm(a) <= tol * dn and np.linalg.norm(c) <= tol * dn:
+            break
+    return np.linalg.inv(eps_s), it, "plain"
+
+
 def dyson_residual(d, alpha, beta, g_s) -> float:
     """r = ||(d - alpha g_s beta) g_s - I||_F / (||d - alpha g_s beta||_F ||g_s||_F)."""
     m = d - alpha @ g_s @ beta

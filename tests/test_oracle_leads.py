@@ -88,3 +88,62 @@ def test_lesser_greater_relation():
     # Sigma^> - Sigma^< = -i Gamma for any occupation
     assert np.allclose(sg - sl, -1j * g, atol=1e-15)
     assert np.allclose(sl, 1j * 0.3 * g)
+
+
+def _decimate(d, a, c, steps):
+    """The decimation state (eps, eps_s, a_k, c_k) after each of `steps` steps."""
+    eps_s, eps = d.copy(), d.copy()
+    out = []
+    for _ in range(steps):
+        g = np.linalg.inv(eps)
+        agc, cga = a @ g @ c, c @ g @ a
+        eps_s, eps = eps_s - agc, eps - agc - cga
+        a, c = a @ g @ a, c @ g @ c
+        out.append((eps, eps_s, a, c))
+    return out
+
+
+@pytest.mark.parametrize("case", ["random", "slab"])
+def test_seeded_closure_exact_for_exact_seed(case):
+    """Closing the decimated chain with the exact surface Green's function
+    reproduces it after any number of steps (the closure is an identity, not
+    an approximation, when the seed is exact)."""
+    if case == "random":
+        dev, E, eta, tol = w.random_device(3, 3, 13, overlap=0.05), 0.35, 0.05, 1e-12
+    else:
+        dev, E, eta, tol = w.slab_device(2, 32, 5), 0.1, 1e-8, 1e-9
+    d, a, c = leads.lead_blocks(dev, 0, E, eta)
+    gs, _, conv = leads.sancho_rubio(d, a, c)
+    assert conv
+    d_seed = d - a @ gs @ c
+    for eps, eps_s, ak, ck in _decimate(d, a, c, 5):
+        gk = leads.seeded_closure(eps, eps_s, ak, ck, d_seed)
+        assert np.linalg.norm(gk - gs) <= tol * np.linalg.norm(gs)
+
+
+def test_seeded_closure_tends_to_plain_result():
+    """With a useless seed the closure still converges to eps_s^{-1} as the couplings vanish."""
+    dev = w.random_device(3, 3, 13, overlap=0.05)
+    d, a, c = leads.lead_blocks(dev, 1, 0.35, 0.05)
+    gs, it, _ = leads.sancho_rubio(d, a, c)
+    eps, eps_s, ak, ck = _decimate(d, a, c, it)[-1]
+    gk = leads.seeded_closure(eps, eps_s, ak, ck, d)   # seed 0: d_seed = d
+    assert np.linalg.norm(gk - gs) <= 1e-12 * np.linalg.norm(gs)
+
+
+def test_seeded_decimation_paths():
+    dev = w.slab_device(2, 32, 5)
+    d, a, c = leads.lead_blocks(dev, 0, 0.1, 1e-8)
+    gs, plain_steps, _ = leads.sancho_rubio(d, a, c)
+    r = np.random.default_rng(1)
+    noise = r.standard_normal(gs.shape) + 1j * r.standard_normal(gs.shape)
+    noise *= np.linalg.norm(gs) / np.linalg.norm(noise)
+    g, k, how = leads.seeded_sancho_rubio(d, a, c, gs)
+    assert how == "candidate" and k == 0
+    g, k, how = leads.seeded_sancho_rubio(d, a, c, gs + 1e-6 * noise)
+    assert how == "closure" and 0 < k < plain_steps
+    assert leads.dyson_residual(d, a, c, g) <= 1e-8
+    assert np.linalg.norm(g - gs) <= 1e-6 * np.linalg.norm(gs)
+    g, k, how = leads.seeded_sancho_rubio(d, a, c, np.zeros_like(gs))
+    assert how in ("closure", "plain") and k <= plain_steps
+    assert np.linalg.norm(g - gs) <= 1e-7 * np.linalg.norm(gs)

@@ -102,6 +102,26 @@ def pins(o):
     out["rgf_vs_dense"] = bool(max(rel(r.GR_diag, Gd), rel(r.GR_upper, Gu), rel(r.GR_lower, Glo),
                                    rel(r.GL_diag, Ld), rel(r.GL_upper, Lu2), rel(r.GG_diag, Hd),
                                    rel(r.GG_upper, Hu)) < 1e-10 and abs(r.T - d["T_rl"]) < 1e-10)
+    # seeded closure: exact at every step for the exact seed; a perturbed seed is
+    # taken by the closure before the plain decimation would stop
+    dev = w.random_device(3, 3, 13, overlap=0.05)
+    d_, a_, c_ = o.leads.lead_blocks(dev, 0, 0.35, 0.05)
+    gs, steps, _ = o.leads.sancho_rubio(d_, a_, c_)
+    ok = True
+    eps_s, eps, ak, ck = d_.copy(), d_.copy(), a_.copy(), c_.copy()
+    d_seed = d_ - a_ @ gs @ c_
+    for _ in range(4):
+        g = np.linalg.inv(eps)
+        agc, cga = ak @ g @ ck, ck @ g @ ak
+        eps_s, eps = eps_s - agc, eps - agc - cga
+        ak, ck = ak @ g @ ak, ck @ g @ ck
+        ok &= rel(o.leads.seeded_closure(eps, eps_s, ak, ck, d_seed), gs) < 1e-10
+    g, k, how = o.leads.seeded_sancho_rubio(d_, a_, c_, gs)
+    ok &= how == "candidate" and k == 0 and rel(g, gs) < 1e-12
+    noise = np.random.default_rng(2).standard_normal(gs.shape) * np.linalg.norm(gs) / 3.0
+    g, k, how = o.leads.seeded_sancho_rubio(d_, a_, c_, gs + 1e-6 * noise)
+    ok &= how == "closure" and k < steps and rel(g, gs) < 1e-6
+    out["seeded_closure"] = bool(ok)
     return out
 
 
@@ -127,6 +147,9 @@ MUTATIONS = [
     ("leads", "gam = 1j * (sig - sig.conj().T)", "gam = 1j * (sig - sig.T)"),
     ("leads", "return 1j * f * gamma, -1j * (1.0 - f) * gamma", "return 1j * f * gamma, -1j * f * gamma"),
     ("leads", "H1, S1 = dev.H_upper[0].conj().T, dev.s_upper(0).conj().T", "H1, S1 = dev.H_upper[0], dev.s_upper(0)"),
+    ("leads", "X = np.linalg.inv(eps - eps_s + d_seed)", "X = np.linalg.inv(eps + d_seed)"),
+    ("leads", "return np.linalg.inv(eps_s - a @ X @ c)", "return np.linalg.inv(eps_s - c @ X @ a)"),
+    ("leads", "d_seed = d - alpha @ g_seed @ beta", "d_seed = d - beta @ g_seed @ alpha"),
     ("dense", "A[s1, s0] = up.conj().T", "A[s1, s0] = up.T"),
     ("dense", "Gl = G @ Sl @ GH", "Gl = GH @ Sl @ G"),
     ("dense", "A[N - b:, N - b:] -= sig_right", "A[N - b:, N - b:] += sig_right"),
