@@ -430,7 +430,8 @@ def bench_learned(args):
     t0 = time.perf_counter()
     losses = net.train(X, Tc, epochs=4, batch=65536, lr=1e-3, log=log)
     train_s = time.perf_counter() - t0
-    res = {"plain": {"iters": [], "s": 0.0}, "seeded": {"iters": [], "s": 0.0, "accepted": 0}}
+    res = {"plain": {"iters": [], "s": 0.0}, "seeded": {"iters": [], "s": 0.0, "accepted": 0, "closed": 0},
+           "zero": {"iters": []}}
     n_eval = 0
     for seed in range(600, 604):
         lead = w.slab_lead(b, seed)
@@ -451,21 +452,29 @@ def bench_learned(args):
         seeded = nb.obc_surface([prob], 0, seed=seeds)
         torch.cuda.synchronize()
         res["seeded"]["s"] += time.perf_counter() - t1
-        res["plain"]["iters"] += plain["iters"].cpu().tolist()
+        # the seeded closure alone (a zero seed: no learned information) for comparison
+        zero = nb.obc_surface([prob], 0, seed=torch.zeros_like(seeds))
+        ip = plain["iters"].cpu().numpy()
+        res["plain"]["iters"] += ip.tolist()
         it = seeded["iters"].cpu().numpy()
         res["seeded"]["iters"] += it.tolist()
         res["seeded"]["accepted"] += int(np.count_nonzero(it == 0))
+        res["seeded"]["closed"] += int(np.count_nonzero((it > 0) & (it < ip)))
+        res["zero"]["iters"] += zero["iters"].cpu().tolist()
         d = (seeded["g_surf"][0] - plain["g_surf"][0]).abs().max().item()
-        log(f"held-out lead {seed}: plain {np.mean(plain['iters'].cpu().numpy()):.2f} steps, seeded "
-            f"{np.mean(it):.2f} steps, accepted {np.count_nonzero(it == 0)}/{E.size}, max |dg| {d:.2e}")
+        log(f"held-out lead {seed}: plain {np.mean(ip):.2f} steps, seeded {np.mean(it):.2f} steps "
+            f"(zero seed {np.mean(zero['iters'].cpu().numpy()):.2f}), candidate accepted {np.count_nonzero(it == 0)}"
+            f"/{E.size}, closed early {np.count_nonzero((it > 0) & (it < ip))}/{E.size}, max |dg| {d:.2e}")
         n_eval += E.size
     line = {"metric": "learned lead initialiser: decimation steps and energy points/s with vs without the seed",
             "unit": "energy points/s", "value": n_eval / res["seeded"]["s"], "higher_is_better": True,
             "plain_value": n_eval / res["plain"]["s"],
             "mean_steps_plain": float(np.mean(res["plain"]["iters"])),
             "mean_steps_seeded": float(np.mean(res["seeded"]["iters"])),
+            "mean_steps_zero_seed_closure": float(np.mean(res["zero"]["iters"])),
             "seed_acceptance": res["seeded"]["accepted"] / n_eval,
-            "fallback_rate": 1.0 - res["seeded"]["accepted"] / n_eval,
+            "closure_rate": res["seeded"]["closed"] / n_eval,
+            "fallback_rate": 1.0 - (res["seeded"]["accepted"] + res["seeded"]["closed"]) / n_eval,
             "train_samples": int(X.shape[0] // b), "train_rows": int(X.shape[0]), "final_mse": losses[-1],
             "data_generation_s": gen_s, "train_s": train_s, "b": b, "eval_points": n_eval,
             "dtype": "f32 training, bf16 inference, f64 decimation", "data": "synthetic"}

@@ -142,11 +142,18 @@ size_t negf_workspace_bytes(int32_t op, const negf_problem* problems, int32_t n_
  * alpha = H1 - z S1, beta = H1^H - z S1^H (H1, S1: coupling from the surface
  * cell to the next cell away from the device), and Sigma^R = alpha g_s beta.
  * This is the boundary term of B^R in Eq. (1).
- *  seed     : NULL, or [points][b][b] initial guesses g~ (learned initialiser):
- *             the candidate g0 = (d - alpha g~ beta)^{-1} is accepted when its
- *             normalised residual is <= sr_accept, else plain decimation runs.
+ *  seed     : NULL, or [points][b][b] initial guesses g~ (learned initialiser,
+ *             Section IV): the candidate g0 = (d - alpha g~ beta)^{-1} is
+ *             accepted when its normalised residual is <= sr_accept; else the
+ *             decimation runs, and after every step k the chain is closed
+ *             with the seed, X = (eps_k - eps_s,k + d - alpha g~ beta)^{-1},
+ *             g^ = (eps_s,k - a_k X c_k)^{-1} (exact for g~ = g_s), which is
+ *             accepted at the first k whose residual is <= sr_accept; else the
+ *             plain result.  Each closure costs two inversions and five
+ *             products per step.
  *  g_surf   : out [points][b][b]; sigma_r: out [points][b][b]
- *  iters    : out int32 [points] decimation steps (0 when the seed was accepted)
+ *  iters    : out int32 [points] decimation steps (0 when the candidate was
+ *             accepted, k when the closure after step k was)
  *  resid    : out double [points] ||(d - alpha g_s beta) g_s - I||_F /
  *             (||d - alpha g_s beta||_F ||g_s||_F)
  *  info     : out int32 [points]                                              */

@@ -130,8 +130,9 @@ struct Blocks {   // a batch of b x b blocks, item p at p * stride
 
 struct LeadWs {   // per (point, lead) pair scratch of the decimation
   Blocks d, alpha, beta, eps_s, eps, a, c, g, ag, cg, t1, t2;
+  Blocks dseed;   // d - alpha g~ beta of a seeded solve (carved only where a seed may be given)
   double *a2, *c2, *d2, *r2, *m2, *g2, *part;
-  int *active, *iters, *n_active, *accepted;
+  int *active, *iters, *n_active, *accepted, *closed;
   void* inv_scratch;
 };
 
@@ -152,10 +153,12 @@ Blocks take_blocks(Carver& cv, int b, int n) {
   return r;
 }
 
-LeadWs carve_leads(Carver& cv, int b, int npairs) {
+LeadWs carve_leads(Carver& cv, int b, int npairs, bool seeded) {
   LeadWs w;
   Blocks* all[] = {&w.d, &w.alpha, &w.beta, &w.eps_s, &w.eps, &w.a, &w.c, &w.g, &w.ag, &w.cg, &w.t1, &w.t2};
   for (Blocks* x : all) *x = take_blocks(cv, b, npairs);
+  w.dseed = seeded ? take_blocks(cv, b, npairs) : Blocks{};
+  w.closed = seeded ? cv.take<int>(npairs) : nullptr;
   w.a2 = cv.take<double>(npairs); w.c2 = cv.take<double>(npairs); w.d2 = cv.take<double>(npairs);
   w.r2 = cv.take<double>(npairs); w.m2 = cv.take<double>(npairs); w.g2 = cv.take<double>(npairs);
   w.part = cv.take<double>((size_t)npairs * FROB_SPLIT);
@@ -187,7 +190,7 @@ ChunkWs carve_chunk(Carver& cv, int opk, int nb, int b, int npts, negf_precision
   }
   // shared region
   Carver sub{cv.base ? cv.base + cv.off : nullptr, cv.base ? cv.cap - std::min(cv.cap, cv.off) : 0};
-  w.lw = carve_leads(sub, b, npts * nsides);
+  w.lw = carve_leads(sub, b, npts * nsides, opk == OPK_OBC);
   size_t lead_bytes = sub.off;
   Carver sub2{cv.base ? cv.base + cv.off : nullptr, cv.base ? cv.cap - std::min(cv.cap, cv.off) : 0};
   if (opk != OPK_OBC) {
@@ -395,6 +398,8 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
       cx.gemm(PREC_F64, OP_N, OP_N, b, npts, ONE, w.alpha.at(si * npts), bb, seed, seed_stride, ZERO, nullptr, 0,
               w.t1.at(si * npts), bb);
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.t1.p, bb, w.beta.p, bb, ONE, w.d.p, bb, w.eps.p, bb);
+    // d - alpha g~ beta is kept for the seeded closure of the decimation steps
+    cx.lincomb(b, np, ONE, w.eps.p, bb, ZERO, nullptr, 0, ZERO, w.dseed.p, bb);
     cx.inverse(b, np, w.eps.p, bb, w.g.p, bb, w.inv_scratch, nullptr, 0);
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.alpha.p, bb, w.g.p, bb, ZERO, nullptr, 0, w.t1.p, bb);
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.t1.p, bb, w.beta.p, bb, ONE, w.d.p, bb, w.t2.p, bb);
@@ -437,6 +442,26 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
       Blocks tmp = c;
       c = w.cg;
       w.cg = tmp;
+    }
+    if (seed) {
+      // seeded closure of the chain after this step: X = (eps - eps_s + d - alpha g~ beta)^{-1},
+      // g^ = (eps_s - a X c)^{-1}, accepted (and the pair finished) when its Dyson residual passes.
+      // Free here: t1, w.ag, w.cg, t2.
+      cx.lincomb(b, np, ONE, w.eps.p, bb, MONE, w.eps_s.p, bb, ZERO, t1.p, bb, act);
+      cx.lincomb(b, np, ONE, t1.p, bb, ONE, w.dseed.p, bb, ZERO, t1.p, bb, act);
+      cx.inverse(b, np, t1.p, bb, w.ag.p, bb, w.inv_scratch, nullptr, 0, act);
+      cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, a.p, bb, w.ag.p, bb, ZERO, nullptr, 0, w.cg.p, bb, act);
+      cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.cg.p, bb, c.p, bb, ONE, w.eps_s.p, bb, t2.p, bb, act);
+      cx.inverse(b, np, t2.p, bb, t1.p, bb, w.inv_scratch, nullptr, 0, act);          // t1 = g^
+      cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.alpha.p, bb, t1.p, bb, ZERO, nullptr, 0, w.ag.p, bb, act);
+      cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.ag.p, bb, w.beta.p, bb, ONE, w.d.p, bb, t2.p, bb, act);
+      cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, t2.p, bb, t1.p, bb, ZERO, nullptr, 0, w.cg.p, bb, act);
+      cx.chk(launch_frob2(b, np, w.cg.p, bb, 1.0, act, w.part, w.r2, s));
+      cx.chk(launch_frob2(b, np, t2.p, bb, 0.0, act, w.part, w.m2, s));
+      cx.chk(launch_frob2(b, np, t1.p, bb, 0.0, act, w.part, w.g2, s));
+      cx.chk(launch_closure_accept(np, w.r2, w.m2, w.g2, cx.o.accept, it, w.active, w.iters, w.accepted, w.closed,
+                                   s));
+      cx.lincomb(b, np, ONE, t1.p, bb, ZERO, nullptr, 0, ZERO, w.g.p, bb, w.closed);
     }
     cx.chk(launch_frob2(b, np, a.p, bb, 0.0, w.active, w.part, w.a2, s));
     cx.chk(launch_frob2(b, np, c.p, bb, 0.0, w.active, w.part, w.c2, s));

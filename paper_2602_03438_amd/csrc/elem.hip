@@ -290,6 +290,23 @@ __global__ void seed_select_kernel(long n, const int* flags, const double2* g_de
     g[(long)p * n + i] = g_dec[(long)p * n + i];
 }
 
+__global__ void closure_accept_kernel(int np, const double* r2, const double* m2, const double* g2, double accept,
+                                      int iter, int* active, int* iters, int* accepted, int* closed) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  int c = 0;
+  if (active[p]) {
+    const double r = sqrt(r2[p]) / (sqrt(m2[p]) * sqrt(g2[p]));
+    if (r == r && isfinite(r) && r <= accept) {
+      c = 1;
+      active[p] = 0;
+      iters[p] = iter;
+      accepted[p] = ST_OK;
+    }
+  }
+  closed[p] = c;
+}
+
 __global__ void stamp_kernel(unsigned long long* dst) {
   if (threadIdx.x == 0) *dst = wall_clock64();
 }
@@ -406,6 +423,14 @@ hipError_t launch_seed_select(int b, int np, const int* flags, const double2* g_
   if (np <= 0) return hipSuccess;
   const long n = (long)b * b;
   hipLaunchKernelGGL(seed_select_kernel, dim3(grid_for(n), np), dim3(256), 0, s, n, flags, g_dec, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_closure_accept(int np, const double* r2, const double* m2, const double* g2, double accept, int iter,
+                                 int* active, int* iters, int* accepted, int* closed, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(closure_accept_kernel, dim3((np + 255) / 256), dim3(256), 0, s, np, r2, m2, g2, accept, iter,
+                     active, iters, accepted, closed);
   return hipGetLastError();
 }
 

@@ -142,6 +142,11 @@ hipError_t launch_fill_int(int n, int* p, int v, hipStream_t s);
 hipError_t launch_seed_flags(int np, const int* flags, int* active, int* iters, hipStream_t s);
 // g_p <- g_dec_p for every pair whose seed was rejected (flags_p != OK)
 hipError_t launch_seed_select(int b, int np, const int* flags, const double2* g_dec, double2* g, hipStream_t s);
+// Seeded closure of the decimation: for every active pair whose closure residual
+// sqrt(r2) / (sqrt(m2) sqrt(g2)) is finite and <= accept: closed = 1, active = 0,
+// iters = iter, accepted = ST_OK; closed = 0 for every other pair.
+hipError_t launch_closure_accept(int np, const double* r2, const double* m2, const double* g2, double accept, int iter,
+                                 int* active, int* iters, int* accepted, int* closed, hipStream_t s);
 
 // ---- runtime helpers and profiling (prof.hip) ----
 // *host_dst = *dev_src after the stream has drained (synchronises s)

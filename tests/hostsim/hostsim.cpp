@@ -356,6 +356,24 @@ hipError_t launch_seed_select(int b, int np, const int* flags, const double2* g_
   return hipSuccess;
 }
 
+hipError_t launch_closure_accept(int np, const double* r2, const double* m2, const double* g2, double accept, int iter,
+                                 int* active, int* iters, int* accepted, int* closed, hipStream_t) {
+  for (int p = 0; p < np; ++p) {
+    int c = 0;
+    if (active[p]) {
+      const double r = std::sqrt(r2[p]) / (std::sqrt(m2[p]) * std::sqrt(g2[p]));
+      if (r == r && std::isfinite(r) && r <= accept) {
+        c = 1;
+        active[p] = 0;
+        iters[p] = iter;
+        accepted[p] = ST_OK;
+      }
+    }
+    closed[p] = c;
+  }
+  return hipSuccess;
+}
+
 hipError_t rt_read_int(int* host_dst, const int* dev_src, hipStream_t) {
   *host_dst = *dev_src;
   return hipSuccess;

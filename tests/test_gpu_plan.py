@@ -95,9 +95,15 @@ def test_seeded_decimation_exact_and_fallback(nb):
     seed[1] = 0.3 * np.eye(48)                     # a poor guess: must fall back
     out = nb.obc_surface([prob], 0, seed=torch.from_numpy(seed).cuda())
     it = out["iters"].cpu().numpy()
-    assert it[0] == 0 and it[2] == 0 and it[1] > 5
+    assert it[0] == 0 and it[2] == 0 and it[1] > 0
     for k in range(3):
-        assert rel(out["g_surf"][0][k, 0].cpu().numpy(), exact[k]) < 1e-10
+        # the oracle's seeded solve: candidate, closure after step k, or plain
+        d, a, c = oleads.lead_blocks(dev, 0, E[k], 1e-8)
+        g_ref, k_ref, how = oleads.seeded_sancho_rubio(d, a, c, seed[k])
+        assert abs(int(it[k]) - k_ref) <= 1, (k, int(it[k]), k_ref, how)
+        g = out["g_surf"][0][k, 0].cpu().numpy()
+        # accepted at a Dyson residual <= 1e-8: within ~1e-8 of the converged decimation
+        assert rel(g, exact[k]) < 1e-7 and rel(g, g_ref) < 1e-8
     assert np.all(out["info"].cpu().numpy() == 0)
 
 
@@ -132,6 +138,8 @@ def test_learned_initialiser_end_to_end(nb):
     assert torch.equal(plain["info"], seeded["info"])
     diff = (seeded["g_surf"][0] - plain["g_surf"][0]).abs().max().item()
     scale = plain["g_surf"][0].abs().max().item()
-    assert diff < 1e-9 * scale
+    # a seeded result is accepted at a Dyson residual <= 1e-8 (candidate or closure)
+    assert diff < 1e-7 * scale
+    assert torch.all(seeded["iters"] <= plain["iters"])
     print(f"mean steps plain {plain['iters'].float().mean().item():.2f}, "
           f"seeded {seeded['iters'].float().mean().item():.2f}")

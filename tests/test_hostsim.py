@@ -185,7 +185,8 @@ def test_hostsim_transmission_and_obc(sim):
 
 
 def test_hostsim_seeded_obc(sim):
-    """An exact seed is accepted with zero iterations; a bad seed falls back."""
+    """An exact seed is accepted with zero iterations; a poor one runs the
+    decimation, closed with the seed after every step (as the oracle does)."""
     L, nb = sim
     dev = w.random_device(3, 4, 2)
     E = np.array([0.3, -0.6])
@@ -202,9 +203,16 @@ def test_hostsim_seeded_obc(sim):
     info = np.zeros(2, np.int32)
     assert L.negf_obc_surface(arr, 1, 0, None, seed.ctypes.data, g.ctypes.data, s.ctypes.data, it.ctypes.data,
                               res.ctypes.data, info.ctypes.data, ws.ctypes.data, ws.size, None) == 0
-    assert it[0] == 0 and it[1] > 5
-    for k in range(2):
-        assert rel(g[k], exact[k]) < 1e-10
+    # the oracle's seeded solve decides the path: candidate, closure after step k, or plain
+    for k, e in enumerate(E):
+        d, a, c = oleads.lead_blocks(dev, 0, e, 1e-8)
+        g_ref, k_ref, how = oleads.seeded_sancho_rubio(d, a, c, seed[k])
+        assert (how == "candidate") == (k == 0)
+        assert abs(int(it[k]) - k_ref) <= 1, (k, int(it[k]), k_ref, how)
+        # the closure is accepted at a Dyson residual <= 1e-8, so it sits within
+        # ~1e-8 of the converged decimation; the same steps on both sides agree closely
+        assert rel(g[k], exact[k]) < 1e-7 and rel(g[k], g_ref) < 1e-11
+    assert it[0] == 0 and it[1] > 0
     assert np.all(info == 0)
 
 
