@@ -122,9 +122,8 @@ typedef struct negf_options {
                            bounded normwise, not componentwise)  [4]   */
   int32_t dense_coupling; /* 1: multiply the coupling blocks A_{i,i+1} as dense
                            blocks; otherwise products with a coupling operand
-                           skip its 16 x 64 slabs that are zero in both H_{i,i+1}
-                           and S_{i,i+1} (exact zeros: the results are the same)
-                           [0]   */
+                           skip its zero 16 x 16 slabs (zero in both H_{i,i+1} and
+                           S_{i,i+1}; exact zeros: the results are the same) [0] */
 } negf_options;
 
 /* Operation codes for negf_workspace_bytes. */
