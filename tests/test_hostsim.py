@@ -140,6 +140,20 @@ def test_hostsim_coupling_slab_maps(sim):
     assert rel(_unpack(sparse["GRd"], [p], 1)[0][0], ref.GR_diag) < tol["GR_diag"]
 
 
+def test_hostsim_empty_energy_list(sim):
+    """A problem with no energies contributes no points; the others are unchanged."""
+    L, nb = sim
+    dev = w.random_device(3, 4, 7, overlap=0.05)
+    E = well_posed(dev, np.linspace(-1.2, 1.2, 9))[:2]
+    empty = HostProblem(nb, dev, np.array([]))
+    full = HostProblem(nb, dev, E)
+    both, info_b = _run_rgf(L, nb, [empty, full], greater=False)
+    alone, info_a = _run_rgf(L, nb, [full], greater=False)
+    assert info_b.size == 2 and np.array_equal(info_b, info_a)
+    for k in ("GRd", "GRu", "GRl", "GLd", "GLu"):
+        assert np.array_equal(both[k], alone[k]), k
+
+
 def test_hostsim_mixed_shapes_and_chunking(sim):
     L, nb = sim
     devs = [w.random_device(3, 4, 11), w.random_device(4, 6, 12, overlap=0.05), w.random_device(3, 4, 13)]
