@@ -205,110 +205,65 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
   constexpr unsigned ALL_ON = (1u << (FM * FN)) - 1u;
   // only the products with a sparse operand (tag 2, 64 x 64 tiles) read a zero-slab map
   constexpr bool SPARSE_OK = TAG == 2 && BM == 64 && BN == 64;
+  // (for the dense kernels the guard folds to true at compile time)
+  auto on_ij = [&](unsigned on, int i, int j) { return !SPARSE_OK || ((on >> (i * FN + j)) & 1u) != 0u; };
   auto mac = [&](const CT* __restrict__ xA, const CT* __restrict__ xB, unsigned on) {
-    if (!SPARSE_OK) {
 #pragma unroll
-      for (int kk = 0; kk < BK / 4; ++kk) {
-        const int kq = kk * 4 + lk;
-        CT av[FM], bv[FN];
-  #pragma unroll
-        for (int i = 0; i < FM; ++i) {
-          const int m = wm * CF::TM + i * 16 + li;
-          av[i] = A_ROW ? xA[m * CF::LD_ROW + kq] : xA[kq * CF::LDA_COL + m];
-        }
-  #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int n = wn * CF::TN + j * 16 + li;
-          bv[j] = B_ROW ? xB[n * CF::LD_ROW + kq] : xB[kq * CF::LDB_COL + n];
-        }
-        if constexpr (GAUSS) {
-          T as[FM], bs[FN];
-  #pragma unroll
-          for (int i = 0; i < FM; ++i) as[i] = av[i].x + av[i].y;
-  #pragma unroll
-          for (int j = 0; j < FN; ++j) bs[j] = bv[j].x + bv[j].y;
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].y, accI[i][j]);
-  #pragma unroll
-          for (int i = 0; i < NS; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) accS[i][j] = mfma16(as[i], bs[j], accS[i][j]);
-        } else {
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
-        }
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kq = kk * 4 + lk;
+      CT av[FM], bv[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int m = wm * CF::TM + i * 16 + li;
+        av[i] = A_ROW ? xA[m * CF::LD_ROW + kq] : xA[kq * CF::LDA_COL + m];
       }
-    } else {
 #pragma unroll
-      for (int kk = 0; kk < BK / 4; ++kk) {
-        const int kq = kk * 4 + lk;
-        CT av[FM], bv[FN];
-  #pragma unroll
-        for (int i = 0; i < FM; ++i) {
-          const int m = wm * CF::TM + i * 16 + li;
-          av[i] = A_ROW ? xA[m * CF::LD_ROW + kq] : xA[kq * CF::LDA_COL + m];
-        }
-  #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int n = wn * CF::TN + j * 16 + li;
-          bv[j] = B_ROW ? xB[n * CF::LD_ROW + kq] : xB[kq * CF::LDB_COL + n];
-        }
-        if constexpr (GAUSS) {
-          T as[FM], bs[FN];
-  #pragma unroll
-          for (int i = 0; i < FM; ++i) as[i] = av[i].x + av[i].y;
-  #pragma unroll
-          for (int j = 0; j < FN; ++j) bs[j] = bv[j].x + bv[j].y;
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accI[i][j] = mfma16(av[i].y, bv[j].y, accI[i][j]);
-  #pragma unroll
-          for (int i = 0; i < NS; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accS[i][j] = mfma16(as[i], bs[j], accS[i][j]);
-        } else {
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
-  #pragma unroll
-          for (int i = 0; i < FM; ++i)
-  #pragma unroll
-            for (int j = 0; j < FN; ++j) if (on >> (i * FN + j) & 1u) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
-        }
+      for (int j = 0; j < FN; ++j) {
+        const int n = wn * CF::TN + j * 16 + li;
+        bv[j] = B_ROW ? xB[n * CF::LD_ROW + kq] : xB[kq * CF::LDB_COL + n];
+      }
+      if constexpr (GAUSS) {
+        T as[FM], bs[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) as[i] = av[i].x + av[i].y;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bs[j] = bv[j].x + bv[j].y;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            if (on_ij(on, i, j)) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            if (on_ij(on, i, j)) accI[i][j] = mfma16(av[i].y, bv[j].y, accI[i][j]);
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            if (on_ij(on, i, j)) accS[i][j] = mfma16(as[i], bs[j], accS[i][j]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            if (on_ij(on, i, j)) accR[i][j] = mfma16(av[i].x, bv[j].x, accR[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            if (on_ij(on, i, j)) accI[i][j] = mfma16(av[i].x, bv[j].y, accI[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            if (on_ij(on, i, j)) accR[i][j] = mfma16(-av[i].y, bv[j].y, accR[i][j]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            if (on_ij(on, i, j)) accI[i][j] = mfma16(av[i].y, bv[j].x, accI[i][j]);
       }
     }
   };

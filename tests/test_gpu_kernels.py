@@ -64,6 +64,18 @@ def test_zgemm_tile_shapes(nb, tile, opa, opb, M, N, K, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 2])
+def test_zgemm_fp64_b1024_largest_block(nb, prec):
+    """The largest block the library accepts: 64 K-steps in one tile."""
+    import torch
+    r = np.random.Generator(np.random.PCG64(6))
+    A = _rand(r, (2, 1024, 1024))
+    B = _rand(r, (2, 1024, 1024))
+    got = nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), prec=prec).cpu().numpy()
+    ref = A @ B
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-14
+
+
+@pytest.mark.parametrize("prec", [0, 2])
 def test_zgemm_fp64_b512_batched(nb, prec):
     import torch
     r = np.random.Generator(np.random.PCG64(5))
@@ -111,7 +123,7 @@ def test_zgemm_fp32_products(nb):
     assert 1e-9 < err < 1e-5, err
 
 
-@pytest.mark.parametrize("n", [1, 5, 8, 16, 33, 100, 130, 300, 512, 700])
+@pytest.mark.parametrize("n", [1, 5, 8, 16, 33, 100, 130, 300, 512, 700, 1000, 1024])
 @pytest.mark.parametrize("panel", [16, 32])
 def test_zinv_parity(nb, n, panel):
     import torch
@@ -137,7 +149,7 @@ def test_zinv_pivoting_needed(nb):
     assert np.allclose(out.cpu().numpy()[0], np.linalg.inv(M[0]), atol=1e-14)
 
 
-@pytest.mark.parametrize("n", [64, 200, 512])
+@pytest.mark.parametrize("n", [64, 200, 512, 1024])
 def test_zinv_scaled_permutation(nb, n):
     """One non-zero per row and column, anywhere in the matrix: every pivot has
     to be the single non-zero of its column among all remaining rows (any other

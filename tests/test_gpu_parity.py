@@ -154,6 +154,35 @@ def test_coupling_slab_skip_matches_dense(nb, b, cmul, prec):
     assert torch.equal(t_sparse["T"], t_dense["T"])
 
 
+def test_coupling_slab_skip_largest_block(nb):
+    """b = 1024: 64 K-steps, every bit of the zero-slab maps in use."""
+    import torch
+    dev = w.slab_device(3, 1024, 2)
+    prob = nb.Problem(nb.DeviceOnGPU(dev), np.array([0.3]), eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
+    sparse = nb.rgf_lesser_greater([prob], opts=nb.make_options(cmul=3))
+    dense = nb.rgf_lesser_greater([prob], opts=nb.make_options(cmul=3, dense_coupling=1))
+    assert torch.equal(sparse["info"], dense["info"])
+    for key in ("GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper"):
+        assert torch.equal(sparse[key][0], dense[key][0]), key
+
+
+def test_empty_energy_list_next_to_a_full_one(nb):
+    """A problem with no energies contributes no points and does not disturb the others."""
+    import torch
+    dev = w.slab_device(4, 64, 2)
+    gdev = nb.DeviceOnGPU(dev)
+    energies = np.array([-0.3, 0.5])
+    empty = nb.Problem(gdev, np.array([]), eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
+    full = nb.Problem(gdev, energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
+    both = nb.rgf_lesser_greater([empty, full])
+    alone = nb.rgf_lesser_greater([full])
+    assert both["info"].numel() == 2
+    assert torch.equal(both["info"], alone["info"])
+    for key in ("GR_diag", "GL_diag", "GL_upper"):
+        assert both[key][0].numel() == 0
+        assert torch.equal(both[key][1], alone[key][0]), key
+
+
 def test_lesser_gpu_identities(nb):
     """I4 and I5 on GPU outputs: G^R - G^A = G^> - G^< and anti-Hermitian G^<."""
     dev = w.slab_device(4, 96, 7)
