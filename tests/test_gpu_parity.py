@@ -218,6 +218,24 @@ def test_multi_problem_mixed_shapes_and_chunking(nb):
             _cmp_point(chunked, k, ref, names, tol, pi=q)
 
 
+def test_k_points_with_scattering(nb):
+    """Transverse-momentum copies of a scattering slab device (the k dependence of
+    the scattering workload) in one call: one chunk holding two devices whose
+    coupling-block maps are merged, each point against the oracle."""
+    base = w.slab_device(4, 128, 2)
+    w.scattering_self_energies(base, 3)
+    devs = [w.k_device(base, 7, k) for k in (0.0, 0.9)]
+    ens = [well_posed(d, np.array([-0.55, 0.35, 0.8]))[:2] for d in devs]
+    probs = [nb.Problem(nb.DeviceOnGPU(d), e, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025) for d, e in zip(devs, ens)]
+    out = nb.rgf_lesser_greater(probs, greater=True)
+    assert np.all(out["info"].cpu().numpy() == 0)
+    names = ["GR_diag", "GR_upper", "GL_diag", "GL_upper", "GG_diag"]
+    for q, (d, e) in enumerate(zip(devs, ens)):
+        for k, E in enumerate(e):
+            ref, tol = _ref(d, E, names, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025, greater=True)
+            _cmp_point(out, k, ref, names, tol, pi=q)
+
+
 # ------------------------------------------------------------------ transmission
 
 def test_transmission_small_workload_and_chain(nb):
