@@ -129,7 +129,7 @@ struct Blocks {   // a batch of b x b blocks, item p at p * stride
 };
 
 struct LeadWs {   // per (point, lead) pair scratch of the decimation
-  Blocks d, alpha, beta, eps_s, eps, a, c, g, ag, cg, t1, t2;
+  Blocks d, alpha, beta, eps_s, eps, a, c, g, ag, cg, t1, t2;   // eps holds eps - eps_s in the chain
   Blocks dseed;   // d - alpha g~ beta of a seeded solve (carved only where a seed may be given)
   double *a2, *c2, *d2, *r2, *m2, *g2, *part;
   int *active, *iters, *n_active, *accepted, *closed;
@@ -412,28 +412,29 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
     cx.chk(launch_seed_flags(np, w.accepted, w.active, w.iters, s));
   }
   if (!cx.ok()) return;
-  // --- plain decimation: eps_s = eps = d, a = alpha, c = beta
+  // --- plain decimation: eps_s = eps = d, a = alpha, c = beta.  The chain keeps eps_s and
+  // D = eps - eps_s (in w.eps): the term a g c that both lose cancels in D, so each update is
+  // one product with an accumulating epilogue, and eps = eps_s + D is formed where it is inverted.
   cx.lincomb(b, np, ONE, w.d.p, bb, ZERO, nullptr, 0, ZERO, w.eps_s.p, bb);
-  cx.lincomb(b, np, ONE, w.d.p, bb, ZERO, nullptr, 0, ZERO, w.eps.p, bb);
+  cx.lincomb(b, np, ZERO, nullptr, 0, ZERO, nullptr, 0, ZERO, w.eps.p, bb);
   cx.lincomb(b, np, ONE, w.alpha.p, bb, ZERO, nullptr, 0, ZERO, w.a.p, bb);
   cx.lincomb(b, np, ONE, w.beta.p, bb, ZERO, nullptr, 0, ZERO, w.c.p, bb);
   Blocks a = w.a, c = w.c, t1 = w.t1, t2 = w.t2;
+  const Blocks D = w.eps;
   int hmax = 0;
   for (int it = 1; it <= cx.o.max_iter && cx.ok(); ++it) {
     const int* act = w.active;
-    // g = eps^{-1}  (eps is kept: invert a copy)
-    cx.lincomb(b, np, ONE, w.eps.p, bb, ZERO, nullptr, 0, ZERO, t1.p, bb, act);
+    // g = eps^{-1} with eps = eps_s + D formed in t1 (the inversion overwrites its input)
+    cx.lincomb(b, np, ONE, w.eps_s.p, bb, ONE, D.p, bb, ZERO, t1.p, bb, act);
     cx.inverse(b, np, t1.p, bb, w.ag.p, bb, w.inv_scratch, nullptr, 0, act);   // ag temporarily holds g
     std::swap(w.ag, w.cg);   // cg := g ; ag free
     const Blocks g = w.cg;
     // ag = a g, t2 = c g
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, a.p, bb, g.p, bb, ZERO, nullptr, 0, w.ag.p, bb, act);
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, c.p, bb, g.p, bb, ZERO, nullptr, 0, t2.p, bb, act);
-    // t1 = ag c ; eps_s -= t1 ; eps -= t1
-    cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.ag.p, bb, c.p, bb, ZERO, nullptr, 0, t1.p, bb, act);
-    cx.chk(launch_sub2(b, np, t1.p, bb, w.eps_s.p, bb, w.eps.p, bb, act, s));
-    // eps -= (c g) a
-    cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, t2.p, bb, a.p, bb, ONE, w.eps.p, bb, w.eps.p, bb, act);
+    // eps_s -= (a g) c ; D -= (c g) a
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.ag.p, bb, c.p, bb, ONE, w.eps_s.p, bb, w.eps_s.p, bb, act);
+    cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, t2.p, bb, a.p, bb, ONE, D.p, bb, D.p, bb, act);
     // a' = (a g) a -> t1 ; c' = (c g) c -> g buffer (g no longer needed)
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, w.ag.p, bb, a.p, bb, ZERO, nullptr, 0, t1.p, bb, act);
     cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, t2.p, bb, c.p, bb, ZERO, nullptr, 0, w.cg.p, bb, act);
@@ -447,8 +448,7 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
       // seeded closure of the chain after this step: X = (eps - eps_s + d - alpha g~ beta)^{-1},
       // g^ = (eps_s - a X c)^{-1}, accepted (and the pair finished) when its Dyson residual passes.
       // Free here: t1, w.ag, w.cg, t2.
-      cx.lincomb(b, np, ONE, w.eps.p, bb, MONE, w.eps_s.p, bb, ZERO, t1.p, bb, act);
-      cx.lincomb(b, np, ONE, t1.p, bb, ONE, w.dseed.p, bb, ZERO, t1.p, bb, act);
+      cx.lincomb(b, np, ONE, D.p, bb, ONE, w.dseed.p, bb, ZERO, t1.p, bb, act);
       cx.inverse(b, np, t1.p, bb, w.ag.p, bb, w.inv_scratch, nullptr, 0, act);
       cx.gemm(PREC_F64, OP_N, OP_N, b, np, ONE, a.p, bb, w.ag.p, bb, ZERO, nullptr, 0, w.cg.p, bb, act);
       cx.gemm(PREC_F64, OP_N, OP_N, b, np, MONE, w.cg.p, bb, c.p, bb, ONE, w.eps_s.p, bb, t2.p, bb, act);

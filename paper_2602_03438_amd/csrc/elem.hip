@@ -73,19 +73,6 @@ __global__ void copy_kernel(long n, int batch, const double2* src, long sS, doub
     dst[(long)p * sD + i] = src[(long)p * sS + i];
 }
 
-__global__ void sub2_kernel(long n, const double2* x, long sx, double2* a, long sa, double2* c, long sc,
-                            const int* active) {
-  const int p = blockIdx.y;
-  if (active && active[p] == 0) return;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double2 v = x[(long)p * sx + i];
-    double2 t = a[(long)p * sa + i];
-    a[(long)p * sa + i] = csub(t, v);
-    t = c[(long)p * sc + i];
-    c[(long)p * sc + i] = csub(t, v);
-  }
-}
-
 template <int NT>
 __device__ double block_sum(double v) {
   __shared__ double red[NT / 64];
@@ -336,14 +323,6 @@ hipError_t launch_copy_blocks(int b, int batch, const double2* src, long sS, dou
   if (batch <= 0) return hipSuccess;
   const long n = (long)b * b;
   hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n), batch), dim3(256), 0, s, n, batch, src, sS, dst, sD);
-  return hipGetLastError();
-}
-
-hipError_t launch_sub2(int b, int batch, const double2* x, long sx, double2* a, long sa, double2* c, long sc,
-                       const int* active, hipStream_t s) {
-  if (batch <= 0) return hipSuccess;
-  const long n = (long)b * b;
-  hipLaunchKernelGGL(sub2_kernel, dim3(grid_for(n), batch), dim3(256), 0, s, n, x, sx, a, sa, c, sc, active);
   return hipGetLastError();
 }
 

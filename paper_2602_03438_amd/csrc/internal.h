@@ -106,10 +106,6 @@ hipError_t launch_assemble(const AssembleDesc& d, hipStream_t s);
 
 // dst_p = src_p (plain copy of a batch of b x b blocks)
 hipError_t launch_copy_blocks(int b, int batch, const double2* src, long sS, double2* dst, long sD, hipStream_t s);
-// a_p -= x_p ; c_p -= x_p
-hipError_t launch_sub2(int b, int batch, const double2* x, long sx, double2* a, long sa, double2* c, long sc,
-                       const int* active, hipStream_t s);
-// nrm2[p] = ||X_p - shift * I||_F^2  (sum of squares)
 // nrm2[p] = ||X_p - shift I||_F^2 for items with active[p] != 0 (all when active is null);
 // part: scratch of batch * FROB_SPLIT doubles.
 constexpr int FROB_SPLIT = 16;

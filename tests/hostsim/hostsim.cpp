@@ -201,18 +201,6 @@ hipError_t launch_copy_blocks(int b, int batch, const double2* src, long sS, dou
   return hipSuccess;
 }
 
-hipError_t launch_sub2(int b, int batch, const double2* x, long sx, double2* a, long sa, double2* c, long sc,
-                       const int* active, hipStream_t) {
-  for (int p = 0; p < batch; ++p) {
-    if (!act(active, p)) continue;
-    for (long i = 0; i < (long)b * b; ++i) {
-      a[(long)p * sa + i] = D(C(a[(long)p * sa + i]) - C(x[(long)p * sx + i]));
-      c[(long)p * sc + i] = D(C(c[(long)p * sc + i]) - C(x[(long)p * sx + i]));
-    }
-  }
-  return hipSuccess;
-}
-
 hipError_t launch_frob2(int b, int batch, const double2* X, long sX, double shift, const int* active, double*,
                         double* nrm2, hipStream_t) {
   for (int p = 0; p < batch; ++p) {
