@@ -615,10 +615,12 @@ void backward_retarded(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision pre
 }
 
 // Forward lesser/greater sweep of one kind; g^<> into gl (stride ds).  Needs g_i in GRd.
+// V_{i-1} = A_{i,i-1} g^<>_{i-1}, formed at step i, is left in the upper output block i-1 (lu,
+// stride (nb-1) b^2), which the backward sweep reads back before it writes that block.
 void forward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, int kind, const double2* GRd,
-                    double2* gl) {
+                    double2* gl, double2* lu) {
   const int b = ch.b, nb = ch.nb, n = ch.npts;
-  const long bb = (long)b * b, ds = (long)nb * bb;
+  const long bb = (long)b * b, ds = (long)nb * bb, us = (long)(nb - 1) * bb;
   // the refined form keeps the lesser sweeps in double: one residual correction of
   // single-precision products here leaves ~3e-7 in g^<, which the backward sweep
   // amplifies beyond 1e-6 over a 60-block device
@@ -630,10 +632,11 @@ void forward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec, 
     const bool has_sig = assemble_sigma_lg(cx, ch, i, kind, pw, pw.T4);
     if (i > 0) {
       assemble_upper(cx, ch, i - 1, pw.T1);   // A_{i-1,i}; A_{i,i-1} = T1^H
-      cx.gemm(pbt, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gl + (long)(i - 1) * bb, ds, ZERO, nullptr, 0, pw.T2.p, bb,
-              nullptr, false, cx.cpl(i - 1, 2));
-      cx.gemm(pbt, OP_N, OP_N, b, n, ONE, pw.T2.p, bb, pw.T1.p, bb, has_sig ? ONE : ZERO, has_sig ? pw.T4.p : nullptr,
-              bb, pw.T4.p, bb, nullptr, false, cx.cpl(i - 1, 1));
+      double2* V = lu + (long)(i - 1) * bb;
+      cx.gemm(pbt, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gl + (long)(i - 1) * bb, ds, ZERO, nullptr, 0, V, us, nullptr,
+              false, cx.cpl(i - 1, 2));
+      cx.gemm(pbt, OP_N, OP_N, b, n, ONE, V, us, pw.T1.p, bb, has_sig ? ONE : ZERO, has_sig ? pw.T4.p : nullptr, bb,
+              pw.T4.p, bb, nullptr, false, cx.cpl(i - 1, 1));
     } else if (!has_sig) {
       cx.lincomb(b, n, ZERO, nullptr, 0, ZERO, nullptr, 0, ZERO, pw.T4.p, bb);
     }
@@ -649,12 +652,11 @@ void backward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec,
   const long bb = (long)b * b, ds = (long)nb * bb, us = (long)(nb - 1) * bb;
   const Prec pp = (prec == NEGF_FP32_NOREFINE) ? PREC_F32 : PREC_F64;
   for (int i = nb - 2; i >= 0 && cx.ok(); --i) {
-    assemble_upper(cx, ch, i, pw.T1);
     double2* gli = Ld + (long)i * bb;                 // holds g^<_i
     const double2* Xi = pw.X + (long)i * bb;
-    // V = A_{i+1,i} g^<_i
-    cx.gemm(pp, OP_C, OP_N, b, n, ONE, pw.T1.p, bb, gli, ds, ZERO, nullptr, 0, pw.T2.p, bb, nullptr, false,
-            cx.cpl(i, 2));
+    // V = A_{i+1,i} g^<_i, left in the upper block i by the forward sweep (same product, same
+    // operands); it moves to T2 because the last product below reads it while writing that block
+    cx.lincomb(b, n, ONE, Lu + (long)i * bb, us, ZERO, nullptr, 0, ZERO, pw.T2.p, bb);
     // Q = -G_{i,i+1} V
     cx.gemm(pp, OP_N, OP_N, b, n, MONE, GRu + (long)i * bb, us, pw.T2.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
     // Z = X_i G^<_{i+1,i+1}
@@ -769,8 +771,9 @@ void run_chunk(Ctx& cx, int opk, const Chunk& ch, ChunkWs& w, negf_precision pre
   double2* GRd = outs.GRd + ch.out_diag_off;
   forward_retarded(cx, ch, w.pw, prec, GRd, ds, info, true, nullptr);
   if (lesser) {
-    forward_lesser(cx, ch, w.pw, prec, 0, GRd, outs.GLd + ch.out_diag_off);
-    if (outs.GGd) forward_lesser(cx, ch, w.pw, prec, 1, GRd, outs.GGd + ch.out_diag_off);
+    forward_lesser(cx, ch, w.pw, prec, 0, GRd, outs.GLd + ch.out_diag_off, outs.GLu + ch.out_off_off);
+    if (outs.GGd)
+      forward_lesser(cx, ch, w.pw, prec, 1, GRd, outs.GGd + ch.out_diag_off, outs.GGu + ch.out_off_off);
   }
   backward_retarded(cx, ch, w.pw, prec, outs);
   if (lesser) {
