@@ -214,11 +214,6 @@ struct Ctx {
   bool ok() const { return err == hipSuccess; }
   void chk(hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; }
 
-  // C = alpha op(A) op(B) + beta Cin over a batch of b x b blocks
-  // skew: the product is known to be anti-Hermitian (only its upper triangle is computed).
-  // Not used by the sweeps: at the conditioning of these devices the non-anti-Hermitian
-  // rounding of a full product (~1e-8 relative) is what the oracle also carries, and
-  // mirroring one triangle moves the result that far from it.
   // zero-slab maps of the current chunk's coupling blocks (nullptr: treat them as dense)
   const unsigned long long* cmask = nullptr;
   int cmask_words = 0;
@@ -227,6 +222,12 @@ struct Ctx {
   struct KMask { const unsigned long long* m; int op; };
   KMask cpl(int i, int op) const { return cmask ? KMask{cmask + (long)i * cmask_words, op} : KMask{nullptr, 0}; }
 
+  // C = alpha op(A) op(B) + beta Cin over a batch of b x b blocks
+  // skew: the product is known to be anti-Hermitian (only its upper triangle is computed).
+  // Not used by the sweeps: at the conditioning of these devices the non-anti-Hermitian
+  // rounding of a full product (~1e-8 relative) is what the oracle also carries, and
+  // mirroring one triangle moves the result that far from it.
+  // km: zero-slab map of a coupling-block operand (products skip its zero slabs)
   void gemm(Prec pr, Op oa, Op ob, int b, int batch, double2 alpha, const double2* A, long sA, const double2* B,
             long sB, double2 beta, const double2* Cin, long sCin, double2* C, long sC, const int* active = nullptr,
             bool skew = false, KMask km = KMask{nullptr, 0}) {
