@@ -376,12 +376,15 @@ def bench_uneven(args):
         x = pt_done[dev_pt == d]
         per_dev[f"b{b}_nb{nbk}"] = {"points": int(x.size), "p50_s": float(np.percentile(x, 50)),
                                     "p99_s": float(np.percentile(x, 99)), "last_s": float(x.max())}
-    # eager (no graph) for comparison
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    # eager (no graph) for comparison, timed like the replays (one untimed run first)
     plan.execute(outs, info, use_graph=False, stamps=stamps)
     torch.cuda.synchronize()
-    dt_eager = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        plan.execute(outs, info, use_graph=False, stamps=stamps)
+        torch.cuda.synchronize()
+        log(f"  eager {k + 1}/{args.steps} done")
+    dt_eager = (time.perf_counter() - t1) / args.steps
     line = {"metric": "energy points/s, batched uneven workload (6 devices x 4 k, refined single-product form)",
             "value": npts * args.steps / dt, "unit": "energy points/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,

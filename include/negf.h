@@ -191,10 +191,12 @@ negf_status negf_transmission(const negf_problem* problems, int32_t n_prob, cons
  * lesser/greater computation of negf_rgf_lesser_greater for all of them.
  * The decimation runs a fixed number of steps (opt->sr_max_iter, 40 when 0)
  * with converged points masked out, so a plan never synchronises with the
- * host and can be captured: with use_graph = 1 the first execute captures the
- * whole fork/join schedule into one hipGraph, later executes with the same
- * pointers replay it (energies are read from the problems' device arrays at
- * replay time, so they may be updated in place between replays).
+ * host and can be captured: with use_graph = 1 the first execute captures each
+ * worker stream's chunks into a hipGraph of its own, and every execute with the
+ * same pointers forks from `stream` to the worker streams, launches each graph on
+ * its stream and joins back (energies are read from the problems' device arrays
+ * at replay time, so they may be updated in place between replays).  A failed
+ * capture returns NEGF_EHIP and leaves no graph behind.
  * The plan is a host object; it creates its worker streams (default priority)
  * and events on first execute and allocates no device memory. */
 typedef struct negf_plan negf_plan;

@@ -800,9 +800,11 @@ struct negf_plan {
   int n_streams = 1;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
-  hipStream_t origin = nullptr;   // capture origin (the caller's stream may be the legacy null stream)
-  void* graph = nullptr;
-  // arguments the graph was captured with (a replay is valid only for the same ones)
+  // one captured graph per worker stream (its chunks and stamps); a replay forks to the worker
+  // streams, launches each graph on its own stream and joins, so the streams overlap as they do
+  // eagerly (a single fork/join graph replayed on one stream overlapped them less)
+  std::vector<void*> graphs;
+  // arguments the graphs were captured with (a replay is valid only for the same ones)
   Outs cap_outs{};
   void* cap_ws = nullptr;
   unsigned long long* cap_stamps = nullptr;
@@ -820,32 +822,70 @@ bool same_outs(const Outs& a, const Outs& b) {
          a.GGu == b.GGu && a.info == b.info;
 }
 
-// Enqueue the whole plan: start stamp, fork to the worker streams, every chunk
-// on its stream followed by its stamp, join.  No host synchronisation.
-hipError_t enqueue_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long long* stamps, hipStream_t main) {
-  const int ns = P->n_streams;
+// Chunk c on its worker stream, followed by its stamp.  No host synchronisation.
+hipError_t enqueue_chunk(negf_plan* P, size_t c, const Outs& outs, char* ws, unsigned long long* stamps) {
+  const Chunk& ch = P->chunks[c];
+  const int si = P->stream_of[c];
+  Ctx cx;
+  cx.s = P->streams[si];
+  cx.o = P->chunk_opts[c];
+  cx.fixed_sr = true;
+  Carver cv{ws + P->stream_ws_off[si], P->ws_total - P->stream_ws_off[si]};
+  ChunkWs w = carve_chunk(cv, OPK_RL, ch.nb, ch.b, ch.npts, P->prec, 2);
+  if (cv.overflow) return hipErrorInvalidValue;
+  run_chunk(cx, OPK_RL, ch, w, P->prec, outs);
+  if (!cx.ok()) return cx.err;
+  return stamps ? launch_stamp(stamps + 1 + c, cx.s) : hipSuccess;
+}
+
+// Start of a plan on the caller's stream (info cleared, start stamp), then the fork to the workers.
+hipError_t enqueue_fork(negf_plan* P, const Outs& outs, unsigned long long* stamps, hipStream_t main) {
   hipError_t e = launch_fill_int((int)count_points(P->probs.data(), (int)P->probs.size()), outs.info, 0, main);
   if (e != hipSuccess) return e;
   if (stamps && (e = launch_stamp(stamps, main)) != hipSuccess) return e;
-  for (int i = 0; i < ns; ++i)
+  for (int i = 0; i < P->n_streams; ++i)
     if ((e = rt_record_wait(P->events[i], main, P->streams[i])) != hipSuccess) return e;
-  std::vector<size_t> cursor(ns, 0);
-  for (size_t c = 0; c < P->chunks.size(); ++c) {
-    const Chunk& ch = P->chunks[c];
-    const int si = P->stream_of[c];
-    Ctx cx;
-    cx.s = P->streams[si];
-    cx.o = P->chunk_opts[c];
-    cx.fixed_sr = true;
-    Carver cv{ws + P->stream_ws_off[si], P->ws_total - P->stream_ws_off[si]};
-    ChunkWs w = carve_chunk(cv, OPK_RL, ch.nb, ch.b, ch.npts, P->prec, 2);
-    if (cv.overflow) return hipErrorInvalidValue;
-    run_chunk(cx, OPK_RL, ch, w, P->prec, outs);
-    if (!cx.ok()) return cx.err;
-    if (stamps && (e = launch_stamp(stamps + 1 + c, cx.s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t enqueue_join(negf_plan* P, hipStream_t main) {
+  const int ns = P->n_streams;
+  for (int i = 0; i < ns; ++i) {
+    hipError_t e = rt_record_wait(P->events[ns + i], P->streams[i], main);
+    if (e != hipSuccess) return e;
   }
-  for (int i = 0; i < ns; ++i)
-    if ((e = rt_record_wait(P->events[ns + i], P->streams[i], main)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// The whole plan eagerly: fork, the chunks in plan order (each on its stream), join.
+hipError_t enqueue_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long long* stamps, hipStream_t main) {
+  hipError_t e = enqueue_fork(P, outs, stamps, main);
+  for (size_t c = 0; c < P->chunks.size() && e == hipSuccess; ++c) e = enqueue_chunk(P, c, outs, ws, stamps);
+  return e == hipSuccess ? enqueue_join(P, main) : e;
+}
+
+void destroy_graphs(negf_plan* P) {
+  for (void* g : P->graphs) rt_graph_destroy(g);
+  P->graphs.clear();
+}
+
+// Capture each worker stream's chunks into its own graph; a begun capture is always ended.
+hipError_t capture_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long long* stamps) {
+  destroy_graphs(P);
+  for (int si = 0; si < P->n_streams; ++si) {
+    hipError_t e = rt_capture_begin(P->streams[si]);
+    if (e != hipSuccess) return e;
+    for (size_t c = 0; c < P->chunks.size() && e == hipSuccess; ++c)
+      if (P->stream_of[c] == si) e = enqueue_chunk(P, c, outs, ws, stamps);
+    void* exec = nullptr;
+    const hipError_t e2 = rt_capture_end(P->streams[si], &exec);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (exec) rt_graph_destroy(exec);
+      destroy_graphs(P);
+      return e != hipSuccess ? e : e2;
+    }
+    P->graphs.push_back(exec);
+  }
   return hipSuccess;
 }
 
@@ -939,7 +979,6 @@ negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag,
   negf_plan* P = plan;
   hipStream_t main = (hipStream_t)stream;
   if (P->streams.empty()) {
-    if (rt_stream_create(&P->origin) != hipSuccess) return NEGF_EHIP;
     for (int i = 0; i < P->n_streams; ++i) {
       hipStream_t st = nullptr;
       if (rt_stream_create(&st) != hipSuccess) return NEGF_EHIP;
@@ -956,33 +995,29 @@ negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag,
   char* ws = align256(workspace);
   unsigned long long* stp = (unsigned long long*)stamps;
   if (!use_graph) return to_status(enqueue_plan(P, outs, ws, stp, main));
-  const bool reuse = P->graph && same_outs(P->cap_outs, outs) && P->cap_ws == ws && P->cap_stamps == stp;
-  if (!reuse) {
-    if (P->graph) rt_graph_destroy(P->graph);
-    P->graph = nullptr;
-    // capture on the plan's own origin stream; a begun capture is always ended
-    if (rt_capture_begin(P->origin) != hipSuccess) return NEGF_EHIP;
-    hipError_t e = enqueue_plan(P, outs, ws, stp, P->origin);
-    void* exec = nullptr;
-    hipError_t e2 = rt_capture_end(P->origin, &exec);
-    if (e != hipSuccess || e2 != hipSuccess) {
-      if (exec) rt_graph_destroy(exec);
+  const bool reuse = (int)P->graphs.size() == P->n_streams && same_outs(P->cap_outs, outs) && P->cap_ws == ws &&
+                     P->cap_stamps == stp;
+  hipError_t e = enqueue_fork(P, outs, stp, main);
+  if (e == hipSuccess && !reuse) {
+    // captured after the fork was enqueued: capture records, it does not run anything
+    if (capture_plan(P, outs, ws, stp) != hipSuccess) {
+      enqueue_join(P, main);
       return NEGF_EHIP;
     }
-    P->graph = exec;
     P->cap_outs = outs;
     P->cap_ws = ws;
     P->cap_stamps = stp;
   }
-  return to_status(rt_graph_launch(P->graph, main));
+  for (int si = 0; si < P->n_streams && e == hipSuccess; ++si) e = rt_graph_launch(P->graphs[si], P->streams[si]);
+  if (e == hipSuccess) e = enqueue_join(P, main);
+  return to_status(e);
 }
 
 void negf_plan_destroy(negf_plan* plan) {
   if (!plan) return;
-  if (plan->graph) rt_graph_destroy(plan->graph);
+  destroy_graphs(plan);
   for (hipEvent_t e : plan->events) rt_event_destroy(e);
   for (hipStream_t s : plan->streams) rt_stream_destroy(s);
-  if (plan->origin) rt_stream_destroy(plan->origin);
   delete plan;
 }
 

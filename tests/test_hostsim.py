@@ -240,8 +240,10 @@ def test_hostsim_noconv_and_singular_info(sim):
 
 def test_hostsim_plan_matches_plain_calls(sim):
     """The plan (fixed decimation count, chunks over worker streams) gives the
-    same blocks as the plain call; a graph 'replay' with the same pointers is
-    the same enqueue in the simulation."""
+    same blocks as the plain call, eagerly and through the graph path.  The
+    simulation runs kernels when they are enqueued, so the chunks run while the
+    per-stream graphs are captured and a later replay runs only the fork and
+    join on the caller's stream (which rewrites the start stamp)."""
     L, nb = sim
     devs = [w.random_device(3, 4, 21), w.random_device(4, 6, 22, overlap=0.05), w.random_device(5, 4, 23)]
     ens = [well_posed(d, np.linspace(-1.2, 1.2, 9))[:k] for d, k in zip(devs, (3, 2, 3))]
@@ -263,12 +265,13 @@ def test_hostsim_plan_matches_plain_calls(sim):
     out = {k: np.zeros(nd if k.endswith("d") else nu, dtype=np.complex128) for k in ("GRd", "GRu", "GRl", "GLd", "GLu")}
     info = np.zeros(sum(p.n for p in probs), dtype=np.int32)
     stamps = np.zeros(nch + 1, dtype=np.uint64)
-    for use_graph in (0, 1, 1):
+    for run, use_graph in enumerate((0, 1, 1)):
         assert L.negf_plan_execute(plan, use_graph, out["GRd"].ctypes.data, out["GRu"].ctypes.data,
                                    out["GRl"].ctypes.data, out["GLd"].ctypes.data, out["GLu"].ctypes.data, None, None,
                                    info.ctypes.data, stamps.ctypes.data, ws.ctypes.data, ws.size, None) == 0
         assert np.array_equal(info, ref_info)
         for k in out:
             assert rel(out[k], ref[k]) < 1e-13, k
-        assert np.all(stamps[1:] > stamps[0])
+        if run < 2:
+            assert np.all(stamps[1:] > stamps[0])
     L.negf_plan_destroy(plan)
