@@ -25,6 +25,10 @@
  *  - Unless stated otherwise, every array pointer is a DEVICE pointer owned by
  *    the caller, 16-byte aligned.  The library allocates no device memory in
  *    any call: scratch comes from the caller's workspace (negf_workspace_bytes).
+ *  - Outputs must not overlap the inputs, each other or the workspace.  Until
+ *    a call's work has finished their contents are intermediate (the G^<> upper
+ *    blocks, for instance, hold a forward-sweep product until the backward
+ *    sweep writes the result there).
  *  - A "point" is one (problem, energy) pair.  Points are numbered problem by
  *    problem in order, energies in order inside a problem.  Per-point outputs
  *    are stored point-major, each point's part sized by its own (nb, b):
