@@ -81,6 +81,7 @@ struct KArgs {
   int upper;   // skip tiles that lie entirely below the diagonal
   const unsigned long long* kmask;   // zero-slab map of a sparse operand (64 x 64 tiles only)
   int kmask_op;                      // 1: indexed by the column tile, 2: by the row tile
+  int skip_lo, skip_hi;              // columns of C not stored (inversion updates, tag 1)
 };
 
 template <int BM_, int BN_, int WM_, int WN_>
@@ -397,6 +398,9 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
     for (int j = 0; j < FN; ++j) {
       const int col = n0 + wn * CF::TN + j * 16 + li;
       if (!FULL && col >= a.N) continue;
+      if constexpr (TAG == 1) {
+        if (col >= a.skip_lo && col < a.skip_hi) continue;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm * CF::TM + i * 16 + acc_row<T>(lk, v);
@@ -591,6 +595,12 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
   ka.kmask_op = d.kmask_op;
   if (d.skew && d.M != d.N) return hipErrorInvalidValue;
   ka.upper = d.skew ? 1 : 0;
+  // only the inversion-update symbols (tag 1: NN or CN with class KC_INV_GEMM) honour a skip range
+  if (d.skip_hi > d.skip_lo &&
+      (d.prof_class != KC_INV_GEMM || d.opB != OP_N || d.skew || d.skip_lo < 0 || d.skip_hi > d.N))
+    return hipErrorInvalidValue;
+  ka.skip_lo = d.skip_lo;
+  ka.skip_hi = d.skip_hi;
   int tile = d.tile;
   if (tile == GEMM_TILE_DEFAULT) tile = GEMM_TILE_64;
   const bool gauss = d.prec != PREC_F32 && d.gauss;

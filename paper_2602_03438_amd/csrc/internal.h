@@ -48,6 +48,9 @@ struct GemmDesc {
   // whole-tile sizes with K <= 1024; ignored otherwise.
   const unsigned long long* kmask;
   int kmask_op;
+  // Columns [skip_lo, skip_hi) of C are computed but not stored (empty when equal).  Inversion
+  // updates only (prof_class KC_INV_GEMM): there op(A) may be those very columns of C.
+  int skip_lo, skip_hi;
 };
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
 

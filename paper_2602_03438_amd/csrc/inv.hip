@@ -16,7 +16,9 @@
 //      the start of the sub-panel).
 //   2. product: A += W U on the matrix cores (one batched complex product,
 //      K = nb) over the other columns of the sub-panel: pivot rows become
-//      A_JJ^{-1} A_JC, the other rows A_RC - A_RJ A_JJ^{-1} A_JC.
+//      A_JJ^{-1} A_JC, the other rows A_RC - A_RJ A_JJ^{-1} A_JC.  One launch
+//      covers the whole sub-panel; the panel's own columns (W, read in place)
+//      are computed from stale U columns and not stored.
 // Three levels: panels of nb columns inside sub-panels of NBM = 64 columns
 // inside super-panels of NBO = 128 columns.  After a sub-panel the other
 // columns of its super-panel are brought up to date (interchanges through rho,
@@ -502,9 +504,12 @@ ScratchLayout layout(int n) {
 // Columns [c_lo, c_hi) of every matrix: A[:, c] += A[:, jb:jb+K] U[:, c], the
 // first operand being the block's result W read in place (those columns are
 // not written by this product).
+// A[:, c] += W U[:, c] for the columns c in [c_lo, c_hi) outside [s_lo, s_hi), W = A[:, jb, jb + K)
+// read in place (the skipped columns may be W's own: they are computed but not stored).
 hipError_t update_cols(const InvDesc& d, int n, int jb, int K, const double2* U, long sU, int c_lo, int c_hi,
-                       hipStream_t s) {
+                       hipStream_t s, int s_lo = 0, int s_hi = 0) {
   if (c_hi <= c_lo) return hipSuccess;
+  if (s_hi > s_lo && s_lo <= c_lo && s_hi >= c_hi) return hipSuccess;   // nothing left to store
   GemmDesc g{};
   g.M = n; g.N = c_hi - c_lo; g.K = K; g.batch = d.batch;
   g.opA = OP_N; g.opB = OP_N;
@@ -520,6 +525,10 @@ hipError_t update_cols(const InvDesc& d, int n, int jb, int K, const double2* U,
   g.tile = GEMM_TILE_64_8W;
   g.prof_class = KC_INV_GEMM;
   g.gauss = d.gauss;
+  if (s_hi > s_lo) {
+    g.skip_lo = s_lo - c_lo;
+    g.skip_hi = s_hi - c_lo;
+  }
   return launch_gemm(g, s);
 }
 
@@ -571,9 +580,9 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
         else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS / 2>), dim3(d.batch), dim3(MAX_ROWS / 2), 0, s, pa);
         prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // the other columns of the sub-panel: A[:, c] += W U[:, c], W read in place from the panel columns
-        if ((e = update_cols(d, n, j0, nbw, U, sItem, S0, j0, s)) != hipSuccess) return e;
-        if ((e = update_cols(d, n, j0, nbw, U, sItem, j0 + nbw, S0 + ms, s)) != hipSuccess) return e;
+        // the other columns of the sub-panel, on both sides of the panel, in one launch:
+        // A[:, c] += W U[:, c], W read in place from the panel columns (which are not stored)
+        if ((e = update_cols(d, n, j0, nbw, U, sItem, S0, S0 + ms, s, j0, j0 + nbw)) != hipSuccess) return e;
       }
       // middle level: the other columns of the super-panel
       if (ms < mo && (e = block_step(S0, ms, J0, J0 + mo, Um, rho)) != hipSuccess) return e;

@@ -103,6 +103,7 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t) {
     double2* Cp = d.C.p + (long)p * d.C.stride;
     for (int i = 0; i < d.M; ++i)
       for (int j = 0; j < d.N; ++j) {
+        if (j >= d.skip_lo && j < d.skip_hi) continue;   // computed, not stored
         // anti-Hermitian products: the strict lower triangle mirrors the upper one
         const cd v = (d.skew && i > j) ? -std::conj(out[(size_t)j * d.N + i]) : out[(size_t)i * d.N + j];
         Cp[(long)i * d.C.ld + j] = D(v);
