@@ -1,5 +1,5 @@
-"""GPU: plans (uneven shapes over worker streams, one captured hipGraph) and
-the learned seed path of the decimation."""
+"""GPU: plans (uneven shapes over worker streams, one captured hipGraph per
+worker stream) and the learned seed path of the decimation."""
 import numpy as np
 import pytest
 
@@ -64,6 +64,36 @@ def test_plan_graph_replays_match_eager_and_plain_call(nb):
             assert torch.equal(outs[k], eager[k]), (rep, k)
         st = stamps.cpu().numpy()
         assert np.all(st[1:] >= st[0])
+    plan.close()
+
+
+def test_plan_graph_replay_reads_energies_updated_in_place(nb):
+    """The graphs read the energies from the problems' device arrays at replay
+    time: after an in-place update a replay equals an eager run at the new energies."""
+    import torch
+    devs, ens, probs = _problems(nb)
+    plan = nb.Plan(probs, nb.PLAIN_FP64, opts=nb.make_options(sr_max_iter=40),
+                   tunings=[(40, 1, 1, 16, 2), (72, 1, 1, 16, 1), (100, 1, 1, 16, 0)], n_streams=2)
+    outs = plan.outputs()
+    npts = sum(p.n_e for p in probs)
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    plan.execute(outs, info, use_graph=True)
+    torch.cuda.synchronize()
+    first = {k: v.clone() for k, v in outs.items() if v is not None}
+    new_e = [well_posed(d, np.linspace(-0.95, 0.95, 9))[:p.n_e] for d, p in zip(devs, probs)]
+    for p, e in zip(probs, new_e):
+        assert e.size == p.n_e
+        p.energies.copy_(torch.from_numpy(e).to("cuda"))
+    plan.execute(outs, info, use_graph=True)
+    torch.cuda.synchronize()
+    replayed = {k: v.clone() for k, v in outs.items() if v is not None}
+    replayed_info = info.clone()
+    plan.execute(outs, info, use_graph=False)
+    torch.cuda.synchronize()
+    for k in replayed:
+        assert torch.equal(replayed[k], outs[k]), k
+        assert not torch.equal(replayed[k], first[k]), k
+    assert torch.equal(replayed_info, info)
     plan.close()
 
 
