@@ -152,6 +152,8 @@ def main():
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation")
     ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload")
+    ap.add_argument("--uneven-batch", type=int, default=0,
+                    help="points per chunk in the uneven workload (0: all points of a block shape in one chunk)")
     ap.add_argument("--streams", type=int, default=None,
                     help="worker streams the batch is split over (1: the plain call on the current stream); "
                          "default 1 for the ribbon workload, 4 for the uneven one")
@@ -185,6 +187,8 @@ def main():
         log(f"calibration copy of {args.calibrate_copy} MiB done")
         del src, dst
     if args.workload == "uneven":
+        # four worker streams (the hardware queues HIP gives a process by default); each device
+        # shape's points form one chunk (see --uneven-batch)
         args.streams = args.streams or 4
         return bench_uneven(args)
     args.streams = args.streams or 1
@@ -340,7 +344,7 @@ def bench_uneven(args):
     tunings = []
     for b, _ in w.DEVICE_MIX:
         t = autotune.lookup(b, args.cmul)
-        tunings.append((b, t["gemm_tile"], t["gemm_tile_f32"], t["inv_nb"], 2 * n_e))
+        tunings.append((b, t["gemm_tile"], t["gemm_tile_f32"], t["inv_nb"], args.uneven_batch))
     plan = nb.Plan(probs, nb.FP32_REFINE, opts=nb.make_options(sr_max_iter=40, cmul=args.cmul), tunings=tunings,
                    n_streams=args.streams)
     chunks = plan.chunks()

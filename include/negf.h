@@ -192,7 +192,9 @@ negf_status negf_transmission(const negf_problem* problems, int32_t n_prob, cons
  * A plan groups the points of all problems into chunks of one block shape
  * (at most `batch` points each, per shape from `tunings`), assigns chunks to
  * n_streams worker streams by estimated work (longest first), and runs the
- * lesser/greater computation of negf_rgf_lesser_greater for all of them.
+ * lesser/greater computation of negf_rgf_lesser_greater for all of them; each
+ * stream runs its chunks shortest first (the same total, earlier completion
+ * of the small ones).
  * The decimation runs a fixed number of steps (opt->sr_max_iter, 40 when 0)
  * with converged points masked out, so a plan never synchronises with the
  * host and can be captured: with use_graph = 1 the first execute captures each

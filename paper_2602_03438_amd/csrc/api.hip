@@ -795,6 +795,7 @@ struct negf_plan {
   std::vector<Chunk> chunks;
   std::vector<Opts> chunk_opts;
   std::vector<int> stream_of;
+  std::vector<size_t> run_order;   // enqueue order: shortest chunk first (per stream: shortest first)
   std::vector<size_t> stream_ws_off;
   size_t ws_total = 0;
   int n_streams = 1;
@@ -857,10 +858,11 @@ hipError_t enqueue_join(negf_plan* P, hipStream_t main) {
   return hipSuccess;
 }
 
-// The whole plan eagerly: fork, the chunks in plan order (each on its stream), join.
+// The whole plan eagerly: fork, the chunks in run order (each on its stream), join.
 hipError_t enqueue_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long long* stamps, hipStream_t main) {
   hipError_t e = enqueue_fork(P, outs, stamps, main);
-  for (size_t c = 0; c < P->chunks.size() && e == hipSuccess; ++c) e = enqueue_chunk(P, c, outs, ws, stamps);
+  for (size_t k = 0; k < P->run_order.size() && e == hipSuccess; ++k)
+    e = enqueue_chunk(P, P->run_order[k], outs, ws, stamps);
   return e == hipSuccess ? enqueue_join(P, main) : e;
 }
 
@@ -875,8 +877,8 @@ hipError_t capture_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long 
   for (int si = 0; si < P->n_streams; ++si) {
     hipError_t e = rt_capture_begin(P->streams[si]);
     if (e != hipSuccess) return e;
-    for (size_t c = 0; c < P->chunks.size() && e == hipSuccess; ++c)
-      if (P->stream_of[c] == si) e = enqueue_chunk(P, c, outs, ws, stamps);
+    for (size_t k = 0; k < P->run_order.size() && e == hipSuccess; ++k)
+      if (P->stream_of[P->run_order[k]] == si) e = enqueue_chunk(P, P->run_order[k], outs, ws, stamps);
     void* exec = nullptr;
     const hipError_t e2 = rt_capture_end(P->streams[si], &exec);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -943,6 +945,9 @@ negf_status negf_plan_create(const negf_problem* problems, int32_t n_prob, negf_
     carve_chunk(cv, OPK_RL, c.nb, c.b, c.npts, prec, 2);
     ws_need[si] = std::max(ws_need[si], cv.off);
   }
+  // each stream runs its chunks shortest first: the same total per stream, earlier completion
+  // of the small ones
+  P->run_order.assign(order.rbegin(), order.rend());
   size_t off = 0;
   for (int i = 0; i < n_streams; ++i) {
     P->stream_ws_off.push_back(off);
