@@ -655,19 +655,19 @@ void backward_lesser(Ctx& cx, const Chunk& ch, PointWs& pw, negf_precision prec,
   for (int i = nb - 2; i >= 0 && cx.ok(); --i) {
     double2* gli = Ld + (long)i * bb;                 // holds g^<_i
     const double2* Xi = pw.X + (long)i * bb;
-    // V = A_{i+1,i} g^<_i, left in the upper block i by the forward sweep (same product, same
-    // operands); it moves to T2 because the last product below reads it while writing that block
-    cx.lincomb(b, n, ONE, Lu + (long)i * bb, us, ZERO, nullptr, 0, ZERO, pw.T2.p, bb);
-    // Q = -G_{i,i+1} V
-    cx.gemm(pp, OP_N, OP_N, b, n, MONE, GRu + (long)i * bb, us, pw.T2.p, bb, ZERO, nullptr, 0, pw.T3.p, bb);
+    // V = A_{i+1,i} g^<_i was left in the upper block i by the forward sweep (same product, same
+    // operands) and is read from there until that block receives G^<_{i,i+1}.
+    const double2* V = Lu + (long)i * bb;
     // Z = X_i G^<_{i+1,i+1}
     cx.gemm(pp, OP_N, OP_N, b, n, ONE, Xi, us, Ld + (long)(i + 1) * bb, ds, ZERO, nullptr, 0, pw.T4.p, bb);
-    // G^<_ii = g^<_i + Z X_i^H + Q - Q^H
-    cx.gemm(pp, OP_N, OP_C, b, n, ONE, pw.T4.p, bb, Xi, us, ONE, gli, ds, gli, ds);
-    cx.chk(launch_add_skew(b, n, pw.T3.p, bb, gli, ds, cx.s));
-    // G^<_{i,i+1} = V^H G_{i+1,i+1}^H - Z
-    cx.gemm(pp, OP_C, OP_C, b, n, ONE, pw.T2.p, bb, GRd + (long)(i + 1) * bb, ds, MONE, pw.T4.p, bb,
-            Lu + (long)i * bb, us);
+    // G^<_{i,i+1} = V^H G_{i+1,i+1}^H - Z, formed in T3
+    cx.gemm(pp, OP_C, OP_C, b, n, ONE, V, us, GRd + (long)(i + 1) * bb, ds, MONE, pw.T4.p, bb, pw.T3.p, bb);
+    // G^<_ii = g^<_i + Z X_i^H + Q - Q^H with Q = -G_{i,i+1} V.  Since Q^H = V^H G_{i+1,i+1}^H X_i^H
+    // (G_{i,i+1} = -X_i G_{i+1,i+1}), Z X_i^H - Q^H = -G^<_{i,i+1} X_i^H, so
+    // G^<_ii = g^<_i - G_{i,i+1} V - G^<_{i,i+1} X_i^H: two accumulating products, no transpose pass.
+    cx.gemm(pp, OP_N, OP_N, b, n, MONE, GRu + (long)i * bb, us, V, us, ONE, gli, ds, gli, ds);
+    cx.gemm(pp, OP_N, OP_C, b, n, MONE, pw.T3.p, bb, Xi, us, ONE, gli, ds, gli, ds);
+    cx.lincomb(b, n, ONE, pw.T3.p, bb, ZERO, nullptr, 0, ZERO, Lu + (long)i * bb, us);
   }
 }
 

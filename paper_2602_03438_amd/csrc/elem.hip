@@ -214,29 +214,6 @@ __global__ void __launch_bounds__(TD * TR) gamma_sigma_kernel(int b, const doubl
   }
 }
 
-// C += Q - Q^H
-__global__ void __launch_bounds__(TD * TR) add_skew_kernel(int b, const double2* Qb, long sQ, double2* Cb, long sC) {
-  const int p = blockIdx.z;
-  const int i0 = blockIdx.y * TD, j0 = blockIdx.x * TD;
-  __shared__ double2 t[TD][TD + 1];
-  const double2* Q = Qb + (long)p * sQ;
-  double2* C = Cb + (long)p * sC;
-  for (int rr = threadIdx.y; rr < TD; rr += TR) {
-    const int sr = j0 + rr, sc = i0 + threadIdx.x;
-    t[rr][threadIdx.x] = (sr < b && sc < b) ? Q[(long)sr * b + sc] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int rr = threadIdx.y; rr < TD; rr += TR) {
-    const int i = i0 + rr, j = j0 + threadIdx.x;
-    if (i >= b || j >= b) continue;
-    const long o = (long)i * b + j;
-    const double2 q = Q[o];
-    const double2 qh = cconj(t[threadIdx.x][rr]);
-    const double2 c = C[o];
-    C[o] = make_double2(c.x + q.x - qh.x, c.y + q.y - qh.y);
-  }
-}
-
 __global__ void __launch_bounds__(RED_NT) check_finite_kernel(int b, const double2* X, long sX, int* info,
                                                               int info_mod) {
   const int p = blockIdx.x;
@@ -348,15 +325,6 @@ hipError_t launch_gamma_sigma(int b, int batch, const double2* sig, long sS, con
   const int nt = (b + TD - 1) / TD;
   hipLaunchKernelGGL(gamma_sigma_kernel, dim3(nt, nt, batch), dim3(TD, TR), 0, s, b, sig, sS, energies, mu, kT,
                      gamma, sG, sl, sL, sg, sGr);
-  return hipGetLastError();
-}
-
-hipError_t launch_add_skew(int b, int batch, const double2* Q, long sQ, double2* C, long sC, hipStream_t s) {
-  if (batch <= 0) return hipSuccess;
-  const int nt = (b + TD - 1) / TD;
-  prof_begin(KC_ELEM, s);
-  hipLaunchKernelGGL(add_skew_kernel, dim3(nt, nt, batch), dim3(TD, TR), 0, s, b, Q, sQ, C, sC);
-  prof_end(KC_ELEM, s, 0, 16.0 * b * b * batch * 4);
   return hipGetLastError();
 }
 

@@ -122,8 +122,6 @@ hipError_t launch_sr_check(int batch, const double* a2, const double* c2, const 
 hipError_t launch_gamma_sigma(int b, int batch, const double2* sig, long sS, const double* energies, double mu,
                               double kT, double2* gamma, long sG, double2* sl, long sL, double2* sg, long sGr,
                               hipStream_t s);
-// C_p += Q_p - Q_p^H
-hipError_t launch_add_skew(int b, int batch, const double2* Q, long sQ, double2* C, long sC, hipStream_t s);
 // T_p = Re sum_ij P_p[i][j] conj(Q_p[i][j])
 hipError_t launch_dot_re(int b, int batch, const double2* P, long sP, const double2* Q, long sQ, double* out,
                          hipStream_t s);

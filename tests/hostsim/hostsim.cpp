@@ -259,18 +259,6 @@ hipError_t launch_gamma_sigma(int b, int batch, const double2* sig, long sS, con
   return hipSuccess;
 }
 
-hipError_t launch_add_skew(int b, int batch, const double2* Q, long sQ, double2* Cb, long sC, hipStream_t) {
-  for (int p = 0; p < batch; ++p)
-    for (int i = 0; i < b; ++i)
-      for (int j = 0; j < b; ++j) {
-        const cd q = C(Q[(long)p * sQ + (long)i * b + j]);
-        const cd qh = std::conj(C(Q[(long)p * sQ + (long)j * b + i]));
-        double2& c = Cb[(long)p * sC + (long)i * b + j];
-        c = D(C(c) + q - qh);
-      }
-  return hipSuccess;
-}
-
 hipError_t launch_dot_re(int b, int batch, const double2* P, long sP, const double2* Q, long sQ, double* out,
                          hipStream_t) {
   for (int p = 0; p < batch; ++p) {
