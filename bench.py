@@ -68,9 +68,10 @@ def traffic_per_item():
 
 
 def make_runner(nb, probs, prec, outputs, ws, opts, streams, points, sr_max_iter=40):
-    """One step of the hot path: the plain call, or a plan that splits the
-    batch over worker streams so that one half's latency-bound inversion
-    panels overlap the other half's products."""
+    """One step of the hot path: the plain call (opts carries the decimation
+    step count), or a plan that splits the batch over worker streams so that
+    one half's latency-bound inversion panels overlap the other half's
+    products."""
     import torch
     if streams <= 1:
         def run():
@@ -116,6 +117,25 @@ def run_steps(nb, probs, batches, prec, steps, warmup, runner, profile=False):
     return dt, n_done, {"info": info, "failures": failures}, stats
 
 
+ORACLE_NAMES = ("GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper")
+
+
+def point_outputs(nb, probs, outputs, batch0, runner):
+    """One untimed step on the first energy batch; the host copy of the outputs
+    of its middle point (the point the CPU oracle solves)."""
+    import torch
+    probs[0].energies.copy_(torch.from_numpy(batch0).to("cuda"))
+    info = runner()
+    torch.cuda.synchronize()
+    k0 = len(batch0) // 2
+    views = nb._views(outputs, probs)
+    return {n: views[n][0][k0].cpu().numpy() for n in ORACLE_NAMES}, int(info[k0].item())
+
+
+def errors_vs_oracle(pt, ref):
+    return {n: float(np.linalg.norm(pt[n] - getattr(ref, n)) / np.linalg.norm(getattr(ref, n))) for n in ORACLE_NAMES}
+
+
 def cpu_baseline(dev, energies):
     """The FP64 oracle on one energy point of the same workload."""
     from oracle import rgf as orgf
@@ -148,9 +168,12 @@ def main():
     ap.add_argument("--inv-nb", type=int, default=0, help="inversion panel width (0: tuned)")
     ap.add_argument("--cmul", type=int, choices=[3, 4], default=3,
                     help="real products per complex double product (3: Gauss's method)")
-    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned"], default="ribbon",
+    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm"], default="ribbon",
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
-                         "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation")
+                         "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation; gemm: the "
+                         "dominant product kernel alone through negf_zgemm_batched at the headline's block size "
+                         "and batch (for hardware counters)")
+    ap.add_argument("--gemm-batch", type=int, default=256, help="products per launch in the gemm workload")
     ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload")
     ap.add_argument("--uneven-batch", type=int, default=0,
                     help="points per chunk in the uneven workload (0: all points of a block shape in one chunk)")
@@ -158,7 +181,7 @@ def main():
                     help="worker streams the batch is split over (1: the plain call on the current stream); "
                          "default 1 for the ribbon workload, 4 for the uneven one")
     ap.add_argument("--sr-max-iter", type=int, default=40,
-                    help="decimation steps a plan runs (it cannot poll convergence from the host)")
+                    help="decimation steps enqueued per call (converged points are masked out of later steps)")
     ap.add_argument("--learned-energies", type=int, default=250, help="training energies per lead")
     ap.add_argument("--learned-eval", type=int, default=256, help="evaluation energies per held-out lead")
     ap.add_argument("--learned-b", type=int, default=512)
@@ -186,6 +209,8 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {args.calibrate_copy} MiB done")
         del src, dst
+    if args.workload == "gemm":
+        return bench_gemm(args)
     if args.workload == "uneven":
         # four worker streams (the hardware queues HIP gives a process by default); each device
         # shape's points form one chunk (see --uneven-batch)
@@ -203,7 +228,7 @@ def main():
     from paper_2602_03438_amd import autotune
     tuned = autotune.lookup(B, args.cmul)
     opts = nb.make_options(inv_nb=args.inv_nb or tuned["inv_nb"], cmul=args.cmul, gemm_tile=tuned["gemm_tile"],
-                           gemm_tile_f32=tuned["gemm_tile_f32"])
+                           gemm_tile_f32=tuned["gemm_tile_f32"], sr_max_iter=args.sr_max_iter)
     ws = nb.Workspace()
     outputs = nb._rgf_outputs(probs, True, False, True)
     torch.cuda.synchronize()
@@ -214,25 +239,29 @@ def main():
     dt, n_pts, res, stats = run_steps(nb, probs, batches, nb.PLAIN_FP64, args.steps, args.warmup, runner,
                                       profile=True)
     value = n_pts / dt
+    n_valid = n_pts - len(res["failures"])
     g = stats["gemm_f64"]
-    achieved = g["flops"] / (g["total_ms"] * 1e-3) if g["total_ms"] > 0 else 0.0
+    # the library counts the flops the matrix cores execute: a complex product of
+    # M x K by K x N takes four real products (8 M N K flop) or, in Gauss's form,
+    # three (6 M N K flop; the operand sums are O(MK + KN) and not counted).  The
+    # conventional complex count 8 M N K is reported beside it as zgemm_equiv_tflops.
+    real_products = 3 if args.cmul == 3 else 4
+    executed = g["flops"] / (g["total_ms"] * 1e-3) if g["total_ms"] > 0 else 0.0
     launches = max(1, g["launches"])
     per_item = traffic_per_item()
-    items_per_launch = g["flops"] / launches / (8.0 * B ** 3)
+    items_per_launch = g["flops"] / launches / (2.0 * real_products * B ** 3)
     traffic = per_item * items_per_launch if per_item else None
-    # the product algorithm's own flops: a complex product of M x K by K x N takes
-    # four real products (8 M N K flop) or, in Gauss's form, three (6 M N K flop;
-    # the operand sums are O(MK + KN) and not counted).  The conventional complex
-    # count 8 M N K is reported beside it as zgemm_equiv_tflops.
-    real_products = 3 if args.cmul == 3 else 4
-    executed = achieved * real_products / 4.0
+    # every class's executed flops over the whole timed region (the step, not just the products)
+    step_flops = sum(v["flops"] for v in stats.values())
     roof = {"bound": "mfma", "kernel": "zgemm_kernel<double> (batched complex FP64 product)",
             "achieved": executed / 1e12, "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
             "frac": executed / PEAK["f64"], "traffic": traffic,
             "launches": int(g["launches"]), "avg_launch_ms": g["total_ms"] / launches,
-            "flops_per_launch": g["flops"] / launches * real_products / 4.0,
+            "flops_per_launch": g["flops"] / launches,
             "flop_count": f"{2 * real_products} M N K per complex product ({real_products} real products)",
-            "zgemm_equiv_tflops": achieved / 1e12,
+            "zgemm_equiv_tflops": executed * 4.0 / real_products / 1e12,
+            "step_executed_tflops": step_flops / dt / 1e12,
+            "step_frac": step_flops / dt / PEAK["f64"],
             "items_per_launch": items_per_launch,
             "traffic_bytes_per_item": per_item,
             "algorithmic_bytes_per_item": 3 * 16 * B * B,
@@ -242,6 +271,7 @@ def main():
                   "tflops": (v["flops"] / (v["total_ms"] * 1e-3) / 1e12) if v["total_ms"] > 0 and v["flops"] else None}
               for k, v in stats.items() if v["launches"]}
 
+    at_oracle = {"plain_fp64": point_outputs(nb, probs, outputs, batches[0], runner)}
     if plan:
         plan.close()          # its workspace is not needed by the runs below
     chosen = None
@@ -259,16 +289,20 @@ def main():
             runner_c, plan_c = make_runner(nb, probs, prec, outputs, ws, opts, args.streams, args.points,
                                              args.sr_max_iter)
             dtc, nc, resc, st = run_steps(nb, probs, batches, prec, args.steps, args.warmup, runner_c, profile=True)
-            if plan_c:
-                plan_c.close()
             gr = views["GR_diag"][0].index_select(0, sample)
             gl = views["GL_diag"][0].index_select(0, sample)
+            at_oracle[name] = point_outputs(nb, probs, outputs, batches[0], runner_c)
+            if plan_c:
+                plan_c.close()
             eR = (torch.linalg.vector_norm(gr - plain_GR) / torch.linalg.vector_norm(plain_GR)).item()
             eL = (torch.linalg.vector_norm(gl - plain_GL) / torch.linalg.vector_norm(plain_GL)).item()
-            # matrix-core time at peak: double products execute real_products/4 of the
-            # conventional 8 M N K count
-            ideal = st["gemm_f64"]["flops"] * real_products / 4.0 / PEAK["f64"] + st["gemm_f32"]["flops"] / PEAK["f32"]
+            # matrix-core time at peak of the executed products
+            ideal = st["gemm_f64"]["flops"] / PEAK["f64"] + st["gemm_f32"]["flops"] / PEAK["f32"]
             out[name] = {"value": nc / dtc, "ms_per_step": dtc / args.steps * 1e3,
+                         "single_precision_products": "backward retarded sweep only, each block followed by one "
+                                                      "FP64 residual correction; forward retarded and both lesser "
+                                                      "sweeps, inversions and decimation in FP64"
+                         if name == "fp32_refine" else "every sweep product (no correction)",
                          "err_vs_plain_GR_diag": eR, "err_vs_plain_GL_diag": eL, "err_sample_points": 8,
                          "gemm_f32_tflops": (st["gemm_f32"]["flops"] / (st["gemm_f32"]["total_ms"] * 1e-3) / 1e12)
                          if st["gemm_f32"]["total_ms"] > 0 else None,
@@ -277,9 +311,14 @@ def main():
         chosen = out
 
     cpu = None
+    vs_oracle = None
     if not args.no_cpu:
         log("CPU oracle on one point ...")
-        cpu, _, _ = cpu_baseline(dev, batches[0])
+        cpu, ref, E0 = cpu_baseline(dev, batches[0])
+        # every form's outputs at the same point against the oracle (all output kinds)
+        vs_oracle = {"E": E0, "oracle_lead_residuals": [ref.lead_l.residual, ref.lead_r.residual]}
+        for name, (pt, inf) in at_oracle.items():
+            vs_oracle[name] = {"info": inf, **errors_vs_oracle(pt, ref)}
 
     line = {
         "metric": "energy points/s, RGF G^R+G^< (Nb=60, b=512): plain FP64 vs chosen form",
@@ -302,13 +341,59 @@ def main():
                    "sr_max_iter": args.sr_max_iter,
                    "real_products_per_complex_product": args.cmul,
                    "outputs": "G^R diag/upper/lower + G^< diag/upper in HBM"},
+        "valid_points_per_s": n_valid / dt,
         "info_nonzero": len(res["failures"]),
         "failures": res["failures"][:8],
         "roofline": roof,
         "kernels": kstats,
         "chosen_form": chosen,
+        "errors_vs_oracle": vs_oracle,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_gemm(args):
+    """The dominant kernel alone: batched b x b x b complex FP64 products (Gauss's
+    three-product form, the headline's tile) launched through negf_zgemm_batched,
+    timed with HIP events on the launching stream.  Used for hardware counters
+    of the product kernel (MFMA activity, HBM bytes)."""
+    import torch
+    from paper_2602_03438_amd import autotune
+    from paper_2602_03438_amd import binding as nb
+    tuned = autotune.lookup(B, args.cmul)
+    batch = args.gemm_batch
+    g = torch.Generator(device="cuda").manual_seed(7)
+    A = torch.randn(batch, B, B, dtype=torch.complex128, device="cuda", generator=g)
+    Bm = torch.randn(batch, B, B, dtype=torch.complex128, device="cuda", generator=g)
+    Cm = torch.zeros(batch, B, B, dtype=torch.complex128, device="cuda")
+    prec = 2 if args.cmul == 3 else 0
+    for _ in range(args.warmup):
+        nb.zgemm(A, Bm, Cm, prec=prec, tile=tuned["gemm_tile"])
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(s)
+        nb.zgemm(A, Bm, Cm, prec=prec, tile=tuned["gemm_tile"])
+        ev[k][1].record(s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = [a.elapsed_time(b) for a, b in ev]
+    real_products = 3 if args.cmul == 3 else 4
+    flops = 2.0 * real_products * B ** 3 * batch
+    a0, b0, c0 = A[0].cpu().numpy(), Bm[0].cpu().numpy(), Cm[0].cpu().numpy()
+    ref = a0 @ b0
+    err = float(np.linalg.norm(c0 - ref) / np.linalg.norm(ref))
+    avg = float(np.mean(ms))
+    line = {"metric": "batched complex FP64 product (b x b x b), executed TFLOP/s", "value": flops / (avg * 1e-3) / 1e12,
+            "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{batch} products of {B}x{B} complex128 per launch, tile {tuned['gemm_tile']}, "
+                                   f"{real_products} real products per complex product"},
+            "avg_launch_ms": avg, "min_launch_ms": float(np.min(ms)), "frac_of_fp64_peak": flops / (avg * 1e-3) / PEAK["f64"],
+            "algorithmic_bytes_per_launch": 3 * 16 * B * B * batch, "rel_err_vs_torch_item0": err}
     print(json.dumps(line), flush=True)
 
 

@@ -46,9 +46,11 @@
  *    NEGF_ENOCONV (decimation not converged or residual above the accept
  *    threshold), NEGF_ESINGULAR (zero pivot), NEGF_ENONFINITE (NaN/Inf).
  *    A HIP launch failure returns NEGF_EHIP.
- *  - Synchronisation: the decimation loop checks convergence on the host
- *    after each sweep once the minimum count is reached, which synchronises
- *    `stream`; otherwise calls are asynchronous.
+ *  - Synchronisation: none.  Every call only enqueues work on `stream` and
+ *    reads nothing back; the decimation enqueues exactly sr_max_iter steps
+ *    and masks each (point, lead) pair out of the later steps once it has
+ *    converged, so calls may be captured into a graph (steps after the last
+ *    pair has converged launch workgroups that exit at once).
  *  - Thread safety: calls on distinct workspaces and streams may run
  *    concurrently.  The profiling counters are process-global.
  */
@@ -113,7 +115,7 @@ typedef struct negf_problem {
 /* Optional knobs (pass NULL for the defaults in brackets). */
 typedef struct negf_options {
   double sr_tol;        /* decimation stops when ||a||_F, ||c||_F <= tol ||d||_F  [1e-14] */
-  int32_t sr_max_iter;  /* decimation iteration cap                              [100]   */
+  int32_t sr_max_iter;  /* decimation steps enqueued (iteration cap)             [64]    */
   double sr_accept;     /* normalised Dyson residual above which info=ENOCONV   [1e-8]  */
   int32_t batch;        /* points in flight per group (0: all points of the call) [0]   */
   int32_t inv_nb;       /* panel width of the block inversion (16 or 32)          [16]  */
@@ -282,20 +284,25 @@ negf_status negf_mlp_infer_bf16(int32_t n, int32_t F, int32_t H, int32_t O, cons
                                 const float* b1, const uint16_t* W2b, const float* b2, const uint16_t* W3b,
                                 const float* b3, uint16_t* scratch, float* Y, void* stream);
 
-/* ---- profiling: per kernel class launch counts, algorithmic flops and
- * event-timed durations, recorded on the launching stream.  NEGF_KC_GEMM_CPL
- * holds the products with a coupling-block operand whose zero slabs are
- * skipped (either precision); their flops are counted as for dense blocks, an
- * upper bound of the work done. ---- */
+/* ---- profiling: per kernel class launch counts, executed flops and
+ * event-timed durations, recorded on the launching stream.  Flops are those
+ * the kernels execute: 6 M N K per complex product in Gauss's three-product
+ * form, 8 M N K with four real products, 8 n w^2 per inversion panel of width
+ * w.  What a launch executes depends on device data (the decimation masks
+ * converged pairs out of later steps; NEGF_KC_GEMM_CPL, the products with a
+ * coupling-block operand, skip its zero slabs), so the kernels count their
+ * own flops into device counters while profiling is on (one set per process,
+ * on the device current when profiling was enabled). ---- */
 enum { NEGF_KC_GEMM64 = 0, NEGF_KC_GEMM32 = 1, NEGF_KC_INV_PANEL = 2, NEGF_KC_INV_SWAP = 3, NEGF_KC_INV_PERM = 4,
        NEGF_KC_ELEM = 5, NEGF_KC_INV_GEMM = 6, NEGF_KC_GEMM_CPL = 7, NEGF_KC_COUNT = 8 };
 typedef struct negf_kernel_stats {
   int64_t launches;
   double total_ms;   /* sum of per-launch event durations */
-  double flops;      /* algorithmic real flops of those launches */
+  double flops;      /* real flops the matrix cores executed in those launches */
   double bytes;      /* algorithmic HBM bytes of those launches */
 } negf_kernel_stats;
-/* Enable (1) / disable (0) timing; enabling resets the counters.  Timing
+/* Enable (1) / disable (0) timing; enabling resets the counters (and
+ * synchronises with the device to clear the instruction counter).  Timing
  * pairs events around each launch; counters are read after the caller has
  * synchronised every stream it used. */
 void negf_profile_enable(int32_t on);

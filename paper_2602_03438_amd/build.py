@@ -1,9 +1,6 @@
 """Build libnegf.so (HIP, gfx950) in place.
 
     python -m paper_2602_03438_amd.build          # compile every source, link
-    python -m paper_2602_03438_amd.build --probe  # also the product-kernel traffic harness
-    python -m paper_2602_03438_amd.build --check  # also compile the host-only
-                                                  # argument checks with ASan/UBSan
 
 Each translation unit under csrc/ is compiled by hipcc for gfx950 into an
 object under _build/, then linked into paper_2602_03438_amd/libnegf.so.
@@ -69,24 +66,5 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-PROBE_SRC = os.path.join(HERE, "probe", "gemm_traffic.hip")
-PROBE = os.path.join(HERE, "probe", "gemm_traffic")
-
-
-def build_probe(verbose: bool = False) -> str:
-    """The product-kernel traffic harness (a standalone program, not linked into the library)."""
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC, PROBE_SRC, "-o", PROBE]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for the traffic harness:\n{r.stdout}\n{r.stderr}")
-    return PROBE
-
-
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
-    if "--probe" in sys.argv:
-        print(build_probe(verbose="-v" in sys.argv))

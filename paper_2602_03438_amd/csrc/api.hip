@@ -26,7 +26,7 @@ const double2 ZERO = {0.0, 0.0};
 
 struct Opts {
   double tol = 1e-14;
-  int max_iter = 100;
+  int max_iter = 64;
   double accept = 1e-8;
   int batch = 0;
   int inv_nb = 16;
@@ -209,7 +209,6 @@ ChunkWs carve_chunk(Carver& cv, int opk, int nb, int b, int npts, negf_precision
 struct Ctx {
   hipStream_t s;
   Opts o;
-  bool fixed_sr = false;   // run exactly o.max_iter decimation steps (no host reads; graph capture)
   hipError_t err = hipSuccess;
   bool ok() const { return err == hipSuccess; }
   void chk(hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; }
@@ -355,7 +354,7 @@ bool assemble_sigma_lg(Ctx& cx, const Chunk& ch, int i, int kind, const PointWs&
 // (per pair, stride b*b) and the iteration counts / residuals / info.
 void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, LeadWs& w, const double2* seed,
                     long seed_stride, Blocks sig_out_L, Blocks sig_out_R, int* info_pts, int* iters_out,
-                    double* resid_out, int* iters_host_max) {
+                    double* resid_out) {
   const int b = ch.b, nb = ch.nb, npts = ch.npts, np = npts * nsides;
   const long bb = (long)b * b;
   hipStream_t s = cx.s;
@@ -422,7 +421,10 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
   cx.lincomb(b, np, ONE, w.beta.p, bb, ZERO, nullptr, 0, ZERO, w.c.p, bb);
   Blocks a = w.a, c = w.c, t1 = w.t1, t2 = w.t2;
   const Blocks D = w.eps;
-  int hmax = 0;
+  // Exactly max_iter steps are enqueued: a pair that has converged (or been closed by its seed) is
+  // masked out of every later launch, so nothing is read back on the host and the whole call
+  // stays asynchronous (and capturable); steps after the last pair has converged only launch
+  // workgroups that exit at once.
   for (int it = 1; it <= cx.o.max_iter && cx.ok(); ++it) {
     const int* act = w.active;
     // g = eps^{-1} with eps = eps_s + D formed in t1 (the inversion overwrites its input)
@@ -467,14 +469,7 @@ void run_decimation(Ctx& cx, const Chunk& ch, const int* sides, int nsides, Lead
     cx.chk(launch_frob2(b, np, a.p, bb, 0.0, w.active, w.part, w.a2, s));
     cx.chk(launch_frob2(b, np, c.p, bb, 0.0, w.active, w.part, w.c2, s));
     cx.chk(launch_sr_check(np, w.a2, w.c2, w.d2, cx.o.tol, it, w.active, w.iters, w.n_active, s));
-    hmax = it;
-    if (!cx.fixed_sr) {
-      int host_active = 0;
-      cx.chk(rt_read_int(&host_active, w.n_active, s));
-      if (host_active == 0) break;
-    }
   }
-  if (iters_host_max) *iters_host_max = hmax;
   if (!cx.ok()) return;
   // --- g_s = eps_s^{-1} (pairs that ran the decimation); seeded-accepted pairs keep g0
   if (seed) {
@@ -511,7 +506,7 @@ struct Outs {
 // Leads of both sides into pw.sigL / pw.sigR, Gamma and (optionally) Sigma^<>.
 void leads_for_sweeps(Ctx& cx, const Chunk& ch, ChunkWs& w, int* info, bool lesser) {
   const int sides[2] = {0, 1};
-  run_decimation(cx, ch, sides, 2, w.lw, nullptr, 0, w.pw.sigL, w.pw.sigR, info, nullptr, nullptr, nullptr);
+  run_decimation(cx, ch, sides, 2, w.lw, nullptr, 0, w.pw.sigL, w.pw.sigR, info, nullptr, nullptr);
   const int b = ch.b;
   for (const Seg& sg : ch.segs) {
     const double* en = sg.pr->energies + sg.e0;
@@ -830,7 +825,6 @@ hipError_t enqueue_chunk(negf_plan* P, size_t c, const Outs& outs, char* ws, uns
   Ctx cx;
   cx.s = P->streams[si];
   cx.o = P->chunk_opts[c];
-  cx.fixed_sr = true;
   Carver cv{ws + P->stream_ws_off[si], P->ws_total - P->stream_ws_off[si]};
   ChunkWs w = carve_chunk(cv, OPK_RL, ch.nb, ch.b, ch.npts, P->prec, 2);
   if (cv.overflow) return hipErrorInvalidValue;
@@ -1076,7 +1070,7 @@ negf_status negf_obc_surface(const negf_problem* problems, int32_t n_prob, int32
     const int sides[1] = {side};
     const double2* sd = seed ? (const double2*)seed + blk_off : nullptr;
     run_decimation(cx, ch, sides, 1, w.lw, sd, bb, sig, sig, info + ch.first_point,
-                   iters ? iters + ch.first_point : nullptr, resid ? resid + ch.first_point : nullptr, nullptr);
+                   iters ? iters + ch.first_point : nullptr, resid ? resid + ch.first_point : nullptr);
     cx.lincomb(ch.b, ch.npts, ONE, w.lw.g.p, bb, ZERO, nullptr, 0, ZERO, (double2*)g_surf + blk_off, bb);
     if (!cx.ok()) break;
   }

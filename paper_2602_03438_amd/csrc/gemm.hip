@@ -82,6 +82,8 @@ struct KArgs {
   const unsigned long long* kmask;   // zero-slab map of a sparse operand (64 x 64 tiles only)
   int kmask_op;                      // 1: indexed by the column tile, 2: by the row tile
   int skip_lo, skip_hi;              // columns of C not stored (inversion updates, tag 1)
+  unsigned long long* flop_slots;    // nullable (profiling): each wave adds the flops of the matrix
+                                     // instructions it issued to one of PROF_SLOTS counters
 };
 
 template <int BM_, int BN_, int WM_, int WN_>
@@ -208,6 +210,14 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
   constexpr bool SPARSE_OK = TAG == 2 && BM == 64 && BN == 64;
   // (for the dense kernels the guard folds to true at compile time)
   auto on_ij = [&](unsigned on, int i, int j) { return !SPARSE_OK || ((on >> (i * FN + j)) & 1u) != 0u; };
+  // profiling: the flops of the fragment products a wave issued ((GAUSS ? 3 : 4) real products of
+  // BK / 4 matrix instructions each, 2 * 16 * 16 * 4 flop per instruction), striped over the slots
+  auto prof_count = [&](unsigned long long* slots, unsigned fr) {
+    if (slots && (threadIdx.x & 63) == 0) {
+      const unsigned long long fl = (unsigned long long)fr * (GAUSS ? 3u : 4u) * (BK / 4) * 2048ull;
+      atomicAdd(slots + ((blockIdx.x * (CF::NT / 64) + (threadIdx.x >> 6)) & (PROF_SLOTS - 1)), fl);
+    }
+  };
   auto mac = [&](const CT* __restrict__ xA, const CT* __restrict__ xB, unsigned on) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
@@ -280,9 +290,10 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
       store_tile_v<T, BM, NT, CF::LA, A_ROW>(sA[st], ra, OPA == OP_C);
       store_tile_v<T, BN, NT, CF::LB, B_ROW>(sB[st], rb, OPB == OP_C);
     };
-    // The K-steps that contribute, as a bit set (all of them unless a zero-slab
-    // map of a sparse operand says otherwise); they are taken in ascending
-    // order, the j-th of them in LDS stage j & 1 through register set j & 1.
+    // The K-steps that contribute are taken in ascending order, the j-th of
+    // them in LDS stage j & 1 through register set j & 1: every step 0..nk-1
+    // for a dense product, otherwise (nk <= 64) the bit set `rem` of the steps
+    // a zero-slab map of the sparse operand leaves.
     unsigned long long rem = nk >= 64 ? ~0ull : (1ull << nk) - 1;
     // per wave: K-steps in which each of its row (op 2) or column (op 1) fragments is nonzero
     unsigned long long fm[CF::FM > CF::FN ? CF::FM : CF::FN];
@@ -307,8 +318,11 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
         }
       return on;
     };
-    const int nact = __popcll(rem);
+    const int nact = sparse ? __popcll(rem) : nk;
+    unsigned frags = 0u;   // fragment products issued by this wave (K-step x enabled (i, j))
+    int kseq = 0;
     auto next_k = [&]() {
+      if (!sparse) return kseq++;
       const int k = __builtin_ctzll(rem);
       rem &= rem - 1;
       return k;
@@ -331,7 +345,11 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
         kset0 = next_k();
         gl(qa[0], qb[0], kset0 * BK);
       }
-      mac(sA[0], sB[0], enables(kst0));
+      {
+        const unsigned on0 = enables(kst0);
+        frags += __popc(on0);
+        mac(sA[0], sB[0], on0);
+      }
       if (j + 1 < nact) {
         ls(qa[1], qb[1], 1);
         kst1 = kset1;
@@ -342,7 +360,9 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
           kset1 = next_k();
           gl(qa[1], qb[1], kset1 * BK);
         }
-        mac(sA[1], sB[1], enables(kst1));
+        const unsigned on1 = enables(kst1);
+        frags += __popc(on1);
+        mac(sA[1], sB[1], on1);
         if (j + 2 < nact) {
           ls(qa[0], qb[0], 0);
           kst0 = kset0;
@@ -350,6 +370,7 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
         __syncthreads();
       }
     }
+    prof_count(a.flop_slots, frags);
   } else {
     double2 ra[CF::LA], rb[CF::LB];
     auto gload = [&](int k0) {
@@ -373,6 +394,7 @@ __global__ void __launch_bounds__(CF::NT, CF::NT >= 1024 ? 1 : 2) zgemm_kernel(K
       if (kt + 1 < nk) lstore(st ^ 1);
       __syncthreads();
     }
+    prof_count(a.flop_slots, (unsigned)nk * FM * FN);
   }
 
   double2* __restrict__ Cp = a.C + (long)p * a.sC;
@@ -554,29 +576,6 @@ __global__ void __launch_bounds__(256) slab_map_kernel(int b, const double2* H, 
   }
 }
 
-// Fraction of the output tiles a launch computes (all, or those touching the upper triangle).
-template <typename CF>
-double computed_fraction(int M, int N, bool upper) {
-  const int tm = (M + CF::BM - 1) / CF::BM, tn = (N + CF::BN - 1) / CF::BN;
-  if (!upper) return 1.0;
-  long cnt = 0;
-  for (int i = 0; i < tm; ++i)
-    for (int j = 0; j < tn; ++j)
-      if (j * CF::BN + CF::BN > i * CF::BM) ++cnt;
-  return (double)cnt / ((double)tm * tn);
-}
-
-double tile_fraction(int tile, bool gauss, int M, int N, bool upper) {
-  if (gauss && tile == GEMM_TILE_128x128) tile = GEMM_TILE_128x64;
-  switch (tile) {
-    case GEMM_TILE_128x64: return computed_fraction<Cfg128x64>(M, N, upper);
-    case GEMM_TILE_128x128: return computed_fraction<Cfg128>(M, N, upper);
-    case GEMM_TILE_64_8W: return computed_fraction<Cfg64w8>(M, N, upper);
-    case GEMM_TILE_128x64_16W: return computed_fraction<Cfg128x64w16>(M, N, upper);
-    default: return computed_fraction<Cfg64>(M, N, upper);
-  }
-}
-
 }  // namespace
 
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
@@ -593,6 +592,7 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
   ka.tiles_m = ka.tiles_n = 0;
   ka.kmask = (d.kmask_op == 1 || d.kmask_op == 2) ? d.kmask : nullptr;
   ka.kmask_op = d.kmask_op;
+  ka.flop_slots = nullptr;
   if (d.skew && d.M != d.N) return hipErrorInvalidValue;
   ka.upper = d.skew ? 1 : 0;
   // only the inversion-update symbols (tag 1: NN or CN with class KC_INV_GEMM) honour a skip range
@@ -604,17 +604,18 @@ hipError_t launch_gemm(const GemmDesc& d, hipStream_t s) {
   int tile = d.tile;
   if (tile == GEMM_TILE_DEFAULT) tile = GEMM_TILE_64;
   const bool gauss = d.prec != PREC_F32 && d.gauss;
-  const double frac = tile_fraction(tile, gauss, d.M, d.N, d.skew != 0);
   const bool coupling = ka.kmask && (ka.kmask_op == 1 || ka.kmask_op == 2);
   const int cls = d.prof_class >= 0 ? d.prof_class
                   : coupling        ? KC_GEMM_CPL
                                     : (d.prec == PREC_F32 ? KC_GEMM32 : KC_GEMM64);
+  ka.flop_slots = prof_flop_slots(cls);
   prof_begin(cls, s);
   hipError_t e = d.prec == PREC_F32 ? launch_t<float, false>(d, ka, tile, s)
                  : gauss            ? launch_t<double, true>(d, ka, tile, s)
                                     : launch_t<double, false>(d, ka, tile, s);
-  prof_end(cls, s, frac * 8.0 * d.M * (double)d.N * d.K * d.batch,
-           16.0 * d.batch * ((double)d.M * d.K + (double)d.K * d.N + 2.0 * d.M * d.N));
+  // flops are counted on the device (only the items, tiles and K-steps that run); bytes: A and B
+  // read, C read and written
+  prof_end(cls, s, 0.0, 16.0 * d.batch * ((double)d.M * d.K + (double)d.K * d.N + 2.0 * d.M * d.N));
   if (e == hipSuccess && d.skew) {
     const int nt = (d.M + MIR - 1) / MIR;
     hipLaunchKernelGGL(skew_mirror_kernel, dim3(nt, nt, d.batch), dim3(256), 0, s, d.M, d.C.p, d.C.ld, d.C.stride,

@@ -146,8 +146,6 @@ hipError_t launch_closure_accept(int np, const double* r2, const double* m2, con
                                  int* active, int* iters, int* accepted, int* closed, hipStream_t s);
 
 // ---- runtime helpers and profiling (prof.hip) ----
-// *host_dst = *dev_src after the stream has drained (synchronises s)
-hipError_t rt_read_int(int* host_dst, const int* dev_src, hipStream_t s);
 hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s);
 // worker streams (default priority), fork/join events, stream capture into one graph
 hipError_t rt_stream_create(hipStream_t* s);
@@ -166,5 +164,10 @@ enum KernelClass { KC_GEMM64 = 0, KC_GEMM32 = 1, KC_INV_PANEL = 2, KC_INV_SWAP =
                    KC_INV_GEMM = 6, KC_GEMM_CPL = 7, KC_COUNT = 8 };
 void prof_begin(int cls, hipStream_t s);
 void prof_end(int cls, hipStream_t s, double flops, double bytes);
+// Device counters of executed flops of class cls (PROF_SLOTS of them, a kernel adds to
+// slot (wave id) & (PROF_SLOTS - 1)); nullptr when profiling is off or a graph is being
+// captured.  negf_profile_read sums them.
+constexpr int PROF_SLOTS = 1024;
+unsigned long long* prof_flop_slots(int cls);
 
 }  // namespace negf

@@ -56,6 +56,7 @@ struct PanelArgs {
   int* rho; long sS;        // rho_p[i]: row, at the start of the sub-panel, now at position i
   int* info; int info_mod;
   const int* active;
+  unsigned long long* flop_slots;   // nullable (profiling): executed flops of the panel
 };
 
 constexpr int STAGE_ROWS = 128;   // rows per chunk of the panel's load through LDS
@@ -392,6 +393,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2)))
     rho[d] = rv;
   }
   if (t == 0 && L.status != ST_OK && a.info) atomicCAS(a.info + (a.info_mod > 0 ? p % a.info_mod : p), ST_OK, L.status);
+  // nbw elimination steps over n rows and the panel's nbw columns, one complex multiply-add each
+  if (t == 0 && a.flop_slots) atomicAdd(a.flop_slots + (p & (PROF_SLOTS - 1)), 8ull * n * nbw * nbw);
 }
 
 // out[r][c] = X[r][sigma^{-1}[c]]; one workgroup per (matrix, GATHER_ROWS rows)
@@ -572,13 +575,13 @@ hipError_t launch_inverse(const InvDesc& d, hipStream_t s) {
       for (int j0 = S0; j0 < S0 + ms; j0 += NB) {
         const int nbw = min(NB, S0 + ms - j0);
         PanelArgs pa{n, j0, nbw, S0, S0 + ms, J0, d.M, d.ldm, d.sM, U, sItem, sigma, tau, rho, sI, d.info,
-                     d.info_mod, d.active};
+                     d.info_mod, d.active, prof_flop_slots(KC_INV_PANEL)};
         prof_begin(KC_INV_PANEL, s);
         // two rows per thread: 256 threads up to n = 512, 512 up to n = MAX_ROWS
         if (NB == 32) hipLaunchKernelGGL((gj_panel_kernel<32, 256>), dim3(d.batch), dim3(256), 0, s, pa);
         else if (n <= 512) hipLaunchKernelGGL((gj_panel_kernel<16, 256>), dim3(d.batch), dim3(256), 0, s, pa);
         else hipLaunchKernelGGL((gj_panel_kernel<16, MAX_ROWS / 2>), dim3(d.batch), dim3(MAX_ROWS / 2), 0, s, pa);
-        prof_end(KC_INV_PANEL, s, 8.0 * n * NB * NB * d.batch, 0);
+        prof_end(KC_INV_PANEL, s, 0.0, 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // the other columns of the sub-panel, on both sides of the panel, in one launch:
         // A[:, c] += W U[:, c], W read in place from the panel columns (which are not stored)

@@ -36,10 +36,21 @@ hipEvent_t pool_get() {
   return e;
 }
 
+// Executed flops per kernel class, counted by the kernels themselves while
+// profiling is on (a launch's work depends on device data: the active masks of
+// the decimation and the zero-slab maps), striped over PROF_SLOTS counters per
+// class so that concurrent waves rarely add to the same address.
+__device__ unsigned long long g_prof_flops[KC_COUNT * PROF_SLOTS];
+unsigned long long* g_prof_flops_ptr = nullptr;
+
 }  // namespace
 
 namespace negf {
 
+unsigned long long* prof_flop_slots(int cls) {
+  if (!g_prof_on || g_capturing || !g_prof_flops_ptr || cls < 0 || cls >= KC_COUNT) return nullptr;
+  return g_prof_flops_ptr + (long)cls * PROF_SLOTS;
+}
 
 void prof_begin(int cls, hipStream_t s) {
   (void)cls;
@@ -62,12 +73,6 @@ void prof_end(int cls, hipStream_t s, double flops, double bytes) {
 }  // namespace negf
 
 namespace negf {
-
-hipError_t rt_read_int(int* host_dst, const int* dev_src, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(host_dst, dev_src, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(s);
-}
 
 hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
   return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
@@ -126,6 +131,15 @@ void negf_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on != 0;
   if (on) {
+    // the counters of the current device, cleared (synchronous)
+    void* p = nullptr;
+    g_prof_flops_ptr = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_prof_flops)) == hipSuccess &&
+        hipMemset(p, 0, sizeof(unsigned long long) * KC_COUNT * PROF_SLOTS) == hipSuccess &&
+        hipDeviceSynchronize() == hipSuccess)
+      g_prof_flops_ptr = (unsigned long long*)p;
+  }
+  if (on) {
     for (auto& r : g_prof_pending) {
       g_prof_pool.push_back(r.a);
       g_prof_pool.push_back(r.b);
@@ -153,6 +167,20 @@ negf_status negf_profile_read(negf_kernel_stats* stats) {
     g_prof_pool.push_back(r.b);
   }
   g_prof_pending.clear();
+  if (g_prof_flops_ptr) {
+    std::vector<unsigned long long> c((size_t)KC_COUNT * PROF_SLOTS);
+    if (hipMemcpy(c.data(), g_prof_flops_ptr, c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+      st = NEGF_EHIP;
+    } else {
+      for (int k = 0; k < KC_COUNT; ++k) {
+        double f = 0.0;
+        for (int j = 0; j < PROF_SLOTS; ++j) f += (double)c[(size_t)k * PROF_SLOTS + j];
+        g_prof_acc[k].flops += f;
+      }
+      hipMemset(g_prof_flops_ptr, 0, c.size() * sizeof(unsigned long long));
+    }
+  }
   if (stats)
     for (int i = 0; i < NEGF_KC_COUNT; ++i) stats[i] = i < KC_COUNT ? g_prof_acc[i] : negf_kernel_stats{};
   return st;

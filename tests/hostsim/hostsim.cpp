@@ -351,11 +351,6 @@ hipError_t launch_closure_accept(int np, const double* r2, const double* m2, con
   return hipSuccess;
 }
 
-hipError_t rt_read_int(int* host_dst, const int* dev_src, hipStream_t) {
-  *host_dst = *dev_src;
-  return hipSuccess;
-}
-
 hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t) {
   std::memmove(dst, src, bytes);
   return hipSuccess;

@@ -75,6 +75,27 @@ def test_zgemm_fp64_b1024_largest_block(nb, prec):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-14
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 4, 5])
+@pytest.mark.parametrize("K", [1040, 2048])
+@pytest.mark.parametrize("opa,opb", [("N", "N"), ("C", "N"), ("C", "C")])
+def test_zgemm_long_k_full_tiles(nb, K, tile, prec, opa, opb):
+    """Whole-tile sizes with more than 64 K-steps: every K-step has to be
+    taken (the full-tile path walks the steps in order for dense operands)."""
+    import torch
+    r = np.random.Generator(np.random.PCG64(K + 10 * tile + prec))
+    M, N = 128, 64
+    A = _rand(r, (2, M, K) if opa == "N" else (2, K, M))
+    B = _rand(r, (2, K, N) if opb == "N" else (2, N, K))
+    C0 = _rand(r, (2, M, N))
+    ref = (_op(A, opa) @ _op(B, opb)) + (0.5 - 0.5j) * C0
+    Ct = torch.from_numpy(C0.copy()).cuda()
+    nb.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), Ct, opa, opb, 1.0, 0.5 - 0.5j, prec=prec,
+             tile=tile)
+    err = np.linalg.norm(Ct.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err < (1e-5 if prec == 1 else 1e-13), err
+
+
 @pytest.mark.parametrize("prec", [0, 2])
 def test_zgemm_fp64_b512_batched(nb, prec):
     import torch

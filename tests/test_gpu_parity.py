@@ -2,6 +2,18 @@
 
 Bars: relative Frobenius error per output kind and point <= 1e-10 for the
 double-precision path and <= 1e-6 for the refined single-product form.
+
+The plain tests run at energies where the oracle itself is stable to the bar:
+its outputs move by at most 2.5e-11 when every one of its inversions is
+followed by Newton refinement (helpers.plain_reference asserts this at run
+time), so the fixed 1e-10 measures the GPU path and not the conditioning of
+the point.  At eta = 1e-8 some energies of these random leads are so
+ill-conditioned that the oracle moves by up to 3e-8 under the same
+refinement; no double-precision method can be held to 1e-10 against it there.
+The tests named ``..._conditioned`` cover such energies with the bar
+max(1e-10, 4 x that spread), and print and record each point's bar.  Every
+comparison is recorded (helpers.record) and written to
+gpurun_out/parity/records.jsonl at the end of the session.
 """
 import numpy as np
 import pytest
@@ -9,12 +21,20 @@ import pytest
 import workloads as w
 from oracle import leads as oleads
 from oracle import rgf as orgf
-from helpers import point_tolerance, refined_inversions, well_posed
+from helpers import kappa_proxy, oracle_spread, plain_reference, record, well_posed, SPREAD_FACTOR
 
 pytestmark = pytest.mark.gpu
 
 PLAIN_TOL = 1e-10
 CHOSEN_TOL = 1e-6
+
+# Energies at which the oracle is stable to the plain bar (spread <= 2.5e-11 for
+# every output of the test), from a CPU scan of a 0.05-spaced grid in
+# [-1.45, 1.45] at eta = 1e-8 with the same devices; plain_reference re-checks
+# each one when the test runs.
+STABLE_OBC = {8: [-1.1, -0.4, 0.05, 1.05], 72: [-1.35, 0.1, 0.75, 1.25], 130: [-0.45, 1.25]}
+STABLE_RET = {64: [-0.95, -0.45, 0.95], 100: [-0.85, 0.65, 0.9], 130: [-1.05, 0.5, 1.1]}
+STABLE_LG = {72: [-0.75, 0.3, 0.9, 1.25], 130: [-1.45, -1.1, 0.45, 0.8], 64: [-0.95, -0.15, 0.25, 0.6]}
 
 
 @pytest.fixture(scope="module")
@@ -30,41 +50,79 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _cmp_point(out, k, ref, names, tol, pi=0):
-    """tol: a number or {name: tolerance} (see helpers.point_tolerance)."""
-    worst = {}
+def _cmp_point(out, k, ref, names, tol, test, spread=None, kappa=None, pi=0):
+    """tol: a number or {name: bar}.  Records and prints every comparison."""
+    t = tol if isinstance(tol, dict) else {n: tol for n in names}
+    worst, bad = {}, {}
     for name in names:
         g = out[name][pi][k].cpu().numpy()
         r = getattr(ref, name)
-        worst[name] = rel(g, r)
-    t = tol if isinstance(tol, dict) else {n: tol for n in names}
-    bad = {n: (e, t[n]) for n, e in worst.items() if not e <= t[n]}
-    assert not bad, f"point {k}: (error, tolerance) {bad}"
+        e = rel(g, r)
+        worst[name] = e
+        record(test, ref.E, name, e, t[name], None if spread is None else spread.get(name), kappa)
+        print(f"  {test} E={ref.E:+.4f} {name}: error {e:.3e}, bar {t[name]:.1e}"
+              + ("" if spread is None else f", oracle spread {spread[name]:.1e}"), flush=True)
+        if not e <= t[name]:
+            bad[name] = (e, t[name])
+    assert not bad, f"point {k}: (error, bar) {bad}"
     return worst
 
 
-def _ref(dev, E, names, base=PLAIN_TOL, **kw):
-    return point_tolerance(lambda: orgf.solve_point(dev, E, **kw), names, base)
+def _plain(dev, E, names, **kw):
+    ref, spread = plain_reference(lambda: orgf.solve_point(dev, E, **kw), names, PLAIN_TOL)
+    return ref, spread, kappa_proxy(dev, ref)
+
+
+def _conditioned(dev, E, names, **kw):
+    ref, spread = oracle_spread(lambda: orgf.solve_point(dev, E, **kw), names)
+    bars = {n: max(PLAIN_TOL, SPREAD_FACTOR * spread[n]) for n in names}
+    return ref, bars, spread, kappa_proxy(dev, ref)
 
 
 # ------------------------------------------------------------------ leads
 
-@pytest.mark.parametrize("side", [0, 1])
-@pytest.mark.parametrize("b", [8, 72, 130])
-def test_obc_surface_matches_oracle(nb, side, b):
-    dev = w.slab_device(3, b, 4) if b > 8 else w.random_device(3, b, 4, overlap=0.05)
-    energies = np.array([-1.2, -0.3, 0.45, 1.3])
-    prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8)
+def _obc_device(b):
+    return w.slab_device(3, b, 4) if b > 8 else w.random_device(3, b, 4, overlap=0.05)
+
+
+def _obc_compare(nb, b, side, energies, test, plain):
+    dev = _obc_device(b)
+    prob = nb.Problem(nb.DeviceOnGPU(dev), np.asarray(energies), eta=1e-8)
     out = nb.obc_surface([prob], side)
     iters = out["iters"].cpu().numpy()
     resid = out["resid"].cpu().numpy()
+    names = ["g_surf", "sigma_r"]
     for k, E in enumerate(energies):
-        ref, tol = point_tolerance(lambda: oleads.lead_self_energy(dev, side, E, 1e-8), ["g_surf", "sigma_r"])
-        assert rel(out["g_surf"][0][k, 0].cpu().numpy(), ref.g_surf) <= tol["g_surf"]
-        assert rel(out["sigma_r"][0][k, 0].cpu().numpy(), ref.sigma_r) <= tol["sigma_r"]
+        f = lambda: oleads.lead_self_energy(dev, side, E, 1e-8)
+        if plain:
+            ref, spread = plain_reference(f, names, PLAIN_TOL)
+            bars = {n: PLAIN_TOL for n in names}
+        else:
+            ref, spread = oracle_spread(f, names)
+            bars = {n: max(PLAIN_TOL, SPREAD_FACTOR * spread[n]) for n in names}
+        d = oleads.lead_blocks(dev, side, E, 1e-8)[0]
+        kappa = float(np.linalg.norm(d) * np.linalg.norm(ref.g_surf))
+        for name in names:
+            e = rel(out[name][0][k, 0].cpu().numpy(), getattr(ref, name))
+            record(test, E, name, e, bars[name], spread[name], kappa, side=side, b=b)
+            print(f"  {test} b={b} side={side} E={E:+.3f} {name}: error {e:.3e}, bar {bars[name]:.1e}", flush=True)
+            assert e <= bars[name], (E, name, e, bars[name])
         assert abs(int(iters[k]) - ref.iters) <= 1
         assert resid[k] < 1e-10
     assert np.all(out["info"].cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("b", [8, 72, 130])
+def test_obc_surface_matches_oracle(nb, side, b):
+    _obc_compare(nb, b, side, STABLE_OBC[b], "obc_surface", plain=True)
+
+
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("b", [72, 130])
+def test_obc_surface_conditioned(nb, side, b):
+    """Energies where the oracle's own decimation is not stable to 1e-10."""
+    _obc_compare(nb, b, side, [-1.2, -0.3, 0.45, 1.3], "obc_surface_conditioned", plain=False)
 
 
 def test_obc_chain_closed_form(nb):
@@ -97,25 +155,51 @@ def test_retarded_small_ballistic_workload(nb):
     prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-6)
     out = nb.rgf_retarded([prob])
     assert np.all(out["info"].cpu().numpy() == 0)
-    for k in range(0, 64, 7):
-        names = ["GR_diag", "GR_upper", "GR_lower"]
-        ref, tol = _ref(dev, energies[k], names, eta=1e-6, lesser_greater=False)
-        _cmp_point(out, k, ref, names, tol)
+    names = ["GR_diag", "GR_upper", "GR_lower"]
+    for k in (0, 7, 14, 21, 35, 42, 49, 56, 63):
+        ref, spread, kappa = _plain(dev, energies[k], names, eta=1e-6, lesser_greater=False)
+        _cmp_point(out, k, ref, names, PLAIN_TOL, "retarded_small_ballistic", spread, kappa)
+
+
+def test_retarded_small_ballistic_conditioned(nb):
+    """The sampled point of the same workload where the oracle moves by ~8e-11."""
+    dev = w.random_device(32, 8, 1)
+    energies = w.energy_grid(-3, 3, 64)
+    prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-6)
+    out = nb.rgf_retarded([prob])
+    names = ["GR_diag", "GR_upper", "GR_lower"]
+    ref, bars, spread, kappa = _conditioned(dev, energies[28], names, eta=1e-6, lesser_greater=False)
+    _cmp_point(out, 28, ref, names, bars, "retarded_small_ballistic_conditioned", spread, kappa)
 
 
 @pytest.mark.parametrize("b", [64, 100, 130])
 def test_retarded_slab_ragged(nb, b):
     dev = w.slab_device(4, b, 2)
+    energies = np.array(STABLE_RET[b])
+    prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8)
+    out = nb.rgf_retarded([prob])
+    names = ["GR_diag", "GR_upper", "GR_lower"]
+    for k, E in enumerate(energies):
+        ref, spread, kappa = _plain(dev, E, names, eta=1e-8, lesser_greater=False)
+        _cmp_point(out, k, ref, names, PLAIN_TOL, "retarded_slab", spread, kappa)
+
+
+@pytest.mark.parametrize("b", [64, 100, 130])
+def test_retarded_slab_conditioned(nb, b):
+    dev = w.slab_device(4, b, 2)
     energies = np.array([-0.9, 0.05, 0.6])
     prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8)
     out = nb.rgf_retarded([prob])
+    names = ["GR_diag", "GR_upper", "GR_lower"]
     for k, E in enumerate(energies):
-        names = ["GR_diag", "GR_upper", "GR_lower"]
-        ref, tol = _ref(dev, E, names, eta=1e-8, lesser_greater=False)
-        _cmp_point(out, k, ref, names, tol)
+        ref, bars, spread, kappa = _conditioned(dev, E, names, eta=1e-8, lesser_greater=False)
+        _cmp_point(out, k, ref, names, bars, "retarded_slab_conditioned", spread, kappa)
 
 
 # ------------------------------------------------------------------ lesser / greater
+
+LG_NAMES = ["GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper", "GG_diag", "GG_upper"]
+
 
 @pytest.mark.parametrize("cmul", [4, 3])
 @pytest.mark.parametrize("b,scatter", [(72, True), (130, True), (64, False)])
@@ -124,14 +208,30 @@ def test_lesser_greater_slab(nb, b, scatter, cmul):
     dev = w.slab_device(5, b, 2)
     if scatter:
         w.scattering_self_energies(dev, 3)
+    energies = well_posed(dev, np.array(STABLE_LG[b]))
+    assert energies.size == 4
+    prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
+    out = nb.rgf_lesser_greater([prob], greater=True, opts=nb.make_options(cmul=cmul))
+    assert np.all(out["info"].cpu().numpy() == 0)
+    for k, E in enumerate(energies):
+        ref, spread, kappa = _plain(dev, E, LG_NAMES, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025, greater=True)
+        _cmp_point(out, k, ref, LG_NAMES, PLAIN_TOL, f"lesser_greater_slab_cmul{cmul}", spread, kappa)
+
+
+@pytest.mark.parametrize("cmul", [4, 3])
+@pytest.mark.parametrize("b,scatter", [(72, True), (130, True), (64, False)])
+def test_lesser_greater_slab_conditioned(nb, b, scatter, cmul):
+    dev = w.slab_device(5, b, 2)
+    if scatter:
+        w.scattering_self_energies(dev, 3)
     energies = well_posed(dev, np.array([-0.7, 0.02, 0.33, 1.1, -1.3, 0.6]))[:4]
     prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
     out = nb.rgf_lesser_greater([prob], greater=True, opts=nb.make_options(cmul=cmul))
     assert np.all(out["info"].cpu().numpy() == 0)
     for k, E in enumerate(energies):
-        names = ["GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper", "GG_diag", "GG_upper"]
-        ref, tol = _ref(dev, E, names, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025, greater=True)
-        _cmp_point(out, k, ref, names, tol)
+        ref, bars, spread, kappa = _conditioned(dev, E, LG_NAMES, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025,
+                                                greater=True)
+        _cmp_point(out, k, ref, LG_NAMES, bars, f"lesser_greater_slab_conditioned_cmul{cmul}", spread, kappa)
 
 
 @pytest.mark.parametrize("b,cmul,prec", [(256, 4, 0), (512, 3, 0), (256, 3, 1)])
@@ -206,16 +306,18 @@ def test_lesser_gpu_identities(nb):
 
 def test_multi_problem_mixed_shapes_and_chunking(nb):
     devs = [w.slab_device(4, 40, 11), w.slab_device(3, 56, 12), w.slab_device(4, 40, 13)]
-    ens = [well_posed(d, np.linspace(-1.2, 1.2, 9))[:k] for d, k in zip(devs, (3, 1, 2))]
+    # stable (see STABLE_*) and well-posed energies of each device
+    ens = [np.array(e) for e in ([-0.7, 0.3, 1.0], [0.45], [-0.3, 0.6])]
     probs = [nb.Problem(nb.DeviceOnGPU(d), e, eta=1e-8, mu_l=0.05, mu_r=-0.05) for d, e in zip(devs, ens)]
     full = nb.rgf_lesser_greater(probs)
     chunked = nb.rgf_lesser_greater(probs, opts=nb.make_options(batch=2))
     for q, (d, e) in enumerate(zip(devs, ens)):
+        assert well_posed(d, e).size == e.size
         for k, E in enumerate(e):
             names = ["GR_diag", "GR_upper", "GL_diag", "GL_upper"]
-            ref, tol = _ref(d, E, names, eta=1e-8, mu_l=0.05, mu_r=-0.05, kT=0.025)
-            _cmp_point(full, k, ref, names, tol, pi=q)
-            _cmp_point(chunked, k, ref, names, tol, pi=q)
+            ref, spread, kappa = _plain(d, E, names, eta=1e-8, mu_l=0.05, mu_r=-0.05, kT=0.025)
+            _cmp_point(full, k, ref, names, PLAIN_TOL, "multi_problem", spread, kappa, pi=q)
+            _cmp_point(chunked, k, ref, names, PLAIN_TOL, "multi_problem_chunked", spread, kappa, pi=q)
 
 
 def test_k_points_with_scattering(nb):
@@ -225,15 +327,17 @@ def test_k_points_with_scattering(nb):
     base = w.slab_device(4, 128, 2)
     w.scattering_self_energies(base, 3)
     devs = [w.k_device(base, 7, k) for k in (0.0, 0.9)]
-    ens = [well_posed(d, np.array([-0.55, 0.35, 0.8]))[:2] for d in devs]
+    # stable and well-posed energies of each k copy
+    ens = [np.array([1.0]), np.array([-1.15, 0.2])]
     probs = [nb.Problem(nb.DeviceOnGPU(d), e, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025) for d, e in zip(devs, ens)]
     out = nb.rgf_lesser_greater(probs, greater=True)
     assert np.all(out["info"].cpu().numpy() == 0)
     names = ["GR_diag", "GR_upper", "GL_diag", "GL_upper", "GG_diag"]
     for q, (d, e) in enumerate(zip(devs, ens)):
+        assert well_posed(d, e).size == e.size
         for k, E in enumerate(e):
-            ref, tol = _ref(d, E, names, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025, greater=True)
-            _cmp_point(out, k, ref, names, tol, pi=q)
+            ref, spread, kappa = _plain(d, E, names, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025, greater=True)
+            _cmp_point(out, k, ref, names, PLAIN_TOL, "k_points_scattering", spread, kappa, pi=q)
 
 
 # ------------------------------------------------------------------ transmission
@@ -263,14 +367,16 @@ def test_transmission_periodic_wire_integer(nb):
 
 def test_fp32_refine_meets_bar_and_norefine_does_not(nb):
     dev = w.slab_device(6, 128, 2)
-    energies = well_posed(dev, np.array([-0.6, 0.2, 0.45, -0.9]))[:2]
+    energies = np.array([-0.45, 0.2])   # stable and well-posed
+    assert well_posed(dev, energies).size == 2
     prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
     ref_out = nb.rgf_lesser_greater([prob], nb.PLAIN_FP64)
     refd = nb.rgf_lesser_greater([prob], nb.FP32_REFINE)
     nor = nb.rgf_lesser_greater([prob], nb.FP32_NOREFINE)
+    names = ["GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper"]
     for k, E in enumerate(energies):
-        ref, tol = _ref(dev, E, ["GR_diag", "GL_diag"], eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
-        _cmp_point(ref_out, k, ref, ["GR_diag", "GL_diag"], tol)
-        _cmp_point(refd, k, ref, ["GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper"], CHOSEN_TOL)
+        ref, spread, kappa = _plain(dev, E, names, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
+        _cmp_point(ref_out, k, ref, names, PLAIN_TOL, "plain_next_to_chosen", spread, kappa)
+        _cmp_point(refd, k, ref, names, CHOSEN_TOL, "chosen_fp32_refine", spread, kappa)
         e_nor = rel(nor["GR_diag"][0][k].cpu().numpy(), ref.GR_diag)
         assert 1e-9 < e_nor < 1e-2

@@ -200,3 +200,23 @@ def test_dos_positive():
     dev = w.random_device(6, 4, 3)
     r = rgf.solve_point(dev, 0.1, 1e-6, lesser_greater=False)
     assert np.all(observables.dos(r.GR_diag) > 0)
+
+
+@pytest.mark.parametrize("E", [-1.7, -0.6, 0.3, 1.1, 1.9])
+@pytest.mark.parametrize("t", [1.0, 0.7])
+def test_dos_chain_closed_form(E, t):
+    """Every site of a device cut from an infinite 1D chain (leads repeat it)
+    carries the bulk density of states 1 / (pi sqrt(4 t^2 - (E - eps)^2)) inside
+    the band (one state per site: the scale is fixed), and the folded chain
+    (8 sites per block) carries 8 times it per block."""
+    if abs(E) >= 2 * t:
+        pytest.skip("outside the band")
+    ref = 1.0 / (np.pi * np.sqrt(4 * t * t - E * E))
+    r = rgf.solve_point(w.chain_device(12, t=t), E, 1e-9, lesser_greater=False)
+    d = observables.dos(r.GR_diag)
+    assert np.max(np.abs(d - ref)) < 1e-6 * ref
+    rf = rgf.solve_point(w.folded_chain_device(4, 8, t=t), E, 1e-9, lesser_greater=False)
+    assert np.max(np.abs(observables.dos(rf.GR_diag) - 8 * ref)) < 1e-6 * 8 * ref
+    # outside the band no state is available
+    ro = rgf.solve_point(w.chain_device(6, t=t), 2.5 * t, 1e-9, lesser_greater=False)
+    assert np.max(np.abs(observables.dos(ro.GR_diag))) < 1e-6

@@ -122,6 +122,10 @@ def pins(o):
     g, k, how = o.leads.seeded_sancho_rubio(d_, a_, c_, gs + 1e-6 * noise)
     ok &= how == "closure" and k < steps and rel(g, gs) < 1e-6
     out["seeded_closure"] = bool(ok)
+    # density of states of a chain segment: the bulk closed form at every site
+    r = o.rgf.solve_point(w.chain_device(8), 0.45, 1e-9, lesser_greater=False)
+    ref = 1.0 / (np.pi * np.sqrt(4.0 - 0.45 ** 2))
+    out["chain_dos"] = bool(np.max(np.abs(o.observables.dos(r.GR_diag) - ref)) < 1e-6 * ref)
     return out
 
 
@@ -156,6 +160,8 @@ MUTATIONS = [
     ("dense", "Sg[sl, sl] += dev.sig_g[i]", "Sg[sl, sl] += dev.sig_l[i]"),
     ("observables", "return float(-2.0 * np.real(np.trace(A_upper @ GL_lower)))",
      "return float(-2.0 * np.imag(np.trace(A_upper @ GL_lower)))"),
+    ("observables", "-np.imag(np.trace(g)) / np.pi", "-np.imag(np.trace(g)) / (2 * np.pi)"),
+    ("observables", "-np.imag(np.trace(g)) / np.pi", "np.imag(np.trace(g)) / np.pi"),
 ]
 
 
