@@ -5,6 +5,11 @@ of dispatches, total and average duration.
 
     python -m paper_2602_03438_amd.profsummary gpurun_out/prof/run_results.db [--by-grid] [--top 20]
 
+Matrix-core activity from one counter run (SQ_INSTS_VALU_MFMA_MOPS_F64,
+SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE) of the product kernel:
+
+    python -m paper_2602_03438_amd.profsummary --mfma MFMA_DIR [--kernel REGEX]
+
 HBM traffic from two counter runs (``--pmc FETCH_SIZE`` and ``--pmc
 WRITE_SIZE``, csv output) of a program that also ran one streaming kernel of
 known size (``bench.py --calibrate-copy MIB``): both counters are scaled by
@@ -125,6 +130,52 @@ def traffic(fetch_dir: str, write_dir: str, calib_mib: int, kernel: str, block: 
                             "fetch_scale": f_scale, "write_scale": w_scale}}
 
 
+def _gpu_agent(d: str):
+    """(SIMD count, XCC count, max engine clock in MHz) of the GPU agent of a counter run."""
+    files = glob.glob(os.path.join(d, "**", "*agent_info.csv"), recursive=True)
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Agent_Type") == "GPU":
+                    return int(row["Simd_Count"]), int(row["Num_Xcc"]), float(row["Max_Engine_Clk_Fcompute"])
+    return 1024, 8, 2400.0
+
+
+def mfma(mfma_dir: str, kernel: str):
+    """Matrix-core activity of the product kernel from one counter run with
+    SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE,
+    per launch: the FP64 matrix flops the hardware counted (MOPS x 512, the
+    derived MfmaFlopsF64 of rocprofv3); the fraction of SIMD cycles the matrix
+    cores were busy, busy / (GUI-active cycles of one XCC x SIMDs) (MfmaUtil;
+    the csv holds GRBM_GUI_ACTIVE summed over the XCCs, so it is divided by
+    their number); and the engine clock the GUI-active cycles imply over the
+    launch's duration."""
+    mops = per_dispatch(mfma_dir, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    busy = per_dispatch(mfma_dir, "SQ_VALU_MFMA_BUSY_CYCLES")
+    simd_num, n_xcc, clk = _gpu_agent(mfma_dir)
+    gui, dur = {}, {}
+    files = glob.glob(os.path.join(mfma_dir, "**", "*counter_collection.csv"), recursive=True)
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                did = int(row["Dispatch_Id"])
+                dur[did] = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-9
+                if row["Counter_Name"] == "GRBM_GUI_ACTIVE":
+                    gui[did] = gui.get(did, 0.0) + float(row["Counter_Value"]) / n_xcc
+    pat = re.compile(kernel)
+    rows = [did for did, (n, _, _) in mops.items() if pat.search(n)]
+    if not rows:
+        raise RuntimeError(f"no dispatch matching '{kernel}'")
+    fl = [mops[d][1] * 512.0 for d in rows]
+    util = [busy[d][1] / (gui[d] * simd_num) for d in rows if d in busy and gui.get(d)]
+    mhz = [gui[d] / dur[d] / 1e6 for d in rows if gui.get(d) and dur.get(d)]
+    mean = lambda x: sum(x) / len(x) if x else None
+    return {"kernel_pattern": kernel, "launches": len(rows), "mfma_f64_flops_per_launch": mean(fl),
+            "mfma_busy_frac_mean": mean(util), "mfma_busy_frac_min": min(util) if util else None,
+            "mfma_busy_frac_max": max(util) if util else None, "simd_num": simd_num, "xcc": n_xcc,
+            "engine_clock_mhz_from_gui_active": mean(mhz), "max_engine_clock_mhz": clk}
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("db", nargs="?")
@@ -134,10 +185,18 @@ if __name__ == "__main__":
     ap.add_argument("--calib-mib", type=int, default=1024)
     ap.add_argument("--kernel", default=r"zgemm_kernel<double, [01], [01], [^>]*Cfg<\d+, \d+, \d, \d>, 0(, (true|false))*>")
     ap.add_argument("--block", type=int, default=512, help="block size b of the products")
+    ap.add_argument("--mfma", metavar="MFMA_DIR", help="counter run with SQ_INSTS_VALU_MFMA_MOPS_F64, "
+                    "SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE")
     ap.add_argument("--json")
     ap.add_argument("--note", default="", help="what the counter runs measured (stored in the JSON)")
     a = ap.parse_args()
-    if a.traffic:
+    if a.mfma:
+        rec = mfma(a.mfma, a.kernel)
+        print(json.dumps(rec, indent=1))
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(rec, f, indent=1)
+    elif a.traffic:
         rec = traffic(a.traffic[0], a.traffic[1], a.calib_mib, a.kernel, a.block)
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         rec["kernel_sha"] = gemm_source_hash(root)
