@@ -184,6 +184,30 @@ negf_status negf_rgf_lesser_greater(const negf_problem* problems, int32_t n_prob
                                     void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info,
                                     void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- allocation-free variant, for callers that cannot allocate device
+ * memory or pass a workspace: code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. ----
+ * negf_rgf_lesser_greater without the workspace arguments: the scratch is a
+ * file-scope device array of NEGF_STATIC_SCRATCH_BYTES inside the library, one
+ * copy per GPU, reserved when the library's code is first used on that GPU
+ * and held until the process ends.  The call allocates nothing (no hipMalloc,
+ * no library that allocates).  Points are processed in chunks of opt->batch
+ * points, or, when opt->batch is 0, of the largest number whose workspace
+ * (negf_workspace_bytes with that batch) fits the scratch.  Returns
+ * NEGF_ENOMEM synchronously, enqueueing nothing, when one point (or the
+ * requested batch) does not fit: e.g. Nb = 60 blocks of b = 512 need
+ * ~368 MiB per point and are rejected; Nb = 60 blocks of b = 128 take 10
+ * points per chunk.  Every other argument, output and error as for
+ * negf_rgf_lesser_greater.  All calls on one GPU share the one scratch
+ * array, which keeps whatever the last call left (nothing of it is read
+ * before it is written): calls that may overlap on one GPU (other host
+ * threads, other streams) race and must be serialised by the caller. */
+#define NEGF_STATIC_SCRATCH_BYTES (256u << 20)
+negf_status negf_rgf_lesser_greater_static(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                                           const negf_options* opt, void* GR_diag, void* GR_upper, void* GR_lower,
+                                           void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper,
+                                           int32_t* info, void* stream);
+
 /* Transmission T(E) = Tr[Gamma_R G_{N-1,0} Gamma_L G_{N-1,0}^H] per point
  * (double [points]); G_{N-1,0} from the left-connected recursion of the RGF
  * forward sweep.  This is the observable of the paper's Fig. 7. */

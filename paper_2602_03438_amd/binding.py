@@ -80,6 +80,9 @@ def lib():
     L.negf_rgf_lesser_greater.argtypes = [P(negf_problem), i32, i32, P(negf_options), vp, vp, vp, vp, vp, vp, vp,
                                           vp, vp, sz, vp]
     L.negf_rgf_lesser_greater.restype = C.c_int
+    L.negf_rgf_lesser_greater_static.argtypes = [P(negf_problem), i32, i32, P(negf_options), vp, vp, vp, vp, vp,
+                                                 vp, vp, vp, vp]
+    L.negf_rgf_lesser_greater_static.restype = C.c_int
     L.negf_transmission.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, sz, vp]
     L.negf_transmission.restype = C.c_int
     L.negf_zgemm_batched.argtypes = [C.c_char, C.c_char, i32, i32, i32, P(dbl), vp, i64, i64, vp, i64, i64, P(dbl),
@@ -155,6 +158,10 @@ def negf_rgf_retarded(*args):
 
 def negf_rgf_lesser_greater(*args):
     return lib().negf_rgf_lesser_greater(*args)
+
+
+def negf_rgf_lesser_greater_static(*args):
+    return lib().negf_rgf_lesser_greater_static(*args)
 
 
 def negf_transmission(*args):
@@ -386,6 +393,27 @@ def rgf_lesser_greater(problems, prec=PLAIN_FP64, opts=None, greater=False, lowe
     res = _views(out, problems)
     res["info"] = info
     res["flat"] = out
+    return res
+
+
+def rgf_lesser_greater_static(problems, prec=PLAIN_FP64, opts=None, greater=False, lower=True, outputs=None):
+    """negf_rgf_lesser_greater_static: the library's own static scratch instead of a
+    workspace.  Outputs (and info) are allocated here unless given; the call itself
+    allocates nothing.  Returns the raw status next to the outputs (NEGF_ENOMEM
+    when a point does not fit the scratch) instead of raising."""
+    torch = _torch()
+    arr = _problem_array(problems)
+    o = C.byref(opts) if opts else None
+    out = outputs or _rgf_outputs(problems, True, greater, lower)
+    npts = sum(p.n_e for p in problems)
+    info = torch.zeros(npts, dtype=torch.int32, device="cuda")
+    code = negf_rgf_lesser_greater_static(arr, len(problems), prec, o, _ptr(out["GR_diag"]), _ptr(out["GR_upper"]),
+                                          _ptr(out.get("GR_lower")), _ptr(out["GL_diag"]), _ptr(out["GL_upper"]),
+                                          _ptr(out.get("GG_diag")), _ptr(out.get("GG_upper")), _ptr(info), _stream())
+    res = _views(out, problems)
+    res["info"] = info
+    res["flat"] = out
+    res["status"] = code
     return res
 
 

@@ -1124,6 +1124,91 @@ negf_status negf_rgf_lesser_greater(const negf_problem* problems, int32_t n_prob
   return rgf_common(OPK_RL, problems, n_prob, prec, opt, o, workspace, ws_bytes, stream);
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free variant
+
+// Scratch of negf_rgf_lesser_greater_static: one copy per GPU (allocated when the
+// library's code object is loaded on that device and held until the process ends).
+// Host code never uses the name itself for device memory; it uses the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static __device__ __align__(256) unsigned char scratch[NEGF_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept.
+hipError_t scratch_address(void** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
+// Points in flight per chunk for the static scratch: opt->batch if set, else the
+// largest count whose workspace fits (0 when not even one point fits).
+int static_batch(const negf_problem* pr, int n_prob, negf_precision prec, const Opts& o) {
+  auto fits = [&](int b) {
+    Opts t = o;
+    t.batch = b;
+    return workspace_for(OPK_RL, pr, n_prob, prec, t) <= (size_t)NEGF_STATIC_SCRATCH_BYTES;
+  };
+  if (o.batch > 0) return fits(o.batch) ? o.batch : 0;
+  const long total = count_points(pr, n_prob);
+  if (total <= 0) return 1;
+  if (!fits(1)) return 0;
+  int lo = 1, hi = (int)std::min<long>(total, 1 << 30);
+  while (lo < hi) {   // largest b in [lo, hi] that fits (fits is monotone in b)
+    const int mid = lo + (hi - lo + 1) / 2;
+    if (fits(mid)) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace
+
+extern "C" {
+
+negf_status negf_rgf_lesser_greater_static(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                                           const negf_options* opt, void* GR_diag, void* GR_upper, void* GR_lower,
+                                           void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper,
+                                           int32_t* info, void* stream) {
+  if (!GR_diag || !GR_upper || !GL_diag || !GL_upper || !info) return NEGF_EINVAL;
+  if ((GG_diag == nullptr) != (GG_upper == nullptr)) return NEGF_EINVAL;
+  const void* ps[] = {GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper};
+  for (const void* p : ps)
+    if (p && !aligned16(p)) return NEGF_EINVAL;
+  negf_status st = check_problems(problems, n_prob);
+  if (st != NEGF_OK) return st;
+  if (prec != NEGF_PLAIN_FP64 && prec != NEGF_FP32_REFINE && prec != NEGF_FP32_NOREFINE) return NEGF_EINVAL;
+  const int batch = static_batch(problems, n_prob, prec, get_opts(opt));
+  if (batch <= 0) return NEGF_ENOMEM;   // one point (or the requested batch) exceeds the scratch
+  void* ws = nullptr;
+  if (scratch_address(&ws) != hipSuccess) return NEGF_EHIP;
+  negf_options o{};
+  if (opt) o = *opt;
+  o.batch = batch;
+  Outs outs{(double2*)GR_diag, (double2*)GR_upper, (double2*)GR_lower, (double2*)GL_diag, (double2*)GL_upper,
+            (double2*)GG_diag, (double2*)GG_upper, info, nullptr};
+  return rgf_common(OPK_RL, problems, n_prob, prec, &o, outs, ws, (size_t)NEGF_STATIC_SCRATCH_BYTES, stream);
+}
+
 negf_status negf_transmission(const negf_problem* problems, int32_t n_prob, const negf_options* opt, double* T,
                               int32_t* info, void* workspace, size_t ws_bytes, void* stream) {
   if (!T) return NEGF_EINVAL;

@@ -99,3 +99,24 @@ def test_invalid_arguments_return_einval_synchronously(L):
                                 None) == nb.NEGF_EINVAL
     assert L.negf_zinv_batched(2048, 1, p, p + 16, None, 16, p, 1 << 30, None) == nb.NEGF_EINVAL
     assert L.negf_zinv_batched(4, 1, p, p, None, 16, p, 1 << 30, None) == nb.NEGF_EINVAL
+
+
+def test_static_entry_point_rejects_synchronously(L):
+    """negf_rgf_lesser_greater_static: argument errors and a point that does not
+    fit the static scratch return before anything touches a GPU (the pointers
+    below are never dereferenced)."""
+    from paper_2602_03438_amd import binding as nb
+    fake = C.c_void_p(1 << 20)
+    dev = nb.negf_device(60, 512, fake, fake, None, None, None, None, None)
+    arr = (nb.negf_problem * 1)(nb.negf_problem(dev, 1, fake, 1e-8, 0.0, 0.0, 0.025))
+    outs = [fake] * 7
+    st = L.negf_rgf_lesser_greater_static(arr, 1, nb.PLAIN_FP64, None, *outs, fake, None)
+    assert st == nb.NEGF_ENOMEM          # ~368 MiB of workspace per point > 256 MiB of scratch
+    st = L.negf_rgf_lesser_greater_static(arr, 1, nb.PLAIN_FP64, None, *outs, None, None)
+    assert st == nb.NEGF_EINVAL          # info is required
+    small = nb.negf_device(60, 128, fake, fake, None, None, None, None, None)
+    arr2 = (nb.negf_problem * 1)(nb.negf_problem(small, 12, fake, 1e-8, 0.0, 0.0, 0.025))
+    st = L.negf_rgf_lesser_greater_static(arr2, 1, nb.PLAIN_FP64, C.byref(nb.make_options(batch=12)), *outs, fake,
+                                          None)
+    assert st == nb.NEGF_ENOMEM          # 12 points in flight need ~283 MiB
+    assert L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr2, 1, nb.PLAIN_FP64, None) > (256 << 20)
