@@ -517,7 +517,7 @@ def bench_learned(args):
     T = torch.cat(T_all)
     gen_s = time.perf_counter() - t_start
     # targets span decades near band edges: train on a signed-log compression, invert at inference
-    Tc = torch.sign(T) * torch.log1p(torch.abs(T))
+    Tc = Lm.signed_log(T)
     net = Lm.MLP(seed=0)
     t0 = time.perf_counter()
     losses = net.train(X, Tc, epochs=4, batch=65536, lr=1e-3, log=log)
@@ -539,7 +539,7 @@ def bench_learned(args):
         t1 = time.perf_counter()
         Xh = torch.from_numpy(Lm.features(basis, E)).cuda()
         Yc = net.infer_bf16(Xh)
-        Y = torch.sign(Yc) * torch.expm1(torch.abs(Yc))
+        Y = Lm.signed_log(Yc, inverse=True)
         seeds = gb.seeds(Y)
         seeded = nb.obc_surface([prob], 0, seed=seeds)
         torch.cuda.synchronize()

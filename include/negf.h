@@ -308,6 +308,32 @@ negf_status negf_mlp_infer_bf16(int32_t n, int32_t F, int32_t H, int32_t O, cons
                                 const float* b1, const uint16_t* W2b, const float* b2, const uint16_t* W3b,
                                 const float* b3, uint16_t* scratch, float* Y, void* stream);
 
+/* Data transforms of the learned pipeline (the network's input features are
+ * standardised, its targets compressed; Section IV's learned shortcut, built
+ * here as the seed of the lead decimation).  float32 row-major arrays.
+ *  negf_mlp_moments : mu[c] = mean over the n rows of X[r][c], sd[c] = the
+ *                     sample standard deviation (n - 1), at least 1e-6;
+ *                     accumulated in double; scratch: 65 * F doubles.
+ *  negf_mlp_normalize: Xn[r][c] = (X[r][c] - mu[c]) / sd[c] (Xn may be X).
+ *  negf_mlp_signed_log: y = sign(x) log(1 + |x|), or with inverse = 1 its
+ *                     inverse sign(x) (exp(|x|) - 1) (y may be x).
+ *  negf_mlp_mse     : *out = mean over count entries of (Y - T)^2 (double);
+ *                     scratch: 64 doubles.
+ * Mode transforms of the per-mode seed (complex128 [n][b][b] blocks):
+ *  negf_mode_diag   : out[p * b + j] = (Re, Im) of T_p[j][j] as float pairs.
+ *  negf_mode_scale_columns: out_p = U diag(x_p), x_p[j] = y[p * b + j][0] +
+ *                     i y[p * b + j][1] (U [b][b], y float pairs), i.e. the
+ *                     left factor of the seed U diag(x) U^H.
+ * Errors: EINVAL for bad sizes or null pointers, EHIP for launch failures. */
+negf_status negf_mlp_moments(int64_t n, int32_t F, const float* X, float* mu, float* sd, double* scratch,
+                             void* stream);
+negf_status negf_mlp_normalize(int64_t n, int32_t F, const float* X, const float* mu, const float* sd, float* Xn,
+                               void* stream);
+negf_status negf_mlp_signed_log(int64_t count, const float* x, float* y, int32_t inverse, void* stream);
+negf_status negf_mlp_mse(int64_t count, const float* Y, const float* T, double* out, double* scratch, void* stream);
+negf_status negf_mode_diag(int32_t n, int32_t b, const void* T, float* out, void* stream);
+negf_status negf_mode_scale_columns(int32_t n, int32_t b, const void* U, const float* y, void* out, void* stream);
+
 /* ---- profiling: per kernel class launch counts, executed flops and
  * event-timed durations, recorded on the launching stream.  Flops are those
  * the kernels execute: 6 M N K per complex product in Gauss's three-product

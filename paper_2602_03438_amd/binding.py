@@ -131,6 +131,19 @@ def _bind_mlp(L):
     L.negf_mlp_infer_bf16.restype = C.c_int
     L.negf_mlp_to_bf16.argtypes = [vp, vp, C.c_int64, vp]
     L.negf_mlp_to_bf16.restype = C.c_int
+    i64 = C.c_int64
+    L.negf_mlp_moments.argtypes = [i64, i32, vp, vp, vp, vp, vp]
+    L.negf_mlp_moments.restype = C.c_int
+    L.negf_mlp_normalize.argtypes = [i64, i32, vp, vp, vp, vp, vp]
+    L.negf_mlp_normalize.restype = C.c_int
+    L.negf_mlp_signed_log.argtypes = [i64, vp, vp, i32, vp]
+    L.negf_mlp_signed_log.restype = C.c_int
+    L.negf_mlp_mse.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.negf_mlp_mse.restype = C.c_int
+    L.negf_mode_diag.argtypes = [i32, i32, vp, vp, vp]
+    L.negf_mode_diag.restype = C.c_int
+    L.negf_mode_scale_columns.argtypes = [i32, i32, vp, vp, vp, vp]
+    L.negf_mode_scale_columns.restype = C.c_int
 
 
 def status_string(code: int) -> str:

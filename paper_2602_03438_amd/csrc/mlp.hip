@@ -181,6 +181,107 @@ __global__ void to_bf16_kernel(long n, const float* src, unsigned short* dst) {
     dst[i] = f2bf(src[i]);
 }
 
+// ---- data transforms of the learned pipeline ----
+constexpr int PART = 64;   // partial sums per column (moments) or in total (squared error)
+
+// part[c * PART + blockIdx.x] = sum over this workgroup's rows of (X[r][c] - shift[c])^pw
+// (pw 1 or 2; shift nullable = 0), accumulated in double.  Grid (PART, F).
+__global__ void __launch_bounds__(256) colpart_kernel(long n, int F, const float* X, const double* shift, int pw,
+                                                      double* part) {
+  const int c = blockIdx.y;
+  const double sh = shift ? shift[c] : 0.0;
+  double acc = 0.0;
+  for (long r = (long)blockIdx.x * 256 + threadIdx.x; r < n; r += (long)PART * 256) {
+    const double d = (double)X[r * F + c] - sh;
+    acc += pw == 1 ? d : d * d;
+  }
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long)c * PART + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// mode 0: mean[c] = sum(part) / n;  mode 1: sd[c] = max(sqrt(sum(part) / (n - 1)), floor)
+__global__ void colfinish_kernel(long n, int F, const double* part, int mode, double* mean, float* outf, float floor_) {
+  const int c = threadIdx.x;
+  if (c >= F) return;
+  double s = 0.0;
+  for (int j = 0; j < PART; ++j) s += part[(long)c * PART + j];
+  if (mode == 0) {
+    mean[c] = s / (double)n;
+    outf[c] = (float)(s / (double)n);
+  } else {
+    const double v = n > 1 ? s / (double)(n - 1) : 0.0;
+    outf[c] = fmaxf((float)sqrt(v), floor_);
+  }
+}
+
+__global__ void normalize_kernel(long n, int F, const float* X, const float* mu, const float* sd, float* Xn) {
+  const long tot = n * F;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(i % F);
+    Xn[i] = (X[i] - mu[c]) / sd[c];
+  }
+}
+
+// y = sign(x) log(1 + |x|), or its inverse sign(x) (exp(|x|) - 1)
+__global__ void signed_log_kernel(long n, const float* x, float* y, int inverse) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float v = x[i], a = fabsf(v);
+    const float m = inverse ? expm1f(a) : log1pf(a);
+    y[i] = v < 0.f ? -m : m;
+  }
+}
+
+// part[blockIdx.x] = sum over this workgroup's elements of (Y - T)^2 (double)
+__global__ void __launch_bounds__(256) sqerr_part_kernel(long n, const float* Y, const float* T, double* part) {
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)PART * 256) {
+    const double d = (double)Y[i] - (double)T[i];
+    acc += d * d;
+  }
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void sqerr_finish_kernel(long n, const double* part, double* out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int j = 0; j < PART; ++j) s += part[j];
+  *out = s / (double)n;
+}
+
+// out[p * b + j] = (Re, Im) of T_p[j][j]  (float)
+__global__ void mode_diag_kernel(long n, int b, const double2* T, float* out) {
+  const long tot = n * b;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+    const long p = i / b;
+    const int j = (int)(i - p * b);
+    const double2 v = T[(p * b + j) * b + j];
+    out[2 * i] = (float)v.x;
+    out[2 * i + 1] = (float)v.y;
+  }
+}
+
+// out_p[r][c] = U[r][c] * (y[p * b + c][0] + i y[p * b + c][1])   (U diag(x_p))
+__global__ void mode_scale_kernel(long n, int b, const double2* U, const float* y, double2* out) {
+  const long bb = (long)b * b, tot = n * bb;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) {
+    const long p = i / bb;
+    const long e = i - p * bb;
+    const int c = (int)(e % b);
+    const double2 u = U[e];
+    const double xr = y[2 * (p * b + c)], xi = y[2 * (p * b + c) + 1];
+    out[i] = make_double2(u.x * xr - u.y * xi, u.x * xi + u.y * xr);
+  }
+}
+
 inline unsigned grid_1d(long n) {
   long g = (n + 255) / 256;
   return (unsigned)(g < 2048 ? (g > 0 ? g : 1) : 2048);
@@ -289,6 +390,61 @@ negf_status negf_mlp_infer_bf16(int32_t n, int32_t F, int32_t H, int32_t O, cons
   a = sa(n, O, H, A2b, H, 0, W3b, O, 0, Y, O, EPI_BIAS);
   a.bias = b3;
   return sgemm(a, true, s) == hipSuccess ? NEGF_OK : NEGF_EHIP;
+}
+
+negf_status negf_mlp_moments(int64_t n, int32_t F, const float* X, float* mu, float* sd, double* scratch,
+                             void* stream) {
+  if (n < 1 || F < 1 || F > 1024 || !X || !mu || !sd || !scratch) return NEGF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  double* part = scratch;
+  double* mean = scratch + (size_t)F * PART;
+  hipLaunchKernelGGL(colpart_kernel, dim3(PART, F), dim3(256), 0, s, (long)n, F, X, (const double*)nullptr, 1, part);
+  hipLaunchKernelGGL(colfinish_kernel, dim3(1), dim3(1024), 0, s, (long)n, F, (const double*)part, 0, mean, mu, 0.f);
+  hipLaunchKernelGGL(colpart_kernel, dim3(PART, F), dim3(256), 0, s, (long)n, F, X, (const double*)mean, 2, part);
+  hipLaunchKernelGGL(colfinish_kernel, dim3(1), dim3(1024), 0, s, (long)n, F, (const double*)part, 1, mean, sd,
+                     1e-6f);
+  return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
+}
+
+negf_status negf_mlp_normalize(int64_t n, int32_t F, const float* X, const float* mu, const float* sd, float* Xn,
+                               void* stream) {
+  if (n < 0 || F < 1 || (n > 0 && (!X || !mu || !sd || !Xn))) return NEGF_EINVAL;
+  if (n == 0) return NEGF_OK;
+  hipLaunchKernelGGL(normalize_kernel, dim3(grid_1d(n * F)), dim3(256), 0, (hipStream_t)stream, (long)n, F, X, mu,
+                     sd, Xn);
+  return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
+}
+
+negf_status negf_mlp_signed_log(int64_t count, const float* x, float* y, int32_t inverse, void* stream) {
+  if (count < 0 || (count > 0 && (!x || !y))) return NEGF_EINVAL;
+  if (count == 0) return NEGF_OK;
+  hipLaunchKernelGGL(signed_log_kernel, dim3(grid_1d(count)), dim3(256), 0, (hipStream_t)stream, (long)count, x, y,
+                     inverse ? 1 : 0);
+  return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
+}
+
+negf_status negf_mlp_mse(int64_t count, const float* Y, const float* T, double* out, double* scratch, void* stream) {
+  if (count < 1 || !Y || !T || !out || !scratch) return NEGF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(sqerr_part_kernel, dim3(PART), dim3(256), 0, s, (long)count, Y, T, scratch);
+  hipLaunchKernelGGL(sqerr_finish_kernel, dim3(1), dim3(64), 0, s, (long)count, (const double*)scratch, out);
+  return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
+}
+
+negf_status negf_mode_diag(int32_t n, int32_t b, const void* T, float* out, void* stream) {
+  if (n < 0 || b < 1 || (n > 0 && (!T || !out))) return NEGF_EINVAL;
+  if (n == 0) return NEGF_OK;
+  hipLaunchKernelGGL(mode_diag_kernel, dim3(grid_1d((long)n * b)), dim3(256), 0, (hipStream_t)stream, (long)n, b,
+                     (const double2*)T, out);
+  return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
+}
+
+negf_status negf_mode_scale_columns(int32_t n, int32_t b, const void* U, const float* y, void* out, void* stream) {
+  if (n < 0 || b < 1 || (n > 0 && (!U || !y || !out))) return NEGF_EINVAL;
+  if (n == 0) return NEGF_OK;
+  hipLaunchKernelGGL(mode_scale_kernel, dim3(grid_1d((long)n * b * b)), dim3(256), 0, (hipStream_t)stream, (long)n,
+                     b, (const double2*)U, y, (double2*)out);
+  return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
 }
 
 }  // extern "C"

@@ -16,8 +16,10 @@ H0 u_j = lambda_j S0 u_j with U^H S0 U = I (host preprocessing, once per lead):
   seed     g~    = U diag(x) U^H
 
 Training (single precision, Adam, mean squared error) and inference (bf16)
-run in the library's MLP kernels; the target and seed transforms use the
-library's complex product kernel.
+run in the library's MLP kernels; the input standardisation, the signed-log
+compression of the targets, the training loss and the mode transforms (the
+diagonal of U^H S0 g S0 U, the column scaling U diag(x)) run in the library's
+transform kernels and complex product kernel.  torch only holds the memory.
 """
 from __future__ import annotations
 
@@ -91,18 +93,30 @@ class GPUBasis:
         R = self.SU.unsqueeze(0).expand(n, -1, -1).contiguous()
         t = nb.zgemm(L, g_surf.contiguous())
         t = nb.zgemm(t, R)
-        x = torch.diagonal(t, dim1=1, dim2=2)
-        return torch.stack([x.real, x.imag], dim=-1).reshape(-1, 2).float()
+        out = torch.empty(n * self.b, 2, dtype=torch.float32, device="cuda")
+        nb.check(nb.lib().negf_mode_diag(n, self.b, nb._ptr(t), nb._ptr(out), nb._stream()), "negf_mode_diag")
+        return out
 
     def seeds(self, y):
         """g~ = U diag(x) U^H from network outputs y [n*b, 2] -> complex128 [n, b, b]."""
         import torch
         n = y.shape[0] // self.b
-        x = torch.complex(y[:, 0].double(), y[:, 1].double()).reshape(n, self.b)
-        D = torch.diag_embed(x)
+        y = y.contiguous()
+        t = torch.empty(n, self.b, self.b, dtype=torch.complex128, device="cuda")
+        nb.check(nb.lib().negf_mode_scale_columns(n, self.b, nb._ptr(self.U), nb._ptr(y), nb._ptr(t), nb._stream()),
+                 "negf_mode_scale_columns")
         Ub = self.U.unsqueeze(0).expand(n, -1, -1).contiguous()
-        t = nb.zgemm(Ub, D)
         return nb.zgemm(t, Ub, opb="C")
+
+
+def signed_log(x, inverse=False):
+    """sign(x) log(1 + |x|) (or its inverse) of a float32 tensor, in the library's kernel."""
+    import torch
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    nb.check(nb.lib().negf_mlp_signed_log(x.numel(), nb._ptr(x), nb._ptr(y), int(inverse), nb._stream()),
+             "negf_mlp_signed_log")
+    return y
 
 
 class MLP:
@@ -127,7 +141,59 @@ class MLP:
         self.sd = torch.ones(n_in, dtype=torch.float32, device="cuda")
 
     def _norm(self, X):
-        return ((X - self.mu) / self.sd).contiguous()
+        import torch
+        X = X.contiguous()
+        Xn = torch.empty_like(X)
+        nb.check(nb.lib().negf_mlp_normalize(X.shape[0], self.F, nb._ptr(X), nb._ptr(self.mu), nb._ptr(self.sd),
+                                             nb._ptr(Xn), nb._stream()), "negf_mlp_normalize")
+        return Xn
+
+    def set_normalisation(self, X):
+        """Input standardisation from the training set (column means and standard deviations)."""
+        import torch
+        X = X.contiguous()
+        scratch = torch.empty(65 * self.F, dtype=torch.float64, device="cuda")
+        nb.check(nb.lib().negf_mlp_moments(X.shape[0], self.F, nb._ptr(X), nb._ptr(self.mu), nb._ptr(self.sd),
+                                           nb._ptr(scratch), nb._stream()), "negf_mlp_moments")
+
+    def loss(self, Y, T):
+        """Mean squared error of a batch (the training objective), in the library's kernel."""
+        import torch
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        scratch = torch.empty(64, dtype=torch.float64, device="cuda")
+        nb.check(nb.lib().negf_mlp_mse(Y.numel(), nb._ptr(Y.contiguous()), nb._ptr(T.contiguous()), nb._ptr(out),
+                                       nb._ptr(scratch), nb._stream()), "negf_mlp_mse")
+        return out
+
+    def state(self):
+        """Checkpoint of the training state: parameters, Adam moments, step count and
+        input standardisation, as host float32 arrays."""
+        d = {"t": np.array([self.t], dtype=np.int64), "mu": self.mu.cpu().numpy(), "sd": self.sd.cpu().numpy()}
+        for k in self.p:
+            d[f"p_{k}"] = self.p[k].cpu().numpy()
+            d[f"m_{k}"] = self.m[k].cpu().numpy()
+            d[f"v_{k}"] = self.v[k].cpu().numpy()
+        return d
+
+    def save(self, path):
+        """Write the checkpoint (safetensors: plain arrays, nothing executable)."""
+        from safetensors.numpy import save_file
+        save_file({k: np.ascontiguousarray(v) for k, v in self.state().items()}, path)
+
+    def load(self, path):
+        """Restore a checkpoint written by save() (shapes must match this network)."""
+        import torch
+        from safetensors.numpy import load_file
+        d = load_file(path)
+        for k in self.p:
+            for pre, tgt in (("p", self.p), ("m", self.m), ("v", self.v)):
+                a = d[f"{pre}_{k}"]
+                if tuple(a.shape) != tuple(tgt[k].shape):
+                    raise ValueError(f"checkpoint {pre}_{k} has shape {a.shape}, the network {tuple(tgt[k].shape)}")
+                tgt[k].copy_(torch.from_numpy(a))
+        self.mu.copy_(torch.from_numpy(d["mu"]))
+        self.sd.copy_(torch.from_numpy(d["sd"]))
+        self.t = int(d["t"][0])
 
     def forward(self, X):
         import torch
@@ -187,10 +253,10 @@ class MLP:
                                        nb._ptr(scratch), nb._ptr(Y), nb._stream()), "negf_mlp_infer_bf16")
         return Y
 
-    def train(self, X, T, epochs=5, batch=65536, lr=1e-3, seed=0, log=None):
+    def train(self, X, T, epochs=5, batch=65536, lr=1e-3, seed=0, log=None, normalise=True):
         import torch
-        self.mu = X.mean(dim=0)
-        self.sd = X.std(dim=0).clamp_min(1e-6)
+        if normalise:
+            self.set_normalisation(X)
         n = X.shape[0]
         g = torch.Generator(device="cuda")
         g.manual_seed(seed)
@@ -204,7 +270,7 @@ class MLP:
                 Y, cache = self.forward(Xb)
                 self.backward(cache, Y, Tb)
                 self.adam(lr)
-                tot += float(((Y - Tb) ** 2).mean()) * idx.numel()
+                tot += float(self.loss(Y, Tb).item()) * idx.numel()
             losses.append(tot / n)
             if log:
                 log(f"epoch {ep + 1}/{epochs} mse {losses[-1]:.4e}")

@@ -30,9 +30,10 @@ CHOSEN_TOL = 1e-6
 
 # Energies at which the oracle is stable to the plain bar (spread <= 2.5e-11 for
 # every output of the test), from a CPU scan of a 0.05-spaced grid in
-# [-1.45, 1.45] at eta = 1e-8 with the same devices; plain_reference re-checks
-# each one when the test runs.
-STABLE_OBC = {8: [-1.1, -0.4, 0.05, 1.05], 72: [-1.35, 0.1, 0.75, 1.25], 130: [-0.45, 1.25]}
+# [-1.45, 1.45] (0.025 for the b = 130 lead) at eta = 1e-8 with the same
+# devices, keeping the most stable ones (the spread itself varies by ~1.5x with
+# the host's BLAS); plain_reference re-checks each one when the test runs.
+STABLE_OBC = {8: [-1.1, -0.4, 0.05, 1.05], 72: [-1.35, 0.1, 0.75, 1.25], 130: [-1.475, -0.45]}
 STABLE_RET = {64: [-0.95, -0.45, 0.95], 100: [-0.85, 0.65, 0.9], 130: [-1.05, 0.5, 1.1]}
 STABLE_LG = {72: [-0.75, 0.3, 0.9, 1.25], 130: [-1.45, -1.1, 0.45, 0.8], 64: [-0.95, -0.15, 0.25, 0.6]}
 

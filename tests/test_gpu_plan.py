@@ -153,7 +153,7 @@ def test_learned_initialiser_end_to_end(nb):
         X.append(torch.from_numpy(Lm.features(basis, E)).cuda())
         T.append(Lm.GPUBasis(basis).targets(out["g_surf"][0][:, 0].contiguous()))
     X, T = torch.cat(X), torch.cat(T)
-    Tc = torch.sign(T) * torch.log1p(torch.abs(T))
+    Tc = Lm.signed_log(T)
     net = Lm.MLP(seed=0, width=64)
     losses = net.train(X, Tc, epochs=40, batch=1024, lr=2e-3)
     assert losses[-1] < losses[0]
@@ -162,7 +162,7 @@ def test_learned_initialiser_end_to_end(nb):
     E = np.linspace(-1.3, 1.3, 16)
     prob = nb.Problem(nb.DeviceOnGPU(lead), E, eta=1e-8)
     Yc = net.infer_bf16(torch.from_numpy(Lm.features(basis, E)).cuda())
-    seeds = Lm.GPUBasis(basis).seeds(torch.sign(Yc) * torch.expm1(torch.abs(Yc)))
+    seeds = Lm.GPUBasis(basis).seeds(Lm.signed_log(Yc, inverse=True))
     plain = nb.obc_surface([prob], 0)
     seeded = nb.obc_surface([prob], 0, seed=seeds)
     assert torch.equal(plain["info"], seeded["info"])
