@@ -168,12 +168,15 @@ def main():
     ap.add_argument("--inv-nb", type=int, default=0, help="inversion panel width (0: tuned)")
     ap.add_argument("--cmul", type=int, choices=[3, 4], default=3,
                     help="real products per complex double product (3: Gauss's method)")
-    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm"], default="ribbon",
+    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm", "serinv"], default="ribbon",
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation; gemm: the "
                          "dominant product kernel alone through negf_zgemm_batched at the headline's block size "
-                         "and batch (for hardware counters)")
+                         "and batch (for hardware counters); serinv: few energies per call, plain RGF against the "
+                         "partitioned inversion")
     ap.add_argument("--gemm-batch", type=int, default=256, help="products per launch in the gemm workload")
+    ap.add_argument("--serinv-points", default="1,2,4,8", help="energy points per call in the serinv workload")
+    ap.add_argument("--serinv-parts", default="4,8", help="partition counts in the serinv workload")
     ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload")
     ap.add_argument("--uneven-batch", type=int, default=0,
                     help="points per chunk in the uneven workload (0: all points of a block shape in one chunk)")
@@ -211,6 +214,8 @@ def main():
         del src, dst
     if args.workload == "gemm":
         return bench_gemm(args)
+    if args.workload == "serinv":
+        return bench_serinv(args)
     if args.workload == "uneven":
         # four worker streams (the hardware queues HIP gives a process by default); each device
         # shape's points form one chunk (see --uneven-batch)
@@ -394,6 +399,71 @@ def bench_gemm(args):
                                    f"{real_products} real products per complex product"},
             "avg_launch_ms": avg, "min_launch_ms": float(np.min(ms)), "frac_of_fp64_peak": flops / (avg * 1e-3) / PEAK["f64"],
             "algorithmic_bytes_per_launch": 3 * 16 * B * B * batch, "rel_err_vs_torch_item0": err}
+    print(json.dumps(line), flush=True)
+
+
+def bench_serinv(args):
+    """Few energy points per call at the headline shape (Nb = 60, b = 512): the plain
+    RGF call (batch = the points) against the partitioned inversion with P partitions
+    (batch = P x the points), G^R + G^<, both leads included; points/s per case."""
+    import torch
+    import workloads as w
+    from paper_2602_03438_amd import autotune
+    from paper_2602_03438_amd import binding as nb
+    # the interacting device (scattering self-energies of norm 0.01 on every block): the partitioned
+    # elimination needs the broadening inside the device that such self-energies give
+    dev = w.scattering_self_energies(w.slab_device(NB, B, SEED), 3)
+    gdev = nb.DeviceOnGPU(dev)
+    t = autotune.lookup(B, args.cmul)
+    opts = nb.make_options(inv_nb=t["inv_nb"], cmul=args.cmul, gemm_tile=t["gemm_tile"],
+                           gemm_tile_f32=t["gemm_tile_f32"], sr_max_iter=args.sr_max_iter)
+    grid = np.linspace(-1.5, 1.5, N_GRID)
+    res = []
+    for npts in [int(x) for x in args.serinv_points.split(",")]:
+        E = grid[np.linspace(0, N_GRID - 1, npts + 2).astype(int)[1:-1]]
+        prob = nb.Problem(gdev, E, eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT)
+        ws = nb.Workspace()
+        outs = nb._rgf_outputs([prob], True, False, True)
+        cases = [("rgf", None)] + [("serinv", int(p)) for p in args.serinv_parts.split(",")]
+        first = None
+        for name, parts in cases:
+            def run():
+                if parts is None:
+                    return nb.rgf_lesser_greater([prob], opts=opts, ws=ws, outputs=outs)["info"]
+                return nb.serinv_lesser_greater(prob, parts, opts=opts, ws=ws, outputs=outs)["info"]
+            for _ in range(args.warmup):
+                run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                info = run()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            # every output of the first point next to the plain RGF call's
+            pt = {k: outs[k][:(NB if k.endswith("diag") else NB - 1) * B * B].clone()
+                  for k in ("GR_diag", "GR_upper", "GL_diag", "GL_upper")}
+            if first is None:
+                first = pt
+            diff = max((torch.linalg.vector_norm(pt[k] - first[k]) / torch.linalg.vector_norm(first[k])).item()
+                       for k in pt)
+            res.append({"points": npts, "solver": name, "partitions": parts, "ms_per_call": dt * 1e3,
+                        "points_per_s": npts / dt, "info_nonzero": int(torch.count_nonzero(info).item()),
+                        "rel_diff_vs_rgf_first_point": diff})
+            log(f"  {npts} point(s), {name}{'' if parts is None else f' P={parts}'}: {dt * 1e3:.1f} ms "
+                f"({npts / dt:.2f} points/s)")
+        del outs, ws
+        torch.cuda.empty_cache()
+    best = {}
+    for r in res:
+        if r["solver"] == "serinv":
+            best[r["points"]] = max(best.get(r["points"], 0.0), r["points_per_s"])
+    line = {"metric": "energy points/s at few points per call, RGF G^R+G^< (Nb=60, b=512): partitioned vs plain",
+            "value": best.get(1), "unit": "energy points/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "nano-ribbon-like slab device Nb=60 b=512 with scattering self-energies (norm 0.01), "
+                                   "eta=1e-8, 1..8 energies per call",
+                       "real_products_per_complex_product": args.cmul, "sr_max_iter": args.sr_max_iter},
+            "cases": res}
     print(json.dumps(line), flush=True)
 
 

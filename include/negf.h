@@ -214,6 +214,29 @@ negf_status negf_rgf_lesser_greater_static(const negf_problem* problems, int32_t
 negf_status negf_transmission(const negf_problem* problems, int32_t n_prob, const negf_options* opt, double* T,
                               int32_t* info, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- partitioned selected inversion (Serinv): one device split into
+ * partitions that are eliminated in parallel (Fig. 3 and the paragraph after
+ * it in Section II) ----
+ * The same outputs as negf_rgf_lesser_greater for ONE problem (a device and
+ * its energies), computed by splitting the nb blocks into `partitions`
+ * partitions of period T = ceil((nb + 1) / partitions): each partition
+ * eliminates its interior blocks independently (partitions and energies are
+ * one batch axis), the 2 (partitions - 1) boundary blocks form a reduced
+ * block-tridiagonal system (retarded and lesser/greater Schur complements)
+ * solved sequentially, and each partition then recovers its selected blocks
+ * with the boundary self-energies the reduced system gives.  This fills the
+ * GPU with `partitions` times more work per launch when few energies are
+ * solved at once.  Plain double precision (opt->cmul and tile/panel knobs
+ * apply; the decimation as in negf_rgf_lesser_greater).
+ * Requirements: partitions >= 2, T >= 3 and nb - (partitions - 1) T >= 1,
+ * else NEGF_EINVAL.  GR_lower may be NULL; GG_diag / GG_upper both NULL skip
+ * G^>.  Workspace: negf_serinv_workspace_bytes(problem, partitions, greater). */
+size_t negf_serinv_workspace_bytes(const negf_problem* problem, int32_t partitions, int32_t greater);
+negf_status negf_serinv_lesser_greater(const negf_problem* problem, int32_t partitions, const negf_options* opt,
+                                       void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper,
+                                       void* GG_diag, void* GG_upper, int32_t* info, void* workspace, size_t ws_bytes,
+                                       void* stream);
+
 /* ---- plans: many problems of uneven block shapes in one launch ----
  * A plan groups the points of all problems into chunks of one block shape
  * (at most `batch` points each, per shape from `tunings`), assigns chunks to

@@ -83,6 +83,11 @@ def lib():
     L.negf_rgf_lesser_greater_static.argtypes = [P(negf_problem), i32, i32, P(negf_options), vp, vp, vp, vp, vp,
                                                  vp, vp, vp, vp]
     L.negf_rgf_lesser_greater_static.restype = C.c_int
+    L.negf_serinv_workspace_bytes.argtypes = [P(negf_problem), i32, i32]
+    L.negf_serinv_workspace_bytes.restype = sz
+    L.negf_serinv_lesser_greater.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, vp, vp, vp, vp, vp,
+                                             vp, sz, vp]
+    L.negf_serinv_lesser_greater.restype = C.c_int
     L.negf_transmission.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, sz, vp]
     L.negf_transmission.restype = C.c_int
     L.negf_zgemm_batched.argtypes = [C.c_char, C.c_char, i32, i32, i32, P(dbl), vp, i64, i64, vp, i64, i64, P(dbl),
@@ -175,6 +180,14 @@ def negf_rgf_lesser_greater(*args):
 
 def negf_rgf_lesser_greater_static(*args):
     return lib().negf_rgf_lesser_greater_static(*args)
+
+
+def negf_serinv_workspace_bytes(*args):
+    return lib().negf_serinv_workspace_bytes(*args)
+
+
+def negf_serinv_lesser_greater(*args):
+    return lib().negf_serinv_lesser_greater(*args)
 
 
 def negf_transmission(*args):
@@ -427,6 +440,28 @@ def rgf_lesser_greater_static(problems, prec=PLAIN_FP64, opts=None, greater=Fals
     res["info"] = info
     res["flat"] = out
     res["status"] = code
+    return res
+
+
+def serinv_lesser_greater(problem, partitions, opts=None, greater=False, lower=True, ws=None, outputs=None):
+    """negf_serinv_lesser_greater for one problem: the partitioned selected inversion
+    (same outputs as rgf_lesser_greater)."""
+    torch = _torch()
+    arr = _problem_array([problem])
+    nbytes = negf_serinv_workspace_bytes(arr, partitions, int(greater))
+    if nbytes == 0:
+        raise NegfError("invalid problem or partition count for the partitioned inversion")
+    buf = (ws or Workspace()).get(nbytes)
+    out = outputs or _rgf_outputs([problem], True, greater, lower)
+    info = torch.zeros(problem.n_e, dtype=torch.int32, device="cuda")
+    code = negf_serinv_lesser_greater(arr, partitions, C.byref(opts) if opts else None, _ptr(out["GR_diag"]),
+                                      _ptr(out["GR_upper"]), _ptr(out.get("GR_lower")), _ptr(out["GL_diag"]),
+                                      _ptr(out["GL_upper"]), _ptr(out.get("GG_diag")), _ptr(out.get("GG_upper")),
+                                      _ptr(info), _ptr(buf), buf.numel(), _stream())
+    check(code, "negf_serinv_lesser_greater")
+    res = _views(out, [problem])
+    res["info"] = info
+    res["flat"] = out
     return res
 
 

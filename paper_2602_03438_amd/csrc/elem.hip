@@ -18,7 +18,11 @@ __global__ void __launch_bounds__(TD * TR) assemble_kernel(AssembleDesc d) {
   const int p = blockIdx.z;
   if (d.active && d.active[p] == 0) return;
   const int b = d.b;
-  const double e = d.energies ? d.energies[p] : 0.0;
+  const long go = d.inner > 0 ? (long)(p / d.inner) * d.sHo : 0;   // block offset of the item's group
+  const double e = d.energies ? d.energies[d.inner > 0 ? p % d.inner : p] : 0.0;
+  const double2* S = d.S ? d.S + go : nullptr;
+  const double2* Hm = d.H ? d.H + go : nullptr;
+  const double2* Y = d.Y ? d.Y + go : nullptr;
   const double2 zc = make_double2(d.s_coef * e, d.s_coef * d.eta);
   const int i0 = blockIdx.y * TD, j0 = blockIdx.x * TD;
   __shared__ double2 tS[TD][TD + 1];
@@ -29,9 +33,9 @@ __global__ void __launch_bounds__(TD * TR) assemble_kernel(AssembleDesc d) {
       const int sr = j0 + rr, sc = i0 + threadIdx.x;
       double2 sv = make_double2(0.0, 0.0), hv = make_double2(0.0, 0.0);
       if (sr < b && sc < b) {
-        if (d.S) sv = d.S[(long)sr * b + sc];
+        if (S) sv = S[(long)sr * b + sc];
         else if (d.s_identity && sr == sc) sv = make_double2(1.0, 0.0);
-        if (d.H) hv = d.H[(long)sr * b + sc];
+        if (Hm) hv = Hm[(long)sr * b + sc];
       }
       tS[rr][threadIdx.x] = sv;
       tH[rr][threadIdx.x] = hv;
@@ -47,14 +51,14 @@ __global__ void __launch_bounds__(TD * TR) assemble_kernel(AssembleDesc d) {
       sv = cconj(tS[threadIdx.x][rr]);
       hv = cconj(tH[threadIdx.x][rr]);
     } else {
-      sv = d.S ? d.S[o] : make_double2((d.s_identity && i == j) ? 1.0 : 0.0, 0.0);
-      hv = ld_or0(d.H, o);
+      sv = S ? S[o] : make_double2((d.s_identity && i == j) ? 1.0 : 0.0, 0.0);
+      hv = ld_or0(Hm, o);
     }
     double2 r = cmul(zc, sv);
     r.x += d.h_coef * hv.x;
     r.y += d.h_coef * hv.y;
-    if (d.Y) {
-      const double2 y = d.Y[o];
+    if (Y) {
+      const double2 y = Y[o];
       r.x += d.y_coef * y.x;
       r.y += d.y_coef * y.y;
     }
@@ -65,6 +69,36 @@ __global__ void __launch_bounds__(TD * TR) assemble_kernel(AssembleDesc d) {
     }
     d.out[(long)p * d.sOut + o] = r;
   }
+}
+
+// out_p += c * W_p^H through 32 x 32 LDS tiles (reads and writes coalesced)
+__global__ void __launch_bounds__(TD * TR) add_adjoint_kernel(int b, double2 c, const double2* W, long sW,
+                                                              double2* out, long sOut) {
+  const int p = blockIdx.z;
+  const int i0 = blockIdx.y * TD, j0 = blockIdx.x * TD;   // output tile rows i0.., cols j0..
+  __shared__ double2 t[TD][TD + 1];
+  const double2* w = W + (long)p * sW;
+  double2* o = out + (long)p * sOut;
+  for (int rr = threadIdx.y; rr < TD; rr += TR) {          // W rows j0.., cols i0..
+    const int r = j0 + rr, cidx = i0 + threadIdx.x;
+    t[rr][threadIdx.x] = (r < b && cidx < b) ? w[(long)r * b + cidx] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int rr = threadIdx.y; rr < TD; rr += TR) {
+    const int i = i0 + rr, j = j0 + threadIdx.x;
+    if (i >= b || j >= b) continue;
+    const double2 v = cconj(t[threadIdx.x][rr]);           // (W^H)[i][j] = conj(W[j][i])
+    o[(long)i * b + j] = cadd(o[(long)i * b + j], cmul(c, v));
+  }
+}
+
+__global__ void scatter_blocks_kernel(long n, int nblk, const double2* src, long sS, double2* dst, int inner,
+                                      long sDo, long sDi) {
+  const int z = blockIdx.y;
+  const double2* s = src + (long)z * sS;
+  double2* d = dst + (long)(z / inner) * sDo + (long)(z % inner) * sDi;
+  const long tot = n * nblk;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
 }
 
 __global__ void copy_kernel(long n, int batch, const double2* src, long sS, double2* dst, long sD) {
@@ -300,6 +334,28 @@ hipError_t launch_copy_blocks(int b, int batch, const double2* src, long sS, dou
   if (batch <= 0) return hipSuccess;
   const long n = (long)b * b;
   hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n), batch), dim3(256), 0, s, n, batch, src, sS, dst, sD);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_adjoint(int b, int batch, double2 c, const double2* W, long sW, double2* out, long sOut,
+                              hipStream_t s) {
+  if (batch <= 0 || b <= 0) return hipSuccess;
+  const int nt = (b + TD - 1) / TD;
+  prof_begin(KC_ELEM, s);
+  hipLaunchKernelGGL(add_adjoint_kernel, dim3(nt, nt, batch), dim3(TD, TR), 0, s, b, c, W, sW, out, sOut);
+  prof_end(KC_ELEM, s, 0, 48.0 * b * b * batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_blocks(int b, int nitems, int nblk, const double2* src, long sS, double2* dst, int inner,
+                                 long sDo, long sDi, hipStream_t s) {
+  if (nitems <= 0 || nblk <= 0 || b <= 0) return hipSuccess;
+  if (inner <= 0) return hipErrorInvalidValue;
+  const long n = (long)b * b;
+  prof_begin(KC_ELEM, s);
+  hipLaunchKernelGGL(scatter_blocks_kernel, dim3(grid_for(n * nblk), nitems), dim3(256), 0, s, n, nblk, src, sS, dst,
+                     inner, sDo, sDi);
+  prof_end(KC_ELEM, s, 0, 32.0 * n * nblk * nitems);
   return hipGetLastError();
 }
 

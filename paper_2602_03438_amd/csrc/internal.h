@@ -104,8 +104,20 @@ struct AssembleDesc {
   double2* out;
   long sOut;
   const int* active;
+  // Items in groups of `inner` (0: no grouping): item p reads energies[p % inner] and the
+  // blocks S, H, Y at offset (p / inner) * sHo elements (the same block index in different
+  // parts of a device, e.g. one per partition).
+  int inner;
+  long sHo;
 };
 hipError_t launch_assemble(const AssembleDesc& d, hipStream_t s);
+// out_p += c * W_p^H for b x b blocks (out must not alias W)
+hipError_t launch_add_adjoint(int b, int batch, double2 c, const double2* W, long sW, double2* out, long sOut,
+                              hipStream_t s);
+// For item z < nitems and t < nblk: block t of dst_z = block t of src_z, with
+// src_z = src + z * sS and dst_z = dst + (z / inner) * sDo + (z % inner) * sDi (elements).
+hipError_t launch_scatter_blocks(int b, int nitems, int nblk, const double2* src, long sS, double2* dst, int inner,
+                                 long sDo, long sDi, hipStream_t s);
 
 // dst_p = src_p (plain copy of a batch of b x b blocks)
 hipError_t launch_copy_blocks(int b, int batch, const double2* src, long sS, double2* dst, long sD, hipStream_t s);

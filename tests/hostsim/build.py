@@ -16,7 +16,7 @@ def build() -> str:
     flags = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"),
              "-I", CSRC, "-Wno-unused-result"]
     objs = []
-    for src in (os.path.join(CSRC, "api.hip"), os.path.join(HERE, "hostsim.cpp")):
+    for src in (os.path.join(CSRC, "api.hip"), os.path.join(CSRC, "serinv.hip"), os.path.join(HERE, "hostsim.cpp")):
         obj = os.path.join(out, os.path.basename(src) + ".o")
         subprocess.run([hipcc, *flags, "-x", "hip", "-c", src, "-o", obj], check=True, capture_output=True)
         objs.append(obj)

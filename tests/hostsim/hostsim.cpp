@@ -175,25 +175,50 @@ hipError_t launch_assemble(const AssembleDesc& d, hipStream_t) {
   const int b = d.b;
   for (int p = 0; p < d.batch; ++p) {
     if (!act(d.active, p)) continue;
-    const double e = d.energies ? d.energies[p] : 0.0;
+    const long go = d.inner > 0 ? (long)(p / d.inner) * d.sHo : 0;
+    const double2* S = d.S ? d.S + go : nullptr;
+    const double2* Hm = d.H ? d.H + go : nullptr;
+    const double2* Y = d.Y ? d.Y + go : nullptr;
+    const double e = d.energies ? d.energies[d.inner > 0 ? p % d.inner : p] : 0.0;
     const cd zc = d.s_coef * cd(e, d.eta);
     for (int i = 0; i < b; ++i)
       for (int j = 0; j < b; ++j) {
         const long o = (long)i * b + j, ot = (long)j * b + i;
         cd sv, hv;
         if (d.op == 1) {
-          sv = d.S ? std::conj(C(d.S[ot])) : cd((d.s_identity && i == j) ? 1.0 : 0.0);
-          hv = d.H ? std::conj(C(d.H[ot])) : cd(0);
+          sv = S ? std::conj(C(S[ot])) : cd((d.s_identity && i == j) ? 1.0 : 0.0);
+          hv = Hm ? std::conj(C(Hm[ot])) : cd(0);
         } else {
-          sv = d.S ? C(d.S[o]) : cd((d.s_identity && i == j) ? 1.0 : 0.0);
-          hv = d.H ? C(d.H[o]) : cd(0);
+          sv = S ? C(S[o]) : cd((d.s_identity && i == j) ? 1.0 : 0.0);
+          hv = Hm ? C(Hm[o]) : cd(0);
         }
         cd r = zc * sv + d.h_coef * hv;
-        if (d.Y) r += d.y_coef * C(d.Y[o]);
+        if (Y) r += d.y_coef * C(Y[o]);
         if (d.Z) r += d.z_coef * C(d.Z[(long)p * d.sZ + o]);
         d.out[(long)p * d.sOut + o] = D(r);
       }
   }
+  return hipSuccess;
+}
+
+hipError_t launch_add_adjoint(int b, int batch, double2 c, const double2* W, long sW, double2* out, long sOut,
+                              hipStream_t) {
+  for (int p = 0; p < batch; ++p)
+    for (int i = 0; i < b; ++i)
+      for (int j = 0; j < b; ++j) {
+        double2& o = out[(long)p * sOut + (long)i * b + j];
+        o = D(C(o) + C(c) * std::conj(C(W[(long)p * sW + (long)j * b + i])));
+      }
+  return hipSuccess;
+}
+
+hipError_t launch_scatter_blocks(int b, int nitems, int nblk, const double2* src, long sS, double2* dst, int inner,
+                                 long sDo, long sDi, hipStream_t) {
+  if (nitems <= 0 || nblk <= 0) return hipSuccess;
+  if (inner <= 0) return hipErrorInvalidValue;
+  for (int z = 0; z < nitems; ++z)
+    std::memmove(dst + (long)(z / inner) * sDo + (long)(z % inner) * sDi, src + (long)z * sS,
+                 sizeof(double2) * b * b * nblk);
   return hipSuccess;
 }
 

@@ -261,3 +261,48 @@ def test_fullsize_plan_path_conditioned(setup, refs, cmul):
     _properties(nb, outputs, prob, info)
     del outputs
     _free()
+
+
+@pytest.fixture(scope="module")
+def scattering_refs(setup):
+    """The same device with the scattering self-energies of the interacting
+    workload (norm 0.01), oracle at two sampled energies at eta = 1e-2."""
+    nb, bench, autotune, dev, gdev, energies = setup
+    sdev = w.scattering_self_energies(w.slab_device(NB, B, 2), 3)
+    out = {}
+    for k in STABLE_K[:2]:
+        _progress(f"oracle (scattering device) at eta = {ETA_STABLE}, point {k} (E = {energies[k]:+.6f}) ...")
+        ref, spread = plain_reference(lambda: orgf.solve_point(sdev, energies[k], ETA_STABLE, MU_L, MU_R, KT),
+                                      NAMES, PLAIN_TOL)
+        out[k] = (ref, PLAIN_TOL, spread, kappa_proxy(sdev, ref))
+    return sdev, out
+
+
+@pytest.mark.parametrize("parts", [8, 4])
+def test_fullsize_serinv_plain_bar(setup, scattering_refs, parts):
+    """The partitioned inversion at the full size (eight or four partitions of
+    the 60 blocks, two energies in one call) against the oracle at eta = 1e-2,
+    on the device with scattering self-energies: the partitions' interiors are
+    then broadened like every other block.  (Without any broadening inside the
+    device, an isolated interior at a real energy is nearly singular and the
+    partitioned elimination loses up to ~1e-7 at this size, the oracle's own
+    partitioned prototype included.)"""
+    nb, bench, autotune, dev, gdev, energies = setup
+    sdev, refs = scattering_refs
+    ks = sorted(refs)
+    prob = nb.Problem(nb.DeviceOnGPU(sdev), energies[ks], eta=ETA_STABLE, mu_l=MU_L, mu_r=MU_R, kT=KT)
+    out = nb.serinv_lesser_greater(prob, parts, opts=_headline_opts(nb, bench, autotune))
+    info = out["info"].cpu().numpy()
+    assert np.all(info == 0), info
+    for i, k in enumerate(ks):
+        ref, bar, spread, kappa = refs[k]
+        for name in NAMES:
+            g = out[name][0][i].cpu().numpy()
+            r = getattr(ref, name)
+            err = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+            record(f"fullsize_serinv_P{parts}_scattering_eta1e-2", energies[k], name, err, bar, spread.get(name),
+                   kappa, partitions=parts)
+            _progress(f"serinv P={parts} point {k} {name}: error {err:.3e}, bar {bar:.1e}")
+            assert err <= bar, (parts, k, name, err)
+    del out
+    _free()
