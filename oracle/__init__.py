@@ -19,9 +19,11 @@ Modules
                  complex64 NumPy products (diagnostic only)
   mlp         -- float64 reference of the small MLP used to seed the lead
                  iteration, with a hand-written backward pass and Adam
+  econv       -- the energy convolution of Eq. (3) on a uniform grid (the
+                 plain sum), and the (E; i,j) -> (i,j; E) layout change
 
 Parity status: every function is pinned by the CPU tests against closed
 forms, brute force or physical invariants, except the absolute throughput,
 for which the paper prints no number (parity unpinned).
 """
-from . import leads, dense, rgf, observables, emulate, mlp  # noqa: F401
+from . import leads, dense, rgf, observables, emulate, mlp, econv  # noqa: F401
