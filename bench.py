@@ -168,12 +168,15 @@ def main():
     ap.add_argument("--inv-nb", type=int, default=0, help="inversion panel width (0: tuned)")
     ap.add_argument("--cmul", type=int, choices=[3, 4], default=3,
                     help="real products per complex double product (3: Gauss's method)")
-    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm", "serinv"], default="ribbon",
+    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm", "serinv", "econv"], default="ribbon",
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation; gemm: the "
                          "dominant product kernel alone through negf_zgemm_batched at the headline's block size "
                          "and batch (for hardware counters); serinv: few energies per call, plain RGF against the "
-                         "partitioned inversion")
+                         "partitioned inversion; econv: the energy convolution of Eq. (3) and the energy/element "
+                         "layout change over one GPU's share of the selected entries")
+    ap.add_argument("--econv-elements", type=int, default=1 << 21, help="elements (matrix entries) in the econv "
+                    "workload")
     ap.add_argument("--gemm-batch", type=int, default=256, help="products per launch in the gemm workload")
     ap.add_argument("--serinv-points", default="1,2,4,8", help="energy points per call in the serinv workload")
     ap.add_argument("--serinv-parts", default="4,8", help="partition counts in the serinv workload")
@@ -216,6 +219,8 @@ def main():
         return bench_gemm(args)
     if args.workload == "serinv":
         return bench_serinv(args)
+    if args.workload == "econv":
+        return bench_econv(args)
     if args.workload == "uneven":
         # four worker streams (the hardware queues HIP gives a process by default); each device
         # shape's points form one chunk (see --uneven-batch)
@@ -399,6 +404,63 @@ def bench_gemm(args):
                                    f"{real_products} real products per complex product"},
             "avg_launch_ms": avg, "min_launch_ms": float(np.min(ms)), "frac_of_fp64_peak": flops / (avg * 1e-3) / PEAK["f64"],
             "algorithmic_bytes_per_launch": 3 * 16 * B * B * batch, "rel_err_vs_torch_item0": err}
+    print(json.dumps(line), flush=True)
+
+
+def bench_econv(args):
+    """Energy convolution of Eq. (3) over one GPU's share of the selected entries: n_el
+    elements x 1024 energies of G and of a two-sided kernel W (1024 frequencies), by
+    zero-padded FFTs of length 2048 per element, read and written energy-major; and the
+    energy/element layout change of the same array.  Roofline: HBM (every byte of G, W
+    and B moves once)."""
+    import torch
+    from paper_2602_03438_amd import binding as nb
+    n_e, n_w, k0, n_el = N_GRID, N_GRID, N_GRID // 2, args.econv_elements
+    g = torch.Generator(device="cuda").manual_seed(11)
+    G = torch.randn(n_e, n_el, dtype=torch.complex128, device="cuda", generator=g)
+    W = torch.randn(n_w, n_el, dtype=torch.complex128, device="cuda", generator=g)
+    B = torch.empty_like(G)
+    ws = nb.Workspace()
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for a, b in ev:
+            a.record(s)
+            fn()
+            b.record(s)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    ms = timed(lambda: nb.energy_convolution(G, W, k0, 1.0, out=B, ws=ws))
+    # a sampled element against the plain sum (oracle definition), computed here on the host
+    x = n_el // 3
+    Gx, Wx, Bx = G[:, x].cpu().numpy(), W[:, x].cpu().numpy(), B[:, x].cpu().numpy()
+    ref = np.convolve(Gx, Wx)[k0:k0 + n_e]
+    err = float(np.linalg.norm(Bx - ref) / np.linalg.norm(ref))
+    del W
+    torch.cuda.empty_cache()
+    T = torch.empty(n_el, n_e, dtype=torch.complex128, device="cuda")
+    ms_t = timed(lambda: nb.transpose(G, out=T))
+    ok_t = bool(torch.equal(T[x], G[:, x]))
+    bytes_conv = 16.0 * n_el * (2 * n_e + n_w)
+    bytes_t = 32.0 * n_el * n_e
+    L = 2048
+    fft_flops = 3 * 5.0 * L * np.log2(L) * n_el + 6.0 * L * n_el
+    line = {"metric": "energy convolution of Eq. (3) by FFT, elements x energies per second",
+            "value": n_el * n_e / (ms * 1e-3), "unit": "element-energies/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{n_el} elements x {n_e} energies, two-sided kernel of {n_w} frequencies "
+                                   f"(k0 = {k0}), FFT length {L}, energy-major in and out"},
+            "roofline": {"bound": "hbm", "achieved": bytes_conv / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": bytes_conv / (ms * 1e-3) / 8e12, "traffic": None,
+                         "algorithmic_bytes_per_launch": bytes_conv, "fft_tflops": fft_flops / (ms * 1e-3) / 1e12},
+            "rel_err_sampled_element_vs_plain_sum": err,
+            "transpose": {"ms": ms_t, "gb_per_s": bytes_t / (ms_t * 1e-3) / 1e9, "frac_of_hbm": bytes_t / (ms_t * 1e-3) / 8e12,
+                          "rows": n_e, "cols": n_el, "sampled_column_exact": ok_t}}
     print(json.dumps(line), flush=True)
 
 

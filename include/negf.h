@@ -237,6 +237,27 @@ negf_status negf_serinv_lesser_greater(const negf_problem* problem, int32_t part
                                        void* GG_diag, void* GG_upper, int32_t* info, void* workspace, size_t ws_bytes,
                                        void* stream);
 
+/* ---- energy convolution of Eq. (3) and the energy/element layout change ----
+ * Eq. (3) builds a self-energy from an integral over energy of an element-wise
+ * product, B(E) ~ int dE' C1(E - E') (.) C2(E') (M1 = M2 = I, the GW form);
+ * the paper evaluates it with FFTs (Section II, after Fig. 3).  On a uniform
+ * grid, for every element x of energy-major complex128 arrays
+ * G [n_e][n_el], W [n_w][n_el] (W[k] at frequency (k - k0) dE):
+ *     B[e][x] = scale * sum_{k=0}^{n_w-1} G[e + k0 - k][x] * W[k][x]
+ * with G zero outside [0, n_e); scale (host, 2 doubles) carries dE and the
+ * prefactor.  Computed per element by zero-padded FFTs of length
+ * L = 2^ceil(log2(n_e + n_w - 1)) in LDS, reading and writing the
+ * energy-major layout directly.  Requirements: n_e, n_w >= 1, 0 <= k0 < n_w,
+ * n_e + n_w - 1 <= 4096; B must not overlap G or W.  Workspace (twiddles):
+ * negf_econv_workspace_bytes(n_e, n_w).  Errors: EINVAL, EHIP. */
+size_t negf_econv_workspace_bytes(int32_t n_e, int32_t n_w);
+negf_status negf_energy_convolution(int32_t n_e, int64_t n_el, const void* G, int32_t n_w, int32_t k0, const void* W,
+                                    const double* scale, void* B, void* workspace, size_t ws_bytes, void* stream);
+/* The (E; i,j) <-> (i,j; E) layout change of Fig. 2 on one GPU:
+ * dst[c][r] = src[r][c] for a rows x cols complex128 array (dst must not
+ * overlap src).  Errors: EINVAL, EHIP. */
+negf_status negf_transpose(int64_t rows, int64_t cols, const void* src, void* dst, void* stream);
+
 /* ---- plans: many problems of uneven block shapes in one launch ----
  * A plan groups the points of all problems into chunks of one block shape
  * (at most `batch` points each, per shape from `tunings`), assigns chunks to

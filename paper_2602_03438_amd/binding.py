@@ -88,6 +88,12 @@ def lib():
     L.negf_serinv_lesser_greater.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, vp, vp, vp, vp, vp,
                                              vp, sz, vp]
     L.negf_serinv_lesser_greater.restype = C.c_int
+    L.negf_econv_workspace_bytes.argtypes = [i32, i32]
+    L.negf_econv_workspace_bytes.restype = sz
+    L.negf_energy_convolution.argtypes = [i32, i64, vp, i32, i32, vp, P(dbl), vp, vp, sz, vp]
+    L.negf_energy_convolution.restype = C.c_int
+    L.negf_transpose.argtypes = [i64, i64, vp, vp, vp]
+    L.negf_transpose.restype = C.c_int
     L.negf_transmission.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, sz, vp]
     L.negf_transmission.restype = C.c_int
     L.negf_zgemm_batched.argtypes = [C.c_char, C.c_char, i32, i32, i32, P(dbl), vp, i64, i64, vp, i64, i64, P(dbl),
@@ -463,6 +469,39 @@ def serinv_lesser_greater(problem, partitions, opts=None, greater=False, lower=T
     res["info"] = info
     res["flat"] = out
     return res
+
+
+def energy_convolution(G, W, k0, scale=1.0, out=None, ws=None):
+    """negf_energy_convolution of energy-major complex128 tensors G [n_e, n_el] and
+    W [n_w, n_el]: B[e] = scale * sum_k G[e + k0 - k] * W[k]."""
+    torch = _torch()
+    for t in (G, W):
+        if not t.is_contiguous() or t.dtype != torch.complex128 or t.dim() != 2:
+            raise NegfError("G and W must be C-contiguous 2-D complex128 tensors [energies, elements]")
+    n_e, n_el = G.shape
+    n_w = W.shape[0]
+    if W.shape[1] != n_el:
+        raise NegfError("G and W must have the same number of elements")
+    nbytes = lib().negf_econv_workspace_bytes(n_e, n_w)
+    if nbytes == 0:
+        raise NegfError("n_e + n_w - 1 exceeds the longest transform (4096)")
+    buf = (ws or Workspace()).get(nbytes)
+    B = out if out is not None else torch.empty_like(G)
+    sc = (C.c_double * 2)(complex(scale).real, complex(scale).imag)
+    check(lib().negf_energy_convolution(n_e, n_el, _ptr(G), n_w, int(k0), _ptr(W), sc, _ptr(B), _ptr(buf),
+                                        buf.numel(), _stream()), "negf_energy_convolution")
+    return B
+
+
+def transpose(X, out=None):
+    """negf_transpose of a C-contiguous 2-D complex128 tensor."""
+    torch = _torch()
+    if not X.is_contiguous() or X.dtype != torch.complex128 or X.dim() != 2:
+        raise NegfError("transpose needs a C-contiguous 2-D complex128 tensor")
+    r, c = X.shape
+    Y = out if out is not None else torch.empty(c, r, dtype=X.dtype, device=X.device)
+    check(lib().negf_transpose(r, c, _ptr(X), _ptr(Y), _stream()), "negf_transpose")
+    return Y
 
 
 def transmission(problems, opts=None, ws=None):
