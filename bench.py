@@ -43,12 +43,26 @@ def energy_batches(P):
     return [grid[j::stride][:P] for j in range(stride)]
 
 
-def kernel_hash():
+def kernel_hash(source="gemm.hip"):
     h = hashlib.sha256()
-    for f in ("gemm.hip",):
-        with open(os.path.join(ROOT, "paper_2602_03438_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2602_03438_amd", "csrc", source), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def econv_traffic_per_element():
+    """HBM bytes per element of the energy-convolution kernel from the committed counter
+    summary, if it was taken on the current source."""
+    p = os.path.join(ROOT, "profiles", "econv_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except Exception:
+        return None
+    if rec.get("kernel_sha") != kernel_hash("econv.hip"):
+        return None
+    return rec.get("bytes_per_item")
 
 
 def traffic_per_item():
@@ -175,6 +189,8 @@ def main():
                          "and batch (for hardware counters); serinv: few energies per call, plain RGF against the "
                          "partitioned inversion; econv: the energy convolution of Eq. (3) and the energy/element "
                          "layout change over one GPU's share of the selected entries")
+    ap.add_argument("--econv-cpu-elements", type=int, default=8192,
+                    help="elements the oracle computes for the econv workload's cpu_baseline")
     ap.add_argument("--econv-elements", type=int, default=1 << 21, help="elements (matrix entries) in the econv "
                     "workload")
     ap.add_argument("--gemm-batch", type=int, default=256, help="products per launch in the gemm workload")
@@ -436,11 +452,26 @@ def bench_econv(args):
         return float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
     ms = timed(lambda: nb.energy_convolution(G, W, k0, 1.0, out=B, ws=ws))
-    # a sampled element against the plain sum (oracle definition), computed here on the host
+    # a sampled element against the plain sum, computed here on the host
     x = n_el // 3
     Gx, Wx, Bx = G[:, x].cpu().numpy(), W[:, x].cpu().numpy(), B[:, x].cpu().numpy()
     ref = np.convolve(Gx, Wx)[k0:k0 + n_e]
     err = float(np.linalg.norm(Bx - ref) / np.linalg.norm(ref))
+    cpu = None
+    if not args.no_cpu:
+        # the oracle (the sum over k as written) on a contiguous run of elements of the same arrays
+        from oracle import econv as oec
+        n_s = min(args.econv_cpu_elements, n_el)
+        x0 = n_el // 2
+        Gs, Ws, Bs = (X[:, x0:x0 + n_s].cpu().numpy() for X in (G, W, B))
+        t0 = time.perf_counter()
+        ref_s = oec.energy_convolution(Gs, Ws, k0, 1.0)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=n_s * n_e / dt, unit="element-energies/s", cores=1, kind="oracle",
+                   sample=f"{n_s} elements x {n_e} energies (elements {x0}..{x0 + n_s - 1}), the sum over the "
+                          f"{n_w} kernel frequencies in NumPy complex128 (single-threaded element-wise)",
+                   seconds=dt, host_cpus=os.cpu_count(),
+                   rel_err_gpu_vs_oracle=float(np.linalg.norm(Bs - ref_s) / np.linalg.norm(ref_s)))
     del W
     torch.cuda.empty_cache()
     T = torch.empty(n_el, n_e, dtype=torch.complex128, device="cuda")
@@ -456,9 +487,11 @@ def bench_econv(args):
             "config": {"workload": f"{n_el} elements x {n_e} energies, two-sided kernel of {n_w} frequencies "
                                    f"(k0 = {k0}), FFT length {L}, energy-major in and out"},
             "roofline": {"bound": "hbm", "achieved": bytes_conv / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": bytes_conv / (ms * 1e-3) / 8e12, "traffic": None,
+                         "frac": bytes_conv / (ms * 1e-3) / 8e12,
+                         "traffic": (per_el * n_el if (per_el := econv_traffic_per_element()) else None),
                          "algorithmic_bytes_per_launch": bytes_conv, "fft_tflops": fft_flops / (ms * 1e-3) / 1e12},
             "rel_err_sampled_element_vs_plain_sum": err,
+            "cpu_baseline": cpu,
             "transpose": {"ms": ms_t, "gb_per_s": bytes_t / (ms_t * 1e-3) / 1e9, "frac_of_hbm": bytes_t / (ms_t * 1e-3) / 8e12,
                           "rows": n_e, "cols": n_el, "sampled_column_exact": ok_t}}
     print(json.dumps(line), flush=True)

@@ -246,7 +246,8 @@ negf_status negf_serinv_lesser_greater(const negf_problem* problem, int32_t part
  *     B[e][x] = scale * sum_{k=0}^{n_w-1} G[e + k0 - k][x] * W[k][x]
  * with G zero outside [0, n_e); scale (host, 2 doubles) carries dE and the
  * prefactor.  Computed per element by zero-padded FFTs of length
- * L = 2^ceil(log2(n_e + n_w - 1)) in LDS, reading and writing the
+ * L = 2^max(4, ceil(log2(n_e + n_w - 1))), held in registers (LDS carries
+ * only the exchanges between radix-8 passes), reading and writing the
  * energy-major layout directly.  Requirements: n_e, n_w >= 1, 0 <= k0 < n_w,
  * n_e + n_w - 1 <= 4096; B must not overlap G or W.  Workspace (twiddles):
  * negf_econv_workspace_bytes(n_e, n_w).  Errors: EINVAL, EHIP. */

@@ -90,17 +90,19 @@ def items_of(name: str, wgs: int, block: int) -> float:
     return wgs / tiles
 
 
-def gemm_source_hash(root: str) -> str:
+def gemm_source_hash(root: str, source: str = "gemm.hip") -> str:
+    """First 16 hex digits of the sha256 of a kernel source under csrc/ (the product kernels by default)."""
     h = hashlib.sha256()
-    with open(os.path.join(root, "paper_2602_03438_amd", "csrc", "gemm.hip"), "rb") as fh:
+    with open(os.path.join(root, "paper_2602_03438_amd", "csrc", source), "rb") as fh:
         h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def traffic(fetch_dir: str, write_dir: str, calib_mib: int, kernel: str, block: int,
-            calib_kernel: str = "elementwise"):
+            calib_kernel: str = "elementwise", items: float = 0.0):
     """HBM bytes of the product kernel: per launch and per b x b x b item (so that a
-    launch of any batch can be priced as items x bytes_per_item)."""
+    launch of any batch can be priced as items x bytes_per_item).  With items > 0 every
+    launch of the kernel counts that many items (another kernel's unit: elements, say)."""
     fetch = per_dispatch(fetch_dir, "FETCH_SIZE")
     write = per_dispatch(write_dir, "WRITE_SIZE")
     nbytes = calib_mib << 20
@@ -114,8 +116,9 @@ def traffic(fetch_dir: str, write_dir: str, calib_mib: int, kernel: str, block: 
     f_cal, w_cal = calib(fetch), calib(write)
     f_scale, w_scale = nbytes / f_cal, nbytes / w_cal
     pat = re.compile(kernel)
-    fk = [(v * 1024.0 * f_scale, items_of(n, g, block)) for (n, v, g) in fetch.values() if pat.search(n)]
-    wk = [(v * 1024.0 * w_scale, items_of(n, g, block)) for (n, v, g) in write.values() if pat.search(n)]
+    count = (lambda n, g: items) if items > 0 else (lambda n, g: items_of(n, g, block))
+    fk = [(v * 1024.0 * f_scale, count(n, g)) for (n, v, g) in fetch.values() if pat.search(n)]
+    wk = [(v * 1024.0 * w_scale, count(n, g)) for (n, v, g) in write.values() if pat.search(n)]
     if not fk or not wk:
         raise RuntimeError(f"no dispatch matching '{kernel}'")
     f_item = sum(b for b, _ in fk) / sum(i for _, i in fk)
@@ -185,6 +188,11 @@ if __name__ == "__main__":
     ap.add_argument("--calib-mib", type=int, default=1024)
     ap.add_argument("--kernel", default=r"zgemm_kernel<double, [01], [01], [^>]*Cfg<\d+, \d+, \d, \d>, 0(, (true|false))*>")
     ap.add_argument("--block", type=int, default=512, help="block size b of the products")
+    ap.add_argument("--items", type=float, default=0.0, help="items per launch for a kernel other than the "
+                    "product (e.g. the elements of an energy convolution)")
+    ap.add_argument("--calib-kernel", default="elementwise", help="name fragment of the calibration copy "
+                    "(the largest matching dispatch is taken)")
+    ap.add_argument("--source", default="gemm.hip", help="csrc/ file whose hash is stored with the summary")
     ap.add_argument("--mfma", metavar="MFMA_DIR", help="counter run with SQ_INSTS_VALU_MFMA_MOPS_F64, "
                     "SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE")
     ap.add_argument("--json")
@@ -197,9 +205,11 @@ if __name__ == "__main__":
             with open(a.json, "w") as f:
                 json.dump(rec, f, indent=1)
     elif a.traffic:
-        rec = traffic(a.traffic[0], a.traffic[1], a.calib_mib, a.kernel, a.block)
+        rec = traffic(a.traffic[0], a.traffic[1], a.calib_mib, a.kernel, a.block, calib_kernel=a.calib_kernel,
+                      items=a.items)
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-        rec["kernel_sha"] = gemm_source_hash(root)
+        rec["kernel_sha"] = gemm_source_hash(root, a.source)
+        rec["source"] = a.source
         rec["note"] = a.note
         print(json.dumps(rec, indent=1))
         if a.json:

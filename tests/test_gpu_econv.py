@@ -22,9 +22,10 @@ def _rand(r, shape):
 
 
 # (n_e, n_w, k0, n_el): every transform length from 16 to 4096 (and so every
-# elements-per-workgroup choice), ragged element counts, one- and two-sided kernels
+# elements-per-workgroup choice), ragged element counts (47 at L = 2048: 24 tiles of
+# two, so the XCD-contiguous order with a ragged last tile), one- and two-sided kernels
 CASES = [(5, 3, 1, 7), (9, 20, 0, 33), (40, 25, 12, 100), (100, 29, 28, 37), (200, 57, 3, 64), (300, 211, 105, 41),
-         (512, 513, 256, 19), (1024, 1024, 512, 24), (1500, 1200, 600, 5), (2048, 2049, 1024, 3)]
+         (512, 513, 256, 19), (1024, 1024, 512, 24), (700, 900, 450, 47), (1500, 1200, 600, 5), (2048, 2049, 1024, 3)]
 
 
 @pytest.mark.parametrize("n_e,n_w,k0,n_el", CASES)
