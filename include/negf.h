@@ -401,6 +401,12 @@ typedef struct negf_kernel_stats {
  * pairs events around each launch; counters are read after the caller has
  * synchronised every stream it used. */
 void negf_profile_enable(int32_t on);
+/* Which kernel classes get timing events while profiling is on: bit k set
+ * times class k (default: all).  Every event pair costs host time per launch,
+ * so a run that times one class (the products, ~4 % of the launches of an RGF
+ * call) keeps close to the unprofiled speed; the flop counters cover every
+ * class regardless (launches and total_ms stay 0 for untimed classes). */
+void negf_profile_time_classes(uint32_t mask);
 /* Fill stats[NEGF_KC_COUNT]; returns NEGF_EHIP if an event query failed. */
 negf_status negf_profile_read(negf_kernel_stats* stats);
 

@@ -105,6 +105,8 @@ def lib():
     L.negf_zinv_batched.restype = C.c_int
     L.negf_profile_enable.argtypes = [i32]
     L.negf_profile_enable.restype = None
+    L.negf_profile_time_classes.argtypes = [C.c_uint32]
+    L.negf_profile_time_classes.restype = None
     L.negf_profile_read.argtypes = [P(negf_kernel_stats)]
     L.negf_profile_read.restype = C.c_int
     L.negf_status_string.argtypes = [C.c_int]
@@ -214,6 +216,10 @@ def negf_inverse_workspace_bytes(n, batch):
 
 def negf_profile_enable(on):
     lib().negf_profile_enable(int(on))
+
+
+def negf_profile_time_classes(mask):
+    lib().negf_profile_time_classes(int(mask) & 0xFFFFFFFF)
 
 
 def negf_profile_read():

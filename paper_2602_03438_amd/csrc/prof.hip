@@ -19,6 +19,7 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+unsigned g_prof_mask = ~0u;              // kernel classes whose launches get timing events
 std::vector<ProfRec> g_prof_pending;
 std::vector<hipEvent_t> g_prof_pool;
 negf_kernel_stats g_prof_acc[KC_COUNT];
@@ -53,8 +54,7 @@ unsigned long long* prof_flop_slots(int cls) {
 }
 
 void prof_begin(int cls, hipStream_t s) {
-  (void)cls;
-  if (!g_prof_on || g_capturing) return;
+  if (!g_prof_on || g_capturing || cls < 0 || cls >= KC_COUNT || !((g_prof_mask >> cls) & 1u)) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   t_open = pool_get();
   if (t_open) hipEventRecord(t_open, s);
@@ -126,6 +126,11 @@ double rt_wallclock_hz() {
 }  // namespace negf
 
 extern "C" {
+
+void negf_profile_time_classes(uint32_t mask) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_mask = mask;
+}
 
 void negf_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
