@@ -201,7 +201,12 @@ def main():
     ap.add_argument("--gemm-batch", type=int, default=256, help="products per launch in the gemm workload")
     ap.add_argument("--serinv-points", default="1,2,4,8", help="energy points per call in the serinv workload")
     ap.add_argument("--serinv-parts", default="4,8", help="partition counts in the serinv workload")
-    ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload")
+    ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload "
+                    "(with --uneven-queue: the slots per (device, k) that the task lists stream through)")
+    ap.add_argument("--uneven-queue", action="store_true",
+                    help="the whole uneven workload: 2048 energies x 4 k = 8192 points (grid energy e on device "
+                         "e mod 6) streamed through the plan by the device-side point queue")
+    ap.add_argument("--uneven-grid", type=int, default=2048, help="grid energies of --uneven-queue (x 4 k points)")
     ap.add_argument("--uneven-batch", type=int, default=0,
                     help="points per chunk in the uneven workload (0: all points of a block shape in one chunk)")
     ap.add_argument("--streams", type=int, default=None,
@@ -580,6 +585,8 @@ def bench_uneven(args):
     import workloads as w
     from paper_2602_03438_amd import autotune
     from paper_2602_03438_amd import binding as nb
+    if args.uneven_queue:
+        return bench_uneven_queue(args)
     ks = [np.pi * j / 4 for j in range(4)]
     grid = np.linspace(-1.5, 1.5, 2048)
     probs, dev_of = [], []
@@ -660,6 +667,138 @@ def bench_uneven(args):
             "eager_points_per_s": npts / dt_eager,
             "info_nonzero": int(torch.count_nonzero(info).item()),
             "per_device_completion": per_dev}
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
+def uneven_devices(nb, w):
+    """The six slab devices of the uneven workload at the 4 k-points: [(device index, k, BTDevice,
+    device-side copy)], the overlap shared by the k copies of a device."""
+    ks = [np.pi * j / 4 for j in range(4)]
+    out = []
+    for d, (b, nbk) in enumerate(w.DEVICE_MIX):
+        log(f"device {d}: b={b} Nb={nbk}")
+        base = w.slab_device(nbk, b, 40 + d)
+        S_d, S_u = nb.to_gpu(base.S_diag), nb.to_gpu(base.S_upper)
+        for ki, k in enumerate(ks):
+            dk = w.k_device(base, 1000 + d, k)
+            g = nb.DeviceOnGPU.__new__(nb.DeviceOnGPU)
+            g.nb, g.b = dk.nb, dk.b
+            g.H_diag, g.H_upper = nb.to_gpu(dk.H_diag), nb.to_gpu(dk.H_upper)
+            g.S_diag, g.S_upper = S_d, S_u
+            g.sig_r = g.sig_l = g.sig_g = None
+            out.append((d, ki, dk, g))
+    return out
+
+
+def bench_uneven_queue(args):
+    """The whole uneven workload (2048 energies x 4 k = 8192 points; grid energy e belongs to device
+    e mod 6) streamed through one plan by the device-side point queue: every (device, k) problem has
+    --uneven-points slots, each worker stream replays its captured round until its task lists are
+    done, and every task gets its density of states, info and a GPU completion stamp.  Points/s over
+    the whole run; per-device p50/p99/last completion from the stamps; the oracle on one task per
+    block shape (the cpu_baseline leg) against the task's density of states."""
+    import torch
+    import workloads as w
+    from paper_2602_03438_amd import autotune
+    from paper_2602_03438_amd import binding as nb
+    grid = np.linspace(-1.5, 1.5, args.uneven_grid)
+    ndev = len(w.DEVICE_MIX)
+    devs = uneven_devices(nb, w)
+    slots = args.uneven_points
+    probs, tasks, dev_of = [], [], []
+    for d, ki, dk, g in devs:
+        probs.append(nb.Problem(g, np.zeros(slots), eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT))
+        tasks.append(grid[d::ndev].copy())
+        dev_of.append(d)
+    tunings = []
+    for b, _ in w.DEVICE_MIX:
+        t = autotune.lookup(b, args.cmul)
+        tunings.append((b, t["gemm_tile"], t["gemm_tile_f32"], t["inv_nb"], args.uneven_batch))
+    plan = nb.Plan(probs, nb.FP32_REFINE, opts=nb.make_options(sr_max_iter=40, cmul=args.cmul), tunings=tunings,
+                   n_streams=args.streams)
+    chunks = plan.chunks()
+    outs = plan.outputs()
+    info = torch.zeros(sum(p.n_e for p in probs), dtype=torch.int32, device="cuda")
+    tE = [torch.from_numpy(t).cuda() for t in tasks]
+    n_tasks = int(sum(t.size for t in tasks))
+    rounds = max(-(-t.size // slots) for t in tasks)
+    log(f"{len(probs)} problems x {slots} slots, {n_tasks} tasks, {len(chunks)} chunks on {args.streams} streams, "
+        f"{rounds} rounds")
+    # the task lists go through the queue in parts of at most 10 rounds (one run_queue call each,
+    # enqueued back to back): the host call returns once the GPU has taken most of its part (the HIP
+    # runtime bounds the launches in flight), which gives a progress line every ~40 s
+    part_rounds = 10
+    parts = -(-rounds // part_rounds)
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(parts):
+        lo = j * part_rounds * slots
+        sl = [t[lo:lo + part_rounds * slots] for t in tE]
+        results.append(plan.run_queue(sl, outs, info, use_graph=True))
+        log(f"  part {j + 1}/{parts} ({sum(x.numel() for x in sl)} tasks) enqueued after {time.perf_counter() - t0:.1f} s")
+    t_enq = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    hz = nb.Plan.clock_hz()
+    # per-part results back in task order (problem-major, each problem's tasks in list order)
+    st, tinfo, dos = [], [], []
+    for q in range(len(tasks)):
+        for j, r in enumerate(results):
+            lo = j * part_rounds * slots
+            n_j = max(0, min(tasks[q].size - lo, part_rounds * slots))
+            off = sum(max(0, min(tasks[p].size - lo, part_rounds * slots)) for p in range(q))
+            st.append(r["stamps"][off:off + n_j].cpu().numpy())
+            tinfo.append(r["info"][off:off + n_j].cpu().numpy())
+            dos.append(r["dos"][off:off + n_j].cpu().numpy())
+    st, tinfo, dos = np.concatenate(st).astype(np.float64), np.concatenate(tinfo), np.concatenate(dos)
+    t_done = (st - float(results[0]["start"].item())) / hz
+    dev_task = np.concatenate([[dev_of[q]] * t.size for q, t in enumerate(tasks)])
+    per_dev = {}
+    for d, (b, nbk) in enumerate(w.DEVICE_MIX):
+        x = t_done[dev_task == d]
+        per_dev[f"b{b}_nb{nbk}"] = {"points": int(x.size), "p50_s": float(np.percentile(x, 50)),
+                                    "p99_s": float(np.percentile(x, 99)), "last_s": float(x.max()),
+                                    "info_nonzero": int(np.count_nonzero(tinfo[dev_task == d]))}
+    cpu = None
+    if not args.no_cpu:
+        # the oracle on one task per block shape (k = 0, the middle task of its list)
+        from oracle import rgf as orgf
+        checks, secs = [], 0.0
+        off = np.cumsum([0] + [t.size for t in tasks])
+        for q, (d, ki, dk, g) in enumerate(devs):
+            if ki != 0:
+                continue
+            i = tasks[q].size // 2
+            E = float(tasks[q][i])
+            t1 = time.perf_counter()
+            o = orgf.solve_point(dk, E, ETA, MU_L, MU_R, KT, lesser_greater=False)
+            secs += time.perf_counter() - t1
+            dos_o = -np.imag(sum(np.trace(x) for x in o.GR_diag)) / np.pi
+            checks.append({"b": dk.b, "nb": dk.nb, "E": E, "dos_gpu": float(dos[off[q] + i]), "dos_oracle": float(dos_o),
+                           "rel_err": float(abs(dos[off[q] + i] - dos_o) / abs(dos_o)), "info": int(tinfo[off[q] + i]),
+                           "oracle_lead_residuals": [o.lead_l.residual, o.lead_r.residual]})
+            log(f"  oracle b={dk.b} Nb={dk.nb} E={E:+.4f}: rel. DOS error {checks[-1]['rel_err']:.2e}")
+        cpu = {"value": len(checks) / secs, "unit": "energy points/s", "cores": os.cpu_count(), "kind": "oracle",
+               "sample": "one task per block shape (k = 0), G^R only, NumPy complex128", "seconds": secs,
+               "checks": checks}
+    line = {"metric": "energy points/s, batched uneven workload streamed by the point queue (6 devices x 4 k, "
+                      "2048 energies, refined single-product form)",
+            "value": n_tasks / dt, "unit": "energy points/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": dt * 1e3, "higher_is_better": True, "dtype": "f32 products + f64 refinement",
+            "data": "synthetic",
+            "config": {"workload": "uneven: six slab devices (b, Nb) in " + str(w.DEVICE_MIX) +
+                       f" x 4 k-points x {args.uneven_grid} energies (grid energy e on device e mod 6): "
+                       f"{n_tasks} points",
+                       "slots_per_device_k": slots, "rounds": rounds, "queue_calls": parts, "chunks": len(chunks),
+                       "streams": args.streams, "tunings": tunings,
+                       "real_products_per_complex_product": args.cmul},
+            "gpu_seconds_start_to_last": float(t_done.max()), "host_enqueue_s": t_enq,
+            "stamped_tasks": int(np.count_nonzero(st)),
+            "info_nonzero": int(np.count_nonzero(tinfo)),
+            "per_device_completion": per_dev,
+            "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
     plan.close()
 

@@ -300,6 +300,36 @@ negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag,
 double negf_plan_clock_hz(void);
 void negf_plan_destroy(negf_plan* plan);
 
+/* ---- point queue: task lists streamed through a plan (Section II: the
+ * energies are independent and are solved in parallel) ----
+ * Problem q of the plan provides n_e slots: its energies array, which the queue
+ * rewrites (caller-owned device memory).  Its task list task_E[q] (device,
+ * n_tasks[q] doubles; task_E and n_tasks are host arrays over the problems) holds
+ * the energies to solve.  negf_plan_run_queue forks to the plan's worker streams
+ * and runs rounds there: in a round each chunk first takes its slots' next
+ * tasks from a device-side round counter (in round r, slot i of problem q takes
+ * task r n_e[q] + i; a slot past the end of the list keeps its energy, runs
+ * again and reports nothing), then runs as in negf_plan_execute, then writes for
+ * every task it solved: task_info, task_dos = -Im sum_k Tr G^R_kk / pi (the
+ * oracle's block-resolved density of states, summed) and task_stamps = the wall
+ * clock (ticks of negf_plan_clock_hz()) when the chunk finished.  Results are
+ * concatenated over the problems in problem order (sum n_tasks entries each).
+ * A worker stream runs as many rounds as the problems of its chunks need
+ * (the largest ceil(n_tasks[q] / n_e[q])); streams do not wait for each other
+ * between rounds.  With use_graph = 1 each worker stream's round is captured once
+ * (again when any pointer or task count changes) and replayed.  start_stamp
+ * (nullable, device uint64) receives the wall clock before the first round.
+ * queue_ws: caller-owned device memory of negf_plan_queue_bytes(plan) bytes
+ * (round counters, the slots' current tasks).  The outputs hold the last round's
+ * points.  Enqueued only (no host synchronisation); the caller synchronises
+ * `stream` before reading results.  Errors: EINVAL (arguments), EHIP. */
+size_t negf_plan_queue_bytes(const negf_plan* plan);
+negf_status negf_plan_run_queue(negf_plan* plan, int32_t use_graph, const double* const* task_E,
+                                const int32_t* n_tasks, int32_t* task_info, double* task_dos, uint64_t* task_stamps,
+                                uint64_t* start_stamp, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag,
+                                void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info, void* queue_ws,
+                                size_t queue_bytes, void* workspace, size_t ws_bytes, void* stream);
+
 /* ---- kernel-level entry points (used by the tests and the tile tuner) ---- */
 
 /* C_p = alpha op(A_p) op(B_p) + beta C_p for p < batch, complex128 M x N

@@ -121,6 +121,11 @@ def lib():
     L.negf_plan_chunks.restype = i32
     L.negf_plan_execute.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.negf_plan_execute.restype = C.c_int
+    L.negf_plan_queue_bytes.argtypes = [vp]
+    L.negf_plan_queue_bytes.restype = sz
+    L.negf_plan_run_queue.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, sz,
+                                      vp]
+    L.negf_plan_run_queue.restype = C.c_int
     L.negf_plan_clock_hz.argtypes = []
     L.negf_plan_clock_hz.restype = dbl
     L.negf_plan_destroy.argtypes = [vp]
@@ -588,6 +593,38 @@ class Plan:
                                       _ptr(o.get("GR_lower")), _ptr(o["GL_diag"]), _ptr(o["GL_upper"]),
                                       _ptr(o.get("GG_diag")), _ptr(o.get("GG_upper")), _ptr(info), _ptr(stamps),
                                       _ptr(buf), buf.numel(), _stream()), "negf_plan_execute")
+
+    def run_queue(self, task_energies, outputs, info, use_graph=True, results=None):
+        """Stream per-problem task lists (device float64 tensors, one per problem)
+        through the plan (negf_plan_run_queue).  Returns the task results, each
+        concatenated over the problems: info (int32), dos (float64), stamps (int64
+        wall-clock ticks), and the start stamp (a one-element int64 tensor); pass
+        `results` (a dict from an earlier call) to reuse their buffers."""
+        torch = _torch()
+        if len(task_energies) != len(self.problems):
+            raise NegfError("run_queue: one task list per problem")
+        n_tasks = [int(t.numel()) for t in task_energies]
+        total = sum(n_tasks)
+        if results is None:
+            results = {"info": torch.zeros(max(1, total), dtype=torch.int32, device="cuda"),
+                       "dos": torch.zeros(max(1, total), dtype=torch.float64, device="cuda"),
+                       "stamps": torch.zeros(max(1, total), dtype=torch.int64, device="cuda"),
+                       "start": torch.zeros(1, dtype=torch.int64, device="cuda")}
+        self._tasks = [t.contiguous() for t in task_energies]
+        ptrs = (C.c_void_p * len(self._tasks))(*[_ptr(t) if t.numel() else None for t in self._tasks])
+        counts = (C.c_int32 * len(n_tasks))(*n_tasks)
+        buf = self.ws.get(lib().negf_plan_workspace_bytes(self.handle))
+        qbytes = lib().negf_plan_queue_bytes(self.handle)
+        if getattr(self, "_qws", None) is None or self._qws.numel() < qbytes:
+            self._qws = torch.empty(int(qbytes), dtype=torch.uint8, device="cuda")
+        o = outputs
+        check(lib().negf_plan_run_queue(self.handle, int(use_graph), ptrs, counts, _ptr(results["info"]),
+                                        _ptr(results["dos"]), _ptr(results["stamps"]), _ptr(results["start"]),
+                                        _ptr(o["GR_diag"]), _ptr(o["GR_upper"]), _ptr(o.get("GR_lower")),
+                                        _ptr(o["GL_diag"]), _ptr(o["GL_upper"]), _ptr(o.get("GG_diag")),
+                                        _ptr(o.get("GG_upper")), _ptr(info), _ptr(self._qws), self._qws.numel(),
+                                        _ptr(buf), buf.numel(), _stream()), "negf_plan_run_queue")
+        return results
 
     def outputs(self, greater=False, lower=True):
         return _rgf_outputs(self.problems, True, greater, lower)

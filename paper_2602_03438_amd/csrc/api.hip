@@ -530,6 +530,9 @@ struct negf_plan {
   Outs cap_outs{};
   void* cap_ws = nullptr;
   unsigned long long* cap_stamps = nullptr;
+  // the point queue's per-stream round graphs and the arguments they were captured with
+  std::vector<void*> qgraphs;
+  std::vector<const void*> qkey;
 };
 
 namespace {
@@ -589,6 +592,81 @@ hipError_t enqueue_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long 
 void destroy_graphs(negf_plan* P) {
   for (void* g : P->graphs) rt_graph_destroy(g);
   P->graphs.clear();
+}
+
+void destroy_queue_graphs(negf_plan* P) {
+  for (void* g : P->qgraphs) rt_graph_destroy(g);
+  P->qgraphs.clear();
+  P->qkey.clear();
+}
+
+// ---- point queue: task lists streamed through the plan's chunks (see negf_plan_run_queue)
+
+struct QueueArgs {
+  const double* const* task_E;   // per problem, device
+  const int32_t* n_tasks;        // per problem, host
+  std::vector<long> task_off;    // per problem: offset of its tasks in the result arrays
+  int32_t* task_info;
+  double* task_dos;
+  unsigned long long* task_stamps;
+  int* rounds;                   // per segment (device)
+  int* slot_task;                // per point (device)
+};
+
+size_t queue_segments(const negf_plan* P) {
+  size_t n = 0;
+  for (const Chunk& c : P->chunks) n += c.segs.size();
+  return n;
+}
+
+// Rounds a worker stream runs: the most any segment of its chunks needs.
+int stream_rounds(const negf_plan* P, int si, const int32_t* n_tasks) {
+  int r = 0;
+  for (size_t c = 0; c < P->chunks.size(); ++c) {
+    if (P->stream_of[c] != si) continue;
+    for (const Seg& g : P->chunks[c].segs) {
+      const int q = (int)(g.pr - P->probs.data());
+      const int nq = g.pr->n_e;
+      r = std::max(r, (int)((n_tasks[q] + nq - 1) / nq));
+    }
+  }
+  return r;
+}
+
+// One round of worker stream si: for each of its chunks (in run order) the task intake of its
+// segments, the chunk, and the results of its segments.
+hipError_t enqueue_queue_round(negf_plan* P, int si, const Outs& outs, char* ws, const QueueArgs& qa) {
+  size_t seg_base = 0;
+  std::vector<size_t> first_seg(P->chunks.size());
+  for (size_t c = 0; c < P->chunks.size(); ++c) {
+    first_seg[c] = seg_base;
+    seg_base += P->chunks[c].segs.size();
+  }
+  for (size_t k = 0; k < P->run_order.size(); ++k) {
+    const size_t c = P->run_order[k];
+    if (P->stream_of[c] != si) continue;
+    const Chunk& ch = P->chunks[c];
+    hipStream_t st = P->streams[si];
+    hipError_t e = hipSuccess;
+    for (size_t j = 0; j < ch.segs.size() && e == hipSuccess; ++j) {
+      const Seg& g = ch.segs[j];
+      const int q = (int)(g.pr - P->probs.data());
+      const long p0 = ch.first_point + g.off;
+      e = launch_queue_pop(const_cast<double*>(g.pr->energies), g.e0, g.n, g.pr->n_e, qa.task_E[q], qa.n_tasks[q],
+                           qa.rounds + first_seg[c] + j, qa.slot_task + p0, outs.info + p0, st);
+    }
+    if (e == hipSuccess) e = enqueue_chunk(P, c, outs, ws, nullptr);
+    for (size_t j = 0; j < ch.segs.size() && e == hipSuccess; ++j) {
+      const Seg& g = ch.segs[j];
+      const int q = (int)(g.pr - P->probs.data());
+      const long p0 = ch.first_point + g.off;
+      const double2* GRd = outs.GRd + ch.out_diag_off + (size_t)g.off * ch.nb * ch.b * ch.b;
+      e = launch_queue_finish(GRd, ch.nb, ch.b, g.n, qa.slot_task + p0, outs.info + p0, qa.task_info + qa.task_off[q],
+                              qa.task_dos + qa.task_off[q], qa.task_stamps + qa.task_off[q], st);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Capture each worker stream's chunks into its own graph; a begun capture is always ended.
@@ -738,9 +816,114 @@ negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag,
   return to_status(e);
 }
 
+size_t negf_plan_queue_bytes(const negf_plan* plan) {
+  if (!plan) return 0;
+  const size_t a = (queue_segments(plan) * sizeof(int) + 255) & ~(size_t)255;
+  const size_t b = ((size_t)count_points(plan->probs.data(), (int)plan->probs.size()) * sizeof(int) + 255) &
+                   ~(size_t)255;
+  return a + b + 256;
+}
+
+negf_status negf_plan_run_queue(negf_plan* plan, int32_t use_graph, const double* const* task_E,
+                                const int32_t* n_tasks, int32_t* task_info, double* task_dos, uint64_t* task_stamps,
+                                uint64_t* start_stamp, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag,
+                                void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info, void* queue_ws,
+                                size_t queue_bytes, void* workspace, size_t ws_bytes, void* stream) {
+  if (!plan || !task_E || !n_tasks || !GR_diag || !GR_upper || !GL_diag || !GL_upper || !info || !workspace ||
+      !queue_ws)
+    return NEGF_EINVAL;
+  if ((GG_diag == nullptr) != (GG_upper == nullptr)) return NEGF_EINVAL;
+  const void* ps[] = {GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper};
+  for (const void* p : ps)
+    if (p && ((uintptr_t)p & 15)) return NEGF_EINVAL;
+  if (ws_bytes < negf_plan_workspace_bytes(plan) || queue_bytes < negf_plan_queue_bytes(plan)) return NEGF_EINVAL;
+  negf_plan* P = plan;
+  const int np = (int)P->probs.size();
+  long total = 0;
+  QueueArgs qa;
+  qa.task_E = task_E;
+  qa.n_tasks = n_tasks;
+  for (int q = 0; q < np; ++q) {
+    if (n_tasks[q] < 0 || (n_tasks[q] > 0 && !task_E[q])) return NEGF_EINVAL;
+    qa.task_off.push_back(total);
+    total += n_tasks[q];
+  }
+  if (total > 0 && (!task_info || !task_dos || !task_stamps)) return NEGF_EINVAL;
+  qa.task_info = task_info;
+  qa.task_dos = task_dos;
+  qa.task_stamps = (unsigned long long*)task_stamps;
+  char* qws = align256(queue_ws);
+  qa.rounds = (int*)qws;
+  qa.slot_task = (int*)(qws + ((queue_segments(P) * sizeof(int) + 255) & ~(size_t)255));
+  hipStream_t main = (hipStream_t)stream;
+  if (P->streams.empty()) {
+    for (int i = 0; i < P->n_streams; ++i) {
+      hipStream_t st = nullptr;
+      if (rt_stream_create(&st) != hipSuccess) return NEGF_EHIP;
+      P->streams.push_back(st);
+    }
+    for (int i = 0; i < 2 * P->n_streams; ++i) {
+      hipEvent_t ev = nullptr;
+      if (rt_event_create(&ev) != hipSuccess) return NEGF_EHIP;
+      P->events.push_back(ev);
+    }
+  }
+  Outs outs{(double2*)GR_diag, (double2*)GR_upper, (double2*)GR_lower, (double2*)GL_diag, (double2*)GL_upper,
+            (double2*)GG_diag, (double2*)GG_upper, info, nullptr};
+  char* ws = align256(workspace);
+  // start: round counters to zero, the start stamp, then the fork to the workers
+  hipError_t e = launch_fill_int((int)queue_segments(P), qa.rounds, 0, main);
+  if (e == hipSuccess && start_stamp) e = launch_stamp((unsigned long long*)start_stamp, main);
+  for (int i = 0; i < P->n_streams && e == hipSuccess; ++i) e = rt_record_wait(P->events[i], main, P->streams[i]);
+  if (e != hipSuccess) return to_status(e);
+  std::vector<int> rounds(P->n_streams);
+  int max_rounds = 0;
+  for (int si = 0; si < P->n_streams; ++si) max_rounds = std::max(max_rounds, rounds[si] = stream_rounds(P, si, n_tasks));
+  if (use_graph) {
+    std::vector<const void*> key = {GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper, info,
+                                    ws, qws, task_info, task_dos, task_stamps};
+    for (int q = 0; q < np; ++q) {
+      key.push_back(task_E[q]);
+      key.push_back((const void*)(intptr_t)n_tasks[q]);
+    }
+    if (P->qkey != key || (int)P->qgraphs.size() != P->n_streams) {
+      destroy_queue_graphs(P);
+      for (int si = 0; si < P->n_streams && e == hipSuccess; ++si) {
+        e = rt_capture_begin(P->streams[si]);
+        if (e != hipSuccess) break;
+        hipError_t ec = enqueue_queue_round(P, si, outs, ws, qa);
+        void* exec = nullptr;
+        const hipError_t e2 = rt_capture_end(P->streams[si], &exec);
+        if (ec != hipSuccess || e2 != hipSuccess) {
+          if (exec) rt_graph_destroy(exec);
+          e = ec != hipSuccess ? ec : e2;
+          break;
+        }
+        P->qgraphs.push_back(exec);
+      }
+      if (e != hipSuccess) {
+        destroy_queue_graphs(P);
+        enqueue_join(P, main);
+        return NEGF_EHIP;
+      }
+      P->qkey = key;
+    }
+    for (int r = 0; r < max_rounds && e == hipSuccess; ++r)
+      for (int si = 0; si < P->n_streams && e == hipSuccess; ++si)
+        if (r < rounds[si]) e = rt_graph_launch(P->qgraphs[si], P->streams[si]);
+  } else {
+    for (int r = 0; r < max_rounds && e == hipSuccess; ++r)
+      for (int si = 0; si < P->n_streams && e == hipSuccess; ++si)
+        if (r < rounds[si]) e = enqueue_queue_round(P, si, outs, ws, qa);
+  }
+  if (e == hipSuccess) e = enqueue_join(P, main);
+  return to_status(e);
+}
+
 void negf_plan_destroy(negf_plan* plan) {
   if (!plan) return;
   destroy_graphs(plan);
+  destroy_queue_graphs(plan);
   for (hipEvent_t e : plan->events) rt_event_destroy(e);
   for (hipStream_t s : plan->streams) rt_stream_destroy(s);
   delete plan;

@@ -309,6 +309,59 @@ __global__ void stamp_kernel(unsigned long long* dst) {
   if (threadIdx.x == 0) *dst = wall_clock64();
 }
 
+// One round of a point queue for one chunk segment (slots [e0, e0 + n) of a problem with n_slots
+// slots): slot e0 + i takes task r n_slots + e0 + i of the task list (r = the segment's round
+// counter), or none past its end (its energy is left as it was and its task index is -1); the
+// slots' info is cleared for the round and the counter advanced.  One workgroup.
+__global__ void queue_pop_kernel(double* energies, int e0, int n, int n_slots, const double* task_E, int n_tasks,
+                                 int* round, int* slot_task, int* info) {
+  __shared__ int r;
+  if (threadIdx.x == 0) r = *round;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const long t = (long)r * n_slots + e0 + i;
+    if (t < n_tasks) {
+      energies[e0 + i] = task_E[t];
+      slot_task[i] = (int)t;
+    } else {
+      slot_task[i] = -1;
+    }
+    info[i] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *round = r + 1;
+}
+
+// Results of one round for one chunk segment: workgroup i takes slot i; if it held a task t, then
+// task_info[t] = info[i], task_dos[t] = -Im sum_blocks Tr G^R_kk / pi and task_stamp[t] = the wall
+// clock now.
+constexpr int QF = 256;
+__global__ void __launch_bounds__(QF) queue_finish_kernel(const double2* GRd, int nb, int b, const int* slot_task,
+                                                          const int* info, int* task_info, double* task_dos,
+                                                          unsigned long long* task_stamp) {
+  const int i = blockIdx.x;
+  const int t = slot_task[i];
+  if (t < 0) return;
+  const double2* g = GRd + (long)i * nb * b * b;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nb * b; k += QF) {
+    const int blk = k / b, j = k - blk * b;
+    acc += g[(long)blk * b * b + (long)j * b + j].y;
+  }
+  __shared__ double red[QF];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = QF / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    task_info[t] = info[i];
+    task_dos[t] = -red[0] / M_PI;
+    task_stamp[t] = wall_clock64();
+  }
+}
+
 __global__ void fill_int_kernel(int n, int* p, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -439,6 +492,22 @@ hipError_t launch_closure_accept(int np, const double* r2, const double* m2, con
 
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s) {
   hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, s, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_pop(double* energies, int e0, int n, int n_slots, const double* task_E, int n_tasks,
+                            int* round, int* slot_task, int* info, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(queue_pop_kernel, dim3(1), dim3(256), 0, s, energies, e0, n, n_slots, task_E, n_tasks, round,
+                     slot_task, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_finish(const double2* GRd, int nb, int b, int n, const int* slot_task, const int* info,
+                               int* task_info, double* task_dos, unsigned long long* task_stamp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(queue_finish_kernel, dim3(n), dim3(QF), 0, s, GRd, nb, b, slot_task, info, task_info, task_dos,
+                     task_stamp);
   return hipGetLastError();
 }
 

@@ -172,6 +172,12 @@ hipError_t rt_graph_destroy(void* exec);
 double rt_wallclock_hz();
 // *dst = device wall clock (constant-rate counter) when the stream reaches this point
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
+// point queue: one round's task intake and results for one chunk segment (slots [e0, e0 + n) of a
+// problem with n_slots slots; slot_task, info and GRd start at the segment's first slot)
+hipError_t launch_queue_pop(double* energies, int e0, int n, int n_slots, const double* task_E, int n_tasks,
+                            int* round, int* slot_task, int* info, hipStream_t s);
+hipError_t launch_queue_finish(const double2* GRd, int nb, int b, int n, const int* slot_task, const int* info,
+                               int* task_info, double* task_dos, unsigned long long* task_stamp, hipStream_t s);
 enum KernelClass { KC_GEMM64 = 0, KC_GEMM32 = 1, KC_INV_PANEL = 2, KC_INV_SWAP = 3, KC_INV_PERM = 4, KC_ELEM = 5,
                    KC_INV_GEMM = 6, KC_GEMM_CPL = 7, KC_COUNT = 8 };
 void prof_begin(int cls, hipStream_t s);

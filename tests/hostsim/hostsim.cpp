@@ -412,6 +412,38 @@ hipError_t launch_stamp(unsigned long long* dst, hipStream_t) {
   return hipSuccess;
 }
 
+hipError_t launch_queue_pop(double* energies, int e0, int n, int n_slots, const double* task_E, int n_tasks,
+                            int* round, int* slot_task, int* info, hipStream_t) {
+  const int r = *round;
+  for (int i = 0; i < n; ++i) {
+    const long t = (long)r * n_slots + e0 + i;
+    if (t < n_tasks) {
+      energies[e0 + i] = task_E[t];
+      slot_task[i] = (int)t;
+    } else {
+      slot_task[i] = -1;
+    }
+    info[i] = 0;
+  }
+  *round = r + 1;
+  return hipSuccess;
+}
+
+hipError_t launch_queue_finish(const double2* GRd, int nb, int b, int n, const int* slot_task, const int* info,
+                               int* task_info, double* task_dos, unsigned long long* task_stamp, hipStream_t s) {
+  for (int i = 0; i < n; ++i) {
+    const int t = slot_task[i];
+    if (t < 0) continue;
+    const double2* g = GRd + (long)i * nb * b * b;
+    double acc = 0.0;
+    for (int k = 0; k < nb * b; ++k) acc += g[(long)(k / b) * b * b + (long)(k % b) * b + (k % b)].y;
+    task_info[t] = info[i];
+    task_dos[t] = -acc / M_PI;
+    launch_stamp(task_stamp + t, s);
+  }
+  return hipSuccess;
+}
+
 void prof_begin(int, hipStream_t) {}
 void prof_end(int, hipStream_t, double, double) {}
 

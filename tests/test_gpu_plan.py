@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as w
-from helpers import well_posed
+from helpers import record, refined_inversions, well_posed, SPREAD_FACTOR
 from oracle import leads as oleads
 from oracle import rgf as orgf
 
@@ -173,3 +173,74 @@ def test_learned_initialiser_end_to_end(nb):
     assert torch.all(seeded["iters"] <= plain["iters"])
     print(f"mean steps plain {plain['iters'].float().mean().item():.2f}, "
           f"seeded {seeded['iters'].float().mean().item():.2f}")
+
+
+def _dos(GRd):
+    """-Im sum_k Tr G^R_kk / pi per point of a [points, nb, b, b] tensor."""
+    import torch
+    return (-torch.diagonal(GRd, dim1=-2, dim2=-1).imag.sum(dim=(-1, -2)) / np.pi).cpu().numpy()
+
+
+def test_point_queue_eager_graph_and_direct_call(nb):
+    """negf_plan_run_queue: three problems (the first two share a chunk) with 7, 5
+    and 4 tasks over 3, 2 and 4 slots (partial last rounds), two worker streams.
+    Eager and graph-replayed runs give bit-identical task results (the same
+    kernels on the same batches), a second graph run replays the cached graphs
+    from fresh round counters, every task is stamped after the start, and each
+    task's density of states matches a direct call on all task energies and,
+    at sampled tasks, the oracle."""
+    import torch
+    devs = [w.slab_device(4, 40, 31), w.slab_device(4, 40, 35), w.slab_device(3, 72, 32)]
+    tasks = [well_posed(d, np.linspace(-1.2, 1.2, 15))[:k] for d, k in zip(devs, (7, 5, 4))]
+    assert [t.size for t in tasks] == [7, 5, 4]
+    slots = (3, 2, 4)
+    probs = [nb.Problem(nb.DeviceOnGPU(d), np.zeros(n), eta=1e-8, mu_l=0.1, mu_r=-0.1) for d, n in zip(devs, slots)]
+    plan = nb.Plan(probs, nb.PLAIN_FP64, opts=nb.make_options(sr_max_iter=40), n_streams=2)
+    assert len(plan.chunks()) == 2
+    outs = plan.outputs()
+    info = torch.zeros(sum(slots), dtype=torch.int32, device="cuda")
+    tE = [torch.from_numpy(t).cuda() for t in tasks]
+    res_e = plan.run_queue(tE, outs, info, use_graph=False)
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in res_e.items()}
+    for rep in range(2):
+        res = {k: torch.zeros_like(v) for k, v in eager.items()}
+        x = torch.randn(128, 128, dtype=torch.float64, device="cuda")
+        (x @ x).sum().item()
+        plan.run_queue(tE, outs, info, use_graph=True, results=res)
+        torch.cuda.synchronize()
+        assert torch.equal(res["info"], eager["info"]), rep
+        assert torch.equal(res["dos"], eager["dos"]), rep
+        st = res["stamps"].cpu().numpy()
+        assert np.all(st > res["start"].item()), rep
+    plan.close()
+    assert np.all(eager["info"].cpu().numpy() == 0)
+    # a direct call on every task energy (other batches: equal up to rounding)
+    direct = [nb.Problem(nb.DeviceOnGPU(d), t, eta=1e-8, mu_l=0.1, mu_r=-0.1) for d, t in zip(devs, tasks)]
+    ref = nb.rgf_lesser_greater(direct, nb.PLAIN_FP64, opts=nb.make_options(sr_max_iter=40))
+    dos_q = eager["dos"].cpu().numpy()
+    off = 0
+    for q, t in enumerate(tasks):
+        dos_d = _dos(ref["GR_diag"][q])
+        np.testing.assert_allclose(dos_q[off:off + t.size], dos_d, rtol=1e-10, atol=0)
+        # the oracle at the first two tasks of the list where it is stable to the plain bar (its DOS
+        # moves by at most 2.5e-11 when its inversions are refined)
+        stable = 0
+        for i in range(t.size):
+            def dos_oracle():
+                o = orgf.solve_point(devs[q], float(t[i]), 1e-8, 0.1, -0.1, 0.025, lesser_greater=False)
+                return -np.imag(sum(np.trace(g) for g in o.GR_diag)) / np.pi
+            dos_o = dos_oracle()
+            with refined_inversions():
+                spread = abs(dos_oracle() - dos_o) / abs(dos_o)
+            if SPREAD_FACTOR * spread > 1e-10:
+                continue
+            err = abs(dos_q[off + i] - dos_o) / abs(dos_o)
+            record("point_queue_dos", t[i], "dos", err, 1e-10, spread, None, problem=q)
+            print(f"  queue problem {q} E={t[i]:+.4f}: DOS error {err:.2e} (oracle spread {spread:.1e})", flush=True)
+            assert err <= 1e-10, (q, i, dos_q[off + i], dos_o, spread)
+            stable += 1
+            if stable == 2:
+                break
+        assert stable >= 1, q
+        off += t.size

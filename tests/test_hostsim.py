@@ -275,3 +275,55 @@ def test_hostsim_plan_matches_plain_calls(sim):
         if run < 2:
             assert np.all(stamps[1:] > stamps[0])
     L.negf_plan_destroy(plan)
+
+
+def test_hostsim_point_queue_rounds_and_results(sim):
+    """negf_plan_run_queue (eager) on the CPU double: three problems of two shapes
+    (the first two share one chunk) with 7, 5 and 4 tasks over 3, 2 and 4 slots
+    (3, 3 and 1 rounds, partial last rounds), two worker streams.  Every task's density of states matches the
+    oracle's at its energy, info is clear, every task is stamped, and the task
+    counts are reached exactly (no task solved twice or skipped)."""
+    L, nb = sim
+    vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+    L.negf_plan_queue_bytes.argtypes = [vp]
+    L.negf_plan_queue_bytes.restype = sz
+    L.negf_plan_run_queue.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
+                                      sz, vp]
+    devs = [w.random_device(10, 8, 1), w.random_device(10, 8, 2), w.slab_device(6, 12, 7)]
+    slots = [3, 2, 4]
+    tasks = [np.linspace(-2.1, 2.2, 7), np.array([-1.3, -0.6, 0.1, 0.9, 1.4]), np.array([-2.5, -0.2, 0.8, 2.3])]
+    probs = [HostProblem(nb, d, np.zeros(n), eta=1e-6) for d, n in zip(devs, slots)]
+    arr = (nb.negf_problem * 3)(*[p.s for p in probs])
+    plan = C.c_void_p()
+    assert L.negf_plan_create(arr, 3, 0, None, None, 0, 2, C.byref(plan)) == 0
+    ws = np.zeros(L.negf_plan_workspace_bytes(plan) + 256, dtype=np.uint8)
+    qws = np.zeros(L.negf_plan_queue_bytes(plan) + 256, dtype=np.uint8)
+    nd = sum(p.n * p.nb * p.b * p.b for p in probs)
+    nu = sum(p.n * (p.nb - 1) * p.b * p.b for p in probs)
+    out = {k: np.zeros(nd if k.endswith("d") else nu, dtype=np.complex128) for k in ("GRd", "GRu", "GRl", "GLd", "GLu")}
+    info = np.zeros(sum(slots), dtype=np.int32)
+    tE = [np.ascontiguousarray(t) for t in tasks]
+    total = sum(t.size for t in tE)
+    t_info = np.full(total, -7, dtype=np.int32)
+    t_dos = np.zeros(total)
+    t_stamp = np.zeros(total, dtype=np.uint64)
+    start = np.zeros(1, dtype=np.uint64)
+    ptrs = (C.c_void_p * 3)(*[t.ctypes.data for t in tE])
+    counts = (C.c_int32 * 3)(*[t.size for t in tE])
+    d = lambda k: out[k].ctypes.data
+    code = L.negf_plan_run_queue(plan, 0, ptrs, counts, t_info.ctypes.data, t_dos.ctypes.data, t_stamp.ctypes.data,
+                                 start.ctypes.data, d("GRd"), d("GRu"), d("GRl"), d("GLd"), d("GLu"), None, None,
+                                 info.ctypes.data, qws.ctypes.data, qws.size, ws.ctypes.data, ws.size, None)
+    assert code == 0
+    L.negf_plan_destroy(plan)
+    assert np.all(t_info == 0), t_info
+    assert np.all(t_stamp > start[0]), (t_stamp, start)
+    off = 0
+    for dev, t in zip(devs, tE):
+        for i, E in enumerate(t):
+            ref = orgf.solve_point(dev, float(E), 1e-6, 0.1, -0.1, 0.025, lesser_greater=False)
+            dos_ref = -np.imag(sum(np.trace(g) for g in ref.GR_diag)) / np.pi
+            assert abs(t_dos[off + i] - dos_ref) <= 1e-9 * abs(dos_ref) + 1e-12, (E, t_dos[off + i], dos_ref)
+        off += t.size
+    # the last round's slots: problem 0 ran tasks 6 (slot 0) and nothing new in slots 1, 2
+    assert probs[0].E[0] == tE[0][6] and probs[0].E[1] == tE[0][4] and probs[0].E[2] == tE[0][5]
