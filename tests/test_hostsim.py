@@ -26,7 +26,7 @@ def sim():
     spec = importlib.util.spec_from_file_location("hostsim_build", os.path.join(HERE, "hostsim", "build.py"))
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
-    path = mod.build()
+    path = mod.build(sanitize=os.environ.get("NEGF_HOSTSIM_SANITIZED") == "1")
     L = C.CDLL(path)
     P = C.POINTER
     vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t

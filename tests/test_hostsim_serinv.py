@@ -24,7 +24,7 @@ def sim():
     spec = importlib.util.spec_from_file_location("hostsim_build", os.path.join(HERE, "hostsim", "build.py"))
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
-    L = C.CDLL(mod.build())
+    L = C.CDLL(mod.build(sanitize=os.environ.get("NEGF_HOSTSIM_SANITIZED") == "1"))
     P = C.POINTER
     vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
     L.negf_serinv_workspace_bytes.argtypes = [P(nb.negf_problem), i32, i32]
