@@ -120,3 +120,62 @@ def test_static_entry_point_rejects_synchronously(L):
                                           None)
     assert st == nb.NEGF_ENOMEM          # 12 points in flight need ~283 MiB
     assert L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr2, 1, nb.PLAIN_FP64, None) > (256 << 20)
+
+
+def test_energy_convolution_and_transpose_reject_synchronously(L):
+    """negf_energy_convolution / negf_transpose: sizes, the FFT length limit, overlap,
+    alignment and workspace are checked before anything is enqueued; empty inputs
+    return OK without touching the GPU."""
+    from paper_2602_03438_amd import binding as nb
+    buf = np.zeros(64, dtype=np.complex128)
+    p = buf.ctypes.data
+    one = (C.c_double * 2)(1.0, 0.0)
+    assert L.negf_econv_workspace_bytes(1024, 1024) == 2048 * 16 + 256
+    assert L.negf_econv_workspace_bytes(5, 3) == 16 * 16 + 256          # L at least 16
+    assert L.negf_econv_workspace_bytes(3000, 1200) == 0                # n_e + n_w - 1 > 4096
+    assert L.negf_econv_workspace_bytes(0, 5) == 0
+    ws = L.negf_econv_workspace_bytes(8, 4)
+    G, W, B = p, p + 256, p + 512
+    ok_args = lambda **k: dict(dict(n_e=8, n_el=2, G=G, n_w=4, k0=1, W=W, scale=one, B=B, ws=p, ws_bytes=ws), **k)
+    call = lambda a: L.negf_energy_convolution(a["n_e"], a["n_el"], a["G"], a["n_w"], a["k0"], a["W"], a["scale"],
+                                               a["B"], a["ws"], a["ws_bytes"], None)
+    assert call(ok_args(n_el=0)) == nb.NEGF_OK                          # nothing to do
+    for bad in (dict(n_e=0), dict(n_w=0), dict(k0=4), dict(k0=-1), dict(n_el=-1), dict(B=G), dict(B=W),
+                dict(G=G + 8), dict(ws_bytes=ws - 1), dict(ws=None), dict(scale=None), dict(n_el=1 << 31),
+                dict(n_e=3000, n_w=1200, k0=0)):
+        assert call(ok_args(**bad)) == nb.NEGF_EINVAL, bad
+    assert L.negf_transpose(0, 5, p, p + 256, None) == nb.NEGF_OK
+    assert L.negf_transpose(-1, 5, p, p + 256, None) == nb.NEGF_EINVAL
+    assert L.negf_transpose(3, 5, p, p, None) == nb.NEGF_EINVAL
+    assert L.negf_transpose(3, 5, p + 8, p + 256, None) == nb.NEGF_EINVAL
+
+
+def test_partitioned_inversion_layout_and_rejects(L):
+    """negf_serinv_workspace_bytes is 0 for a partition count the block count cannot
+    hold (fewer than 2 partitions, periods below 3 blocks, an empty last partition),
+    and the call rejects those layouts and missing outputs synchronously."""
+    from paper_2602_03438_amd import binding as nb
+    pr, keep = _fake_problem(nb_=14, b=8, n_e=2)
+    arr = (nb.negf_problem * 1)(pr)
+    for parts, ok in ((1, False), (2, True), (3, True), (4, True), (5, True), (6, False), (14, False)):
+        n = L.negf_serinv_workspace_bytes(arr, parts, 0)
+        assert (n > 0) == ok, (parts, n)
+    assert L.negf_serinv_workspace_bytes(arr, 3, 1) > L.negf_serinv_workspace_bytes(arr, 3, 0)
+    p = keep.ctypes.data
+    ws = L.negf_serinv_workspace_bytes(arr, 3, 0)
+    info = np.zeros(2, dtype=np.int32).ctypes.data
+    call = lambda parts, grd=p, wsb=ws, inf=info: L.negf_serinv_lesser_greater(
+        arr, parts, None, grd, p, p, p, p, None, None, inf, p, wsb, None)
+    assert call(1) == nb.NEGF_EINVAL
+    assert call(6) == nb.NEGF_EINVAL
+    assert call(3, grd=None) == nb.NEGF_EINVAL
+    assert call(3, inf=None) == nb.NEGF_EINVAL
+    assert call(3, wsb=ws - 1) == nb.NEGF_EINVAL
+
+
+def test_point_queue_rejects_synchronously(L):
+    from paper_2602_03438_amd import binding as nb
+    assert L.negf_plan_queue_bytes(None) == 0
+    p = np.zeros(8, dtype=np.complex128).ctypes.data
+    assert L.negf_plan_run_queue(None, 0, None, None, None, None, None, None, p, p, p, p, p, None, None, p, p, 1024,
+                                 p, 1024, None) == nb.NEGF_EINVAL
