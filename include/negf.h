@@ -322,7 +322,8 @@ void negf_plan_destroy(negf_plan* plan);
  * queue_ws: caller-owned device memory of negf_plan_queue_bytes(plan) bytes
  * (round counters, the slots' current tasks).  The outputs hold the last round's
  * points.  Enqueued only (no host synchronisation); the caller synchronises
- * `stream` before reading results.  Errors: EINVAL (arguments), EHIP. */
+ * `stream` before reading results.  Errors: EINVAL (arguments, including tasks
+ * for a problem with no slots), EHIP. */
 size_t negf_plan_queue_bytes(const negf_plan* plan);
 negf_status negf_plan_run_queue(negf_plan* plan, int32_t use_graph, const double* const* task_E,
                                 const int32_t* n_tasks, int32_t* task_info, double* task_dos, uint64_t* task_stamps,

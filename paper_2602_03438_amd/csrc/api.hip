@@ -844,7 +844,8 @@ negf_status negf_plan_run_queue(negf_plan* plan, int32_t use_graph, const double
   qa.task_E = task_E;
   qa.n_tasks = n_tasks;
   for (int q = 0; q < np; ++q) {
-    if (n_tasks[q] < 0 || (n_tasks[q] > 0 && !task_E[q])) return NEGF_EINVAL;
+    // a problem without slots cannot take tasks
+    if (n_tasks[q] < 0 || (n_tasks[q] > 0 && (!task_E[q] || P->probs[q].n_e < 1))) return NEGF_EINVAL;
     qa.task_off.push_back(total);
     total += n_tasks[q];
   }
