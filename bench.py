@@ -43,6 +43,21 @@ def energy_batches(P):
     return [grid[j::stride][:P] for j in range(stride)]
 
 
+def point_flops(nb, b, steps=28):
+    """Algorithmic flops of one energy point of G^R + G^< by the dense count (one complex
+    product or inversion of b x b blocks = 8 b^3): G^R (8 + 56 (nb - 1)) b^3, G^< (16 + 64 (nb - 1)) b^3,
+    both leads 2 (56 steps + 24) b^3 with `steps` decimation steps."""
+    return float(b) ** 3 * ((8 + 56 * (nb - 1)) + (16 + 64 * (nb - 1)) + 2 * (56 * steps + 24))
+
+
+def algorithmic_roofline(flops, seconds, note):
+    """The dense algorithmic rate of a whole run against the FP64 matrix peak (the executed work
+    differs: three real products per complex one, zero coupling slabs skipped, refinement products)."""
+    r = flops / seconds
+    return {"bound": "mfma", "achieved": r / 1e12, "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+            "frac": r / PEAK["f64"], "traffic": None, "flop_count": "dense algorithmic: " + note}
+
+
 def kernel_hash(source="gemm.hip"):
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2602_03438_amd", "csrc", source), "rb") as fh:
@@ -573,7 +588,10 @@ def bench_serinv(args):
             "config": {"workload": "nano-ribbon-like slab device Nb=60 b=512 with scattering self-energies (norm 0.01), "
                                    "eta=1e-8, 1..8 energies per call",
                        "real_products_per_complex_product": args.cmul, "sr_max_iter": args.sr_max_iter},
-            "cases": res}
+            "cases": res,
+            "roofline": algorithmic_roofline(point_flops(NB, B), 1.0 / best.get(1),
+                                             "G^R + G^< of one energy point per call (both leads, 28 decimation steps), "
+                                             "best partitioned case")}
     print(json.dumps(line), flush=True)
 
 
@@ -794,6 +812,11 @@ def bench_uneven_queue(args):
                        "slots_per_device_k": slots, "rounds": rounds, "queue_calls": parts, "chunks": len(chunks),
                        "streams": args.streams, "tunings": tunings,
                        "real_products_per_complex_product": args.cmul},
+            "roofline": algorithmic_roofline(sum(point_flops(nbk, b) * tasks[q].size
+                                                 for q, (d, ki, dk, g) in enumerate(devs)
+                                                 for (b, nbk) in [w.DEVICE_MIX[d]]), dt,
+                                             "G^R + G^< of every task at its device's (Nb, b), 28 decimation steps; "
+                                             "single-precision products of the refined form counted like double"),
             "gpu_seconds_start_to_last": float(t_done.max()), "host_enqueue_s": t_enq,
             "stamped_tasks": int(np.count_nonzero(st)),
             "info_nonzero": int(np.count_nonzero(tinfo)),
