@@ -381,3 +381,29 @@ def test_fp32_refine_meets_bar_and_norefine_does_not(nb):
         _cmp_point(refd, k, ref, names, CHOSEN_TOL, "chosen_fp32_refine", spread, kappa)
         e_nor = rel(nor["GR_diag"][0][k].cpu().numpy(), ref.GR_diag)
         assert 1e-9 < e_nor < 1e-2
+
+
+def test_two_block_device_and_exact_zero_greater(nb):
+    """The smallest device the leads allow (Nb = 2: both leads take their cells
+    from its two blocks) at energies where the oracle is stable to the plain bar,
+    every output kind and the transmission.  At E = -1.3 the greater occupation
+    1 - f underflows to exactly 0 in double precision ((E - mu) / kT = -56), so
+    Sigma^> and G^> vanish identically: the GPU must return exact zeros there
+    (a relative error is undefined)."""
+    dev = w.slab_device(2, 40, 9)
+    energies = np.array([-1.3, 0.0, 0.7, 1.0])
+    prob = nb.Problem(nb.DeviceOnGPU(dev), energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025)
+    out = nb.rgf_lesser_greater([prob], greater=True)
+    assert np.all(out["info"].cpu().numpy() == 0)
+    T = nb.transmission([prob])["T"].cpu().numpy()
+    for k, E in enumerate(energies):
+        names = LG_NAMES if k > 0 else LG_NAMES[:5]
+        ref, spread, kappa = _plain(dev, E, names, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025, greater=True,
+                                    want_T=True)
+        _cmp_point(out, k, ref, names, PLAIN_TOL, "two_block_device", spread, kappa)
+        e_t = abs(T[k] - ref.T) / abs(ref.T)
+        record("two_block_device", E, "T", e_t, PLAIN_TOL)
+        assert e_t <= PLAIN_TOL, (E, T[k], ref.T)
+        if k == 0:
+            assert float(out["GG_diag"][0][0].abs().max()) == 0.0
+            assert float(out["GG_upper"][0][0].abs().max()) == 0.0
