@@ -590,12 +590,12 @@ hipError_t enqueue_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long 
 }
 
 void destroy_graphs(negf_plan* P) {
-  for (void* g : P->graphs) rt_graph_destroy(g);
+  for (void* g : P->graphs) (void)rt_graph_destroy(g);
   P->graphs.clear();
 }
 
 void destroy_queue_graphs(negf_plan* P) {
-  for (void* g : P->qgraphs) rt_graph_destroy(g);
+  for (void* g : P->qgraphs) (void)rt_graph_destroy(g);
   P->qgraphs.clear();
   P->qkey.clear();
 }
@@ -680,7 +680,7 @@ hipError_t capture_plan(negf_plan* P, const Outs& outs, char* ws, unsigned long 
     void* exec = nullptr;
     const hipError_t e2 = rt_capture_end(P->streams[si], &exec);
     if (e != hipSuccess || e2 != hipSuccess) {
-      if (exec) rt_graph_destroy(exec);
+      if (exec) (void)rt_graph_destroy(exec);
       destroy_graphs(P);
       return e != hipSuccess ? e : e2;
     }
@@ -804,7 +804,7 @@ negf_status negf_plan_execute(negf_plan* plan, int32_t use_graph, void* GR_diag,
   if (e == hipSuccess && !reuse) {
     // captured after the fork was enqueued: capture records, it does not run anything
     if (capture_plan(P, outs, ws, stp) != hipSuccess) {
-      enqueue_join(P, main);
+      (void)enqueue_join(P, main);   // the capture failed; the join keeps the streams ordered
       return NEGF_EHIP;
     }
     P->cap_outs = outs;
@@ -896,7 +896,7 @@ negf_status negf_plan_run_queue(negf_plan* plan, int32_t use_graph, const double
         void* exec = nullptr;
         const hipError_t e2 = rt_capture_end(P->streams[si], &exec);
         if (ec != hipSuccess || e2 != hipSuccess) {
-          if (exec) rt_graph_destroy(exec);
+          if (exec) (void)rt_graph_destroy(exec);
           e = ec != hipSuccess ? ec : e2;
           break;
         }
@@ -904,7 +904,7 @@ negf_status negf_plan_run_queue(negf_plan* plan, int32_t use_graph, const double
       }
       if (e != hipSuccess) {
         destroy_queue_graphs(P);
-        enqueue_join(P, main);
+        (void)enqueue_join(P, main);   // the capture failed; the join keeps the streams ordered
         return NEGF_EHIP;
       }
       P->qkey = key;
@@ -925,8 +925,8 @@ void negf_plan_destroy(negf_plan* plan) {
   if (!plan) return;
   destroy_graphs(plan);
   destroy_queue_graphs(plan);
-  for (hipEvent_t e : plan->events) rt_event_destroy(e);
-  for (hipStream_t s : plan->streams) rt_stream_destroy(s);
+  for (hipEvent_t e : plan->events) (void)rt_event_destroy(e);
+  for (hipStream_t s : plan->streams) (void)rt_stream_destroy(s);
   delete plan;
 }
 

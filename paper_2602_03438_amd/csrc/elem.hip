@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(QF) queue_finish_kernel(const double2* GRd, in
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = QF / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {

@@ -57,7 +57,7 @@ void prof_begin(int cls, hipStream_t s) {
   if (!g_prof_on || g_capturing || cls < 0 || cls >= KC_COUNT || !((g_prof_mask >> cls) & 1u)) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   t_open = pool_get();
-  if (t_open) hipEventRecord(t_open, s);
+  if (t_open) (void)hipEventRecord(t_open, s);   // a failed record shows up when the pair is read
 }
 
 void prof_end(int cls, hipStream_t s, double flops, double bytes) {
@@ -65,7 +65,7 @@ void prof_end(int cls, hipStream_t s, double flops, double bytes) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = pool_get();
   if (!e) return;
-  hipEventRecord(e, s);
+  (void)hipEventRecord(e, s);
   g_prof_pending.push_back(ProfRec{t_open, e, cls, flops, bytes});
   t_open = nullptr;
 }
@@ -102,12 +102,12 @@ hipError_t rt_capture_end(hipStream_t s, void** exec) {
   hipGraph_t g = nullptr;
   hipError_t r = hipStreamEndCapture(s, &g);
   if (r != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return r;
   }
   hipGraphExec_t ex = nullptr;
   r = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (r != hipSuccess) return r;
   *exec = (void*)ex;
   return hipSuccess;
@@ -183,7 +183,7 @@ negf_status negf_profile_read(negf_kernel_stats* stats) {
         for (int j = 0; j < PROF_SLOTS; ++j) f += (double)c[(size_t)k * PROF_SLOTS + j];
         g_prof_acc[k].flops += f;
       }
-      hipMemset(g_prof_flops_ptr, 0, c.size() * sizeof(unsigned long long));
+      if (hipMemset(g_prof_flops_ptr, 0, c.size() * sizeof(unsigned long long)) != hipSuccess) st = NEGF_EHIP;
     }
   }
   if (stats)

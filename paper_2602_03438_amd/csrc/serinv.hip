@@ -264,7 +264,6 @@ struct Serinv {
   // ---------------------------------------------------------------- 2. reduced system
   void reduce() {
     const int np = L.npts, P = L.P, T = L.T, Q = L.Q;
-    const long bb = L.bb;
     // top boundaries s_p = p T - 1 (p >= 1): items [np, Q)
     {
       const int q0 = np, n = Q - np;
