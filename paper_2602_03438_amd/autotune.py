@@ -11,7 +11,13 @@ because only those tiles skip the zero slabs of a coupling-block operand).  Resu
 path in $NEGF_TUNE_CACHE); a block size with no entry gets the deterministic
 default (64x64 tiles, panel 16).
 
-    python -m paper_2602_03438_amd.autotune 128 256 384 512 640 768
+With --step it then times the whole hot path (both lead decimations and the
+G^R and G^< sweeps of one batched call) for the product tiles within 10 % of the
+fastest and both panel widths, on a random block-tridiagonal device of that
+block size, and keeps the fastest combination under op "step"; lookup() prefers
+that entry, so kernel timings in isolation only decide where no step was timed.
+
+    python -m paper_2602_03438_amd.autotune [--step] 128 256 384 512 640 768
 """
 from __future__ import annotations
 
@@ -58,6 +64,10 @@ def lookup(b: int, cmul: int = 4) -> dict:
         out["gemm_tile_f32"] = int(g32["best"])
     if inv:
         out["inv_nb"] = int(inv["best"])
+    step = c.get(key(b, "f64g" if cmul == 3 else "f64", "step"))
+    if step:
+        out["gemm_tile"] = int(step["best"]["gemm_tile"])
+        out["inv_nb"] = int(step["best"]["inv_nb"])
     return out
 
 
@@ -111,10 +121,71 @@ def tune_block(b: int, batch: int = 64, log=print) -> dict:
     return res
 
 
-def tune(blocks, batch=64, log=print, save=True) -> dict:
+def pick_step(times: dict):
+    """Fastest (tile, panel) of a step timing; as for the products, a 64 x 64 tile within TIE of it
+    is preferred (the tuner's device has dense couplings, where the other tiles lose nothing to
+    slab skipping)."""
+    best = min(times, key=times.get)
+    near = [k for k in times if k[0] in SLAB_TILES and times[k] <= times[best] * (1.0 + TIE)]
+    return min(near, key=times.get) if near else best
+
+
+def _step_device(b: int, nblocks: int, seed: int):
+    """A random block-tridiagonal device of block size b on the GPU: Hermitian on-site blocks,
+    couplings of norm about one, S = I (the tuner's own input, not a physical model)."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    X = torch.randn(nblocks, b, b, dtype=torch.complex128, device="cuda", generator=g)
+    Hd = (X + X.conj().transpose(-1, -2)) * (0.5 / b ** 0.5)
+    Hu = torch.randn(nblocks - 1, b, b, dtype=torch.complex128, device="cuda", generator=g) * (0.3 / b ** 0.5)
+    dev = nb.DeviceOnGPU.__new__(nb.DeviceOnGPU)
+    dev.nb, dev.b = nblocks, b
+    dev.H_diag, dev.H_upper = Hd.contiguous(), Hu.contiguous()
+    dev.S_diag = dev.S_upper = None
+    dev.sig_r = dev.sig_l = dev.sig_g = None
+    return dev
+
+
+def tune_step(b: int, cmul: int = 3, points: int = 32, nblocks: int = 8, log=print) -> dict:
+    """Time one batched G^R + G^< call (decimation of both leads included) for every
+    combination of the product tiles within 10 % of the fastest (from the kernel timings
+    in the cache) and the two panel widths."""
+    import numpy as np
+    import torch
+    c = load_cache()
+    dtype = "f64g" if cmul == 3 else "f64"
+    g = c.get(key(b, dtype, "zgemm"))
+    tiles = [1]
+    if g:
+        ms = {k: v for k, v in g["ms"].items()}
+        fastest = min(ms.values())
+        tiles = [t for t, name in TILES.items() if name in ms and ms[name] <= 1.10 * fastest]
+    dev = _step_device(b, nblocks, 7 + b)
+    prob = nb.Problem(dev, np.linspace(-0.9, 0.9, points), eta=1e-6)
+    ws = nb.Workspace()
+    times = {}
+    for tile in tiles:
+        for panel in (16, 32):
+            opts = nb.make_options(cmul=cmul, gemm_tile=tile, inv_nb=panel, sr_max_iter=40)
+            t = _time(lambda: nb.rgf_lesser_greater([prob], nb.PLAIN_FP64, opts=opts, ws=ws), reps=3)
+            times[(tile, panel)] = t
+            log(f"b={b} step ({nblocks} blocks, {points} points) tile {TILES[tile]} panel {panel}: "
+                f"{t * 1e3:.1f} ms ({points / t:.1f} points/s)")
+    best = pick_step(times)
+    return {key(b, dtype, "step"): {"best": {"gemm_tile": best[0], "inv_nb": best[1]},
+                                    "ms": {f"{TILES[k[0]]}/panel{k[1]}": v * 1e3 for k, v in times.items()},
+                                    "points": points, "blocks": nblocks}}
+
+
+def tune(blocks, batch=64, log=print, save=True, step=False) -> dict:
     cache = load_cache()
     for b in blocks:
         cache.update(tune_block(int(b), batch, log))
+        if step:
+            if save:
+                with open(cache_path(), "w") as f:
+                    json.dump(cache, f, indent=1, sort_keys=True)
+            cache.update(tune_step(int(b), log=log))
     if save:
         with open(cache_path(), "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
@@ -124,6 +195,6 @@ def tune(blocks, batch=64, log=print, save=True) -> dict:
 if __name__ == "__main__":
     import torch
     assert torch.cuda.is_available(), "the tuner runs on the GPU"
-    bs = [int(x) for x in sys.argv[1:]] or [512]
-    tune(bs, log=lambda m: print(m, flush=True))
+    bs = [int(x) for x in sys.argv[1:] if not x.startswith("--")] or [512]
+    tune(bs, log=lambda m: print(m, flush=True), step="--step" in sys.argv)
     print("wrote", cache_path())

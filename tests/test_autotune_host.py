@@ -32,4 +32,21 @@ def test_shipped_cache_is_valid():
     assert c, "the shipped tune_cache.json is empty or unreadable"
     for k, v in c.items():
         assert k.startswith(autotune.ARCH + "/b="), k
-        assert int(v["best"]) in (1, 2, 3, 4, 5, 16, 32), (k, v)
+        if k.endswith("/step"):
+            assert v["best"]["gemm_tile"] in (1, 2, 3, 4, 5) and v["best"]["inv_nb"] in (16, 32), (k, v)
+        else:
+            assert int(v["best"]) in (1, 2, 3, 4, 5, 16, 32), (k, v)
+
+
+def test_step_entry_overrides_kernel_timings(tmp_path, monkeypatch):
+    """A whole-step timing decides over the kernel timings in isolation (for the
+    complex-product form it was timed with)."""
+    p = tmp_path / "tune_cache.json"
+    p.write_text(json.dumps({autotune.key(640, "f64g", "zgemm"): {"best": 4},
+                             autotune.key(640, "f64", "zinv"): {"best": 16},
+                             autotune.key(640, "f64g", "step"): {"best": {"gemm_tile": 1, "inv_nb": 32}}}))
+    monkeypatch.setenv("NEGF_TUNE_CACHE", str(p))
+    got = autotune.lookup(640, 3)
+    assert got["gemm_tile"] == 1 and got["inv_nb"] == 32
+    got4 = autotune.lookup(640, 4)            # no step (nor product) entry for the four-product form
+    assert got4["gemm_tile"] == autotune.DEFAULT["gemm_tile"] and got4["inv_nb"] == 16
