@@ -121,7 +121,10 @@ typedef struct negf_options {
   int32_t inv_nb;       /* panel width of the block inversion (16 or 32)          [16]  */
   int32_t xcd_remap;    /* 1: place the tiles of one matrix on one XCD            [1]   */
   int32_t gemm_tile;    /* product tile: 1 = 64x64, 2 = 128x64, 3 = 128x128,
-                           4 = 64x64 with 8 waves, 5 = 128x64 with 16 waves       [1]   */
+                           4 = 64x64 with 8 waves, 5 = 128x64 with 16 waves,
+                           6 = 32x32; a launch whose 64x64 tiles would number
+                           fewer than two per CU (a few points per call) runs
+                           on 32x32 tiles whatever is set here                   [1]   */
   int32_t gemm_tile_f32;/* tile of the single-precision products                  [1]   */
   int32_t cmul;         /* real products per complex double product: 4, or 3 by
                            Gauss's method (3/4 of the matrix-core work; error
@@ -341,7 +344,7 @@ negf_status negf_plan_run_queue(negf_plan* plan, int32_t use_graph, const double
  * declares the result anti-Hermitian (M == N): only its upper triangle is
  * computed and the strict lower triangle is set to -conj of the upper one.
  * tile: 0 default, 1 = 64x64, 2 = 128x64, 3 = 128x128, 4 = 64x64 (8 waves),
- * 5 = 128x64 (16 waves) output tiles.
+ * 5 = 128x64 (16 waves), 6 = 32x32 output tiles (taken as given here).
  * Returns NEGF_EINVAL for bad sizes. */
 negf_status negf_zgemm_batched(char opa, char opb, int32_t M, int32_t N, int32_t K, const double* alpha,
                                const void* A, int64_t lda, int64_t sa, const void* B, int64_t ldb, int64_t sb,

@@ -30,7 +30,7 @@ from . import binding as nb
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ARCH = "gfx950"
-TILES = {1: "64x64", 2: "128x64", 3: "128x128", 4: "64x64/8w", 5: "128x64/16w"}
+TILES = {1: "64x64", 2: "128x64", 3: "128x128", 4: "64x64/8w", 5: "128x64/16w", 6: "32x32"}
 DEFAULT = {"gemm_tile": 1, "gemm_tile_f32": 1, "inv_nb": 16}
 
 

@@ -451,6 +451,12 @@ typedef Cfg<128, 64, 4, 2> Cfg128x64;
 typedef Cfg<128, 128, 4, 2> Cfg128;
 typedef Cfg<64, 64, 4, 2> Cfg64w8;   // 8 waves of 16 x 32: fewer registers per wave, more waves per SIMD
 typedef Cfg<128, 64, 8, 2> Cfg128x64w16;   // 16 waves of 16 x 32
+typedef Cfg<32, 32, 2, 2> Cfg32;           // small batches: four times the workgroups of a 64 x 64 tile
+
+// A launch whose 64 x 64 tiles would give fewer workgroups than two per CU (a few energy points
+// per call: one b = 512 product is 64 tiles) is better off on 32 x 32 tiles, so that the whole chip
+// takes part; it gives up the zero-slab skipping of coupling operands (64 x 64 tiles only).
+constexpr long SMALL_LAUNCH_TILES = 512;
 
 template <typename T, typename CF, bool GAUSS, bool FULL>
 void launch_ops(const GemmDesc& d, const KArgs& ka, dim3 grid, hipStream_t s) {
@@ -504,6 +510,7 @@ template <typename T, bool GAUSS>
 hipError_t launch_t(const GemmDesc& d, const KArgs& ka, int tile, hipStream_t s) {
   if (GAUSS && tile == GEMM_TILE_128x128) tile = GEMM_TILE_128x64;
   switch (tile) {
+    case GEMM_TILE_32: return launch_cfg<T, Cfg32, GAUSS>(d, ka, s);
     case GEMM_TILE_128x64: return launch_cfg<T, Cfg128x64, GAUSS>(d, ka, s);
     case GEMM_TILE_64_8W: return launch_cfg<T, Cfg64w8, GAUSS>(d, ka, s);
     case GEMM_TILE_128x64_16W: return launch_cfg<T, Cfg128x64w16, GAUSS>(d, ka, s);
@@ -513,6 +520,15 @@ hipError_t launch_t(const GemmDesc& d, const KArgs& ka, int tile, hipStream_t s)
     default: return launch_cfg<T, Cfg64, GAUSS>(d, ka, s);
   }
 }
+
+}  // namespace
+
+int tile_for_launch(int tile, int M, int N, long batch) {
+  const long tiles64 = (long)((M + 63) / 64) * ((N + 63) / 64) * batch;
+  return (tiles64 < SMALL_LAUNCH_TILES && M >= 32 && N >= 32) ? GEMM_TILE_32 : tile;
+}
+
+namespace {
 
 // Strict lower triangle of each n x n item from its upper triangle,
 // C[r][c] = -conj(C[c][r]) for r > c: 32 x 32 tiles on or below the diagonal,

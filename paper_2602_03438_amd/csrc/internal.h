@@ -7,7 +7,7 @@ namespace negf {
 enum Op { OP_N = 0, OP_C = 1 };          // op(X) = X or X^H
 // Output tile shapes of the complex product kernel (see gemm.hip)
 enum { GEMM_TILE_DEFAULT = 0, GEMM_TILE_64 = 1, GEMM_TILE_128x64 = 2, GEMM_TILE_128x128 = 3, GEMM_TILE_64_8W = 4,
-       GEMM_TILE_128x64_16W = 5, GEMM_TILE_LAST = GEMM_TILE_128x64_16W };
+       GEMM_TILE_128x64_16W = 5, GEMM_TILE_32 = 6, GEMM_TILE_LAST = GEMM_TILE_32 };
 enum Prec { PREC_F64 = 0, PREC_F32 = 1 };  // arithmetic of the product
 
 // A batch of b x b (or M x K ...) complex matrices: item p starts at p * stride.
@@ -53,6 +53,9 @@ struct GemmDesc {
   int skip_lo, skip_hi;
 };
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
+// The tile a library launch of batch x (M x N) outputs uses: `tile`, or 32 x 32 when 64 x 64 tiles
+// would give fewer workgroups than two per CU (a few energy points per call).
+int tile_for_launch(int tile, int M, int N, long batch);
 
 // Zero-slab maps (see GemmDesc::kmask) of nblk b x b blocks T_i = x H_i + y S_i
 // for any x, y: a slab is marked when H_i or S_i (nullable) has a nonzero in

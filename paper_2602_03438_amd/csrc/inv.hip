@@ -525,7 +525,7 @@ hipError_t update_cols(const InvDesc& d, int n, int jb, int K, const double2* U,
   g.active = d.active;
   g.prec = PREC_F64;
   g.xcd_remap = 1;
-  g.tile = GEMM_TILE_64_8W;
+  g.tile = tile_for_launch(GEMM_TILE_64_8W, g.M, g.N, g.batch);
   g.prof_class = KC_INV_GEMM;
   g.gauss = d.gauss;
   if (s_hi > s_lo) {

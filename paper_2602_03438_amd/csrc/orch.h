@@ -234,7 +234,7 @@ struct Ctx {
     g.active = active;
     g.prec = pr;
     g.xcd_remap = o.xcd;
-    g.tile = pr == PREC_F32 ? o.tile32 : o.tile;
+    g.tile = tile_for_launch(pr == PREC_F32 ? o.tile32 : o.tile, b, b, batch);
     g.prof_class = -1;
     g.gauss = pr == PREC_F64 ? o.gauss : 0;
     g.skew = skew ? 1 : 0;

@@ -70,6 +70,8 @@ hipError_t launch_slab_map(int b, int nblk, const double2* H, const double2* S, 
   return hipSuccess;
 }
 
+int tile_for_launch(int tile, int, int, long) { return tile; }   // the double computes every tile alike
+
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (!kmask_valid(d)) {

@@ -33,9 +33,9 @@ def test_shipped_cache_is_valid():
     for k, v in c.items():
         assert k.startswith(autotune.ARCH + "/b="), k
         if k.endswith("/step"):
-            assert v["best"]["gemm_tile"] in (1, 2, 3, 4, 5) and v["best"]["inv_nb"] in (16, 32), (k, v)
+            assert v["best"]["gemm_tile"] in (1, 2, 3, 4, 5, 6) and v["best"]["inv_nb"] in (16, 32), (k, v)
         else:
-            assert int(v["best"]) in (1, 2, 3, 4, 5, 16, 32), (k, v)
+            assert int(v["best"]) in (1, 2, 3, 4, 5, 6, 16, 32), (k, v)
 
 
 def test_step_entry_overrides_kernel_timings(tmp_path, monkeypatch):

@@ -43,7 +43,7 @@ def test_zgemm_fp64_parity(nb, opa, opb, M, N, K, prec):
     assert err < 1e-14 * max(1, np.sqrt(K)), err
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("opa,opb", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
 @pytest.mark.parametrize("M,N,K", [(200, 130, 77), (128, 256, 64), (128, 128, 48), (128, 64, 16)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -76,7 +76,7 @@ def test_zgemm_fp64_b1024_largest_block(nb, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
-@pytest.mark.parametrize("tile", [1, 2, 4, 5])
+@pytest.mark.parametrize("tile", [1, 2, 4, 5, 6])
 @pytest.mark.parametrize("K", [1040, 2048])
 @pytest.mark.parametrize("opa,opb", [("N", "N"), ("C", "N"), ("C", "C")])
 def test_zgemm_long_k_full_tiles(nb, K, tile, prec, opa, opb):
@@ -109,7 +109,7 @@ def test_zgemm_fp64_b512_batched(nb, prec):
 
 @pytest.mark.parametrize("n", [8, 72, 130, 512])
 @pytest.mark.parametrize("prec", [0, 2, 1])
-@pytest.mark.parametrize("tile", [1, 2, 4])
+@pytest.mark.parametrize("tile", [1, 2, 4, 6])
 def test_zgemm_skew_product(nb, n, prec, tile):
     """A X A^H + S with X and S anti-Hermitian, computed as an anti-Hermitian
     product (prec + 4): upper triangle computed, lower mirrored."""
