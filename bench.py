@@ -541,7 +541,7 @@ def bench_serinv(args):
     dev = w.scattering_self_energies(w.slab_device(NB, B, SEED), 3)
     gdev = nb.DeviceOnGPU(dev)
     t = autotune.lookup(B, args.cmul)
-    opts = nb.make_options(inv_nb=t["inv_nb"], cmul=args.cmul, gemm_tile=t["gemm_tile"],
+    opts = nb.make_options(inv_nb=args.inv_nb or t["inv_nb"], cmul=args.cmul, gemm_tile=t["gemm_tile"],
                            gemm_tile_f32=t["gemm_tile_f32"], sr_max_iter=args.sr_max_iter)
     grid = np.linspace(-1.5, 1.5, N_GRID)
     res = []
