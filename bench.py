@@ -223,6 +223,8 @@ def main():
                     help="the whole uneven workload: 2048 energies x 4 k = 8192 points (grid energy e on device "
                          "e mod 6) streamed through the plan by the device-side point queue")
     ap.add_argument("--uneven-grid", type=int, default=2048, help="grid energies of --uneven-queue (x 4 k points)")
+    ap.add_argument("--uneven-plain", action="store_true",
+                    help="uneven workload in plain FP64 instead of the refined single-product form")
     ap.add_argument("--uneven-batch", type=int, default=0,
                     help="points per chunk in the uneven workload (0: all points of a block shape in one chunk)")
     ap.add_argument("--streams", type=int, default=None,
@@ -764,7 +766,8 @@ def bench_uneven_queue(args):
     for b, _ in w.DEVICE_MIX:
         t = autotune.lookup(b, args.cmul)
         tunings.append((b, t["gemm_tile"], t["gemm_tile_f32"], t["inv_nb"], args.uneven_batch))
-    plan = nb.Plan(probs, nb.FP32_REFINE, opts=nb.make_options(sr_max_iter=40, cmul=args.cmul), tunings=tunings,
+    prec = nb.PLAIN_FP64 if args.uneven_plain else nb.FP32_REFINE
+    plan = nb.Plan(probs, prec, opts=nb.make_options(sr_max_iter=40, cmul=args.cmul), tunings=tunings,
                    n_streams=args.streams)
     chunks = plan.chunks()
     outs = plan.outputs()
@@ -832,10 +835,12 @@ def bench_uneven_queue(args):
         cpu = {"value": len(checks) / secs, "unit": "energy points/s", "cores": os.cpu_count(), "kind": "oracle",
                "sample": "one task per block shape (k = 0), G^R only, NumPy complex128", "seconds": secs,
                "checks": checks}
+    form = "plain FP64" if args.uneven_plain else "refined single-product form"
     line = {"metric": "energy points/s, batched uneven workload streamed by the point queue (6 devices x 4 k, "
-                      "2048 energies, refined single-product form)",
+                      f"2048 energies, {form})",
             "value": n_tasks / dt, "unit": "energy points/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-            "ms_per_step": dt * 1e3, "higher_is_better": True, "dtype": "f32 products + f64 refinement",
+            "ms_per_step": dt * 1e3, "higher_is_better": True,
+            "dtype": "f64" if args.uneven_plain else "f32 products + f64 refinement",
             "data": "synthetic",
             "config": {"workload": "uneven: six slab devices (b, Nb) in " + str(w.DEVICE_MIX) +
                        f" x 4 k-points x {args.uneven_grid} energies (grid energy e on device e mod 6): "
