@@ -386,6 +386,26 @@ def _rgf_outputs(problems, lesser, greater, lower):
     return out
 
 
+def _check_outputs(out, problems, lesser, greater, lower):
+    """Caller-supplied outputs: every required array a contiguous complex128 device tensor
+    with room for all points (the library writes through raw pointers)."""
+    torch = _torch()
+    need_d = sum(p.n_e * p.dev.nb * p.dev.b * p.dev.b for p in problems)
+    need_o = sum(p.n_e * (p.dev.nb - 1) * p.dev.b * p.dev.b for p in problems)
+    req = {"GR_diag": need_d, "GR_upper": need_o}
+    if lower:
+        req["GR_lower"] = need_o
+    if lesser:
+        req.update(GL_diag=need_d, GL_upper=need_o)
+    if greater:
+        req.update(GG_diag=need_d, GG_upper=need_o)
+    for k, n in req.items():
+        v = out.get(k)
+        if v is None or not v.is_cuda or v.dtype != torch.complex128 or not v.is_contiguous() or v.numel() < n:
+            raise NegfError(f"outputs[{k!r}] must be a contiguous complex128 device tensor of at least {n} elements")
+    return out
+
+
 def _views(flat, problems):
     res = {}
     for k, v in flat.items():
@@ -405,7 +425,7 @@ def rgf_retarded(problems, prec=PLAIN_FP64, opts=None, lower=True, ws=None, outp
     if nbytes == 0:
         raise NegfError("invalid problems")
     buf = (ws or Workspace()).get(nbytes)
-    out = outputs or _rgf_outputs(problems, False, False, lower)
+    out = _check_outputs(outputs, problems, False, False, lower) if outputs else _rgf_outputs(problems, False, False, lower)
     npts = sum(p.n_e for p in problems)
     info = torch.zeros(npts, dtype=torch.int32, device="cuda")
     code = negf_rgf_retarded(arr, len(problems), prec, o, _ptr(out["GR_diag"]), _ptr(out["GR_upper"]),
@@ -425,7 +445,7 @@ def rgf_lesser_greater(problems, prec=PLAIN_FP64, opts=None, greater=False, lowe
     if nbytes == 0:
         raise NegfError("invalid problems")
     buf = (ws or Workspace()).get(nbytes)
-    out = outputs or _rgf_outputs(problems, True, greater, lower)
+    out = _check_outputs(outputs, problems, True, greater, lower) if outputs else _rgf_outputs(problems, True, greater, lower)
     npts = sum(p.n_e for p in problems)
     info = torch.zeros(npts, dtype=torch.int32, device="cuda")
     code = negf_rgf_lesser_greater(arr, len(problems), prec, o, _ptr(out["GR_diag"]), _ptr(out["GR_upper"]),
@@ -447,7 +467,7 @@ def rgf_lesser_greater_static(problems, prec=PLAIN_FP64, opts=None, greater=Fals
     torch = _torch()
     arr = _problem_array(problems)
     o = C.byref(opts) if opts else None
-    out = outputs or _rgf_outputs(problems, True, greater, lower)
+    out = _check_outputs(outputs, problems, True, greater, lower) if outputs else _rgf_outputs(problems, True, greater, lower)
     npts = sum(p.n_e for p in problems)
     info = torch.zeros(npts, dtype=torch.int32, device="cuda")
     code = negf_rgf_lesser_greater_static(arr, len(problems), prec, o, _ptr(out["GR_diag"]), _ptr(out["GR_upper"]),
@@ -469,7 +489,7 @@ def serinv_lesser_greater(problem, partitions, opts=None, greater=False, lower=T
     if nbytes == 0:
         raise NegfError("invalid problem or partition count for the partitioned inversion")
     buf = (ws or Workspace()).get(nbytes)
-    out = outputs or _rgf_outputs([problem], True, greater, lower)
+    out = _check_outputs(outputs, [problem], True, greater, lower) if outputs else _rgf_outputs([problem], True, greater, lower)
     info = torch.zeros(problem.n_e, dtype=torch.int32, device="cuda")
     code = negf_serinv_lesser_greater(arr, partitions, C.byref(opts) if opts else None, _ptr(out["GR_diag"]),
                                       _ptr(out["GR_upper"]), _ptr(out.get("GR_lower")), _ptr(out["GL_diag"]),
@@ -498,6 +518,8 @@ def energy_convolution(G, W, k0, scale=1.0, out=None, ws=None):
         raise NegfError("n_e + n_w - 1 exceeds the longest transform (4096)")
     buf = (ws or Workspace()).get(nbytes)
     B = out if out is not None else torch.empty_like(G)
+    if not B.is_contiguous() or B.dtype != torch.complex128 or tuple(B.shape) != (n_e, n_el) or not B.is_cuda:
+        raise NegfError("out must be a C-contiguous complex128 device tensor of G's shape")
     sc = (C.c_double * 2)(complex(scale).real, complex(scale).imag)
     check(lib().negf_energy_convolution(n_e, n_el, _ptr(G), n_w, int(k0), _ptr(W), sc, _ptr(B), _ptr(buf),
                                         buf.numel(), _stream()), "negf_energy_convolution")
@@ -511,6 +533,8 @@ def transpose(X, out=None):
         raise NegfError("transpose needs a C-contiguous 2-D complex128 tensor")
     r, c = X.shape
     Y = out if out is not None else torch.empty(c, r, dtype=X.dtype, device=X.device)
+    if not Y.is_contiguous() or Y.dtype != torch.complex128 or tuple(Y.shape) != (c, r) or not Y.is_cuda:
+        raise NegfError("out must be a C-contiguous complex128 device tensor of the transposed shape")
     check(lib().negf_transpose(r, c, _ptr(X), _ptr(Y), _stream()), "negf_transpose")
     return Y
 
@@ -586,9 +610,21 @@ class Plan:
         lib().negf_plan_chunks(self.handle, fp, npn, si)
         return [(fp[i], npn[i], si[i]) for i in range(n)]
 
+    def _checked(self, outputs, info):
+        torch = _torch()
+        _check_outputs(outputs, self.problems, True, outputs.get("GG_diag") is not None,
+                       outputs.get("GR_lower") is not None)
+        npts = sum(p.n_e for p in self.problems)
+        if info is None or info.dtype != torch.int32 or not info.is_cuda or info.numel() < npts:
+            raise NegfError(f"info must be an int32 device tensor of at least {npts} entries")
+        return outputs
+
     def execute(self, outputs, info, use_graph=True, stamps=None):
         buf = self.ws.get(lib().negf_plan_workspace_bytes(self.handle))
-        o = outputs
+        o = self._checked(outputs, info)
+        if stamps is not None and (stamps.dtype != _torch().int64 or not stamps.is_cuda or
+                                   stamps.numel() < len(self.chunks()) + 1):
+            raise NegfError("stamps must be an int64 device tensor of (chunks + 1) entries")
         check(lib().negf_plan_execute(self.handle, int(use_graph), _ptr(o["GR_diag"]), _ptr(o["GR_upper"]),
                                       _ptr(o.get("GR_lower")), _ptr(o["GL_diag"]), _ptr(o["GL_upper"]),
                                       _ptr(o.get("GG_diag")), _ptr(o.get("GG_upper")), _ptr(info), _ptr(stamps),
@@ -613,6 +649,7 @@ class Plan:
         self._tasks = [t.contiguous() for t in task_energies]
         ptrs = (C.c_void_p * len(self._tasks))(*[_ptr(t) if t.numel() else None for t in self._tasks])
         counts = (C.c_int32 * len(n_tasks))(*n_tasks)
+        self._checked(outputs, info)
         buf = self.ws.get(lib().negf_plan_workspace_bytes(self.handle))
         qbytes = lib().negf_plan_queue_bytes(self.handle)
         if getattr(self, "_qws", None) is None or self._qws.numel() < qbytes:

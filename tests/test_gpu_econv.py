@@ -81,3 +81,17 @@ def test_transpose_matches_numpy(nb, rows, cols):
     X = _rand(r, (rows, cols))
     got = nb.transpose(torch.from_numpy(X).cuda()).cpu().numpy()
     assert np.array_equal(got, oec.to_element_major(X))
+
+
+def test_output_tensors_are_checked(nb):
+    """The helpers refuse outputs that the kernels would write past (the library
+    itself only sees pointers)."""
+    import torch
+    G = torch.zeros(8, 3, dtype=torch.complex128, device="cuda")
+    W = torch.zeros(4, 3, dtype=torch.complex128, device="cuda")
+    with pytest.raises(nb.NegfError):
+        nb.energy_convolution(G, W, 1, out=torch.zeros(8, 2, dtype=torch.complex128, device="cuda"))
+    with pytest.raises(nb.NegfError):
+        nb.energy_convolution(G, W, 1, out=torch.zeros(8, 3, dtype=torch.complex64, device="cuda"))
+    with pytest.raises(nb.NegfError):
+        nb.transpose(G, out=torch.zeros(8, 3, dtype=torch.complex128, device="cuda"))

@@ -254,3 +254,18 @@ def test_point_queue_eager_graph_and_direct_call(nb):
                 break
         assert stable >= 1, q
         off += t.size
+
+
+def test_caller_outputs_are_checked(nb):
+    import torch
+    dev = w.slab_device(3, 40, 31)
+    prob = nb.Problem(nb.DeviceOnGPU(dev), np.array([-0.5, 0.5]), eta=1e-8)
+    outs = nb._rgf_outputs([prob], True, False, True)
+    outs["GL_upper"] = outs["GL_upper"][:-1]
+    with pytest.raises(nb.NegfError):
+        nb.rgf_lesser_greater([prob], outputs=outs)
+    plan = nb.Plan([prob], nb.PLAIN_FP64, n_streams=1)
+    good = plan.outputs()
+    with pytest.raises(nb.NegfError):
+        plan.execute(good, torch.zeros(1, dtype=torch.int32, device="cuda"), use_graph=False)
+    plan.close()
