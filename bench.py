@@ -200,6 +200,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-chosen", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="serinv workload: skip the graph-replayed timings")
+    ap.add_argument("--gemm-f32", action="store_true", help="gemm workload: the single-precision product kernel")
     ap.add_argument("--inv-nb", type=int, default=0, help="inversion panel width (0: tuned)")
     ap.add_argument("--cmul", type=int, choices=[3, 4], default=3,
                     help="real products per complex double product (3: Gauss's method)")
@@ -426,32 +427,39 @@ def bench_gemm(args):
     A = torch.randn(batch, B, B, dtype=torch.complex128, device="cuda", generator=g)
     Bm = torch.randn(batch, B, B, dtype=torch.complex128, device="cuda", generator=g)
     Cm = torch.zeros(batch, B, B, dtype=torch.complex128, device="cuda")
-    prec = 2 if args.cmul == 3 else 0
+    f32 = args.gemm_f32
+    prec = 1 if f32 else (2 if args.cmul == 3 else 0)
+    tile = tuned["gemm_tile_f32"] if f32 else tuned["gemm_tile"]
     for _ in range(args.warmup):
-        nb.zgemm(A, Bm, Cm, prec=prec, tile=tuned["gemm_tile"])
+        nb.zgemm(A, Bm, Cm, prec=prec, tile=tile)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(s)
-        nb.zgemm(A, Bm, Cm, prec=prec, tile=tuned["gemm_tile"])
+        nb.zgemm(A, Bm, Cm, prec=prec, tile=tile)
         ev[k][1].record(s)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = [a.elapsed_time(b) for a, b in ev]
-    real_products = 3 if args.cmul == 3 else 4
+    real_products = 3 if (args.cmul == 3 and not f32) else 4
     flops = 2.0 * real_products * B ** 3 * batch
     a0, b0, c0 = A[0].cpu().numpy(), Bm[0].cpu().numpy(), Cm[0].cpu().numpy()
     ref = a0 @ b0
     err = float(np.linalg.norm(c0 - ref) / np.linalg.norm(ref))
     avg = float(np.mean(ms))
-    line = {"metric": "batched complex FP64 product (b x b x b), executed TFLOP/s", "value": flops / (avg * 1e-3) / 1e12,
+    peak = PEAK["f32"] if f32 else PEAK["f64"]
+    line = {"metric": f"batched complex {'FP32' if f32 else 'FP64'} product (b x b x b), executed TFLOP/s",
+            "value": flops / (avg * 1e-3) / 1e12,
             "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"{batch} products of {B}x{B} complex128 per launch, tile {tuned['gemm_tile']}, "
-                                   f"{real_products} real products per complex product"},
-            "avg_launch_ms": avg, "min_launch_ms": float(np.min(ms)), "frac_of_fp64_peak": flops / (avg * 1e-3) / PEAK["f64"],
+            "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "dtype": "f32" if f32 else "f64",
+            "data": "synthetic",
+            "config": {"workload": f"{batch} products of {B}x{B} complex128 per launch"
+                                   f"{' (operands rounded to single precision at staging)' if f32 else ''}, "
+                                   f"tile {tile}, {real_products} real products per complex product"},
+            "avg_launch_ms": avg, "min_launch_ms": float(np.min(ms)),
+            f"frac_of_{'fp32' if f32 else 'fp64'}_peak": flops / (avg * 1e-3) / peak,
             "algorithmic_bytes_per_launch": 3 * 16 * B * B * batch, "rel_err_vs_torch_item0": err}
     print(json.dumps(line), flush=True)
 

@@ -144,7 +144,7 @@ def _gpu_agent(d: str):
     return 1024, 8, 2400.0
 
 
-def mfma(mfma_dir: str, kernel: str):
+def mfma(mfma_dir: str, kernel: str, mops_counter: str = "SQ_INSTS_VALU_MFMA_MOPS_F64"):
     """Matrix-core activity of the product kernel from one counter run with
     SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE,
     per launch: the FP64 matrix flops the hardware counted (MOPS x 512, the
@@ -153,7 +153,7 @@ def mfma(mfma_dir: str, kernel: str):
     the csv holds GRBM_GUI_ACTIVE summed over the XCCs, so it is divided by
     their number); and the engine clock the GUI-active cycles imply over the
     launch's duration."""
-    mops = per_dispatch(mfma_dir, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    mops = per_dispatch(mfma_dir, mops_counter)
     busy = per_dispatch(mfma_dir, "SQ_VALU_MFMA_BUSY_CYCLES")
     simd_num, n_xcc, clk = _gpu_agent(mfma_dir)
     gui, dur = {}, {}
@@ -173,7 +173,8 @@ def mfma(mfma_dir: str, kernel: str):
     util = [busy[d][1] / (gui[d] * simd_num) for d in rows if d in busy and gui.get(d)]
     mhz = [gui[d] / dur[d] / 1e6 for d in rows if gui.get(d) and dur.get(d)]
     mean = lambda x: sum(x) / len(x) if x else None
-    return {"kernel_pattern": kernel, "launches": len(rows), "mfma_f64_flops_per_launch": mean(fl),
+    return {"kernel_pattern": kernel, "launches": len(rows), "mops_counter": mops_counter,
+            "mfma_flops_per_launch": mean(fl),
             "mfma_busy_frac_mean": mean(util), "mfma_busy_frac_min": min(util) if util else None,
             "mfma_busy_frac_max": max(util) if util else None, "simd_num": simd_num, "xcc": n_xcc,
             "engine_clock_mhz_from_gui_active": mean(mhz), "max_engine_clock_mhz": clk}
@@ -195,11 +196,12 @@ if __name__ == "__main__":
     ap.add_argument("--source", default="gemm.hip", help="csrc/ file whose hash is stored with the summary")
     ap.add_argument("--mfma", metavar="MFMA_DIR", help="counter run with SQ_INSTS_VALU_MFMA_MOPS_F64, "
                     "SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE")
+    ap.add_argument("--mops", default="SQ_INSTS_VALU_MFMA_MOPS_F64", help="matrix-op counter of the --mfma run")
     ap.add_argument("--json")
     ap.add_argument("--note", default="", help="what the counter runs measured (stored in the JSON)")
     a = ap.parse_args()
     if a.mfma:
-        rec = mfma(a.mfma, a.kernel)
+        rec = mfma(a.mfma, a.kernel, a.mops)
         print(json.dumps(rec, indent=1))
         if a.json:
             with open(a.json, "w") as f:
