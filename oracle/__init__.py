@@ -21,9 +21,11 @@ Modules
                  iteration, with a hand-written backward pass and Adam
   econv       -- the energy convolution of Eq. (3) on a uniform grid (the
                  plain sum), and the (E; i,j) -> (i,j; E) layout change
+  scba        -- the self-consistent loop of Fig. 1 around Eq. (1)-(3) with a
+                 fixed boson bath (solve, convolve, mix, repeat)
 
 Parity status: every function is pinned by the CPU tests against closed
 forms, brute force or physical invariants, except the absolute throughput,
 for which the paper prints no number (parity unpinned).
 """
-from . import leads, dense, rgf, observables, emulate, mlp, econv  # noqa: F401
+from . import leads, dense, rgf, observables, emulate, mlp, econv, scba  # noqa: F401

@@ -32,7 +32,7 @@ __all__ = [
     "BTDevice", "rng", "cgauss", "random_device", "chain_device",
     "folded_chain_device", "periodic_wire_device", "slab_device", "slab_lead",
     "slab_geometry", "scattering_self_energies", "k_device", "mixed_devices",
-    "energy_grid", "DEVICE_MIX",
+    "energy_grid", "DEVICE_MIX", "boson_bath",
 ]
 
 
@@ -325,3 +325,38 @@ def mixed_devices(seed0: int = 40, scale_nb: float = 1.0, blocks=None):
 def energy_grid(lo: float, hi: float, n: int) -> np.ndarray:
     """Uniform energy grid including both end points."""
     return np.linspace(lo, hi, n, dtype=np.float64)
+
+
+def boson_bath(nb: int, b: int, n_w: int, k0: int, dE: float, kT: float, strength: float = 0.05,
+               width: float = 0.1, decay: float = 2.0):
+    """Lesser and greater propagators W^<[k], W^>[k] ([n_w][nb][b][b] complex128) of a bosonic
+    bath held in equilibrium at temperature ``kT``, sampled at the frequencies w_k = (k - k0) dE.
+
+    They stand in for the screened interaction (or phonon propagator) of the energy convolution
+    of Eq. (3); nothing here is random.  Spatial part, the same in every diagonal block:
+    K_oo' = exp(-|o - o'| / decay), real symmetric and positive definite (the exponential
+    covariance).  Spectral part: the odd density B(w) = strength (w / width) exp(-w^2 / (2 width^2))
+    with the Bose occupation n(w) = 1 / (e^{w / kT} - 1):
+
+        W^<(w) = -i K B(w) n(w),     W^>(w) = -i K B(w) (1 + n(w)),
+
+    both -i K strength kT / width at w = 0 (the limit).  B n >= 0 and B (1 + n) >= 0 for every w,
+    W^>(w) = e^{w / kT} W^<(w) (detailed balance) and W^<(w) = W^>(-w).
+    """
+    if not (kT > 0.0):
+        raise ValueError("the bath needs kT > 0")
+    o = np.arange(b, dtype=np.float64)
+    K = np.exp(-np.abs(o[:, None] - o[None, :]) / decay)
+    Wl = np.empty((n_w, nb, b, b), dtype=np.complex128)
+    Wg = np.empty((n_w, nb, b, b), dtype=np.complex128)
+    for k in range(n_w):
+        w = (k - k0) * dE
+        if w == 0.0:
+            lo = hi = strength * kT / width
+        else:
+            dens = strength * (w / width) * math.exp(-0.5 * (w / width) ** 2)
+            occ = 1.0 / math.expm1(w / kT)
+            lo, hi = dens * occ, dens * (1.0 + occ)
+        Wl[k] = (-1j * lo) * K
+        Wg[k] = (-1j * hi) * K
+    return Wl, Wg
