@@ -88,9 +88,10 @@ typedef enum { NEGF_PLAIN_FP64 = 0, NEGF_FP32_REFINE = 1, NEGF_FP32_NOREFINE = 2
 /* One block-tridiagonal device (Section II: BT shape imposed on A and B).
  * H_diag [nb][b][b] and H_upper [nb-1][b][b] (H_{i,i+1}) are required; the
  * lower blocks are H_{i+1,i} = H_{i,i+1}^H.  S_diag/S_upper == NULL means
- * S = I.  sig_r_sc / sig_l_sc / sig_g_sc: optional energy-independent
- * block-diagonal scattering self-energies [nb][b][b] (retarded, lesser,
- * greater); NULL = none (ballistic). */
+ * S = I.  sig_r_sc / sig_l_sc / sig_g_sc: optional block-diagonal
+ * scattering self-energies [nb][b][b] (retarded, lesser, greater), the same
+ * for every energy unless the problem's sc_stride says otherwise; NULL =
+ * none (ballistic). */
 typedef struct negf_device {
   int32_t nb, b;
   const void* H_diag;
@@ -104,12 +105,18 @@ typedef struct negf_device {
 
 /* A device and its list of energies (device array of n_e doubles).
  * eta: lead broadening; mu_l, mu_r, kT: contact Fermi levels and temperature
- * for Sigma^<_B = i f Gamma, Sigma^>_B = -i (1 - f) Gamma. */
+ * for Sigma^<_B = i f Gamma, Sigma^>_B = -i (1 - f) Gamma.
+ * sc_stride: 0, or the distance in complex elements (>= nb b b) between the
+ * scattering self-energies of consecutive energies, so that energy e reads
+ * sig_*_sc + e sc_stride: energy-dependent self-energies, as the
+ * self-consistent loop of Fig. 1 produces them (Eq. (3)).  The point queue
+ * (negf_plan_run_queue) takes only sc_stride = 0. */
 typedef struct negf_problem {
   negf_device dev;
   int32_t n_e;
   const double* energies;
   double eta, mu_l, mu_r, kT;
+  int64_t sc_stride;
 } negf_problem;
 
 /* Optional knobs (pass NULL for the defaults in brackets). */
@@ -261,6 +268,45 @@ negf_status negf_energy_convolution(int32_t n_e, int64_t n_el, const void* G, in
  * dst[c][r] = src[r][c] for a rows x cols complex128 array (dst must not
  * overlap src).  Errors: EINVAL, EHIP. */
 negf_status negf_transpose(int64_t rows, int64_t cols, const void* src, void* dst, void* stream);
+
+/* ---- the self-consistent loop of Fig. 1 (Eq. (1)-(3)) with a fixed boson bath ----
+ * Alternates the two halves of Fig. 1 for one problem (one device, n_e >= 1
+ * energies on a uniform grid of spacing dE): every energy is solved from
+ * Eq. (1) and (2) with its own block-diagonal scattering self-energies, then
+ * the self-energies are rebuilt from the new G^<> by the energy convolution
+ * of Eq. (3), restricted to the diagonal blocks:
+ *     F^<>_ii(E_e) = scale * sum_k G^<>_ii(E_e - w_k) (.) W^<>[k],  w_k = (k - k0) dE
+ * (M1 = M2 = I; W^<> [n_w][nb][b][b] complex128, a bath held fixed: the
+ * polarisation loop of Fig. 1 is not run; scale, host, 2 doubles, e.g.
+ * i dE / 2 pi).  The retarded self-energy is (Sigma^> - Sigma^<) / 2 (its
+ * principal-value part is not formed).  Iteration n solves with Sigma_n and
+ * measures r_n = ||F - Sigma_n||_F / ||F||_F over both kinds, every energy
+ * and block (0 when both norms are 0); it stops when r_n <= tol or at
+ * n = max_iter - 1, leaving Sigma_n and the Green's functions it produced in
+ * the outputs, else Sigma_{n+1} = Sigma_n + mixing (F - Sigma_n) (both kinds)
+ * and Sigma^R_{n+1} = (Sigma^>_{n+1} - Sigma^<_{n+1}) / 2.
+ * problem: one problem whose device has no scattering self-energies and
+ * sc_stride 0 (the loop supplies both).  sig_r / sig_l / sig_g: device,
+ * [n_e][nb][b][b] complex128, in: Sigma_0 (sig_r is overwritten from sig_l
+ * and sig_g before the first solve), out: the final Sigma_n.  Outputs as in
+ * negf_rgf_lesser_greater (GR_lower may be NULL; G^> is required), info
+ * [n_e] per point of the last solve.  n_iter (host): solves performed;
+ * history (host, nullable, max_iter doubles): r_0 .. r_{n_iter-1}.
+ * The call synchronises `stream` once per iteration (the stopping decision is
+ * taken on the host) and so cannot be captured in a graph.
+ * Requirements: 0 <= k0 < n_w, n_e + n_w - 1 <= 4096, 0 < mixing <= 1,
+ * tol >= 0, max_iter >= 1.  Returns NEGF_OK when r_n <= tol was reached,
+ * NEGF_ENOCONV when max_iter solves ended above tol, NEGF_ENONFINITE when r_n
+ * is not finite (the outputs then hold that iteration); argument errors
+ * (EINVAL) before any work.  Workspace: negf_scba_workspace_bytes(...). */
+size_t negf_scba_workspace_bytes(const negf_problem* problem, negf_precision prec, const negf_options* opt,
+                                 int32_t n_w);
+negf_status negf_scba(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
+                      int32_t k0, const void* W_lesser, const void* W_greater, const double* scale, double mixing,
+                      double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g, void* GR_diag,
+                      void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper,
+                      int32_t* info, int32_t* n_iter, double* history, void* workspace, size_t ws_bytes,
+                      void* stream);
 
 /* ---- plans: many problems of uneven block shapes in one launch ----
  * A plan groups the points of all problems into chunks of one block shape

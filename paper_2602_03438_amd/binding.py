@@ -36,7 +36,8 @@ class negf_device(C.Structure):
 
 class negf_problem(C.Structure):
     _fields_ = [("dev", negf_device), ("n_e", C.c_int32), ("energies", C.c_void_p),
-                ("eta", C.c_double), ("mu_l", C.c_double), ("mu_r", C.c_double), ("kT", C.c_double)]
+                ("eta", C.c_double), ("mu_l", C.c_double), ("mu_r", C.c_double), ("kT", C.c_double),
+                ("sc_stride", C.c_int64)]
 
 
 class negf_options(C.Structure):
@@ -94,6 +95,11 @@ def lib():
     L.negf_energy_convolution.restype = C.c_int
     L.negf_transpose.argtypes = [i64, i64, vp, vp, vp]
     L.negf_transpose.restype = C.c_int
+    L.negf_scba_workspace_bytes.argtypes = [P(negf_problem), i32, P(negf_options), i32]
+    L.negf_scba_workspace_bytes.restype = sz
+    L.negf_scba.argtypes = [P(negf_problem), i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32, vp, vp,
+                            vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(dbl), vp, sz, vp]
+    L.negf_scba.restype = C.c_int
     L.negf_transmission.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, sz, vp]
     L.negf_transmission.restype = C.c_int
     L.negf_zgemm_batched.argtypes = [C.c_char, C.c_char, i32, i32, i32, P(dbl), vp, i64, i64, vp, i64, i64, P(dbl),
@@ -285,18 +291,22 @@ class DeviceOnGPU:
 class Problem:
     """A device on the GPU plus its energies and contact parameters."""
 
-    def __init__(self, dev: DeviceOnGPU, energies, eta=1e-8, mu_l=0.0, mu_r=0.0, kT=0.025):
+    def __init__(self, dev: DeviceOnGPU, energies, eta=1e-8, mu_l=0.0, mu_r=0.0, kT=0.025, sc_stride=0):
+        """``sc_stride`` > 0: the device's scattering self-energies are [n_e][nb][b][b], one set per
+        energy, ``sc_stride`` elements apart (normally nb b b)."""
         torch = _torch()
         self.dev = dev
         self.energies = torch.as_tensor(np.asarray(energies, dtype=np.float64)).to("cuda")
         self.eta, self.mu_l, self.mu_r, self.kT = float(eta), float(mu_l), float(mu_r), float(kT)
+        self.sc_stride = int(sc_stride)
 
     @property
     def n_e(self):
         return int(self.energies.numel())
 
     def struct(self) -> negf_problem:
-        return negf_problem(self.dev.struct(), self.n_e, _ptr(self.energies), self.eta, self.mu_l, self.mu_r, self.kT)
+        return negf_problem(self.dev.struct(), self.n_e, _ptr(self.energies), self.eta, self.mu_l, self.mu_r, self.kT,
+                            self.sc_stride)
 
 
 def _problem_array(problems: Sequence[Problem]):
@@ -524,6 +534,63 @@ def energy_convolution(G, W, k0, scale=1.0, out=None, ws=None):
     check(lib().negf_energy_convolution(n_e, n_el, _ptr(G), n_w, int(k0), _ptr(W), sc, _ptr(B), _ptr(buf),
                                         buf.numel(), _stream()), "negf_energy_convolution")
     return B
+
+
+def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_iter=50, sig0=None, prec=PLAIN_FP64,
+         opts=None, lower=True, ws=None, outputs=None, sigmas=None):
+    """negf_scba: the self-consistent loop of Fig. 1 for one problem with a fixed bath.
+
+    W_lesser / W_greater: complex128 device tensors [n_w, nb, b, b] (W[k] at (k - k0) dE);
+    scale: the convolution's prefactor (e.g. 1j dE / 2 pi); sig0: optional (Sigma^<, Sigma^>)
+    [n_e, nb, b, b] to start from (default zero); sigmas: optional dict of caller-owned
+    sig_r / sig_l / sig_g tensors to run in place (their lesser / greater contents are the
+    start when sig0 is None).  Returns the outputs (per-point views), the final self-energies,
+    info, n_iter, the residual history and the status (OK: converged; ENOCONV: max_iter reached;
+    ENONFINITE: a non-finite residual)."""
+    torch = _torch()
+    arr = _problem_array([problem])
+    o = C.byref(opts) if opts else None
+    dv = problem.dev
+    n_w = int(W_lesser.shape[0])
+    shape = (problem.n_e, dv.nb, dv.b, dv.b)
+    for t in (W_lesser, W_greater):
+        if (not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous()
+                or tuple(t.shape) != (n_w, dv.nb, dv.b, dv.b)):
+            raise NegfError("W_lesser / W_greater must be contiguous complex128 device tensors [n_w, nb, b, b]")
+    nbytes = lib().negf_scba_workspace_bytes(arr, prec, o, n_w)
+    if nbytes == 0:
+        raise NegfError("invalid problem or bath for the self-consistent loop")
+    buf = (ws or Workspace()).get(nbytes)
+    if sigmas is None:
+        sigmas = {k: torch.zeros(shape, dtype=torch.complex128, device="cuda") for k in ("sig_r", "sig_l", "sig_g")}
+    for k in ("sig_r", "sig_l", "sig_g"):
+        t = sigmas.get(k)
+        if t is None or not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise NegfError(f"sigmas[{k!r}] must be a contiguous complex128 device tensor {shape}")
+    if sig0 is not None:
+        sigmas["sig_l"].copy_(torch.as_tensor(sig0[0]).to(sigmas["sig_l"].device))
+        sigmas["sig_g"].copy_(torch.as_tensor(sig0[1]).to(sigmas["sig_g"].device))
+    out = (_check_outputs(outputs, [problem], True, True, lower) if outputs
+           else _rgf_outputs([problem], True, True, lower))
+    info = torch.zeros(problem.n_e, dtype=torch.int32, device="cuda")
+    sc = (C.c_double * 2)(complex(scale).real, complex(scale).imag)
+    n_iter = C.c_int32(0)
+    hist = (C.c_double * max(int(max_iter), 1))()
+    code = lib().negf_scba(arr, prec, o, n_w, int(k0), _ptr(W_lesser), _ptr(W_greater), sc, float(mixing), float(tol),
+                           int(max_iter), _ptr(sigmas["sig_r"]), _ptr(sigmas["sig_l"]), _ptr(sigmas["sig_g"]),
+                           _ptr(out["GR_diag"]), _ptr(out["GR_upper"]), _ptr(out.get("GR_lower")),
+                           _ptr(out["GL_diag"]), _ptr(out["GL_upper"]), _ptr(out["GG_diag"]), _ptr(out["GG_upper"]),
+                           _ptr(info), C.byref(n_iter), hist, _ptr(buf), buf.numel(), _stream())
+    if code not in (NEGF_OK, NEGF_ENOCONV, NEGF_ENONFINITE):
+        check(code, "negf_scba")
+    res = _views(out, [problem])
+    res.update(sigmas)
+    res["info"] = info
+    res["flat"] = out
+    res["n_iter"] = int(n_iter.value)
+    res["history"] = [hist[i] for i in range(n_iter.value)]
+    res["status"] = int(code)
+    return res
 
 
 def transpose(X, out=None):

@@ -22,6 +22,12 @@ using namespace negf::orch;
 
 namespace negf {
 namespace orch {
+// block i of a scattering self-energy for the first energy of the segment (energy-dependent
+// self-energies advance by the problem's sc_stride per energy)
+inline const double2* sc_blk(const Seg& sg, const void* base, int i, int b) {
+  return base ? blk(base, i, b) + (long)sg.e0 * sg.pr->sc_stride : nullptr;
+}
+
 // A_ii = E S_ii - H_ii - Sigma_sc,ii - [i==0] SigL - [i==nb-1] SigR for every point of the chunk
 void assemble_diag(Ctx& cx, const Chunk& ch, int i, const PointWs& pw, Blocks out, bool with_leads = true) {
   const int b = ch.b, nb = ch.nb;
@@ -30,7 +36,7 @@ void assemble_diag(Ctx& cx, const Chunk& ch, int i, const PointWs& pw, Blocks ou
     AssembleDesc d = asm_base(b, sg.n, sg.pr->energies + sg.e0, out.at(sg.off), out.stride);
     d.S = blk(dv.S_diag, i, b); d.s_identity = 1;
     d.H = blk(dv.H_diag, i, b);
-    d.Y = blk(dv.sig_r_sc, i, b);
+    d.Y = sc_blk(sg, dv.sig_r_sc, i, b); d.sY = sg.pr->sc_stride;
     if (with_leads && i == 0) { d.Z = pw.sigL.at(sg.off); d.sZ = pw.sigL.stride; }
     if (with_leads && i == nb - 1) {
       if (d.Z) {
@@ -72,7 +78,7 @@ bool assemble_sigma_lg(Ctx& cx, const Chunk& ch, int i, int kind, const PointWs&
     AssembleDesc d = asm_base(b, sg.n, nullptr, out.at(sg.off), out.stride);
     d.S = nullptr; d.s_identity = 0; d.s_coef = 0.0;
     d.H = nullptr;
-    d.Y = blk(kind == 0 ? dv.sig_l_sc : dv.sig_g_sc, i, b); d.y_coef = 1.0;
+    d.Y = sc_blk(sg, kind == 0 ? dv.sig_l_sc : dv.sig_g_sc, i, b); d.sY = sg.pr->sc_stride; d.y_coef = 1.0;
     if (i == 0) { d.Z = leadL.at(sg.off); d.sZ = leadL.stride; d.z_coef = 1.0; }
     if (i == nb - 1) { d.Z = leadR.at(sg.off); d.sZ = leadR.stride; d.z_coef = 1.0; }
     cx.assemble(d);
@@ -411,6 +417,7 @@ negf_status check_problems(const negf_problem* pr, int n_prob) {
       if (p && !aligned16(p)) return NEGF_EINVAL;
     if ((d.S_diag == nullptr) != (d.S_upper == nullptr)) return NEGF_EINVAL;
     if ((d.sig_l_sc == nullptr) != (d.sig_g_sc == nullptr)) return NEGF_EINVAL;
+    if (pr[q].sc_stride != 0 && pr[q].sc_stride < (int64_t)d.nb * d.b * d.b) return NEGF_EINVAL;
   }
   return NEGF_OK;
 }
@@ -844,8 +851,10 @@ negf_status negf_plan_run_queue(negf_plan* plan, int32_t use_graph, const double
   qa.task_E = task_E;
   qa.n_tasks = n_tasks;
   for (int q = 0; q < np; ++q) {
-    // a problem without slots cannot take tasks
+    // a problem without slots cannot take tasks; a slot takes any task's energy, so the
+    // scattering self-energies must be the same for every energy
     if (n_tasks[q] < 0 || (n_tasks[q] > 0 && (!task_E[q] || P->probs[q].n_e < 1))) return NEGF_EINVAL;
+    if (n_tasks[q] > 0 && P->probs[q].sc_stride != 0) return NEGF_EINVAL;
     qa.task_off.push_back(total);
     total += n_tasks[q];
   }

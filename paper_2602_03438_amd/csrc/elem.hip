@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(TD * TR) assemble_kernel(AssembleDesc d) {
   const double e = d.energies ? d.energies[d.inner > 0 ? p % d.inner : p] : 0.0;
   const double2* S = d.S ? d.S + go : nullptr;
   const double2* Hm = d.H ? d.H + go : nullptr;
-  const double2* Y = d.Y ? d.Y + go : nullptr;
+  const double2* Y = d.Y ? d.Y + go + (long)(d.inner > 0 ? p % d.inner : p) * d.sY : nullptr;
   const double2 zc = make_double2(d.s_coef * e, d.s_coef * d.eta);
   const int i0 = blockIdx.y * TD, j0 = blockIdx.x * TD;
   __shared__ double2 tS[TD][TD + 1];

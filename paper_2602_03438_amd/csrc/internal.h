@@ -112,6 +112,9 @@ struct AssembleDesc {
   // parts of a device, e.g. one per partition).
   int inner;
   long sHo;
+  // Y of item p additionally offset by (inner > 0 ? p % inner : p) * sY elements: one block per
+  // energy (energy-dependent scattering self-energies); 0 for a Y shared by every item
+  long sY;
 };
 hipError_t launch_assemble(const AssembleDesc& d, hipStream_t s);
 // out_p += c * W_p^H for b x b blocks (out must not alias W)

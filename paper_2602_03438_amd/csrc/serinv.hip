@@ -155,7 +155,7 @@ struct Serinv {
     if (kind == 0) {
       a.S = blk(d.S_diag, blk0, b); a.s_identity = 1;
       a.H = blk(d.H_diag, blk0, b);
-      a.Y = blk(d.sig_r_sc, blk0, b);
+      a.Y = blk(d.sig_r_sc, blk0, b); a.sY = pr.sc_stride;
     } else if (kind == 1) {
       a.S = blk(d.S_upper, blk0, b); a.s_identity = 0;
       a.H = blk(d.H_upper, blk0, b);
@@ -163,7 +163,7 @@ struct Serinv {
       a.energies = nullptr;
       a.S = nullptr; a.s_identity = 0; a.s_coef = 0.0;
       a.H = nullptr;
-      a.Y = blk(kind == 2 ? d.sig_l_sc : d.sig_g_sc, blk0, b); a.y_coef = 1.0;
+      a.Y = blk(kind == 2 ? d.sig_l_sc : d.sig_g_sc, blk0, b); a.sY = pr.sc_stride; a.y_coef = 1.0;
     }
     cx.assemble(a);
   }

@@ -180,7 +180,7 @@ hipError_t launch_assemble(const AssembleDesc& d, hipStream_t) {
     const long go = d.inner > 0 ? (long)(p / d.inner) * d.sHo : 0;
     const double2* S = d.S ? d.S + go : nullptr;
     const double2* Hm = d.H ? d.H + go : nullptr;
-    const double2* Y = d.Y ? d.Y + go : nullptr;
+    const double2* Y = d.Y ? d.Y + go + (long)(d.inner > 0 ? p % d.inner : p) * d.sY : nullptr;
     const double e = d.energies ? d.energies[d.inner > 0 ? p % d.inner : p] : 0.0;
     const cd zc = d.s_coef * cd(e, d.eta);
     for (int i = 0; i < b; ++i)

@@ -1,0 +1,245 @@
+"""GPU self-consistent loop (negf_scba) and energy-dependent scattering
+self-energies (negf_problem.sc_stride) against the oracle (oracle/scba.py,
+oracle/rgf.py), plus properties of the loop's output that hold at any size
+(the Fermi relation at equilibrium, current conservation once converged)."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import workloads as w
+from helpers import point_tolerance, record, refined_inversions
+from oracle import leads as oleads
+from oracle import observables as oobs
+from oracle import rgf as orgf
+from oracle import scba as oscba
+
+pytestmark = pytest.mark.gpu
+
+KT = 0.025
+ETA = 1e-6
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2602_03438_amd import binding
+    binding.lib()
+    return binding
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _bath(dev, n_e, lo=-1.5, hi=1.5, n_w=17, strength=1.0):
+    E = w.energy_grid(lo, hi, n_e)
+    dE = float(E[1] - E[0])
+    k0 = (n_w - 1) // 2
+    Wl, Wg = w.boson_bath(dev.nb, dev.b, n_w, k0, dE, KT, strength=strength)
+    return E, dE, k0, Wl, Wg
+
+
+def _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, mu_l, mu_r, **kw):
+    import torch
+    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=mu_l, mu_r=mu_r, kT=KT)
+    print(f"  negf_scba nb={dev.nb} b={dev.b} n_e={len(E)} n_w={Wl.shape[0]} {kw}", flush=True)
+    res = nb.scba(prob, torch.from_numpy(Wl).cuda(), torch.from_numpy(Wg).cuda(), k0, scale, **kw)
+    torch.cuda.synchronize()
+    return res
+
+
+def _stack(points, name):
+    return np.stack([getattr(p, name) for p in points])
+
+
+# --------------------------------------------------------------- energy-dependent self-energies
+
+@pytest.mark.parametrize("prec,bar", [(0, 1e-10), (1, 1e-6)])
+def test_energy_dependent_self_energies_match_oracle(nb, prec, bar):
+    """sc_stride = nb b b: energy e of the problem reads its own Sigma_sc; chunked (batch 4 of 6 energies,
+    so the second chunk starts inside the problem) and at a block size with a ragged tile (b = 40)."""
+    import torch
+    base = w.slab_device(5, 40, 2)
+    E = np.linspace(-0.9, 1.1, 6)
+    per_e = [w.scattering_self_energies(dataclasses.replace(base), 50 + e, norm=0.02) for e in range(E.size)]
+    dev = dataclasses.replace(base, sig_r=np.stack([d.sig_r for d in per_e]), sig_l=np.stack([d.sig_l for d in per_e]),
+                              sig_g=np.stack([d.sig_g for d in per_e]))
+    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=0.1, mu_r=-0.1, kT=KT, sc_stride=5 * 40 * 40)
+    out = nb.rgf_lesser_greater([prob], prec=prec, opts=nb.make_options(batch=4), greater=True)
+    torch.cuda.synchronize()
+    assert int(out["info"].abs().sum()) == 0
+    names = ("GR_diag", "GR_upper", "GL_diag", "GL_upper", "GG_diag")
+    for k, e in enumerate(E):
+        ref, tol = point_tolerance(lambda: orgf.solve_point(per_e[k], e, ETA, 0.1, -0.1, KT, greater=True), names,
+                                   base=bar)
+        for n in names:
+            err = rel(out[n][0][k].cpu().numpy(), getattr(ref, n))
+            record("energy_dependent_sigma", e, n, err, tol[n], prec=prec)
+            assert err < tol[n], (k, n, err, tol[n])
+
+
+def test_energy_dependent_self_energies_partitioned(nb):
+    """The partitioned inversion reads the per-energy self-energies as the sweeps do."""
+    import torch
+    base = w.slab_device(8, 24, 3)
+    E = np.linspace(-0.7, 0.9, 3)
+    per_e = [w.scattering_self_energies(dataclasses.replace(base), 70 + e, norm=0.02) for e in range(E.size)]
+    dev = dataclasses.replace(base, sig_r=np.stack([d.sig_r for d in per_e]), sig_l=np.stack([d.sig_l for d in per_e]),
+                              sig_g=np.stack([d.sig_g for d in per_e]))
+    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=0.1, mu_r=-0.1, kT=KT, sc_stride=8 * 24 * 24)
+    out = nb.serinv_lesser_greater(prob, 2, greater=True)
+    torch.cuda.synchronize()
+    assert int(out["info"].abs().sum()) == 0
+    names = ("GR_diag", "GL_diag", "GG_upper")
+    for k, e in enumerate(E):
+        ref, tol = point_tolerance(lambda: orgf.solve_point(per_e[k], e, ETA, 0.1, -0.1, KT, greater=True), names)
+        for n in names:
+            err = rel(out[n][0][k].cpu().numpy(), getattr(ref, n))
+            record("energy_dependent_sigma_partitioned", e, n, err, tol[n])
+            assert err < tol[n], (k, n, err, tol[n])
+
+
+# --------------------------------------------------------------- the loop against the oracle
+
+def _loop_reference(compute):
+    """(oracle result, {output: spread}) where the spread is how far the whole loop's outputs move
+    when every inversion inside it is Newton-refined (its sensitivity to rounding)."""
+    ref = compute()
+    with refined_inversions():
+        ref2 = compute()
+    out = {}
+    for n in ("sig_l", "sig_g"):
+        out[n] = rel(getattr(ref2, n), getattr(ref, n))
+    for n in ("GR_diag", "GR_upper", "GL_diag", "GL_upper", "GG_diag"):
+        out[n] = rel(_stack(ref2.points, n), _stack(ref.points, n))
+    return ref, out
+
+
+def _compare_loop(test, res, ref, spread, bar=1e-10):
+    for n in ("sig_l", "sig_g", "sig_r"):
+        got = res[n].cpu().numpy()
+        tol = max(bar, 4.0 * spread.get(n, spread["sig_l"]))
+        err = rel(got, getattr(ref, n))
+        record(test, 0.0, n, err, tol, spread=spread.get(n, spread["sig_l"]))
+        assert err < tol, (n, err, tol)
+    for n in ("GR_diag", "GR_upper", "GL_diag", "GL_upper", "GG_diag"):
+        got = res[n][0].cpu().numpy()
+        tol = max(bar, 4.0 * spread[n])
+        err = rel(got, _stack(ref.points, n))
+        record(test, 0.0, n, err, tol, spread=spread[n])
+        assert err < tol, (n, err, tol)
+
+
+@pytest.mark.parametrize("b", [4, 40])
+def test_loop_fixed_iterations_matches_oracle(nb, b):
+    """Four solves with no stopping (tol = 0): the self-energies after three mixings and the Green's
+    functions they produced, element by element, plus the residual history."""
+    dev = w.folded_chain_device(4, b)
+    E, dE, k0, Wl, Wg = _bath(dev, 48)
+    scale = 1j * dE / (2 * math.pi)
+    ref, spread = _loop_reference(lambda: oscba.scba(dev, E, ETA, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=0.7,
+                                                     tol=0.0, max_iter=4))
+    res = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=0.7, tol=0.0, max_iter=4)
+    assert res["status"] == nb.NEGF_ENOCONV and res["n_iter"] == 4
+    assert int(res["info"].abs().sum()) == 0
+    _compare_loop(f"scba_fixed_b{b}", res, ref, spread)
+    for got, want in zip(res["history"], ref.history):
+        assert abs(got - want) <= 1e-8 * want + 1e-12, (res["history"], ref.history)
+
+
+def test_loop_converges_with_the_oracle(nb):
+    """Run to tol = 1e-11: the GPU loop stops at the oracle's iteration (or one apart, when a
+    residual sits at the tolerance) at the same fixed point."""
+    dev = w.folded_chain_device(4, 24)
+    E, dE, k0, Wl, Wg = _bath(dev, 40, n_w=21)
+    scale = 1j * dE / (2 * math.pi)
+    ref = oscba.scba(dev, E, ETA, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=1.0, tol=1e-11, max_iter=30)
+    assert ref.converged
+    res = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=1.0, tol=1e-11, max_iter=30)
+    assert res["status"] == nb.NEGF_OK, res["history"]
+    assert abs(res["n_iter"] - ref.n_iter) <= 1, (res["history"], ref.history)
+    for n in ("sig_l", "sig_g"):
+        err = rel(res[n].cpu().numpy(), getattr(ref, n))
+        record("scba_converged", 0.0, n, err, 1e-9)
+        assert err < 1e-9, (n, err)
+
+
+def test_loop_without_bath_is_one_ballistic_solve(nb):
+    """W = 0: one solve, zero self-energies, the plain sweeps' result."""
+    import torch
+    dev = w.folded_chain_device(4, 16)
+    E, dE, k0, Wl, Wg = _bath(dev, 20)
+    Z = np.zeros_like(Wl)
+    res = _gpu_loop(nb, dev, E, Z, Z, k0, 1j * dE / (2 * math.pi), 0.1, -0.1, tol=1e-12, max_iter=5)
+    assert res["status"] == nb.NEGF_OK and res["n_iter"] == 1 and res["history"] == [0.0]
+    for n in ("sig_r", "sig_l", "sig_g"):
+        assert not bool(res[n].abs().max() > 0)
+    plain = nb.rgf_lesser_greater([nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=0.1, mu_r=-0.1, kT=KT)],
+                                  greater=True)
+    torch.cuda.synchronize()
+    for n in ("GR_diag", "GL_diag", "GG_upper"):
+        assert rel(res[n][0].cpu().numpy(), plain[n][0].cpu().numpy()) < 1e-13
+
+
+def test_loop_starts_from_given_self_energies(nb):
+    """A start Sigma_0 taken from a converged run is already the fixed point: one solve."""
+    dev = w.folded_chain_device(4, 8)
+    E, dE, k0, Wl, Wg = _bath(dev, 32)
+    scale = 1j * dE / (2 * math.pi)
+    ref = oscba.scba(dev, E, ETA, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=1.0, tol=1e-13, max_iter=40)
+    res = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, sig0=(ref.sig_l, ref.sig_g), tol=1e-11, max_iter=3)
+    assert res["status"] == nb.NEGF_OK and res["n_iter"] == 1, res["history"]
+
+
+# --------------------------------------------------------------- properties at a larger size
+
+def _fermi_residual(E, mu, GL, GG):
+    worst = 0.0
+    for e in range(len(E)):
+        f = oleads.fermi(E[e] - mu, KT)
+        scl = np.abs(GL[e]).max() + np.abs(GG[e]).max()
+        worst = max(worst, float(np.abs((1 - f) * GL[e] + f * GG[e]).max() / scl))
+    return worst
+
+
+def test_loop_equilibrium_keeps_the_fermi_relation(nb):
+    """One Fermi level and a bath at the same temperature: (1 - f) X^< + f X^> = 0 for the
+    Green's functions and the self-energies of the last iterate (b = 96, 64 energies)."""
+    dev = w.folded_chain_device(6, 96)
+    E, dE, k0, Wl, Wg = _bath(dev, 64, n_w=33)
+    mu = 0.05
+    res = _gpu_loop(nb, dev, E, Wl, Wg, k0, 1j * dE / (2 * math.pi), mu, mu, mixing=0.7, tol=0.0, max_iter=3)
+    assert res["n_iter"] == 3
+    worst = max(_fermi_residual(E, mu, res["GL_diag"][0].cpu().numpy(), res["GG_diag"][0].cpu().numpy()),
+                _fermi_residual(E, mu, res["sig_l"].cpu().numpy(), res["sig_g"].cpu().numpy()))
+    record("scba_fermi_relation", mu, "GL/GG", worst, 1e-11)
+    assert worst < 1e-11, worst
+    assert float(res["sig_l"].abs().max()) > 1e-4
+
+
+def test_loop_conserves_the_energy_integrated_current(nb):
+    """Converged inelastic loop (b = 64): the energy-integrated current is the same at every
+    interface and equals the left lead's injection, while the per-energy currents differ."""
+    dev = w.folded_chain_device(5, 64)
+    E, dE, k0, Wl, Wg = _bath(dev, 64, n_w=25)
+    res = _gpu_loop(nb, dev, E, Wl, Wg, k0, 1j * dE / (2 * math.pi), 0.1, -0.1, mixing=1.0, tol=1e-12,
+                    max_iter=40)
+    assert res["status"] == nb.NEGF_OK, res["history"]
+    GLu = res["GL_upper"][0].cpu().numpy()
+    GLd = res["GL_diag"][0].cpu().numpy()
+    GGd = res["GG_diag"][0].cpu().numpy()
+    j = np.array([oobs.currents([E[e] * dev.s_upper(i) - dev.H_upper[i] for i in range(dev.nb - 1)], GLu[e])
+                  for e in range(len(E))])
+    inj = []
+    for e in range(len(E)):
+        lead = oleads.lead_self_energy(dev, 0, E[e], ETA)
+        sl, sg = oleads.lesser_greater(lead.gamma, oleads.fermi(E[e] - 0.1, KT))
+        inj.append(oobs.lead_current(sl, sg, GLd[e][0], GGd[e][0]))
+    J, Jin = j.sum(axis=0), float(np.sum(inj))
+    err = float(max(np.abs(J - J[0]).max(), abs(J[0] - Jin)) / abs(J[0]))
+    record("scba_current_conservation", 0.0, "J", err, 1e-9)
+    assert err < 1e-9, (J, Jin)
+    assert np.abs(j - j[:, :1]).max() > 1e-4 * np.abs(j).max()

@@ -179,3 +179,41 @@ def test_point_queue_rejects_synchronously(L):
     p = np.zeros(8, dtype=np.complex128).ctypes.data
     assert L.negf_plan_run_queue(None, 0, None, None, None, None, None, None, p, p, p, p, p, None, None, p, p, 1024,
                                  p, 1024, None) == nb.NEGF_EINVAL
+
+
+def test_self_consistent_loop_rejects_synchronously(L):
+    """negf_scba: a device that already carries scattering self-energies, an out-of-range bath
+    index, mixing, tolerance or iteration cap, a convolution longer than 4096, missing or
+    aliased buffers and a short workspace all return EINVAL before any work."""
+    from paper_2602_03438_amd import binding as nb
+    pr, keep = _fake_problem(nb_=4, b=8, n_e=6)
+    arr = (nb.negf_problem * 1)(pr)
+    n_w = 5
+    ws = L.negf_scba_workspace_bytes(arr, nb.PLAIN_FP64, None, n_w)
+    sig_bytes = 6 * 4 * 8 * 8 * 16
+    assert ws >= L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr, 1, nb.PLAIN_FP64, None) + 2 * sig_bytes
+    assert L.negf_scba_workspace_bytes(arr, nb.PLAIN_FP64, None, 0) == 0
+    assert L.negf_scba_workspace_bytes(arr, nb.PLAIN_FP64, None, 4092) == 0      # 6 + 4092 - 1 > 4096
+    one = (C.c_double * 2)(0.0, 1.0)
+    bufs = [np.zeros(64, dtype=np.complex128) for _ in range(13)]
+    W_l, W_g, s_r, s_l, s_g, grd, gru, grl, gld, glu, ggd, ggu, info = [b.ctypes.data for b in bufs]
+    n_iter = C.c_int32(-1)
+    hist = (C.c_double * 8)()
+
+    def call(a=arr, k0=2, mixing=0.5, tol=1e-10, max_iter=8, wsb=ws, **over):
+        p = dict(W_l=W_l, W_g=W_g, s_r=s_r, s_l=s_l, s_g=s_g, ggd=ggd, info=info, scale=one, n_iter=C.byref(n_iter))
+        p.update(over)
+        return L.negf_scba(a, nb.PLAIN_FP64, None, n_w, k0, p["W_l"], p["W_g"], p["scale"], mixing, tol, max_iter,
+                           p["s_r"], p["s_l"], p["s_g"], grd, gru, grl, gld, glu, p["ggd"], ggu, p["info"],
+                           p["n_iter"], hist, grd, wsb, None)
+
+    for bad in (dict(k0=-1), dict(k0=5), dict(mixing=0.0), dict(mixing=1.5), dict(mixing=float("nan")),
+                dict(tol=-1.0), dict(max_iter=0), dict(wsb=ws - 1), dict(W_l=None), dict(ggd=None), dict(info=None),
+                dict(scale=None), dict(n_iter=None), dict(s_l=s_g), dict(W_g=W_g + 8)):
+        assert call(**bad) == nb.NEGF_EINVAL, bad
+    # the loop supplies the scattering self-energies: a device with its own is rejected
+    dev = nb.negf_device(4, 8, W_l, W_l, None, None, s_r, s_l, s_g)
+    with_sc = (nb.negf_problem * 1)(nb.negf_problem(dev, 6, W_l, 1e-8, 0.1, -0.1, 0.025))
+    assert call(a=with_sc) == nb.NEGF_EINVAL
+    strided = (nb.negf_problem * 1)(nb.negf_problem(pr.dev, 6, W_l, 1e-8, 0.1, -0.1, 0.025, 4 * 8 * 8))
+    assert call(a=strided) == nb.NEGF_EINVAL

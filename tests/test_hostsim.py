@@ -6,6 +6,7 @@ transposes, strides, chunking, workspace carving, masks and info codes)
 without a GPU; the HIP kernels themselves are checked by the gpu tests.
 """
 import ctypes as C
+import dataclasses
 import os
 
 import numpy as np
@@ -48,13 +49,13 @@ def sim():
 
 
 class HostProblem:
-    def __init__(self, nb, dev, energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025):
+    def __init__(self, nb, dev, energies, eta=1e-8, mu_l=0.1, mu_r=-0.1, kT=0.025, sc_stride=0):
         self.keep = [np.ascontiguousarray(x) if x is not None else None
                      for x in (dev.H_diag, dev.H_upper, dev.S_diag, dev.S_upper, dev.sig_r, dev.sig_l, dev.sig_g)]
         self.E = np.ascontiguousarray(energies, dtype=np.float64)
         ptr = lambda a: a.ctypes.data if a is not None else None
         d = nb.negf_device(dev.nb, dev.b, *[ptr(a) for a in self.keep])
-        self.s = nb.negf_problem(d, self.E.size, self.E.ctypes.data, eta, mu_l, mu_r, kT)
+        self.s = nb.negf_problem(d, self.E.size, self.E.ctypes.data, eta, mu_l, mu_r, kT, sc_stride)
         self.nb, self.b, self.n = dev.nb, dev.b, self.E.size
 
 
@@ -106,6 +107,36 @@ def test_hostsim_lesser_greater_matches_oracle(sim, scatter):
         for k, e in enumerate(E):
             ref = getattr(orgf.solve_point(dev, e, 1e-8, 0.1, -0.1, 0.025, greater=True), ref_name)
             assert rel(got[k], ref) < 1e-11, (name, k)
+
+
+def test_hostsim_energy_dependent_self_energies(sim):
+    """sc_stride: every energy reads its own scattering self-energies, also when its problem's
+    energies are split over chunks (batch 2) that they share with another problem."""
+    L, nb = sim
+    base = w.random_device(4, 5, 3, overlap=0.05)
+    E = well_posed(base, np.linspace(-1.2, 1.2, 13))[:5]
+    assert E.size == 5
+    per_e = [w.scattering_self_energies(dataclasses.replace(base), 20 + e, norm=0.05) for e in range(E.size)]
+    dev = dataclasses.replace(base, sig_r=np.stack([d.sig_r for d in per_e]), sig_l=np.stack([d.sig_l for d in per_e]),
+                              sig_g=np.stack([d.sig_g for d in per_e]))
+    other = w.scattering_self_energies(w.random_device(4, 5, 7, overlap=0.05), 30, norm=0.05)
+    E2 = well_posed(other, np.linspace(-1.0, 1.0, 7))[:3]
+    p = HostProblem(nb, dev, E, sc_stride=4 * 5 * 5)
+    q = HostProblem(nb, other, E2)
+    out, info = _run_rgf(L, nb, [q, p], opts=nb.make_options(batch=2))
+    assert np.all(info == 0)
+    names = ("GR_diag", "GL_diag", "GG_upper")
+    for prob, devs, energies, slot in ((p, per_e, E, 1), (q, [other] * E2.size, E2, 0)):
+        for k, e in enumerate(energies):
+            ref, tol = point_tolerance(
+                lambda: orgf.solve_point(devs[k], e, 1e-8, 0.1, -0.1, 0.025, greater=True), names, base=1e-11)
+            for name, ref_name, diag in (("GRd", "GR_diag", 1), ("GLd", "GL_diag", 1), ("GGu", "GG_upper", 0)):
+                got = _unpack(out[name], [q, p], diag)[slot][k]
+                assert rel(got, getattr(ref, ref_name)) < tol[ref_name], (name, slot, k)
+    # a stride shorter than one energy's blocks is rejected
+    bad = HostProblem(nb, dev, E, sc_stride=4 * 5 * 5 - 1)
+    arr = (nb.negf_problem * 1)(bad.s)
+    assert L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr, 1, 0, None) == 0
 
 
 @pytest.mark.parametrize("prec,tol", [(1, 1e-6), (2, 1e-2)])
