@@ -204,7 +204,8 @@ def main():
     ap.add_argument("--inv-nb", type=int, default=0, help="inversion panel width (0: tuned)")
     ap.add_argument("--cmul", type=int, choices=[3, 4], default=3,
                     help="real products per complex double product (3: Gauss's method)")
-    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm", "serinv", "econv"], default="ribbon",
+    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm", "serinv", "econv", "scba"],
+                    default="ribbon",
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation; gemm: the "
                          "dominant product kernel alone through negf_zgemm_batched at the headline's block size "
@@ -216,6 +217,9 @@ def main():
     ap.add_argument("--econv-elements", type=int, default=1 << 21, help="elements (matrix entries) in the econv "
                     "workload")
     ap.add_argument("--gemm-batch", type=int, default=256, help="products per launch in the gemm workload")
+    ap.add_argument("--scba-energies", type=int, default=32, help="energies of the scba workload's uniform grid")
+    ap.add_argument("--scba-freqs", type=int, default=17, help="bath frequencies of the scba workload")
+    ap.add_argument("--scba-strength", type=float, default=0.05, help="bath strength of the scba workload")
     ap.add_argument("--serinv-points", default="1,2,4,8", help="energy points per call in the serinv workload")
     ap.add_argument("--serinv-parts", default="4,8", help="partition counts in the serinv workload")
     ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload "
@@ -266,6 +270,8 @@ def main():
         return bench_serinv(args)
     if args.workload == "econv":
         return bench_econv(args)
+    if args.workload == "scba":
+        return bench_scba(args)
     if args.workload == "uneven":
         # four worker streams (the hardware queues HIP gives a process by default); each device
         # shape's points form one chunk (see --uneven-batch)
@@ -535,6 +541,89 @@ def bench_econv(args):
             "cpu_baseline": cpu,
             "transpose": {"ms": ms_t, "gb_per_s": bytes_t / (ms_t * 1e-3) / 1e9, "frac_of_hbm": bytes_t / (ms_t * 1e-3) / 8e12,
                           "rows": n_e, "cols": n_el, "sampled_column_exact": ok_t}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_scba(args):
+    """The self-consistent loop of Fig. 1 around Eq. (1)-(3) at the headline device (Nb = 60,
+    b = 512): --scba-energies energies, uniform on [-1.5, 1.5], and a boson bath of --scba-freqs
+    frequencies (the grid spacing apart).  An iteration solves every energy (G^R, G^<, G^>, both
+    leads), convolves the diagonal blocks of G^< and of G^> with the bath (Eq. (3)), reduces the
+    residual, reads it on the host and mixes.  --steps iterations are timed as one call with
+    tol = 0 (no early stop), after --warmup iterations in a call of their own; points/s =
+    energies x iterations / wall time of the call.  The convolutions are also timed alone, on the
+    same arrays, for their share of an iteration."""
+    import torch
+    import workloads as w
+    from paper_2602_03438_amd import autotune
+    from paper_2602_03438_amd import binding as nb
+    n_e, n_w = args.scba_energies, args.scba_freqs
+    k0 = (n_w - 1) // 2
+    dev = w.slab_device(NB, B, SEED)
+    E = np.linspace(-1.5, 1.5, n_e)
+    dE = float(E[1] - E[0])
+    Wl, Wg = w.boson_bath(NB, B, n_w, k0, dE, KT, strength=args.scba_strength)
+    gWl, gWg = torch.from_numpy(Wl).cuda(), torch.from_numpy(Wg).cuda()
+    del Wl, Wg
+    t = autotune.lookup(B, args.cmul)
+    opts = nb.make_options(inv_nb=args.inv_nb or t["inv_nb"], cmul=args.cmul, gemm_tile=t["gemm_tile"],
+                           gemm_tile_f32=t["gemm_tile_f32"], sr_max_iter=args.sr_max_iter)
+    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT)
+    ws = nb.Workspace()
+    outs = nb._rgf_outputs([prob], True, True, True)
+    shape = (n_e, NB, B, B)
+    sig = {k: torch.zeros(shape, dtype=torch.complex128, device="cuda") for k in ("sig_r", "sig_l", "sig_g")}
+    scale = 1j * dE / (2 * np.pi)
+    log(f"scba: {n_e} energies x Nb={NB} b={B}, {n_w} bath frequencies; warm-up {args.warmup} iteration(s)")
+    if args.warmup > 0:
+        nb.scba(prob, gWl, gWg, k0, scale, tol=0.0, max_iter=args.warmup, opts=opts, ws=ws, outputs=outs, sigmas=sig)
+    for v in sig.values():
+        v.zero_()
+    torch.cuda.synchronize()
+    log(f"scba: {args.steps} timed iteration(s)")
+    t0 = time.perf_counter()
+    r = nb.scba(prob, gWl, gWg, k0, scale, mixing=0.5, tol=0.0, max_iter=args.steps, opts=opts, ws=ws, outputs=outs,
+                sigmas=sig)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = r["n_iter"]
+    log(f"scba: {its} iteration(s) in {dt:.2f} s, residuals {['%.2e' % h for h in r['history']]}")
+    # the two convolutions of one iteration, alone
+    n_el = NB * B * B
+    GL = outs["GL_diag"].view(n_e, n_el)
+    GG = outs["GG_diag"].view(n_e, n_el)
+    Fl = torch.empty_like(GL)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    s = torch.cuda.current_stream()
+    nb.energy_convolution(GL, gWl.view(n_w, n_el), k0, scale, out=Fl, ws=ws)
+    ev[0].record(s)
+    for _ in range(3):
+        nb.energy_convolution(GL, gWl.view(n_w, n_el), k0, scale, out=Fl, ws=ws)
+        nb.energy_convolution(GG, gWg.view(n_w, n_el), k0, scale, out=Fl, ws=ws)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    conv_ms = ev[0].elapsed_time(ev[1]) / 3
+    it_ms = dt / its * 1e3
+    flops = point_flops(NB, B) + float(B) ** 3 * (16 + 64 * (NB - 1))      # + G^>
+    line = {"metric": "self-consistent loop (Fig. 1, Eq. (1)-(3)) at Nb=60, b=512: energy points solved and "
+                      "convolved per second",
+            "value": n_e * its / dt, "unit": "energy points/s", "n_gpus": 1, "steps": its, "warmup": args.warmup,
+            "ms_per_step": it_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"nano-ribbon-like slab device Nb={NB} b={B}, {n_e} energies on [-1.5, 1.5], "
+                                   f"boson bath of {n_w} frequencies (strength {args.scba_strength}, kT={KT}), "
+                                   f"eta={ETA}, mixing 0.5, one iteration per step",
+                       "real_products_per_complex_product": args.cmul, "sr_max_iter": args.sr_max_iter},
+            "ms_per_iteration": it_ms, "convolutions_ms_per_iteration": conv_ms,
+            "convolution_share": conv_ms / it_ms, "residual_history": r["history"], "status": r["status"],
+            "info_nonzero": int(torch.count_nonzero(r["info"]).item()),
+            "roofline": algorithmic_roofline(flops, it_ms * 1e-3 / n_e,
+                                             "G^R + G^< + G^> of one energy point (both leads, 28 decimation steps) "
+                                             "per (iteration time / energies); the convolutions add no flops to "
+                                             "the count"),
+            "cpu_baseline": None,
+            "cpu_baseline_note": "not taken: one oracle iteration at this shape solves every energy point "
+                                 "(about 1.4e12 flop each) on the host"}
     print(json.dumps(line), flush=True)
 
 
