@@ -21,6 +21,7 @@ namespace {
 constexpr int SB = 256;       // threads per workgroup of the streaming kernels
 constexpr int RPARTS = 1024;  // workgroups of the residual's first stage (fixed: the sum's order is fixed)
 constexpr long MIX_WG = 8192; // grid cap of the mixing pass (grid-stride beyond)
+constexpr int U = 4;          // elements per thread and pass of the streaming kernels
 
 __device__ __forceinline__ double norm2(double2 z) { return z.x * z.x + z.y * z.y; }
 
@@ -39,16 +40,30 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
 
 // part[2 w]     = sum over workgroup w's elements of |F^< - S^<|^2 + |F^> - S^>|^2
 // part[2 w + 1] = sum of |F^<|^2 + |F^>|^2
+// Each thread takes U elements SB apart per pass (lanes next to each other read neighbouring elements)
+// and issues all of their loads before the arithmetic, so that 4 U independent 16-byte loads are in flight.
 __global__ void __launch_bounds__(SB) resid_partial_kernel(long n, const double2* __restrict__ Fl,
                                                            const double2* __restrict__ Fg,
                                                            const double2* __restrict__ Sl,
                                                            const double2* __restrict__ Sg, double* part) {
   __shared__ double red[SB];
   double num = 0.0, den = 0.0;
-  for (long x = (long)blockIdx.x * SB + threadIdx.x; x < n; x += (long)gridDim.x * SB) {
-    const double2 fl = Fl[x], fg = Fg[x];
-    num += norm2(csub(fl, Sl[x])) + norm2(csub(fg, Sg[x]));
-    den += norm2(fl) + norm2(fg);
+  for (long x0 = (long)blockIdx.x * SB * U + threadIdx.x; x0 < n; x0 += (long)gridDim.x * SB * U) {
+    double2 fl[U], fg[U], sl[U], sg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long x = x0 + (long)u * SB;
+      const bool in = x < n;
+      fl[u] = in ? Fl[x] : make_double2(0.0, 0.0);
+      fg[u] = in ? Fg[x] : make_double2(0.0, 0.0);
+      sl[u] = in ? Sl[x] : make_double2(0.0, 0.0);
+      sg[u] = in ? Sg[x] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      num += norm2(csub(fl[u], sl[u])) + norm2(csub(fg[u], sg[u]));
+      den += norm2(fl[u]) + norm2(fg[u]);
+    }
   }
   num = wg_sum(num, red);
   den = wg_sum(den, red);
@@ -74,20 +89,37 @@ __global__ void __launch_bounds__(SB) resid_final_kernel(int nparts, const doubl
   }
 }
 
-// with F: S^<> += m (F^<> - S^<>); then S^R = (S^> - S^<) / 2 (without F only the latter)
+// with F: S^<> += m (F^<> - S^<>); then S^R = (S^> - S^<) / 2 (without F only the latter).  U elements
+// SB apart per thread and pass, all loads first (as in the residual).
 __global__ void __launch_bounds__(SB) mix_kernel(long n, double m, const double2* __restrict__ Fl,
                                                  const double2* __restrict__ Fg, double2* __restrict__ Sl,
                                                  double2* __restrict__ Sg, double2* __restrict__ Sr) {
-  for (long x = (long)blockIdx.x * SB + threadIdx.x; x < n; x += (long)gridDim.x * SB) {
-    double2 sl = Sl[x], sg = Sg[x];
-    if (Fl) {
-      const double2 fl = Fl[x], fg = Fg[x];
-      sl = make_double2(sl.x + m * (fl.x - sl.x), sl.y + m * (fl.y - sl.y));
-      sg = make_double2(sg.x + m * (fg.x - sg.x), sg.y + m * (fg.y - sg.y));
-      Sl[x] = sl;
-      Sg[x] = sg;
+  for (long x0 = (long)blockIdx.x * SB * U + threadIdx.x; x0 < n; x0 += (long)gridDim.x * SB * U) {
+    double2 sl[U], sg[U], fl[U], fg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long x = x0 + (long)u * SB;
+      if (x < n) {
+        sl[u] = Sl[x];
+        sg[u] = Sg[x];
+        if (Fl) {
+          fl[u] = Fl[x];
+          fg[u] = Fg[x];
+        }
+      }
     }
-    Sr[x] = make_double2(0.5 * (sg.x - sl.x), 0.5 * (sg.y - sl.y));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long x = x0 + (long)u * SB;
+      if (x >= n) continue;
+      if (Fl) {
+        sl[u] = make_double2(sl[u].x + m * (fl[u].x - sl[u].x), sl[u].y + m * (fl[u].y - sl[u].y));
+        sg[u] = make_double2(sg[u].x + m * (fg[u].x - sg[u].x), sg[u].y + m * (fg[u].y - sg[u].y));
+        Sl[x] = sl[u];
+        Sg[x] = sg[u];
+      }
+      Sr[x] = make_double2(0.5 * (sg[u].x - sl[u].x), 0.5 * (sg[u].y - sl[u].y));
+    }
   }
 }
 
@@ -172,8 +204,8 @@ negf_status negf_scba(const negf_problem* problem, negf_precision prec, const ne
   double2* Sl = (double2*)sig_l;
   double2* Sg = (double2*)sig_g;
   double2* Sr = (double2*)sig_r;
-  const unsigned mix_grid = (unsigned)std::min<long>((n + SB - 1) / SB, MIX_WG);
-  const unsigned part_grid = (unsigned)std::min<long>((n + SB - 1) / SB, RPARTS);
+  const unsigned mix_grid = (unsigned)std::min<long>((n + SB * U - 1) / (SB * U), MIX_WG);
+  const unsigned part_grid = (unsigned)std::min<long>((n + SB * U - 1) / (SB * U), RPARTS);
   *n_iter = 0;
 
   prof_begin(KC_ELEM, s);

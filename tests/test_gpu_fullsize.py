@@ -26,6 +26,7 @@ Two broadenings of the leads:
               one where the oracle's own decimation is not clean and every
               sampled clean point to be unflagged.
 """
+import dataclasses
 import os
 import time
 
@@ -35,6 +36,7 @@ import pytest
 import workloads as w
 from helpers import kappa_proxy, oracle_spread, plain_reference, record, well_posed, SPREAD_FACTOR
 from oracle import leads as oleads
+from oracle import econv as oecv
 from oracle import rgf as orgf
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -305,4 +307,68 @@ def test_fullsize_serinv_plain_bar(setup, scattering_refs, parts):
             _progress(f"serinv P={parts} point {k} {name}: error {err:.3e}, bar {bar:.1e}")
             assert err <= bar, (parts, k, name, err)
     del out
+    _free()
+
+
+# ------------------------------------------------------------------ the self-consistent loop at full size
+
+def test_fullsize_self_consistent_loop_plain_bar(setup):
+    """negf_scba at the benchmark's shape and options (Nb = 60, b = 512, three-product complex
+    products), eta = 1e-2: two iterations from zero self-energies over 8 energies, a bath of 3
+    frequencies.  After them the self-energies are m F_0, with F_0 the Eq. (3) convolution of the
+    ballistic G^<> (the oracle solves the three energies the sampled energy's window reaches and
+    convolves them), and the Green's functions at the sampled energy are the oracle's solve with
+    the oracle's self-energies there.  The oracle is stable to the plain bar at these points
+    (asserted through its spread)."""
+    import torch
+    nb, bench, autotune, dev, gdev, _ = setup
+    n_e, n_w, k0, es, m = 8, 3, 1, 4, 0.5
+    E = 0.095 + (np.arange(n_e) - 4) * 0.03
+    dE = float(E[1] - E[0])
+    Wl, Wg = w.boson_bath(NB, B, n_w, k0, dE, KT, strength=0.05)
+    scale = 1j * dE / (2 * np.pi)
+    prob = nb.Problem(gdev, E, eta=ETA_STABLE, mu_l=MU_L, mu_r=MU_R, kT=KT)
+    _progress("negf_scba at full size: 8 energies, bath of 3 frequencies, 2 iterations ...")
+    res = nb.scba(prob, torch.from_numpy(Wl).cuda(), torch.from_numpy(Wg).cuda(), k0, scale, mixing=m, tol=0.0,
+                  max_iter=2, opts=_headline_opts(nb, bench, autotune))
+    torch.cuda.synchronize()
+    assert res["n_iter"] == 2 and res["status"] == nb.NEGF_ENOCONV
+    assert int(res["info"].abs().sum()) == 0
+    # the oracle's ballistic G^<> on the window es - k0 .. es + k0 and its convolution at es
+    win = range(es - k0, es + n_w - k0)
+    Gl, Gg, spread0 = [], [], 0.0
+    for e in win:
+        _progress(f"oracle (ballistic) at E = {E[e]:+.4f} ...")
+        ref, sp = plain_reference(lambda: orgf.solve_point(dev, E[e], ETA_STABLE, MU_L, MU_R, KT, greater=True),
+                                  ["GL_diag", "GG_diag"], PLAIN_TOL)
+        Gl.append(ref.GL_diag)
+        Gg.append(ref.GG_diag)
+        spread0 = max(spread0, *sp.values())
+        del ref
+    Gl, Gg = np.stack(Gl), np.stack(Gg)
+    n_el = NB * B * B
+    j = es - win.start
+    Sl = m * oecv.energy_convolution(Gl.reshape(n_w, n_el), Wl.reshape(n_w, n_el), k0, scale)[j].reshape(NB, B, B)
+    Sg = m * oecv.energy_convolution(Gg.reshape(n_w, n_el), Wg.reshape(n_w, n_el), k0, scale)[j].reshape(NB, B, B)
+    del Gl, Gg
+    for name, want in (("sig_l", Sl), ("sig_g", Sg), ("sig_r", 0.5 * (Sg - Sl))):
+        got = res[name][es].cpu().numpy()
+        err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        record("fullsize_scba_eta1e-2", E[es], name, err, PLAIN_TOL, spread0)
+        _progress(f"scba self-energy {name} at E = {E[es]:+.4f}: error {err:.3e}, bar {PLAIN_TOL:.1e}")
+        assert err <= PLAIN_TOL, (name, err)
+    # the Green's functions at es: the oracle's solve with the oracle's self-energies
+    sdev = dataclasses.replace(dev, sig_r=0.5 * (Sg - Sl), sig_l=Sl, sig_g=Sg)
+    names = NAMES + ["GG_diag"]
+    _progress(f"oracle (with the loop's self-energies) at E = {E[es]:+.4f} ...")
+    ref, sp = plain_reference(lambda: orgf.solve_point(sdev, E[es], ETA_STABLE, MU_L, MU_R, KT, greater=True), names,
+                              PLAIN_TOL)
+    for name in names:
+        got = res[name][0][es].cpu().numpy()
+        want = getattr(ref, name)
+        err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        record("fullsize_scba_eta1e-2", E[es], name, err, PLAIN_TOL, sp.get(name))
+        _progress(f"scba {name} at E = {E[es]:+.4f}: error {err:.3e}, bar {PLAIN_TOL:.1e}")
+        assert err <= PLAIN_TOL, (name, err)
+    del res
     _free()
