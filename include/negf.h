@@ -491,6 +491,8 @@ void negf_profile_time_classes(uint32_t mask);
 negf_status negf_profile_read(negf_kernel_stats* stats);
 
 const char* negf_status_string(negf_status s);
+/* 101: negf_problem carries sc_stride (energy-dependent scattering
+ * self-energies); callers built against 100 pass a shorter struct. */
 int32_t negf_version(void);
 
 #ifdef __cplusplus

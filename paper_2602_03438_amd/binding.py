@@ -20,6 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnegf.so")
 
 NEGF_OK, NEGF_EINVAL, NEGF_ENOCONV, NEGF_ESINGULAR, NEGF_ENONFINITE, NEGF_EHIP, NEGF_ENOMEM = range(7)
+ABI_VERSION = 101          # negf_version() of the struct layouts below (negf_problem with sc_stride)
 PLAIN_FP64, FP32_REFINE, FP32_NOREFINE = 0, 1, 2
 OP_OBC, OP_RETARDED, OP_LESSER_GREATER, OP_TRANSMISSION = 0, 1, 2, 3
 KC_NAMES = ["gemm_f64", "gemm_f32", "inv_panel", "inv_swap", "inv_perm", "elementwise", "inv_update_gemm",
@@ -138,6 +139,9 @@ def lib():
     L.negf_plan_destroy.restype = None
     if hasattr(L, "negf_mlp_forward"):
         _bind_mlp(L)
+    if L.negf_version() < ABI_VERSION:
+        raise NegfError(f"{LIB_PATH} is older than this binding (negf_problem layout {L.negf_version()}, "
+                        f"need {ABI_VERSION}): rebuild it")
     _lib = L
     return L
 

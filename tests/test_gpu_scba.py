@@ -243,3 +243,29 @@ def test_loop_conserves_the_energy_integrated_current(nb):
     record("scba_current_conservation", 0.0, "J", err, 1e-9)
     assert err < 1e-9, (J, Jin)
     assert np.abs(j - j[:, :1]).max() > 1e-4 * np.abs(j).max()
+
+
+def test_energy_dependent_self_energies_through_a_plan(nb):
+    """A plan (two worker streams, graph-replayed chunks of 3 points) reads per-energy
+    self-energies like the direct call; its point queue refuses them (a slot takes any task's
+    energy), before any work."""
+    import torch
+    base = w.slab_device(4, 24, 5)
+    E = np.linspace(-0.8, 0.9, 7)
+    per_e = [w.scattering_self_energies(dataclasses.replace(base), 90 + e, norm=0.02) for e in range(E.size)]
+    dev = dataclasses.replace(base, sig_r=np.stack([d.sig_r for d in per_e]), sig_l=np.stack([d.sig_l for d in per_e]),
+                              sig_g=np.stack([d.sig_g for d in per_e]))
+    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=0.1, mu_r=-0.1, kT=KT, sc_stride=4 * 24 * 24)
+    direct = nb.rgf_lesser_greater([prob], greater=True)
+    plan = nb.Plan([prob], opts=nb.make_options(batch=3), n_streams=2)
+    outs = plan.outputs(greater=True)
+    info = torch.zeros(E.size, dtype=torch.int32, device="cuda")
+    plan.execute(outs, info, use_graph=True)
+    torch.cuda.synchronize()
+    assert int(info.abs().sum()) == 0
+    for n in ("GR_diag", "GR_upper", "GL_diag", "GL_upper", "GG_diag"):
+        a, b = outs[n].cpu().numpy(), direct["flat"][n].cpu().numpy()
+        assert rel(a, b) < 1e-13, n
+    with pytest.raises(nb.NegfError):
+        plan.run_queue([torch.tensor([0.1, 0.2], dtype=torch.float64, device="cuda")], outs, info)
+    plan.close()

@@ -42,7 +42,7 @@ def test_status_strings_and_version(L):
     from paper_2602_03438_amd import binding as nb
     assert nb.status_string(nb.NEGF_OK) == "ok"
     assert "converge" in nb.status_string(nb.NEGF_ENOCONV)
-    assert nb.negf_version() >= 100
+    assert nb.negf_version() >= nb.ABI_VERSION == 101
 
 
 def _fake_problem(nb_=4, b=8, n_e=3, h=True):
