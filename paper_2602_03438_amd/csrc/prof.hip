@@ -3,6 +3,7 @@
 #include "../../include/negf.h"
 #include "internal.h"
 
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -18,8 +19,9 @@ struct ProfRec {
   double flops, bytes;
 };
 std::mutex g_prof_mu;
-bool g_prof_on = false;
-unsigned g_prof_mask = ~0u;              // kernel classes whose launches get timing events
+// read on every launch without the lock (atomics: another thread may switch profiling meanwhile)
+std::atomic<bool> g_prof_on{false};
+std::atomic<unsigned> g_prof_mask{~0u}; // kernel classes whose launches get timing events
 std::vector<ProfRec> g_prof_pending;
 std::vector<hipEvent_t> g_prof_pool;
 negf_kernel_stats g_prof_acc[KC_COUNT];
@@ -42,26 +44,27 @@ hipEvent_t pool_get() {
 // the decimation and the zero-slab maps), striped over PROF_SLOTS counters per
 // class so that concurrent waves rarely add to the same address.
 __device__ unsigned long long g_prof_flops[KC_COUNT * PROF_SLOTS];
-unsigned long long* g_prof_flops_ptr = nullptr;
+std::atomic<unsigned long long*> g_prof_flops_ptr{nullptr};   // published before g_prof_on
 
 }  // namespace
 
 namespace negf {
 
 unsigned long long* prof_flop_slots(int cls) {
-  if (!g_prof_on || g_capturing || !g_prof_flops_ptr || cls < 0 || cls >= KC_COUNT) return nullptr;
-  return g_prof_flops_ptr + (long)cls * PROF_SLOTS;
+  if (!g_prof_on.load() || g_capturing || cls < 0 || cls >= KC_COUNT) return nullptr;
+  unsigned long long* p = g_prof_flops_ptr.load();
+  return p ? p + (long)cls * PROF_SLOTS : nullptr;
 }
 
 void prof_begin(int cls, hipStream_t s) {
-  if (!g_prof_on || g_capturing || cls < 0 || cls >= KC_COUNT || !((g_prof_mask >> cls) & 1u)) return;
+  if (!g_prof_on.load() || g_capturing || cls < 0 || cls >= KC_COUNT || !((g_prof_mask.load() >> cls) & 1u)) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   t_open = pool_get();
   if (t_open) (void)hipEventRecord(t_open, s);   // a failed record shows up when the pair is read
 }
 
 void prof_end(int cls, hipStream_t s, double flops, double bytes) {
-  if (!g_prof_on || !t_open || g_capturing) return;
+  if (!g_prof_on.load() || !t_open || g_capturing) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = pool_get();
   if (!e) return;
@@ -129,20 +132,21 @@ extern "C" {
 
 void negf_profile_time_classes(uint32_t mask) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_mask = mask;
+  g_prof_mask.store(mask);
 }
 
 void negf_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_on = on != 0;
+  if (!on) g_prof_on.store(false);
   if (on) {
-    // the counters of the current device, cleared (synchronous)
+    // the counters of the current device, cleared (synchronous), published before profiling turns on
     void* p = nullptr;
-    g_prof_flops_ptr = nullptr;
+    g_prof_flops_ptr.store(nullptr);
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_prof_flops)) == hipSuccess &&
         hipMemset(p, 0, sizeof(unsigned long long) * KC_COUNT * PROF_SLOTS) == hipSuccess &&
         hipDeviceSynchronize() == hipSuccess)
-      g_prof_flops_ptr = (unsigned long long*)p;
+      g_prof_flops_ptr.store((unsigned long long*)p);
+    g_prof_on.store(true);
   }
   if (on) {
     for (auto& r : g_prof_pending) {
@@ -172,9 +176,9 @@ negf_status negf_profile_read(negf_kernel_stats* stats) {
     g_prof_pool.push_back(r.b);
   }
   g_prof_pending.clear();
-  if (g_prof_flops_ptr) {
+  if (unsigned long long* fp = g_prof_flops_ptr.load()) {
     std::vector<unsigned long long> c((size_t)KC_COUNT * PROF_SLOTS);
-    if (hipMemcpy(c.data(), g_prof_flops_ptr, c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
+    if (hipMemcpy(c.data(), fp, c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
         hipSuccess) {
       st = NEGF_EHIP;
     } else {
@@ -183,7 +187,7 @@ negf_status negf_profile_read(negf_kernel_stats* stats) {
         for (int j = 0; j < PROF_SLOTS; ++j) f += (double)c[(size_t)k * PROF_SLOTS + j];
         g_prof_acc[k].flops += f;
       }
-      if (hipMemset(g_prof_flops_ptr, 0, c.size() * sizeof(unsigned long long)) != hipSuccess) st = NEGF_EHIP;
+      if (hipMemset(fp, 0, c.size() * sizeof(unsigned long long)) != hipSuccess) st = NEGF_EHIP;
     }
   }
   if (stats)

@@ -15,32 +15,44 @@ SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=unde
             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
 
 
-def asan_runtime() -> str:
-    """The shared AddressSanitizer runtime of the compiler that builds the sanitized library (a
-    process that loads the library must preload it)."""
+LIB_TSAN = os.path.join(HERE, "libnegf_hostsim_tsan.so")
+# host code only: ThreadSanitizer
+SANITIZE_THREAD = ["-Xarch_host", "-fsanitize=thread", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def runtime(name: str = "asan") -> str:
+    """The shared sanitizer runtime (``asan`` or ``tsan``) of the compiler that builds the
+    sanitized library (a process that loads the library must preload it)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    r = subprocess.run([hipcc, "-print-file-name=libclang_rt.asan-x86_64.so"], check=True, capture_output=True,
-                       text=True)
+    lib = f"libclang_rt.{name}-x86_64.so"
+    r = subprocess.run([hipcc, f"-print-file-name={lib}"], check=True, capture_output=True, text=True)
     path = r.stdout.strip()
     if not os.path.isabs(path):
         r = subprocess.run([hipcc, "-print-resource-dir"], check=True, capture_output=True, text=True)
-        path = os.path.join(r.stdout.strip(), "lib", "linux", "libclang_rt.asan-x86_64.so")
+        path = os.path.join(r.stdout.strip(), "lib", "linux", lib)
     return path
 
 
-def build(sanitize: bool = False) -> str:
+def asan_runtime() -> str:
+    return runtime("asan")
+
+
+def build(sanitize=False) -> str:
+    """sanitize: False, True (AddressSanitizer + UndefinedBehaviorSanitizer) or "thread"."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    out = os.path.join(ROOT, "_build", "hostsim_sanitized" if sanitize else "hostsim")
+    tsan = sanitize == "thread"
+    out = os.path.join(ROOT, "_build", "hostsim_tsan" if tsan else "hostsim_sanitized" if sanitize else "hostsim")
     os.makedirs(out, exist_ok=True)
+    san = SANITIZE_THREAD if tsan else SANITIZE if sanitize else []
     flags = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"),
-             "-I", CSRC, "-Wno-unused-result"] + (SANITIZE if sanitize else [])
+             "-I", CSRC, "-Wno-unused-result"] + san
     objs = []
     for src in (os.path.join(CSRC, "api.hip"), os.path.join(CSRC, "serinv.hip"), os.path.join(HERE, "hostsim.cpp")):
         obj = os.path.join(out, os.path.basename(src) + ".o")
         subprocess.run([hipcc, *flags, "-x", "hip", "-c", src, "-o", obj], check=True, capture_output=True)
         objs.append(obj)
-    lib = LIB_SANITIZED if sanitize else LIB
-    link = ["-shared-libasan", *SANITIZE] if sanitize else []
+    lib = LIB_TSAN if tsan else LIB_SANITIZED if sanitize else LIB
+    link = SANITIZE_THREAD if tsan else ["-shared-libasan", *SANITIZE] if sanitize else []
     subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *link, "-o", lib, *objs], check=True,
                    capture_output=True)
     return lib
@@ -48,4 +60,4 @@ def build(sanitize: bool = False) -> str:
 
 if __name__ == "__main__":
     import sys
-    print(build(sanitize="--sanitize" in sys.argv))
+    print(build(sanitize="thread" if "--tsan" in sys.argv else "--sanitize" in sys.argv))

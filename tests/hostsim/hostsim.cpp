@@ -9,6 +9,7 @@
 // info codes and the in-place conventions), with bounds assertions on every
 // batch item it touches.  It is test infrastructure only: the product library
 // libnegf.so never contains it.
+#include <atomic>
 #include "internal.h"
 
 #include <cassert>
@@ -387,14 +388,14 @@ hipError_t rt_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t) {
 // issue order, which is one valid schedule of the fork/join plan.
 hipError_t rt_stream_create(hipStream_t* s) {
   static int dummy[16];
-  static int next = 0;
+  static std::atomic<int> next{0};
   *s = (hipStream_t)&dummy[(next++) % 16];
   return hipSuccess;
 }
 hipError_t rt_stream_destroy(hipStream_t) { return hipSuccess; }
 hipError_t rt_event_create(hipEvent_t* e) {
   static int dummy[64];
-  static int next = 0;
+  static std::atomic<int> next{0};
   *e = (hipEvent_t)&dummy[(next++) % 64];
   return hipSuccess;
 }
@@ -409,7 +410,7 @@ hipError_t rt_graph_launch(void*, hipStream_t) { return hipSuccess; }
 hipError_t rt_graph_destroy(void*) { return hipSuccess; }
 double rt_wallclock_hz() { return 1e8; }
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t) {
-  static unsigned long long t = 0;
+  static std::atomic<unsigned long long> t{0};
   *dst = ++t;
   return hipSuccess;
 }
