@@ -967,6 +967,8 @@ def bench_learned(args):
     from paper_2602_03438_amd import binding as nb
     from paper_2602_03438_amd import learned as Lm
     b = args.learned_b
+    # points in flight per decimation call (bounds the workspace: ~54 MiB per point at b = 512)
+    lopts = nb.make_options(batch=1024)
     rng = np.random.Generator(np.random.PCG64(599))
     t_start = time.perf_counter()
     X_all, T_all = [], []
@@ -977,7 +979,7 @@ def bench_learned(args):
         gb = Lm.GPUBasis(basis)
         E = rng.uniform(-1.5, 1.5, args.learned_energies)
         prob = nb.Problem(nb.DeviceOnGPU(lead), E, eta=ETA)
-        out = nb.obc_surface([prob], 0)
+        out = nb.obc_surface([prob], 0, opts=lopts)
         g = out["g_surf"][0][:, 0].contiguous()
         T_all.append(gb.targets(g))
         X_all.append(torch.from_numpy(Lm.features(basis, E)).cuda())
@@ -1003,7 +1005,7 @@ def bench_learned(args):
         prob = nb.Problem(nb.DeviceOnGPU(lead), E, eta=ETA)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        plain = nb.obc_surface([prob], 0)
+        plain = nb.obc_surface([prob], 0, opts=lopts)
         torch.cuda.synchronize()
         res["plain"]["s"] += time.perf_counter() - t1
         t1 = time.perf_counter()
@@ -1011,11 +1013,11 @@ def bench_learned(args):
         Yc = net.infer_bf16(Xh)
         Y = Lm.signed_log(Yc, inverse=True)
         seeds = gb.seeds(Y)
-        seeded = nb.obc_surface([prob], 0, seed=seeds)
+        seeded = nb.obc_surface([prob], 0, opts=lopts, seed=seeds)
         torch.cuda.synchronize()
         res["seeded"]["s"] += time.perf_counter() - t1
         # the seeded closure alone (a zero seed: no learned information) for comparison
-        zero = nb.obc_surface([prob], 0, seed=torch.zeros_like(seeds))
+        zero = nb.obc_surface([prob], 0, opts=lopts, seed=torch.zeros_like(seeds))
         ip = plain["iters"].cpu().numpy()
         res["plain"]["iters"] += ip.tolist()
         it = seeded["iters"].cpu().numpy()
