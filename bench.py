@@ -58,6 +58,37 @@ def algorithmic_roofline(flops, seconds, note):
             "frac": r / PEAK["f64"], "traffic": None, "flop_count": "dense algorithmic: " + note}
 
 
+def executed_roofline(nb, stats, seconds, cmul, note=""):
+    """Roofline of the dominant kernel (the batched FP64 products) from the flops the kernels count as they
+    execute and the products' event-timed durations, plus the executed fraction of the whole timed region."""
+    g = stats["gemm_f64"]
+    real = 3 if cmul == 3 else 4
+    ex = g["flops"] / (g["total_ms"] * 1e-3) if g["total_ms"] > 0 else 0.0
+    step = sum(v["flops"] for v in stats.values())
+    return {"bound": "mfma", "kernel": "zgemm_kernel<double> (batched complex FP64 product)", "achieved": ex / 1e12,
+            "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s", "frac": ex / PEAK["f64"], "traffic": None,
+            "launches": int(g["launches"]), "avg_launch_ms": g["total_ms"] / max(1, g["launches"]),
+            "flop_count": f"{2 * real} M N K per complex product ({real} real products), counted by the kernels",
+            "step_executed_tflops": step / seconds / 1e12, "step_frac": step / seconds / PEAK["f64"], "note": note}
+
+
+def profiled(nb, fn):
+    """fn() with the kernels counting their executed flops and the products timed by events; returns
+    (fn's result, wall seconds, per-class stats)."""
+    import torch
+    torch.cuda.synchronize()
+    nb.negf_profile_time_classes(1 << nb.KC_NAMES.index("gemm_f64"))
+    nb.negf_profile_enable(1)
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = nb.negf_profile_read()
+    nb.negf_profile_enable(0)
+    nb.negf_profile_time_classes(~0)
+    return out, dt, stats
+
+
 def kernel_hash(source="gemm.hip"):
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2602_03438_amd", "csrc", source), "rb") as fh:
@@ -204,7 +235,8 @@ def main():
     ap.add_argument("--inv-nb", type=int, default=0, help="inversion panel width (0: tuned)")
     ap.add_argument("--cmul", type=int, choices=[3, 4], default=3,
                     help="real products per complex double product (3: Gauss's method)")
-    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm", "serinv", "econv", "scba"],
+    ap.add_argument("--workload", choices=["ribbon", "uneven", "learned", "gemm", "serinv", "econv", "scba", "small",
+                                           "scattering"],
                     default="ribbon",
                     help="ribbon: the headline Nb=60 b=512 measurement; uneven: six devices of different block "
                          "shapes x 4 k-points in one plan; learned: the MLP-seeded lead decimation; gemm: the "
@@ -218,6 +250,9 @@ def main():
                     "workload")
     ap.add_argument("--gemm-batch", type=int, default=256, help="products per launch in the gemm workload")
     ap.add_argument("--scba-energies", type=int, default=32, help="energies of the scba workload's uniform grid")
+    ap.add_argument("--scattering-energies", type=int, default=512, help="energies per k-point of the scattering "
+                                                                          "workload")
+    ap.add_argument("--scattering-batch", type=int, default=64, help="points per call in the scattering workload")
     ap.add_argument("--scba-freqs", type=int, default=17, help="bath frequencies of the scba workload")
     ap.add_argument("--scba-strength", type=float, default=0.05, help="bath strength of the scba workload")
     ap.add_argument("--serinv-points", default="1,2,4,8", help="energy points per call in the serinv workload")
@@ -272,6 +307,10 @@ def main():
         return bench_econv(args)
     if args.workload == "scba":
         return bench_scba(args)
+    if args.workload == "small":
+        return bench_small(args)
+    if args.workload == "scattering":
+        return bench_scattering(args)
     if args.workload == "uneven":
         # four worker streams (the hardware queues HIP gives a process by default); each device
         # shape's points form one chunk (see --uneven-batch)
@@ -544,6 +583,248 @@ def bench_econv(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_small(args):
+    """The small ballistic workload: a random device Nb = 32, b = 8 (seed 1), the 1D chain (b = 1,
+    Nb = 32), the chain folded into cells of 8 sites and a periodic random wire (b = 8, seed 1), each at
+    64 energies in [-3, 3], eta = 1e-6: 256 points per step, G^R (every block) and the transmission per
+    point through negf_rgf_retarded and negf_transmission, both leads.  Timed eagerly and as a captured
+    graph replayed (each replay checked equal to the eager result); plain FP64 and the refined
+    single-product form of the retarded call.  Every point is compared with the oracle (G^R diagonal
+    and T), the chains with the closed form (T = 1 inside |E| < 2t, 0 outside) and the wire with
+    integers; the oracle over all 256 points is the CPU baseline."""
+    import torch
+    import workloads as w
+    from oracle import leads as oleads
+    from oracle import rgf as orgf
+    from paper_2602_03438_amd import binding as nb
+    eta = 1e-6
+    E = np.linspace(-3.0, 3.0, 64)
+    devs = {"random": w.random_device(32, 8, 1), "chain": w.chain_device(32),
+            "folded_chain": w.folded_chain_device(32, 8), "wire": w.periodic_wire_device(32, 8, 1)}
+    probs = [nb.Problem(nb.DeviceOnGPU(d), E, eta=eta, mu_l=MU_L, mu_r=MU_R, kT=KT) for d in devs.values()]
+    npts = len(probs) * E.size
+    ws_r, ws_t = nb.Workspace(), nb.Workspace()
+    res = {}
+    for prec, name in ((nb.PLAIN_FP64, "plain"), (nb.FP32_REFINE, "fp32_refine")):
+        outs = nb._rgf_outputs(probs, False, False, True)
+
+        def step():
+            r = nb.rgf_retarded(probs, prec, ws=ws_r, outputs=outs)
+            t = nb.transmission(probs, ws=ws_t)
+            return r["info"], t
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        reps = 20 * args.steps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            info, tr = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        gd = nb._views(outs, probs)["GR_diag"]
+        eager = {k: v.clone() for k, v in outs.items() if v is not None}
+        T_eager = tr["T"].clone()
+        # the same step captured once and replayed
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        with torch.cuda.graph(g):
+            _, tg = step()
+        torch.cuda.synchronize()
+        same = True
+        for _ in range(2):
+            for v in outs.values():
+                if v is not None:
+                    v.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            same = same and all(torch.equal(outs[k], eager[k]) for k in eager) and torch.equal(tg["T"], T_eager)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        dtg = (time.perf_counter() - t0) / reps
+        del g
+        res[name] = {"points_per_s": npts / dt, "ms_per_step": dt * 1e3, "graph_points_per_s": npts / dtg,
+                     "graph_ms_per_step": dtg * 1e3, "graph_replays_equal_eager": bool(same),
+                     "info_nonzero": int(torch.count_nonzero(info).item()), "gd": [x.cpu().numpy() for x in gd],
+                     "T": T_eager.cpu().numpy()}
+        log(f"small workload {name}: {npts / dt:.0f} points/s eager, {npts / dtg:.0f} points/s graph-replayed "
+            f"(replays equal to eager: {same})")
+    # the oracle at every point: G^R diagonal and T; the CPU baseline is its time.  A device without
+    # broadening inside (leads at eta = 1e-6 only) is nearly singular at energies of states localised
+    # away from the leads, so each point's G^R error is read against the oracle's own spread there
+    # (its change when every inversion is Newton-refined)
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    from helpers import refined_inversions
+    t0 = time.perf_counter()
+    refs = [[orgf.solve_point(d, float(e), eta, MU_L, MU_R, KT, lesser_greater=False, want_T=True) for e in E]
+            for d in devs.values()]
+    cpu_s = time.perf_counter() - t0
+    with refined_inversions():
+        refs2 = [[orgf.solve_point(d, float(e), eta, MU_L, MU_R, KT, lesser_greater=False) for e in E]
+                 for d in devs.values()]
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    spread = [[rel(refs2[q][k].GR_diag, refs[q][k].GR_diag) for k in range(E.size)] for q in range(len(devs))]
+    errs = {}
+    for name, bar in (("plain", 1e-10), ("fp32_refine", 1e-6)):
+        e_all, e_stable, n_stable, t_err = [], [], 0, 0.0
+        for q, d in enumerate(devs):
+            for k in range(E.size):
+                err = rel(res[name]["gd"][q][k], refs[q][k].GR_diag)
+                e_all.append(err)
+                if 4.0 * spread[q][k] <= bar:
+                    e_stable.append(err)
+                t_err = max(t_err, abs(float(res[name]["T"][q * E.size + k]) - refs[q][k].T))
+        errs[name] = {"GR_diag_max_rel_all_points": max(e_all), "GR_diag_median_rel": float(np.median(e_all)),
+                      "bar": bar, "points_where_oracle_stable_to_bar": len(e_stable),
+                      "GR_diag_max_rel_stable_points": max(e_stable) if e_stable else None,
+                      "stable_points_meeting_bar": int(sum(e <= bar for e in e_stable)),
+                      "oracle_spread_max": float(np.max(spread)), "T_max_abs": t_err}
+    T_plain = res["plain"]["T"].reshape(len(devs), E.size)
+    inband = np.abs(E) < 2.0
+    dev_int = np.abs(T_plain[3] - np.round(T_plain[3]))
+    closed = {"chain_T_vs_step": float(np.abs(T_plain[1] - inband).max()),
+              "folded_chain_T_vs_step": float(np.abs(T_plain[2] - inband).max()),
+              "wire_T_vs_integer_max": float(dev_int.max()), "wire_T_vs_integer_median": float(np.median(dev_int)),
+              "wire_points_within_1e-6_of_an_integer": int(np.count_nonzero(dev_int < 1e-6)),
+              "wire_note": "T steps between integers at the wire's subband edges; within ~eta of an edge it is not "
+                           "an integer"}
+    sr = {}
+    for q, d in enumerate(devs):
+        it = [oleads.lead_self_energy(devs[d], side, float(e), eta).iters for side in (0, 1) for e in E[::8]]
+        sr[d] = {"oracle_mean_steps": float(np.mean(it)), "oracle_max_steps": int(np.max(it))}
+    for name in res:
+        res[name].pop("gd")
+        res[name].pop("T")
+    # dense algorithmic flops of one step: per point G^R (8 + 56 (nb - 1)) b^3, the transmission's corner
+    # recursion 16 (nb - 1) b^3 and both leads 2 (56 K + 24) b^3 with K = 30 steps
+    step_flops = E.size * sum(float(d.b) ** 3 * ((8 + 56 * (d.nb - 1)) + 16 * (d.nb - 1) + 2 * (56 * 30 + 24))
+                              for d in devs.values())
+    best = res["plain"]["graph_points_per_s"]
+    rate = step_flops / (res["plain"]["graph_ms_per_step"] * 1e-3)
+    line = {"metric": "energy points/s, G^R + transmission of the small ballistic workload (Nb=32, b=8)",
+            "value": best, "unit": "energy points/s", "n_gpus": 1, "steps": 20 * args.steps, "warmup": args.warmup,
+            "ms_per_step": res["plain"]["graph_ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "random device Nb=32 b=8 (seed 1), 1D chain Nb=32 b=1, chain folded into cells "
+                                   "of 8 (Nb=32), periodic random wire Nb=32 b=8; 64 energies in [-3, 3] each, "
+                                   "eta=1e-6; one step = negf_rgf_retarded + negf_transmission over the 256 points, "
+                                   "value = graph-replayed plain FP64"},
+            "forms": res, "errors_vs_oracle_every_point": errs, "closed_forms": closed, "decimation_steps": sr,
+            "roofline": {"bound": "mfma", "achieved": rate / 1e12, "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                         "frac": rate / PEAK["f64"], "traffic": None,
+                         "note": "blocks of 8 x 8 (and 1 x 1): every launch is a few microseconds of latency; the "
+                                 "fraction of the matrix peak is tiny by construction"},
+            "cpu_baseline": {"value": npts / cpu_s, "unit": "energy points/s", "cores": os.cpu_count(),
+                             "kind": "oracle", "sample": f"all {npts} points (G^R sweeps, both leads, T) in NumPy "
+                                                         f"complex128", "seconds": cpu_s}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_scattering(args):
+    """The scattering workload: the benchmark device (Nb = 60, b = 512) with block-diagonal scattering
+    self-energies (norm 0.01, seed 3) at 4 transverse momenta k = 0, pi/4, pi/2, 3 pi/4 (H_ii(k), seed 31)
+    x --scattering-energies energies on [-1.5, 1.5]: G^R (diagonal, upper, lower), G^< and G^>
+    (diagonal, upper) and both leads per point, in calls of --scattering-batch points (one k each);
+    plain FP64 and the refined single-product form, each over the whole grid.  The point in the middle
+    of the k = 0 grid is compared with the oracle for every output (with the oracle's own spread under
+    refined inversions), and its oracle time is the CPU baseline."""
+    import torch
+    import workloads as w
+    from oracle import rgf as orgf
+    from paper_2602_03438_amd import autotune
+    from paper_2602_03438_amd import binding as nb
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    from helpers import oracle_spread
+    log("generating the Nb=60 b=512 device with scattering self-energies and its 4 k-points ...")
+    base = w.scattering_self_energies(w.slab_device(NB, B, SEED), 3)
+    ks = [np.pi * j / 4 for j in range(4)]
+    devs = [w.k_device(base, 31, k) for k in ks]
+    gdevs = [nb.DeviceOnGPU(d) for d in devs]
+    E = np.linspace(-1.5, 1.5, args.scattering_energies)
+    nbat = args.scattering_batch
+    t = autotune.lookup(B, args.cmul)
+    opts = nb.make_options(inv_nb=args.inv_nb or t["inv_nb"], cmul=args.cmul, gemm_tile=t["gemm_tile"],
+                           gemm_tile_f32=t["gemm_tile_f32"], sr_max_iter=args.sr_max_iter)
+    probs = [nb.Problem(g, E[:nbat], eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT) for g in gdevs]
+    ws = nb.Workspace()
+    outs = nb._rgf_outputs([probs[0]], True, True, True)
+    calls = [(q, e0) for q in range(len(devs)) for e0 in range(0, E.size, nbat)]
+    k_mid = E.size // 2
+    res = {}
+    for prec, name in ((nb.PLAIN_FP64, "plain"), (nb.FP32_REFINE, "fp32_refine")):
+        def call(q, e0):
+            pr = probs[q]
+            pr.energies.copy_(torch.from_numpy(np.ascontiguousarray(E[e0:e0 + nbat])).to("cuda"))
+            return nb.rgf_lesser_greater([pr], prec, opts=opts, ws=ws, outputs=outs, greater=True)["info"]
+        for _ in range(args.warmup):
+            call(0, 0)
+        torch.cuda.synchronize()
+
+        def sweep_all():
+            bad = 0
+            for j, (q, e0) in enumerate(calls):
+                bad += int(torch.count_nonzero(call(q, e0)).item())
+                if j % 8 == 7:
+                    log(f"  scattering {name}: {j + 1}/{len(calls)} calls")
+            return bad
+        if prec == nb.PLAIN_FP64:
+            n_bad, dt, stats = profiled(nb, sweep_all)
+            roof = executed_roofline(nb, stats, dt, args.cmul)
+        else:
+            t0 = time.perf_counter()
+            n_bad = sweep_all()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        # the sampled point: k = 0, the middle energy (its call recomputed, untimed)
+        call(0, (k_mid // nbat) * nbat)
+        torch.cuda.synchronize()
+        v = nb._views(outs, [probs[0]])
+        pt = {n: v[n][0][k_mid % nbat].cpu().numpy()
+              for n in ("GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper", "GG_diag", "GG_upper")}
+        res[name] = {"points_per_s": len(calls) * nbat / dt, "seconds": dt, "info_nonzero": n_bad, "pt": pt}
+        log(f"scattering {name}: {len(calls) * nbat / dt:.2f} points/s, {n_bad} points flagged")
+    names = ("GR_diag", "GR_upper", "GR_lower", "GL_diag", "GL_upper", "GG_diag", "GG_upper")
+    log(f"oracle at E = {E[k_mid]:+.4f}, k = 0 ...")
+    t0 = time.perf_counter()
+    ref = orgf.solve_point(devs[0], float(E[k_mid]), ETA, MU_L, MU_R, KT, greater=True)
+    cpu_s = time.perf_counter() - t0
+    _, spread = oracle_spread(lambda: orgf.solve_point(devs[0], float(E[k_mid]), ETA, MU_L, MU_R, KT, greater=True),
+                              names)
+    for name in res:
+        pt = res[name].pop("pt")
+        res[name]["errors_vs_oracle"] = {n: float(np.linalg.norm(pt[n] - getattr(ref, n)) / np.linalg.norm(getattr(ref, n)))
+                                         for n in names}
+    res_sr = {"oracle_lead_steps": [ref.lead_l.iters, ref.lead_r.iters],
+              "oracle_lead_residuals": [ref.lead_l.residual, ref.lead_r.residual]}
+    flops = point_flops(NB, B) + float(B) ** 3 * (16 + 64 * (NB - 1))      # + G^>
+    value = res["plain"]["points_per_s"]
+    line = {"metric": "energy points/s, RGF G^R + G^< + G^> with scattering self-energies at 4 k-points (Nb=60, b=512)",
+            "value": value, "unit": "energy points/s", "n_gpus": 1, "steps": len(calls), "warmup": args.warmup,
+            "ms_per_step": res["plain"]["seconds"] / len(calls) * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"nano-ribbon-like slab device Nb={NB} b={B} with block-diagonal scattering "
+                                   f"self-energies (norm 0.01), 4 k-points x {E.size} energies on [-1.5, 1.5], "
+                                   f"eta={ETA}; one step = one call of {nbat} points (one k)",
+                       "real_products_per_complex_product": args.cmul, "sr_max_iter": args.sr_max_iter},
+            "forms": res, "sampled_point": {"E": float(E[k_mid]), "k": 0.0, "oracle_spread": spread},
+            "decimation": res_sr,
+            "roofline": roof,
+            "algorithmic": algorithmic_roofline(flops, 1.0 / value,
+                                                "G^R + G^< + G^> of one energy point (both leads, 28 decimation "
+                                                "steps); above 1 because the executed work is smaller (three real "
+                                                "products per complex one, zero coupling slabs skipped)"),
+            "cpu_baseline": {"value": 1.0 / cpu_s, "unit": "energy points/s", "cores": os.cpu_count(),
+                             "kind": "oracle", "sample": f"1 point (E={E[k_mid]:.4f}, k=0): both leads, G^R, G^<, "
+                                                         f"G^> sweeps in NumPy complex128", "seconds": cpu_s}}
+    print(json.dumps(line), flush=True)
+
+
 def bench_scba(args):
     """The self-consistent loop of Fig. 1 around Eq. (1)-(3) at the headline device (Nb = 60,
     b = 512): --scba-energies energies, uniform on [-1.5, 1.5], and a boson bath of --scba-freqs
@@ -581,11 +862,8 @@ def bench_scba(args):
         v.zero_()
     torch.cuda.synchronize()
     log(f"scba: {args.steps} timed iteration(s)")
-    t0 = time.perf_counter()
-    r = nb.scba(prob, gWl, gWg, k0, scale, mixing=0.5, tol=0.0, max_iter=args.steps, opts=opts, ws=ws, outputs=outs,
-                sigmas=sig)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    r, dt, stats = profiled(nb, lambda: nb.scba(prob, gWl, gWg, k0, scale, mixing=0.5, tol=0.0, max_iter=args.steps,
+                                                opts=opts, ws=ws, outputs=outs, sigmas=sig))
     its = r["n_iter"]
     log(f"scba: {its} iteration(s) in {dt:.2f} s, residuals {['%.2e' % h for h in r['history']]}")
     # the two convolutions of one iteration, alone
@@ -617,10 +895,11 @@ def bench_scba(args):
             "ms_per_iteration": it_ms, "convolutions_ms_per_iteration": conv_ms,
             "convolution_share": conv_ms / it_ms, "residual_history": r["history"], "status": r["status"],
             "info_nonzero": int(torch.count_nonzero(r["info"]).item()),
-            "roofline": algorithmic_roofline(flops, it_ms * 1e-3 / n_e,
-                                             "G^R + G^< + G^> of one energy point (both leads, 28 decimation steps) "
-                                             "per (iteration time / energies); the convolutions add no flops to "
-                                             "the count"),
+            "roofline": executed_roofline(nb, stats, dt, args.cmul, "timed iterations, products event-timed"),
+            "algorithmic": algorithmic_roofline(flops, it_ms * 1e-3 / n_e,
+                                                "G^R + G^< + G^> of one energy point (both leads, 28 decimation "
+                                                "steps) per (iteration time / energies); the convolutions add no "
+                                                "flops to the count"),
             "cpu_baseline": None,
             "cpu_baseline_note": "not taken: one oracle iteration at this shape solves every energy point "
                                  "(about 1.4e12 flop each) on the host"}
