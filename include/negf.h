@@ -292,8 +292,9 @@ negf_status negf_transpose(int64_t rows, int64_t cols, const void* src, void* ds
  * negf_rgf_lesser_greater (GR_lower may be NULL; G^> is required), info
  * [n_e] per point of the last solve.  n_iter (host): solves performed;
  * history (host, nullable, max_iter doubles): r_0 .. r_{n_iter-1}.
- * The call synchronises `stream` once per iteration (the stopping decision is
- * taken on the host) and so cannot be captured in a graph.
+ * negf_scba drives negf_scba_step from the host and synchronises `stream` once
+ * per iteration to read the loop state (the stopping decision), so it cannot
+ * be captured in a graph; negf_scba_step can.
  * Requirements: 0 <= k0 < n_w, n_e + n_w - 1 <= 4096, 0 < mixing <= 1,
  * tol >= 0, max_iter >= 1.  Returns NEGF_OK when r_n <= tol was reached,
  * NEGF_ENOCONV when max_iter solves ended above tol, NEGF_ENONFINITE when r_n
@@ -301,6 +302,26 @@ negf_status negf_transpose(int64_t rows, int64_t cols, const void* src, void* ds
  * (EINVAL) before any work.  Workspace: negf_scba_workspace_bytes(...). */
 size_t negf_scba_workspace_bytes(const negf_problem* problem, negf_precision prec, const negf_options* opt,
                                  int32_t n_w);
+/* One iteration of that loop, enqueued on `stream` with no host
+ * synchronisation (capturable in a graph); arguments as for negf_scba plus:
+ * it: the iteration index (it = 0 starts a loop: the state is reset and
+ * Sigma^R formed from sig_l, sig_g); update: 0 = never mix (the last
+ * iteration of a fixed count, so that the outputs hold Sigma_n and the Green's
+ * functions it produced); history: nullable device array, history[it] = r_it;
+ * state: device int32[2], [0] = solves performed until r <= tol (or so far),
+ * [1] = 0 running, 1 converged, 2 non-finite residual.  Once [1] != 0 the
+ * self-energies are no longer changed, so further iterations recompute the
+ * same Green's functions (a fixed number of iterations ends where a loop
+ * stopped at convergence ends).  The same workspace (negf_scba_workspace_bytes)
+ * must serve every iteration of a loop only for its temporaries; the state
+ * and history live in caller memory.  Errors: EINVAL (as negf_scba, it < 0,
+ * state NULL), EHIP. */
+negf_status negf_scba_step(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
+                           int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
+                           double mixing, double tol, int32_t it, int32_t update, void* sig_r, void* sig_l,
+                           void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper,
+                           void* GG_diag, void* GG_upper, int32_t* info, double* history, int32_t* state,
+                           void* workspace, size_t ws_bytes, void* stream);
 negf_status negf_scba(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
                       int32_t k0, const void* W_lesser, const void* W_greater, const double* scale, double mixing,
                       double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g, void* GR_diag,

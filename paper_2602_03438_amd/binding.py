@@ -101,6 +101,9 @@ def lib():
     L.negf_scba.argtypes = [P(negf_problem), i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32, vp, vp,
                             vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(dbl), vp, sz, vp]
     L.negf_scba.restype = C.c_int
+    L.negf_scba_step.argtypes = [P(negf_problem), i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32, i32,
+                                 vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.negf_scba_step.restype = C.c_int
     L.negf_transmission.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, sz, vp]
     L.negf_transmission.restype = C.c_int
     L.negf_zgemm_batched.argtypes = [C.c_char, C.c_char, i32, i32, i32, P(dbl), vp, i64, i64, vp, i64, i64, P(dbl),
@@ -595,6 +598,54 @@ def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_ite
     res["history"] = [hist[i] for i in range(n_iter.value)]
     res["status"] = int(code)
     return res
+
+
+class ScbaLoop:
+    """The loop of negf_scba as single steps (negf_scba_step): nothing synchronises, so a run of
+    steps can be captured in a graph.  Holds the self-energies, the outputs, the per-point info,
+    the device history and the device state {solves, 0 running / 1 converged / 2 non-finite}."""
+
+    def __init__(self, problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_steps=64,
+                 prec=PLAIN_FP64, opts=None, lower=True):
+        torch = _torch()
+        self.problem, self.Wl, self.Wg, self.k0 = problem, W_lesser, W_greater, int(k0)
+        self.scale = (C.c_double * 2)(complex(scale).real, complex(scale).imag)
+        self.mixing, self.tol, self.prec, self.opts = float(mixing), float(tol), prec, opts
+        self._arr = _problem_array([problem])
+        dv = problem.dev
+        self.n_w = int(W_lesser.shape[0])
+        for t in (W_lesser, W_greater):
+            if (not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous()
+                    or tuple(t.shape) != (self.n_w, dv.nb, dv.b, dv.b)):
+                raise NegfError("W_lesser / W_greater must be contiguous complex128 device tensors [n_w, nb, b, b]")
+        o = C.byref(opts) if opts else None
+        nbytes = lib().negf_scba_workspace_bytes(self._arr, prec, o, self.n_w)
+        if nbytes == 0:
+            raise NegfError("invalid problem or bath for the self-consistent loop")
+        self.ws = Workspace().get(nbytes)
+        shape = (problem.n_e, dv.nb, dv.b, dv.b)
+        self.sig = {k: torch.zeros(shape, dtype=torch.complex128, device="cuda") for k in ("sig_r", "sig_l", "sig_g")}
+        self.out = _rgf_outputs([problem], True, True, lower)
+        self.info = torch.zeros(problem.n_e, dtype=torch.int32, device="cuda")
+        self.history = torch.zeros(max(1, int(max_steps)), dtype=torch.float64, device="cuda")
+        self.state = torch.zeros(2, dtype=torch.int32, device="cuda")
+
+    def step(self, it, update=True):
+        if not 0 <= it < self.history.numel():
+            raise NegfError("iteration index beyond the history")
+        o = self.out
+        check(lib().negf_scba_step(self._arr, self.prec, C.byref(self.opts) if self.opts else None, self.n_w, self.k0,
+                                   _ptr(self.Wl), _ptr(self.Wg), self.scale, self.mixing, self.tol, int(it),
+                                   int(bool(update)), _ptr(self.sig["sig_r"]), _ptr(self.sig["sig_l"]),
+                                   _ptr(self.sig["sig_g"]), _ptr(o["GR_diag"]), _ptr(o["GR_upper"]),
+                                   _ptr(o.get("GR_lower")), _ptr(o["GL_diag"]), _ptr(o["GL_upper"]),
+                                   _ptr(o["GG_diag"]), _ptr(o["GG_upper"]), _ptr(self.info), _ptr(self.history),
+                                   _ptr(self.state), _ptr(self.ws), self.ws.numel(), _stream()), "negf_scba_step")
+
+    def run(self, n):
+        """n steps, the last without mixing."""
+        for it in range(n):
+            self.step(it, update=it < n - 1)
 
 
 def transpose(X, out=None):

@@ -3,12 +3,17 @@
 // rebuild the self-energies from G^<> by the energy convolution of Eq. (3),
 // measure how far they moved, mix, repeat.
 //
-// Everything an iteration computes runs on the device: the sweeps, two
-// convolutions (lesser, greater) that read the energy-major diagonal blocks
-// the sweeps wrote, one streaming pass for the residual and one for the
-// mixing.  The host only reads the two sums of the residual to decide whether
-// to stop.  Per energy the self-energies are nb b b complex elements; the
-// problem handed to the sweeps points at them with sc_stride = nb b b.
+// One iteration (negf_scba_step) runs entirely on the device and is enqueued
+// without any host synchronisation: the sweeps, two convolutions (lesser,
+// greater) that read the energy-major diagonal blocks the sweeps wrote, one
+// streaming pass for the residual, whose last workgroup also records the
+// residual and the loop state in device memory, and one mixing pass that reads
+// that state and leaves the self-energies alone once the loop has converged
+// (so that a fixed number of captured iterations ends on the same self-energies
+// and Green's functions as a loop stopped at convergence).  negf_scba drives the
+// steps from the host and reads the state after each one to stop early.  Per
+// energy the self-energies are nb b b complex elements; the problem handed to
+// the sweeps points at them with sc_stride = nb b b.
 #include "../../include/negf.h"
 #include "internal.h"
 
@@ -73,8 +78,12 @@ __global__ void __launch_bounds__(SB) resid_partial_kernel(long n, const double2
   }
 }
 
-// out[0], out[1] = the sums of the nparts partial pairs (one workgroup)
-__global__ void __launch_bounds__(SB) resid_final_kernel(int nparts, const double* part, double* out) {
+// The residual r = sqrt(sum |F - S|^2 / sum |F|^2) of iteration `it` from the nparts partial pairs (one
+// workgroup, fixed order): last[0] = r, history[it] = r (history nullable), and the loop state, while it is
+// still running (state[1] == 0): state[0] = it + 1 (solves so far), state[1] = 1 once r <= tol, 2 if r is not
+// finite.  A converged or failed loop keeps its state.
+__global__ void __launch_bounds__(SB) resid_final_kernel(int nparts, const double* part, double tol, int it,
+                                                         double* last, double* history, int* state) {
   __shared__ double red[SB];
   double num = 0.0, den = 0.0;
   for (int w = threadIdx.x; w < nparts; w += SB) {
@@ -84,16 +93,32 @@ __global__ void __launch_bounds__(SB) resid_final_kernel(int nparts, const doubl
   num = wg_sum(num, red);
   den = wg_sum(den, red);
   if (threadIdx.x == 0) {
-    out[0] = num;
-    out[1] = den;
+    const double r = den > 0.0 ? sqrt(num / den) : (num == 0.0 ? 0.0 : INFINITY);
+    last[0] = r;
+    if (history) history[it] = r;
+    if (state[1] == 0) {
+      state[0] = it + 1;
+      state[1] = !isfinite(r) ? 2 : (r <= tol ? 1 : 0);
+    }
   }
 }
 
-// with F: S^<> += m (F^<> - S^<>); then S^R = (S^> - S^<) / 2 (without F only the latter).  U elements
-// SB apart per thread and pass, all loads first (as in the residual).
+// state = {0, 0}: a new loop
+__global__ void scba_reset_kernel(int* state) {
+  if (threadIdx.x == 0) {
+    state[0] = 0;
+    state[1] = 0;
+  }
+}
+
+// with F: S^<> += m (F^<> - S^<>); then S^R = (S^> - S^<) / 2 (without F only the latter).  Nothing is
+// written once the loop state (nullable) says converged or failed.  U elements SB apart per thread and
+// pass, all loads first (as in the residual).
 __global__ void __launch_bounds__(SB) mix_kernel(long n, double m, const double2* __restrict__ Fl,
                                                  const double2* __restrict__ Fg, double2* __restrict__ Sl,
-                                                 double2* __restrict__ Sg, double2* __restrict__ Sr) {
+                                                 double2* __restrict__ Sg, double2* __restrict__ Sr,
+                                                 const int* state) {
+  if (state && state[1] != 0) return;
   for (long x0 = (long)blockIdx.x * SB * U + threadIdx.x; x0 < n; x0 += (long)gridDim.x * SB * U) {
     double2 sl[U], sg[U], fl[U], fg[U];
 #pragma unroll
@@ -139,7 +164,7 @@ bool scba_layout(const negf_problem* problem, negf_precision prec, const negf_op
   if (L.rgf == 0 || L.ec == 0) return false;
   L.sig = (size_t)p.n_e * p.dev.nb * p.dev.b * p.dev.b * sizeof(double2);
   L.total = up256(L.rgf) + up256(L.ec) + 2 * up256(L.sig) + up256(2 * RPARTS * sizeof(double)) +
-            up256(2 * sizeof(double)) + 256;
+            up256(sizeof(double)) + up256(2 * sizeof(int)) + 256;
   return true;
 }
 
@@ -150,6 +175,116 @@ inline bool a16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 using namespace negf;
 
+namespace negf {
+namespace {
+
+struct StepArgs {
+  const negf_problem* problem;
+  negf_precision prec;
+  const negf_options* opt;
+  int32_t n_w, k0;
+  const void *W_lesser, *W_greater;
+  const double* scale;
+  double mixing, tol;
+  void *sig_r, *sig_l, *sig_g;
+  void *GR_diag, *GR_upper, *GR_lower, *GL_diag, *GL_upper, *GG_diag, *GG_upper;
+  int32_t* info;
+  void* workspace;
+  size_t ws_bytes;
+};
+
+// argument checks shared by the step and the driver; fills the layout
+negf_status check_step(const StepArgs& a, ScbaLayout& L) {
+  if (!a.problem || !a.scale) return NEGF_EINVAL;
+  const negf_problem& p0 = *a.problem;
+  const negf_device& d0 = p0.dev;
+  if (d0.sig_r_sc || d0.sig_l_sc || d0.sig_g_sc || p0.sc_stride != 0) return NEGF_EINVAL;
+  if (a.k0 < 0 || a.k0 >= a.n_w || !(a.mixing > 0.0 && a.mixing <= 1.0) || !(a.tol >= 0.0)) return NEGF_EINVAL;
+  if (!scba_layout(a.problem, a.prec, a.opt, a.n_w, L)) return NEGF_EINVAL;
+  const void* req[] = {a.W_lesser, a.W_greater, a.sig_r, a.sig_l, a.sig_g, a.GR_diag, a.GR_upper, a.GL_diag,
+                       a.GL_upper, a.GG_diag, a.GG_upper, a.info, a.workspace};
+  for (const void* q : req)
+    if (!q || !a16(q)) return NEGF_EINVAL;
+  if (a.GR_lower && !a16(a.GR_lower)) return NEGF_EINVAL;
+  if (a.sig_r == a.sig_l || a.sig_r == a.sig_g || a.sig_l == a.sig_g) return NEGF_EINVAL;
+  if (a.ws_bytes < L.total) return NEGF_EINVAL;
+  return NEGF_OK;
+}
+
+struct Carved {
+  void *rgf, *ec;
+  double2 *Fl, *Fg;
+  double *part, *last;
+  int* state;
+};
+
+Carved carve(void* workspace, const ScbaLayout& L) {
+  Carved c;
+  char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  c.rgf = base;
+  base += up256(L.rgf);
+  c.ec = base;
+  base += up256(L.ec);
+  c.Fl = (double2*)base;
+  base += up256(L.sig);
+  c.Fg = (double2*)base;
+  base += up256(L.sig);
+  c.part = (double*)base;
+  base += up256(2 * RPARTS * sizeof(double));
+  c.last = (double*)base;
+  base += up256(sizeof(double));
+  c.state = (int*)base;
+  return c;
+}
+
+// iteration `it` of the loop (it = 0 starts one: state reset, Sigma^R formed from Sigma^<, Sigma^>);
+// `update` = 0 never mixes (the last iteration of a fixed count)
+negf_status step_impl(const StepArgs& a, const ScbaLayout& L, const Carved& c, int it, int update, double* history,
+                      int* state, hipStream_t s) {
+  const negf_problem& p0 = *a.problem;
+  const negf_device& d0 = p0.dev;
+  const long nbb = (long)d0.nb * d0.b * d0.b;
+  const long n = (long)p0.n_e * nbb;
+  double2* Sl = (double2*)a.sig_l;
+  double2* Sg = (double2*)a.sig_g;
+  double2* Sr = (double2*)a.sig_r;
+  const unsigned mix_grid = (unsigned)std::min<long>((n + SB * U - 1) / (SB * U), MIX_WG);
+  const unsigned part_grid = (unsigned)std::min<long>((n + SB * U - 1) / (SB * U), RPARTS);
+  if (it == 0) {
+    prof_begin(KC_ELEM, s);
+    hipLaunchKernelGGL(scba_reset_kernel, dim3(1), dim3(64), 0, s, state);
+    hipLaunchKernelGGL(mix_kernel, dim3(mix_grid), dim3(SB), 0, s, n, 0.0, (const double2*)nullptr,
+                       (const double2*)nullptr, Sl, Sg, Sr, (const int*)nullptr);
+    prof_end(KC_ELEM, s, 0.0, 48.0 * (double)n);
+    if (hipGetLastError() != hipSuccess) return NEGF_EHIP;
+  }
+  negf_problem pq = p0;
+  pq.dev.sig_r_sc = a.sig_r;
+  pq.dev.sig_l_sc = a.sig_l;
+  pq.dev.sig_g_sc = a.sig_g;
+  pq.sc_stride = nbb;
+  negf_status st = negf_rgf_lesser_greater(&pq, 1, a.prec, a.opt, a.GR_diag, a.GR_upper, a.GR_lower, a.GL_diag,
+                                           a.GL_upper, a.GG_diag, a.GG_upper, a.info, c.rgf, L.rgf, s);
+  if (st != NEGF_OK) return st;
+  st = negf_energy_convolution(p0.n_e, nbb, a.GL_diag, a.n_w, a.k0, a.W_lesser, a.scale, c.Fl, c.ec, L.ec, s);
+  if (st != NEGF_OK) return st;
+  st = negf_energy_convolution(p0.n_e, nbb, a.GG_diag, a.n_w, a.k0, a.W_greater, a.scale, c.Fg, c.ec, L.ec, s);
+  if (st != NEGF_OK) return st;
+  prof_begin(KC_ELEM, s);
+  hipLaunchKernelGGL(resid_partial_kernel, dim3(part_grid), dim3(SB), 0, s, n, (const double2*)c.Fl,
+                     (const double2*)c.Fg, (const double2*)Sl, (const double2*)Sg, c.part);
+  hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(SB), 0, s, (int)part_grid, (const double*)c.part, a.tol, it,
+                     c.last, history, state);
+  if (update)
+    hipLaunchKernelGGL(mix_kernel, dim3(mix_grid), dim3(SB), 0, s, n, a.mixing, (const double2*)c.Fl,
+                       (const double2*)c.Fg, Sl, Sg, Sr, (const int*)state);
+  prof_end(KC_ELEM, s, 0.0, (update ? 176.0 : 64.0) * (double)n);
+  return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
+}
+
+}  // namespace
+}  // namespace negf
+
 extern "C" {
 
 size_t negf_scba_workspace_bytes(const negf_problem* problem, negf_precision prec, const negf_options* opt,
@@ -158,89 +293,52 @@ size_t negf_scba_workspace_bytes(const negf_problem* problem, negf_precision pre
   return scba_layout(problem, prec, opt, n_w, L) ? L.total : 0;
 }
 
+negf_status negf_scba_step(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
+                           int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
+                           double mixing, double tol, int32_t it, int32_t update, void* sig_r, void* sig_l,
+                           void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper,
+                           void* GG_diag, void* GG_upper, int32_t* info, double* history, int32_t* state,
+                           void* workspace, size_t ws_bytes, void* stream) {
+  StepArgs a{problem, prec, opt, n_w, k0, W_lesser, W_greater, scale, mixing, tol, sig_r, sig_l, sig_g,
+             GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper, info, workspace, ws_bytes};
+  ScbaLayout L;
+  negf_status st = check_step(a, L);
+  if (st != NEGF_OK) return st;
+  if (it < 0 || !state || !a16(state) || (history && ((uintptr_t)history & 7))) return NEGF_EINVAL;
+  return step_impl(a, L, carve(workspace, L), it, update != 0, history, state, (hipStream_t)stream);
+}
+
 negf_status negf_scba(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
                       int32_t k0, const void* W_lesser, const void* W_greater, const double* scale, double mixing,
                       double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g, void* GR_diag,
                       void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper,
                       int32_t* info, int32_t* n_iter, double* history, void* workspace, size_t ws_bytes,
                       void* stream) {
-  if (!problem || !scale || !n_iter) return NEGF_EINVAL;
-  const negf_problem& p0 = *problem;
-  const negf_device& d0 = p0.dev;
-  if (d0.sig_r_sc || d0.sig_l_sc || d0.sig_g_sc || p0.sc_stride != 0) return NEGF_EINVAL;
-  if (k0 < 0 || k0 >= n_w || !(mixing > 0.0 && mixing <= 1.0) || !(tol >= 0.0) || max_iter < 1)
-    return NEGF_EINVAL;
+  StepArgs a{problem, prec, opt, n_w, k0, W_lesser, W_greater, scale, mixing, tol, sig_r, sig_l, sig_g,
+             GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper, info, workspace, ws_bytes};
+  if (!n_iter || max_iter < 1) return NEGF_EINVAL;
   ScbaLayout L;
-  if (!scba_layout(problem, prec, opt, n_w, L)) return NEGF_EINVAL;
-  const void* req[] = {W_lesser, W_greater, sig_r, sig_l, sig_g, GR_diag, GR_upper, GL_diag, GL_upper, GG_diag,
-                       GG_upper, info, workspace};
-  for (const void* q : req)
-    if (!q || !a16(q)) return NEGF_EINVAL;
-  if (GR_lower && !a16(GR_lower)) return NEGF_EINVAL;
-  if (sig_r == sig_l || sig_r == sig_g || sig_l == sig_g) return NEGF_EINVAL;
-  if (ws_bytes < L.total) return NEGF_EINVAL;
-
-  const long nbb = (long)d0.nb * d0.b * d0.b;
-  const long n = (long)p0.n_e * nbb;
-  char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-  void* ws_rgf = base;
-  base += up256(L.rgf);
-  void* ws_ec = base;
-  base += up256(L.ec);
-  double2* Fl = (double2*)base;
-  base += up256(L.sig);
-  double2* Fg = (double2*)base;
-  base += up256(L.sig);
-  double* part = (double*)base;
-  base += up256(2 * RPARTS * sizeof(double));
-  double* sums = (double*)base;
-
-  negf_problem pq = p0;
-  pq.dev.sig_r_sc = sig_r;
-  pq.dev.sig_l_sc = sig_l;
-  pq.dev.sig_g_sc = sig_g;
-  pq.sc_stride = nbb;
+  negf_status st = check_step(a, L);
+  if (st != NEGF_OK) return st;
+  const Carved c = carve(workspace, L);
   hipStream_t s = (hipStream_t)stream;
-  double2* Sl = (double2*)sig_l;
-  double2* Sg = (double2*)sig_g;
-  double2* Sr = (double2*)sig_r;
-  const unsigned mix_grid = (unsigned)std::min<long>((n + SB * U - 1) / (SB * U), MIX_WG);
-  const unsigned part_grid = (unsigned)std::min<long>((n + SB * U - 1) / (SB * U), RPARTS);
   *n_iter = 0;
-
-  prof_begin(KC_ELEM, s);
-  hipLaunchKernelGGL(mix_kernel, dim3(mix_grid), dim3(SB), 0, s, n, 0.0, (const double2*)nullptr,
-                     (const double2*)nullptr, Sl, Sg, Sr);
-  prof_end(KC_ELEM, s, 0.0, 48.0 * (double)n);
-  if (hipGetLastError() != hipSuccess) return NEGF_EHIP;
   for (int it = 0; it < max_iter; ++it) {
-    negf_status st = negf_rgf_lesser_greater(&pq, 1, prec, opt, GR_diag, GR_upper, GR_lower, GL_diag, GL_upper,
-                                             GG_diag, GG_upper, info, ws_rgf, L.rgf, stream);
+    // the last allowed solve does not mix: the outputs then hold Sigma_n and the G it produced
+    st = step_impl(a, L, c, it, it < max_iter - 1, nullptr, c.state, s);
     if (st != NEGF_OK) return st;
-    st = negf_energy_convolution(p0.n_e, nbb, GL_diag, n_w, k0, W_lesser, scale, Fl, ws_ec, L.ec, stream);
-    if (st != NEGF_OK) return st;
-    st = negf_energy_convolution(p0.n_e, nbb, GG_diag, n_w, k0, W_greater, scale, Fg, ws_ec, L.ec, stream);
-    if (st != NEGF_OK) return st;
-    prof_begin(KC_ELEM, s);
-    hipLaunchKernelGGL(resid_partial_kernel, dim3(part_grid), dim3(SB), 0, s, n, (const double2*)Fl,
-                       (const double2*)Fg, (const double2*)Sl, (const double2*)Sg, part);
-    hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(SB), 0, s, (int)part_grid, (const double*)part, sums);
-    prof_end(KC_ELEM, s, 0.0, 64.0 * (double)n);
-    double h[2] = {0.0, 0.0};
-    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    struct {
+      double r;
+      int state[2];
+    } h{0.0, {0, 0}};
+    if (hipMemcpyAsync(&h.r, c.last, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h.state, c.state, 2 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return NEGF_EHIP;
-    const double r = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] == 0.0 ? 0.0 : INFINITY);
-    if (history) history[it] = r;
+    if (history) history[it] = h.r;
     *n_iter = it + 1;
-    if (!std::isfinite(r)) return NEGF_ENONFINITE;
-    if (r <= tol) return NEGF_OK;
-    if (it == max_iter - 1) return NEGF_ENOCONV;
-    prof_begin(KC_ELEM, s);
-    hipLaunchKernelGGL(mix_kernel, dim3(mix_grid), dim3(SB), 0, s, n, mixing, (const double2*)Fl,
-                       (const double2*)Fg, Sl, Sg, Sr);
-    prof_end(KC_ELEM, s, 0.0, 112.0 * (double)n);
-    if (hipGetLastError() != hipSuccess) return NEGF_EHIP;
+    if (h.state[1] == 2) return NEGF_ENONFINITE;
+    if (h.state[1] == 1) return NEGF_OK;
   }
   return NEGF_ENOCONV;
 }

@@ -269,3 +269,68 @@ def test_energy_dependent_self_energies_through_a_plan(nb):
     with pytest.raises(nb.NegfError):
         plan.run_queue([torch.tensor([0.1, 0.2], dtype=torch.float64, device="cuda")], outs, info)
     plan.close()
+
+
+# --------------------------------------------------------------- the loop as single captured steps
+
+def _step_loop(nb, dev, E, Wl, Wg, k0, scale, mixing, tol, max_steps):
+    import torch
+    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=0.1, mu_r=-0.1, kT=KT)
+    return nb.ScbaLoop(prob, torch.from_numpy(Wl).cuda(), torch.from_numpy(Wg).cuda(), k0, scale, mixing=mixing,
+                       tol=tol, max_steps=max_steps)
+
+
+@pytest.mark.parametrize("tol,steps", [(0.0, 4), (1e-11, 16)])
+def test_loop_steps_equal_the_driver_and_replay_from_a_graph(nb, tol, steps):
+    """negf_scba_step run `steps` times (the last without mixing) ends on exactly what negf_scba ends on:
+    with tol = 0 after the same four solves; with tol = 1e-11 the steps after convergence leave the
+    self-energies alone and recompute the same Green's functions.  The same steps captured once in a
+    graph and replayed (self-energies cleared between replays) give the same bits again."""
+    import torch
+    dev = w.folded_chain_device(4, 24)
+    E, dE, k0, Wl, Wg = _bath(dev, 40, n_w=21)
+    scale = 1j * dE / (2 * math.pi)
+    ref = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=1.0, tol=tol, max_iter=steps)
+    loop = _step_loop(nb, dev, E, Wl, Wg, k0, scale, 1.0, tol, steps)
+    loop.run(steps)
+    torch.cuda.synchronize()
+    names = ("sig_r", "sig_l", "sig_g")
+    outs = ("GR_diag", "GR_upper", "GL_diag", "GL_upper", "GG_diag", "GG_upper")
+    st = loop.state.cpu().tolist()
+    assert st[0] == ref["n_iter"], (st, ref["n_iter"])
+    assert st[1] == (1 if ref["status"] == nb.NEGF_OK else 0), (st, ref["status"])
+    assert loop.history[:ref["n_iter"]].cpu().tolist() == ref["history"]
+    for n in names:
+        assert torch.equal(loop.sig[n], ref[n]), n
+    for n in outs:
+        assert torch.equal(loop.out[n], ref["flat"][n]), n
+    eager = {n: loop.sig[n].clone() for n in names}
+    eager.update({n: loop.out[n].clone() for n in outs})
+    # capture the whole loop once
+    for n in names:
+        loop.sig[n].zero_()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        loop.run(steps)
+    torch.cuda.current_stream().wait_stream(side)
+    for n in names:
+        loop.sig[n].zero_()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        loop.run(steps)
+    for rep in range(2):
+        for n in names:
+            loop.sig[n].zero_()
+        for n in outs:
+            loop.out[n].zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for n in names:
+            assert torch.equal(loop.sig[n], eager[n]), (rep, n)
+        for n in outs:
+            assert torch.equal(loop.out[n], eager[n]), (rep, n)
+        assert loop.state.cpu().tolist() == st, rep
+    del g

@@ -217,3 +217,22 @@ def test_self_consistent_loop_rejects_synchronously(L):
     assert call(a=with_sc) == nb.NEGF_EINVAL
     strided = (nb.negf_problem * 1)(nb.negf_problem(pr.dev, 6, W_l, 1e-8, 0.1, -0.1, 0.025, 4 * 8 * 8))
     assert call(a=strided) == nb.NEGF_EINVAL
+
+
+def test_self_consistent_step_rejects_synchronously(L):
+    """negf_scba_step: the checks of negf_scba plus a negative iteration index and a missing state."""
+    from paper_2602_03438_amd import binding as nb
+    pr, keep = _fake_problem(nb_=4, b=8, n_e=6)
+    arr = (nb.negf_problem * 1)(pr)
+    ws = L.negf_scba_workspace_bytes(arr, nb.PLAIN_FP64, None, 5)
+    one = (C.c_double * 2)(0.0, 1.0)
+    bufs = [np.zeros(64, dtype=np.complex128) for _ in range(14)]
+    W_l, W_g, s_r, s_l, s_g, grd, gru, grl, gld, glu, ggd, ggu, info, state = [b.ctypes.data for b in bufs]
+
+    def call(it=0, st=state, k0=2, wsb=ws):
+        return L.negf_scba_step(arr, nb.PLAIN_FP64, None, 5, k0, W_l, W_g, one, 0.5, 1e-10, it, 1, s_r, s_l, s_g, grd,
+                                gru, grl, gld, glu, ggd, ggu, info, None, st, grd, wsb, None)
+    assert call(it=-1) == nb.NEGF_EINVAL
+    assert call(st=None) == nb.NEGF_EINVAL
+    assert call(k0=5) == nb.NEGF_EINVAL
+    assert call(wsb=ws - 1) == nb.NEGF_EINVAL
