@@ -603,14 +603,16 @@ def bench_small(args):
             "folded_chain": w.folded_chain_device(32, 8), "wire": w.periodic_wire_device(32, 8, 1)}
     probs = [nb.Problem(nb.DeviceOnGPU(d), E, eta=eta, mu_l=MU_L, mu_r=MU_R, kT=KT) for d in devs.values()]
     npts = len(probs) * E.size
+    # the decimation steps enqueued per call (the leads here need at most 27 at eta = 1e-6)
+    sopts = nb.make_options(sr_max_iter=args.sr_max_iter)
     ws_r, ws_t = nb.Workspace(), nb.Workspace()
     res = {}
     for prec, name in ((nb.PLAIN_FP64, "plain"), (nb.FP32_REFINE, "fp32_refine")):
         outs = nb._rgf_outputs(probs, False, False, True)
 
         def step():
-            r = nb.rgf_retarded(probs, prec, ws=ws_r, outputs=outs)
-            t = nb.transmission(probs, ws=ws_t)
+            r = nb.rgf_retarded(probs, prec, opts=sopts, ws=ws_r, outputs=outs)
+            t = nb.transmission(probs, opts=sopts, ws=ws_t)
             return r["info"], t
 
         for _ in range(max(1, args.warmup)):
@@ -714,7 +716,7 @@ def bench_small(args):
             "config": {"workload": "random device Nb=32 b=8 (seed 1), 1D chain Nb=32 b=1, chain folded into cells "
                                    "of 8 (Nb=32), periodic random wire Nb=32 b=8; 64 energies in [-3, 3] each, "
                                    "eta=1e-6; one step = negf_rgf_retarded + negf_transmission over the 256 points, "
-                                   "value = graph-replayed plain FP64"},
+                                   "value = graph-replayed plain FP64", "sr_max_iter": args.sr_max_iter},
             "forms": res, "errors_vs_oracle_every_point": errs, "closed_forms": closed, "decimation_steps": sr,
             "roofline": {"bound": "mfma", "achieved": rate / 1e12, "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
                          "frac": rate / PEAK["f64"], "traffic": None,
