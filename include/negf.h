@@ -269,6 +269,21 @@ negf_status negf_energy_convolution(int32_t n_e, int64_t n_el, const void* G, in
  * overlap src).  Errors: EINVAL, EHIP. */
 negf_status negf_transpose(int64_t rows, int64_t cols, const void* src, void* dst, void* stream);
 
+/* ---- observables of Section III from the outputs of the sweeps ----
+ * Per point of the problems (outputs laid out as negf_rgf_lesser_greater
+ * writes them):
+ *   dos[point][i]     = -Im Tr G^R_ii / pi                      (the block-resolved density of states)
+ *   current[point][i] = -2 Re Tr[A_{i,i+1} G^<_{i+1,i}]         (i < nb - 1; e = hbar = 1, one spin)
+ * with A_{i,i+1} = E S_{i,i+1} - H_{i,i+1} and G^<_{i+1,i} = -(G^<_{i,i+1})^H,
+ * i.e. 2 Re sum_ab A_{i,i+1}[a][b] conj(G^<_{i,i+1}[a][b]).  The spectral
+ * current is the same at every interface when the current is conserved (the
+ * paper's check of its implementation, Section III).  GR_diag is needed for
+ * dos, GL_upper for current; either output may be NULL.  Device doubles,
+ * point-major, problems in order.  Errors: EINVAL (a required pointer
+ * missing or misaligned, more than 65535 energies in a problem), EHIP. */
+negf_status negf_observables(const negf_problem* problems, int32_t n_prob, const void* GR_diag, const void* GL_upper,
+                             double* dos, double* current, void* stream);
+
 /* ---- the self-consistent loop of Fig. 1 (Eq. (1)-(3)) with a fixed boson bath ----
  * Alternates the two halves of Fig. 1 for one problem (one device, n_e >= 1
  * energies on a uniform grid of spacing dE): every energy is solved from

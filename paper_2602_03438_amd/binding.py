@@ -104,6 +104,8 @@ def lib():
     L.negf_scba_step.argtypes = [P(negf_problem), i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32, i32,
                                  vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.negf_scba_step.restype = C.c_int
+    L.negf_observables.argtypes = [P(negf_problem), i32, vp, vp, vp, vp, vp]
+    L.negf_observables.restype = C.c_int
     L.negf_transmission.argtypes = [P(negf_problem), i32, P(negf_options), vp, vp, vp, sz, vp]
     L.negf_transmission.restype = C.c_int
     L.negf_zgemm_batched.argtypes = [C.c_char, C.c_char, i32, i32, i32, P(dbl), vp, i64, i64, vp, i64, i64, P(dbl),
@@ -597,6 +599,30 @@ def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_ite
     res["n_iter"] = int(n_iter.value)
     res["history"] = [hist[i] for i in range(n_iter.value)]
     res["status"] = int(code)
+    return res
+
+
+def observables(problems, outputs, dos=True, current=True):
+    """negf_observables on the flat outputs of rgf_lesser_greater (or rgf_retarded, for dos alone):
+    returns {"dos": [per problem: (n_e, nb)], "current": [per problem: (n_e, nb - 1)]} float64 device
+    tensors."""
+    torch = _torch()
+    arr = _problem_array(problems)
+    nd = sum(p.n_e * p.dev.nb for p in problems)
+    nc = sum(p.n_e * (p.dev.nb - 1) for p in problems)
+    D = torch.empty(max(1, nd), dtype=torch.float64, device="cuda") if dos else None
+    J = torch.empty(max(1, nc), dtype=torch.float64, device="cuda") if current else None
+    check(lib().negf_observables(arr, len(problems), _ptr(outputs.get("GR_diag")) if dos else None,
+                                 _ptr(outputs.get("GL_upper")) if current else None, _ptr(D), _ptr(J), _stream()),
+          "negf_observables")
+    res, od, oc = {"dos": [], "current": []}, 0, 0
+    for p in problems:
+        if dos:
+            res["dos"].append(D[od:od + p.n_e * p.dev.nb].view(p.n_e, p.dev.nb))
+        if current:
+            res["current"].append(J[oc:oc + p.n_e * (p.dev.nb - 1)].view(p.n_e, p.dev.nb - 1))
+        od += p.n_e * p.dev.nb
+        oc += p.n_e * (p.dev.nb - 1)
     return res
 
 

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnegf.so")
-SOURCES = ["gemm.hip", "inv.hip", "elem.hip", "api.hip", "serinv.hip", "econv.hip", "scba.hip", "prof.hip", "mlp.hip"]
+SOURCES = ["gemm.hip", "inv.hip", "elem.hip", "api.hip", "serinv.hip", "econv.hip", "scba.hip", "obs.hip", "prof.hip", "mlp.hip"]
 ARCH = "gfx950"
 
 

@@ -169,6 +169,14 @@ def test_fullsize_headline_path_plain_bar(setup, stable_refs):
     assert np.all(info == 0), np.nonzero(info)[0]
     _compare(nb, outputs, prob, energies, stable_refs, "fullsize_headline_eta1e-2")
     _properties(nb, outputs, prob, info)
+    # every point: the spectral current (negf_observables) is the same at all 59 interfaces
+    cur = nb.observables([prob], outputs, dos=False)["current"][0].cpu().numpy()
+    scale = float(np.abs(cur).max())
+    spread = float(np.abs(cur - cur[:, :1]).max() / scale)
+    record("fullsize_current_conservation_eta1e-2", 0.0, "current", spread, 1e-8, points=int(cur.shape[0]))
+    _progress(f"current conservation over {cur.shape[0]} points x {cur.shape[1]} interfaces: {spread:.2e} of the "
+              f"largest current")
+    assert spread < 1e-8, spread
     del outputs
     _free()
 

@@ -1,0 +1,88 @@
+"""GPU observables (negf_observables): the block-resolved density of states and the spectral
+current through every interface, against the oracle (oracle/observables.py on the oracle's own
+Green's functions) and against what physics fixes at any size: current conservation along the
+device, the Landauer current (f_L - f_R) T of a ballistic device with T from negf_transmission,
+and the density of states of the perfect 1D chain, 1 / (pi sqrt(4 t^2 - E^2)) per site."""
+import numpy as np
+import pytest
+
+import workloads as w
+from helpers import point_tolerance, record
+from oracle import leads as oleads
+from oracle import observables as oobs
+from oracle import rgf as orgf
+
+pytestmark = pytest.mark.gpu
+
+KT = 0.025
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2602_03438_amd import binding
+    binding.lib()
+    return binding
+
+
+def _solve(nb, dev, E, eta, mu_l, mu_r, greater=False):
+    import torch
+    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=eta, mu_l=mu_l, mu_r=mu_r, kT=KT)
+    out = nb.rgf_lesser_greater([prob], greater=greater)
+    obs = nb.observables([prob], out["flat"])
+    torch.cuda.synchronize()
+    return prob, out, obs["dos"][0].cpu().numpy(), obs["current"][0].cpu().numpy()
+
+
+def test_observables_match_the_oracle(nb):
+    """Slab device with S != I and scattering self-energies (b = 40: a ragged tile): DOS per block and
+    current per interface at every energy against the oracle's, each within the bar of its Green's
+    functions (1e-10, or 4 x the oracle's spread where it is not stable to that)."""
+    dev = w.scattering_self_energies(w.slab_device(5, 40, 2), 3, norm=0.02)
+    E = np.linspace(-0.9, 1.1, 6)
+    _, _, dos, cur = _solve(nb, dev, E, 1e-6, 0.1, -0.1)
+    names = ("GR_diag", "GL_upper")
+    for k, e in enumerate(E):
+        ref, tol = point_tolerance(lambda: orgf.solve_point(dev, e, 1e-6, 0.1, -0.1, KT), names)
+        d_ref = oobs.dos(ref.GR_diag)
+        Au = [e * dev.s_upper(i) - dev.H_upper[i] for i in range(dev.nb - 1)]
+        j_ref = oobs.currents(Au, ref.GL_upper)
+        e_d = float(np.abs(dos[k] - d_ref).max() / np.abs(d_ref).max())
+        e_j = float(np.abs(cur[k] - j_ref).max() / np.abs(j_ref).max())
+        record("observables", e, "dos", e_d, tol["GR_diag"])
+        record("observables", e, "current", e_j, tol["GL_upper"])
+        assert e_d < tol["GR_diag"], (k, e_d)
+        assert e_j < tol["GL_upper"], (k, e_j)
+
+
+def test_ballistic_current_is_conserved_and_equals_landauer(nb):
+    """Ballistic slab device (b = 48, S != I): the current is the same at every interface and equals
+    (f_L - f_R) T with T from negf_transmission, at every energy."""
+    import torch
+    dev = w.slab_device(6, 48, 4)
+    E = np.linspace(-1.2, 1.2, 24)
+    prob, _, _, cur = _solve(nb, dev, E, 1e-6, 0.1, -0.1)
+    T = nb.transmission([prob])["T"].cpu().numpy()
+    torch.cuda.synchronize()
+    scale = np.abs(cur).max()
+    assert scale > 1e-4
+    spread = float(np.abs(cur - cur[:, :1]).max() / scale)
+    f = np.array([oleads.fermi(e - 0.1, KT) - oleads.fermi(e + 0.1, KT) for e in E])
+    land = float(np.abs(cur[:, 0] - f * T).max() / scale)
+    record("observables_conservation", 0.0, "current", spread, 1e-9)
+    record("observables_landauer", 0.0, "current", land, 1e-9)
+    assert spread < 1e-9, spread
+    assert land < 1e-9, land
+
+
+def test_chain_density_of_states_closed_form(nb):
+    """The perfect 1D chain (eps = 0, t = 1) folded into cells of 4 sites: the DOS of every site inside
+    the band is 1 / (pi sqrt(4 - E^2)), so every block holds 4 times that (to O(eta))."""
+    dev = w.folded_chain_device(8, 4)
+    E = np.linspace(-1.8, 1.8, 19)
+    _, _, dos, _ = _solve(nb, dev, E, 1e-8, 0.0, 0.0)
+    exact = 4.0 / (np.pi * np.sqrt(4.0 - E ** 2))
+    err = float(np.abs(dos - exact[:, None]).max() / exact.max())
+    record("observables_chain_dos", 0.0, "dos", err, 1e-6)
+    assert err < 1e-6, err

@@ -236,3 +236,20 @@ def test_self_consistent_step_rejects_synchronously(L):
     assert call(st=None) == nb.NEGF_EINVAL
     assert call(k0=5) == nb.NEGF_EINVAL
     assert call(wsb=ws - 1) == nb.NEGF_EINVAL
+
+
+def test_observables_reject_synchronously(L):
+    """negf_observables: an output without the Green's function it needs, misalignment, more than
+    65535 energies in a problem; nothing requested is a no-op."""
+    from paper_2602_03438_amd import binding as nb
+    pr, keep = _fake_problem(nb_=4, b=8, n_e=3)
+    arr = (nb.negf_problem * 1)(pr)
+    x = np.zeros(64, dtype=np.complex128)
+    p = x.ctypes.data
+    assert L.negf_observables(arr, 1, None, None, None, None, None) == nb.NEGF_OK
+    assert L.negf_observables(arr, 1, None, p, p, None, None) == nb.NEGF_EINVAL      # dos needs GR_diag
+    assert L.negf_observables(arr, 1, p, None, None, p, None) == nb.NEGF_EINVAL      # current needs GL_upper
+    assert L.negf_observables(arr, 1, p + 8, p, p, p, None) == nb.NEGF_EINVAL
+    assert L.negf_observables(arr, 0, p, p, p, p, None) == nb.NEGF_EINVAL
+    big, keep2 = _fake_problem(nb_=4, b=8, n_e=70000)
+    assert L.negf_observables((nb.negf_problem * 1)(big), 1, p, p, p, p, None) == nb.NEGF_EINVAL
