@@ -377,6 +377,15 @@ def main():
     # one untimed step on the first energy batch: the middle point's outputs (compared with the
     # oracle below) and 8 points spread over the batch (compared with the other forms)
     at_oracle = {"plain_fp64": point_outputs(nb, probs, outputs, batches[0], runner)}
+    # a property of every point of that step: the spectral current is the same at all interfaces
+    cur = nb.observables(probs, outputs, dos=False)["current"][0].cpu().numpy()
+    scale = float(np.abs(cur).max())
+    per_pt = np.abs(cur - cur[:, :1]).max(axis=1) / scale
+    conservation = {"points": int(cur.shape[0]), "interfaces": int(cur.shape[1]),
+                    "max_spread_rel_to_largest_current": float(per_pt.max()),
+                    "median_spread": float(np.median(per_pt)),
+                    "note": "negf_observables on the first energy batch's outputs (all points, flagged ones "
+                            "included); exact conservation in exact arithmetic"}
     if plan:
         plan.close()          # its workspace is not needed by the runs below
     chosen = None
@@ -449,6 +458,7 @@ def main():
         "info_nonzero": len(res["failures"]),
         "failures": res["failures"][:8],
         "roofline": roof,
+        "current_conservation": conservation,
         "kernels": kstats,
         "kernels_note": "one extra untimed step with every kernel class timed (the timed steps time the products only)",
         "chosen_form": chosen,
