@@ -327,10 +327,12 @@ size_t negf_scba_workspace_bytes(const negf_problem* problem, negf_precision pre
  * [1] = 0 running, 1 converged, 2 non-finite residual.  Once [1] != 0 the
  * self-energies are no longer changed, so further iterations recompute the
  * same Green's functions (a fixed number of iterations ends where a loop
- * stopped at convergence ends).  The same workspace (negf_scba_workspace_bytes)
- * must serve every iteration of a loop only for its temporaries; the state
- * and history live in caller memory.  Errors: EINVAL (as negf_scba, it < 0,
- * state NULL), EHIP. */
+ * stopped at convergence ends).  The workspace (negf_scba_workspace_bytes)
+ * holds only one iteration's temporaries, so any workspace of that size
+ * serves any iteration; the loop's state and history live in caller memory.
+ * The iterations of a loop go on one stream in order; calls that overlap on
+ * one workspace or one state race.  Errors: EINVAL (as negf_scba, it < 0,
+ * state NULL or misaligned), EHIP. */
 negf_status negf_scba_step(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
                            int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
                            double mixing, double tol, int32_t it, int32_t update, void* sig_r, void* sig_l,
