@@ -249,7 +249,7 @@ def main():
     ap.add_argument("--econv-elements", type=int, default=1 << 21, help="elements (matrix entries) in the econv "
                     "workload")
     ap.add_argument("--gemm-batch", type=int, default=256, help="products per launch in the gemm workload")
-    ap.add_argument("--scba-energies", type=int, default=32, help="energies of the scba workload's uniform grid")
+    ap.add_argument("--scba-energies", type=int, default=64, help="energies of the scba workload's uniform grid")
     ap.add_argument("--scattering-energies", type=int, default=512, help="energies per k-point of the scattering "
                                                                           "workload")
     ap.add_argument("--scattering-batch", type=int, default=64, help="points per call in the scattering workload")
