@@ -86,3 +86,20 @@ def test_chain_density_of_states_closed_form(nb):
     err = float(np.abs(dos - exact[:, None]).max() / exact.max())
     record("observables_chain_dos", 0.0, "dos", err, 1e-6)
     assert err < 1e-6, err
+
+
+def test_observables_of_several_problems_in_one_call(nb):
+    """Problems of different block shapes in one call: each one's DOS and currents equal those of a call
+    on that problem alone (the per-problem offsets into the point-major outputs)."""
+    import torch
+    devs = [w.random_device(4, 16, 5, overlap=0.05), w.slab_device(5, 24, 6), w.chain_device(7)]
+    Es = [np.linspace(-0.8, 0.8, 3), np.linspace(-0.5, 0.9, 4), np.linspace(-1.5, 1.5, 2)]
+    probs = [nb.Problem(nb.DeviceOnGPU(d), E, eta=1e-6, mu_l=0.1, mu_r=-0.1, kT=KT) for d, E in zip(devs, Es)]
+    both = nb.observables(probs, nb.rgf_lesser_greater(probs)["flat"])
+    for q, p in enumerate(probs):
+        alone = nb.observables([p], nb.rgf_lesser_greater([p])["flat"])
+        torch.cuda.synchronize()
+        for k in ("dos", "current"):
+            a, b = both[k][q].cpu().numpy(), alone[k][0].cpu().numpy()
+            assert a.shape == b.shape, (q, k)
+            assert np.allclose(a, b, rtol=1e-12, atol=1e-14 * np.abs(b).max()), (q, k)
