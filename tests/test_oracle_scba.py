@@ -191,3 +191,18 @@ def test_planted_mistake_in_the_loop_is_caught(k):
         except (np.linalg.LinAlgError, ValueError, FloatingPointError):
             return
     assert not all(res.values()), f"mutation {k} ({target}: {new!r}) passed every pin: {res}"
+
+
+def test_boson_bath_detailed_balance_and_symmetry():
+    """The bath the loop tests use: W^>(w) = e^{w/kT} W^<(w), W^<(w) = W^>(-w) on a symmetric grid,
+    i W^<> positive semi-definite in every block (the spatial kernel is positive definite)."""
+    nb_, b, n_w, k0, dE = 2, 6, 21, 10, 0.03
+    Wl, Wg = w.boson_bath(nb_, b, n_w, k0, dE, KT, strength=0.7)
+    for k in range(n_w):
+        om = (k - k0) * dE
+        assert np.allclose(Wg[k], np.exp(om / KT) * Wl[k], rtol=1e-12, atol=0), k
+        assert np.allclose(Wl[k], Wg[2 * k0 - k], rtol=1e-12, atol=1e-300), k
+        for blk in range(nb_):
+            for X in (Wl[k, blk], Wg[k, blk]):
+                assert np.allclose(X, X.T)
+                assert np.linalg.eigvalsh((1j * X).real).min() >= -1e-14

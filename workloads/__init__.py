@@ -355,8 +355,8 @@ def boson_bath(nb: int, b: int, n_w: int, k0: int, dE: float, kT: float, strengt
             lo = hi = strength * kT / width
         else:
             dens = strength * (w / width) * math.exp(-0.5 * (w / width) ** 2)
-            occ = 1.0 / math.expm1(w / kT)
-            lo, hi = dens * occ, dens * (1.0 + occ)
+            # n and 1 + n = -1 / (e^{-w/kT} - 1), each without cancellation
+            lo, hi = dens / math.expm1(w / kT), -dens / math.expm1(-w / kT)
         Wl[k] = (-1j * lo) * K
         Wg[k] = (-1j * hi) * K
     return Wl, Wg
