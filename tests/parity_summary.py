@@ -23,8 +23,10 @@ def main(path):
         spreads = [r["spread"] for r in rs if r["spread"] is not None]
         kap = [r["kappa"] for r in rs if r["kappa"] is not None]
         pts = len({(r["E"], r.get("side"), r.get("b"), r.get("point")) for r in rs})
-        barcol = "1e-10 (plain)" if bars == [1e-10] else ("1e-6 (chosen form)" if bars == [1e-6] else
-                                                          f"{min(bars):.1e} .. {max(bars):.1e}")
+        chosen = "fp32" in t or "refine" in t
+        barcol = ("1e-10 (plain)" if bars == [1e-10] else
+                  "1e-6 (chosen form)" if bars == [1e-6] and chosen else
+                  f"{bars[0]:.1e}" if len(bars) == 1 else f"{min(bars):.1e} .. {max(bars):.1e}")
         if bars == [1e-10]:
             plain_tests.append(t)
         print(f"| {t} | {len(rs)} | {pts} | {max(r['err'] for r in rs):.2e} | {barcol} | "
