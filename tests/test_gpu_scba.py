@@ -334,3 +334,28 @@ def test_loop_steps_equal_the_driver_and_replay_from_a_graph(nb, tol, steps):
             assert torch.equal(loop.out[n], eager[n]), (rep, n)
         assert loop.state.cpu().tolist() == st, rep
     del g
+
+
+def test_loop_in_the_refined_form_and_in_chunks(nb):
+    """The loop's solves in the refined single-product form stay within its 1e-6 bar of the oracle loop
+    (plain arithmetic) after three iterations; with the solves split into chunks of 5 energies (so that
+    chunks start inside the self-energy arrays) the plain loop is unchanged to 1e-13."""
+    import torch
+    dev = w.slab_device(4, 32, 8)
+    E, dE, k0, Wl, Wg = _bath(dev, 24, lo=-0.6, hi=0.6, n_w=9, strength=0.3)
+    scale = 1j * dE / (2 * math.pi)
+    ref = oscba.scba(dev, E, ETA, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=0.7, tol=0.0, max_iter=3)
+    plain = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=0.7, tol=0.0, max_iter=3)
+    refined = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=0.7, tol=0.0, max_iter=3, prec=nb.FP32_REFINE)
+    chunked = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=0.7, tol=0.0, max_iter=3,
+                        opts=nb.make_options(batch=5))
+    for n in ("sig_l", "sig_g"):
+        err = rel(refined[n].cpu().numpy(), getattr(ref, n))
+        record("scba_refined_form", 0.0, n, err, 1e-6)
+        assert err < 1e-6, (n, err)
+        assert rel(chunked[n].cpu().numpy(), plain[n].cpu().numpy()) < 1e-13, n
+    for n in ("GR_diag", "GL_diag", "GG_diag"):
+        err = rel(refined[n][0].cpu().numpy(), _stack(ref.points, n))
+        record("scba_refined_form", 0.0, n, err, 1e-6)
+        assert err < 1e-6, (n, err)
+        assert rel(chunked[n][0].cpu().numpy(), plain[n][0].cpu().numpy()) < 1e-13, n
