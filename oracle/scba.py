@@ -15,7 +15,10 @@ w_k = (k - k0) dE:
 
 (the plain sum of ``econv``; G is zero outside the grid), and the retarded
 self-energy is the anti-Hermitian combination (F^> - F^<) / 2 (the
-Hermitian, principal-value part is not formed).
+Hermitian, principal-value part is not formed).  With several transverse
+momenta k (one device H(k) each, Eq. (1)-(3) omit k) the self-energies are
+taken independent of k and G^<> in the convolution is the average over the
+k-points of each energy (the local-in-k reading).
 
 Iteration n (n = 0, 1, ...) solves every energy with Sigma_n, forms F from the
 new G^<>, and measures
@@ -76,9 +79,14 @@ def solve_all(dev, energies, eta, mu_l, mu_r, kT, sig_r, sig_l, sig_g):
 
 
 def convolve(points, W_l, W_g, k0, scale):
-    """F^<> of Eq. (3) from the diagonal blocks of every energy's G^<>."""
-    Gl = np.stack([p.GL_diag for p in points])
-    Gg = np.stack([p.GG_diag for p in points])
+    """F^<> of Eq. (3) from the diagonal blocks of every energy's G^<> (``points`` [e], or [k][e]
+    for several k-points: the average over k)."""
+    if isinstance(points[0], list):
+        Gl = np.mean([np.stack([p.GL_diag for p in pk]) for pk in points], axis=0)
+        Gg = np.mean([np.stack([p.GG_diag for p in pk]) for pk in points], axis=0)
+    else:
+        Gl = np.stack([p.GL_diag for p in points])
+        Gg = np.stack([p.GG_diag for p in points])
     shp = Gl.shape
     n_w = W_l.shape[0]
     Fl = _econv.energy_convolution(Gl.reshape(shp[0], -1), W_l.reshape(n_w, -1), k0, scale)
@@ -90,8 +98,10 @@ def scba(dev, energies, eta, mu_l, mu_r, kT, W_l, W_g, k0, scale, mixing=0.5, to
          sig0=None) -> ScbaResult:
     """The loop of Fig. 1 with a fixed bath.  ``sig0`` = (Sigma^<, Sigma^>) to start from
     (default zero: the ballistic solution is iteration 0); ``energies`` must be uniform, the
-    spacing entering only through ``scale`` (i dE / 2 pi for the usual normalisation)."""
-    n_e, nb, b = len(energies), dev.nb, dev.b
+    spacing entering only through ``scale`` (i dE / 2 pi for the usual normalisation).  ``dev`` may
+    be a list of devices (one per k-point, same block shape): the points are then [k][e]."""
+    devs = dev if isinstance(dev, (list, tuple)) else None
+    n_e, nb, b = len(energies), (devs or [dev])[0].nb, (devs or [dev])[0].b
     if sig0 is None:
         Sl = np.zeros((n_e, nb, b, b), dtype=np.complex128)
         Sg = np.zeros_like(Sl)
@@ -101,7 +111,10 @@ def scba(dev, energies, eta, mu_l, mu_r, kT, W_l, W_g, k0, scale, mixing=0.5, to
     Sr = retarded_from(Sl, Sg)
     hist = []
     for n in range(max_iter):
-        pts = solve_all(dev, energies, eta, mu_l, mu_r, kT, Sr, Sl, Sg)
+        if devs is None:
+            pts = solve_all(dev, energies, eta, mu_l, mu_r, kT, Sr, Sl, Sg)
+        else:
+            pts = [solve_all(d, energies, eta, mu_l, mu_r, kT, Sr, Sl, Sg) for d in devs]
         Fl, Fg = convolve(pts, W_l, W_g, k0, scale)
         r = residual(Fl, Fg, Sl, Sg)
         hist.append(r)

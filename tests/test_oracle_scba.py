@@ -206,3 +206,33 @@ def test_boson_bath_detailed_balance_and_symmetry():
             for X in (Wl[k, blk], Wg[k, blk]):
                 assert np.allclose(X, X.T)
                 assert np.linalg.eigvalsh((1j * X).real).min() >= -1e-14
+
+
+def test_k_points_average_and_conserve_the_summed_current():
+    """Several k-points: identical devices at every k give the single-device loop exactly; two
+    different k-devices, converged, conserve the energy-integrated current summed over k at every
+    interface (the pairing argument of the single-device pin applies to the k-averaged G^<>)."""
+    from oracle import scba, observables
+    dev = w.folded_chain_device(4, 4)
+    E, dE = _grid(32)
+    n_w, k0 = 9, 4
+    scale = 1j * dE / (2 * math.pi)
+    Wl, Wg = w.boson_bath(dev.nb, dev.b, n_w, k0, dE, KT, strength=1.0)
+    one = scba.scba(dev, E, 1e-6, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=1.0, tol=0.0, max_iter=3)
+    two = scba.scba([dev, dev], E, 1e-6, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=1.0, tol=0.0, max_iter=3)
+    assert np.array_equal(one.sig_l, two.sig_l) and np.array_equal(one.sig_g, two.sig_g)
+    # two genuinely different k-points of a wire with transverse hopping
+    base = w.folded_chain_device(4, 4)
+    T = 0.2 * np.eye(4, k=1)
+    devs = []
+    for kk in (0.0, 1.3):
+        ph = complex(math.cos(kk), math.sin(kk))
+        H = np.stack([h + ph * T + np.conj(ph) * T.T for h in base.H_diag])
+        devs.append(w.BTDevice(H, base.H_upper))
+    r = scba.scba(devs, E, 1e-6, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=1.0, tol=1e-13, max_iter=60)
+    assert r.converged
+    J = np.zeros(base.nb - 1)
+    for d, pk in zip(devs, r.points):
+        for p in pk:
+            J += observables.currents([p.E * d.s_upper(i) - d.H_upper[i] for i in range(d.nb - 1)], p.GL_upper)
+    assert np.abs(J - J[0]).max() <= 1e-9 * abs(J[0]), J
