@@ -285,12 +285,15 @@ negf_status negf_observables(const negf_problem* problems, int32_t n_prob, const
                              double* dos, double* current, void* stream);
 
 /* ---- the self-consistent loop of Fig. 1 (Eq. (1)-(3)) with a fixed boson bath ----
- * Alternates the two halves of Fig. 1 for one problem (one device, n_e >= 1
- * energies on a uniform grid of spacing dE): every energy is solved from
+ * Alternates the two halves of Fig. 1 for n_prob >= 1 problems, one per
+ * transverse momentum k (devices H(k) of one block shape, each with the same
+ * n_e >= 1 energies on a uniform grid of spacing dE): every energy is solved from
  * Eq. (1) and (2) with its own block-diagonal scattering self-energies, then
  * the self-energies are rebuilt from the new G^<> by the energy convolution
  * of Eq. (3), restricted to the diagonal blocks:
  *     F^<>_ii(E_e) = scale * sum_k G^<>_ii(E_e - w_k) (.) W^<>[k],  w_k = (k - k0) dE
+ * (with several k-points G^<> here is the average over them of each energy:
+ * the self-energies are taken independent of k)
  * (M1 = M2 = I; W^<> [n_w][nb][b][b] complex128, a bath held fixed: the
  * polarisation loop of Fig. 1 is not run; scale, host, 2 doubles, e.g.
  * i dE / 2 pi).  The retarded self-energy is (Sigma^> - Sigma^<) / 2 (its
@@ -300,12 +303,13 @@ negf_status negf_observables(const negf_problem* problems, int32_t n_prob, const
  * n = max_iter - 1, leaving Sigma_n and the Green's functions it produced in
  * the outputs, else Sigma_{n+1} = Sigma_n + mixing (F - Sigma_n) (both kinds)
  * and Sigma^R_{n+1} = (Sigma^>_{n+1} - Sigma^<_{n+1}) / 2.
- * problem: one problem whose device has no scattering self-energies and
- * sc_stride 0 (the loop supplies both).  sig_r / sig_l / sig_g: device,
+ * problem[n_prob]: devices without scattering self-energies and sc_stride 0
+ * (the loop supplies both).  sig_r / sig_l / sig_g: device,
  * [n_e][nb][b][b] complex128, in: Sigma_0 (sig_r is overwritten from sig_l
  * and sig_g before the first solve), out: the final Sigma_n.  Outputs as in
- * negf_rgf_lesser_greater (GR_lower may be NULL; G^> is required), info
- * [n_e] per point of the last solve.  n_iter (host): solves performed;
+ * negf_rgf_lesser_greater for the n_prob problems (point-major, problems in
+ * order; GR_lower may be NULL; G^> is required), info [n_prob n_e] per point
+ * of the last solve.  n_iter (host): solves performed;
  * history (host, nullable, max_iter doubles): r_0 .. r_{n_iter-1}.
  * negf_scba drives negf_scba_step from the host and synchronises `stream` once
  * per iteration to read the loop state (the stopping decision), so it cannot
@@ -315,8 +319,8 @@ negf_status negf_observables(const negf_problem* problems, int32_t n_prob, const
  * NEGF_ENOCONV when max_iter solves ended above tol, NEGF_ENONFINITE when r_n
  * is not finite (the outputs then hold that iteration); argument errors
  * (EINVAL) before any work.  Workspace: negf_scba_workspace_bytes(...). */
-size_t negf_scba_workspace_bytes(const negf_problem* problem, negf_precision prec, const negf_options* opt,
-                                 int32_t n_w);
+size_t negf_scba_workspace_bytes(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                                 const negf_options* opt, int32_t n_w);
 /* One iteration of that loop, enqueued on `stream` with no host
  * synchronisation (capturable in a graph); arguments as for negf_scba plus:
  * it: the iteration index (it = 0 starts a loop: the state is reset and
@@ -333,18 +337,18 @@ size_t negf_scba_workspace_bytes(const negf_problem* problem, negf_precision pre
  * The iterations of a loop go on one stream in order; calls that overlap on
  * one workspace or one state race.  Errors: EINVAL (as negf_scba, it < 0,
  * state NULL or misaligned), EHIP. */
-negf_status negf_scba_step(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
-                           int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
-                           double mixing, double tol, int32_t it, int32_t update, void* sig_r, void* sig_l,
-                           void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper,
-                           void* GG_diag, void* GG_upper, int32_t* info, double* history, int32_t* state,
-                           void* workspace, size_t ws_bytes, void* stream);
-negf_status negf_scba(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
-                      int32_t k0, const void* W_lesser, const void* W_greater, const double* scale, double mixing,
-                      double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g, void* GR_diag,
-                      void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper,
-                      int32_t* info, int32_t* n_iter, double* history, void* workspace, size_t ws_bytes,
-                      void* stream);
+negf_status negf_scba_step(const negf_problem* problem, int32_t n_prob, negf_precision prec, const negf_options* opt,
+                           int32_t n_w, int32_t k0, const void* W_lesser, const void* W_greater,
+                           const double* scale, double mixing, double tol, int32_t it, int32_t update, void* sig_r,
+                           void* sig_l, void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag,
+                           void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info, double* history,
+                           int32_t* state, void* workspace, size_t ws_bytes, void* stream);
+negf_status negf_scba(const negf_problem* problem, int32_t n_prob, negf_precision prec, const negf_options* opt,
+                      int32_t n_w, int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
+                      double mixing, double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g,
+                      void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper, void* GG_diag,
+                      void* GG_upper, int32_t* info, int32_t* n_iter, double* history, void* workspace,
+                      size_t ws_bytes, void* stream);
 
 /* ---- plans: many problems of uneven block shapes in one launch ----
  * A plan groups the points of all problems into chunks of one block shape

@@ -96,13 +96,13 @@ def lib():
     L.negf_energy_convolution.restype = C.c_int
     L.negf_transpose.argtypes = [i64, i64, vp, vp, vp]
     L.negf_transpose.restype = C.c_int
-    L.negf_scba_workspace_bytes.argtypes = [P(negf_problem), i32, P(negf_options), i32]
+    L.negf_scba_workspace_bytes.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32]
     L.negf_scba_workspace_bytes.restype = sz
-    L.negf_scba.argtypes = [P(negf_problem), i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32, vp, vp,
-                            vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(dbl), vp, sz, vp]
+    L.negf_scba.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32, vp,
+                            vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(dbl), vp, sz, vp]
     L.negf_scba.restype = C.c_int
-    L.negf_scba_step.argtypes = [P(negf_problem), i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32, i32,
-                                 vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.negf_scba_step.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32,
+                                 i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.negf_scba_step.restype = C.c_int
     L.negf_observables.argtypes = [P(negf_problem), i32, vp, vp, vp, vp, vp]
     L.negf_observables.restype = C.c_int
@@ -547,7 +547,9 @@ def energy_convolution(G, W, k0, scale=1.0, out=None, ws=None):
 
 def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_iter=50, sig0=None, prec=PLAIN_FP64,
          opts=None, lower=True, ws=None, outputs=None, sigmas=None):
-    """negf_scba: the self-consistent loop of Fig. 1 for one problem with a fixed bath.
+    """negf_scba: the self-consistent loop of Fig. 1 with a fixed bath, for one problem or a list of
+    problems (one per k-point, same block shape and energies; the outputs and info then run over
+    them in order, point-major, and the self-energies are shared).
 
     W_lesser / W_greater: complex128 device tensors [n_w, nb, b, b] (W[k] at (k - k0) dE);
     scale: the convolution's prefactor (e.g. 1j dE / 2 pi); sig0: optional (Sigma^<, Sigma^>)
@@ -557,16 +559,17 @@ def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_ite
     info, n_iter, the residual history and the status (OK: converged; ENOCONV: max_iter reached;
     ENONFINITE: a non-finite residual)."""
     torch = _torch()
-    arr = _problem_array([problem])
+    probs = list(problem) if isinstance(problem, (list, tuple)) else [problem]
+    arr = _problem_array(probs)
     o = C.byref(opts) if opts else None
-    dv = problem.dev
+    dv = probs[0].dev
     n_w = int(W_lesser.shape[0])
-    shape = (problem.n_e, dv.nb, dv.b, dv.b)
+    shape = (probs[0].n_e, dv.nb, dv.b, dv.b)
     for t in (W_lesser, W_greater):
         if (not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous()
                 or tuple(t.shape) != (n_w, dv.nb, dv.b, dv.b)):
             raise NegfError("W_lesser / W_greater must be contiguous complex128 device tensors [n_w, nb, b, b]")
-    nbytes = lib().negf_scba_workspace_bytes(arr, prec, o, n_w)
+    nbytes = lib().negf_scba_workspace_bytes(arr, len(probs), prec, o, n_w)
     if nbytes == 0:
         raise NegfError("invalid problem or bath for the self-consistent loop")
     buf = (ws or Workspace()).get(nbytes)
@@ -579,20 +582,20 @@ def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_ite
     if sig0 is not None:
         sigmas["sig_l"].copy_(torch.as_tensor(sig0[0]).to(sigmas["sig_l"].device))
         sigmas["sig_g"].copy_(torch.as_tensor(sig0[1]).to(sigmas["sig_g"].device))
-    out = (_check_outputs(outputs, [problem], True, True, lower) if outputs
-           else _rgf_outputs([problem], True, True, lower))
-    info = torch.zeros(problem.n_e, dtype=torch.int32, device="cuda")
+    out = (_check_outputs(outputs, probs, True, True, lower) if outputs
+           else _rgf_outputs(probs, True, True, lower))
+    info = torch.zeros(sum(p.n_e for p in probs), dtype=torch.int32, device="cuda")
     sc = (C.c_double * 2)(complex(scale).real, complex(scale).imag)
     n_iter = C.c_int32(0)
     hist = (C.c_double * max(int(max_iter), 1))()
-    code = lib().negf_scba(arr, prec, o, n_w, int(k0), _ptr(W_lesser), _ptr(W_greater), sc, float(mixing), float(tol),
+    code = lib().negf_scba(arr, len(probs), prec, o, n_w, int(k0), _ptr(W_lesser), _ptr(W_greater), sc, float(mixing), float(tol),
                            int(max_iter), _ptr(sigmas["sig_r"]), _ptr(sigmas["sig_l"]), _ptr(sigmas["sig_g"]),
                            _ptr(out["GR_diag"]), _ptr(out["GR_upper"]), _ptr(out.get("GR_lower")),
                            _ptr(out["GL_diag"]), _ptr(out["GL_upper"]), _ptr(out["GG_diag"]), _ptr(out["GG_upper"]),
                            _ptr(info), C.byref(n_iter), hist, _ptr(buf), buf.numel(), _stream())
     if code not in (NEGF_OK, NEGF_ENOCONV, NEGF_ENONFINITE):
         check(code, "negf_scba")
-    res = _views(out, [problem])
+    res = _views(out, probs)
     res.update(sigmas)
     res["info"] = info
     res["flat"] = out
@@ -634,25 +637,26 @@ class ScbaLoop:
     def __init__(self, problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_steps=64,
                  prec=PLAIN_FP64, opts=None, lower=True):
         torch = _torch()
-        self.problem, self.Wl, self.Wg, self.k0 = problem, W_lesser, W_greater, int(k0)
+        self.problems = list(problem) if isinstance(problem, (list, tuple)) else [problem]
+        self.problem, self.Wl, self.Wg, self.k0 = self.problems[0], W_lesser, W_greater, int(k0)
         self.scale = (C.c_double * 2)(complex(scale).real, complex(scale).imag)
         self.mixing, self.tol, self.prec, self.opts = float(mixing), float(tol), prec, opts
-        self._arr = _problem_array([problem])
-        dv = problem.dev
+        self._arr = _problem_array(self.problems)
+        dv = self.problem.dev
         self.n_w = int(W_lesser.shape[0])
         for t in (W_lesser, W_greater):
             if (not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous()
                     or tuple(t.shape) != (self.n_w, dv.nb, dv.b, dv.b)):
                 raise NegfError("W_lesser / W_greater must be contiguous complex128 device tensors [n_w, nb, b, b]")
         o = C.byref(opts) if opts else None
-        nbytes = lib().negf_scba_workspace_bytes(self._arr, prec, o, self.n_w)
+        nbytes = lib().negf_scba_workspace_bytes(self._arr, len(self.problems), prec, o, self.n_w)
         if nbytes == 0:
             raise NegfError("invalid problem or bath for the self-consistent loop")
         self.ws = Workspace().get(nbytes)
-        shape = (problem.n_e, dv.nb, dv.b, dv.b)
+        shape = (self.problem.n_e, dv.nb, dv.b, dv.b)
         self.sig = {k: torch.zeros(shape, dtype=torch.complex128, device="cuda") for k in ("sig_r", "sig_l", "sig_g")}
-        self.out = _rgf_outputs([problem], True, True, lower)
-        self.info = torch.zeros(problem.n_e, dtype=torch.int32, device="cuda")
+        self.out = _rgf_outputs(self.problems, True, True, lower)
+        self.info = torch.zeros(sum(p.n_e for p in self.problems), dtype=torch.int32, device="cuda")
         self.history = torch.zeros(max(1, int(max_steps)), dtype=torch.float64, device="cuda")
         self.state = torch.zeros(2, dtype=torch.int32, device="cuda")
 
@@ -660,7 +664,7 @@ class ScbaLoop:
         if not 0 <= it < self.history.numel():
             raise NegfError("iteration index beyond the history")
         o = self.out
-        check(lib().negf_scba_step(self._arr, self.prec, C.byref(self.opts) if self.opts else None, self.n_w, self.k0,
+        check(lib().negf_scba_step(self._arr, len(self.problems), self.prec, C.byref(self.opts) if self.opts else None, self.n_w, self.k0,
                                    _ptr(self.Wl), _ptr(self.Wg), self.scale, self.mixing, self.tol, int(it),
                                    int(bool(update)), _ptr(self.sig["sig_r"]), _ptr(self.sig["sig_l"]),
                                    _ptr(self.sig["sig_g"]), _ptr(o["GR_diag"]), _ptr(o["GR_upper"]),

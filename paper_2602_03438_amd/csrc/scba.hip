@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace negf {
 namespace {
@@ -148,22 +149,39 @@ __global__ void __launch_bounds__(SB) mix_kernel(long n, double m, const double2
   }
 }
 
+// out[x] = (1 / nk) sum_q G[q stride + x]: the average over the k-points (problems) of each energy's
+// diagonal blocks, summed in problem order
+__global__ void __launch_bounds__(SB) kavg_kernel(long n, int nk, long stride, const double2* __restrict__ G,
+                                                  double2* __restrict__ out) {
+  const double inv = 1.0 / nk;
+  for (long x = (long)blockIdx.x * SB + threadIdx.x; x < n; x += (long)gridDim.x * SB) {
+    double2 acc = G[x];
+    for (int q = 1; q < nk; ++q) acc = cadd(acc, G[q * stride + x]);
+    out[x] = make_double2(acc.x * inv, acc.y * inv);
+  }
+}
+
 inline size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 struct ScbaLayout {
   size_t rgf, ec, sig, total;   // bytes: sweeps' workspace, convolution's, one [n_e][nb][b][b] array
+  bool kavg;                    // several k-points: one more such array for their average
 };
 
-bool scba_layout(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
-                 ScbaLayout& L) {
-  if (!problem || n_w < 1) return false;
-  const negf_problem& p = *problem;
+// the problems (k-points) of one loop share the block shape and the energy count
+bool scba_layout(const negf_problem* problems, int32_t n_prob, negf_precision prec, const negf_options* opt,
+                 int32_t n_w, ScbaLayout& L) {
+  if (!problems || n_prob < 1 || n_w < 1) return false;
+  const negf_problem& p = problems[0];
   if (p.n_e < 1 || p.dev.nb < 2 || p.dev.b < 1) return false;
-  L.rgf = negf_workspace_bytes(NEGF_OP_LESSER_GREATER, problem, 1, prec, opt);
+  for (int q = 1; q < n_prob; ++q)
+    if (problems[q].n_e != p.n_e || problems[q].dev.nb != p.dev.nb || problems[q].dev.b != p.dev.b) return false;
+  L.rgf = negf_workspace_bytes(NEGF_OP_LESSER_GREATER, problems, n_prob, prec, opt);
   L.ec = negf_econv_workspace_bytes(p.n_e, n_w);
   if (L.rgf == 0 || L.ec == 0) return false;
   L.sig = (size_t)p.n_e * p.dev.nb * p.dev.b * p.dev.b * sizeof(double2);
-  L.total = up256(L.rgf) + up256(L.ec) + 2 * up256(L.sig) + up256(2 * RPARTS * sizeof(double)) +
+  L.kavg = n_prob > 1;
+  L.total = up256(L.rgf) + up256(L.ec) + (L.kavg ? 3 : 2) * up256(L.sig) + up256(2 * RPARTS * sizeof(double)) +
             up256(sizeof(double)) + up256(2 * sizeof(int)) + 256;
   return true;
 }
@@ -179,7 +197,8 @@ namespace negf {
 namespace {
 
 struct StepArgs {
-  const negf_problem* problem;
+  const negf_problem* problem;   // n_prob problems: one per k-point
+  int32_t n_prob;
   negf_precision prec;
   const negf_options* opt;
   int32_t n_w, k0;
@@ -195,12 +214,14 @@ struct StepArgs {
 
 // argument checks shared by the step and the driver; fills the layout
 negf_status check_step(const StepArgs& a, ScbaLayout& L) {
-  if (!a.problem || !a.scale) return NEGF_EINVAL;
-  const negf_problem& p0 = *a.problem;
-  const negf_device& d0 = p0.dev;
-  if (d0.sig_r_sc || d0.sig_l_sc || d0.sig_g_sc || p0.sc_stride != 0) return NEGF_EINVAL;
+  if (!a.problem || a.n_prob < 1 || !a.scale) return NEGF_EINVAL;
+  for (int q = 0; q < a.n_prob; ++q) {
+    const negf_problem& pq = a.problem[q];
+    const negf_device& dq = pq.dev;
+    if (dq.sig_r_sc || dq.sig_l_sc || dq.sig_g_sc || pq.sc_stride != 0) return NEGF_EINVAL;
+  }
   if (a.k0 < 0 || a.k0 >= a.n_w || !(a.mixing > 0.0 && a.mixing <= 1.0) || !(a.tol >= 0.0)) return NEGF_EINVAL;
-  if (!scba_layout(a.problem, a.prec, a.opt, a.n_w, L)) return NEGF_EINVAL;
+  if (!scba_layout(a.problem, a.n_prob, a.prec, a.opt, a.n_w, L)) return NEGF_EINVAL;
   const void* req[] = {a.W_lesser, a.W_greater, a.sig_r, a.sig_l, a.sig_g, a.GR_diag, a.GR_upper, a.GL_diag,
                        a.GL_upper, a.GG_diag, a.GG_upper, a.info, a.workspace};
   for (const void* q : req)
@@ -213,7 +234,7 @@ negf_status check_step(const StepArgs& a, ScbaLayout& L) {
 
 struct Carved {
   void *rgf, *ec;
-  double2 *Fl, *Fg;
+  double2 *Fl, *Fg, *Gk;   // Gk: the k-average (nullptr with one k-point)
   double *part, *last;
   int* state;
 };
@@ -229,6 +250,11 @@ Carved carve(void* workspace, const ScbaLayout& L) {
   base += up256(L.sig);
   c.Fg = (double2*)base;
   base += up256(L.sig);
+  c.Gk = nullptr;
+  if (L.kavg) {
+    c.Gk = (double2*)base;
+    base += up256(L.sig);
+  }
   c.part = (double*)base;
   base += up256(2 * RPARTS * sizeof(double));
   c.last = (double*)base;
@@ -258,18 +284,34 @@ negf_status step_impl(const StepArgs& a, const ScbaLayout& L, const Carved& c, i
     prof_end(KC_ELEM, s, 0.0, 48.0 * (double)n);
     if (hipGetLastError() != hipSuccess) return NEGF_EHIP;
   }
-  negf_problem pq = p0;
-  pq.dev.sig_r_sc = a.sig_r;
-  pq.dev.sig_l_sc = a.sig_l;
-  pq.dev.sig_g_sc = a.sig_g;
-  pq.sc_stride = nbb;
-  negf_status st = negf_rgf_lesser_greater(&pq, 1, a.prec, a.opt, a.GR_diag, a.GR_upper, a.GR_lower, a.GL_diag,
-                                           a.GL_upper, a.GG_diag, a.GG_upper, a.info, c.rgf, L.rgf, s);
+  // every k-point reads the same per-energy self-energies
+  std::vector<negf_problem> pq(a.problem, a.problem + a.n_prob);
+  for (negf_problem& q : pq) {
+    q.dev.sig_r_sc = a.sig_r;
+    q.dev.sig_l_sc = a.sig_l;
+    q.dev.sig_g_sc = a.sig_g;
+    q.sc_stride = nbb;
+  }
+  negf_status st = negf_rgf_lesser_greater(pq.data(), a.n_prob, a.prec, a.opt, a.GR_diag, a.GR_upper, a.GR_lower,
+                                           a.GL_diag, a.GL_upper, a.GG_diag, a.GG_upper, a.info, c.rgf, L.rgf, s);
   if (st != NEGF_OK) return st;
-  st = negf_energy_convolution(p0.n_e, nbb, a.GL_diag, a.n_w, a.k0, a.W_lesser, a.scale, c.Fl, c.ec, L.ec, s);
-  if (st != NEGF_OK) return st;
-  st = negf_energy_convolution(p0.n_e, nbb, a.GG_diag, a.n_w, a.k0, a.W_greater, a.scale, c.Fg, c.ec, L.ec, s);
-  if (st != NEGF_OK) return st;
+  // the convolution of Eq. (3) on G^<> (averaged over the k-points when there are several)
+  const unsigned avg_grid = (unsigned)std::min<long>((n + SB - 1) / SB, MIX_WG);
+  const void* Gsrc[2] = {a.GL_diag, a.GG_diag};
+  const void* Wk[2] = {a.W_lesser, a.W_greater};
+  double2* Fk[2] = {c.Fl, c.Fg};
+  for (int kind = 0; kind < 2; ++kind) {
+    const void* Gin = Gsrc[kind];
+    if (c.Gk) {
+      prof_begin(KC_ELEM, s);
+      hipLaunchKernelGGL(kavg_kernel, dim3(avg_grid), dim3(SB), 0, s, n, (int)a.n_prob, n, (const double2*)Gin,
+                         c.Gk);
+      prof_end(KC_ELEM, s, 0.0, 16.0 * (double)n * (a.n_prob + 1));
+      Gin = c.Gk;
+    }
+    st = negf_energy_convolution(p0.n_e, nbb, Gin, a.n_w, a.k0, Wk[kind], a.scale, Fk[kind], c.ec, L.ec, s);
+    if (st != NEGF_OK) return st;
+  }
   prof_begin(KC_ELEM, s);
   hipLaunchKernelGGL(resid_partial_kernel, dim3(part_grid), dim3(SB), 0, s, n, (const double2*)c.Fl,
                      (const double2*)c.Fg, (const double2*)Sl, (const double2*)Sg, c.part);
@@ -287,19 +329,19 @@ negf_status step_impl(const StepArgs& a, const ScbaLayout& L, const Carved& c, i
 
 extern "C" {
 
-size_t negf_scba_workspace_bytes(const negf_problem* problem, negf_precision prec, const negf_options* opt,
-                                 int32_t n_w) {
+size_t negf_scba_workspace_bytes(const negf_problem* problems, int32_t n_prob, negf_precision prec,
+                                 const negf_options* opt, int32_t n_w) {
   ScbaLayout L;
-  return scba_layout(problem, prec, opt, n_w, L) ? L.total : 0;
+  return scba_layout(problems, n_prob, prec, opt, n_w, L) ? L.total : 0;
 }
 
-negf_status negf_scba_step(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
-                           int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
-                           double mixing, double tol, int32_t it, int32_t update, void* sig_r, void* sig_l,
-                           void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper,
-                           void* GG_diag, void* GG_upper, int32_t* info, double* history, int32_t* state,
-                           void* workspace, size_t ws_bytes, void* stream) {
-  StepArgs a{problem, prec, opt, n_w, k0, W_lesser, W_greater, scale, mixing, tol, sig_r, sig_l, sig_g,
+negf_status negf_scba_step(const negf_problem* problem, int32_t n_prob, negf_precision prec, const negf_options* opt,
+                           int32_t n_w, int32_t k0, const void* W_lesser, const void* W_greater,
+                           const double* scale, double mixing, double tol, int32_t it, int32_t update, void* sig_r,
+                           void* sig_l, void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag,
+                           void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info, double* history,
+                           int32_t* state, void* workspace, size_t ws_bytes, void* stream) {
+  StepArgs a{problem, n_prob, prec, opt, n_w, k0, W_lesser, W_greater, scale, mixing, tol, sig_r, sig_l, sig_g,
              GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper, info, workspace, ws_bytes};
   ScbaLayout L;
   negf_status st = check_step(a, L);
@@ -308,13 +350,13 @@ negf_status negf_scba_step(const negf_problem* problem, negf_precision prec, con
   return step_impl(a, L, carve(workspace, L), it, update != 0, history, state, (hipStream_t)stream);
 }
 
-negf_status negf_scba(const negf_problem* problem, negf_precision prec, const negf_options* opt, int32_t n_w,
-                      int32_t k0, const void* W_lesser, const void* W_greater, const double* scale, double mixing,
-                      double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g, void* GR_diag,
-                      void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper, void* GG_diag, void* GG_upper,
-                      int32_t* info, int32_t* n_iter, double* history, void* workspace, size_t ws_bytes,
-                      void* stream) {
-  StepArgs a{problem, prec, opt, n_w, k0, W_lesser, W_greater, scale, mixing, tol, sig_r, sig_l, sig_g,
+negf_status negf_scba(const negf_problem* problem, int32_t n_prob, negf_precision prec, const negf_options* opt,
+                      int32_t n_w, int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
+                      double mixing, double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g,
+                      void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper, void* GG_diag,
+                      void* GG_upper, int32_t* info, int32_t* n_iter, double* history, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  StepArgs a{problem, n_prob, prec, opt, n_w, k0, W_lesser, W_greater, scale, mixing, tol, sig_r, sig_l, sig_g,
              GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper, info, workspace, ws_bytes};
   if (!n_iter || max_iter < 1) return NEGF_EINVAL;
   ScbaLayout L;

@@ -189,11 +189,17 @@ def test_self_consistent_loop_rejects_synchronously(L):
     pr, keep = _fake_problem(nb_=4, b=8, n_e=6)
     arr = (nb.negf_problem * 1)(pr)
     n_w = 5
-    ws = L.negf_scba_workspace_bytes(arr, nb.PLAIN_FP64, None, n_w)
+    ws = L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, n_w)
     sig_bytes = 6 * 4 * 8 * 8 * 16
     assert ws >= L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr, 1, nb.PLAIN_FP64, None) + 2 * sig_bytes
-    assert L.negf_scba_workspace_bytes(arr, nb.PLAIN_FP64, None, 0) == 0
-    assert L.negf_scba_workspace_bytes(arr, nb.PLAIN_FP64, None, 4092) == 0      # 6 + 4092 - 1 > 4096
+    assert L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 0) == 0
+    assert L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 4092) == 0   # 6 + 4092 - 1 > 4096
+    assert L.negf_scba_workspace_bytes(arr, 0, nb.PLAIN_FP64, None, n_w) == 0
+    # k-points must share the block shape and the energy count; several need room for their average
+    other, keep_o = _fake_problem(nb_=4, b=8, n_e=5)
+    assert L.negf_scba_workspace_bytes((nb.negf_problem * 2)(pr, other), 2, nb.PLAIN_FP64, None, n_w) == 0
+    two = L.negf_scba_workspace_bytes((nb.negf_problem * 2)(pr, pr), 2, nb.PLAIN_FP64, None, n_w)
+    assert two > ws
     one = (C.c_double * 2)(0.0, 1.0)
     bufs = [np.zeros(64, dtype=np.complex128) for _ in range(13)]
     W_l, W_g, s_r, s_l, s_g, grd, gru, grl, gld, glu, ggd, ggu, info = [b.ctypes.data for b in bufs]
@@ -203,7 +209,7 @@ def test_self_consistent_loop_rejects_synchronously(L):
     def call(a=arr, k0=2, mixing=0.5, tol=1e-10, max_iter=8, wsb=ws, **over):
         p = dict(W_l=W_l, W_g=W_g, s_r=s_r, s_l=s_l, s_g=s_g, ggd=ggd, info=info, scale=one, n_iter=C.byref(n_iter))
         p.update(over)
-        return L.negf_scba(a, nb.PLAIN_FP64, None, n_w, k0, p["W_l"], p["W_g"], p["scale"], mixing, tol, max_iter,
+        return L.negf_scba(a, 1, nb.PLAIN_FP64, None, n_w, k0, p["W_l"], p["W_g"], p["scale"], mixing, tol, max_iter,
                            p["s_r"], p["s_l"], p["s_g"], grd, gru, grl, gld, glu, p["ggd"], ggu, p["info"],
                            p["n_iter"], hist, grd, wsb, None)
 
@@ -224,13 +230,13 @@ def test_self_consistent_step_rejects_synchronously(L):
     from paper_2602_03438_amd import binding as nb
     pr, keep = _fake_problem(nb_=4, b=8, n_e=6)
     arr = (nb.negf_problem * 1)(pr)
-    ws = L.negf_scba_workspace_bytes(arr, nb.PLAIN_FP64, None, 5)
+    ws = L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 5)
     one = (C.c_double * 2)(0.0, 1.0)
     bufs = [np.zeros(64, dtype=np.complex128) for _ in range(14)]
     W_l, W_g, s_r, s_l, s_g, grd, gru, grl, gld, glu, ggd, ggu, info, state = [b.ctypes.data for b in bufs]
 
     def call(it=0, st=state, k0=2, wsb=ws):
-        return L.negf_scba_step(arr, nb.PLAIN_FP64, None, 5, k0, W_l, W_g, one, 0.5, 1e-10, it, 1, s_r, s_l, s_g, grd,
+        return L.negf_scba_step(arr, 1, nb.PLAIN_FP64, None, 5, k0, W_l, W_g, one, 0.5, 1e-10, it, 1, s_r, s_l, s_g, grd,
                                 gru, grl, gld, glu, ggd, ggu, info, None, st, grd, wsb, None)
     assert call(it=-1) == nb.NEGF_EINVAL
     assert call(st=None) == nb.NEGF_EINVAL
