@@ -254,6 +254,8 @@ def main():
                                                                           "workload")
     ap.add_argument("--scattering-batch", type=int, default=64, help="points per call in the scattering workload")
     ap.add_argument("--scba-freqs", type=int, default=17, help="bath frequencies of the scba workload")
+    ap.add_argument("--scba-kpoints", type=int, default=1, help="transverse momenta of the scba workload (k = pi j / 4; "
+                                                             "the self-energies are shared, built from their average)")
     ap.add_argument("--scba-strength", type=float, default=0.05, help="bath strength of the scba workload")
     ap.add_argument("--serinv-points", default="1,2,4,8", help="energy points per call in the serinv workload")
     ap.add_argument("--serinv-parts", default="4,8", help="partition counts in the serinv workload")
@@ -850,9 +852,10 @@ def bench_scba(args):
     import workloads as w
     from paper_2602_03438_amd import autotune
     from paper_2602_03438_amd import binding as nb
-    n_e, n_w = args.scba_energies, args.scba_freqs
+    n_e, n_w, nk = args.scba_energies, args.scba_freqs, args.scba_kpoints
     k0 = (n_w - 1) // 2
     dev = w.slab_device(NB, B, SEED)
+    devs = [dev] if nk == 1 else [w.k_device(dev, 31, np.pi * j / 4) for j in range(nk)]
     E = np.linspace(-1.5, 1.5, n_e)
     dE = float(E[1] - E[0])
     Wl, Wg = w.boson_bath(NB, B, n_w, k0, dE, KT, strength=args.scba_strength)
@@ -861,13 +864,15 @@ def bench_scba(args):
     t = autotune.lookup(B, args.cmul)
     opts = nb.make_options(inv_nb=args.inv_nb or t["inv_nb"], cmul=args.cmul, gemm_tile=t["gemm_tile"],
                            gemm_tile_f32=t["gemm_tile_f32"], sr_max_iter=args.sr_max_iter)
-    prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT)
+    probs = [nb.Problem(nb.DeviceOnGPU(d), E, eta=ETA, mu_l=MU_L, mu_r=MU_R, kT=KT) for d in devs]
+    prob = probs if nk > 1 else probs[0]
     ws = nb.Workspace()
-    outs = nb._rgf_outputs([prob], True, True, True)
+    outs = nb._rgf_outputs(probs, True, True, True)
     shape = (n_e, NB, B, B)
     sig = {k: torch.zeros(shape, dtype=torch.complex128, device="cuda") for k in ("sig_r", "sig_l", "sig_g")}
     scale = 1j * dE / (2 * np.pi)
-    log(f"scba: {n_e} energies x Nb={NB} b={B}, {n_w} bath frequencies; warm-up {args.warmup} iteration(s)")
+    log(f"scba: {nk} k-point(s) x {n_e} energies x Nb={NB} b={B}, {n_w} bath frequencies; warm-up {args.warmup} "
+        f"iteration(s)")
     if args.warmup > 0:
         nb.scba(prob, gWl, gWg, k0, scale, tol=0.0, max_iter=args.warmup, opts=opts, ws=ws, outputs=outs, sigmas=sig)
     for v in sig.values():
@@ -880,8 +885,8 @@ def bench_scba(args):
     log(f"scba: {its} iteration(s) in {dt:.2f} s, residuals {['%.2e' % h for h in r['history']]}")
     # the two convolutions of one iteration, alone
     n_el = NB * B * B
-    GL = outs["GL_diag"].view(n_e, n_el)
-    GG = outs["GG_diag"].view(n_e, n_el)
+    GL = outs["GL_diag"][: n_e * n_el].view(n_e, n_el)
+    GG = outs["GG_diag"][: n_e * n_el].view(n_e, n_el)
     Fl = torch.empty_like(GL)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     s = torch.cuda.current_stream()
@@ -897,10 +902,11 @@ def bench_scba(args):
     flops = point_flops(NB, B) + float(B) ** 3 * (16 + 64 * (NB - 1))      # + G^>
     line = {"metric": "self-consistent loop (Fig. 1, Eq. (1)-(3)) at Nb=60, b=512: energy points solved and "
                       "convolved per second",
-            "value": n_e * its / dt, "unit": "energy points/s", "n_gpus": 1, "steps": its, "warmup": args.warmup,
+            "value": nk * n_e * its / dt, "unit": "energy points/s", "n_gpus": 1, "steps": its, "warmup": args.warmup,
             "ms_per_step": it_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
-            "config": {"workload": f"nano-ribbon-like slab device Nb={NB} b={B}, {n_e} energies on [-1.5, 1.5], "
+            "config": {"workload": f"nano-ribbon-like slab device Nb={NB} b={B}, {nk} k-point(s) x {n_e} energies on "
+                                   f"[-1.5, 1.5], "
                                    f"boson bath of {n_w} frequencies (strength {args.scba_strength}, kT={KT}), "
                                    f"eta={ETA}, mixing 0.5, one iteration per step",
                        "real_products_per_complex_product": args.cmul, "sr_max_iter": args.sr_max_iter},
@@ -908,7 +914,7 @@ def bench_scba(args):
             "convolution_share": conv_ms / it_ms, "residual_history": r["history"], "status": r["status"],
             "info_nonzero": int(torch.count_nonzero(r["info"]).item()),
             "roofline": executed_roofline(nb, stats, dt, args.cmul, "timed iterations, products event-timed"),
-            "algorithmic": algorithmic_roofline(flops, it_ms * 1e-3 / n_e,
+            "algorithmic": algorithmic_roofline(flops, it_ms * 1e-3 / (nk * n_e),
                                                 "G^R + G^< + G^> of one energy point (both leads, 28 decimation "
                                                 "steps) per (iteration time / energies); the convolutions add no "
                                                 "flops to the count"),
