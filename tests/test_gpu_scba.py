@@ -400,3 +400,20 @@ def test_loop_over_k_points_matches_oracle(nb, b):
     torch.cuda.synchronize()
     for n in ("sig_l", "sig_g", "sig_r"):
         assert torch.equal(one[n], twice[n]), n
+
+
+def test_loop_over_k_points_conserves_the_summed_current(nb):
+    """Converged over two k-points (b = 24): the energy-integrated current summed over the k-points is the
+    same at every interface (negf_observables on the loop's outputs)."""
+    import torch
+    base, devs = _k_devices(24)
+    E, dE, k0, Wl, Wg = _bath(base, 40, n_w=13)
+    probs = [nb.Problem(nb.DeviceOnGPU(d), E, eta=ETA, mu_l=0.1, mu_r=-0.1, kT=KT) for d in devs]
+    res = nb.scba(probs, torch.from_numpy(Wl).cuda(), torch.from_numpy(Wg).cuda(), k0, 1j * dE / (2 * math.pi),
+                  mixing=1.0, tol=1e-12, max_iter=40)
+    assert res["status"] == nb.NEGF_OK, res["history"]
+    cur = nb.observables(probs, res["flat"], dos=False)["current"]
+    J = sum(c.cpu().numpy().sum(axis=0) for c in cur)
+    err = float(np.abs(J - J[0]).max() / abs(J[0]))
+    record("scba_k_points_current", 0.0, "J", err, 1e-9)
+    assert err < 1e-9, J
