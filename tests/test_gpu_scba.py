@@ -417,3 +417,18 @@ def test_loop_over_k_points_conserves_the_summed_current(nb):
     err = float(np.abs(J - J[0]).max() / abs(J[0]))
     record("scba_k_points_current", 0.0, "J", err, 1e-9)
     assert err < 1e-9, J
+
+
+def test_loop_reports_a_non_finite_residual(nb):
+    """A NaN in the bath makes the first residual non-finite: negf_scba returns ENONFINITE after that
+    solve, and the self-energies are left as they were (the mixing pass reads the state)."""
+    import torch
+    dev = w.folded_chain_device(4, 8)
+    E, dE, k0, Wl, Wg = _bath(dev, 20)
+    Wl = Wl.copy()
+    Wl[k0, 1, 2, 3] = np.nan
+    res = _gpu_loop(nb, dev, E, Wl, Wg, k0, 1j * dE / (2 * math.pi), 0.1, -0.1, tol=1e-12, max_iter=5)
+    assert res["status"] == nb.NEGF_ENONFINITE and res["n_iter"] == 1, (res["status"], res["history"])
+    assert not math.isfinite(res["history"][0])
+    for n in ("sig_r", "sig_l", "sig_g"):
+        assert not bool(res[n].abs().max() > 0), n          # still the zero start
