@@ -243,7 +243,10 @@ def main():
                          "dominant product kernel alone through negf_zgemm_batched at the headline's block size "
                          "and batch (for hardware counters); serinv: few energies per call, plain RGF against the "
                          "partitioned inversion; econv: the energy convolution of Eq. (3) and the energy/element "
-                         "layout change over one GPU's share of the selected entries")
+                         "layout change over one GPU's share of the selected entries; scba: the self-consistent "
+                         "loop of Fig. 1 at the headline device; small: G^R and T of the small ballistic devices "
+                         "(Nb=32, b=8) at every point against the oracle; scattering: G^R, G^<, G^> with "
+                         "scattering self-energies at 4 k-points x 512 energies")
     ap.add_argument("--econv-cpu-elements", type=int, default=8192,
                     help="elements the oracle computes for the econv workload's cpu_baseline")
     ap.add_argument("--econv-elements", type=int, default=1 << 21, help="elements (matrix entries) in the econv "
