@@ -31,6 +31,14 @@ r_n <= tol, or at n = max_iter - 1, and returns Sigma_n with the Green's
 functions that Sigma_n produced (so G^<> = G Sigma^<>_n G^H holds for the
 returned pair); otherwise Sigma_{n+1} = Sigma_n + m (F - Sigma_n) for both
 kinds, and Sigma^R_{n+1} = (Sigma^>_{n+1} - Sigma^<_{n+1}) / 2.
+
+With a memory M > 0 the update is Anderson's (Pulay's) extrapolation instead:
+x = (Sigma^<, Sigma^>), f = F - x, and the differences dx_j, df_j of the last
+k = min(n, M) pairs (x, f);  gamma minimises ||f_n - sum_j gamma_j df_j||
+(the normal equations A gamma = r with A_ij = Re <df_i, df_j>,
+r_i = Re <df_i, f_n>, A's diagonal raised by 1e-12 trace(A) / k), and
+x_{n+1} = x_n + m f_n - sum_j gamma_j (dx_j + m df_j)  (D. G. Anderson,
+J. ACM 12, 547 (1965); P. Pulay, Chem. Phys. Lett. 73, 393 (1980)).
 """
 from __future__ import annotations
 
@@ -94,8 +102,22 @@ def convolve(points, W_l, W_g, k0, scale):
     return Fl.reshape(shp), Fg.reshape(shp)
 
 
+def anderson(x, f, dxs, dfs, mixing):
+    """x_{n+1} from x_n, f_n and the differences of the previous pairs (lists, any order)."""
+    k = len(dfs)
+    if k == 0:
+        return x + mixing * f
+    DF = np.array(dfs)
+    DX = np.array(dxs)
+    A = np.real(DF.conj() @ DF.T)
+    r = np.real(DF.conj() @ f)
+    A = A + 1e-12 * np.trace(A) / k * np.eye(k)
+    g = np.linalg.solve(A, r)
+    return x + mixing * f - g @ (DX + mixing * DF)
+
+
 def scba(dev, energies, eta, mu_l, mu_r, kT, W_l, W_g, k0, scale, mixing=0.5, tol=1e-10, max_iter=50,
-         sig0=None) -> ScbaResult:
+         sig0=None, memory=0) -> ScbaResult:
     """The loop of Fig. 1 with a fixed bath.  ``sig0`` = (Sigma^<, Sigma^>) to start from
     (default zero: the ballistic solution is iteration 0); ``energies`` must be uniform, the
     spacing entering only through ``scale`` (i dE / 2 pi for the usual normalisation).  ``dev`` may
@@ -110,6 +132,7 @@ def scba(dev, energies, eta, mu_l, mu_r, kT, W_l, W_g, k0, scale, mixing=0.5, to
         Sg = np.array(sig0[1], dtype=np.complex128)
     Sr = retarded_from(Sl, Sg)
     hist = []
+    prev, dxs, dfs = None, [], []
     for n in range(max_iter):
         if devs is None:
             pts = solve_all(dev, energies, eta, mu_l, mu_r, kT, Sr, Sl, Sg)
@@ -120,7 +143,20 @@ def scba(dev, energies, eta, mu_l, mu_r, kT, W_l, W_g, k0, scale, mixing=0.5, to
         hist.append(r)
         if r <= tol or n == max_iter - 1 or not math.isfinite(r):
             return ScbaResult(Sr, Sl, Sg, pts, n + 1, hist, r <= tol)
-        Sl = Sl + mixing * (Fl - Sl)
-        Sg = Sg + mixing * (Fg - Sg)
+        if memory == 0:
+            Sl = Sl + mixing * (Fl - Sl)
+            Sg = Sg + mixing * (Fg - Sg)
+        else:
+            x = np.concatenate([Sl.ravel(), Sg.ravel()])
+            f = np.concatenate([Fl.ravel(), Fg.ravel()]) - x
+            if prev is not None:
+                dxs.append(x - prev[0])
+                dfs.append(f - prev[1])
+                dxs, dfs = dxs[-memory:], dfs[-memory:]
+            prev = (x, f)
+            xn = anderson(x, f, dxs, dfs, mixing)
+            h = xn.size // 2
+            Sl = xn[:h].reshape(Sl.shape)
+            Sg = xn[h:].reshape(Sg.shape)
         Sr = retarded_from(Sl, Sg)
     raise ValueError("max_iter must be at least 1")

@@ -236,3 +236,31 @@ def test_k_points_average_and_conserve_the_summed_current():
         for p in pk:
             J += observables.currents([p.E * d.s_upper(i) - d.H_upper[i] for i in range(d.nb - 1)], p.GL_upper)
     assert np.abs(J - J[0]).max() <= 1e-9 * abs(J[0]), J
+
+
+def test_anderson_mixing_reaches_the_fixed_point_where_linear_mixing_does_not():
+    """Anderson's extrapolation (memory 3): on a contractive case the same fixed point as linear mixing
+    (1e-10) in fewer solves; on a periodic wire at a coupling where linear mixing first converges and then
+    diverges (an unstable mode grows out of rounding), it converges; memory 0 is linear mixing exactly."""
+    from oracle import scba
+    dev = w.folded_chain_device(4, 4)
+    E, dE = _grid(32)
+    n_w, k0 = 9, 4
+    scale = 1j * dE / (2 * math.pi)
+    Wl, Wg = w.boson_bath(dev.nb, dev.b, n_w, k0, dE, KT, strength=1.0)
+    lin = scba.scba(dev, E, 1e-6, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=0.5, tol=1e-12, max_iter=80)
+    and3 = scba.scba(dev, E, 1e-6, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=0.5, tol=1e-12, max_iter=80, memory=3)
+    assert lin.converged and and3.converged and and3.n_iter < lin.n_iter, (lin.n_iter, and3.n_iter)
+    assert np.abs(and3.sig_l - lin.sig_l).max() <= 1e-10 * np.abs(lin.sig_l).max()
+    zero = scba.scba(dev, E, 1e-6, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=0.5, tol=0.0, max_iter=4, memory=0)
+    ref = scba.scba(dev, E, 1e-6, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=0.5, tol=0.0, max_iter=4)
+    assert np.array_equal(zero.sig_l, ref.sig_l)
+    wire = w.periodic_wire_device(4, 4, 3)
+    Ew = w.energy_grid(-3.0, 3.0, 64)
+    dEw = float(Ew[1] - Ew[0])
+    Wl, Wg = w.boson_bath(wire.nb, wire.b, 17, 8, dEw, KT, strength=0.2)
+    sw = 1j * dEw / (2 * math.pi)
+    lin = scba.scba(wire, Ew, 1e-6, 0.1, -0.1, KT, Wl, Wg, 8, sw, mixing=1.0, tol=1e-12, max_iter=40)
+    assert not lin.converged and lin.history[-1] > 1e-9
+    acc = scba.scba(wire, Ew, 1e-6, 0.1, -0.1, KT, Wl, Wg, 8, sw, mixing=1.0, tol=1e-12, max_iter=40, memory=3)
+    assert acc.converged, acc.history
