@@ -301,8 +301,17 @@ negf_status negf_observables(const negf_problem* problems, int32_t n_prob, const
  * measures r_n = ||F - Sigma_n||_F / ||F||_F over both kinds, every energy
  * and block (0 when both norms are 0); it stops when r_n <= tol or at
  * n = max_iter - 1, leaving Sigma_n and the Green's functions it produced in
- * the outputs, else Sigma_{n+1} = Sigma_n + mixing (F - Sigma_n) (both kinds)
- * and Sigma^R_{n+1} = (Sigma^>_{n+1} - Sigma^<_{n+1}) / 2.
+ * the outputs, else, with memory = 0, Sigma_{n+1} = Sigma_n + mixing
+ * (F - Sigma_n) (both kinds), and Sigma^R_{n+1} = (Sigma^>_{n+1} -
+ * Sigma^<_{n+1}) / 2.  With memory M in 1..4 the update is Anderson's (Pulay's)
+ * extrapolation instead: x = (Sigma^<, Sigma^>), f = F - x, dx_j and df_j the
+ * differences of the last k = min(n, M) consecutive pairs (x, f), gamma the
+ * solution of A gamma = r with A_ij = Re <df_i, df_j> (diagonal raised by
+ * 1e-12 trace(A) / k) and r_i = Re <df_i, f_n>, and
+ * x_{n+1} = x_n + mixing f_n - sum_j gamma_j (dx_j + mixing df_j); it
+ * converges where linear mixing diverges on some devices, at the cost of
+ * 2 M + 2 more [n_e][nb][b][b] pairs of workspace (a singular A, df all zero,
+ * gives a non-finite Sigma and NEGF_ENONFINITE at the next residual).
  * problem[n_prob]: devices without scattering self-energies and sc_stride 0
  * (the loop supplies both).  sig_r / sig_l / sig_g: device,
  * [n_e][nb][b][b] complex128, in: Sigma_0 (sig_r is overwritten from sig_l
@@ -314,38 +323,43 @@ negf_status negf_observables(const negf_problem* problems, int32_t n_prob, const
  * negf_scba drives negf_scba_step from the host and synchronises `stream` once
  * per iteration to read the loop state (the stopping decision), so it cannot
  * be captured in a graph; negf_scba_step can.
- * Requirements: 0 <= k0 < n_w, n_e + n_w - 1 <= 4096, 0 < mixing <= 1,
+ * Requirements: 0 <= k0 < n_w, n_e + n_w - 1 <= 4096, 0 < mixing <= 1, 0 <= memory <= 4,
  * tol >= 0, max_iter >= 1.  Returns NEGF_OK when r_n <= tol was reached,
  * NEGF_ENOCONV when max_iter solves ended above tol, NEGF_ENONFINITE when r_n
  * is not finite (the outputs then hold that iteration); argument errors
  * (EINVAL) before any work.  Workspace: negf_scba_workspace_bytes(...). */
 size_t negf_scba_workspace_bytes(const negf_problem* problems, int32_t n_prob, negf_precision prec,
-                                 const negf_options* opt, int32_t n_w);
+                                 const negf_options* opt, int32_t n_w, int32_t memory);
 /* One iteration of that loop, enqueued on `stream` with no host
  * synchronisation (capturable in a graph); arguments as for negf_scba plus:
  * it: the iteration index (it = 0 starts a loop: the state is reset and
- * Sigma^R formed from sig_l, sig_g); update: 0 = never mix (the last
+ * Sigma^R formed from sig_l, sig_g; with memory > 0 the iterations of a loop
+ * are it = 0, 1, 2, ... in order, each but the last with update = 1, since
+ * the Anderson history kept in the workspace counts on it); update: 0 = never mix (the last
  * iteration of a fixed count, so that the outputs hold Sigma_n and the Green's
  * functions it produced); history: nullable device array, history[it] = r_it;
  * state: device int32[2], [0] = solves performed until r <= tol (or so far),
  * [1] = 0 running, 1 converged, 2 non-finite residual.  Once [1] != 0 the
  * self-energies are no longer changed, so further iterations recompute the
  * same Green's functions (a fixed number of iterations ends where a loop
- * stopped at convergence ends).  The workspace (negf_scba_workspace_bytes)
- * holds only one iteration's temporaries, so any workspace of that size
- * serves any iteration; the loop's state and history live in caller memory.
+ * stopped at convergence ends).  With memory = 0 the workspace
+ * (negf_scba_workspace_bytes) holds only one iteration's temporaries, so any
+ * workspace of that size serves any iteration; with memory > 0 it also holds
+ * the Anderson history, which belongs to one loop.  The loop's state and
+ * r history live in caller memory.
  * The iterations of a loop go on one stream in order; calls that overlap on
  * one workspace or one state race.  Errors: EINVAL (as negf_scba, it < 0,
  * state NULL or misaligned), EHIP. */
 negf_status negf_scba_step(const negf_problem* problem, int32_t n_prob, negf_precision prec, const negf_options* opt,
                            int32_t n_w, int32_t k0, const void* W_lesser, const void* W_greater,
-                           const double* scale, double mixing, double tol, int32_t it, int32_t update, void* sig_r,
-                           void* sig_l, void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag,
+                           const double* scale, double mixing, int32_t memory, double tol, int32_t it,
+                           int32_t update, void* sig_r, void* sig_l, void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag,
                            void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info, double* history,
                            int32_t* state, void* workspace, size_t ws_bytes, void* stream);
 negf_status negf_scba(const negf_problem* problem, int32_t n_prob, negf_precision prec, const negf_options* opt,
                       int32_t n_w, int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
-                      double mixing, double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g,
+                      double mixing, int32_t memory, double tol, int32_t max_iter, void* sig_r, void* sig_l,
+                      void* sig_g,
                       void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper, void* GG_diag,
                       void* GG_upper, int32_t* info, int32_t* n_iter, double* history, void* workspace,
                       size_t ws_bytes, void* stream);
@@ -534,7 +548,8 @@ negf_status negf_profile_read(negf_kernel_stats* stats);
 
 const char* negf_status_string(negf_status s);
 /* 101: negf_problem carries sc_stride (energy-dependent scattering
- * self-energies); callers built against 100 pass a shorter struct. */
+ * self-energies); callers built against 100 pass a shorter struct.
+ * 102: the loop's entry points take the Anderson memory. */
 int32_t negf_version(void);
 
 #ifdef __cplusplus

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnegf.so")
 
 NEGF_OK, NEGF_EINVAL, NEGF_ENOCONV, NEGF_ESINGULAR, NEGF_ENONFINITE, NEGF_EHIP, NEGF_ENOMEM = range(7)
-ABI_VERSION = 101          # negf_version() of the struct layouts below (negf_problem with sc_stride)
+ABI_VERSION = 102          # negf_version() of the struct layouts and loop signatures below
 PLAIN_FP64, FP32_REFINE, FP32_NOREFINE = 0, 1, 2
 OP_OBC, OP_RETARDED, OP_LESSER_GREATER, OP_TRANSMISSION = 0, 1, 2, 3
 KC_NAMES = ["gemm_f64", "gemm_f32", "inv_panel", "inv_swap", "inv_perm", "elementwise", "inv_update_gemm",
@@ -96,13 +96,13 @@ def lib():
     L.negf_energy_convolution.restype = C.c_int
     L.negf_transpose.argtypes = [i64, i64, vp, vp, vp]
     L.negf_transpose.restype = C.c_int
-    L.negf_scba_workspace_bytes.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32]
+    L.negf_scba_workspace_bytes.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32, i32]
     L.negf_scba_workspace_bytes.restype = sz
-    L.negf_scba.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32, vp,
-                            vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(dbl), vp, sz, vp]
+    L.negf_scba.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, i32, dbl, i32,
+                            vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(dbl), vp, sz, vp]
     L.negf_scba.restype = C.c_int
-    L.negf_scba_step.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, dbl, i32,
-                                 i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.negf_scba_step.argtypes = [P(negf_problem), i32, i32, P(negf_options), i32, i32, vp, vp, P(dbl), dbl, i32, dbl,
+                                 i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.negf_scba_step.restype = C.c_int
     L.negf_observables.argtypes = [P(negf_problem), i32, vp, vp, vp, vp, vp]
     L.negf_observables.restype = C.c_int
@@ -546,13 +546,14 @@ def energy_convolution(G, W, k0, scale=1.0, out=None, ws=None):
 
 
 def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_iter=50, sig0=None, prec=PLAIN_FP64,
-         opts=None, lower=True, ws=None, outputs=None, sigmas=None):
+         opts=None, lower=True, ws=None, outputs=None, sigmas=None, memory=0):
     """negf_scba: the self-consistent loop of Fig. 1 with a fixed bath, for one problem or a list of
     problems (one per k-point, same block shape and energies; the outputs and info then run over
     them in order, point-major, and the self-energies are shared).
 
     W_lesser / W_greater: complex128 device tensors [n_w, nb, b, b] (W[k] at (k - k0) dE);
-    scale: the convolution's prefactor (e.g. 1j dE / 2 pi); sig0: optional (Sigma^<, Sigma^>)
+    scale: the convolution's prefactor (e.g. 1j dE / 2 pi); memory: 0 for linear mixing, 1..4 for
+    Anderson mixing over that many previous iterations; sig0: optional (Sigma^<, Sigma^>)
     [n_e, nb, b, b] to start from (default zero); sigmas: optional dict of caller-owned
     sig_r / sig_l / sig_g tensors to run in place (their lesser / greater contents are the
     start when sig0 is None).  Returns the outputs (per-point views), the final self-energies,
@@ -569,7 +570,7 @@ def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_ite
         if (not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous()
                 or tuple(t.shape) != (n_w, dv.nb, dv.b, dv.b)):
             raise NegfError("W_lesser / W_greater must be contiguous complex128 device tensors [n_w, nb, b, b]")
-    nbytes = lib().negf_scba_workspace_bytes(arr, len(probs), prec, o, n_w)
+    nbytes = lib().negf_scba_workspace_bytes(arr, len(probs), prec, o, n_w, int(memory))
     if nbytes == 0:
         raise NegfError("invalid problem or bath for the self-consistent loop")
     buf = (ws or Workspace()).get(nbytes)
@@ -588,8 +589,8 @@ def scba(problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_ite
     sc = (C.c_double * 2)(complex(scale).real, complex(scale).imag)
     n_iter = C.c_int32(0)
     hist = (C.c_double * max(int(max_iter), 1))()
-    code = lib().negf_scba(arr, len(probs), prec, o, n_w, int(k0), _ptr(W_lesser), _ptr(W_greater), sc, float(mixing), float(tol),
-                           int(max_iter), _ptr(sigmas["sig_r"]), _ptr(sigmas["sig_l"]), _ptr(sigmas["sig_g"]),
+    code = lib().negf_scba(arr, len(probs), prec, o, n_w, int(k0), _ptr(W_lesser), _ptr(W_greater), sc, float(mixing), int(memory),
+                           float(tol), int(max_iter), _ptr(sigmas["sig_r"]), _ptr(sigmas["sig_l"]), _ptr(sigmas["sig_g"]),
                            _ptr(out["GR_diag"]), _ptr(out["GR_upper"]), _ptr(out.get("GR_lower")),
                            _ptr(out["GL_diag"]), _ptr(out["GL_upper"]), _ptr(out["GG_diag"]), _ptr(out["GG_upper"]),
                            _ptr(info), C.byref(n_iter), hist, _ptr(buf), buf.numel(), _stream())
@@ -635,12 +636,13 @@ class ScbaLoop:
     the device history and the device state {solves, 0 running / 1 converged / 2 non-finite}."""
 
     def __init__(self, problem, W_lesser, W_greater, k0, scale, mixing=0.5, tol=1e-10, max_steps=64,
-                 prec=PLAIN_FP64, opts=None, lower=True):
+                 prec=PLAIN_FP64, opts=None, lower=True, memory=0):
         torch = _torch()
         self.problems = list(problem) if isinstance(problem, (list, tuple)) else [problem]
         self.problem, self.Wl, self.Wg, self.k0 = self.problems[0], W_lesser, W_greater, int(k0)
         self.scale = (C.c_double * 2)(complex(scale).real, complex(scale).imag)
         self.mixing, self.tol, self.prec, self.opts = float(mixing), float(tol), prec, opts
+        self.memory = int(memory)
         self._arr = _problem_array(self.problems)
         dv = self.problem.dev
         self.n_w = int(W_lesser.shape[0])
@@ -649,7 +651,7 @@ class ScbaLoop:
                     or tuple(t.shape) != (self.n_w, dv.nb, dv.b, dv.b)):
                 raise NegfError("W_lesser / W_greater must be contiguous complex128 device tensors [n_w, nb, b, b]")
         o = C.byref(opts) if opts else None
-        nbytes = lib().negf_scba_workspace_bytes(self._arr, len(self.problems), prec, o, self.n_w)
+        nbytes = lib().negf_scba_workspace_bytes(self._arr, len(self.problems), prec, o, self.n_w, self.memory)
         if nbytes == 0:
             raise NegfError("invalid problem or bath for the self-consistent loop")
         self.ws = Workspace().get(nbytes)
@@ -665,7 +667,7 @@ class ScbaLoop:
             raise NegfError("iteration index beyond the history")
         o = self.out
         check(lib().negf_scba_step(self._arr, len(self.problems), self.prec, C.byref(self.opts) if self.opts else None, self.n_w, self.k0,
-                                   _ptr(self.Wl), _ptr(self.Wg), self.scale, self.mixing, self.tol, int(it),
+                                   _ptr(self.Wl), _ptr(self.Wg), self.scale, self.mixing, self.memory, self.tol, int(it),
                                    int(bool(update)), _ptr(self.sig["sig_r"]), _ptr(self.sig["sig_l"]),
                                    _ptr(self.sig["sig_g"]), _ptr(o["GR_diag"]), _ptr(o["GR_upper"]),
                                    _ptr(o.get("GR_lower")), _ptr(o["GL_diag"]), _ptr(o["GL_upper"]),

@@ -1204,6 +1204,6 @@ const char* negf_status_string(negf_status s) {
   return "unknown status";
 }
 
-int32_t negf_version(void) { return 101; }
+int32_t negf_version(void) { return 102; }
 
 }  // extern "C"

@@ -28,6 +28,8 @@ constexpr int SB = 256;       // threads per workgroup of the streaming kernels
 constexpr int RPARTS = 1024;  // workgroups of the residual's first stage (fixed: the sum's order is fixed)
 constexpr long MIX_WG = 8192; // grid cap of the mixing pass (grid-stride beyond)
 constexpr int U = 4;          // elements per thread and pass of the streaming kernels
+constexpr int MAXM = 4;       // longest Anderson memory
+constexpr int NACC = MAXM * (MAXM + 1) / 2 + MAXM;   // accumulators of its normal equations
 
 __device__ __forceinline__ double norm2(double2 z) { return z.x * z.x + z.y * z.y; }
 
@@ -161,17 +163,157 @@ __global__ void __launch_bounds__(SB) kavg_kernel(long n, int nk, long stride, c
   }
 }
 
+// ---- Anderson (Pulay) mixing: x = (Sigma^<, Sigma^>), f = F - x, both kinds stored one after the other
+// (2n complex per vector).  History: the differences dx_j, df_j of consecutive pairs (x, f), M slots used
+// as a ring; xp, fp: the previous pair.
+
+// the previous pair's differences into slot `slot` (unless `first`), then the current pair as the previous
+__global__ void __launch_bounds__(SB) anderson_hist_kernel(long n, int first, int slot, const double2* Sl,
+                                                           const double2* Sg, const double2* Fl, const double2* Fg,
+                                                           double2* xp, double2* fp, double2* DX, double2* DF,
+                                                           const int* state) {
+  if (state[1] != 0) return;
+  for (long x = (long)blockIdx.x * SB + threadIdx.x; x < n; x += (long)gridDim.x * SB) {
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+      const double2 sv = kind ? Sg[x] : Sl[x];
+      const double2 fv = csub(kind ? Fg[x] : Fl[x], sv);
+      const long i = kind * n + x;
+      if (!first) {
+        DX[slot * 2 * n + i] = csub(sv, xp[i]);
+        DF[slot * 2 * n + i] = csub(fv, fp[i]);
+      }
+      xp[i] = sv;
+      fp[i] = fv;
+    }
+  }
+}
+
+// per workgroup: A_ij = Re <df_i, df_j> (i <= j < k, packed row by row) and r_i = Re <df_i, f>
+__global__ void __launch_bounds__(SB) anderson_gram_kernel(long n, int k, const double2* Sl, const double2* Sg,
+                                                           const double2* Fl, const double2* Fg, const double2* DF,
+                                                           double* part, const int* state) {
+  if (state[1] != 0) return;
+  __shared__ double red[SB];
+  double acc[NACC];
+#pragma unroll
+  for (int a = 0; a < NACC; ++a) acc[a] = 0.0;
+  for (long x = (long)blockIdx.x * SB + threadIdx.x; x < n; x += (long)gridDim.x * SB) {
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+      const double2 fv = csub(kind ? Fg[x] : Fl[x], kind ? Sg[x] : Sl[x]);
+      const long i = kind * n + x;
+      double2 d[MAXM];
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) d[j] = j < k ? DF[j * 2 * n + i] : make_double2(0.0, 0.0);
+      int a = 0;
+#pragma unroll
+      for (int p = 0; p < MAXM; ++p)
+#pragma unroll
+        for (int q = p; q < MAXM; ++q) acc[a++] += d[p].x * d[q].x + d[p].y * d[q].y;
+#pragma unroll
+      for (int p = 0; p < MAXM; ++p) acc[a++] += d[p].x * fv.x + d[p].y * fv.y;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NACC; ++a) {
+    const double t = wg_sum(acc[a], red);
+    if (threadIdx.x == 0) part[(long)blockIdx.x * NACC + a] = t;
+  }
+}
+
+// one workgroup: the partial sums added in a fixed order, then gamma from (A + 1e-12 trace(A) / k I) gamma = r
+// by Gaussian elimination with partial pivoting (k <= MAXM)
+__global__ void __launch_bounds__(SB) anderson_solve_kernel(int nparts, int k, const double* part, double* gamma,
+                                                            const int* state) {
+  if (state[1] != 0) return;
+  __shared__ double tot[NACC];
+  if ((int)threadIdx.x < NACC) {
+    double t = 0.0;
+    for (int w = 0; w < nparts; ++w) t += part[(long)w * NACC + threadIdx.x];
+    tot[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double A[MAXM][MAXM + 1];
+  int a = 0;
+  for (int p = 0; p < MAXM; ++p)
+    for (int q = p; q < MAXM; ++q, ++a) {
+      A[p][q] = tot[a];
+      A[q][p] = tot[a];
+    }
+  for (int p = 0; p < MAXM; ++p) A[p][MAXM] = tot[a++];
+  double tr = 0.0;
+  for (int p = 0; p < k; ++p) tr += A[p][p];
+  for (int p = 0; p < k; ++p) A[p][p] += 1e-12 * tr / k;
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (piv != c)
+      for (int q = 0; q <= MAXM; ++q) {
+        const double t = A[c][q];
+        A[c][q] = A[piv][q];
+        A[piv][q] = t;
+      }
+    for (int r = c + 1; r < k; ++r) {
+      const double l = A[r][c] / A[c][c];
+      for (int q = c; q < k; ++q) A[r][q] -= l * A[c][q];
+      A[r][MAXM] -= l * A[c][MAXM];
+    }
+  }
+  for (int c = k - 1; c >= 0; --c) {
+    double v = A[c][MAXM];
+    for (int q = c + 1; q < k; ++q) v -= A[c][q] * gamma[q];
+    gamma[c] = v / A[c][c];
+  }
+}
+
+// x += m f - sum_j gamma_j (dx_j + m df_j) for both kinds, then Sigma^R = (Sigma^> - Sigma^<) / 2
+__global__ void __launch_bounds__(SB) anderson_update_kernel(long n, int k, double m, const double* gamma,
+                                                             double2* Sl, double2* Sg, const double2* Fl,
+                                                             const double2* Fg, const double2* DX, const double2* DF,
+                                                             double2* Sr, const int* state) {
+  if (state[1] != 0) return;
+  double g[MAXM];
+#pragma unroll
+  for (int j = 0; j < MAXM; ++j) g[j] = j < k ? gamma[j] : 0.0;
+  for (long x = (long)blockIdx.x * SB + threadIdx.x; x < n; x += (long)gridDim.x * SB) {
+    double2 out[2];
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+      const double2 sv = kind ? Sg[x] : Sl[x];
+      const double2 fv = csub(kind ? Fg[x] : Fl[x], sv);
+      const long i = kind * n + x;
+      double2 v = make_double2(sv.x + m * fv.x, sv.y + m * fv.y);
+#pragma unroll
+      for (int j = 0; j < MAXM; ++j) {
+        if (j < k) {
+          const double2 dx = DX[j * 2 * n + i], df = DF[j * 2 * n + i];
+          v.x -= g[j] * (dx.x + m * df.x);
+          v.y -= g[j] * (dx.y + m * df.y);
+        }
+      }
+      out[kind] = v;
+    }
+    Sl[x] = out[0];
+    Sg[x] = out[1];
+    Sr[x] = make_double2(0.5 * (out[1].x - out[0].x), 0.5 * (out[1].y - out[0].y));
+  }
+}
+
 inline size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 struct ScbaLayout {
   size_t rgf, ec, sig, total;   // bytes: sweeps' workspace, convolution's, one [n_e][nb][b][b] array
   bool kavg;                    // several k-points: one more such array for their average
+  int memory;                   // Anderson memory (0: linear mixing)
 };
 
 // the problems (k-points) of one loop share the block shape and the energy count
 bool scba_layout(const negf_problem* problems, int32_t n_prob, negf_precision prec, const negf_options* opt,
-                 int32_t n_w, ScbaLayout& L) {
-  if (!problems || n_prob < 1 || n_w < 1) return false;
+                 int32_t n_w, int32_t memory, ScbaLayout& L) {
+  if (!problems || n_prob < 1 || n_w < 1 || memory < 0 || memory > MAXM) return false;
   const negf_problem& p = problems[0];
   if (p.n_e < 1 || p.dev.nb < 2 || p.dev.b < 1) return false;
   for (int q = 1; q < n_prob; ++q)
@@ -181,8 +323,13 @@ bool scba_layout(const negf_problem* problems, int32_t n_prob, negf_precision pr
   if (L.rgf == 0 || L.ec == 0) return false;
   L.sig = (size_t)p.n_e * p.dev.nb * p.dev.b * p.dev.b * sizeof(double2);
   L.kavg = n_prob > 1;
+  L.memory = memory;
+  // Anderson: 2 M difference vectors and the previous pair, each of both kinds (2 arrays), partial sums, gamma
+  const size_t anderson = memory > 0 ? (2 * (size_t)memory + 2) * 2 * up256(L.sig) +
+                                           up256((size_t)RPARTS * NACC * sizeof(double)) + up256(MAXM * sizeof(double))
+                                     : 0;
   L.total = up256(L.rgf) + up256(L.ec) + (L.kavg ? 3 : 2) * up256(L.sig) + up256(2 * RPARTS * sizeof(double)) +
-            up256(sizeof(double)) + up256(2 * sizeof(int)) + 256;
+            up256(sizeof(double)) + up256(2 * sizeof(int)) + anderson + 256;
   return true;
 }
 
@@ -204,7 +351,9 @@ struct StepArgs {
   int32_t n_w, k0;
   const void *W_lesser, *W_greater;
   const double* scale;
-  double mixing, tol;
+  double mixing;
+  int32_t memory;
+  double tol;
   void *sig_r, *sig_l, *sig_g;
   void *GR_diag, *GR_upper, *GR_lower, *GL_diag, *GL_upper, *GG_diag, *GG_upper;
   int32_t* info;
@@ -221,7 +370,7 @@ negf_status check_step(const StepArgs& a, ScbaLayout& L) {
     if (dq.sig_r_sc || dq.sig_l_sc || dq.sig_g_sc || pq.sc_stride != 0) return NEGF_EINVAL;
   }
   if (a.k0 < 0 || a.k0 >= a.n_w || !(a.mixing > 0.0 && a.mixing <= 1.0) || !(a.tol >= 0.0)) return NEGF_EINVAL;
-  if (!scba_layout(a.problem, a.n_prob, a.prec, a.opt, a.n_w, L)) return NEGF_EINVAL;
+  if (!scba_layout(a.problem, a.n_prob, a.prec, a.opt, a.n_w, a.memory, L)) return NEGF_EINVAL;
   const void* req[] = {a.W_lesser, a.W_greater, a.sig_r, a.sig_l, a.sig_g, a.GR_diag, a.GR_upper, a.GL_diag,
                        a.GL_upper, a.GG_diag, a.GG_upper, a.info, a.workspace};
   for (const void* q : req)
@@ -235,6 +384,8 @@ negf_status check_step(const StepArgs& a, ScbaLayout& L) {
 struct Carved {
   void *rgf, *ec;
   double2 *Fl, *Fg, *Gk;   // Gk: the k-average (nullptr with one k-point)
+  double2 *DX, *DF, *xp, *fp;   // Anderson history (memory > 0)
+  double *apart, *gamma;
   double *part, *last;
   int* state;
 };
@@ -260,6 +411,23 @@ Carved carve(void* workspace, const ScbaLayout& L) {
   c.last = (double*)base;
   base += up256(sizeof(double));
   c.state = (int*)base;
+  base += up256(2 * sizeof(int));
+  c.DX = c.DF = c.xp = c.fp = nullptr;
+  c.apart = c.gamma = nullptr;
+  if (L.memory > 0) {
+    const size_t v = 2 * up256(L.sig);   // one vector of both kinds
+    c.DX = (double2*)base;
+    base += L.memory * v;
+    c.DF = (double2*)base;
+    base += L.memory * v;
+    c.xp = (double2*)base;
+    base += v;
+    c.fp = (double2*)base;
+    base += v;
+    c.apart = (double*)base;
+    base += up256((size_t)RPARTS * NACC * sizeof(double));
+    c.gamma = (double*)base;
+  }
   return c;
 }
 
@@ -317,10 +485,33 @@ negf_status step_impl(const StepArgs& a, const ScbaLayout& L, const Carved& c, i
                      (const double2*)c.Fg, (const double2*)Sl, (const double2*)Sg, c.part);
   hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(SB), 0, s, (int)part_grid, (const double*)c.part, a.tol, it,
                      c.last, history, state);
-  if (update)
+  if (update && L.memory == 0)
     hipLaunchKernelGGL(mix_kernel, dim3(mix_grid), dim3(SB), 0, s, n, a.mixing, (const double2*)c.Fl,
                        (const double2*)c.Fg, Sl, Sg, Sr, (const int*)state);
-  prof_end(KC_ELEM, s, 0.0, (update ? 176.0 : 64.0) * (double)n);
+  if (update && L.memory > 0) {
+    // history vectors hold 2 n complex (Sigma^< then Sigma^>); `it` counts the iterations since the start
+    const int k = std::min(it, L.memory);
+    const unsigned ag = (unsigned)std::min<long>((n + SB - 1) / SB, RPARTS);
+    hipLaunchKernelGGL(anderson_hist_kernel, dim3(mix_grid), dim3(SB), 0, s, n, it == 0 ? 1 : 0,
+                       it == 0 ? 0 : (it - 1) % L.memory, (const double2*)Sl, (const double2*)Sg,
+                       (const double2*)c.Fl, (const double2*)c.Fg, c.xp, c.fp, c.DX, c.DF, (const int*)state);
+    if (k > 0) {
+      hipLaunchKernelGGL(anderson_gram_kernel, dim3(ag), dim3(SB), 0, s, n, k, (const double2*)Sl,
+                         (const double2*)Sg, (const double2*)c.Fl, (const double2*)c.Fg, (const double2*)c.DF,
+                         c.apart, (const int*)state);
+      hipLaunchKernelGGL(anderson_solve_kernel, dim3(1), dim3(SB), 0, s, (int)ag, k, (const double*)c.apart,
+                         c.gamma, (const int*)state);
+    }
+    hipLaunchKernelGGL(anderson_update_kernel, dim3(mix_grid), dim3(SB), 0, s, n, k, a.mixing,
+                       (const double*)c.gamma, Sl, Sg, (const double2*)c.Fl, (const double2*)c.Fg,
+                       (const double2*)c.DX, (const double2*)c.DF, Sr, (const int*)state);
+  }
+  // bytes: the residual reads F and Sigma of both kinds (4 n complex); linear mixing reads them again and
+  // writes three arrays; Anderson's passes move 16 n (history; 12 n at the first) + (4 + 2 k) n (normal
+  // equations, none at the first) + (7 + 4 k) n (update) complex
+  const int kk = std::min(it, L.memory);
+  const double mixc = !update ? 0.0 : L.memory == 0 ? 7.0 : kk == 0 ? 19.0 : 27.0 + 6.0 * kk;
+  prof_end(KC_ELEM, s, 0.0, 16.0 * (4.0 + mixc) * (double)n);
   return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
 }
 
@@ -330,19 +521,21 @@ negf_status step_impl(const StepArgs& a, const ScbaLayout& L, const Carved& c, i
 extern "C" {
 
 size_t negf_scba_workspace_bytes(const negf_problem* problems, int32_t n_prob, negf_precision prec,
-                                 const negf_options* opt, int32_t n_w) {
+                                 const negf_options* opt, int32_t n_w, int32_t memory) {
   ScbaLayout L;
-  return scba_layout(problems, n_prob, prec, opt, n_w, L) ? L.total : 0;
+  return scba_layout(problems, n_prob, prec, opt, n_w, memory, L) ? L.total : 0;
 }
 
 negf_status negf_scba_step(const negf_problem* problem, int32_t n_prob, negf_precision prec, const negf_options* opt,
                            int32_t n_w, int32_t k0, const void* W_lesser, const void* W_greater,
-                           const double* scale, double mixing, double tol, int32_t it, int32_t update, void* sig_r,
+                           const double* scale, double mixing, int32_t memory, double tol, int32_t it, int32_t update,
+                           void* sig_r,
                            void* sig_l, void* sig_g, void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag,
                            void* GL_upper, void* GG_diag, void* GG_upper, int32_t* info, double* history,
                            int32_t* state, void* workspace, size_t ws_bytes, void* stream) {
-  StepArgs a{problem, n_prob, prec, opt, n_w, k0, W_lesser, W_greater, scale, mixing, tol, sig_r, sig_l, sig_g,
-             GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper, info, workspace, ws_bytes};
+  StepArgs a{problem, n_prob,  prec,    opt,      n_w,      k0,      W_lesser, W_greater, scale,
+             mixing,  memory,  tol,     sig_r,    sig_l,    sig_g,   GR_diag,  GR_upper,  GR_lower,
+             GL_diag, GL_upper, GG_diag, GG_upper, info,   workspace, ws_bytes};
   ScbaLayout L;
   negf_status st = check_step(a, L);
   if (st != NEGF_OK) return st;
@@ -352,12 +545,14 @@ negf_status negf_scba_step(const negf_problem* problem, int32_t n_prob, negf_pre
 
 negf_status negf_scba(const negf_problem* problem, int32_t n_prob, negf_precision prec, const negf_options* opt,
                       int32_t n_w, int32_t k0, const void* W_lesser, const void* W_greater, const double* scale,
-                      double mixing, double tol, int32_t max_iter, void* sig_r, void* sig_l, void* sig_g,
+                      double mixing, int32_t memory, double tol, int32_t max_iter, void* sig_r, void* sig_l,
+                      void* sig_g,
                       void* GR_diag, void* GR_upper, void* GR_lower, void* GL_diag, void* GL_upper, void* GG_diag,
                       void* GG_upper, int32_t* info, int32_t* n_iter, double* history, void* workspace,
                       size_t ws_bytes, void* stream) {
-  StepArgs a{problem, n_prob, prec, opt, n_w, k0, W_lesser, W_greater, scale, mixing, tol, sig_r, sig_l, sig_g,
-             GR_diag, GR_upper, GR_lower, GL_diag, GL_upper, GG_diag, GG_upper, info, workspace, ws_bytes};
+  StepArgs a{problem, n_prob,  prec,    opt,      n_w,      k0,      W_lesser, W_greater, scale,
+             mixing,  memory,  tol,     sig_r,    sig_l,    sig_g,   GR_diag,  GR_upper,  GR_lower,
+             GL_diag, GL_upper, GG_diag, GG_upper, info,   workspace, ws_bytes};
   if (!n_iter || max_iter < 1) return NEGF_EINVAL;
   ScbaLayout L;
   negf_status st = check_step(a, L);

@@ -167,6 +167,45 @@ def test_loop_converges_with_the_oracle(nb):
         assert err < 1e-9, (n, err)
 
 
+@pytest.mark.parametrize("b", [4, 40])
+def test_loop_anderson_fixed_iterations_matches_oracle(nb, b):
+    """Anderson mixing with memory 3 over six solves (five updates, so the history ring wraps once):
+    the self-energies and Green's functions element by element against the oracle's loop, and the
+    residual history."""
+    dev = w.folded_chain_device(4, b)
+    E, dE, k0, Wl, Wg = _bath(dev, 48)
+    scale = 1j * dE / (2 * math.pi)
+    ref, spread = _loop_reference(lambda: oscba.scba(dev, E, ETA, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=0.7,
+                                                     tol=0.0, max_iter=6, memory=3))
+    res = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=0.7, tol=0.0, max_iter=6, memory=3)
+    assert res["status"] == nb.NEGF_ENOCONV and res["n_iter"] == 6
+    assert int(res["info"].abs().sum()) == 0
+    _compare_loop(f"scba_anderson_fixed_b{b}", res, ref, spread)
+    for got, want in zip(res["history"], ref.history):
+        assert abs(got - want) <= 1e-8 * want + 1e-12, (res["history"], ref.history)
+
+
+def test_loop_anderson_converges_where_linear_mixing_diverges(nb):
+    """A periodic wire at a coupling where linear mixing (mixing 1) first approaches the fixed point and
+    then diverges: the GPU loop with memory 3 converges to the oracle's fixed point (Anderson, memory 3),
+    and with linear mixing it does not converge."""
+    wire = w.periodic_wire_device(4, 4, 3)
+    E = w.energy_grid(-3.0, 3.0, 64)
+    dE = float(E[1] - E[0])
+    Wl, Wg = w.boson_bath(wire.nb, wire.b, 17, 8, dE, KT, strength=0.2)
+    scale = 1j * dE / (2 * math.pi)
+    ref = oscba.scba(wire, E, ETA, 0.1, -0.1, KT, Wl, Wg, 8, scale, mixing=1.0, tol=1e-12, max_iter=40, memory=3)
+    assert ref.converged
+    res = _gpu_loop(nb, wire, E, Wl, Wg, 8, scale, 0.1, -0.1, mixing=1.0, tol=1e-12, max_iter=40, memory=3)
+    assert res["status"] == nb.NEGF_OK, res["history"]
+    for n in ("sig_l", "sig_g"):
+        err = rel(res[n].cpu().numpy(), getattr(ref, n))
+        record("scba_anderson_converged", 0.0, n, err, 1e-9)
+        assert err < 1e-9, (n, err)
+    lin = _gpu_loop(nb, wire, E, Wl, Wg, 8, scale, 0.1, -0.1, mixing=1.0, tol=1e-12, max_iter=40)
+    assert lin["status"] != nb.NEGF_OK, lin["history"]
+
+
 def test_loop_without_bath_is_one_ballistic_solve(nb):
     """W = 0: one solve, zero self-energies, the plain sweeps' result."""
     import torch
@@ -273,25 +312,27 @@ def test_energy_dependent_self_energies_through_a_plan(nb):
 
 # --------------------------------------------------------------- the loop as single captured steps
 
-def _step_loop(nb, dev, E, Wl, Wg, k0, scale, mixing, tol, max_steps):
+def _step_loop(nb, dev, E, Wl, Wg, k0, scale, mixing, tol, max_steps, memory=0):
     import torch
     prob = nb.Problem(nb.DeviceOnGPU(dev), E, eta=ETA, mu_l=0.1, mu_r=-0.1, kT=KT)
     return nb.ScbaLoop(prob, torch.from_numpy(Wl).cuda(), torch.from_numpy(Wg).cuda(), k0, scale, mixing=mixing,
-                       tol=tol, max_steps=max_steps)
+                       tol=tol, max_steps=max_steps, memory=memory)
 
 
-@pytest.mark.parametrize("tol,steps", [(0.0, 4), (1e-11, 16)])
-def test_loop_steps_equal_the_driver_and_replay_from_a_graph(nb, tol, steps):
+@pytest.mark.parametrize("tol,steps,memory", [(0.0, 4, 0), (1e-11, 16, 0), (0.0, 7, 2), (1e-11, 16, 3)])
+def test_loop_steps_equal_the_driver_and_replay_from_a_graph(nb, tol, steps, memory):
     """negf_scba_step run `steps` times (the last without mixing) ends on exactly what negf_scba ends on:
     with tol = 0 after the same four solves; with tol = 1e-11 the steps after convergence leave the
     self-energies alone and recompute the same Green's functions.  The same steps captured once in a
-    graph and replayed (self-energies cleared between replays) give the same bits again."""
+    graph and replayed (self-energies cleared between replays) give the same bits again.  With an
+    Anderson memory the history in the workspace is rebuilt by every run from its first step, so the
+    replays match as well."""
     import torch
     dev = w.folded_chain_device(4, 24)
     E, dE, k0, Wl, Wg = _bath(dev, 40, n_w=21)
     scale = 1j * dE / (2 * math.pi)
-    ref = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=1.0, tol=tol, max_iter=steps)
-    loop = _step_loop(nb, dev, E, Wl, Wg, k0, scale, 1.0, tol, steps)
+    ref = _gpu_loop(nb, dev, E, Wl, Wg, k0, scale, 0.1, -0.1, mixing=1.0, tol=tol, max_iter=steps, memory=memory)
+    loop = _step_loop(nb, dev, E, Wl, Wg, k0, scale, 1.0, tol, steps, memory=memory)
     loop.run(steps)
     torch.cuda.synchronize()
     names = ("sig_r", "sig_l", "sig_g")

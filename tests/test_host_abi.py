@@ -42,7 +42,7 @@ def test_status_strings_and_version(L):
     from paper_2602_03438_amd import binding as nb
     assert nb.status_string(nb.NEGF_OK) == "ok"
     assert "converge" in nb.status_string(nb.NEGF_ENOCONV)
-    assert nb.negf_version() >= nb.ABI_VERSION == 101
+    assert nb.negf_version() >= nb.ABI_VERSION == 102
 
 
 def _fake_problem(nb_=4, b=8, n_e=3, h=True):
@@ -183,22 +183,27 @@ def test_point_queue_rejects_synchronously(L):
 
 def test_self_consistent_loop_rejects_synchronously(L):
     """negf_scba: a device that already carries scattering self-energies, an out-of-range bath
-    index, mixing, tolerance or iteration cap, a convolution longer than 4096, missing or
-    aliased buffers and a short workspace all return EINVAL before any work."""
+    index, mixing, Anderson memory, tolerance or iteration cap, a convolution longer than 4096,
+    missing or aliased buffers and a short workspace all return EINVAL before any work."""
     from paper_2602_03438_amd import binding as nb
     pr, keep = _fake_problem(nb_=4, b=8, n_e=6)
     arr = (nb.negf_problem * 1)(pr)
     n_w = 5
-    ws = L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, n_w)
+    ws = L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, n_w, 0)
     sig_bytes = 6 * 4 * 8 * 8 * 16
     assert ws >= L.negf_workspace_bytes(nb.OP_LESSER_GREATER, arr, 1, nb.PLAIN_FP64, None) + 2 * sig_bytes
-    assert L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 0) == 0
-    assert L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 4092) == 0   # 6 + 4092 - 1 > 4096
-    assert L.negf_scba_workspace_bytes(arr, 0, nb.PLAIN_FP64, None, n_w) == 0
+    assert L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 0, 0) == 0
+    assert L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 4092, 0) == 0   # 6 + 4092 - 1 > 4096
+    assert L.negf_scba_workspace_bytes(arr, 0, nb.PLAIN_FP64, None, n_w, 0) == 0
+    # Anderson memory 1..4: room for 2 M + 2 history vectors of both kinds; beyond 4 rejected
+    ws3 = L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, n_w, 3)
+    assert ws3 >= ws + 8 * 2 * sig_bytes
+    assert L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, n_w, 5) == 0
+    assert L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, n_w, -1) == 0
     # k-points must share the block shape and the energy count; several need room for their average
     other, keep_o = _fake_problem(nb_=4, b=8, n_e=5)
-    assert L.negf_scba_workspace_bytes((nb.negf_problem * 2)(pr, other), 2, nb.PLAIN_FP64, None, n_w) == 0
-    two = L.negf_scba_workspace_bytes((nb.negf_problem * 2)(pr, pr), 2, nb.PLAIN_FP64, None, n_w)
+    assert L.negf_scba_workspace_bytes((nb.negf_problem * 2)(pr, other), 2, nb.PLAIN_FP64, None, n_w, 0) == 0
+    two = L.negf_scba_workspace_bytes((nb.negf_problem * 2)(pr, pr), 2, nb.PLAIN_FP64, None, n_w, 0)
     assert two > ws
     one = (C.c_double * 2)(0.0, 1.0)
     bufs = [np.zeros(64, dtype=np.complex128) for _ in range(13)]
@@ -206,16 +211,17 @@ def test_self_consistent_loop_rejects_synchronously(L):
     n_iter = C.c_int32(-1)
     hist = (C.c_double * 8)()
 
-    def call(a=arr, k0=2, mixing=0.5, tol=1e-10, max_iter=8, wsb=ws, **over):
+    def call(a=arr, k0=2, mixing=0.5, memory=0, tol=1e-10, max_iter=8, wsb=ws, **over):
         p = dict(W_l=W_l, W_g=W_g, s_r=s_r, s_l=s_l, s_g=s_g, ggd=ggd, info=info, scale=one, n_iter=C.byref(n_iter))
         p.update(over)
-        return L.negf_scba(a, 1, nb.PLAIN_FP64, None, n_w, k0, p["W_l"], p["W_g"], p["scale"], mixing, tol, max_iter,
+        return L.negf_scba(a, 1, nb.PLAIN_FP64, None, n_w, k0, p["W_l"], p["W_g"], p["scale"], mixing, memory, tol, max_iter,
                            p["s_r"], p["s_l"], p["s_g"], grd, gru, grl, gld, glu, p["ggd"], ggu, p["info"],
                            p["n_iter"], hist, grd, wsb, None)
 
     for bad in (dict(k0=-1), dict(k0=5), dict(mixing=0.0), dict(mixing=1.5), dict(mixing=float("nan")),
                 dict(tol=-1.0), dict(max_iter=0), dict(wsb=ws - 1), dict(W_l=None), dict(ggd=None), dict(info=None),
-                dict(scale=None), dict(n_iter=None), dict(s_l=s_g), dict(W_g=W_g + 8)):
+                dict(scale=None), dict(n_iter=None), dict(s_l=s_g), dict(W_g=W_g + 8), dict(memory=5),
+                dict(memory=-1), dict(memory=3)):   # memory 3 needs the larger workspace
         assert call(**bad) == nb.NEGF_EINVAL, bad
     # the loop supplies the scattering self-energies: a device with its own is rejected
     dev = nb.negf_device(4, 8, W_l, W_l, None, None, s_r, s_l, s_g)
@@ -230,18 +236,20 @@ def test_self_consistent_step_rejects_synchronously(L):
     from paper_2602_03438_amd import binding as nb
     pr, keep = _fake_problem(nb_=4, b=8, n_e=6)
     arr = (nb.negf_problem * 1)(pr)
-    ws = L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 5)
+    ws = L.negf_scba_workspace_bytes(arr, 1, nb.PLAIN_FP64, None, 5, 0)
     one = (C.c_double * 2)(0.0, 1.0)
     bufs = [np.zeros(64, dtype=np.complex128) for _ in range(14)]
     W_l, W_g, s_r, s_l, s_g, grd, gru, grl, gld, glu, ggd, ggu, info, state = [b.ctypes.data for b in bufs]
 
-    def call(it=0, st=state, k0=2, wsb=ws):
-        return L.negf_scba_step(arr, 1, nb.PLAIN_FP64, None, 5, k0, W_l, W_g, one, 0.5, 1e-10, it, 1, s_r, s_l, s_g, grd,
+    def call(it=0, st=state, k0=2, wsb=ws, memory=0):
+        return L.negf_scba_step(arr, 1, nb.PLAIN_FP64, None, 5, k0, W_l, W_g, one, 0.5, memory, 1e-10, it, 1, s_r, s_l, s_g, grd,
                                 gru, grl, gld, glu, ggd, ggu, info, None, st, grd, wsb, None)
     assert call(it=-1) == nb.NEGF_EINVAL
     assert call(st=None) == nb.NEGF_EINVAL
     assert call(k0=5) == nb.NEGF_EINVAL
     assert call(wsb=ws - 1) == nb.NEGF_EINVAL
+    assert call(memory=5) == nb.NEGF_EINVAL
+    assert call(memory=1) == nb.NEGF_EINVAL     # workspace sized for linear mixing
 
 
 def test_observables_reject_synchronously(L):
