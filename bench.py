@@ -260,6 +260,11 @@ def main():
     ap.add_argument("--scba-kpoints", type=int, default=1, help="transverse momenta of the scba workload (k = pi j / 4; "
                                                              "the self-energies are shared, built from their average)")
     ap.add_argument("--scba-strength", type=float, default=0.05, help="bath strength of the scba workload")
+    ap.add_argument("--scba-memory", type=int, default=0, help="Anderson memory of the scba workload (0: linear "
+                    "mixing at 0.5; 1..4: Anderson mixing at 1.0, with 4 M + 4 more [energies][Nb][b][b] "
+                    "arrays of workspace)")
+    ap.add_argument("--scba-tol", type=float, default=0.0, help="stopping tolerance of the scba workload's timed "
+                    "call (0: exactly --steps iterations)")
     ap.add_argument("--serinv-points", default="1,2,4,8", help="energy points per call in the serinv workload")
     ap.add_argument("--serinv-parts", default="4,8", help="partition counts in the serinv workload")
     ap.add_argument("--uneven-points", type=int, default=8, help="energies per (device, k) in the uneven workload "
@@ -847,15 +852,18 @@ def bench_scba(args):
     b = 512): --scba-energies energies, uniform on [-1.5, 1.5], and a boson bath of --scba-freqs
     frequencies (the grid spacing apart).  An iteration solves every energy (G^R, G^<, G^>, both
     leads), convolves the diagonal blocks of G^< and of G^> with the bath (Eq. (3)), reduces the
-    residual, reads it on the host and mixes.  --steps iterations are timed as one call with
-    tol = 0 (no early stop), after --warmup iterations in a call of their own; points/s =
-    energies x iterations / wall time of the call.  The convolutions are also timed alone, on the
+    residual, reads it on the host and mixes (linearly, or by Anderson's extrapolation with
+    --scba-memory).  --steps iterations are timed as one call with tol = --scba-tol (0: no early
+    stop), after --warmup iterations in a call of their own; points/s = energies x iterations
+    performed / wall time of the call.  The convolutions are also timed alone, on the
     same arrays, for their share of an iteration."""
     import torch
     import workloads as w
     from paper_2602_03438_amd import autotune
     from paper_2602_03438_amd import binding as nb
     n_e, n_w, nk = args.scba_energies, args.scba_freqs, args.scba_kpoints
+    memory = args.scba_memory
+    mixing = 1.0 if memory > 0 else 0.5
     k0 = (n_w - 1) // 2
     dev = w.slab_device(NB, B, SEED)
     devs = [dev] if nk == 1 else [w.k_device(dev, 31, np.pi * j / 4) for j in range(nk)]
@@ -877,13 +885,15 @@ def bench_scba(args):
     log(f"scba: {nk} k-point(s) x {n_e} energies x Nb={NB} b={B}, {n_w} bath frequencies; warm-up {args.warmup} "
         f"iteration(s)")
     if args.warmup > 0:
-        nb.scba(prob, gWl, gWg, k0, scale, tol=0.0, max_iter=args.warmup, opts=opts, ws=ws, outputs=outs, sigmas=sig)
+        nb.scba(prob, gWl, gWg, k0, scale, mixing=mixing, tol=0.0, max_iter=args.warmup, opts=opts, ws=ws, outputs=outs,
+                sigmas=sig, memory=memory)
     for v in sig.values():
         v.zero_()
     torch.cuda.synchronize()
     log(f"scba: {args.steps} timed iteration(s)")
-    r, dt, stats = profiled(nb, lambda: nb.scba(prob, gWl, gWg, k0, scale, mixing=0.5, tol=0.0, max_iter=args.steps,
-                                                opts=opts, ws=ws, outputs=outs, sigmas=sig))
+    r, dt, stats = profiled(nb, lambda: nb.scba(prob, gWl, gWg, k0, scale, mixing=mixing, tol=args.scba_tol,
+                                                max_iter=args.steps, opts=opts, ws=ws, outputs=outs, sigmas=sig,
+                                                memory=memory))
     its = r["n_iter"]
     log(f"scba: {its} iteration(s) in {dt:.2f} s, residuals {['%.2e' % h for h in r['history']]}")
     # the two convolutions of one iteration, alone
@@ -911,7 +921,9 @@ def bench_scba(args):
             "config": {"workload": f"nano-ribbon-like slab device Nb={NB} b={B}, {nk} k-point(s) x {n_e} energies on "
                                    f"[-1.5, 1.5], "
                                    f"boson bath of {n_w} frequencies (strength {args.scba_strength}, kT={KT}), "
-                                   f"eta={ETA}, mixing 0.5, one iteration per step",
+                                   f"eta={ETA}, "
+                                   + (f"Anderson mixing (memory {memory}, mixing 1.0)" if memory else "mixing 0.5")
+                                   + f", tol {args.scba_tol}, one iteration per step",
                        "real_products_per_complex_product": args.cmul, "sr_max_iter": args.sr_max_iter},
             "ms_per_iteration": it_ms, "convolutions_ms_per_iteration": conv_ms,
             "convolution_share": conv_ms / it_ms, "residual_history": r["history"], "status": r["status"],
