@@ -15,6 +15,10 @@ def main(path):
     by = collections.OrderedDict()
     for r in rows:
         by.setdefault(r["test"], []).append(r)
+    print("Parity of the GPU path against the oracle, from the records of one session of "
+          "`python -u -m pytest tests -m gpu -x -v --timeout 300 --timeout-method thread`, summarised by "
+          f"`python tests/parity_summary.py {path} > profiles/parity_bars.md`.")
+    print()
     print("| test | comparisons | points | max error | bars used | max oracle spread | max conditioning proxy |")
     print("|---|---|---|---|---|---|---|")
     plain_tests = []
