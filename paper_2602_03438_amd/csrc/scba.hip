@@ -507,10 +507,10 @@ negf_status step_impl(const StepArgs& a, const ScbaLayout& L, const Carved& c, i
                        (const double2*)c.DX, (const double2*)c.DF, Sr, (const int*)state);
   }
   // bytes: the residual reads F and Sigma of both kinds (4 n complex); linear mixing reads them again and
-  // writes three arrays; Anderson's passes move 16 n (history; 12 n at the first) + (4 + 2 k) n (normal
-  // equations, none at the first) + (7 + 4 k) n (update) complex
+  // writes three arrays; Anderson's passes move 16 n (history; 8 n at the first, which stores no
+  // differences) + (4 + 2 k) n (normal equations, none at the first) + (7 + 4 k) n (update) complex
   const int kk = std::min(it, L.memory);
-  const double mixc = !update ? 0.0 : L.memory == 0 ? 7.0 : kk == 0 ? 19.0 : 27.0 + 6.0 * kk;
+  const double mixc = !update ? 0.0 : L.memory == 0 ? 7.0 : kk == 0 ? 15.0 : 27.0 + 6.0 * kk;
   prof_end(KC_ELEM, s, 0.0, 16.0 * (4.0 + mixc) * (double)n);
   return hipGetLastError() == hipSuccess ? NEGF_OK : NEGF_EHIP;
 }

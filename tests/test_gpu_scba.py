@@ -443,6 +443,34 @@ def test_loop_over_k_points_matches_oracle(nb, b):
         assert torch.equal(one[n], twice[n]), n
 
 
+def test_loop_anderson_over_k_points_and_in_the_refined_form(nb):
+    """Anderson mixing (memory 2) over two k-points: five solves against the oracle's Anderson loop
+    (plain 1e-10); the same loop with its solves in the refined single-product form within that form's
+    1e-6 bar."""
+    import torch
+    base, devs = _k_devices(4)
+    E, dE, k0, Wl, Wg = _bath(base, 32, n_w=9)
+    scale = 1j * dE / (2 * math.pi)
+    ref = oscba.scba(devs, E, ETA, 0.1, -0.1, KT, Wl, Wg, k0, scale, mixing=0.7, tol=0.0, max_iter=5, memory=2)
+    probs = [nb.Problem(nb.DeviceOnGPU(d), E, eta=ETA, mu_l=0.1, mu_r=-0.1, kT=KT) for d in devs]
+    gWl, gWg = torch.from_numpy(Wl).cuda(), torch.from_numpy(Wg).cuda()
+    print(f"  negf_scba over {len(devs)} k-points, memory 2, plain and refined", flush=True)
+    res = nb.scba(probs, gWl, gWg, k0, scale, mixing=0.7, tol=0.0, max_iter=5, memory=2)
+    fine = nb.scba(probs, gWl, gWg, k0, scale, mixing=0.7, tol=0.0, max_iter=5, memory=2, prec=nb.FP32_REFINE)
+    torch.cuda.synchronize()
+    assert res["n_iter"] == 5 and int(res["info"].abs().sum()) == 0
+    for got, bar, name in ((res, 1e-10, "scba_anderson_k_points"), (fine, 1e-6, "scba_anderson_k_points_refine")):
+        for n in ("sig_l", "sig_g", "sig_r"):
+            err = rel(got[n].cpu().numpy(), getattr(ref, n))
+            record(name, 0.0, n, err, bar)
+            assert err < bar, (name, n, err)
+        for q in range(len(devs)):
+            for n in ("GR_diag", "GL_diag", "GG_diag"):
+                err = rel(got[n][q].cpu().numpy(), _stack(ref.points[q], n))
+                record(name, 0.0, n, err, bar)
+                assert err < bar, (name, q, n, err)
+
+
 def test_loop_over_k_points_conserves_the_summed_current(nb):
     """Converged over two k-points (b = 24): the energy-integrated current summed over the k-points is the
     same at every interface (negf_observables on the loop's outputs)."""
