@@ -396,6 +396,18 @@ def main():
                     "median_spread": float(np.median(per_pt)),
                     "note": "negf_observables on the first energy batch's outputs (all points, flagged ones "
                             "included); exact conservation in exact arithmetic"}
+    # decimation steps per point and lead on that batch (negf_obc_surface with the step's options): the
+    # Sancho-Rubio step histogram and the points whose surface Green's function is flagged
+    decim = {}
+    for side, name in ((0, "left"), (1, "right")):
+        o = nb.obc_surface(probs, side, opts=opts, ws=ws)
+        its = o["iters"].cpu().numpy()
+        vals, counts = np.unique(its, return_counts=True)
+        decim[name] = {"mean": float(its.mean()), "min": int(its.min()), "max": int(its.max()),
+                       "histogram": {str(int(v)): int(c) for v, c in zip(vals, counts)},
+                       "flagged": int(np.count_nonzero(o["info"].cpu().numpy())),
+                       "max_residual": float(o["resid"].max().item())}
+        del o
     if plan:
         plan.close()          # its workspace is not needed by the runs below
     chosen = None
@@ -469,6 +481,8 @@ def main():
         "failures": res["failures"][:8],
         "roofline": roof,
         "current_conservation": conservation,
+        "decimation_steps": {**decim, "note": "Sancho-Rubio steps per point of the first energy batch, each lead "
+                                              "(negf_obc_surface, untimed)"},
         "kernels": kstats,
         "kernels_note": "one extra untimed step with every kernel class timed (the timed steps time the products only)",
         "chosen_form": chosen,

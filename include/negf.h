@@ -168,7 +168,9 @@ size_t negf_workspace_bytes(int32_t op, const negf_problem* problems, int32_t n_
  *             products per step.
  *  g_surf   : out [points][b][b]; sigma_r: out [points][b][b]
  *  iters    : out int32 [points] decimation steps (0 when the candidate was
- *             accepted, k when the closure after step k was)
+ *             accepted, k when the closure after step k was; -k when the
+ *             couplings' norms after step k were not finite, which stopped
+ *             that point's decimation there)
  *  resid    : out double [points] ||(d - alpha g_s beta) g_s - I||_F /
  *             (||d - alpha g_s beta||_F ||g_s||_F)
  *  info     : out int32 [points]                                              */
