@@ -264,3 +264,36 @@ def test_anderson_mixing_reaches_the_fixed_point_where_linear_mixing_does_not():
     assert not lin.converged and lin.history[-1] > 1e-9
     acc = scba.scba(wire, Ew, 1e-6, 0.1, -0.1, KT, Wl, Wg, 8, sw, mixing=1.0, tol=1e-12, max_iter=40, memory=3)
     assert acc.converged, acc.history
+
+
+def test_anderson_step_solves_a_linear_fixed_point_like_gmres():
+    """On a linear map x -> G x + c of dimension d, Anderson's extrapolation with memory >= d and mixing 1
+    is equivalent to GMRES on (I - G) x = c (Walker and Ni, SIAM J. Numer. Anal. 49, 1715 (2011)): it
+    reaches the exact solution within d + 1 updates, also where plain iteration diverges (eigenvalues of G
+    outside the unit disc).  A dropped difference, a wrong sign of gamma or a transposed normal matrix
+    fails this."""
+    from oracle.scba import anderson
+    rng = np.random.default_rng(7)
+    d = 4
+    Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    G = Q @ np.diag([1.7, -2.5, 0.4, 0.9]) @ Q.T          # spectral radius 2.5: plain iteration diverges
+    c = rng.standard_normal(d)
+    exact = np.linalg.solve(np.eye(d) - G, c)
+    for memory in (d, d + 2):
+        x, prev, dxs, dfs = np.zeros(d), None, [], []
+        errs = []
+        for n in range(d + 2):
+            f = G @ x + c - x
+            if prev is not None:
+                dxs.append(x - prev[0])
+                dfs.append(f - prev[1])
+                dxs, dfs = dxs[-memory:], dfs[-memory:]
+            prev = (x, f)
+            x = anderson(x, f, dxs, dfs, 1.0)
+            errs.append(float(np.linalg.norm(x - exact) / np.linalg.norm(exact)))
+        assert errs[d] < 1e-9, (memory, errs)
+    # plain iteration from the same start runs away
+    x = np.zeros(d)
+    for _ in range(d + 2):
+        x = G @ x + c
+    assert np.linalg.norm(x - exact) > np.linalg.norm(exact)
