@@ -7,10 +7,13 @@
 // without any host synchronisation: the sweeps, two convolutions (lesser,
 // greater) that read the energy-major diagonal blocks the sweeps wrote, one
 // streaming pass for the residual, whose last workgroup also records the
-// residual and the loop state in device memory, and one mixing pass that reads
+// residual and the loop state in device memory, and the mixing, which reads
 // that state and leaves the self-energies alone once the loop has converged
 // (so that a fixed number of captured iterations ends on the same self-energies
-// and Green's functions as a loop stopped at convergence).  negf_scba drives the
+// and Green's functions as a loop stopped at convergence).  The mixing is one
+// linear pass, or Anderson's extrapolation in four launches (history, normal
+// equations, their solution in one workgroup, update), its history of
+// differences kept in the workspace as a ring of M slots.  negf_scba drives the
 // steps from the host and reads the state after each one to stop early.  Per
 // energy the self-energies are nb b b complex elements; the problem handed to
 // the sweeps points at them with sc_stride = nb b b.
