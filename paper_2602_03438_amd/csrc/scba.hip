@@ -31,7 +31,7 @@ constexpr int SB = 256;       // threads per workgroup of the streaming kernels
 constexpr int RPARTS = 1024;  // workgroups of the residual's first stage (fixed: the sum's order is fixed)
 constexpr long MIX_WG = 8192; // grid cap of the mixing pass (grid-stride beyond)
 constexpr int U = 4;          // elements per thread and pass of the streaming kernels
-constexpr int MAXM = 4;       // longest Anderson memory
+constexpr int MAXM = 4;       // longest Anderson memory  (the launch tables below list one kernel per length)
 constexpr int NACC = MAXM * (MAXM + 1) / 2 + MAXM;   // accumulators of its normal equations
 
 __device__ __forceinline__ double norm2(double2 z) { return z.x * z.x + z.y * z.y; }
@@ -192,8 +192,10 @@ __global__ void __launch_bounds__(SB) anderson_hist_kernel(long n, int first, in
   }
 }
 
-// per workgroup: A_ij = Re <df_i, df_j> (i <= j < k, packed row by row) and r_i = Re <df_i, f>
-__global__ void __launch_bounds__(SB) anderson_gram_kernel(long n, int k, const double2* Sl, const double2* Sg,
+// per workgroup: A_ij = Re <df_i, df_j> (i <= j < K, packed row by row over MAXM) and r_i = Re <df_i, f>;
+// K is a template argument so that every load of an element is issued before its arithmetic
+template <int K>
+__global__ void __launch_bounds__(SB) anderson_gram_kernel(long n, const double2* Sl, const double2* Sg,
                                                            const double2* Fl, const double2* Fg, const double2* DF,
                                                            double* part, const int* state) {
   if (state[1] != 0) return;
@@ -208,7 +210,7 @@ __global__ void __launch_bounds__(SB) anderson_gram_kernel(long n, int k, const 
       const long i = kind * n + x;
       double2 d[MAXM];
 #pragma unroll
-      for (int j = 0; j < MAXM; ++j) d[j] = j < k ? DF[j * 2 * n + i] : make_double2(0.0, 0.0);
+      for (int j = 0; j < MAXM; ++j) d[j] = j < K ? DF[j * 2 * n + i] : make_double2(0.0, 0.0);
       int a = 0;
 #pragma unroll
       for (int p = 0; p < MAXM; ++p)
@@ -272,15 +274,16 @@ __global__ void __launch_bounds__(SB) anderson_solve_kernel(int nparts, int k, c
   }
 }
 
-// x += m f - sum_j gamma_j (dx_j + m df_j) for both kinds, then Sigma^R = (Sigma^> - Sigma^<) / 2
-__global__ void __launch_bounds__(SB) anderson_update_kernel(long n, int k, double m, const double* gamma,
+// x += m f - sum_j gamma_j (dx_j + m df_j) for both kinds (j < K), then Sigma^R = (Sigma^> - Sigma^<) / 2
+template <int K>
+__global__ void __launch_bounds__(SB) anderson_update_kernel(long n, double m, const double* gamma,
                                                              double2* Sl, double2* Sg, const double2* Fl,
                                                              const double2* Fg, const double2* DX, const double2* DF,
                                                              double2* Sr, const int* state) {
   if (state[1] != 0) return;
   double g[MAXM];
 #pragma unroll
-  for (int j = 0; j < MAXM; ++j) g[j] = j < k ? gamma[j] : 0.0;
+  for (int j = 0; j < MAXM; ++j) g[j] = j < K ? gamma[j] : 0.0;
   for (long x = (long)blockIdx.x * SB + threadIdx.x; x < n; x += (long)gridDim.x * SB) {
     double2 out[2];
 #pragma unroll
@@ -290,12 +293,10 @@ __global__ void __launch_bounds__(SB) anderson_update_kernel(long n, int k, doub
       const long i = kind * n + x;
       double2 v = make_double2(sv.x + m * fv.x, sv.y + m * fv.y);
 #pragma unroll
-      for (int j = 0; j < MAXM; ++j) {
-        if (j < k) {
-          const double2 dx = DX[j * 2 * n + i], df = DF[j * 2 * n + i];
-          v.x -= g[j] * (dx.x + m * df.x);
-          v.y -= g[j] * (dx.y + m * df.y);
-        }
+      for (int j = 0; j < K; ++j) {
+        const double2 dx = DX[j * 2 * n + i], df = DF[j * 2 * n + i];
+        v.x -= g[j] * (dx.x + m * df.x);
+        v.y -= g[j] * (dx.y + m * df.y);
       }
       out[kind] = v;
     }
@@ -499,13 +500,18 @@ negf_status step_impl(const StepArgs& a, const ScbaLayout& L, const Carved& c, i
                        it == 0 ? 0 : (it - 1) % L.memory, (const double2*)Sl, (const double2*)Sg,
                        (const double2*)c.Fl, (const double2*)c.Fg, c.xp, c.fp, c.DX, c.DF, (const int*)state);
     if (k > 0) {
-      hipLaunchKernelGGL(anderson_gram_kernel, dim3(ag), dim3(SB), 0, s, n, k, (const double2*)Sl,
-                         (const double2*)Sg, (const double2*)c.Fl, (const double2*)c.Fg, (const double2*)c.DF,
-                         c.apart, (const int*)state);
+      decltype(&anderson_gram_kernel<1>) gram[MAXM] = {anderson_gram_kernel<1>, anderson_gram_kernel<2>,
+                                                        anderson_gram_kernel<3>, anderson_gram_kernel<4>};
+      hipLaunchKernelGGL(gram[k - 1], dim3(ag), dim3(SB), 0, s, n, (const double2*)Sl, (const double2*)Sg,
+                         (const double2*)c.Fl, (const double2*)c.Fg, (const double2*)c.DF, c.apart,
+                         (const int*)state);
       hipLaunchKernelGGL(anderson_solve_kernel, dim3(1), dim3(SB), 0, s, (int)ag, k, (const double*)c.apart,
                          c.gamma, (const int*)state);
     }
-    hipLaunchKernelGGL(anderson_update_kernel, dim3(mix_grid), dim3(SB), 0, s, n, k, a.mixing,
+    decltype(&anderson_update_kernel<0>) upd[MAXM + 1] = {anderson_update_kernel<0>, anderson_update_kernel<1>,
+                                                          anderson_update_kernel<2>, anderson_update_kernel<3>,
+                                                          anderson_update_kernel<4>};
+    hipLaunchKernelGGL(upd[k], dim3(mix_grid), dim3(SB), 0, s, n, a.mixing,
                        (const double*)c.gamma, Sl, Sg, (const double2*)c.Fl, (const double2*)c.Fg,
                        (const double2*)c.DX, (const double2*)c.DF, Sr, (const int*)state);
   }
