@@ -276,33 +276,57 @@ __global__ void __launch_bounds__(SB) anderson_solve_kernel(int nparts, int k, c
 
 // x += m f - sum_j gamma_j (dx_j + m df_j) for both kinds (j < K), then Sigma^R = (Sigma^> - Sigma^<) / 2
 template <int K>
-__global__ void __launch_bounds__(SB) anderson_update_kernel(long n, double m, const double* gamma,
-                                                             double2* Sl, double2* Sg, const double2* Fl,
-                                                             const double2* Fg, const double2* DX, const double2* DF,
-                                                             double2* Sr, const int* state) {
+__global__ void __launch_bounds__(SB) anderson_update_kernel(long n, double m, const double* __restrict__ gamma,
+                                                             double2* __restrict__ Sl, double2* __restrict__ Sg,
+                                                             const double2* __restrict__ Fl,
+                                                             const double2* __restrict__ Fg,
+                                                             const double2* __restrict__ DX,
+                                                             const double2* __restrict__ DF, double2* __restrict__ Sr,
+                                                             const int* state) {
   if (state[1] != 0) return;
+  constexpr int UA = 2;   // elements per thread and pass: all of their loads are issued first
   double g[MAXM];
 #pragma unroll
   for (int j = 0; j < MAXM; ++j) g[j] = j < K ? gamma[j] : 0.0;
-  for (long x = (long)blockIdx.x * SB + threadIdx.x; x < n; x += (long)gridDim.x * SB) {
-    double2 out[2];
+  for (long x0 = (long)blockIdx.x * SB * UA + threadIdx.x; x0 < n; x0 += (long)gridDim.x * SB * UA) {
+    double2 sv[UA][2], fv[UA][2], dx[UA][2][K > 0 ? K : 1], df[UA][2][K > 0 ? K : 1];
 #pragma unroll
-    for (int kind = 0; kind < 2; ++kind) {
-      const double2 sv = kind ? Sg[x] : Sl[x];
-      const double2 fv = csub(kind ? Fg[x] : Fl[x], sv);
-      const long i = kind * n + x;
-      double2 v = make_double2(sv.x + m * fv.x, sv.y + m * fv.y);
+    for (int u = 0; u < UA; ++u) {
+      const long x = x0 + (long)u * SB;
+      if (x < n) {
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const double2 dx = DX[j * 2 * n + i], df = DF[j * 2 * n + i];
-        v.x -= g[j] * (dx.x + m * df.x);
-        v.y -= g[j] * (dx.y + m * df.y);
+        for (int kind = 0; kind < 2; ++kind) {
+          const long i = kind * n + x;
+          sv[u][kind] = kind ? Sg[x] : Sl[x];
+          fv[u][kind] = kind ? Fg[x] : Fl[x];
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            dx[u][kind][j] = DX[j * 2 * n + i];
+            df[u][kind][j] = DF[j * 2 * n + i];
+          }
+        }
       }
-      out[kind] = v;
     }
-    Sl[x] = out[0];
-    Sg[x] = out[1];
-    Sr[x] = make_double2(0.5 * (out[1].x - out[0].x), 0.5 * (out[1].y - out[0].y));
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      const long x = x0 + (long)u * SB;
+      if (x >= n) continue;
+      double2 out[2];
+#pragma unroll
+      for (int kind = 0; kind < 2; ++kind) {
+        const double2 f = csub(fv[u][kind], sv[u][kind]);
+        double2 v = make_double2(sv[u][kind].x + m * f.x, sv[u][kind].y + m * f.y);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          v.x -= g[j] * (dx[u][kind][j].x + m * df[u][kind][j].x);
+          v.y -= g[j] * (dx[u][kind][j].y + m * df[u][kind][j].y);
+        }
+        out[kind] = v;
+      }
+      Sl[x] = out[0];
+      Sg[x] = out[1];
+      Sr[x] = make_double2(0.5 * (out[1].x - out[0].x), 0.5 * (out[1].y - out[0].y));
+    }
   }
 }
 
