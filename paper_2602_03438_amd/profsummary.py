@@ -3,7 +3,7 @@
 Kernel trace (``*_results.db``): per kernel symbol (and grid size) the number
 of dispatches, total and average duration.
 
-    python -m paper_2602_03438_amd.profsummary gpurun_out/prof/run_results.db [--by-grid] [--top 20]
+    python -m paper_2602_03438_amd.profsummary <output dir>/run_results.db [--by-grid] [--top 20]
 
 Matrix-core activity from one counter run (SQ_INSTS_VALU_MFMA_MOPS_F64,
 SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE) of the product kernel:

@@ -119,9 +119,9 @@ def kappa_proxy(dev, ref):
 
 # ---- per-point parity records -------------------------------------------------
 # Every GPU parity comparison appends (test, point, output kind, error, bar,
-# oracle spread, conditioning proxy); the session writes them to
-# gpurun_out/parity/records.jsonl (see conftest.py) so that a run states which
-# bar each point was held to.
+# oracle spread, conditioning proxy); at its end the session writes them to
+# parity/records.jsonl under the results folder (conftest.py) so that a run
+# states which bar each point was held to.
 RECORDS = []
 
 

@@ -1,9 +1,9 @@
 """Summary of the per-point parity records a GPU test session writes to
-gpurun_out/parity/records.jsonl (helpers.record): per test, the points and
+parity/records.jsonl under the results folder (helpers.record): per test, the points and
 output kinds compared, the largest error, the bars used, and whether every bar
 was the plain one.
 
-    python tests/parity_summary.py gpurun_out/parity/records.jsonl > profiles/parity_bars.md
+    python tests/parity_summary.py <results folder>/parity/records.jsonl > profiles/parity_bars.md
 """
 import collections
 import json

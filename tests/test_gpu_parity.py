@@ -12,8 +12,8 @@ ill-conditioned that the oracle moves by up to 3e-8 under the same
 refinement; no double-precision method can be held to 1e-10 against it there.
 The tests named ``..._conditioned`` cover such energies with the bar
 max(1e-10, 4 x that spread), and print and record each point's bar.  Every
-comparison is recorded (helpers.record) and written to
-gpurun_out/parity/records.jsonl at the end of the session.
+comparison is recorded (helpers.record) and written to parity/records.jsonl
+under the results folder at the end of the session (conftest.py).
 """
 import numpy as np
 import pytest
